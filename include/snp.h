@@ -1,0 +1,218 @@
+/*
+ * snp.h -- C ABI of libsnp, a gfx950 (MI355X) simulator for spiking neural P
+ * systems without delays that expands the computation tree breadth first.
+ *
+ * Model (Cabarle, Adorna, Martinez-del-Amor, "Simulating Spiking Neural P
+ * systems without delays using GPUs", arXiv:1104.1824):
+ *   - A system Pi has m neurons and r rules in a total order, grouped neuron by
+ *     neuron (Definition 1; Section 2.2 "a total ordering of rules").
+ *   - Rule k of neuron s has regular expression E = a^i (a^j)* (j = 0: exactly
+ *     a^i), consumes c >= 1 spikes and sends p >= 0 spikes along every synapse
+ *     (s, d) (Definition 1 rule forms b-1, b-2, b-3; Definition 2).  It applies
+ *     to a neuron holding n spikes iff a^n is in L(E) and n >= c (Section 2.1).
+ *   - A configuration C is the vector of spike counts (Section 2.2).  A valid
+ *     spiking vector S fires exactly one applicable rule in every neuron that
+ *     has one, and nothing in the others (Section 2.2, "validity").
+ *   - The next configuration is C' = C + S . M_Pi (Equation next-config) with
+ *     M_Pi the r x m spiking transition matrix of Definition 2.
+ *   - Breadth-first expansion (Algorithm 1): every valid S of every frontier
+ *     configuration is applied; a configuration produced before, at any level,
+ *     is not recorded again (Algorithm 1 step IV, second stopping criterion).
+ *
+ * Canonical order.  The children of one configuration are numbered
+ * t = 0 .. Psi-1 in the order of Algorithm 2 step II-3: neuron 1 is the most
+ * significant digit, the last neuron the least, and the digit of a neuron
+ * selects among its applicable rules in their total order.  A neuron with no
+ * applicable rule has one digit value (it fires nothing).  Psi is the product
+ * of max(1, omega_n) over neurons (omega_n = number of applicable rules of
+ * neuron n, Algorithm 2 II-1/II-2); a configuration where no rule applies
+ * anywhere is halting and has Psi = 0.  The children of a frontier are
+ * numbered g = 0, 1, ... parent by parent, in frontier order.  Every level
+ * lists its new configurations by increasing g of their first occurrence.
+ *
+ * All arithmetic is integer.  Spike counts are stored as int32 or uint16
+ * (snp_count_t); a count outside [0, max of the type] is SNP_ERR_OVERFLOW,
+ * never wrapped or saturated.
+ *
+ * Conventions shared by every entry point:
+ *   - Nothing throws across the ABI; every call returns snp_status and, on an
+ *     error, snp_last_error() describes it (thread-local, valid until the next
+ *     call on the same thread).
+ *   - "device pointer" arguments are HIP device memory (e.g. a torch tensor's
+ *     data_ptr()); the caller owns them and keeps them alive for the call.
+ *     "host pointer" arguments are ordinary CPU memory.
+ *   - A row is one configuration: m consecutive elements of the count type.
+ *     Arrays of rows are row-major and densely packed.
+ *   - A handle is used by one thread at a time and launches all of its work on
+ *     the stream given at load (NULL: the default stream).  Every entry point
+ *     returns after that stream has finished the call's work.
+ *   - Device-side failures (allocation, launch) return SNP_ERR_DEVICE.
+ */
+#ifndef SNP_H
+#define SNP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SNP_OK = 0,
+    SNP_ERR_INVALID = 1,  /* malformed system or argument; nothing was changed */
+    SNP_ERR_OVERFLOW = 2, /* a spike count left the range of the count type */
+    SNP_ERR_CAPACITY = 3, /* an output or internal buffer is too small */
+    SNP_ERR_BUDGET = 4,   /* reserved: limits reached are reported as stop reasons */
+    SNP_ERR_DEVICE = 5    /* HIP runtime failure */
+} snp_status;
+
+typedef enum { SNP_COUNT_I32 = 0, SNP_COUNT_U16 = 1 } snp_count_t;
+
+/* How S . M is evaluated for a chunk of children.  Results are identical. */
+typedef enum {
+    SNP_PATH_AUTO = 0,   /* per chunk: int8 matrix cores when M fits int8 and the chunk is dense */
+    SNP_PATH_SPARSE = 1, /* gather over the in-synapses of every neuron (int32 adds) */
+    SNP_PATH_INT8 = 2    /* S (0/1) x M (int8) on MFMA with int32 accumulation; falls back to
+                            SPARSE (stats.int8_fallback = 1) when some |M entry| > 127 */
+} snp_path;
+
+/* Why a BFS run ended. */
+typedef enum {
+    SNP_STOP_EMPTY_FRONTIER = 0, /* a level produced no new configuration (second criterion) */
+    SNP_STOP_ALL_HALTING = 1,    /* no rule applies in any frontier configuration (first
+                                    criterion generalised: the zero vector is halting) */
+    SNP_STOP_DEPTH = 2,          /* max_depth levels were expanded */
+    SNP_STOP_CAP = 3,            /* a level reached frontier_cap and stop_at_cap was set */
+    SNP_STOP_BUDGET = 4          /* child_budget children were enumerated and more remained */
+} snp_stop;
+
+/* An SN P system (Definition 1).  All arrays are host pointers and are copied
+ * by snp_load / snp_batch_load; the caller keeps ownership. */
+typedef struct {
+    int32_t m;                  /* neurons, >= 1 */
+    int32_t r;                  /* rules, >= 0 */
+    const int32_t *rule_neuron; /* [r] owner neuron (0-based), non-decreasing */
+    const int32_t *rule_i;      /* [r] E = a^i (a^j)*: i >= 1 */
+    const int32_t *rule_j;      /* [r] j >= 0 (0: E = a^i exactly) */
+    const int32_t *rule_c;      /* [r] spikes consumed, c >= 1 */
+    const int32_t *rule_p;      /* [r] spikes sent along each out-synapse, p >= 0 */
+    int32_t n_syn;              /* synapses, >= 0 */
+    const int32_t *syn_src;     /* [n_syn] (src, dst), src != dst, no duplicate pair */
+    const int32_t *syn_dst;     /* [n_syn] */
+    const int32_t *M;           /* optional [r*m] row-major M_Pi; when non-NULL it must equal
+                                   the Definition 2 matrix of the rules and synapses above */
+    int32_t count_type;         /* snp_count_t */
+} snp_desc;
+
+typedef struct {
+    int32_t path;             /* snp_path */
+    int32_t stop_at_cap;      /* nonzero: snp_run ends when a level reaches frontier_cap */
+    int64_t frontier_cap;     /* > 0: a level keeps only its first frontier_cap new
+                                 configurations (later ones are not recorded as visited);
+                                 0: no cap */
+    int64_t child_budget;     /* > 0: at most this many children are enumerated per level;
+                                 0: no budget */
+    int64_t expand_max_count; /* >= 0: a configuration holding more spikes than this in some
+                                 neuron is recorded but never expanded; < 0: off */
+    int64_t max_rows;         /* > 0: most configurations one run (or one snp_reset and the
+                                 snp_expand calls after it) records, C0 included; sizes the
+                                 visited set */
+    int64_t max_frontier;     /* largest frontier one expansion takes; 0: max_rows */
+    int64_t chunk;            /* most children expanded per device pass; 0: automatic */
+    uint64_t hash_mask;       /* 0: full 64-bit configuration hash; otherwise the hash is
+                                 ANDed with it (forces collisions; results do not change) */
+    void *stream;             /* hipStream_t for all work of the handle; NULL: default */
+} snp_options;
+
+/* Per-level counters of one expansion. */
+typedef struct {
+    int64_t parents;         /* frontier configurations */
+    int64_t halting_parents; /* parents where no rule applies */
+    int64_t children_total;  /* sum of Psi over the parents, saturated at 2^62 */
+    int64_t enumerated;      /* children in canonical order up to where the level stopped:
+                                the cap-filling child, the budget, or all of them */
+    int64_t new_configs;     /* configurations recorded for the level */
+    int64_t chunks;          /* device passes used */
+    int32_t truncated;       /* 1: the level reached frontier_cap */
+    int32_t budget_hit;      /* 1: child_budget ran out with children left */
+    int32_t path_used;       /* snp_path of the last chunk (SPARSE or INT8) */
+    int32_t int8_fallback;   /* 1: INT8 was requested but M does not fit int8 */
+} snp_expand_stats;
+
+typedef struct snp_system snp_system; /* opaque; owns derived tables and the visited set */
+
+/* Validate a system, derive M_Pi (Definition 2) and its device tables, and
+ * allocate the visited set for opt->max_rows configurations.
+ *   desc: host description, copied.  opt: host options, copied (NULL: defaults
+ *   with max_rows = 1<<20).  out: receives the handle.
+ * Errors: SNP_ERR_INVALID for a malformed system (rule order, i < 1, j < 0,
+ * c < 1, p < 0, neuron id out of range, self or duplicate synapse, M that
+ * differs from Definition 2, bad count_type or options); SNP_ERR_DEVICE. */
+snp_status snp_load(const snp_desc *desc, const snp_options *opt, snp_system **out);
+
+/* Release a handle (NULL is ignored). */
+void snp_free(snp_system *sys);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *snp_last_error(void);
+
+/* Number of bytes of one row (m * size of the count type). */
+int64_t snp_row_bytes(const snp_system *sys);
+
+/* Start a caller-driven walk: forget every visited configuration and record
+ * C0 (device pointer, one row) as level 0 in the handle's own row store.
+ * Errors: SNP_ERR_OVERFLOW if C0 holds a count outside the type's range (only
+ * negative counts can be out of range for int32 here). */
+snp_status snp_reset(snp_system *sys, const void *c0_dev);
+
+/* Expand one level (Algorithm 1 steps II-III for every frontier configuration).
+ *   frontier_dev: device pointer, n rows.  The children of these rows are
+ *     enumerated in canonical order and compared with every configuration
+ *     recorded since snp_reset (earlier levels and earlier children).
+ *   next_dev: device pointer with room for next_capacity rows; receives the new
+ *     configurations in first-occurrence order.  *n_next (host) receives their
+ *     number.  They are also recorded in the handle as visited.
+ *   parent_of_next: nullable device int64 [next_capacity]: index in
+ *     frontier_dev of the parent of every new row.
+ *   child_of_next: nullable device int64 [next_capacity]: child index t of every
+ *     new row within its parent (canonical order).
+ *   stats: nullable host pointer, filled on success.
+ * frontier_cap, child_budget and expand_max_count of the options apply.
+ * Errors: SNP_ERR_CAPACITY when the new rows exceed next_capacity or the
+ *   handle's max_rows, or n exceeds max_frontier; *n_next then receives the
+ *   number of new rows found so far (a lower bound) and the visited set is left
+ *   as it was before the call.  SNP_ERR_OVERFLOW when a child's count leaves
+ *   the type's range (the visited set is then left as before the call). */
+snp_status snp_expand(snp_system *sys, const void *frontier_dev, int64_t n, void *next_dev,
+                      int64_t next_capacity, int64_t *n_next, int64_t *parent_of_next,
+                      int64_t *child_of_next, snp_expand_stats *stats);
+
+/* Breadth-first walk from C0 (Algorithm 1) until a stop condition.
+ *   c0_dev: device pointer, one row.
+ *   max_depth: levels to expand; < 0: no depth limit.
+ *   out_dev: device pointer with room for out_capacity rows; receives every
+ *     recorded configuration, level after level (level 0 = C0), and serves as
+ *     the run's row store (no other copy of the rows is made).
+ *   *n_configs (host): rows written.
+ *   level_sizes: host int64 [max_levels]: rows of every level; *n_levels (host)
+ *     receives the number of levels (an expansion that yields nothing adds none).
+ *   *stop_reason (host): snp_stop.
+ *   level_stats: nullable host [max_levels]: counters of the expansion of each
+ *     level (zeros for a level that was not expanded).
+ *   parent_of: nullable device int64 [out_capacity]: row index (in out_dev) of
+ *     the parent of every row, -1 for C0.
+ *   child_of: nullable device int64 [out_capacity]: child index t of every row
+ *     within its parent (canonical order), -1 for C0.
+ * Errors: SNP_ERR_CAPACITY when out_capacity, max_levels or max_rows is too
+ *   small (rows and levels written so far stay valid and *n_configs, *n_levels
+ *   say how many); SNP_ERR_OVERFLOW as for snp_expand. */
+snp_status snp_run(snp_system *sys, const void *c0_dev, int32_t max_depth, void *out_dev,
+                   int64_t out_capacity, int64_t *n_configs, int64_t *level_sizes, int32_t max_levels,
+                   int32_t *n_levels, int32_t *stop_reason, snp_expand_stats *level_stats,
+                   int64_t *parent_of, int64_t *child_of);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNP_H */

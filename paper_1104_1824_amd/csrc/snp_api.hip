@@ -1,0 +1,540 @@
+// C ABI of libsnp: validation and derivation of a system's tables, the visited
+// set, and the host loop over levels and chunks that drives the kernels of
+// snp_kernels.hip.  Semantics of every entry point are documented in snp.h.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <climits>
+#include <string>
+#include <vector>
+
+#include "snp.h"
+#include "snp_internal.hpp"
+
+using snp::u64;
+
+namespace {
+
+thread_local std::string g_err;
+
+snp_status fail(snp_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                            \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return fail(SNP_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kMaxRulesPerNeuron = 32;  // applicable-rule masks are 32-bit
+constexpr int kMaxNeurons = 4608;       // per-wave LDS state of the expansion kernel (14 B per neuron) <= 64 KiB
+constexpr long long kInf = LLONG_MAX / 4;
+
+u64 next_pow2(u64 x) {
+    u64 p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+template <typename P>
+hipError_t dmalloc(P** p, size_t bytes) {
+    return hipMalloc((void**)p, bytes > 0 ? bytes : 16);
+}
+
+}  // namespace
+
+struct snp_system {
+    int m = 0, r = 0, elem_bytes = 4;
+    long long count_max = INT_MAX;
+    snp_options opt{};
+    hipStream_t stream = nullptr;
+    bool int8_ok = false;
+
+    // device tables
+    int* d_nrule_ptr = nullptr;
+    int4* d_rules = nullptr;
+    int* d_in_ptr = nullptr;
+    int* d_in_src = nullptr;
+    snp::DevSystem dsys{};
+
+    // visited set
+    u64* d_table = nullptr;
+    u64 slots = 0;
+    long long tombs = 0;
+    uint32_t* d_row_slot = nullptr;
+    long long max_rows = 0, max_frontier = 0, chunk_max = 0;
+
+    // per-frontier and per-chunk buffers
+    u64 *d_psi = nullptr, *d_off = nullptr, *d_sc_sums = nullptr, *d_sc_pre = nullptr;
+    void* d_stage = nullptr;
+    u64* d_hash = nullptr;
+    int* d_cpar = nullptr;
+    u64* d_ct = nullptr;
+    uint32_t *d_slot = nullptr, *d_flag = nullptr, *d_pos = nullptr, *d_fsums = nullptr, *d_fpre = nullptr;
+    snp::DevCounters* d_ctr = nullptr;
+    snp::DevCounters* h_ctr = nullptr;
+
+    // caller-driven walk (snp_reset / snp_expand): the handle's own row store
+    void* d_store = nullptr;
+    bool walk_active = false;
+    long long walk_rows = 0;
+
+    double new_ratio = 1.0;  // new / enumerated of the last chunk (chunk sizing)
+
+    ~snp_system() {
+        void* ptrs[] = {d_nrule_ptr, d_rules, d_in_ptr, d_in_src, d_table, d_row_slot, d_psi, d_off,
+                        d_sc_sums, d_sc_pre, d_stage, d_hash, d_cpar, d_ct, d_slot, d_flag, d_pos,
+                        d_fsums, d_fpre, d_ctr, d_store};
+        for (void* p : ptrs)
+            if (p) (void)hipFree(p);
+        if (h_ctr) (void)hipHostFree(h_ctr);
+    }
+};
+
+namespace {
+
+long long row_bytes(const snp_system* S) { return (long long)S->m * S->elem_bytes; }
+
+snp_status validate(const snp_desc* d) {
+    if (!d) return fail(SNP_ERR_INVALID, "desc is NULL");
+    if (d->m < 1) return fail(SNP_ERR_INVALID, "m must be >= 1 (got %d)", d->m);
+    if (d->m > kMaxNeurons) return fail(SNP_ERR_INVALID, "m above %d is not supported", kMaxNeurons);
+    if (d->r < 0 || d->n_syn < 0) return fail(SNP_ERR_INVALID, "negative r or n_syn");
+    if (d->count_type != SNP_COUNT_I32 && d->count_type != SNP_COUNT_U16)
+        return fail(SNP_ERR_INVALID, "count_type must be SNP_COUNT_I32 or SNP_COUNT_U16");
+    if (d->r > 0 && (!d->rule_neuron || !d->rule_i || !d->rule_j || !d->rule_c || !d->rule_p))
+        return fail(SNP_ERR_INVALID, "rule arrays must be non-NULL when r > 0");
+    if (d->n_syn > 0 && (!d->syn_src || !d->syn_dst))
+        return fail(SNP_ERR_INVALID, "synapse arrays must be non-NULL when n_syn > 0");
+    std::vector<int> per(d->m, 0);
+    for (int k = 0; k < d->r; ++k) {
+        const int n = d->rule_neuron[k];
+        if (n < 0 || n >= d->m) return fail(SNP_ERR_INVALID, "rule %d: neuron %d out of range", k, n);
+        if (k > 0 && n < d->rule_neuron[k - 1])
+            return fail(SNP_ERR_INVALID, "rule %d: rules must be grouped by non-decreasing neuron", k);
+        if (d->rule_i[k] < 1) return fail(SNP_ERR_INVALID, "rule %d: i must be >= 1", k);
+        if (d->rule_j[k] < 0) return fail(SNP_ERR_INVALID, "rule %d: j must be >= 0", k);
+        if (d->rule_c[k] < 1) return fail(SNP_ERR_INVALID, "rule %d: c must be >= 1", k);
+        if (d->rule_p[k] < 0) return fail(SNP_ERR_INVALID, "rule %d: p must be >= 0", k);
+        if (d->rule_p[k] > (1 << 20)) return fail(SNP_ERR_INVALID, "rule %d: p above 2^20", k);
+        if (++per[n] > kMaxRulesPerNeuron)
+            return fail(SNP_ERR_INVALID, "neuron %d has more than %d rules", n, kMaxRulesPerNeuron);
+    }
+    std::vector<std::pair<int, int>> edges;
+    edges.reserve(d->n_syn);
+    for (int e = 0; e < d->n_syn; ++e) {
+        const int s = d->syn_src[e], t = d->syn_dst[e];
+        if (s < 0 || s >= d->m || t < 0 || t >= d->m)
+            return fail(SNP_ERR_INVALID, "synapse %d: neuron out of range", e);
+        if (s == t) return fail(SNP_ERR_INVALID, "synapse %d: self-synapse (%d,%d)", e, s, t);
+        edges.emplace_back(s, t);
+    }
+    std::sort(edges.begin(), edges.end());
+    for (size_t e = 1; e < edges.size(); ++e)
+        if (edges[e] == edges[e - 1])
+            return fail(SNP_ERR_INVALID, "duplicate synapse (%d,%d)", edges[e].first, edges[e].second);
+    return SNP_OK;
+}
+
+// Definition 2, entry (k, n) of M_Pi.
+int def2_entry(const snp_desc* d, const std::vector<std::vector<char>>& adj, int k, int n) {
+    const int owner = d->rule_neuron[k];
+    if (n == owner) return -d->rule_c[k];
+    if (adj[owner][n]) return d->rule_p[k];
+    return 0;
+}
+
+snp_status validate_options(const snp_options* o) {
+    if (o->path < SNP_PATH_AUTO || o->path > SNP_PATH_INT8) return fail(SNP_ERR_INVALID, "bad path");
+    if (o->frontier_cap < 0 || o->child_budget < 0 || o->chunk < 0 || o->max_frontier < 0)
+        return fail(SNP_ERR_INVALID, "negative frontier_cap, child_budget, chunk or max_frontier");
+    if (o->max_rows < 1 || o->max_rows >= (long long)snp::kStageBase)
+        return fail(SNP_ERR_INVALID, "max_rows must be in [1, 2^31)");
+    if (o->chunk > (long long)snp::kMaxChunk) return fail(SNP_ERR_INVALID, "chunk above 2^30");
+    return SNP_OK;
+}
+
+snp_status read_counters(snp_system* S) {
+    HIPCHK(hipMemcpyAsync(S->h_ctr, S->d_ctr, sizeof(snp::DevCounters), hipMemcpyDeviceToHost, S->stream));
+    HIPCHK(hipStreamSynchronize(S->stream));
+    return SNP_OK;
+}
+
+snp_status clear_counters(snp_system* S) {
+    HIPCHK(hipMemsetAsync(S->d_ctr, 0, sizeof(snp::DevCounters), S->stream));
+    return SNP_OK;
+}
+
+// Empty the visited set and insert rows [0, rows) of the row store.
+snp_status rebuild_table(snp_system* S, const void* arena, long long rows) {
+    HIPCHK(snp::launch_fill_u64(S->d_table, (long long)S->slots, snp::kEmpty, S->stream));
+    HIPCHK(snp::launch_rows_insert(S->elem_bytes, S->m, S->d_table, S->slots - 1, arena, 0, rows,
+                                   S->opt.hash_mask ? S->opt.hash_mask : ~0ULL, S->d_row_slot, S->d_ctr,
+                                   S->stream));
+    S->tombs = 0;
+    return SNP_OK;
+}
+
+// Record C0 as the only visited configuration, stored at arena row 0.
+snp_status start_walk(snp_system* S, const void* c0_dev, void* arena) {
+    if (!c0_dev) return fail(SNP_ERR_INVALID, "c0 is NULL");
+    snp_status st;
+    if ((st = clear_counters(S))) return st;
+    if (arena != c0_dev) HIPCHK(hipMemcpyAsync(arena, c0_dev, row_bytes(S), hipMemcpyDeviceToDevice, S->stream));
+    HIPCHK(snp::launch_check_rows(S->elem_bytes, arena, S->m, S->count_max, S->d_ctr, S->stream));
+    if ((st = rebuild_table(S, arena, 1))) return st;
+    if ((st = read_counters(S))) return st;
+    if (S->h_ctr->overflow) return fail(SNP_ERR_OVERFLOW, "C0 holds a count outside the count type's range");
+    if (S->h_ctr->probe_fail) return fail(SNP_ERR_DEVICE, "visited set: no free slot");
+    return SNP_OK;
+}
+
+struct LevelIO {
+    const void* frontier;
+    long long n;
+    void* arena;            // row store
+    long long level_base;   // rows recorded before this level
+    long long arena_cap;    // rows the row store holds
+    long long limit_sem;    // frontier_cap (kInf: none)
+    long long limit_cap;    // caller buffer capacity (kInf: none)
+    void* row2;             // nullable copy destination
+    long long* par_out;
+    long long par_out_base;
+    long long par_value_base;
+    long long* t_out;
+};
+
+snp_status rollback_level(snp_system* S, long long first, long long count) {
+    HIPCHK(snp::launch_rollback(S->d_row_slot, S->d_table, first, count, S->stream));
+    HIPCHK(hipStreamSynchronize(S->stream));
+    S->tombs += count;
+    return SNP_OK;
+}
+
+// One BFS level: children of io.frontier, deduplicated, committed in order.
+snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out, long long* count_out) {
+    snp_expand_stats stt{};
+    *count_out = 0;
+    stt.parents = io.n;
+    stt.path_used = SNP_PATH_SPARSE;
+    stt.int8_fallback = (S->opt.path == SNP_PATH_INT8 && !S->int8_ok) ? 1 : 0;
+    if (io.n > S->max_frontier)
+        return fail(SNP_ERR_CAPACITY, "frontier of %lld rows exceeds max_frontier %lld", io.n, S->max_frontier);
+    snp_status st;
+    if (io.n <= 0) {
+        if (out) *out = stt;
+        return SNP_OK;
+    }
+    const u64 hmask = S->opt.hash_mask ? S->opt.hash_mask : ~0ULL;
+
+    // Psi per parent and its exclusive prefix sum
+    if ((st = clear_counters(S))) return st;
+    HIPCHK(snp::launch_psi(S->elem_bytes, S->dsys, io.frontier, io.n, S->opt.expand_max_count, S->d_psi, S->d_ctr,
+                           S->stream));
+    HIPCHK(snp::launch_scan_u64(S->d_psi, S->d_off, io.n, S->d_sc_sums, S->d_sc_pre, &S->d_ctr->total, S->stream));
+    if ((st = read_counters(S))) return st;
+    const u64 T = S->h_ctr->total;
+    stt.halting_parents = (long long)S->h_ctr->halting;
+    stt.children_total = (long long)T;
+    const u64 budget = S->opt.child_budget > 0 ? (u64)S->opt.child_budget : ~0ULL;
+    const u64 T_eff = std::min(T, budget);
+
+    const long long cap_limit = std::min(io.limit_cap, io.arena_cap - io.level_base);
+    const long long limit = std::min(io.limit_sem, cap_limit);
+    const bool sem_binds = io.limit_sem <= cap_limit;
+    long long count = 0;
+    u64 G = 0;
+    u64 enumerated = T_eff;
+    bool cap_hit = false;
+    while (G < T_eff) {
+        long long B = (long long)std::min<u64>((u64)S->chunk_max, T_eff - G);
+        if (io.limit_sem < kInf) {
+            const double ratio = std::max(S->new_ratio, 1.0 / 64.0);
+            const double want = (double)(io.limit_sem - count) / ratio * 1.1 + 1024.0;
+            if (want < (double)B) B = std::max<long long>((long long)want, std::min<long long>(B, 4096));
+        }
+        // keep the table at most half full (tombstones included)
+        const long long live = io.level_base + count;
+        if ((u64)(live + S->tombs + B) * 2 > S->slots) {
+            if ((st = rebuild_table(S, io.arena, live))) return st;
+            if ((u64)(live + B) * 2 > S->slots)
+                return fail(SNP_ERR_CAPACITY, "visited set too small for %lld rows", live + B);
+        }
+        if ((st = clear_counters(S))) return st;
+        snp::ChunkArgs ca{io.frontier, io.n, S->d_psi, S->d_off, G, B, S->d_stage, S->d_hash, S->d_cpar, S->d_ct,
+                          hmask, S->d_ctr};
+        HIPCHK(snp::launch_expand_sparse(S->elem_bytes, S->dsys, ca, S->stream));
+        snp::TableArgs ta{S->d_table, S->slots - 1, io.arena, S->d_stage, S->d_hash, S->d_slot, B, S->d_ctr};
+        HIPCHK(snp::launch_insert(S->elem_bytes, S->m, ta, S->stream));
+        HIPCHK(snp::launch_flags(S->d_table, S->d_slot, B, S->d_flag, S->stream));
+        HIPCHK(snp::launch_scan_u32(S->d_flag, S->d_pos, B, S->d_fsums, S->d_fpre, &S->d_ctr->total, S->stream));
+        snp::CommitArgs cm{S->d_table, S->d_table, S->d_slot, S->d_hash, S->d_pos, S->d_flag, S->d_stage,
+                           S->d_cpar, S->d_ct, B, io.arena, io.level_base, count, limit, io.row2, io.par_out,
+                           io.par_out_base, io.par_value_base, io.t_out, S->d_row_slot, S->d_ctr};
+        HIPCHK(snp::launch_commit(S->elem_bytes, S->m, cm, S->stream));
+        if ((st = read_counters(S))) return st;
+        ++stt.chunks;
+        const snp::DevCounters c = *S->h_ctr;
+        S->tombs += (long long)c.tombs;
+        const long long new_total = (long long)c.total;
+        const long long avail = limit - count;
+        const long long committed = std::min(new_total, avail);
+        if (c.probe_fail) return fail(SNP_ERR_DEVICE, "visited set: probe found no free slot");
+        if (c.overflow) {
+            if ((st = rollback_level(S, io.level_base, count + committed))) return st;
+            *count_out = count;
+            return fail(SNP_ERR_OVERFLOW, "a child configuration holds a count above %lld", S->count_max);
+        }
+        S->new_ratio = (double)new_total / (double)B;
+        if (new_total >= avail && sem_binds && avail > 0) {
+            count = limit;
+            cap_hit = true;
+            enumerated = G + c.cap_g;
+            break;
+        }
+        if (new_total > avail) {
+            if ((st = rollback_level(S, io.level_base, count + committed))) return st;
+            *count_out = count + new_total;
+            return fail(SNP_ERR_CAPACITY, "level needs more than %lld rows", cap_limit);
+        }
+        count += new_total;
+        G += (u64)B;
+    }
+    stt.enumerated = (long long)enumerated;
+    stt.new_configs = count;
+    stt.truncated = cap_hit ? 1 : 0;
+    stt.budget_hit = (!cap_hit && T > budget) ? 1 : 0;
+    if (out) *out = stt;
+    *count_out = count;
+    return SNP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* snp_last_error(void) { return g_err.c_str(); }
+
+int64_t snp_row_bytes(const snp_system* S) { return S ? row_bytes(S) : 0; }
+
+void snp_free(snp_system* S) { delete S; }
+
+snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
+    g_err.clear();
+    if (!out) return fail(SNP_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    snp_status st = validate(d);
+    if (st) return st;
+    snp_options opt{};
+    if (o) opt = *o;
+    else opt.max_rows = 1 << 20;
+    if ((st = validate_options(&opt))) return st;
+
+    // Definition 2 cross-check of a caller-supplied M, and the int8 range test.
+    std::vector<std::vector<char>> adj(d->m, std::vector<char>(d->m, 0));
+    for (int e = 0; e < d->n_syn; ++e) adj[d->syn_src[e]][d->syn_dst[e]] = 1;
+    bool int8_ok = true;
+    for (int k = 0; k < d->r; ++k) {
+        if (d->rule_c[k] > 127 || d->rule_p[k] > 127) int8_ok = false;
+        if (d->M)
+            for (int n = 0; n < d->m; ++n) {
+                const int want = def2_entry(d, adj, k, n);
+                if (d->M[(long long)k * d->m + n] != want)
+                    return fail(SNP_ERR_INVALID, "M[%d][%d] = %d but Definition 2 gives %d", k, n,
+                                d->M[(long long)k * d->m + n], want);
+            }
+    }
+
+    snp_system* S = new snp_system();
+    S->m = d->m;
+    S->r = d->r;
+    S->elem_bytes = d->count_type == SNP_COUNT_U16 ? 2 : 4;
+    S->count_max = d->count_type == SNP_COUNT_U16 ? 65535 : INT_MAX;
+    S->opt = opt;
+    S->stream = (hipStream_t)opt.stream;
+    S->int8_ok = int8_ok;
+    S->max_rows = opt.max_rows;
+    S->max_frontier = opt.max_frontier > 0 ? opt.max_frontier : opt.max_rows;
+    const long long rb = row_bytes(S);
+    S->chunk_max = opt.chunk > 0 ? opt.chunk : std::min<long long>(1 << 20, std::max<long long>(4096, (1LL << 28) / rb));
+
+    // rule tables (rules of a neuron are contiguous: validated order)
+    std::vector<int> nrule_ptr(d->m + 1, 0);
+    for (int k = 0; k < d->r; ++k) nrule_ptr[d->rule_neuron[k] + 1]++;
+    for (int n = 0; n < d->m; ++n) nrule_ptr[n + 1] += nrule_ptr[n];
+    std::vector<int4> rules(d->r);
+    for (int k = 0; k < d->r; ++k) rules[k] = make_int4(d->rule_i[k], d->rule_j[k], d->rule_c[k], d->rule_p[k]);
+    // in-synapses of every neuron (column view of the synapse part of M)
+    std::vector<int> in_ptr(d->m + 1, 0), in_src(d->n_syn), fill(d->m, 0);
+    for (int e = 0; e < d->n_syn; ++e) in_ptr[d->syn_dst[e] + 1]++;
+    for (int n = 0; n < d->m; ++n) in_ptr[n + 1] += in_ptr[n];
+    for (int e = 0; e < d->n_syn; ++e) {
+        const int t = d->syn_dst[e];
+        in_src[in_ptr[t] + fill[t]++] = d->syn_src[e];
+    }
+    for (int n = 0; n < d->m; ++n) std::sort(in_src.begin() + in_ptr[n], in_src.begin() + in_ptr[n + 1]);
+
+    auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+        if (bytes == 0) return hipSuccess;
+        return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    };
+#define LOADCHK(expr)                                                                                \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess) {                                                                      \
+            delete S;                                                                                \
+            return fail(SNP_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));                    \
+        }                                                                                            \
+    } while (0)
+    LOADCHK(dmalloc(&S->d_nrule_ptr, sizeof(int) * (d->m + 1)));
+    LOADCHK(dmalloc(&S->d_rules, sizeof(int4) * d->r));
+    LOADCHK(dmalloc(&S->d_in_ptr, sizeof(int) * (d->m + 1)));
+    LOADCHK(dmalloc(&S->d_in_src, sizeof(int) * d->n_syn));
+    LOADCHK(up(S->d_nrule_ptr, nrule_ptr.data(), sizeof(int) * (d->m + 1)));
+    LOADCHK(up(S->d_rules, rules.data(), sizeof(int4) * d->r));
+    LOADCHK(up(S->d_in_ptr, in_ptr.data(), sizeof(int) * (d->m + 1)));
+    LOADCHK(up(S->d_in_src, in_src.data(), sizeof(int) * d->n_syn));
+    S->dsys = snp::DevSystem{d->m, d->r, S->d_nrule_ptr, S->d_rules, S->d_in_ptr, S->d_in_src, nullptr,
+                             S->count_max};
+
+    S->slots = next_pow2((u64)std::max<long long>(1024, 2 * (S->max_rows + 2 * S->chunk_max)));
+    LOADCHK(dmalloc(&S->d_table, sizeof(u64) * S->slots));
+    LOADCHK(dmalloc(&S->d_row_slot, sizeof(uint32_t) * S->max_rows));
+    const long long F = S->max_frontier;
+    LOADCHK(dmalloc(&S->d_psi, sizeof(u64) * F));
+    LOADCHK(dmalloc(&S->d_off, sizeof(u64) * F));
+    const long long ft = snp::scan_tiles(std::max(F, S->chunk_max)) + 1;
+    LOADCHK(dmalloc(&S->d_sc_sums, sizeof(u64) * ft));
+    LOADCHK(dmalloc(&S->d_sc_pre, sizeof(u64) * ft));
+    const long long C = S->chunk_max;
+    LOADCHK(dmalloc(&S->d_stage, (size_t)(C * rb)));
+    LOADCHK(dmalloc(&S->d_hash, sizeof(u64) * C));
+    LOADCHK(dmalloc(&S->d_cpar, sizeof(int) * C));
+    LOADCHK(dmalloc(&S->d_ct, sizeof(u64) * C));
+    LOADCHK(dmalloc(&S->d_slot, sizeof(uint32_t) * C));
+    LOADCHK(dmalloc(&S->d_flag, sizeof(uint32_t) * C));
+    LOADCHK(dmalloc(&S->d_pos, sizeof(uint32_t) * C));
+    LOADCHK(dmalloc(&S->d_fsums, sizeof(uint32_t) * ft));
+    LOADCHK(dmalloc(&S->d_fpre, sizeof(uint32_t) * ft));
+    LOADCHK(dmalloc(&S->d_ctr, sizeof(snp::DevCounters)));
+    LOADCHK(hipHostMalloc((void**)&S->h_ctr, sizeof(snp::DevCounters), hipHostMallocDefault));
+#undef LOADCHK
+    *out = S;
+    return SNP_OK;
+}
+
+snp_status snp_reset(snp_system* S, const void* c0_dev) {
+    g_err.clear();
+    if (!S) return fail(SNP_ERR_INVALID, "handle is NULL");
+    if (!S->d_store) HIPCHK(dmalloc(&S->d_store, (size_t)(S->max_rows * row_bytes(S))));
+    S->walk_active = false;
+    snp_status st = start_walk(S, c0_dev, S->d_store);
+    if (st) return st;
+    S->walk_active = true;
+    S->walk_rows = 1;
+    return SNP_OK;
+}
+
+snp_status snp_expand(snp_system* S, const void* frontier_dev, int64_t n, void* next_dev, int64_t next_capacity,
+                      int64_t* n_next, int64_t* parent_of_next, int64_t* child_of_next, snp_expand_stats* stats) {
+    g_err.clear();
+    if (!S) return fail(SNP_ERR_INVALID, "handle is NULL");
+    if (!n_next) return fail(SNP_ERR_INVALID, "n_next is NULL");
+    *n_next = 0;
+    if (!S->walk_active) return fail(SNP_ERR_INVALID, "snp_expand before snp_reset");
+    if (n < 0 || next_capacity < 0) return fail(SNP_ERR_INVALID, "negative n or next_capacity");
+    if (n > 0 && !frontier_dev) return fail(SNP_ERR_INVALID, "frontier is NULL");
+    if (next_capacity > 0 && !next_dev) return fail(SNP_ERR_INVALID, "next is NULL");
+    const long long rb = row_bytes(S);
+    const char* f0 = (const char*)frontier_dev;
+    const char* n0 = (const char*)next_dev;
+    if (n > 0 && next_capacity > 0 && f0 < n0 + next_capacity * rb && n0 < f0 + n * rb)
+        return fail(SNP_ERR_INVALID, "frontier and next buffers overlap");
+    LevelIO io{frontier_dev, n, S->d_store, S->walk_rows, S->max_rows,
+               S->opt.frontier_cap > 0 ? S->opt.frontier_cap : kInf, next_capacity, next_dev,
+               (long long*)parent_of_next, 0, 0, (long long*)child_of_next};
+    long long count = 0;
+    snp_status st = expand_level(S, io, stats, &count);
+    *n_next = count;
+    if (st) return st;
+    S->walk_rows += count;
+    return SNP_OK;
+}
+
+snp_status snp_run(snp_system* S, const void* c0_dev, int32_t max_depth, void* out_dev, int64_t out_capacity,
+                   int64_t* n_configs, int64_t* level_sizes, int32_t max_levels, int32_t* n_levels,
+                   int32_t* stop_reason, snp_expand_stats* level_stats, int64_t* parent_of,
+                   int64_t* child_of) {
+    g_err.clear();
+    if (!S) return fail(SNP_ERR_INVALID, "handle is NULL");
+    if (!out_dev || !n_configs || !level_sizes || !n_levels || !stop_reason)
+        return fail(SNP_ERR_INVALID, "out, n_configs, level_sizes, n_levels and stop_reason are required");
+    if (out_capacity < 1 || max_levels < 1) return fail(SNP_ERR_CAPACITY, "out_capacity and max_levels must be >= 1");
+    *n_configs = 0;
+    *n_levels = 0;
+    *stop_reason = SNP_STOP_DEPTH;
+    S->walk_active = false;
+    if (level_stats) memset(level_stats, 0, sizeof(snp_expand_stats) * (size_t)max_levels);
+    const long long rb = row_bytes(S);
+    snp_status st = start_walk(S, c0_dev, out_dev);
+    if (st) return st;
+    if (parent_of) HIPCHK(hipMemsetAsync(parent_of, 0xFF, sizeof(int64_t), S->stream));  // -1 for C0
+    if (child_of) HIPCHK(hipMemsetAsync(child_of, 0xFF, sizeof(int64_t), S->stream));
+    const long long arena_cap = std::min<long long>(out_capacity, S->max_rows);
+    long long rows = 1, lv_begin = 0, lv_end = 1;
+    int32_t levels = 1;
+    level_sizes[0] = 1;
+    *n_configs = 1;
+    *n_levels = 1;
+    int32_t stop = SNP_STOP_DEPTH;
+    for (;;) {
+        const int32_t depth = levels - 1;
+        if (max_depth >= 0 && depth >= max_depth) {
+            stop = SNP_STOP_DEPTH;
+            break;
+        }
+        if (levels >= max_levels) {
+            HIPCHK(hipStreamSynchronize(S->stream));
+            return fail(SNP_ERR_CAPACITY, "more than max_levels = %d levels", max_levels);
+        }
+        LevelIO io{(const char*)out_dev + lv_begin * rb, lv_end - lv_begin, out_dev, rows, arena_cap,
+                   S->opt.frontier_cap > 0 ? S->opt.frontier_cap : kInf, kInf, nullptr, (long long*)parent_of,
+                   rows, lv_begin, (long long*)child_of};
+        snp_expand_stats es{};
+        long long count = 0;
+        st = expand_level(S, io, &es, &count);
+        if (st) {
+            if (st == SNP_ERR_CAPACITY && rows + count > arena_cap)
+                return fail(SNP_ERR_CAPACITY, "run needs more than %lld rows (out_capacity or max_rows)", arena_cap);
+            return st;
+        }
+        if (level_stats) level_stats[depth] = es;
+        const bool all_halting = es.halting_parents == es.parents;
+        if (count > 0) {
+            level_sizes[levels++] = count;
+            lv_begin = lv_end;
+            lv_end = rows + count;
+            rows += count;
+            *n_configs = rows;
+            *n_levels = levels;
+        }
+        if (all_halting) { stop = SNP_STOP_ALL_HALTING; break; }
+        if (es.truncated && S->opt.stop_at_cap) { stop = SNP_STOP_CAP; break; }
+        if (es.budget_hit) { stop = SNP_STOP_BUDGET; break; }
+        if (count == 0) { stop = SNP_STOP_EMPTY_FRONTIER; break; }
+    }
+    *stop_reason = stop;
+    HIPCHK(hipStreamSynchronize(S->stream));
+    return SNP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+// Internal interface between the C-ABI runtime (snp_api.hip) and the gfx950
+// kernels (snp_kernels.hip).  Not installed, not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace snp {
+
+typedef unsigned long long u64;
+
+// Saturation point of child counts Psi and of their prefix sums (2^62): every
+// count at or above it is "too many to enumerate", and sums of two such values
+// still fit in 64 bits.
+constexpr u64 kPsiSat = 1ULL << 62;
+
+// Visited-set entry: high 32 bits = hash tag, low 32 bits = row reference.
+// References below kStageBase name rows of the row store (the configurations
+// recorded so far); kStageBase + b names child b of the chunk being expanded.
+constexpr uint32_t kStageBase = 0x80000000u;
+constexpr uint32_t kMaxChunk = 1u << 30;
+constexpr u64 kEmpty = ~0ULL;           // never a valid entry (reference 0xFFFFFFFF)
+constexpr u64 kTomb = ~0ULL - 1;        // removed entry (reference 0xFFFFFFFE); never reused
+
+// Device counters one expansion pass reads back in a single copy.
+struct DevCounters {
+    u64 halting;       // parents with no applicable rule
+    u64 overflow;      // nonzero: a child count left the type's range
+    u64 probe_fail;    // nonzero: a probe sequence found no free slot
+    u64 cap_g;         // chunk-relative index + 1 of the child that filled the cap (0: none)
+    u64 tombs;         // entries turned into tombstones by this pass
+    u64 total;         // scan total (children of the frontier / new children of a chunk)
+    u64 pad[2];
+};
+
+// Device-side description of a loaded system.
+struct DevSystem {
+    int m, r;
+    const int* nrule_ptr;  // [m+1] rules of neuron n: nrule_ptr[n] .. nrule_ptr[n+1]
+    const int4* rules;     // [r] (i, j, c, p)
+    const int* in_ptr;     // [m+1] in-synapses of neuron d: in_src[in_ptr[d] .. in_ptr[d+1])
+    const int* in_src;     // sources of the in-synapses
+    const int8_t* M8;      // [r*m] int8 copy of M_Pi (nullptr when some |entry| > 127)
+    long long count_max;
+};
+
+// One chunk of children [g0, g0 + B) of the frontier.
+struct ChunkArgs {
+    const void* frontier;  // n rows
+    long long n;
+    const u64* psi;        // [n] children per parent (0: none)
+    const u64* off;        // [n] exclusive prefix sums of psi
+    u64 g0;
+    long long B;
+    void* stage;           // [B] child rows
+    u64* hash;             // [B]
+    int* cpar;             // [B] parent index in the frontier
+    u64* ct;               // [B] child index within the parent
+    u64 hash_mask;
+    DevCounters* ctr;
+};
+
+// Insert/commit arguments.
+struct TableArgs {
+    u64* table;
+    u64 slot_mask;
+    const void* arena;     // row store (rows referenced by entries below kStageBase)
+    const void* stage;
+    const u64* hash;
+    uint32_t* slot;        // [B] slot each child resolved to
+    long long B;
+    DevCounters* ctr;
+};
+
+struct CommitArgs {
+    const u64* table_ro;
+    u64* table;
+    const uint32_t* slot;
+    const u64* hash;
+    const uint32_t* pos;   // [B] exclusive scan of the new-child flags
+    const uint32_t* flag;  // [B] 1: child is the first occurrence of a new configuration
+    const void* stage;
+    const int* cpar;
+    const u64* ct;
+    long long B;
+    void* arena;           // row store
+    long long level_base;  // row-store index of the level's first row
+    long long level_count; // rows of the level recorded before this chunk
+    long long limit;       // most rows the level may hold
+    void* row2;            // nullable second destination (index level_count + pos)
+    long long* par_out;    // nullable parent index output
+    long long par_out_base;
+    long long par_value_base;
+    long long* t_out;      // nullable child index output
+    uint32_t* row_slot;    // [max_rows] slot of every row-store row
+    DevCounters* ctr;
+};
+
+hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, long long n,
+                      long long expand_max, u64* psi, DevCounters* ctr, hipStream_t st);
+hipError_t launch_scan_u64(const u64* in, u64* out, long long n, u64* tile_sums, u64* tile_pre,
+                           u64* total, hipStream_t st);
+hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, long long n, uint32_t* tile_sums,
+                           uint32_t* tile_pre, u64* total, hipStream_t st);
+long long scan_tiles(long long n);
+hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st);
+hipError_t launch_insert(int elem_bytes, int m, const TableArgs& a, hipStream_t st);
+hipError_t launch_flags(const u64* table, const uint32_t* slot, long long B, uint32_t* flag, hipStream_t st);
+hipError_t launch_commit(int elem_bytes, int m, const CommitArgs& a, hipStream_t st);
+hipError_t launch_fill_u64(u64* p, long long n, u64 v, hipStream_t st);
+hipError_t launch_rows_insert(int elem_bytes, int m, u64* table, u64 slot_mask, const void* arena,
+                              long long first, long long count, u64 hash_mask, uint32_t* row_slot,
+                              DevCounters* ctr, hipStream_t st);
+hipError_t launch_rollback(const uint32_t* row_slot, u64* table, long long first, long long count,
+                           hipStream_t st);
+hipError_t launch_check_rows(int elem_bytes, const void* rows, long long n_elems, long long count_max,
+                             DevCounters* ctr, hipStream_t st);
+
+}  // namespace snp

@@ -1,0 +1,222 @@
+"""Thin ctypes binding of libsnp (include/snp.h) with the same entry-point names.
+
+Only argument marshalling happens here: host arrays of a system description
+are passed as-is, device buffers are torch CUDA tensors whose ``data_ptr()``
+is handed to the library, and the handle launches on the torch stream given at
+load.  Every step of the computation runs in the library's HIP kernels; when
+the library is not built, loading fails with an error instead of falling back.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+from .build import library_path
+
+SNP_OK, SNP_ERR_INVALID, SNP_ERR_OVERFLOW, SNP_ERR_CAPACITY, SNP_ERR_BUDGET, SNP_ERR_DEVICE = range(6)
+SNP_COUNT_I32, SNP_COUNT_U16 = 0, 1
+SNP_PATH_AUTO, SNP_PATH_SPARSE, SNP_PATH_INT8 = 0, 1, 2
+STOP_NAMES = {0: "EMPTY_FRONTIER", 1: "ALL_HALTING", 2: "DEPTH", 3: "CAP", 4: "BUDGET"}
+STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OVERFLOW", 3: "CAPACITY", 4: "BUDGET", 5: "DEVICE"}
+
+EXPORTED = ("snp_load", "snp_free", "snp_last_error", "snp_row_bytes", "snp_reset", "snp_expand", "snp_run")
+
+
+class SnpError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class snp_desc(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int32), ("r", ctypes.c_int32),
+        ("rule_neuron", ctypes.c_void_p), ("rule_i", ctypes.c_void_p), ("rule_j", ctypes.c_void_p),
+        ("rule_c", ctypes.c_void_p), ("rule_p", ctypes.c_void_p),
+        ("n_syn", ctypes.c_int32), ("syn_src", ctypes.c_void_p), ("syn_dst", ctypes.c_void_p),
+        ("M", ctypes.c_void_p), ("count_type", ctypes.c_int32),
+    ]
+
+
+class snp_options(ctypes.Structure):
+    _fields_ = [
+        ("path", ctypes.c_int32), ("stop_at_cap", ctypes.c_int32),
+        ("frontier_cap", ctypes.c_int64), ("child_budget", ctypes.c_int64),
+        ("expand_max_count", ctypes.c_int64), ("max_rows", ctypes.c_int64),
+        ("max_frontier", ctypes.c_int64), ("chunk", ctypes.c_int64),
+        ("hash_mask", ctypes.c_uint64), ("stream", ctypes.c_void_p),
+    ]
+
+
+class snp_expand_stats(ctypes.Structure):
+    _fields_ = [
+        ("parents", ctypes.c_int64), ("halting_parents", ctypes.c_int64),
+        ("children_total", ctypes.c_int64), ("enumerated", ctypes.c_int64),
+        ("new_configs", ctypes.c_int64), ("chunks", ctypes.c_int64),
+        ("truncated", ctypes.c_int32), ("budget_hit", ctypes.c_int32),
+        ("path_used", ctypes.c_int32), ("int8_fallback", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libsnp.so; raises if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise FileNotFoundError(
+                f"{path} is missing: build it with __graft_entry__.build() or "
+                "python -m paper_1104_1824_amd.build")
+        L = ctypes.CDLL(path)
+        P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.snp_load.argtypes = [ctypes.POINTER(snp_desc), ctypes.POINTER(snp_options), ctypes.POINTER(P)]
+        L.snp_load.restype = I32
+        L.snp_free.argtypes = [P]
+        L.snp_free.restype = None
+        L.snp_last_error.argtypes = []
+        L.snp_last_error.restype = ctypes.c_char_p
+        L.snp_row_bytes.argtypes = [P]
+        L.snp_row_bytes.restype = I64
+        L.snp_reset.argtypes = [P, P]
+        L.snp_reset.restype = I32
+        L.snp_expand.argtypes = [P, P, I64, P, I64, ctypes.POINTER(I64), P, P, ctypes.POINTER(snp_expand_stats)]
+        L.snp_expand.restype = I32
+        L.snp_run.argtypes = [P, P, I32, P, I64, ctypes.POINTER(I64), P, I32, ctypes.POINTER(I32),
+                              ctypes.POINTER(I32), P, P, P]
+        L.snp_run.restype = I32
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != SNP_OK:
+        raise SnpError(status, where, lib().snp_last_error().decode())
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _ptr(t) -> Optional[int]:
+    """Device pointer of a torch tensor (None stays None)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("device buffers must be contiguous")
+    return t.data_ptr()
+
+
+class Handle:
+    """An loaded system (snp_system*); freed by close() or garbage collection."""
+
+    def __init__(self, ptr: int, keep, m: int, count_type: int):
+        self.ptr = ctypes.c_void_p(ptr)
+        self._keep = keep
+        self.m = m
+        self.count_type = count_type
+
+    def close(self):
+        if self.ptr:
+            lib().snp_free(self.ptr)
+            self.ptr = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def snp_load(system, *, path: int = SNP_PATH_AUTO, stop_at_cap: bool = False, frontier_cap: int = 0,
+             child_budget: int = 0, expand_max_count: int = -1, max_rows: int = 1 << 20,
+             max_frontier: int = 0, chunk: int = 0, hash_mask: int = 0, stream=None,
+             M: Optional[np.ndarray] = None) -> Handle:
+    """snp_load.  ``system`` has m, rule_neuron/i/j/c/p, syn_src/dst and
+    count_type ("i32" or "u16") attributes; ``stream`` is a torch.cuda.Stream
+    (None: torch's current stream)."""
+    arrs = [_i32(system.rule_neuron), _i32(system.rule_i), _i32(system.rule_j), _i32(system.rule_c),
+            _i32(system.rule_p), _i32(system.syn_src), _i32(system.syn_dst)]
+    Mp = None
+    if M is not None:
+        Mp = _i32(M)
+        arrs.append(Mp)
+    ct = SNP_COUNT_U16 if getattr(system, "count_type", "i32") == "u16" else SNP_COUNT_I32
+    d = snp_desc(int(system.m), int(arrs[0].shape[0]), arrs[0].ctypes.data, arrs[1].ctypes.data,
+                 arrs[2].ctypes.data, arrs[3].ctypes.data, arrs[4].ctypes.data, int(arrs[5].shape[0]),
+                 arrs[5].ctypes.data, arrs[6].ctypes.data, Mp.ctypes.data if Mp is not None else None, ct)
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream() if torch.cuda.is_available() else 0
+    sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0)
+    o = snp_options(int(path), int(bool(stop_at_cap)), int(frontier_cap), int(child_budget),
+                    int(expand_max_count), int(max_rows), int(max_frontier), int(chunk),
+                    int(hash_mask) & ((1 << 64) - 1), sp or None)
+    out = ctypes.c_void_p()
+    _check(lib().snp_load(ctypes.byref(d), ctypes.byref(o), ctypes.byref(out)), "snp_load")
+    return Handle(out.value, arrs, int(system.m), ct)
+
+
+def snp_free(h: Handle):
+    h.close()
+
+
+def snp_row_bytes(h: Handle) -> int:
+    return int(lib().snp_row_bytes(h.ptr))
+
+
+def snp_reset(h: Handle, c0_dev):
+    _check(lib().snp_reset(h.ptr, _ptr(c0_dev)), "snp_reset")
+
+
+def snp_expand(h: Handle, frontier_dev, n: int, next_dev, next_capacity: int, parent_of_next=None,
+               child_of_next=None):
+    """Returns (n_next, stats dict)."""
+    n_next = ctypes.c_int64(0)
+    st = snp_expand_stats()
+    status = lib().snp_expand(h.ptr, _ptr(frontier_dev), int(n), _ptr(next_dev), int(next_capacity),
+                              ctypes.byref(n_next), _ptr(parent_of_next), _ptr(child_of_next), ctypes.byref(st))
+    if status != SNP_OK:
+        err = SnpError(status, "snp_expand", lib().snp_last_error().decode())
+        err.n_next = int(n_next.value)
+        raise err
+    return int(n_next.value), st.as_dict()
+
+
+def snp_run(h: Handle, c0_dev, max_depth: int, out_dev, out_capacity: int, max_levels: int = 4096,
+            parent_of=None, child_of=None, with_stats: bool = True) -> dict:
+    """Returns dict(n_configs, level_sizes, stop_reason, level_stats)."""
+    n_configs = ctypes.c_int64(0)
+    n_levels = ctypes.c_int32(0)
+    stop = ctypes.c_int32(0)
+    sizes = np.zeros(max_levels, dtype=np.int64)
+    stats = (snp_expand_stats * max_levels)() if with_stats else None
+    status = lib().snp_run(h.ptr, _ptr(c0_dev), int(max_depth), _ptr(out_dev), int(out_capacity),
+                           ctypes.byref(n_configs), sizes.ctypes.data, int(max_levels), ctypes.byref(n_levels),
+                           ctypes.byref(stop), ctypes.cast(stats, ctypes.c_void_p) if stats is not None else None,
+                           _ptr(parent_of), _ptr(child_of))
+    if status != SNP_OK:
+        err = SnpError(status, "snp_run", lib().snp_last_error().decode())
+        err.n_configs = int(n_configs.value)
+        raise err
+    L = int(n_levels.value)
+    return dict(
+        n_configs=int(n_configs.value),
+        level_sizes=sizes[:L].copy(),
+        stop_reason=int(stop.value),
+        level_stats=[stats[k].as_dict() for k in range(L)] if stats is not None else None,
+    )
+
+
+def torch_dtype(count_type: int):
+    import torch
+    return torch.uint16 if count_type == SNP_COUNT_U16 else torch.int32

@@ -1,0 +1,225 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle: element by
+element on the same seeded inputs; all integer, so bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_1104_1824_amd import snp
+from tests.conftest import read_golden
+from tests.gpu_helpers import assert_same_bfs, gpu_bfs, note, to_device_rows, from_device_rows, dev_dtype
+
+pytestmark = pytest.mark.gpu
+
+SPARSE = snp.SNP_PATH_SPARSE
+
+
+def cfg(row):
+    return "-".join(str(int(x)) for x in row)
+
+
+def test_paper_printed_run(gpu, oracle_mod):
+    note("paper example, expand_max_count=9")
+    ex = synth.paper_example()
+    g = gpu_bfs(ex, expand_max_count=9, out_capacity=256)
+    assert [cfg(x) for x in g["rows"]] == read_golden("paper_allgenck.txt")
+    assert g["stop_reason"] == 0
+    assert_same_bfs(g, oracle_mod.bfs(ex, expand_max_count=9))
+
+
+def test_textbook_reading(gpu, oracle_mod):
+    note("paper example, textbook reading")
+    ex = synth.paper_example(True)
+    assert_same_bfs(gpu_bfs(ex, out_capacity=64), oracle_mod.bfs(ex))
+
+
+def test_paper_depth_limited(gpu, oracle_mod):
+    ex = synth.paper_example()
+    for d in (0, 1, 2, 7, 30):
+        note(f"paper example depth {d}")
+        assert_same_bfs(gpu_bfs(ex, max_depth=d, out_capacity=512), oracle_mod.bfs(ex, max_depth=d))
+
+
+@pytest.mark.parametrize("seed", range(100))
+def test_tiny_plain(gpu, oracle_mod, seed):
+    note(f"tiny plain seed {seed}")
+    s = synth.config_system(1, seed)
+    assert_same_bfs(gpu_bfs(s, max_depth=8, out_capacity=4096, chunk=4096), oracle_mod.bfs(s, max_depth=8))
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_plain_sparse_small_cap(gpu, oracle_mod, seed):
+    note(f"plain sparse seed {seed}, cap 3000")
+    s = synth.config_system(2, seed)
+    g = gpu_bfs(s, max_depth=1000, frontier_cap=3000, stop_at_cap=True, out_capacity=20000)
+    assert_same_bfs(g, oracle_mod.bfs(s, max_depth=1000, frontier_cap=3000, stop_at_cap=True))
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_plain_sparse_full(gpu, oracle_mod, seed):
+    """The plain-sparse workload at full size: BFS until a level reaches 1e5."""
+    note(f"plain sparse seed {seed}, full size")
+    s = synth.config_system(2, seed)
+    g = gpu_bfs(s, max_depth=1000, frontier_cap=100000, stop_at_cap=True, out_capacity=400000)
+    assert_same_bfs(g, oracle_mod.bfs(s, max_depth=1000, frontier_cap=100000, stop_at_cap=True))
+
+
+def test_chunk_invariance(gpu, oracle_mod):
+    s = synth.config_system(2, 1)
+    want = oracle_mod.bfs(s, max_depth=1000, frontier_cap=20000, stop_at_cap=True)
+    for chunk in (4096, 5000, 65536, 0):
+        note(f"chunk invariance chunk={chunk}")
+        g = gpu_bfs(s, max_depth=1000, frontier_cap=20000, stop_at_cap=True, out_capacity=60000, chunk=chunk)
+        assert_same_bfs(g, want)
+
+
+@pytest.mark.parametrize("seed", [0, 7, 19, 42])
+def test_hash_collisions(gpu, oracle_mod, seed):
+    """A 4-bit hash makes nearly every probe a tag match: full-row compares
+    must keep the result exact."""
+    note(f"hash mask 0xF, tiny seed {seed}")
+    s = synth.config_system(1, seed)
+    assert_same_bfs(gpu_bfs(s, max_depth=8, out_capacity=4096, chunk=4096, hash_mask=0xF),
+                    oracle_mod.bfs(s, max_depth=8))
+    note(f"hash mask 0xF00000000000000F, plain seed {seed % 5}")
+    s2 = synth.config_system(2, seed % 5)
+    assert_same_bfs(gpu_bfs(s2, max_depth=3, frontier_cap=400, out_capacity=4096,
+                            hash_mask=0xF00000000000000F),
+                    oracle_mod.bfs(s2, max_depth=3, frontier_cap=400))
+
+
+def test_dense_recipe_small_cap(gpu, oracle_mod):
+    note("dense recipe m=512 seed 0, cap 3000, depth 3")
+    s = synth.config_system(3, 0)
+    g = gpu_bfs(s, max_depth=3, frontier_cap=3000, out_capacity=10000)
+    assert_same_bfs(g, oracle_mod.bfs(s, max_depth=3, frontier_cap=3000))
+
+
+def test_large_recipe_small_cap(gpu, oracle_mod):
+    note("large recipe m=4096 u16 seed 0, cap 300, depth 2")
+    s = synth.config_system(5, 0)
+    g = gpu_bfs(s, max_depth=2, frontier_cap=300, out_capacity=1000)
+    assert_same_bfs(g, oracle_mod.bfs(s, max_depth=2, frontier_cap=300))
+
+
+def test_budget_and_cap(gpu, oracle_mod):
+    ex = synth.paper_example()
+    note("budget 1")
+    assert_same_bfs(gpu_bfs(ex, child_budget=1, out_capacity=16), oracle_mod.bfs(ex, child_budget=1))
+    note("cap 1 stop")
+    assert_same_bfs(gpu_bfs(ex, frontier_cap=1, stop_at_cap=True, out_capacity=16),
+                    oracle_mod.bfs(ex, frontier_cap=1, stop_at_cap=True))
+    for seed in (3, 11, 25, 40):
+        note(f"cap truncation tiny seed {seed}")
+        s = synth.config_system(1, seed)
+        assert_same_bfs(gpu_bfs(s, max_depth=5, frontier_cap=2, out_capacity=64, chunk=4096),
+                        oracle_mod.bfs(s, max_depth=5, frontier_cap=2))
+
+
+def test_out_capacity_error(gpu):
+    note("out capacity too small")
+    ex = synth.paper_example()
+    with pytest.raises(snp.SnpError) as e:
+        gpu_bfs(ex, expand_max_count=9, out_capacity=10, max_rows=10)
+    assert e.value.status == snp.SNP_ERR_CAPACITY
+
+
+def test_overflow(gpu, oracle_mod):
+    note("uint16 overflow")
+    s = synth.make_system(2, [(1, 1, 1, 1, 1)], [(1, 0)], [65535, 1], count_type="u16")
+    with pytest.raises(snp.SnpError) as e:
+        gpu_bfs(s, max_depth=2, out_capacity=16)
+    assert e.value.status == snp.SNP_ERR_OVERFLOW
+    note("int32 overflow")
+    s = synth.make_system(2, [(1, 1, 1, 1, 3)], [(1, 0)], [2**31 - 2, 1])
+    with pytest.raises(snp.SnpError) as e:
+        gpu_bfs(s, max_depth=2, out_capacity=16)
+    assert e.value.status == snp.SNP_ERR_OVERFLOW
+    note("int32 at the edge, no overflow")
+    s = synth.make_system(2, [(1, 1, 1, 1, 1)], [(1, 0)], [2**31 - 2, 1])
+    assert_same_bfs(gpu_bfs(s, max_depth=3, out_capacity=16), oracle_mod.bfs(s, max_depth=3))
+
+
+def test_all_halting(gpu, oracle_mod):
+    note("zero configuration halts")
+    ex = synth.paper_example()
+    g = gpu_bfs(ex, c0=[0, 0, 0], out_capacity=8)
+    o = oracle_mod.bfs(ex, c0=[0, 0, 0])
+    assert_same_bfs(g, o)
+    assert g["stop_reason"] == 1  # ALL_HALTING
+
+
+def test_expand_api(gpu, oracle_mod):
+    """snp_reset + snp_expand driven level by level equals the oracle's levels."""
+    import torch
+
+    for seed in (0, 5, 17, 63):
+        note(f"expand api tiny seed {seed}")
+        s = synth.config_system(1, seed)
+        o = oracle_mod.bfs(s, max_depth=6)
+        h = snp.snp_load(s, path=SPARSE, max_rows=4096, chunk=4096)
+        try:
+            snp.snp_reset(h, to_device_rows(s, s.c0))
+            frontier = to_device_rows(s, [s.c0])
+            for k in range(1, o.n_levels):
+                nxt = torch.empty((256, s.m), dtype=dev_dtype(s), device="cuda")
+                par = torch.empty(256, dtype=torch.int64, device="cuda")
+                chi = torch.empty(256, dtype=torch.int64, device="cuda")
+                n, st = snp.snp_expand(h, frontier, frontier.shape[0], nxt, 256, par, chi)
+                assert n == int(o.level_sizes[k])
+                assert from_device_rows(s, nxt[:n]).tolist() == o.level(k).tolist()
+                off = int(o.level_sizes[:k].sum())
+                prev_off = int(o.level_sizes[: k - 1].sum())
+                assert (par[:n].cpu().numpy() + prev_off).tolist() == o.parent[off: off + n].tolist()
+                assert chi[:n].cpu().numpy().tolist() == o.tindex[off: off + n].tolist()
+                frontier = nxt[:n].clone()
+        finally:
+            h.close()
+
+
+def test_expand_errors_and_rollback(gpu, oracle_mod):
+    import torch
+
+    s = synth.config_system(2, 0)
+    h = snp.snp_load(s, path=SPARSE, max_rows=1 << 15)
+    try:
+        note("expand before reset")
+        f = to_device_rows(s, [s.c0])
+        nxt = torch.empty((512, s.m), dtype=torch.int32, device="cuda")
+        with pytest.raises(snp.SnpError) as e:
+            snp.snp_expand(h, f, 1, nxt, 512)
+        assert e.value.status == snp.SNP_ERR_INVALID
+        snp.snp_reset(h, f[0])
+        note("overlapping frontier and next")
+        with pytest.raises(snp.SnpError) as e:
+            snp.snp_expand(h, nxt[:1], 1, nxt, 512)
+        assert e.value.status == snp.SNP_ERR_INVALID
+        note("next capacity too small, then retry")
+        small = torch.empty((10, s.m), dtype=torch.int32, device="cuda")
+        with pytest.raises(snp.SnpError) as e:
+            snp.snp_expand(h, f, 1, small, 10)
+        assert e.value.status == snp.SNP_ERR_CAPACITY
+        n, _ = snp.snp_expand(h, f, 1, nxt, 512)   # the failed call left nothing recorded
+        o = oracle_mod.bfs(s, max_depth=1)
+        assert n == int(o.level_sizes[1])
+        assert from_device_rows(s, nxt[:n]).tolist() == o.level(1).tolist()
+        note("empty frontier")
+        n, st = snp.snp_expand(h, f, 0, small, 10)
+        assert n == 0 and st["parents"] == 0
+        note("frontier already visited")
+        n, st = snp.snp_expand(h, f, 1, small, 10)
+        assert n == 0 and st["enumerated"] == st["children_total"]
+    finally:
+        h.close()
+
+
+def test_nondefault_stream(gpu, oracle_mod):
+    import torch
+
+    note("handle on a side stream")
+    s = synth.config_system(2, 3)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        g = gpu_bfs(s, max_depth=3, frontier_cap=1000, out_capacity=8192, stream=side)
+    torch.cuda.synchronize()
+    assert_same_bfs(g, oracle_mod.bfs(s, max_depth=3, frontier_cap=1000))
