@@ -94,6 +94,8 @@ def _load():
         lib.or_child_at.argtypes = [ctypes.POINTER(_System), P, ctypes.c_int64, P]
         lib.or_mix64.argtypes = [ctypes.c_uint64]
         lib.or_mix64.restype = ctypes.c_uint64
+        lib.or_config_hash.argtypes = [P, ctypes.c_int32]
+        lib.or_config_hash.restype = ctypes.c_uint64
         _lib = lib
     return _lib
 
@@ -168,6 +170,12 @@ def child_at(sys, C, t: int) -> np.ndarray:
 def mix64(z: int) -> int:
     """The SplitMix64 output finaliser used by the trajectory digest."""
     return int(_load().or_mix64(int(z) & ((1 << 64) - 1)))
+
+
+def config_hash(C) -> int:
+    """H(C) = sum_n (uint32)C[n] * mix64((n + 1) * gamma) mod 2^64."""
+    C = _i64(C)
+    return int(_load().or_config_hash(C.ctypes.data, int(C.shape[0])))
 
 
 @dataclass

@@ -462,11 +462,17 @@ int or_bfs(const or_system *sys, const int64_t *c0, const or_bfs_opts *opt, or_b
 /* explores), C_{k+1} = C_k + S_k.M.  The run stops early when no rule        */
 /* applies (halting).                                                        */
 /*                                                                           */
-/* digest = sum over computed steps k (C_0 included) and neurons n of         */
-/*          mix64(k * 2^44 + n * 2^32 + (uint32)C_k[n])   (mod 2^64),          */
-/* mix64 = the SplitMix64 output finaliser (Steele, Lea, Flood 2014).         */
+/* Checksum of a trajectory (a test device, not a quantity of the paper):     */
+/*   R_n    = mix64((n + 1) * gamma)            (the SplitMix64 stream, seed 0) */
+/*   H(C)   = sum over neurons n of (uint32)C[n] * R_n        (mod 2^64)      */
+/*   digest = sum over computed steps k (C_0 included) of                     */
+/*            mix64(H(C_k) + k * gamma)                          (mod 2^64)   */
+/* with mix64 the SplitMix64 output finaliser (Steele, Lea, Flood 2014) and   */
+/* gamma = 0x9E3779B97F4A7C15.                                               */
 /* first_repeat = least k with C_k equal to some C_l, l < k (-1: none).      */
 /* ------------------------------------------------------------------------- */
+#define OR_GAMMA 0x9E3779B97F4A7C15ULL
+
 static uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
@@ -475,11 +481,14 @@ static uint64_t mix64(uint64_t z) {
 
 uint64_t or_mix64(uint64_t z) { return mix64(z); }
 
+uint64_t or_config_hash(const int64_t *C, int32_t m) {
+    uint64_t h = 0;
+    for (int32_t n = 0; n < m; ++n) h += (uint64_t)(uint32_t)C[n] * mix64((uint64_t)(n + 1) * OR_GAMMA);
+    return h;
+}
+
 static uint64_t step_digest(int64_t k, const int64_t *C, int32_t m) {
-    uint64_t d = 0;
-    for (int32_t n = 0; n < m; ++n)
-        d += mix64(((uint64_t)k << 44) + ((uint64_t)n << 32) + (uint64_t)(uint32_t)C[n]);
-    return d;
+    return mix64(or_config_hash(C, m) + (uint64_t)k * OR_GAMMA);
 }
 
 int or_deterministic(const or_system *sys, const int64_t *c0, int32_t steps, int64_t *final_c,

@@ -312,12 +312,27 @@ def test_deterministic_closed_forms(oracle_mod):
     assert d.final.tolist() == [1, 0, 0] and d.halt_step == 2 and d.steps_done == 2
 
 
+GAMMA = 0x9E3779B97F4A7C15
+
+
+def test_config_hash_weights_are_splitmix64_stream(oracle_mod):
+    # H of a unit vector e_n is the n-th output of SplitMix64 seeded with 0
+    r = synth.SplitMix64(0)
+    for n in range(5):
+        e = [0] * 5
+        e[n] = 1
+        assert oracle_mod.config_hash(e) == r.next_u64()
+    # linear in C (mod 2^64)
+    a, b = [3, 0, 7, 1], [1, 2, 0, 5]
+    s = [x + y for x, y in zip(a, b)]
+    assert oracle_mod.config_hash(s) == (oracle_mod.config_hash(a) + oracle_mod.config_hash(b)) % (1 << 64)
+
+
 def test_deterministic_digest_structure(oracle_mod):
-    # digest = sum over steps k and neurons n of mix64(k * 2^44 + n * 2^32 + C_k[n])
+    # digest = sum over computed steps k of mix64(H(C_k) + k * gamma)
     d0 = oracle_mod.deterministic(EX_TB, 0, c0=[1, 0, 0])
-    want = sum(oracle_mod.mix64((n << 32) + v) for n, v in enumerate([1, 0, 0])) % (1 << 64)
-    assert d0.digest == want and d0.steps_done == 0
+    assert d0.digest == oracle_mod.mix64(oracle_mod.config_hash([1, 0, 0])) and d0.steps_done == 0
     d1 = oracle_mod.deterministic(EX_TB, 1, c0=[0, 1, 1])   # C_1 = (1, 0, 1)
-    want1 = (sum(oracle_mod.mix64((n << 32) + v) for n, v in enumerate([0, 1, 1]))
-             + sum(oracle_mod.mix64((1 << 44) + (n << 32) + v) for n, v in enumerate([1, 0, 1]))) % (1 << 64)
+    want1 = (oracle_mod.mix64(oracle_mod.config_hash([0, 1, 1]))
+             + oracle_mod.mix64(oracle_mod.config_hash([1, 0, 1]) + GAMMA)) % (1 << 64)
     assert d1.digest == want1
