@@ -1,0 +1,177 @@
+"""Benchmark: new configurations per second of the breadth-first expansion.
+
+One step is one complete breadth-first walk of the plain-sparse workload
+(seeded synthetic system, m = 64 neurons, 2 rules per neuron, out-degree 4,
+C0 uniform in [0, 4], int32 counts) from C0 until a level reaches 100,000
+configurations: every level runs applicability + Psi, the prefix sum, the
+expansion C' = C + S.M, the visited-set insert and the ordered commit, all on
+the GPU through the C ABI.  The value is new (deduplicated) configurations
+per second over the timed steps; inputs are resident in HBM before timing.
+
+The JSON line also carries the roofline of the dominant kernel (device time
+from HIP events recorded by the library on its stream inside the timed
+region) and the CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "new configurations/sec (deduped) per BFS step; int8-MFMA/batched vs plain sparse"
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def plain_sparse_workload(seed=0):
+    import synth
+
+    return synth.config_system(2, seed), dict(frontier_cap=100000, stop_at_cap=True, max_depth=1000)
+
+
+def run_gpu(system, run_opts, steps, warmup):
+    import torch
+
+    from paper_1104_1824_amd import snp
+
+    cap = 200000
+    h = snp.snp_load(system, path=snp.SNP_PATH_SPARSE, frontier_cap=run_opts["frontier_cap"],
+                     stop_at_cap=run_opts["stop_at_cap"], max_rows=cap, chunk=1 << 17, profile=True)
+    c0 = torch.tensor(system.c0, dtype=torch.int32, device="cuda")
+    out = torch.empty((cap, system.m), dtype=torch.int32, device="cuda")
+    res = None
+    for _ in range(warmup):
+        res = snp.snp_run(h, c0, run_opts["max_depth"], out, cap)
+    torch.cuda.synchronize()
+    results = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        results.append(snp.snp_run(h, c0, run_opts["max_depth"], out, cap))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    h.close()
+    return results, t1 - t0, res
+
+
+def roofline(system, results):
+    """Roofline of the expansion kernel: its algorithmic bytes over its device
+    time.  Algorithmic bytes per launch = children computed x (row bytes written
+    + 20 B of per-child hash, parent index and child index); parent rows, read
+    once per run of children, are not counted."""
+    rb = system.m * 4
+    tot = dict(psi=0, expand=0, insert=0, flags=0, commit=0)
+    launches = 0
+    children = 0
+    for r in results:
+        for st in r["level_stats"]:
+            for k in tot:
+                tot[k] += st["ns_" + k]
+            launches += st["chunks"]
+            children += st["expanded"]
+    steps = len(results)
+    bytes_expand = children * (rb + 20)
+    achieved = bytes_expand / max(1, tot["expand"])  # bytes per ns = GB/s
+    return dict(
+        kernel="k_expand_sparse",
+        dominant_stage=max(tot, key=tot.get),
+        bound="hbm",
+        achieved=round(achieved, 2),
+        peak=HBM_PEAK_GBS,
+        unit="GB/s",
+        frac=round(achieved / HBM_PEAK_GBS, 4),
+        traffic=None,
+        bytes_per_launch=round(bytes_expand / max(1, launches)),
+        avg_launch_us=round(tot["expand"] / max(1, launches) / 1e3, 3),
+        launches_per_step=launches // max(1, steps),
+        stage_us_per_step={k: round(v / 1e3 / max(1, steps), 2) for k, v in tot.items()},
+    )
+
+
+def cpu_baseline(system, run_opts, budget_s=12.0):
+    import oracle
+
+    oracle.build(force=False)
+    n_new = 0
+    runs = 0
+    t0 = time.perf_counter()
+    while True:
+        res = oracle.bfs(system, max_depth=run_opts["max_depth"], frontier_cap=run_opts["frontier_cap"],
+                         stop_at_cap=run_opts["stop_at_cap"], rows_cap=1 << 18)
+        n_new += int(res.level_sizes[1:].sum())
+        runs += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=round(n_new / dt, 1), unit="configs/s", cores=1, kind="oracle",
+                sample=f"{runs} complete BFS walks of the same workload (plain sparse seed 0), "
+                       f"single-threaded C oracle, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    system, run_opts = plain_sparse_workload(0)
+    log(f"plain sparse seed 0: m={system.m} r={system.r} syn={system.n_syn}; warmup {args.warmup}, steps {args.steps}")
+    results, dt, _ = run_gpu(system, run_opts, args.steps, args.warmup)
+    new_per_step = results[-1]["n_configs"] - 1
+    sizes = results[-1]["level_sizes"].tolist()
+    assert all(r["n_configs"] - 1 == new_per_step for r in results)
+    value = args.steps * new_per_step / dt
+    log(f"levels {sizes}, {new_per_step} new configurations per step, {dt / args.steps * 1e3:.3f} ms/step")
+    rl = roofline(system, results)
+    log(f"stage us/step {rl['stage_us_per_step']}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on the same workload")
+        cpu = cpu_baseline(system, run_opts)
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "configs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain_sparse: seeded SN P system m=64, 2 rules/neuron (r=128), E=a^i(a^j)* "
+                        "i in [1,4] j in [0,3], out-degree 4, C0 in [0,4], int32; BFS until a level "
+                        "reaches 1e5 configurations (seed 0)",
+            "levels": sizes,
+            "new_configs_per_step": new_per_step,
+            "path": "sparse",
+            "parallelism": "single GPU",
+        },
+        "roofline": {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "dominant_kernel": {k: rl[k] for k in ("kernel", "dominant_stage", "bytes_per_launch", "avg_launch_us",
+                                                "launches_per_step", "stage_us_per_step")},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

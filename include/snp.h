@@ -89,13 +89,13 @@ typedef enum {
 /* An SN P system (Definition 1).  All arrays are host pointers and are copied
  * by snp_load / snp_batch_load; the caller keeps ownership. */
 typedef struct {
-    int32_t m;                  /* neurons, >= 1 */
+    int32_t m;                  /* neurons, 1 <= m <= 4608 */
     int32_t r;                  /* rules, >= 0 */
-    const int32_t *rule_neuron; /* [r] owner neuron (0-based), non-decreasing */
+    const int32_t *rule_neuron; /* [r] owner neuron (0-based), non-decreasing; <= 32 rules per neuron */
     const int32_t *rule_i;      /* [r] E = a^i (a^j)*: i >= 1 */
     const int32_t *rule_j;      /* [r] j >= 0 (0: E = a^i exactly) */
-    const int32_t *rule_c;      /* [r] spikes consumed, c >= 1 */
-    const int32_t *rule_p;      /* [r] spikes sent along each out-synapse, p >= 0 */
+    const int32_t *rule_c;      /* [r] spikes consumed, 1 <= c <= 65535 */
+    const int32_t *rule_p;      /* [r] spikes sent along each out-synapse, 0 <= p <= 65535 */
     int32_t n_syn;              /* synapses, >= 0 */
     const int32_t *syn_src;     /* [n_syn] (src, dst), src != dst, no duplicate pair */
     const int32_t *syn_dst;     /* [n_syn] */
@@ -121,6 +121,9 @@ typedef struct {
     int64_t chunk;            /* most children expanded per device pass; 0: automatic */
     uint64_t hash_mask;       /* 0: full 64-bit configuration hash; otherwise the hash is
                                  ANDed with it (forces collisions; results do not change) */
+    int32_t profile;          /* nonzero: time every stage with HIP events on the handle's
+                                 stream and report it in snp_expand_stats.ns_* */
+    int32_t reserved;         /* must be 0 */
     void *stream;             /* hipStream_t for all work of the handle; NULL: default */
 } snp_options;
 
@@ -132,11 +135,18 @@ typedef struct {
     int64_t enumerated;      /* children in canonical order up to where the level stopped:
                                 the cap-filling child, the budget, or all of them */
     int64_t new_configs;     /* configurations recorded for the level */
+    int64_t expanded;        /* children computed on the device (>= enumerated: the pass that
+                                fills the cap runs to its end) */
     int64_t chunks;          /* device passes used */
     int32_t truncated;       /* 1: the level reached frontier_cap */
     int32_t budget_hit;      /* 1: child_budget ran out with children left */
     int32_t path_used;       /* snp_path of the last chunk (SPARSE or INT8) */
     int32_t int8_fallback;   /* 1: INT8 was requested but M does not fit int8 */
+    /* Device time of each stage summed over the level's passes, in ns, when the
+     * handle was loaded with profile != 0 (else 0): applicability + Psi and its
+     * prefix sum; child expansion (S.M + C); visited-set insert; first-occurrence
+     * flags and their prefix sum; ordered commit. */
+    int64_t ns_psi, ns_expand, ns_insert, ns_flags, ns_commit;
 } snp_expand_stats;
 
 typedef struct snp_system snp_system; /* opaque; owns derived tables and the visited set */
@@ -210,6 +220,49 @@ snp_status snp_run(snp_system *sys, const void *c0_dev, int32_t max_depth, void 
                    int64_t out_capacity, int64_t *n_configs, int64_t *level_sizes, int32_t max_levels,
                    int32_t *n_levels, int32_t *stop_reason, snp_expand_stats *level_stats,
                    int64_t *parent_of, int64_t *child_of);
+
+/* ------------------------------------------------------------------------- */
+/* Deterministic branch of many independent systems in one launch.            */
+/* At every step each neuron fires the first of its applicable rules in the   */
+/* total order (the first spiking vector of Algorithm 2; one rule per neuron, */
+/* all neurons on a global clock, Section 2.1), C_{k+1} = C_k + S_k . M       */
+/* (Equation next-config), until `steps` steps or a configuration where no    */
+/* rule applies (halting).                                                   */
+/* ------------------------------------------------------------------------- */
+typedef struct snp_batch snp_batch; /* opaque; owns the packed tables of all systems */
+
+/* Load n >= 1 systems (host descriptions, copied).  All must share one
+ * count_type.  Limits of this mode: m <= 4096, and i, j, c, p <= 255.
+ * opt: NULL or options whose stream is used (other fields are ignored).
+ * Errors: SNP_ERR_INVALID (as snp_load, plus the limits above), SNP_ERR_DEVICE. */
+snp_status snp_batch_load(const snp_desc *descs, int32_t n, const snp_options *opt, snp_batch **out);
+
+void snp_batch_free(snp_batch *b);
+
+/* Element offsets of every system's row in the packed row buffers that
+ * snp_batch_run reads and writes: system k occupies elements
+ * [offsets[k], offsets[k+1]).  offsets: host int64 [n + 1]. */
+snp_status snp_batch_offsets(const snp_batch *b, int64_t *offsets);
+
+/* Run every system from its C0 for at most `steps` steps in one launch.
+ *   c0_dev: device pointer, packed rows (offsets above).
+ *   final_dev: device pointer, packed rows: the configuration after the last
+ *     computed step (the halting one if the system halted).
+ *   halt_step: host int32 [n]: step k whose configuration C_k is halting, -1 if none.
+ *   first_repeat: host int32 [n]: least k with C_k equal to an earlier C_l, -1 if
+ *     none (or if detect_repeats is 0).
+ *   steps_done: host int32 [n]: steps computed.
+ *   digest: host uint64 [n]: sum over computed steps k (C_0 included) of
+ *     mix64(H(C_k) + k * 0x9E3779B97F4A7C15) mod 2^64, where
+ *     H(C) = sum_n (uint32)C[n] * R_n mod 2^64, R_n = mix64((n + 1) * 0x9E3779B97F4A7C15)
+ *     and mix64 is the SplitMix64 output finaliser.
+ * Errors: SNP_ERR_OVERFLOW when a count leaves the type's range (outputs then
+ *   undefined); SNP_ERR_DEVICE when two different configurations of one
+ *   trajectory share a 64-bit H, so that repeat detection cannot vouch for
+ *   its answer (never observed; the probability is about steps^2 / 2^64). */
+snp_status snp_batch_run(snp_batch *b, const void *c0_dev, int32_t steps, int32_t detect_repeats,
+                         void *final_dev, int32_t *halt_step, int32_t *first_repeat, int32_t *steps_done,
+                         uint64_t *digest);
 
 #ifdef __cplusplus
 }

@@ -90,6 +90,10 @@ struct snp_system {
 
     double new_ratio = 1.0;  // new / enumerated of the last chunk (chunk sizing)
 
+    // stage timing (profile option): event pairs around psi+scan, expand, insert, flags+scan, commit
+    static constexpr int kStages = 5;
+    hipEvent_t ev[kStages + 1] = {};
+
     ~snp_system() {
         void* ptrs[] = {d_nrule_ptr, d_rules, d_in_ptr, d_in_src, d_table, d_row_slot, d_psi, d_off,
                         d_sc_sums, d_sc_pre, d_stage, d_hash, d_cpar, d_ct, d_slot, d_flag, d_pos,
@@ -97,6 +101,33 @@ struct snp_system {
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         if (h_ctr) (void)hipHostFree(h_ctr);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+struct snp_batch {
+    int n = 0, elem_bytes = 4, m_max = 0, r_max = 0, npt = 1;
+    long long count_max = INT_MAX;
+    hipStream_t stream = nullptr;
+    std::vector<snp::BatchSys> sys;
+    std::vector<long long> row_off;  // n + 1
+    snp::BatchSys* d_sys = nullptr;
+    uint32_t* d_rules = nullptr;
+    int *d_nrp = nullptr, *d_out_ptr = nullptr, *d_out_dst = nullptr;
+    // per-run buffers, grown on demand
+    int cap_steps = -1;
+    void* d_ckpt = nullptr;
+    u64* d_hkey = nullptr;
+    int* d_hstep = nullptr;
+    u64 table_slots = 0;
+    int *d_halt = nullptr, *d_rep = nullptr, *d_done = nullptr;
+    u64 *d_digest = nullptr, *d_err = nullptr;
+    ~snp_batch() {
+        void* ptrs[] = {d_sys, d_rules, d_nrp, d_out_ptr, d_out_dst, d_ckpt, d_hkey, d_hstep,
+                        d_halt, d_rep, d_done, d_digest, d_err};
+        for (void* p : ptrs)
+            if (p) (void)hipFree(p);
     }
 };
 
@@ -125,7 +156,8 @@ snp_status validate(const snp_desc* d) {
         if (d->rule_j[k] < 0) return fail(SNP_ERR_INVALID, "rule %d: j must be >= 0", k);
         if (d->rule_c[k] < 1) return fail(SNP_ERR_INVALID, "rule %d: c must be >= 1", k);
         if (d->rule_p[k] < 0) return fail(SNP_ERR_INVALID, "rule %d: p must be >= 0", k);
-        if (d->rule_p[k] > (1 << 20)) return fail(SNP_ERR_INVALID, "rule %d: p above 2^20", k);
+        if (d->rule_c[k] > 65535 || d->rule_p[k] > 65535)
+            return fail(SNP_ERR_INVALID, "rule %d: c and p must be <= 65535", k);
         if (++per[n] > kMaxRulesPerNeuron)
             return fail(SNP_ERR_INVALID, "neuron %d has more than %d rules", n, kMaxRulesPerNeuron);
     }
@@ -153,6 +185,19 @@ int def2_entry(const snp_desc* d, const std::vector<std::vector<char>>& adj, int
     return 0;
 }
 
+// Adds the device time between events a and b to *acc (ns); events are recorded only when profiling.
+snp_status add_elapsed(snp_system* S, int a, int b, int64_t* acc) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, S->ev[a], S->ev[b]));
+    *acc += (int64_t)((double)ms * 1.0e6);
+    return SNP_OK;
+}
+
+snp_status mark(snp_system* S, int k) {
+    if (S->opt.profile) HIPCHK(hipEventRecord(S->ev[k], S->stream));
+    return SNP_OK;
+}
+
 snp_status validate_options(const snp_options* o) {
     if (o->path < SNP_PATH_AUTO || o->path > SNP_PATH_INT8) return fail(SNP_ERR_INVALID, "bad path");
     if (o->frontier_cap < 0 || o->child_budget < 0 || o->chunk < 0 || o->max_frontier < 0)
@@ -160,6 +205,7 @@ snp_status validate_options(const snp_options* o) {
     if (o->max_rows < 1 || o->max_rows >= (long long)snp::kStageBase)
         return fail(SNP_ERR_INVALID, "max_rows must be in [1, 2^31)");
     if (o->chunk > (long long)snp::kMaxChunk) return fail(SNP_ERR_INVALID, "chunk above 2^30");
+    if (o->reserved != 0) return fail(SNP_ERR_INVALID, "reserved option field must be 0");
     return SNP_OK;
 }
 
@@ -238,10 +284,13 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
 
     // Psi per parent and its exclusive prefix sum
     if ((st = clear_counters(S))) return st;
+    if ((st = mark(S, 0))) return st;
     HIPCHK(snp::launch_psi(S->elem_bytes, S->dsys, io.frontier, io.n, S->opt.expand_max_count, S->d_psi, S->d_ctr,
                            S->stream));
     HIPCHK(snp::launch_scan_u64(S->d_psi, S->d_off, io.n, S->d_sc_sums, S->d_sc_pre, &S->d_ctr->total, S->stream));
+    if ((st = mark(S, 1))) return st;
     if ((st = read_counters(S))) return st;
+    if (S->opt.profile && (st = add_elapsed(S, 0, 1, &stt.ns_psi))) return st;
     const u64 T = S->h_ctr->total;
     stt.halting_parents = (long long)S->h_ctr->halting;
     stt.children_total = (long long)T;
@@ -272,22 +321,34 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         if ((st = clear_counters(S))) return st;
         snp::ChunkArgs ca{io.frontier, io.n, S->d_psi, S->d_off, G, B, S->d_stage, S->d_hash, S->d_cpar, S->d_ct,
                           hmask, S->d_ctr};
+        if ((st = mark(S, 0))) return st;
         HIPCHK(snp::launch_expand_sparse(S->elem_bytes, S->dsys, ca, S->stream));
+        if ((st = mark(S, 1))) return st;
         snp::TableArgs ta{S->d_table, S->slots - 1, io.arena, S->d_stage, S->d_hash, S->d_slot, B, S->d_ctr};
         HIPCHK(snp::launch_insert(S->elem_bytes, S->m, ta, S->stream));
+        if ((st = mark(S, 2))) return st;
         HIPCHK(snp::launch_flags(S->d_table, S->d_slot, B, S->d_flag, S->stream));
         HIPCHK(snp::launch_scan_u32(S->d_flag, S->d_pos, B, S->d_fsums, S->d_fpre, &S->d_ctr->total, S->stream));
+        if ((st = mark(S, 3))) return st;
         snp::CommitArgs cm{S->d_table, S->d_table, S->d_slot, S->d_hash, S->d_pos, S->d_flag, S->d_stage,
                            S->d_cpar, S->d_ct, B, io.arena, io.level_base, count, limit, io.row2, io.par_out,
                            io.par_out_base, io.par_value_base, io.t_out, S->d_row_slot, S->d_ctr};
         HIPCHK(snp::launch_commit(S->elem_bytes, S->m, cm, S->stream));
+        if ((st = mark(S, 4))) return st;
         if ((st = read_counters(S))) return st;
+        if (S->opt.profile) {
+            if ((st = add_elapsed(S, 0, 1, &stt.ns_expand))) return st;
+            if ((st = add_elapsed(S, 1, 2, &stt.ns_insert))) return st;
+            if ((st = add_elapsed(S, 2, 3, &stt.ns_flags))) return st;
+            if ((st = add_elapsed(S, 3, 4, &stt.ns_commit))) return st;
+        }
         ++stt.chunks;
+        stt.expanded += B;
         const snp::DevCounters c = *S->h_ctr;
-        S->tombs += (long long)c.tombs;
         const long long new_total = (long long)c.total;
         const long long avail = limit - count;
         const long long committed = std::min(new_total, avail);
+        S->tombs += new_total - committed;  // new children past the limit became tombstones
         if (c.probe_fail) return fail(SNP_ERR_DEVICE, "visited set: probe found no free slot");
         if (c.overflow) {
             if ((st = rollback_level(S, io.level_base, count + committed))) return st;
@@ -403,7 +464,7 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     LOADCHK(up(S->d_rules, rules.data(), sizeof(int4) * d->r));
     LOADCHK(up(S->d_in_ptr, in_ptr.data(), sizeof(int) * (d->m + 1)));
     LOADCHK(up(S->d_in_src, in_src.data(), sizeof(int) * d->n_syn));
-    S->dsys = snp::DevSystem{d->m, d->r, S->d_nrule_ptr, S->d_rules, S->d_in_ptr, S->d_in_src, nullptr,
+    S->dsys = snp::DevSystem{d->m, d->r, S->d_nrule_ptr, S->d_rules, S->d_in_ptr, S->d_in_src, d->n_syn, nullptr,
                              S->count_max};
 
     S->slots = next_pow2((u64)std::max<long long>(1024, 2 * (S->max_rows + 2 * S->chunk_max)));
@@ -427,6 +488,8 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     LOADCHK(dmalloc(&S->d_fpre, sizeof(uint32_t) * ft));
     LOADCHK(dmalloc(&S->d_ctr, sizeof(snp::DevCounters)));
     LOADCHK(hipHostMalloc((void**)&S->h_ctr, sizeof(snp::DevCounters), hipHostMallocDefault));
+    if (opt.profile)
+        for (hipEvent_t& e : S->ev) LOADCHK(hipEventCreate(&e));
 #undef LOADCHK
     *out = S;
     return SNP_OK;
@@ -534,6 +597,158 @@ snp_status snp_run(snp_system* S, const void* c0_dev, int32_t max_depth, void* o
     }
     *stop_reason = stop;
     HIPCHK(hipStreamSynchronize(S->stream));
+    return SNP_OK;
+}
+
+snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* opt, snp_batch** out) {
+    g_err.clear();
+    if (!out) return fail(SNP_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!descs || n < 1) return fail(SNP_ERR_INVALID, "need at least one system");
+    const int ct = descs[0].count_type;
+    std::vector<snp::BatchSys> sys(n);
+    std::vector<long long> row_off(n + 1, 0);
+    std::vector<uint32_t> rules;
+    std::vector<int> nrp, out_ptr, out_dst;
+    int m_max = 0, r_max = 0;
+    for (int k = 0; k < n; ++k) {
+        const snp_desc* d = &descs[k];
+        snp_status st = validate(d);
+        if (st) return fail(st, "system %d: %s", k, g_err.c_str());
+        if (d->count_type != ct) return fail(SNP_ERR_INVALID, "system %d: all systems must share count_type", k);
+        if (d->m > 4 * snp::batch_threads())
+            return fail(SNP_ERR_INVALID, "system %d: m above %d is not supported in batched mode", k,
+                        4 * snp::batch_threads());
+        for (int q = 0; q < d->r; ++q)
+            if (d->rule_i[q] > 255 || d->rule_j[q] > 255 || d->rule_c[q] > 255 || d->rule_p[q] > 255)
+                return fail(SNP_ERR_INVALID, "system %d rule %d: batched mode needs i, j, c, p <= 255", k, q);
+        snp::BatchSys& B = sys[k];
+        B.m = d->m;
+        B.r = d->r;
+        B.row_off = row_off[k];
+        row_off[k + 1] = row_off[k] + d->m;
+        B.rule_off = (int)rules.size();
+        B.nrp_off = (int)nrp.size();
+        B.out_off = (int)out_dst.size();
+        for (int q = 0; q < d->r; ++q)
+            rules.push_back((uint32_t)d->rule_i[q] | ((uint32_t)d->rule_j[q] << 8) | ((uint32_t)d->rule_c[q] << 16) |
+                            ((uint32_t)d->rule_p[q] << 24));
+        std::vector<int> cnt(d->m + 1, 0), ocnt(d->m + 1, 0);
+        for (int q = 0; q < d->r; ++q) cnt[d->rule_neuron[q] + 1]++;
+        for (int e = 0; e < d->n_syn; ++e) ocnt[d->syn_src[e] + 1]++;
+        for (int j = 0; j < d->m; ++j) {
+            cnt[j + 1] += cnt[j];
+            ocnt[j + 1] += ocnt[j];
+        }
+        std::vector<int> dst(d->n_syn), fill(d->m, 0);
+        for (int e = 0; e < d->n_syn; ++e) {
+            const int src = d->syn_src[e];
+            dst[ocnt[src] + fill[src]++] = d->syn_dst[e];
+        }
+        nrp.insert(nrp.end(), cnt.begin(), cnt.end());
+        out_ptr.insert(out_ptr.end(), ocnt.begin(), ocnt.end());
+        out_dst.insert(out_dst.end(), dst.begin(), dst.end());
+        m_max = std::max(m_max, d->m);
+        r_max = std::max(r_max, d->r);
+    }
+    if (snp::batch_lds_bytes(m_max, r_max) > 64 * 1024)
+        return fail(SNP_ERR_INVALID, "batched mode: the largest system needs more than 64 KiB of LDS");
+    snp_batch* b = new snp_batch();
+    b->n = n;
+    b->elem_bytes = ct == SNP_COUNT_U16 ? 2 : 4;
+    b->count_max = ct == SNP_COUNT_U16 ? 65535 : INT_MAX;
+    b->m_max = m_max;
+    b->r_max = r_max;
+    b->npt = m_max <= snp::batch_threads() ? 1 : (m_max <= 2 * snp::batch_threads() ? 2 : 4);
+    b->stream = opt ? (hipStream_t)opt->stream : nullptr;
+    b->sys = sys;
+    b->row_off = row_off;
+#define BLOADCHK(expr)                                                        \
+    do {                                                                      \
+        hipError_t e_ = (expr);                                               \
+        if (e_ != hipSuccess) {                                               \
+            delete b;                                                         \
+            return fail(SNP_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+        }                                                                     \
+    } while (0)
+    BLOADCHK(dmalloc(&b->d_sys, sizeof(snp::BatchSys) * n));
+    BLOADCHK(dmalloc(&b->d_rules, sizeof(uint32_t) * rules.size()));
+    BLOADCHK(dmalloc(&b->d_nrp, sizeof(int) * nrp.size()));
+    BLOADCHK(dmalloc(&b->d_out_ptr, sizeof(int) * out_ptr.size()));
+    BLOADCHK(dmalloc(&b->d_out_dst, sizeof(int) * out_dst.size()));
+    BLOADCHK(dmalloc(&b->d_halt, sizeof(int) * n));
+    BLOADCHK(dmalloc(&b->d_rep, sizeof(int) * n));
+    BLOADCHK(dmalloc(&b->d_done, sizeof(int) * n));
+    BLOADCHK(dmalloc(&b->d_digest, sizeof(u64) * n));
+    BLOADCHK(dmalloc(&b->d_err, sizeof(u64) * n));
+    if (!rules.empty()) BLOADCHK(hipMemcpy(b->d_rules, rules.data(), sizeof(uint32_t) * rules.size(), hipMemcpyHostToDevice));
+    BLOADCHK(hipMemcpy(b->d_nrp, nrp.data(), sizeof(int) * nrp.size(), hipMemcpyHostToDevice));
+    BLOADCHK(hipMemcpy(b->d_out_ptr, out_ptr.data(), sizeof(int) * out_ptr.size(), hipMemcpyHostToDevice));
+    if (!out_dst.empty())
+        BLOADCHK(hipMemcpy(b->d_out_dst, out_dst.data(), sizeof(int) * out_dst.size(), hipMemcpyHostToDevice));
+#undef BLOADCHK
+    *out = b;
+    return SNP_OK;
+}
+
+void snp_batch_free(snp_batch* b) { delete b; }
+
+snp_status snp_batch_offsets(const snp_batch* b, int64_t* offsets) {
+    g_err.clear();
+    if (!b || !offsets) return fail(SNP_ERR_INVALID, "batch and offsets are required");
+    for (int k = 0; k <= b->n; ++k) offsets[k] = b->row_off[k];
+    return SNP_OK;
+}
+
+snp_status snp_batch_run(snp_batch* b, const void* c0_dev, int32_t steps, int32_t detect_repeats, void* final_dev,
+                         int32_t* halt_step, int32_t* first_repeat, int32_t* steps_done, uint64_t* digest) {
+    g_err.clear();
+    if (!b) return fail(SNP_ERR_INVALID, "batch is NULL");
+    if (!c0_dev || !final_dev || !halt_step || !first_repeat || !steps_done || !digest)
+        return fail(SNP_ERR_INVALID, "c0, final and every result array are required");
+    if (steps < 0 || steps > (1 << 24)) return fail(SNP_ERR_INVALID, "steps must be in [0, 2^24]");
+    const int interval = snp::batch_interval();
+    if (steps > b->cap_steps) {  // checkpoints and H sets sized for this many steps
+        if (b->d_ckpt) HIPCHK(hipFree(b->d_ckpt));
+        if (b->d_hkey) HIPCHK(hipFree(b->d_hkey));
+        if (b->d_hstep) HIPCHK(hipFree(b->d_hstep));
+        b->d_ckpt = nullptr;
+        b->d_hkey = nullptr;
+        b->d_hstep = nullptr;
+        const long long rows = steps / interval + 1;
+        long long ck = 0;
+        for (int k = 0; k < b->n; ++k) {
+            b->sys[k].ckpt_off = ck;
+            b->sys[k].ckpt_stride = b->sys[k].m;
+            ck += rows * b->sys[k].m;
+        }
+        b->table_slots = next_pow2((u64)std::max(64, 2 * (steps + 1)));
+        for (int k = 0; k < b->n; ++k) b->sys[k].table_off = (long long)k * (long long)b->table_slots;
+        HIPCHK(dmalloc(&b->d_ckpt, (size_t)ck * b->elem_bytes));
+        HIPCHK(dmalloc(&b->d_hkey, sizeof(u64) * b->table_slots * b->n));
+        HIPCHK(dmalloc(&b->d_hstep, sizeof(int) * b->table_slots * b->n));
+        HIPCHK(hipMemcpy(b->d_sys, b->sys.data(), sizeof(snp::BatchSys) * b->n, hipMemcpyHostToDevice));
+        b->cap_steps = steps;
+    }
+    if (detect_repeats)
+        HIPCHK(snp::launch_fill_i32(b->d_hstep, (long long)b->table_slots * b->n, -1, b->stream));
+    snp::BatchArgs a{b->d_sys, b->d_rules, b->d_nrp, b->d_out_ptr, b->d_out_dst, c0_dev, final_dev, b->d_ckpt,
+                     b->d_hkey, b->d_hstep, b->table_slots, b->m_max, b->r_max, steps, detect_repeats ? 1 : 0,
+                     b->count_max, b->d_halt, b->d_rep, b->d_done, b->d_digest, b->d_err};
+    HIPCHK(snp::launch_batch_det(b->elem_bytes, b->npt, a, b->n, b->stream));
+    std::vector<u64> err(b->n);
+    HIPCHK(hipMemcpyAsync(halt_step, b->d_halt, sizeof(int) * b->n, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipMemcpyAsync(first_repeat, b->d_rep, sizeof(int) * b->n, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipMemcpyAsync(steps_done, b->d_done, sizeof(int) * b->n, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipMemcpyAsync(digest, b->d_digest, sizeof(u64) * b->n, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipMemcpyAsync(err.data(), b->d_err, sizeof(u64) * b->n, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    for (int k = 0; k < b->n; ++k) {
+        if (err[k] & 1) return fail(SNP_ERR_OVERFLOW, "system %d: a count left the count type's range", k);
+        if (err[k] & 2)
+            return fail(SNP_ERR_DEVICE, "system %d: two configurations share a 64-bit hash; repeat detection "
+                        "cannot vouch for its answer", k);
+    }
     return SNP_OK;
 }
 

@@ -1,0 +1,347 @@
+// gfx950 kernel of the deterministic single-branch run of many independent
+// SN P systems in one launch: at every step each neuron fires the first of its
+// applicable rules (Section 2.1: one rule per neuron, all neurons on a global
+// clock; the first of Algorithm 2's spiking vectors), C_{k+1} = C_k + S_k.M
+// (Equation next-config), until the step limit or a halting configuration.
+//
+// One workgroup of 1024 threads runs one system; thread t owns neurons
+// t, t + 1024, ... (NPT per thread).  Counts, rule ranges and the first
+// kOutReg out-synapses of every owned neuron live in registers; the block
+// shares the packed rule table and double-buffered spike accumulators in LDS.
+// A step: pick the fired rule, add p into the accumulator of every target (LDS
+// atomics), one barrier (which also tells whether any neuron fired), then
+// C' = C - c + received and the accumulator entry is cleared.  Step k uses
+// buffer k & 1, so the barrier of step k+1 separates step k's reads from step
+// k+2's adds into the same buffer.
+//
+// Trajectory checksum: H(C) = sum_n C[n] * R_n (mod 2^64) with R_n the
+// SplitMix64 stream (seed 0); digest = sum_k mix64(H(C_k) + k * gamma).
+// First repeat: every kBatch steps the block stores a checkpoint row and looks
+// the batch's H values up in a per-system open-addressing set of earlier H
+// values (and within the batch); a candidate pair (l, k) is confirmed by
+// re-simulating C_l and C_k from their checkpoints and comparing the rows.  A
+// candidate whose rows differ (two configurations with one 64-bit H) is
+// reported as an error, never guessed.
+#include "snp_internal.hpp"
+
+namespace snp {
+
+namespace {
+
+constexpr int kThreads = 1024;
+constexpr int kWaves = kThreads / 64;
+constexpr int kOutReg = 32;  // out-synapses per neuron held in registers
+constexpr int kBatch = 64;   // steps between checkpoints / repeat checks
+constexpr u64 kGamma = 0x9E3779B97F4A7C15ULL;
+
+__device__ __forceinline__ u64 mix64(u64 z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+// 64-bit wave sum on DPP: row shifts 1, 2, 4, 8 then row broadcasts of lanes
+// 15 and 31; lane 63 holds the total, returned to every lane.
+#define SNP_DPP64(V, CTRL, RM, BC)                                                                \
+    do {                                                                                          \
+        const uint32_t lo_ = __builtin_amdgcn_update_dpp(0u, (uint32_t)(V), CTRL, RM, 0xf, BC);    \
+        const uint32_t hi_ = __builtin_amdgcn_update_dpp(0u, (uint32_t)((V) >> 32), CTRL, RM, 0xf, BC); \
+        (V) += ((u64)hi_ << 32) | lo_;                                                            \
+    } while (0)
+
+__device__ __forceinline__ u64 wave_sum64(u64 v) {
+    SNP_DPP64(v, 0x111, 0xf, true);
+    SNP_DPP64(v, 0x112, 0xf, true);
+    SNP_DPP64(v, 0x114, 0xf, true);
+    SNP_DPP64(v, 0x118, 0xf, true);
+    SNP_DPP64(v, 0x142, 0xa, false);
+    SNP_DPP64(v, 0x143, 0xc, false);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), 63);
+    return ((u64)hi << 32) | lo;
+}
+#undef SNP_DPP64
+
+// Packed rule (i | j << 8 | c << 16 | p << 24): a^n in L(a^i (a^j)*) and n >= c.
+__device__ __forceinline__ bool applies_packed(int n, uint32_t R) {
+    const int i = R & 0xFF, j = (R >> 8) & 0xFF, c = (R >> 16) & 0xFF;
+    if (n < i || n < c) return false;
+    if (j == 0) return n == i;
+    return ((uint32_t)(n - i) % (uint32_t)j) == 0;
+}
+
+template <int NPT>
+struct Neurons {
+    int cnt[NPT];          // current spike count
+    int rs[NPT], rn[NPT];  // rules: lrules[rs .. rs + rn)
+    int os[NPT], on[NPT];  // out-synapses: out_dst[os .. os + on)
+    uint32_t reg_out[NPT][kOutReg / 2];  // first kOutReg targets, two u16 per word
+    u64 R[NPT];            // H weights
+    bool valid[NPT];
+};
+
+// One step of the deterministic branch on accumulator buffer acc.  Returns
+// (block-wide) whether any neuron fired; when none fired nothing changes.
+template <int NPT>
+__device__ __forceinline__ bool det_step(Neurons<NPT>& N, const uint32_t* lrules, int* acc,
+                                         const int* __restrict__ out_dst, long long count_max, bool& ovf) {
+    int fc[NPT];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+        fc[q] = 0;
+        int fp = 0;
+        if (N.valid[q]) {
+            for (int k = 0; k < N.rn[q]; ++k) {
+                const uint32_t R = lrules[N.rs[q] + k];
+                if (applies_packed(N.cnt[q], R)) {
+                    fc[q] = (R >> 16) & 0xFF;
+                    fp = (int)(R >> 24);
+                    any = true;
+                    break;
+                }
+            }
+        }
+        if (fp != 0) {
+#pragma unroll
+            for (int e = 0; e < kOutReg; ++e)
+                if (e < N.on[q]) {
+                    const uint32_t w = N.reg_out[q][e >> 1];
+                    const int d = (e & 1) ? (int)(w >> 16) : (int)(w & 0xFFFFu);
+                    atomicAdd(&acc[d], fp);
+                }
+            for (int e = kOutReg; e < N.on[q]; ++e) atomicAdd(&acc[out_dst[N.os[q] + e]], fp);
+        }
+    }
+    if (__syncthreads_or(any) == 0) return false;
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+        if (!N.valid[q]) continue;
+        const int j = threadIdx.x + q * kThreads;
+        const long long v = (long long)N.cnt[q] - fc[q] + acc[j];
+        acc[j] = 0;
+        ovf |= (v < 0) | (v > count_max);
+        N.cnt[q] = (int)v;
+    }
+    return true;
+}
+
+template <int NPT>
+__device__ __forceinline__ u64 h_partial(const Neurons<NPT>& N) {
+    u64 h = 0;
+#pragma unroll
+    for (int q = 0; q < NPT; ++q)
+        if (N.valid[q]) h += (u64)(uint32_t)N.cnt[q] * N.R[q];
+    return h;
+}
+
+template <typename T, int NPT>
+__device__ __forceinline__ void load_counts(Neurons<NPT>& N, const T* row) {
+#pragma unroll
+    for (int q = 0; q < NPT; ++q)
+        if (N.valid[q]) N.cnt[q] = (int)row[threadIdx.x + q * kThreads];
+}
+
+template <typename T, int NPT>
+__device__ __forceinline__ void store_counts(const Neurons<NPT>& N, T* row) {
+#pragma unroll
+    for (int q = 0; q < NPT; ++q)
+        if (N.valid[q]) row[threadIdx.x + q * kThreads] = (T)N.cnt[q];
+}
+
+// Block-wide H of the current counts (every thread gets it).
+template <int NPT>
+__device__ __forceinline__ u64 block_hash(const Neurons<NPT>& N, u64* wpart) {
+    const u64 w = wave_sum64(h_partial(N));
+    if ((threadIdx.x & 63) == 0) wpart[threadIdx.x >> 6] = w;
+    __syncthreads();
+    u64 h = 0;
+    for (int q = 0; q < kWaves; ++q) h += wpart[q];
+    __syncthreads();  // wpart may be rewritten afterwards
+    return h;
+}
+
+}  // namespace
+
+size_t batch_lds_bytes(int m_max, int r_max) {
+    const size_t r4 = ((size_t)r_max + 3) & ~(size_t)3;
+    const size_t m4 = ((size_t)m_max + 3) & ~(size_t)3;
+    return r4 * 4 + m4 * 4 * 3 + kWaves * 8 + (kBatch + 1) * 8 + (kBatch + 1) * 4 + 64;
+}
+
+int batch_threads() { return kThreads; }
+int batch_interval() { return kBatch; }
+
+template <typename T, int NPT>
+__global__ __launch_bounds__(kThreads) void k_batch_det(BatchArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int sys = blockIdx.x;
+    const BatchSys B = a.sys[sys];
+    const int m4 = (a.m_max + 3) & ~3;
+    uint32_t* lrules = (uint32_t*)smem;                       // [r_max]
+    int* acc0 = (int*)(lrules + ((a.r_max + 3) & ~3));        // [m4]
+    int* acc1 = acc0 + m4;                                    // [m4]
+    int* xrow = acc1 + m4;                                    // [m4] a configuration under verification
+    u64* wpart = (u64*)(xrow + m4);                           // [kWaves]
+    u64* hring = wpart + kWaves;                              // [kBatch + 1]: H(C_{batch_start + i})
+    int* cand = (int*)(hring + kBatch + 1);                   // [kBatch + 1]: earliest step with equal H
+
+    for (int q = threadIdx.x; q < B.r; q += kThreads) lrules[q] = a.rules[B.rule_off + q];
+    for (int q = threadIdx.x; q < 2 * m4; q += kThreads) acc0[q] = 0;
+
+    Neurons<NPT> N;
+    const T* c0 = (const T*)a.c0 + B.row_off;
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+        const int j = threadIdx.x + q * kThreads;
+        N.valid[q] = j < B.m;
+        N.cnt[q] = 0;
+        N.rs[q] = N.rn[q] = N.os[q] = N.on[q] = 0;
+        N.R[q] = 0;
+#pragma unroll
+        for (int e = 0; e < kOutReg / 2; ++e) N.reg_out[q][e] = 0;
+        if (N.valid[q]) {
+            N.cnt[q] = (int)c0[j];
+            N.rs[q] = a.nrp[B.nrp_off + j];
+            N.rn[q] = a.nrp[B.nrp_off + j + 1] - N.rs[q];
+            N.os[q] = B.out_off + a.out_ptr[B.nrp_off + j];
+            N.on[q] = a.out_ptr[B.nrp_off + j + 1] - a.out_ptr[B.nrp_off + j];
+            N.R[q] = mix64((u64)(j + 1) * kGamma);
+#pragma unroll
+            for (int e = 0; e < kOutReg; ++e)
+                if (e < N.on[q]) {
+                    const uint32_t d = (uint32_t)a.out_dst[N.os[q] + e] & 0xFFFFu;
+                    N.reg_out[q][e >> 1] |= (e & 1) ? (d << 16) : d;
+                }
+        }
+    }
+    T* ckpt = (T*)a.ckpt + B.ckpt_off;  // row q = the configuration at step q * kBatch
+    u64* hkey = a.hkey + B.table_off;
+    int* hstep = a.hstep + B.table_off;  // -1: empty slot
+    const u64 hmask = a.table_slots - 1;
+    const int steps = a.steps;
+    __syncthreads();
+
+    store_counts<T, NPT>(N, ckpt);
+    const u64 h0 = block_hash<NPT>(N, wpart);
+    u64 digest = mix64(h0);
+    if (threadIdx.x == 0) hring[0] = h0;
+    int k = 0, batch_start = 0, halt = -1, first_rep = -1;
+    bool ovf = false, collision = false;
+
+    for (;;) {
+        bool done = k >= steps;
+        if (!done) {
+            if (det_step<NPT>(N, lrules, (k & 1) ? acc1 : acc0, a.out_dst, a.count_max, ovf)) {
+                ++k;
+                const u64 h = block_hash<NPT>(N, wpart);
+                digest += mix64(h + (u64)k * kGamma);
+                if (threadIdx.x == 0) hring[k - batch_start] = h;
+            } else {
+                halt = k;
+                done = true;
+            }
+        }
+        if (!done && k - batch_start < kBatch) continue;
+
+        // ---- batch boundary (or end of run) ----
+        const int nb = k - batch_start;  // H(C_{batch_start + i}) in hring[i], i = 0 .. nb
+        if (done) store_counts<T, NPT>(N, (T*)a.final_out + B.row_off);
+        else store_counts<T, NPT>(N, ckpt + (long long)(k / kBatch) * B.ckpt_stride);
+        __syncthreads();
+        bool resimulated = false;
+        if (first_rep < 0 && a.detect_repeats) {
+            const int first_new = (batch_start == 0) ? 0 : 1;  // H(C_batch_start) is already in the set
+            const int i = threadIdx.x;
+            if (i <= kBatch) cand[i] = -1;
+            __syncthreads();
+            if (i >= first_new && i <= nb) {  // earlier batches: read-only probes
+                const u64 key = hring[i];
+                u64 s = (key * kGamma) >> 17;
+                for (u64 it = 0; it <= hmask; ++it, ++s) {
+                    const int st = hstep[s & hmask];
+                    if (st < 0) break;
+                    if (hkey[s & hmask] == key) {
+                        cand[i] = st;
+                        break;
+                    }
+                }
+                if (cand[i] < 0)  // within this batch
+                    for (int l = 0; l < i; ++l)
+                        if (hring[l] == key) {
+                            cand[i] = batch_start + l;
+                            break;
+                        }
+            }
+            __syncthreads();
+            // confirm candidates in step order by re-simulating both rows
+            for (int q = first_new; q <= nb && first_rep < 0; ++q) {
+                const int l = cand[q];
+                if (l < 0) continue;
+                const int kk = batch_start + q;
+                resimulated = true;
+                load_counts<T, NPT>(N, ckpt + (long long)(l / kBatch) * B.ckpt_stride);
+                for (int t = (l / kBatch) * kBatch; t < l; ++t)
+                    det_step<NPT>(N, lrules, (t & 1) ? acc1 : acc0, a.out_dst, a.count_max, ovf);
+                store_counts<int, NPT>(N, xrow);
+                load_counts<T, NPT>(N, ckpt + (long long)(kk / kBatch) * B.ckpt_stride);
+                for (int t = (kk / kBatch) * kBatch; t < kk; ++t)
+                    det_step<NPT>(N, lrules, (t & 1) ? acc1 : acc0, a.out_dst, a.count_max, ovf);
+                bool diff = false;
+#pragma unroll
+                for (int u = 0; u < NPT; ++u)
+                    if (N.valid[u]) diff |= (xrow[threadIdx.x + u * kThreads] != N.cnt[u]);
+                if (__syncthreads_or(diff) == 0) first_rep = kk;
+                else collision = true;
+            }
+            // insert the first occurrence of every new H value
+            if (i >= first_new && i <= nb && cand[i] < 0) {
+                const u64 key = hring[i];
+                u64 s = (key * kGamma) >> 17;
+                for (u64 it = 0; it <= hmask; ++it, ++s)
+                    if (atomicCAS(&hstep[s & hmask], -1, batch_start + i) == -1) {
+                        hkey[s & hmask] = key;
+                        break;
+                    }
+            }
+            __syncthreads();
+        }
+        if (done) break;
+        if (resimulated) {  // back to the configuration at step k
+            load_counts<T, NPT>(N, ckpt + (long long)(k / kBatch) * B.ckpt_stride);
+            for (int q = threadIdx.x; q < 2 * m4; q += kThreads) acc0[q] = 0;
+        }
+        if (threadIdx.x == 0) hring[0] = hring[nb];
+        batch_start = k;
+        __syncthreads();
+    }
+    const bool any_ovf = __syncthreads_or(ovf) != 0;
+    const bool any_col = __syncthreads_or(collision) != 0;
+    if (threadIdx.x == 0) {
+        a.halt_step[sys] = halt;
+        a.first_repeat[sys] = first_rep;
+        a.steps_done[sys] = k;
+        a.digest[sys] = digest;
+        a.err[sys] = (any_ovf ? 1ULL : 0ULL) | (any_col ? 2ULL : 0ULL);
+    }
+}
+
+hipError_t launch_batch_det(int elem_bytes, int npt, const BatchArgs& a, int n_sys, hipStream_t st) {
+    if (n_sys <= 0) return hipSuccess;
+    const size_t lds = batch_lds_bytes(a.m_max, a.r_max);
+#define SNP_BATCH(TT, NN) \
+    hipLaunchKernelGGL((k_batch_det<TT, NN>), dim3(n_sys), dim3(kThreads), lds, st, a)
+    if (elem_bytes == 4) {
+        if (npt == 1) SNP_BATCH(int32_t, 1);
+        else if (npt == 2) SNP_BATCH(int32_t, 2);
+        else SNP_BATCH(int32_t, 4);
+    } else {
+        if (npt == 1) SNP_BATCH(uint16_t, 1);
+        else if (npt == 2) SNP_BATCH(uint16_t, 2);
+        else SNP_BATCH(uint16_t, 4);
+    }
+#undef SNP_BATCH
+    return hipGetLastError();
+}
+
+}  // namespace snp

@@ -40,6 +40,7 @@ struct DevSystem {
     const int4* rules;     // [r] (i, j, c, p)
     const int* in_ptr;     // [m+1] in-synapses of neuron d: in_src[in_ptr[d] .. in_ptr[d+1])
     const int* in_src;     // sources of the in-synapses
+    int nnz_in;            // number of synapses
     const int8_t* M8;      // [r*m] int8 copy of M_Pi (nullptr when some |entry| > 127)
     long long count_max;
 };
@@ -95,6 +96,47 @@ struct CommitArgs {
     uint32_t* row_slot;    // [max_rows] slot of every row-store row
     DevCounters* ctr;
 };
+
+// Deterministic batched run: one system per workgroup.
+struct BatchSys {
+    int m, r;
+    long long row_off;      // first element of the system's row in packed row buffers
+    int rule_off;           // first packed rule of the system
+    int nrp_off;            // first entry of the system's (m+1)-long rule and out-synapse offsets
+    int out_off;            // first out-synapse target of the system
+    long long ckpt_off;     // first element of the system's checkpoint rows
+    long long ckpt_stride;  // elements per checkpoint row (m)
+    long long table_off;    // first slot of the system's H set
+};
+
+struct BatchArgs {
+    const BatchSys* sys;
+    const uint32_t* rules;  // packed (i | j << 8 | c << 16 | p << 24)
+    const int* nrp;         // per system: rules of neuron n are [nrp[n], nrp[n+1]) (system-relative)
+    const int* out_ptr;     // per system: out-synapses of neuron n are out_dst[out_off + out_ptr[n] ..)
+    const int* out_dst;
+    const void* c0;
+    void* final_out;
+    void* ckpt;
+    u64* hkey;
+    int* hstep;
+    u64 table_slots;        // per system, power of two
+    int m_max, r_max;
+    int steps;
+    int detect_repeats;
+    long long count_max;
+    int* halt_step;
+    int* first_repeat;
+    int* steps_done;
+    u64* digest;
+    u64* err;               // bit 0: overflow; bit 1: two configurations with one 64-bit H
+};
+
+size_t batch_lds_bytes(int m_max, int r_max);
+int batch_threads();
+int batch_interval();
+hipError_t launch_batch_det(int elem_bytes, int npt, const BatchArgs& a, int n_sys, hipStream_t st);
+hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st);
 
 hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, long long n,
                       long long expand_max, u64* psi, DevCounters* ctr, hipStream_t st);

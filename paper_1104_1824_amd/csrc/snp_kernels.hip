@@ -43,23 +43,41 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ u64 wave_sum_u64(u64 x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    return x;
+// Wave64 reductions on DPP: inclusive sums within rows of 16 lanes by row
+// shifts 1, 2, 4, 8 (lanes shifted in from outside the row read 0), then
+// row broadcasts of lanes 15 and 31 carry the row totals upward; lane 63 ends
+// with the total, which is returned to every lane.  All 64 lanes must be
+// active.
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, true);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, true);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, true);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, true);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
-__device__ __forceinline__ int wave_max_i32(int x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o));
-    return x;
+// Maximum of non-negative values (0 is the identity).
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, true));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, true));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, true));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, true));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false));
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
-__device__ __forceinline__ u64 wave_satprod(u64 x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x = sat_mul(x, __shfl_xor(x, o));
-    return x;
+// 64-bit configuration hash of a row from per-lane partial sums: the low and
+// high halves of the per-element hashes are summed separately (mod 2^32).
+__device__ __forceinline__ u64 wave_hash_total(u64 partial) {
+    const uint32_t lo = wave_sum_u32((uint32_t)partial);
+    const uint32_t hi = wave_sum_u32((uint32_t)(partial >> 32));
+    return ((u64)hi << 32) | lo;
 }
+
+__device__ __forceinline__ int wave_max_i32(int x) { return (int)wave_max_u32((uint32_t)(x + 1)) - 1; }
 
 // Rule applicability: a^n in L(a^i (a^j)*) and n >= c.
 __device__ __forceinline__ bool rule_applies(int n, const int4 R) {
@@ -90,11 +108,19 @@ __device__ __forceinline__ u64 elem_hash(int j, uint32_t v) {
     return fmix64((((u64)(uint32_t)j << 32) | v) ^ 0x9E3779B97F4A7C15ULL);
 }
 
+// Per-lane partial: sums of the low and high halves of the element hashes,
+// each mod 2^32, kept in one 64-bit word (no carry between the halves).
+__device__ __forceinline__ u64 hash_acc(u64 acc, u64 e) {
+    const uint32_t lo = (uint32_t)acc + (uint32_t)e;
+    const uint32_t hi = (uint32_t)(acc >> 32) + (uint32_t)(e >> 32);
+    return ((u64)hi << 32) | lo;
+}
+
 template <typename T>
 __device__ __forceinline__ u64 row_hash_wave(const T* row, int m, int lane) {
     u64 h = 0;
-    for (int j = lane; j < m; j += 64) h += elem_hash(j, (uint32_t)row[j]);
-    return wave_sum_u64(h);
+    for (int j = lane; j < m; j += 64) h = hash_acc(h, elem_hash(j, (uint32_t)row[j]));
+    return wave_hash_total(h);
 }
 
 // ---------------------------------------------------------------------------
@@ -102,44 +128,94 @@ __device__ __forceinline__ u64 row_hash_wave(const T* row, int m, int lane) {
 // product over neurons of max(1, omega_n), saturated; 0 when no rule applies
 // anywhere (halting) or when the parent exceeds the expansion count limit.
 // ---------------------------------------------------------------------------
-template <typename T>
+__device__ __forceinline__ u64 sat_pow(u64 b, uint32_t e) {
+    u64 r = 1;
+    for (uint32_t q = 0; q < e && r < kPsiSat; ++q) r = sat_mul(r, b);
+    return r;
+}
+
+// Saturating product over the wave (64-bit shuffles; only for radices above 4).
+__device__ __forceinline__ u64 wave_satprod(u64 x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = sat_mul(x, __shfl_xor(x, o));
+    return x;
+}
+
+template <typename T, bool TBL_LDS>
 __global__ __launch_bounds__(256) void k_psi(DevSystem s, const T* __restrict__ F, long long n,
                                              long long expand_max, u64* __restrict__ psi,
-                                             DevCounters* __restrict__ ctr) {
+                                             DevCounters* __restrict__ ctr, int parents_per_wave) {
+    extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
-    const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (p >= n) return;
-    const T* row = F + p * (long long)s.m;
-    u64 prod = 1;
-    bool any = false, over = false;
-    for (int j = lane; j < s.m; j += 64) {
-        const int x = (int)row[j];
-        int w = 0;
-        const int r1 = s.nrule_ptr[j + 1];
-        for (int q = s.nrule_ptr[j]; q < r1; ++q) w += rule_applies(x, s.rules[q]) ? 1 : 0;
-        any |= (w > 0);
-        over |= (expand_max >= 0 && (long long)x > expand_max);
-        prod = sat_mul(prod, (u64)(w > 1 ? w : 1));
+    const int m = s.m;
+    const int* nrp = s.nrule_ptr;
+    const int4* rules = s.rules;
+    if constexpr (TBL_LDS) {
+        int4* l_rules = (int4*)smem;
+        int* l_nrp = (int*)(l_rules + s.r);
+        for (int q = threadIdx.x; q < s.r; q += blockDim.x) l_rules[q] = s.rules[q];
+        for (int q = threadIdx.x; q <= m; q += blockDim.x) l_nrp[q] = s.nrule_ptr[q];
+        __syncthreads();
+        nrp = l_nrp;
+        rules = l_rules;
     }
-    prod = wave_satprod(prod);
-    const bool wany = __any(any);
-    const bool wover = __any(over);
-    if (lane == 0) {
-        psi[p] = (!wany || wover) ? 0 : prod;
-        if (!wany) atomicAdd(&ctr->halting, 1ULL);
+    const long long w0 = ((long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * parents_per_wave;
+    unsigned halting = 0;
+    for (long long p = w0; p < min(n, w0 + parents_per_wave); ++p) {
+        const T* row = F + p * (long long)m;
+        uint32_t c2 = 0, c3 = 0, c4 = 0;
+        bool any = false, over = false, big = false;
+        u64 bigprod = 1;
+        for (int base = 0; base < m; base += 64) {
+            const int j = base + lane;
+            int w = 0;
+            if (j < m) {
+                const int x = (int)row[j];
+                const int r1 = nrp[j + 1];
+                for (int q = nrp[j]; q < r1; ++q) w += rule_applies(x, rules[q]) ? 1 : 0;
+                over |= (expand_max >= 0 && (long long)x > expand_max);
+            }
+            any |= (w > 0);
+            c2 += __popcll(__ballot(w == 2));
+            c3 += __popcll(__ballot(w == 3));
+            c4 += __popcll(__ballot(w == 4));
+            if (w > 4) {
+                big = true;
+                bigprod = sat_mul(bigprod, (u64)w);
+            }
+        }
+        const bool wany = __any(any);
+        const bool wover = __any(over);
+        u64 prod = sat_mul(sat_mul(sat_pow(2, c2), sat_pow(3, c3)), sat_pow(4, c4));
+        if (__any(big)) prod = sat_mul(prod, wave_satprod(bigprod));
+        if (lane == 0) psi[p] = (!wany || wover) ? 0 : prod;
+        halting += wany ? 0u : 1u;
     }
+    if (lane == 0 && halting) atomicAdd(&ctr->halting, (u64)halting);
 }
 
 hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, long long n,
                       long long expand_max, u64* psi, DevCounters* ctr, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((n + 3) / 4);
-    if (elem_bytes == 4)
-        hipLaunchKernelGGL(k_psi<int32_t>, dim3(blocks), dim3(256), 0, st, s, (const int32_t*)frontier, n,
-                           expand_max, psi, ctr);
-    else
-        hipLaunchKernelGGL(k_psi<uint16_t>, dim3(blocks), dim3(256), 0, st, s, (const uint16_t*)frontier, n,
-                           expand_max, psi, ctr);
+    const size_t tbl = (size_t)s.r * 16 + (size_t)(s.m + 1) * 4;
+    const bool tbl_lds = tbl <= (size_t)(32 * 1024);
+    // enough parents per wave to amortise the table staging, while filling the GPU
+    int ppw = 1;
+    while (ppw < 16 && (long long)ppw * 2 * 4 * 2048 <= n) ppw <<= 1;
+    const long long waves = (n + ppw - 1) / ppw;
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    const size_t lds = tbl_lds ? tbl : 0;
+#define SNP_PSI(TT, L)                                                                                       \
+    hipLaunchKernelGGL((k_psi<TT, L>), dim3(blocks), dim3(256), lds, st, s, (const TT*)frontier, n, expand_max, \
+                       psi, ctr, ppw)
+    if (elem_bytes == 4) {
+        if (tbl_lds) SNP_PSI(int32_t, true);
+        else SNP_PSI(int32_t, false);
+    } else {
+        if (tbl_lds) SNP_PSI(uint16_t, true);
+        else SNP_PSI(uint16_t, false);
+    }
+#undef SNP_PSI
     return hipGetLastError();
 }
 
@@ -252,30 +328,53 @@ hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, long long n, uint3
 // Expansion, sparse form.  Every wave owns a run of consecutive children
 // g0 + b0 .. g0 + b0 + run - 1.  Per wave, LDS holds the parent row, the
 // applicable-rule mask and count omega of every neuron, the current digit of
-// every neuron and the production p of every neuron's fired rule.
+// every neuron, and the consumption c and production p of every neuron's
+// fired rule.  When the rule table and the in-synapse lists are small they are
+// staged once per block in LDS as well, so the per-child loop touches no
+// global memory except the row it writes.
 //
 //   decode (once per run): place value of each lane's block of neurons is a
 //     suffix product across lanes; digits follow by division.
 //   advance (per child): add one to the mixed-radix number: the last neuron
 //     with omega >= 2 whose digit is below omega - 1 steps up and every later
-//     neuron with omega >= 2 resets to 0; past the last child of a parent the
-//     wave moves to the next parent with Psi > 0, digits all 0.
+//     neuron with omega >= 2 resets to 0; only those neurons refresh their
+//     fired (c, p).  Past the last child of a parent the wave moves to the
+//     next parent with Psi > 0, digits all 0.
 //   child (per child): C'[d] = C[d] - c(fired rule of d) + sum over in-synapses
 //     (s, d) of p(fired rule of s): the nonzero entries of column d of S.M.
 // ---------------------------------------------------------------------------
-constexpr int kLdsBytesPerNeuron = 4 /*par*/ + 4 /*prod*/ + 4 /*mask*/ + 1 /*omega*/ + 1 /*digit*/;
+constexpr int kLdsBytesPerNeuron = 4 /*par*/ + 4 /*c:p*/ + 4 /*mask*/ + 1 /*omega*/ + 1 /*digit*/;
+constexpr int kTableLdsLimit = 24 * 1024;
+
+struct Tables {
+    const int* nrp;    // [m+1]
+    const int4* rules; // [r]
+    const int* inp;    // [m+1]
+    const int* ins;    // [nnz]
+};
+
+// Fired rule of neuron j packed as (c << 16) | p (both <= 65535, checked at load); 0 when none.
+__device__ __forceinline__ void set_fired(const Tables& tb, int j, const uint8_t* om, const uint32_t* am,
+                                          const uint8_t* dg, uint32_t* cp) {
+    uint32_t v = 0;
+    if (om[j]) {
+        const int4 R = tb.rules[tb.nrp[j] + nth_bit(am[j], dg[j])];
+        v = ((uint32_t)R.z << 16) | (uint32_t)R.w;
+    }
+    cp[j] = v;
+}
 
 template <typename T>
-__device__ __forceinline__ void load_parent(const DevSystem& s, const T* row, int lane, int* par, uint32_t* am,
+__device__ __forceinline__ void load_parent(const Tables& tb, int m, const T* row, int lane, int* par, uint32_t* am,
                                             uint8_t* om) {
-    for (int j = lane; j < s.m; j += 64) {
+    for (int j = lane; j < m; j += 64) {
         const int x = (int)row[j];
         par[j] = x;
         uint32_t mask = 0;
         int w = 0;
-        const int r0 = s.nrule_ptr[j], r1 = s.nrule_ptr[j + 1];
+        const int r0 = tb.nrp[j], r1 = tb.nrp[j + 1];
         for (int q = r0; q < r1; ++q)
-            if (rule_applies(x, s.rules[q])) {
+            if (rule_applies(x, tb.rules[q])) {
                 mask |= 1u << (q - r0);
                 ++w;
             }
@@ -306,84 +405,90 @@ __device__ __forceinline__ void decode_digits(int m, int lane, u64 t, const uint
     }
 }
 
-__device__ __forceinline__ void advance_digits(int m, int lane, const uint8_t* om, uint8_t* dg) {
-    int myJ = -1;
-    for (int j = lane; j < m; j += 64) {
-        const int w = om[j];
-        if (w >= 2 && dg[j] < w - 1) myJ = j;
-    }
-    const int J = wave_max_i32(myJ);
-    for (int j = lane; j < m; j += 64) {
-        const int w = om[j];
-        if (j == J) dg[j] = (uint8_t)(dg[j] + 1);
-        else if (w >= 2 && j > J) dg[j] = 0;
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a, int run, int lds_stride) {
+template <typename T, bool TBL_LDS>
+__global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a, int run, int wave_stride) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
+    const int m = s.m;
+    Tables tb{s.nrule_ptr, s.rules, s.in_ptr, s.in_src};
+    unsigned char* wave_base = smem;
+    if constexpr (TBL_LDS) {
+        // rule table and in-synapse lists, shared by the block's waves
+        int4* l_rules = (int4*)smem;
+        int* l_nrp = (int*)(l_rules + s.r);
+        int* l_inp = l_nrp + (m + 1);
+        int* l_ins = l_inp + (m + 1);
+        const int nnz = s.in_ptr[m];
+        for (int q = threadIdx.x; q < s.r; q += blockDim.x) l_rules[q] = s.rules[q];
+        for (int q = threadIdx.x; q <= m; q += blockDim.x) {
+            l_nrp[q] = s.nrule_ptr[q];
+            l_inp[q] = s.in_ptr[q];
+        }
+        for (int q = threadIdx.x; q < nnz; q += blockDim.x) l_ins[q] = s.in_src[q];
+        __syncthreads();
+        tb = Tables{l_nrp, l_rules, l_inp, l_ins};
+        const size_t tbytes = (size_t)s.r * 16 + (size_t)(m + 1) * 8 + (size_t)nnz * 4;
+        wave_base = smem + ((tbytes + 15) & ~(size_t)15);
+    }
     const long long wave = (long long)blockIdx.x * (blockDim.x >> 6) + wid;
     const long long b0 = wave * run;
     if (b0 >= a.B) return;
-    const int m = s.m;
-    unsigned char* base = smem + (size_t)wid * lds_stride;
+    unsigned char* base = wave_base + (size_t)wid * wave_stride;
     int* par = (int*)base;
-    int* prod = par + m;
-    uint32_t* am = (uint32_t*)(prod + m);
+    uint32_t* cp = (uint32_t*)(par + m);
+    uint32_t* am = cp + m;
     uint8_t* om = (uint8_t*)(am + m);
     uint8_t* dg = om + m;
     const T* F = (const T*)a.frontier;
     T* stage = (T*)a.stage;
     const int cnt = (int)min((long long)run, a.B - b0);
 
-    // parent of the first child: last p with off[p] <= g (it has Psi > 0)
+    // parent of the first child: last p with off[p] <= g (it has Psi > 0),
+    // found by a 64-ary search: every lane probes one point per round
     const u64 g = a.g0 + (u64)b0;
-    long long lo = 0, hi = a.n;
-    while (lo < hi) {
-        const long long mid = (lo + hi) >> 1;
-        if (a.off[mid] <= g) lo = mid + 1;
-        else hi = mid;
+    long long lo = 0, hi = a.n;  // off[lo] <= g; the answer lies in [lo, hi)
+    while (hi - lo > 1) {
+        const long long step = (hi - lo + 63) / 64;
+        const long long idx = lo + (long long)lane * step;
+        const bool ok = idx < hi && a.off[idx] <= g;
+        const u64 mask = __ballot(ok);
+        const int last = 63 - __clzll((long long)mask);
+        lo = lo + (long long)last * step;
+        hi = min(hi, lo + step);
     }
-    long long p = uni_ll(lo - 1);
+    long long p = uni_ll(lo);
     u64 t = uni64(g - a.off[p]);
     u64 psi_p = uni64(a.psi[p]);
-    load_parent<T>(s, F + p * (long long)m, lane, par, am, om);
+    load_parent<T>(tb, m, F + p * (long long)m, lane, par, am, om);
     wave_lds_sync();
     decode_digits(m, lane, t, om, dg);
     wave_lds_sync();
+    for (int j = lane; j < m; j += 64) set_fired(tb, j, om, am, dg, cp);
 
     bool ovf = false;
     for (int k = 0; k < cnt; ++k) {
         const long long b = b0 + k;
-        for (int j = lane; j < m; j += 64) {
-            int pv = 0;
-            if (om[j]) pv = s.rules[s.nrule_ptr[j] + nth_bit(am[j], dg[j])].w;
-            prod[j] = pv;
-        }
         wave_lds_sync();
         u64 h = 0;
         T* out = stage + b * (long long)m;
         for (int j = lane; j < m; j += 64) {
-            long long v = par[j];
-            if (om[j]) v -= s.rules[s.nrule_ptr[j] + nth_bit(am[j], dg[j])].z;
-            const int e1 = s.in_ptr[j + 1];
-            for (int e = s.in_ptr[j]; e < e1; ++e) v += prod[s.in_src[e]];
+            long long v = (long long)par[j] - (long long)(cp[j] >> 16);
+            const int e1 = tb.inp[j + 1];
+            for (int e = tb.inp[j]; e < e1; ++e) v += cp[tb.ins[e]] & 0xFFFFu;
             ovf |= (v < 0) | (v > s.count_max);
             out[j] = (T)v;
-            h += elem_hash(j, (uint32_t)v);
+            h = hash_acc(h, elem_hash(j, (uint32_t)v));
         }
-        h = wave_sum_u64(h);
+        h = wave_hash_total(h);
         if (lane == 0) {
             a.hash[b] = h & a.hash_mask;
             a.cpar[b] = (int)p;
             a.ct[b] = t;
         }
-        wave_lds_sync();
         if (k + 1 < cnt) {
             ++t;
+            wave_lds_sync();  // every lane has read cp before it changes
             if (t >= psi_p) {
                 ++p;
                 while (p < a.n && a.psi[p] == 0) ++p;
@@ -391,45 +496,94 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
                 if (p >= a.n) break;  // unreachable while g0 + B <= sum of Psi
                 t = 0;
                 psi_p = uni64(a.psi[p]);
-                load_parent<T>(s, F + p * (long long)m, lane, par, am, om);
-                for (int j = lane; j < m; j += 64) dg[j] = 0;
+                load_parent<T>(tb, m, F + p * (long long)m, lane, par, am, om);
+                for (int j = lane; j < m; j += 64) {
+                    dg[j] = 0;
+                    set_fired(tb, j, om, am, dg, cp);
+                }
             } else {
-                advance_digits(m, lane, om, dg);
+                int myJ = -1;
+                for (int j = lane; j < m; j += 64) {
+                    const int w = om[j];
+                    if (w >= 2 && dg[j] < w - 1) myJ = j;
+                }
+                const int J = wave_max_i32(myJ);
+                for (int j = lane; j < m; j += 64) {
+                    const int w = om[j];
+                    if (j == J) {
+                        dg[j] = (uint8_t)(dg[j] + 1);
+                        set_fired(tb, j, om, am, dg, cp);
+                    } else if (w >= 2 && j > J) {
+                        dg[j] = 0;
+                        set_fired(tb, j, om, am, dg, cp);
+                    }
+                }
             }
-            wave_lds_sync();
         }
     }
     if (__any(ovf) && lane == 0) atomicOr((unsigned long long*)&a.ctr->overflow, 1ULL);
 }
 
+static size_t table_lds_bytes(const DevSystem& s, int nnz) {
+    return (((size_t)s.r * 16 + (size_t)(s.m + 1) * 8 + (size_t)nnz * 4) + 15) & ~(size_t)15;
+}
+
 hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st) {
     if (a.B <= 0) return hipSuccess;
     const int stride = ((kLdsBytesPerNeuron * s.m) + 15) & ~15;
-    int wpb = 4;
-    while (wpb > 1 && (size_t)wpb * stride > 64 * 1024) wpb >>= 1;
     if ((size_t)stride > 64 * 1024) return hipErrorInvalidValue;  // m too large for this form
-    const int run = 16;
+    const size_t tbl = table_lds_bytes(s, s.nnz_in);
+    const bool tbl_lds = tbl <= (size_t)kTableLdsLimit;
+    int wpb = 4;
+    while (wpb > 1 && (size_t)wpb * stride + (tbl_lds ? tbl : 0) > 64 * 1024) wpb >>= 1;
+    if (tbl_lds && (size_t)wpb * stride + tbl > 64 * 1024) return hipErrorInvalidValue;
+    // runs short enough that the chunk spreads over the whole GPU
+    int run = 4;
+    while (run < 32 && (long long)run * 2 * 8192 <= a.B) run <<= 1;
     const long long waves = (a.B + run - 1) / run;
     const unsigned blocks = (unsigned)((waves + wpb - 1) / wpb);
-    const size_t lds = (size_t)wpb * stride;
-    if (elem_bytes == 4)
-        hipLaunchKernelGGL(k_expand_sparse<int32_t>, dim3(blocks), dim3(64 * wpb), lds, st, s, a, run, stride);
-    else
-        hipLaunchKernelGGL(k_expand_sparse<uint16_t>, dim3(blocks), dim3(64 * wpb), lds, st, s, a, run, stride);
+    const size_t lds = (size_t)wpb * stride + (tbl_lds ? tbl : 0);
+    if (elem_bytes == 4) {
+        if (tbl_lds)
+            hipLaunchKernelGGL((k_expand_sparse<int32_t, true>), dim3(blocks), dim3(64 * wpb), lds, st, s, a, run, stride);
+        else
+            hipLaunchKernelGGL((k_expand_sparse<int32_t, false>), dim3(blocks), dim3(64 * wpb), lds, st, s, a, run, stride);
+    } else {
+        if (tbl_lds)
+            hipLaunchKernelGGL((k_expand_sparse<uint16_t, true>), dim3(blocks), dim3(64 * wpb), lds, st, s, a, run, stride);
+        else
+            hipLaunchKernelGGL((k_expand_sparse<uint16_t, false>), dim3(blocks), dim3(64 * wpb), lds, st, s, a, run, stride);
+    }
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Visited set.  Open addressing with linear probing over 64-bit entries
-// (tag:32 | ref:32).  A child claims an empty slot with a CAS; a child that
-// meets an entry with its tag compares the whole rows; an equal row of the
-// current chunk with a larger index is replaced by atomicMin on the entry, so
-// the entry ends at the first occurrence in canonical order.
+// (tag:32 | ref:32).  One thread per child: it claims an empty slot with a
+// CAS; on an entry with its tag it compares the whole rows; an equal row of
+// the current chunk with a larger index is replaced by atomicMin on the entry,
+// so the entry ends at the first occurrence in canonical order.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_insert(int m, TableArgs a) {
-    const int lane = threadIdx.x & 63;
-    const long long b = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+__device__ __forceinline__ bool rows_equal(const T* x, const T* y, int m, bool vec16) {
+    if (vec16) {
+        const uint4* a = (const uint4*)x;
+        const uint4* b = (const uint4*)y;
+        const int n = (int)((size_t)m * sizeof(T) / 16);
+        for (int q = 0; q < n; ++q) {
+            const uint4 u = a[q], v = b[q];
+            if (u.x != v.x || u.y != v.y || u.z != v.z || u.w != v.w) return false;
+        }
+        return true;
+    }
+    for (int j = 0; j < m; ++j)
+        if (x[j] != y[j]) return false;
+    return true;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_insert(int m, TableArgs a, int vec16) {
+    const long long b = (long long)blockIdx.x * 256 + threadIdx.x;
     if (b >= a.B) return;
     const u64 h = a.hash[b];
     const uint32_t tag = (uint32_t)(h >> 32);
@@ -438,13 +592,11 @@ __global__ __launch_bounds__(256) void k_insert(int m, TableArgs a) {
     const T* row = (const T*)a.stage + b * (long long)m;
     u64 sl = h & a.slot_mask;
     for (u64 it = 0; it <= a.slot_mask; ++it) {
-        u64 e = uni64(__hip_atomic_load(&a.table[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        u64 e = __hip_atomic_load(&a.table[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (e == kEmpty) {
-            u64 old = 0;
-            if (lane == 0) old = atomicCAS(&a.table[sl], kEmpty, mine);
-            old = uni64(__shfl(old, 0));
+            const u64 old = atomicCAS(&a.table[sl], kEmpty, mine);
             if (old == kEmpty) {
-                if (lane == 0) a.slot[b] = (uint32_t)sl;
+                a.slot[b] = (uint32_t)sl;
                 return;
             }
             e = old;
@@ -453,29 +605,25 @@ __global__ __launch_bounds__(256) void k_insert(int m, TableArgs a) {
             const uint32_t ref = (uint32_t)e;
             const T* other = ref < kStageBase ? (const T*)a.arena + (u64)ref * (u64)m
                                               : (const T*)a.stage + (u64)(ref - kStageBase) * (u64)m;
-            bool diff = false;
-            for (int j = lane; j < m; j += 64) diff |= (row[j] != other[j]);
-            if (!__any(diff)) {
-                if (lane == 0) {
-                    if (ref >= kStageBase && myref < ref) atomicMin(&a.table[sl], mine);
-                    a.slot[b] = (uint32_t)sl;
-                }
+            if (rows_equal<T>(row, other, m, vec16 != 0)) {
+                if (ref >= kStageBase && myref < ref) atomicMin(&a.table[sl], mine);
+                a.slot[b] = (uint32_t)sl;
                 return;
             }
         }
         sl = (sl + 1) & a.slot_mask;
     }
-    if (lane == 0) {
-        a.slot[b] = 0;  // keep later kernels in bounds; the host reports the failure
-        atomicOr((unsigned long long*)&a.ctr->probe_fail, 1ULL);
-    }
+    a.slot[b] = 0;  // keep later kernels in bounds; the host reports the failure
+    atomicOr((unsigned long long*)&a.ctr->probe_fail, 1ULL);
 }
 
 hipError_t launch_insert(int elem_bytes, int m, const TableArgs& a, hipStream_t st) {
     if (a.B <= 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((a.B + 3) / 4);
-    if (elem_bytes == 4) hipLaunchKernelGGL(k_insert<int32_t>, dim3(blocks), dim3(256), 0, st, m, a);
-    else hipLaunchKernelGGL(k_insert<uint16_t>, dim3(blocks), dim3(256), 0, st, m, a);
+    const size_t rb = (size_t)m * elem_bytes;
+    const int vec16 = (rb % 16 == 0 && ((uintptr_t)a.arena % 16) == 0 && ((uintptr_t)a.stage % 16) == 0) ? 1 : 0;
+    const unsigned blocks = (unsigned)((a.B + 255) / 256);
+    if (elem_bytes == 4) hipLaunchKernelGGL(k_insert<int32_t>, dim3(blocks), dim3(256), 0, st, m, a, vec16);
+    else hipLaunchKernelGGL(k_insert<uint16_t>, dim3(blocks), dim3(256), 0, st, m, a, vec16);
     return hipGetLastError();
 }
 
@@ -494,44 +642,61 @@ hipError_t launch_flags(const u64* table, const uint32_t* slot, long long B, uin
 
 // Commit the new children of a chunk in canonical order: rows below the
 // level's limit are copied to the row store and their entries re-pointed at
-// it; the rest (past a cap) become tombstones, i.e. are not recorded.
-template <typename T>
-__global__ __launch_bounds__(256) void k_commit(int m, CommitArgs a) {
-    const int lane = threadIdx.x & 63;
-    const long long b = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (b >= a.B) return;
-    if (!a.flag[b]) return;
-    const long long local = a.level_count + (long long)a.pos[b];
-    const uint32_t sl = a.slot[b];
-    const uint32_t tag = (uint32_t)(a.hash[b] >> 32);
-    if (local < a.limit) {
-        const long long A = a.level_base + local;
-        const T* src = (const T*)a.stage + b * (long long)m;
-        T* dst = (T*)a.arena + A * (long long)m;
-        T* dst2 = a.row2 ? (T*)a.row2 + local * (long long)m : nullptr;
-        for (int j = lane; j < m; j += 64) {
-            const T v = src[j];
-            dst[j] = v;
-            if (dst2) dst2[j] = v;
-        }
-        if (lane == 0) {
+// it; the rest (past a cap) become tombstones, i.e. are not recorded.  One
+// block per 256 children: a thread per child updates the visited set, then the
+// block copies the tile's new rows, which land contiguously, in units of U.
+template <typename U>
+__global__ __launch_bounds__(256) void k_commit(int upr /* units per row */, CommitArgs a) {
+    __shared__ int srcb[256];
+    const long long b0 = (long long)blockIdx.x * 256;
+    const long long b = b0 + threadIdx.x;
+    const uint32_t p0 = a.pos[b0];
+    bool isnew = false;
+    if (b < a.B && a.flag[b]) {
+        isnew = true;
+        const uint32_t pb = a.pos[b];
+        srcb[pb - p0] = threadIdx.x;
+        const long long local = a.level_count + (long long)pb;
+        const uint32_t sl = a.slot[b];
+        const uint32_t tag = (uint32_t)(a.hash[b] >> 32);
+        if (local < a.limit) {
+            const long long A = a.level_base + local;
             a.table[sl] = ((u64)tag << 32) | (uint32_t)A;
             a.row_slot[A] = sl;
             if (a.par_out) a.par_out[a.par_out_base + local] = (long long)a.cpar[b] + a.par_value_base;
             if (a.t_out) a.t_out[a.par_out_base + local] = (long long)a.ct[b];
             if (local == a.limit - 1) a.ctr->cap_g = (u64)b + 1;
+        } else {
+            a.table[sl] = kTomb;
         }
-    } else if (lane == 0) {
-        a.table[sl] = kTomb;
-        atomicAdd(&a.ctr->tombs, 1ULL);
+    }
+    const int nnew = __syncthreads_count(isnew);
+    const long long first_local = a.level_count + (long long)p0;
+    const int ncopy = (int)max(0LL, min((long long)nnew, a.limit - first_local));
+    const U* src = (const U*)a.stage + b0 * upr;
+    U* dst = (U*)a.arena + (a.level_base + first_local) * upr;
+    U* dst2 = a.row2 ? (U*)a.row2 + first_local * upr : nullptr;
+    const int total = ncopy * upr;
+    for (int v = threadIdx.x; v < total; v += 256) {
+        const int i = v / upr;
+        const int o = v - i * upr;
+        const U x = src[(long long)srcb[i] * upr + o];
+        dst[v] = x;
+        if (dst2) dst2[v] = x;
     }
 }
 
 hipError_t launch_commit(int elem_bytes, int m, const CommitArgs& a, hipStream_t st) {
     if (a.B <= 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((a.B + 3) / 4);
-    if (elem_bytes == 4) hipLaunchKernelGGL(k_commit<int32_t>, dim3(blocks), dim3(256), 0, st, m, a);
-    else hipLaunchKernelGGL(k_commit<uint16_t>, dim3(blocks), dim3(256), 0, st, m, a);
+    const size_t rb = (size_t)m * elem_bytes;
+    const uintptr_t al = (uintptr_t)a.stage | (uintptr_t)a.arena | (uintptr_t)a.row2;
+    const unsigned blocks = (unsigned)((a.B + 255) / 256);
+    if (rb % 16 == 0 && al % 16 == 0)
+        hipLaunchKernelGGL(k_commit<uint4>, dim3(blocks), dim3(256), 0, st, (int)(rb / 16), a);
+    else if (rb % 4 == 0 && al % 4 == 0)
+        hipLaunchKernelGGL(k_commit<uint32_t>, dim3(blocks), dim3(256), 0, st, (int)(rb / 4), a);
+    else
+        hipLaunchKernelGGL(k_commit<uint16_t>, dim3(blocks), dim3(256), 0, st, (int)(rb / 2), a);
     return hipGetLastError();
 }
 
@@ -548,6 +713,17 @@ __global__ __launch_bounds__(256) void k_fill_u64(u64* __restrict__ p, long long
 hipError_t launch_fill_u64(u64* p, long long n, u64 v, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_fill_i32(int* __restrict__ p, long long n, int v) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
     return hipGetLastError();
 }
 

@@ -22,7 +22,8 @@ SNP_PATH_AUTO, SNP_PATH_SPARSE, SNP_PATH_INT8 = 0, 1, 2
 STOP_NAMES = {0: "EMPTY_FRONTIER", 1: "ALL_HALTING", 2: "DEPTH", 3: "CAP", 4: "BUDGET"}
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OVERFLOW", 3: "CAPACITY", 4: "BUDGET", 5: "DEVICE"}
 
-EXPORTED = ("snp_load", "snp_free", "snp_last_error", "snp_row_bytes", "snp_reset", "snp_expand", "snp_run")
+EXPORTED = ("snp_load", "snp_free", "snp_last_error", "snp_row_bytes", "snp_reset", "snp_expand", "snp_run",
+            "snp_batch_load", "snp_batch_free", "snp_batch_offsets", "snp_batch_run")
 
 
 class SnpError(RuntimeError):
@@ -48,7 +49,8 @@ class snp_options(ctypes.Structure):
         ("frontier_cap", ctypes.c_int64), ("child_budget", ctypes.c_int64),
         ("expand_max_count", ctypes.c_int64), ("max_rows", ctypes.c_int64),
         ("max_frontier", ctypes.c_int64), ("chunk", ctypes.c_int64),
-        ("hash_mask", ctypes.c_uint64), ("stream", ctypes.c_void_p),
+        ("hash_mask", ctypes.c_uint64), ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
     ]
 
 
@@ -56,9 +58,11 @@ class snp_expand_stats(ctypes.Structure):
     _fields_ = [
         ("parents", ctypes.c_int64), ("halting_parents", ctypes.c_int64),
         ("children_total", ctypes.c_int64), ("enumerated", ctypes.c_int64),
-        ("new_configs", ctypes.c_int64), ("chunks", ctypes.c_int64),
+        ("new_configs", ctypes.c_int64), ("expanded", ctypes.c_int64), ("chunks", ctypes.c_int64),
         ("truncated", ctypes.c_int32), ("budget_hit", ctypes.c_int32),
         ("path_used", ctypes.c_int32), ("int8_fallback", ctypes.c_int32),
+        ("ns_psi", ctypes.c_int64), ("ns_expand", ctypes.c_int64), ("ns_insert", ctypes.c_int64),
+        ("ns_flags", ctypes.c_int64), ("ns_commit", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -94,6 +98,14 @@ def lib():
         L.snp_run.argtypes = [P, P, I32, P, I64, ctypes.POINTER(I64), P, I32, ctypes.POINTER(I32),
                               ctypes.POINTER(I32), P, P, P]
         L.snp_run.restype = I32
+        L.snp_batch_load.argtypes = [ctypes.POINTER(snp_desc), I32, ctypes.POINTER(snp_options), ctypes.POINTER(P)]
+        L.snp_batch_load.restype = I32
+        L.snp_batch_free.argtypes = [P]
+        L.snp_batch_free.restype = None
+        L.snp_batch_offsets.argtypes = [P, P]
+        L.snp_batch_offsets.restype = I32
+        L.snp_batch_run.argtypes = [P, P, I32, I32, P, P, P, P, P]
+        L.snp_batch_run.restype = I32
         _lib = L
     return _lib
 
@@ -137,30 +149,40 @@ class Handle:
             pass
 
 
-def snp_load(system, *, path: int = SNP_PATH_AUTO, stop_at_cap: bool = False, frontier_cap: int = 0,
-             child_budget: int = 0, expand_max_count: int = -1, max_rows: int = 1 << 20,
-             max_frontier: int = 0, chunk: int = 0, hash_mask: int = 0, stream=None,
-             M: Optional[np.ndarray] = None) -> Handle:
-    """snp_load.  ``system`` has m, rule_neuron/i/j/c/p, syn_src/dst and
-    count_type ("i32" or "u16") attributes; ``stream`` is a torch.cuda.Stream
-    (None: torch's current stream)."""
+def _desc(system, keep, M=None) -> snp_desc:
     arrs = [_i32(system.rule_neuron), _i32(system.rule_i), _i32(system.rule_j), _i32(system.rule_c),
             _i32(system.rule_p), _i32(system.syn_src), _i32(system.syn_dst)]
-    Mp = None
-    if M is not None:
-        Mp = _i32(M)
-        arrs.append(Mp)
+    Mp = _i32(M) if M is not None else None
+    keep.extend(arrs)
+    if Mp is not None:
+        keep.append(Mp)
     ct = SNP_COUNT_U16 if getattr(system, "count_type", "i32") == "u16" else SNP_COUNT_I32
-    d = snp_desc(int(system.m), int(arrs[0].shape[0]), arrs[0].ctypes.data, arrs[1].ctypes.data,
-                 arrs[2].ctypes.data, arrs[3].ctypes.data, arrs[4].ctypes.data, int(arrs[5].shape[0]),
-                 arrs[5].ctypes.data, arrs[6].ctypes.data, Mp.ctypes.data if Mp is not None else None, ct)
+    return snp_desc(int(system.m), int(arrs[0].shape[0]), arrs[0].ctypes.data, arrs[1].ctypes.data,
+                    arrs[2].ctypes.data, arrs[3].ctypes.data, arrs[4].ctypes.data, int(arrs[5].shape[0]),
+                    arrs[5].ctypes.data, arrs[6].ctypes.data, Mp.ctypes.data if Mp is not None else None, ct)
+
+
+def _stream_ptr(stream):
     if stream is None:
         import torch
         stream = torch.cuda.current_stream() if torch.cuda.is_available() else 0
-    sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0)
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0)
+
+
+def snp_load(system, *, path: int = SNP_PATH_AUTO, stop_at_cap: bool = False, frontier_cap: int = 0,
+             child_budget: int = 0, expand_max_count: int = -1, max_rows: int = 1 << 20,
+             max_frontier: int = 0, chunk: int = 0, hash_mask: int = 0, profile: bool = False,
+             stream=None, M: Optional[np.ndarray] = None) -> Handle:
+    """snp_load.  ``system`` has m, rule_neuron/i/j/c/p, syn_src/dst and
+    count_type ("i32" or "u16") attributes; ``stream`` is a torch.cuda.Stream
+    (None: torch's current stream)."""
+    arrs = []
+    d = _desc(system, arrs, M)
+    ct = d.count_type
+    sp = _stream_ptr(stream)
     o = snp_options(int(path), int(bool(stop_at_cap)), int(frontier_cap), int(child_budget),
                     int(expand_max_count), int(max_rows), int(max_frontier), int(chunk),
-                    int(hash_mask) & ((1 << 64) - 1), sp or None)
+                    int(hash_mask) & ((1 << 64) - 1), int(bool(profile)), 0, sp or None)
     out = ctypes.c_void_p()
     _check(lib().snp_load(ctypes.byref(d), ctypes.byref(o), ctypes.byref(out)), "snp_load")
     return Handle(out.value, arrs, int(system.m), ct)
@@ -220,3 +242,58 @@ def snp_run(h: Handle, c0_dev, max_depth: int, out_dev, out_capacity: int, max_l
 def torch_dtype(count_type: int):
     import torch
     return torch.uint16 if count_type == SNP_COUNT_U16 else torch.int32
+
+
+class BatchHandle:
+    """A loaded batch of systems (snp_batch*)."""
+
+    def __init__(self, ptr: int, keep, n: int, count_type: int):
+        self.ptr = ctypes.c_void_p(ptr)
+        self._keep = keep
+        self.n = n
+        self.count_type = count_type
+
+    def close(self):
+        if self.ptr:
+            lib().snp_batch_free(self.ptr)
+            self.ptr = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def snp_batch_load(systems, stream=None) -> BatchHandle:
+    keep = []
+    descs = (snp_desc * len(systems))(*[_desc(s, keep) for s in systems])
+    o = snp_options()
+    o.max_rows = 1
+    o.stream = _stream_ptr(stream) or None
+    out = ctypes.c_void_p()
+    _check(lib().snp_batch_load(descs, len(systems), ctypes.byref(o), ctypes.byref(out)), "snp_batch_load")
+    return BatchHandle(out.value, (keep, descs), len(systems), int(descs[0].count_type))
+
+
+def snp_batch_free(b: BatchHandle):
+    b.close()
+
+
+def snp_batch_offsets(b: BatchHandle) -> np.ndarray:
+    off = np.zeros(b.n + 1, dtype=np.int64)
+    _check(lib().snp_batch_offsets(b.ptr, off.ctypes.data), "snp_batch_offsets")
+    return off
+
+
+def snp_batch_run(b: BatchHandle, c0_dev, steps: int, final_dev, detect_repeats: bool = True) -> dict:
+    """Returns dict of numpy arrays: halt_step, first_repeat, steps_done, digest."""
+    n = b.n
+    halt = np.zeros(n, dtype=np.int32)
+    rep = np.zeros(n, dtype=np.int32)
+    done = np.zeros(n, dtype=np.int32)
+    dig = np.zeros(n, dtype=np.uint64)
+    _check(lib().snp_batch_run(b.ptr, _ptr(c0_dev), int(steps), int(bool(detect_repeats)), _ptr(final_dev),
+                               halt.ctypes.data, rep.ctypes.data, done.ctypes.data, dig.ctypes.data),
+           "snp_batch_run")
+    return dict(halt_step=halt, first_repeat=rep, steps_done=done, digest=dig)

@@ -1,0 +1,127 @@
+"""Deterministic batched mode (one launch for many systems) against the oracle:
+final configuration, halting step, first repeat, steps computed and the
+trajectory checksum, all bit-exact."""
+import numpy as np
+import pytest
+
+import synth
+from paper_1104_1824_amd import snp
+from tests.gpu_helpers import from_device_rows, note
+
+pytestmark = pytest.mark.gpu
+
+
+def ring(m, c0_pos=0):
+    """One spike travelling round a ring: C_k = e_{k mod m}, first repeat at step m."""
+    rules = [(n, 1, 1, 1, 1) for n in range(m)]
+    syn = [(n, (n + 1) % m) for n in range(m)]
+    c0 = [0] * m
+    c0[c0_pos] = 1
+    return synth.make_system(m, rules, syn, c0, name=f"ring{m}")
+
+
+def path(m):
+    """One spike along a path that leaves at its end: C_m = 0, which halts."""
+    rules = [(n, 1, 1, 1, 1) for n in range(m)]
+    syn = [(n, n + 1) for n in range(m - 1)]
+    c0 = [0] * m
+    c0[0] = 1
+    return synth.make_system(m, rules, syn, c0, name=f"path{m}")
+
+
+def run_batch(systems, steps, detect=True):
+    import torch
+
+    b = snp.snp_batch_load(systems)
+    try:
+        off = snp.snp_batch_offsets(b)
+        dt = torch.int16 if systems[0].count_type == "u16" else torch.int32
+        c0 = np.concatenate([np.asarray(s.c0, dtype=np.int64) for s in systems])
+        if systems[0].count_type == "u16":
+            c0 = c0.astype(np.uint16).view(np.int16)
+        c0_t = torch.from_numpy(c0.astype(np.int16 if systems[0].count_type == "u16" else np.int32)).cuda()
+        final = torch.empty(int(off[-1]), dtype=dt, device="cuda")
+        res = snp.snp_batch_run(b, c0_t, steps, final, detect)
+        fin = from_device_rows(systems[0], final)
+        res["final"] = [fin[off[k]: off[k + 1]] for k in range(len(systems))]
+        return res
+    finally:
+        b.close()
+
+
+def check_against_oracle(oracle_mod, systems, steps, res, detect=True):
+    for k, s in enumerate(systems):
+        d = oracle_mod.deterministic(s, steps)
+        assert res["final"][k].tolist() == d.final.tolist(), (k, s.name)
+        assert int(res["halt_step"][k]) == d.halt_step, (k, s.name)
+        assert int(res["steps_done"][k]) == d.steps_done, (k, s.name)
+        assert int(res["digest"][k]) == d.digest, (k, s.name)
+        if detect:
+            assert int(res["first_repeat"][k]) == d.first_repeat, (k, s.name)
+
+
+def test_batch_constructed_repeats_and_halts(gpu, oracle_mod):
+    ex, tb = synth.paper_example(), synth.paper_example(True)
+    tb_halt = synth.make_system(tb.m, tb.rules(), list(zip(tb.syn_src, tb.syn_dst)), [0, 1, 1])
+    systems = [ex, tb, tb_halt, ring(5), ring(64), ring(100), ring(128), ring(200, 7), path(150), path(64)]
+    for steps in (0, 1, 63, 64, 65, 300):
+        note(f"batch constructed systems, steps {steps}")
+        res = run_batch(systems, steps)
+        check_against_oracle(oracle_mod, systems, steps, res)
+    res = run_batch(systems, 300)
+    assert res["first_repeat"].tolist()[3:8] == [5, 64, 100, 128, 200]
+    assert res["halt_step"].tolist()[8:] == [150, 64]
+
+
+def test_batch_tiny_seeds(gpu, oracle_mod):
+    systems = [synth.config_system(1, s) for s in range(64)]
+    note("batch of 64 tiny systems, 500 steps")
+    check_against_oracle(oracle_mod, systems, 500, run_batch(systems, 500))
+
+
+def test_batch_uneven_recipe_sample(gpu, oracle_mod):
+    """Systems of the batched recipe (m in [16, 1024]) for 1500 steps."""
+    systems = synth.batched_systems(0, 24)
+    note("batch of 24 uneven systems, 1500 steps")
+    check_against_oracle(oracle_mod, systems, 1500, run_batch(systems, 1500))
+
+
+def test_batch_full_recipe_sampled(gpu, oracle_mod):
+    """The full batched workload (256 systems, 10k steps) in one launch; every
+    fourth-largest... a sample of systems checked against the oracle."""
+    systems = synth.batched_systems(0, 256)
+    note("batch of 256 uneven systems, 10000 steps")
+    res = run_batch(systems, 10000)
+    sample = [0, 1, 2, 37, 101, 255]
+    sub = {k: systems[k] for k in sample}
+    for k, s in sub.items():
+        d = oracle_mod.deterministic(s, 10000)
+        assert res["final"][k].tolist() == d.final.tolist()
+        assert int(res["digest"][k]) == d.digest
+        assert int(res["first_repeat"][k]) == d.first_repeat
+        assert int(res["halt_step"][k]) == d.halt_step
+
+
+def test_batch_uint16_and_overflow(gpu, oracle_mod):
+    systems = [synth.config_system(1, s) for s in range(8)]
+    u16 = [synth.make_system(s.m, s.rules(), list(zip(s.syn_src, s.syn_dst)), s.c0, count_type="u16")
+           for s in systems]
+    note("uint16 batch")
+    check_against_oracle(oracle_mod, u16, 200, run_batch(u16, 200))
+    note("uint16 overflow")
+    # two neurons feeding each other: each consumes 1 and receives 2 per step
+    grow = synth.make_system(2, [(0, 1, 1, 1, 2), (1, 1, 1, 1, 2)], [(0, 1), (1, 0)], [65530, 65530],
+                             count_type="u16")
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.deterministic(grow, 50)
+    with pytest.raises(snp.SnpError) as e:
+        run_batch([grow] + u16, 50)
+    assert e.value.status == snp.SNP_ERR_OVERFLOW
+
+
+def test_batch_without_repeat_detection(gpu, oracle_mod):
+    systems = [ring(100), synth.paper_example(True), path(70)]
+    note("repeat detection off")
+    res = run_batch(systems, 250, detect=False)
+    check_against_oracle(oracle_mod, systems, 250, res, detect=False)
+    assert res["first_repeat"].tolist() == [-1, -1, -1]
