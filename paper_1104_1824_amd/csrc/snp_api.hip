@@ -39,6 +39,12 @@ constexpr int kMaxRulesPerNeuron = 32;  // applicable-rule masks are 32-bit
 constexpr int kMaxNeurons = 4608;       // per-wave LDS state of the expansion kernel (14 B per neuron) <= 64 KiB
 constexpr long long kInf = LLONG_MAX / 4;
 
+u64 host_mix64(u64 z) {  // SplitMix64 output finaliser
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
 u64 next_pow2(u64 x) {
     u64 p = 1;
     while (p < x) p <<= 1;
@@ -64,6 +70,12 @@ struct snp_system {
     int4* d_rules = nullptr;
     int* d_in_ptr = nullptr;
     int* d_in_src = nullptr;
+    int8_t* d_M8 = nullptr;  // r x m int8 copy of M_Pi when every entry fits (int8 path)
+    u64* d_R = nullptr;      // hash weights
+    u64* d_hM = nullptr;     // H of every row of M_Pi
+    bool int8_ready = false; // d_M8 built and the int8 kernel's limits hold
+    double sparse_work = 0;  // per-child work estimates of the two forms (path choice)
+    double int8_work = 0;
     snp::DevSystem dsys{};
 
     // visited set
@@ -95,7 +107,7 @@ struct snp_system {
     hipEvent_t ev[kStages + 1] = {};
 
     ~snp_system() {
-        void* ptrs[] = {d_nrule_ptr, d_rules, d_in_ptr, d_in_src, d_table, d_row_slot, d_psi, d_off,
+        void* ptrs[] = {d_nrule_ptr, d_rules, d_in_ptr, d_in_src, d_M8, d_R, d_hM, d_table, d_row_slot, d_psi, d_off,
                         d_sc_sums, d_sc_pre, d_stage, d_hash, d_cpar, d_ct, d_slot, d_flag, d_pos,
                         d_fsums, d_fpre, d_ctr, d_store};
         for (void* p : ptrs)
@@ -223,7 +235,7 @@ snp_status clear_counters(snp_system* S) {
 // Empty the visited set and insert rows [0, rows) of the row store.
 snp_status rebuild_table(snp_system* S, const void* arena, long long rows) {
     HIPCHK(snp::launch_fill_u64(S->d_table, (long long)S->slots, snp::kEmpty, S->stream));
-    HIPCHK(snp::launch_rows_insert(S->elem_bytes, S->m, S->d_table, S->slots - 1, arena, 0, rows,
+    HIPCHK(snp::launch_rows_insert(S->elem_bytes, S->m, S->d_R, S->d_table, S->slots - 1, arena, 0, rows,
                                    S->opt.hash_mask ? S->opt.hash_mask : ~0ULL, S->d_row_slot, S->d_ctr,
                                    S->stream));
     S->tombs = 0;
@@ -271,8 +283,11 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
     snp_expand_stats stt{};
     *count_out = 0;
     stt.parents = io.n;
-    stt.path_used = SNP_PATH_SPARSE;
-    stt.int8_fallback = (S->opt.path == SNP_PATH_INT8 && !S->int8_ok) ? 1 : 0;
+    stt.int8_fallback = (S->opt.path == SNP_PATH_INT8 && !S->int8_ready) ? 1 : 0;
+    bool use_int8 = false;
+    if (S->opt.path == SNP_PATH_INT8) use_int8 = S->int8_ready;
+    else if (S->opt.path == SNP_PATH_AUTO) use_int8 = S->int8_ready && S->int8_work < S->sparse_work;
+    stt.path_used = use_int8 ? SNP_PATH_INT8 : SNP_PATH_SPARSE;
     if (io.n > S->max_frontier)
         return fail(SNP_ERR_CAPACITY, "frontier of %lld rows exceeds max_frontier %lld", io.n, S->max_frontier);
     snp_status st;
@@ -322,7 +337,8 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         snp::ChunkArgs ca{io.frontier, io.n, S->d_psi, S->d_off, G, B, S->d_stage, S->d_hash, S->d_cpar, S->d_ct,
                           hmask, S->d_ctr};
         if ((st = mark(S, 0))) return st;
-        HIPCHK(snp::launch_expand_sparse(S->elem_bytes, S->dsys, ca, S->stream));
+        if (use_int8) HIPCHK(snp::launch_expand_int8(S->elem_bytes, S->dsys, ca, S->stream));
+        else HIPCHK(snp::launch_expand_sparse(S->elem_bytes, S->dsys, ca, S->stream));
         if ((st = mark(S, 1))) return st;
         snp::TableArgs ta{S->d_table, S->slots - 1, io.arena, S->d_stage, S->d_hash, S->d_slot, B, S->d_ctr};
         HIPCHK(snp::launch_insert(S->elem_bytes, S->m, ta, S->stream));
@@ -464,8 +480,43 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     LOADCHK(up(S->d_rules, rules.data(), sizeof(int4) * d->r));
     LOADCHK(up(S->d_in_ptr, in_ptr.data(), sizeof(int) * (d->m + 1)));
     LOADCHK(up(S->d_in_src, in_src.data(), sizeof(int) * d->n_syn));
-    S->dsys = snp::DevSystem{d->m, d->r, S->d_nrule_ptr, S->d_rules, S->d_in_ptr, S->d_in_src, d->n_syn, nullptr,
-                             S->count_max};
+    // hash weights R[n] and the hash H of every row of M_Pi (Definition 2 rows,
+    // entries sign-extended, arithmetic mod 2^64)
+    std::vector<u64> R(d->m), hM(d->r);
+    for (int n = 0; n < d->m; ++n) R[n] = host_mix64((u64)(n + 1) * 0x9E3779B97F4A7C15ULL);
+    std::vector<std::vector<int>> outs(d->m);
+    for (int e = 0; e < d->n_syn; ++e) outs[d->syn_src[e]].push_back(d->syn_dst[e]);
+    int max_rules = 0;
+    for (int n = 0; n < d->m; ++n) max_rules = std::max(max_rules, nrule_ptr[n + 1] - nrule_ptr[n]);
+    for (int k = 0; k < d->r; ++k) {
+        const int src = d->rule_neuron[k];
+        u64 h = (u64)(-(long long)d->rule_c[k]) * R[src];
+        for (int t : outs[src]) h += (u64)(long long)d->rule_p[k] * R[t];
+        hM[k] = h;
+    }
+    LOADCHK(dmalloc(&S->d_R, sizeof(u64) * d->m));
+    LOADCHK(dmalloc(&S->d_hM, sizeof(u64) * d->r));
+    LOADCHK(up(S->d_R, R.data(), sizeof(u64) * d->m));
+    LOADCHK(up(S->d_hM, hM.data(), sizeof(u64) * d->r));
+    // int8 copy of M_Pi for the matrix-core form (every |entry| <= 127, <= 16 rules per neuron)
+    S->int8_ready = int8_ok && max_rules <= 16 && opt.path != SNP_PATH_SPARSE &&
+                    snp::int8_lds(d->m, 64) <= 64 * 1024 && (size_t)d->r * d->m <= ((size_t)1 << 33);
+    if (S->int8_ready) {
+        std::vector<int8_t> M8((size_t)d->r * d->m, 0);
+        for (int k = 0; k < d->r; ++k) {
+            const int src = d->rule_neuron[k];
+            M8[(size_t)k * d->m + src] = (int8_t)(-d->rule_c[k]);
+            for (int t : outs[src]) M8[(size_t)k * d->m + t] = (int8_t)d->rule_p[k];
+        }
+        LOADCHK(dmalloc(&S->d_M8, M8.size()));
+        LOADCHK(up(S->d_M8, M8.data(), M8.size()));
+    }
+    // per-child work of the two forms: the pull visits every neuron and synapse;
+    // the matrix-core form writes the row and amortises one pull over a 64-child tile
+    S->sparse_work = (double)d->m + (double)d->n_syn;
+    S->int8_work = (double)d->m * 1.5 + ((double)d->m + (double)d->n_syn) / 64.0;
+    S->dsys = snp::DevSystem{d->m, d->r, S->d_nrule_ptr, S->d_rules, S->d_in_ptr, S->d_in_src, d->n_syn, S->d_M8,
+                             S->count_max, S->d_R, S->d_hM};
 
     S->slots = next_pow2((u64)std::max<long long>(1024, 2 * (S->max_rows + 2 * S->chunk_max)));
     LOADCHK(dmalloc(&S->d_table, sizeof(u64) * S->slots));

@@ -1,0 +1,149 @@
+// Device helpers shared by the kernels of libsnp (gfx950, wave64).
+#pragma once
+
+#include "snp_internal.hpp"
+
+namespace snp {
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ u64 sat_mul(u64 a, u64 b) {
+    if (a == 0 || b == 0) return 0;
+    if (a >= kPsiSat || b >= kPsiSat) return kPsiSat;
+    const u64 hi = __umul64hi(a, b);
+    const u64 lo = a * b;
+    return (hi != 0 || lo >= kPsiSat) ? kPsiSat : lo;
+}
+
+__device__ __forceinline__ u64 sat_add(u64 a, u64 b) {  // a, b <= 2^62: no wrap
+    const u64 s = a + b;
+    return s >= kPsiSat ? kPsiSat : s;
+}
+
+__device__ __forceinline__ u64 uni64(u64 x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((u64)hi << 32) | lo;
+}
+
+__device__ __forceinline__ long long uni_ll(long long x) { return (long long)uni64((u64)x); }
+
+// Orders this wave's LDS traffic: LDS operations of one wavefront complete in
+// issue order, so a compiler-level fence plus a wave barrier is enough for
+// lanes to see each other's writes.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Wave64 reductions on DPP: inclusive sums within rows of 16 lanes by row
+// shifts 1, 2, 4, 8 (lanes shifted in from outside the row read 0), then
+// row broadcasts of lanes 15 and 31 carry the row totals upward; lane 63 ends
+// with the total, which is returned to every lane.  All 64 lanes must be
+// active.
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, true);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, true);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, true);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, true);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Maximum of non-negative values (0 is the identity).
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, true));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, true));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, true));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, true));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// 64-bit wave sum (mod 2^64) on the same DPP pattern, carries included.
+#define SNP_DPP_ADD64(V, CTRL, RM, BC)                                                              \
+    do {                                                                                            \
+        const uint32_t lo_ = __builtin_amdgcn_update_dpp(0u, (uint32_t)(V), CTRL, RM, 0xf, BC);      \
+        const uint32_t hi_ = __builtin_amdgcn_update_dpp(0u, (uint32_t)((V) >> 32), CTRL, RM, 0xf, BC); \
+        (V) += ((u64)hi_ << 32) | lo_;                                                              \
+    } while (0)
+
+__device__ __forceinline__ u64 wave_sum_u64(u64 v) {
+    SNP_DPP_ADD64(v, 0x111, 0xf, true);
+    SNP_DPP_ADD64(v, 0x112, 0xf, true);
+    SNP_DPP_ADD64(v, 0x114, 0xf, true);
+    SNP_DPP_ADD64(v, 0x118, 0xf, true);
+    SNP_DPP_ADD64(v, 0x142, 0xa, false);
+    SNP_DPP_ADD64(v, 0x143, 0xc, false);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), 63);
+    return ((u64)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int wave_max_i32(int x) { return (int)wave_max_u32((uint32_t)(x + 1)) - 1; }
+
+// Rule applicability: a^n in L(a^i (a^j)*) and n >= c.
+__device__ __forceinline__ bool rule_applies(int n, const int4 R) {
+    if (n < R.x || n < R.z) return false;
+    if (R.y == 0) return n == R.x;
+    return ((n - R.x) % R.y) == 0;
+}
+
+// Index of the d-th set bit of mask (d < popcount(mask)).
+__device__ __forceinline__ int nth_bit(uint32_t mask, int d) {
+    for (int q = 0; q < d; ++q) mask &= mask - 1;
+    return __ffs(mask) - 1;
+}
+
+// Configuration hash.  H(C) = sum over neurons n of C[n] * R[n] (mod 2^64),
+// R[n] = mix64((n + 1) * gamma) (the SplitMix64 stream), which is linear in C:
+// H(C + M_k) = H(C) + H(M_k) for a row M_k of M_Pi.  The visited-set key is
+// fmix64(H) (MurmurHash3's 64-bit finaliser), masked by the hash_mask option.
+__device__ __forceinline__ u64 fmix64(u64 k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdULL;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ULL;
+    k ^= k >> 33;
+    return k;
+}
+
+__device__ __forceinline__ u64 hterm(uint32_t v, u64 R) { return (u64)v * R; }
+
+template <typename T>
+__device__ __forceinline__ u64 row_hash_wave(const T* row, const u64* R, int m, int lane) {
+    u64 h = 0;
+    for (int j = lane; j < m; j += 64) h += hterm((uint32_t)row[j], R[j]);
+    return wave_sum_u64(h);
+}
+
+// Mixed-radix decode of child index t (Algorithm 2 II-3 order: the last neuron
+// is the least significant digit; a neuron with omega <= 1 has one value).
+// Lane L owns the contiguous neurons [L*Q, L*Q + Q); the place value of its
+// block is a suffix product across lanes (saturated at 2^62, above any t).
+__device__ __forceinline__ void decode_digits(int m, int lane, u64 t, const uint8_t* om, uint8_t* dg) {
+    const int Q = (m + 63) >> 6;
+    const int j0 = lane * Q;
+    const int j1 = min(m, j0 + Q);
+    u64 bp = 1;
+    for (int j = j0; j < j1; ++j) bp = sat_mul(bp, (u64)max(1, (int)om[j]));
+    u64 incl = bp;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const u64 y = __shfl_down(incl, o);
+        if (lane + o < 64) incl = sat_mul(incl, y);
+    }
+    u64 after = __shfl_down(incl, 1);
+    if (lane == 63) after = 1;
+    u64 tl = (after > t) ? 0 : t / after;
+    for (int j = j1 - 1; j >= j0; --j) {
+        const uint32_t w = (uint32_t)max(1, (int)om[j]);
+        dg[j] = (uint8_t)(tl % w);
+        tl /= w;
+    }
+}
+
+}  // namespace snp

@@ -43,6 +43,8 @@ struct DevSystem {
     int nnz_in;            // number of synapses
     const int8_t* M8;      // [r*m] int8 copy of M_Pi (nullptr when some |entry| > 127)
     long long count_max;
+    const u64* R;          // [m] hash weights: R[n] = mix64((n + 1) * gamma)
+    const u64* hM;         // [r] H of every row of M_Pi (entries sign-extended, mod 2^64)
 };
 
 // One chunk of children [g0, g0 + B) of the frontier.
@@ -145,12 +147,14 @@ hipError_t launch_scan_u64(const u64* in, u64* out, long long n, u64* tile_sums,
 hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, long long n, uint32_t* tile_sums,
                            uint32_t* tile_pre, u64* total, hipStream_t st);
 long long scan_tiles(long long n);
+hipError_t launch_expand_int8(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st);
+size_t int8_lds(int m, int nt);
 hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st);
 hipError_t launch_insert(int elem_bytes, int m, const TableArgs& a, hipStream_t st);
 hipError_t launch_flags(const u64* table, const uint32_t* slot, long long B, uint32_t* flag, hipStream_t st);
 hipError_t launch_commit(int elem_bytes, int m, const CommitArgs& a, hipStream_t st);
 hipError_t launch_fill_u64(u64* p, long long n, u64 v, hipStream_t st);
-hipError_t launch_rows_insert(int elem_bytes, int m, u64* table, u64 slot_mask, const void* arena,
+hipError_t launch_rows_insert(int elem_bytes, int m, const u64* R, u64* table, u64 slot_mask, const void* arena,
                               long long first, long long count, u64 hash_mask, uint32_t* row_slot,
                               DevCounters* ctr, hipStream_t st);
 hipError_t launch_rollback(const uint32_t* row_slot, u64* table, long long first, long long count,

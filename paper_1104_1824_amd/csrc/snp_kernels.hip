@@ -7,121 +7,9 @@
 // Wave64 throughout: one wavefront per parent (Psi), per run of consecutive
 // children (expand), or per child (insert / commit), lanes striding over the
 // neurons of a row so that row loads and stores are contiguous.
-#include "snp_internal.hpp"
+#include "snp_device.hpp"
 
 namespace snp {
-
-// ---------------------------------------------------------------------------
-// small device helpers
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ u64 sat_mul(u64 a, u64 b) {
-    if (a == 0 || b == 0) return 0;
-    if (a >= kPsiSat || b >= kPsiSat) return kPsiSat;
-    const u64 hi = __umul64hi(a, b);
-    const u64 lo = a * b;
-    return (hi != 0 || lo >= kPsiSat) ? kPsiSat : lo;
-}
-
-__device__ __forceinline__ u64 sat_add(u64 a, u64 b) {  // a, b <= 2^62: no wrap
-    const u64 s = a + b;
-    return s >= kPsiSat ? kPsiSat : s;
-}
-
-__device__ __forceinline__ u64 uni64(u64 x) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
-    return ((u64)hi << 32) | lo;
-}
-
-__device__ __forceinline__ long long uni_ll(long long x) { return (long long)uni64((u64)x); }
-
-// Orders this wave's LDS traffic: LDS operations of one wavefront complete in
-// issue order, so a compiler-level fence plus a wave barrier is enough for
-// lanes to see each other's writes.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-// Wave64 reductions on DPP: inclusive sums within rows of 16 lanes by row
-// shifts 1, 2, 4, 8 (lanes shifted in from outside the row read 0), then
-// row broadcasts of lanes 15 and 31 carry the row totals upward; lane 63 ends
-// with the total, which is returned to every lane.  All 64 lanes must be
-// active.
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-    v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, true);   // row_shr:1
-    v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, true);   // row_shr:2
-    v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, true);   // row_shr:4
-    v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, true);   // row_shr:8
-    v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
-    v += __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
-    return __builtin_amdgcn_readlane(v, 63);
-}
-
-// Maximum of non-negative values (0 is the identity).
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, true));
-    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, true));
-    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, true));
-    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, true));
-    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false));
-    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false));
-    return __builtin_amdgcn_readlane(v, 63);
-}
-
-// 64-bit configuration hash of a row from per-lane partial sums: the low and
-// high halves of the per-element hashes are summed separately (mod 2^32).
-__device__ __forceinline__ u64 wave_hash_total(u64 partial) {
-    const uint32_t lo = wave_sum_u32((uint32_t)partial);
-    const uint32_t hi = wave_sum_u32((uint32_t)(partial >> 32));
-    return ((u64)hi << 32) | lo;
-}
-
-__device__ __forceinline__ int wave_max_i32(int x) { return (int)wave_max_u32((uint32_t)(x + 1)) - 1; }
-
-// Rule applicability: a^n in L(a^i (a^j)*) and n >= c.
-__device__ __forceinline__ bool rule_applies(int n, const int4 R) {
-    if (n < R.x || n < R.z) return false;
-    if (R.y == 0) return n == R.x;
-    return ((n - R.x) % R.y) == 0;
-}
-
-// Index of the d-th set bit of mask (d < popcount(mask)).
-__device__ __forceinline__ int nth_bit(uint32_t mask, int d) {
-    for (int q = 0; q < d; ++q) mask &= mask - 1;
-    return __ffs(mask) - 1;
-}
-
-// Configuration hash: sum over neurons of a 64-bit finaliser (MurmurHash3
-// fmix64) of (neuron, count).  Order independent across lanes, position
-// dependent through the neuron index.
-__device__ __forceinline__ u64 fmix64(u64 k) {
-    k ^= k >> 33;
-    k *= 0xff51afd7ed558ccdULL;
-    k ^= k >> 33;
-    k *= 0xc4ceb9fe1a85ec53ULL;
-    k ^= k >> 33;
-    return k;
-}
-
-__device__ __forceinline__ u64 elem_hash(int j, uint32_t v) {
-    return fmix64((((u64)(uint32_t)j << 32) | v) ^ 0x9E3779B97F4A7C15ULL);
-}
-
-// Per-lane partial: sums of the low and high halves of the element hashes,
-// each mod 2^32, kept in one 64-bit word (no carry between the halves).
-__device__ __forceinline__ u64 hash_acc(u64 acc, u64 e) {
-    const uint32_t lo = (uint32_t)acc + (uint32_t)e;
-    const uint32_t hi = (uint32_t)(acc >> 32) + (uint32_t)(e >> 32);
-    return ((u64)hi << 32) | lo;
-}
-
-template <typename T>
-__device__ __forceinline__ u64 row_hash_wave(const T* row, int m, int lane) {
-    u64 h = 0;
-    for (int j = lane; j < m; j += 64) h = hash_acc(h, elem_hash(j, (uint32_t)row[j]));
-    return wave_hash_total(h);
-}
 
 // ---------------------------------------------------------------------------
 // Psi: per parent, number of valid spiking vectors (Algorithm 2 II-1/II-2):
@@ -351,6 +239,7 @@ struct Tables {
     const int4* rules; // [r]
     const int* inp;    // [m+1]
     const int* ins;    // [nnz]
+    const u64* R;      // [m] hash weights
 };
 
 // Fired rule of neuron j packed as (c << 16) | p (both <= 65535, checked at load); 0 when none.
@@ -383,26 +272,9 @@ __device__ __forceinline__ void load_parent(const Tables& tb, int m, const T* ro
     }
 }
 
-__device__ __forceinline__ void decode_digits(int m, int lane, u64 t, const uint8_t* om, uint8_t* dg) {
-    const int Q = (m + 63) >> 6;
-    const int j0 = lane * Q;
-    const int j1 = min(m, j0 + Q);
-    u64 bp = 1;
-    for (int j = j0; j < j1; ++j) bp = sat_mul(bp, (u64)max(1, (int)om[j]));
-    u64 incl = bp;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const u64 y = __shfl_down(incl, o);
-        if (lane + o < 64) incl = sat_mul(incl, y);
-    }
-    u64 after = __shfl_down(incl, 1);
-    if (lane == 63) after = 1;
-    u64 tl = (after > t) ? 0 : t / after;
-    for (int j = j1 - 1; j >= j0; --j) {
-        const uint32_t w = (uint32_t)max(1, (int)om[j]);
-        dg[j] = (uint8_t)(tl % w);
-        tl /= w;
-    }
+__host__ __device__ __forceinline__ size_t table_lds_bytes(const DevSystem& s, int nnz) {
+    return ((size_t)((s.m + 1) & ~1) * 8 + (size_t)s.r * 16 + (size_t)(s.m + 1) * 8 + (size_t)nnz * 4 + 15) &
+           ~(size_t)15;
 }
 
 template <typename T, bool TBL_LDS>
@@ -411,15 +283,17 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
     const int m = s.m;
-    Tables tb{s.nrule_ptr, s.rules, s.in_ptr, s.in_src};
+    Tables tb{s.nrule_ptr, s.rules, s.in_ptr, s.in_src, s.R};
     unsigned char* wave_base = smem;
     if constexpr (TBL_LDS) {
-        // rule table and in-synapse lists, shared by the block's waves
-        int4* l_rules = (int4*)smem;
+        // hash weights, rule table and in-synapse lists, shared by the block's waves
+        u64* l_R = (u64*)smem;
+        int4* l_rules = (int4*)(l_R + ((m + 1) & ~1));
         int* l_nrp = (int*)(l_rules + s.r);
         int* l_inp = l_nrp + (m + 1);
         int* l_ins = l_inp + (m + 1);
         const int nnz = s.in_ptr[m];
+        for (int q = threadIdx.x; q < m; q += blockDim.x) l_R[q] = s.R[q];
         for (int q = threadIdx.x; q < s.r; q += blockDim.x) l_rules[q] = s.rules[q];
         for (int q = threadIdx.x; q <= m; q += blockDim.x) {
             l_nrp[q] = s.nrule_ptr[q];
@@ -427,9 +301,8 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
         }
         for (int q = threadIdx.x; q < nnz; q += blockDim.x) l_ins[q] = s.in_src[q];
         __syncthreads();
-        tb = Tables{l_nrp, l_rules, l_inp, l_ins};
-        const size_t tbytes = (size_t)s.r * 16 + (size_t)(m + 1) * 8 + (size_t)nnz * 4;
-        wave_base = smem + ((tbytes + 15) & ~(size_t)15);
+        tb = Tables{l_nrp, l_rules, l_inp, l_ins, l_R};
+        wave_base = smem + table_lds_bytes(s, nnz);
     }
     const long long wave = (long long)blockIdx.x * (blockDim.x >> 6) + wid;
     const long long b0 = wave * run;
@@ -478,11 +351,11 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
             for (int e = tb.inp[j]; e < e1; ++e) v += cp[tb.ins[e]] & 0xFFFFu;
             ovf |= (v < 0) | (v > s.count_max);
             out[j] = (T)v;
-            h = hash_acc(h, elem_hash(j, (uint32_t)v));
+            h += hterm((uint32_t)v, tb.R[j]);
         }
-        h = wave_hash_total(h);
+        h = wave_sum_u64(h);
         if (lane == 0) {
-            a.hash[b] = h & a.hash_mask;
+            a.hash[b] = fmix64(h) & a.hash_mask;
             a.cpar[b] = (int)p;
             a.ct[b] = t;
         }
@@ -522,10 +395,6 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
         }
     }
     if (__any(ovf) && lane == 0) atomicOr((unsigned long long*)&a.ctr->overflow, 1ULL);
-}
-
-static size_t table_lds_bytes(const DevSystem& s, int nnz) {
-    return (((size_t)s.r * 16 + (size_t)(s.m + 1) * 8 + (size_t)nnz * 4) + 15) & ~(size_t)15;
 }
 
 hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st) {
@@ -728,14 +597,14 @@ hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_rows_insert(int m, u64* table, u64 slot_mask, const T* arena,
+__global__ __launch_bounds__(256) void k_rows_insert(int m, const u64* R, u64* table, u64 slot_mask, const T* arena,
                                                      long long first, long long count, u64 hash_mask,
                                                      uint32_t* row_slot, DevCounters* ctr) {
     const int lane = threadIdx.x & 63;
     const long long q = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (q >= count) return;
     const long long A = first + q;
-    const u64 h = row_hash_wave<T>(arena + A * (long long)m, m, lane) & hash_mask;
+    const u64 h = fmix64(row_hash_wave<T>(arena + A * (long long)m, R, m, lane)) & hash_mask;
     const u64 mine = ((h >> 32) << 32) | (uint32_t)A;
     u64 sl = h & slot_mask;
     for (u64 it = 0; it <= slot_mask; ++it) {
@@ -751,16 +620,16 @@ __global__ __launch_bounds__(256) void k_rows_insert(int m, u64* table, u64 slot
     if (lane == 0) atomicOr((unsigned long long*)&ctr->probe_fail, 1ULL);
 }
 
-hipError_t launch_rows_insert(int elem_bytes, int m, u64* table, u64 slot_mask, const void* arena,
+hipError_t launch_rows_insert(int elem_bytes, int m, const u64* R, u64* table, u64 slot_mask, const void* arena,
                               long long first, long long count, u64 hash_mask, uint32_t* row_slot,
                               DevCounters* ctr, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)((count + 3) / 4);
     if (elem_bytes == 4)
-        hipLaunchKernelGGL(k_rows_insert<int32_t>, dim3(blocks), dim3(256), 0, st, m, table, slot_mask,
+        hipLaunchKernelGGL(k_rows_insert<int32_t>, dim3(blocks), dim3(256), 0, st, m, R, table, slot_mask,
                            (const int32_t*)arena, first, count, hash_mask, row_slot, ctr);
     else
-        hipLaunchKernelGGL(k_rows_insert<uint16_t>, dim3(blocks), dim3(256), 0, st, m, table, slot_mask,
+        hipLaunchKernelGGL(k_rows_insert<uint16_t>, dim3(blocks), dim3(256), 0, st, m, R, table, slot_mask,
                            (const uint16_t*)arena, first, count, hash_mask, row_slot, ctr);
     return hipGetLastError();
 }
