@@ -92,6 +92,7 @@ struct snp_system {
     int* d_cpar = nullptr;
     u64* d_ct = nullptr;
     uint32_t *d_slot = nullptr, *d_flag = nullptr, *d_pos = nullptr, *d_fsums = nullptr, *d_fpre = nullptr;
+    uint32_t* d_cand = nullptr;
     snp::DevCounters* d_ctr = nullptr;
     snp::DevCounters* h_ctr = nullptr;
 
@@ -109,7 +110,7 @@ struct snp_system {
     ~snp_system() {
         void* ptrs[] = {d_nrule_ptr, d_rules, d_in_ptr, d_in_src, d_M8, d_R, d_hM, d_table, d_row_slot, d_psi, d_off,
                         d_sc_sums, d_sc_pre, d_stage, d_hash, d_cpar, d_ct, d_slot, d_flag, d_pos,
-                        d_fsums, d_fpre, d_ctr, d_store};
+                        d_fsums, d_fpre, d_ctr, d_store, d_cand};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         if (h_ctr) (void)hipHostFree(h_ctr);
@@ -340,7 +341,8 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         if (use_int8) HIPCHK(snp::launch_expand_int8(S->elem_bytes, S->dsys, ca, S->stream));
         else HIPCHK(snp::launch_expand_sparse(S->elem_bytes, S->dsys, ca, S->stream));
         if ((st = mark(S, 1))) return st;
-        snp::TableArgs ta{S->d_table, S->slots - 1, io.arena, S->d_stage, S->d_hash, S->d_slot, B, S->d_ctr};
+        snp::TableArgs ta{S->d_table, S->slots - 1, io.arena, S->d_stage, S->d_hash, S->d_slot, B, S->d_ctr,
+                          S->d_cand};
         HIPCHK(snp::launch_insert(S->elem_bytes, S->m, ta, S->stream));
         if ((st = mark(S, 2))) return st;
         HIPCHK(snp::launch_flags(S->d_table, S->d_slot, B, S->d_flag, S->stream));
@@ -533,6 +535,7 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     LOADCHK(dmalloc(&S->d_cpar, sizeof(int) * C));
     LOADCHK(dmalloc(&S->d_ct, sizeof(u64) * C));
     LOADCHK(dmalloc(&S->d_slot, sizeof(uint32_t) * C));
+    LOADCHK(dmalloc(&S->d_cand, sizeof(uint32_t) * C));
     LOADCHK(dmalloc(&S->d_flag, sizeof(uint32_t) * C));
     LOADCHK(dmalloc(&S->d_pos, sizeof(uint32_t) * C));
     LOADCHK(dmalloc(&S->d_fsums, sizeof(uint32_t) * ft));

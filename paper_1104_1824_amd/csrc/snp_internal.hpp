@@ -30,7 +30,8 @@ struct DevCounters {
     u64 cap_g;         // chunk-relative index + 1 of the child that filled the cap (0: none)
     u64 tombs;         // entries turned into tombstones by this pass
     u64 total;         // scan total (children of the frontier / new children of a chunk)
-    u64 pad[2];
+    u64 ncand;         // children whose probe met an entry with their tag (row compare pending)
+    u64 pad;
 };
 
 // Device-side description of a loaded system.
@@ -73,6 +74,7 @@ struct TableArgs {
     uint32_t* slot;        // [B] slot each child resolved to
     long long B;
     DevCounters* ctr;
+    uint32_t* cand;        // [B] children waiting for a row compare
 };
 
 struct CommitArgs {

@@ -9,6 +9,8 @@
 // neurons of a row so that row loads and stores are contiguous.
 #include "snp_device.hpp"
 
+#include <algorithm>
+
 namespace snp {
 
 // ---------------------------------------------------------------------------
@@ -428,71 +430,121 @@ hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkA
 
 // ---------------------------------------------------------------------------
 // Visited set.  Open addressing with linear probing over 64-bit entries
-// (tag:32 | ref:32).  One thread per child: it claims an empty slot with a
-// CAS; on an entry with its tag it compares the whole rows; an equal row of
-// the current chunk with a larger index is replaced by atomicMin on the entry,
-// so the entry ends at the first occurrence in canonical order.
+// (tag:32 | ref:32), in two passes:
+//   A (a thread per child): probe from the hash slot; claim the first empty
+//     slot with a CAS, or stop at the first entry with the child's tag and
+//     queue the child for a row compare.
+//   B (a wave per queued child): compare the two rows with all 64 lanes; if
+//     equal and the entry names a later child of the current chunk, lower it
+//     with atomicMin (the entry ends at the first occurrence in canonical
+//     order); if different, keep probing (lane 0 drives, compares stay
+//     cooperative) until an empty slot or an equal row.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ bool rows_equal(const T* x, const T* y, int m, bool vec16) {
-    if (vec16) {
-        const uint4* a = (const uint4*)x;
-        const uint4* b = (const uint4*)y;
-        const int n = (int)((size_t)m * sizeof(T) / 16);
-        for (int q = 0; q < n; ++q) {
-            const uint4 u = a[q], v = b[q];
-            if (u.x != v.x || u.y != v.y || u.z != v.z || u.w != v.w) return false;
-        }
-        return true;
-    }
-    for (int j = 0; j < m; ++j)
-        if (x[j] != y[j]) return false;
-    return true;
+__device__ __forceinline__ const T* entry_row(const TableArgs& a, uint32_t ref, int m) {
+    return ref < kStageBase ? (const T*)a.arena + (u64)ref * (u64)m
+                            : (const T*)a.stage + (u64)(ref - kStageBase) * (u64)m;
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_insert(int m, TableArgs a, int vec16) {
+__global__ __launch_bounds__(256) void k_insert_probe(int m, TableArgs a) {
     const long long b = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (b >= a.B) return;
-    const u64 h = a.hash[b];
-    const uint32_t tag = (uint32_t)(h >> 32);
-    const uint32_t myref = kStageBase + (uint32_t)b;
-    const u64 mine = ((u64)tag << 32) | myref;
-    const T* row = (const T*)a.stage + b * (long long)m;
-    u64 sl = h & a.slot_mask;
-    for (u64 it = 0; it <= a.slot_mask; ++it) {
-        u64 e = __hip_atomic_load(&a.table[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (e == kEmpty) {
-            const u64 old = atomicCAS(&a.table[sl], kEmpty, mine);
-            if (old == kEmpty) {
-                a.slot[b] = (uint32_t)sl;
-                return;
+    bool queue = false;
+    if (b < a.B) {
+        const u64 h = a.hash[b];
+        const uint32_t tag = (uint32_t)(h >> 32);
+        const u64 mine = ((u64)tag << 32) | (kStageBase + (uint32_t)b);
+        u64 sl = h & a.slot_mask;
+        bool placed = false;
+        for (u64 it = 0; it <= a.slot_mask; ++it) {
+            u64 e = __hip_atomic_load(&a.table[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (e == kEmpty) {
+                const u64 old = atomicCAS(&a.table[sl], kEmpty, mine);
+                if (old == kEmpty) {
+                    placed = true;
+                    break;
+                }
+                e = old;
             }
-            e = old;
-        }
-        if (e != kTomb && (uint32_t)(e >> 32) == tag) {
-            const uint32_t ref = (uint32_t)e;
-            const T* other = ref < kStageBase ? (const T*)a.arena + (u64)ref * (u64)m
-                                              : (const T*)a.stage + (u64)(ref - kStageBase) * (u64)m;
-            if (rows_equal<T>(row, other, m, vec16 != 0)) {
-                if (ref >= kStageBase && myref < ref) atomicMin(&a.table[sl], mine);
-                a.slot[b] = (uint32_t)sl;
-                return;
+            if (e != kTomb && (uint32_t)(e >> 32) == tag) {
+                queue = true;
+                placed = true;
+                break;
             }
+            sl = (sl + 1) & a.slot_mask;
         }
-        sl = (sl + 1) & a.slot_mask;
+        a.slot[b] = placed ? (uint32_t)sl : 0u;
+        if (!placed) atomicOr((unsigned long long*)&a.ctr->probe_fail, 1ULL);
     }
-    a.slot[b] = 0;  // keep later kernels in bounds; the host reports the failure
-    atomicOr((unsigned long long*)&a.ctr->probe_fail, 1ULL);
+    // append the queued children, one atomic per wave
+    const u64 qm = __ballot(queue);
+    if (qm) {
+        const int lane = threadIdx.x & 63;
+        u64 base = 0;
+        if (lane == 0) base = atomicAdd(&a.ctr->ncand, (u64)__popcll(qm));
+        base = __shfl(base, 0);
+        if (queue) a.cand[base + __popcll(qm & ((1ULL << lane) - 1))] = (uint32_t)b;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_insert_compare(int m, TableArgs a) {
+    const int lane = threadIdx.x & 63;
+    const long long waves = (long long)gridDim.x * (blockDim.x >> 6);
+    const long long ncand = (long long)a.ctr->ncand;
+    for (long long q = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < ncand; q += waves) {
+        const long long b = a.cand[q];
+        const T* row = (const T*)a.stage + b * (long long)m;
+        const u64 h = a.hash[b];
+        const uint32_t tag = (uint32_t)(h >> 32);
+        const uint32_t myref = kStageBase + (uint32_t)b;
+        const u64 mine = ((u64)tag << 32) | myref;
+        u64 sl = a.slot[b];
+        bool done = false;
+        for (u64 it = 0; it <= a.slot_mask && !done; ++it) {
+            u64 e = uni64(__hip_atomic_load(&a.table[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            if (e == kEmpty) {
+                u64 old = 0;
+                if (lane == 0) old = atomicCAS(&a.table[sl], kEmpty, mine);
+                old = uni64(__shfl(old, 0));
+                if (old == kEmpty) {
+                    done = true;
+                    break;
+                }
+                e = old;
+            }
+            if (e != kTomb && (uint32_t)(e >> 32) == tag) {
+                const uint32_t ref = (uint32_t)e;
+                const T* other = entry_row<T>(a, ref, m);
+                bool diff = false;
+                for (int j = lane; j < m; j += 64) diff |= (row[j] != other[j]);
+                if (!__any(diff)) {
+                    if (lane == 0 && ref >= kStageBase && myref < ref) atomicMin(&a.table[sl], mine);
+                    done = true;
+                    break;
+                }
+            }
+            sl = (sl + 1) & a.slot_mask;
+        }
+        if (lane == 0) {
+            a.slot[b] = done ? (uint32_t)sl : 0u;
+            if (!done) atomicOr((unsigned long long*)&a.ctr->probe_fail, 1ULL);
+        }
+    }
 }
 
 hipError_t launch_insert(int elem_bytes, int m, const TableArgs& a, hipStream_t st) {
     if (a.B <= 0) return hipSuccess;
-    const size_t rb = (size_t)m * elem_bytes;
-    const int vec16 = (rb % 16 == 0 && ((uintptr_t)a.arena % 16) == 0 && ((uintptr_t)a.stage % 16) == 0) ? 1 : 0;
     const unsigned blocks = (unsigned)((a.B + 255) / 256);
-    if (elem_bytes == 4) hipLaunchKernelGGL(k_insert<int32_t>, dim3(blocks), dim3(256), 0, st, m, a, vec16);
-    else hipLaunchKernelGGL(k_insert<uint16_t>, dim3(blocks), dim3(256), 0, st, m, a, vec16);
+    // compare pass: enough waves to cover the device, each looping over the queue
+    const unsigned cblocks = (unsigned)std::min<long long>((a.B + 3) / 4, 4096);
+    if (elem_bytes == 4) {
+        hipLaunchKernelGGL(k_insert_probe<int32_t>, dim3(blocks), dim3(256), 0, st, m, a);
+        hipLaunchKernelGGL(k_insert_compare<int32_t>, dim3(cblocks), dim3(256), 0, st, m, a);
+    } else {
+        hipLaunchKernelGGL(k_insert_probe<uint16_t>, dim3(blocks), dim3(256), 0, st, m, a);
+        hipLaunchKernelGGL(k_insert_compare<uint16_t>, dim3(cblocks), dim3(256), 0, st, m, a);
+    }
     return hipGetLastError();
 }
 
