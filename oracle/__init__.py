@@ -185,7 +185,8 @@ class BfsResult:
     parent: np.ndarray        # [n_configs] global index of the parent, -1 for C0
     tindex: np.ndarray        # [n_configs] index of the spiking vector among the parent's
     enumerated: np.ndarray    # [n_levels] children considered when expanding level k (0: not expanded)
-    halting: np.ndarray       # [n_levels] parents of level k with no applicable rule (0: not expanded)
+    halting: np.ndarray       # [n_levels] parents of level k with no applicable rule, counted up to the
+                              # parent of the last child enumerated (all of them unless cut by cap/budget)
     stop_reason: int
 
     @property

@@ -400,13 +400,13 @@ int or_bfs(const or_system *sys, const int64_t *c0, const or_bfs_opts *opt, or_b
         int32_t depth = levels - 1;
         if (opt->max_depth >= 0 && depth >= opt->max_depth) { stop = OR_STOP_DEPTH; break; }
         if (levels >= res->max_levels) { st = OR_ERR_CAPACITY; break; }
-        int64_t enumerated = 0, halting = 0, added = 0;
+        int64_t enumerated = 0, halting = 0, added = 0, last_par = -1;
         int all_halting = 1, budget_hit = 0, cap_hit = 0;
         for (int64_t par = lvl_begin; par < lvl_end && !cap_hit && !budget_hit && st == OR_OK; ++par) {
             const int64_t *C = res->rows + par * m;
             or_enum E;
             if (enum_open(&E, sys, &R, C)) { enum_close(&E); st = OR_ERR_NOMEM; break; }
-            if (!E.any) { halting++; enum_close(&E); continue; }
+            if (!E.any) { enum_close(&E); continue; }
             all_halting = 0;
             int expand = 1;
             if (opt->expand_max_count >= 0)
@@ -418,6 +418,7 @@ int or_bfs(const or_system *sys, const int64_t *c0, const or_bfs_opts *opt, or_b
                 enum_spiking_vector(&E, S);
                 if ((st = next_config(sys, &R, C, S, child))) break;
                 ++enumerated;
+                last_par = par;
                 if (set_find(&H, child) < 0) {
                     if (total >= res->rows_cap) { st = OR_ERR_CAPACITY; break; }
                     memcpy(res->rows + total * m, child, sizeof(int64_t) * (size_t)m);
@@ -433,6 +434,16 @@ int or_bfs(const or_system *sys, const int64_t *c0, const or_bfs_opts *opt, or_b
             /* A budget that runs out exactly at the end of a parent is only "hit" when a
              * later parent of the level still has a child: the check above, made before
              * each child, sees that on the later parent's first child. */
+            enum_close(&E);
+        }
+        if (st) break;
+        /* halting parents are counted up to the parent of the last child the
+         * level enumerated (all parents when the level was not cut short) */
+        const int64_t p_end = (cap_hit || budget_hit) ? last_par + 1 : lvl_end;
+        for (int64_t par = lvl_begin; par < p_end; ++par) {
+            or_enum E;
+            if (enum_open(&E, sys, &R, res->rows + par * m)) { enum_close(&E); st = OR_ERR_NOMEM; break; }
+            if (!E.any) halting++;
             enum_close(&E);
         }
         if (st) break;
