@@ -60,6 +60,81 @@ def run_gpu(system, run_opts, steps, warmup):
     return results, t1 - t0, res
 
 
+def walk_timing(system, path, cap, depth, stop, chunk, out_cap, reps):
+    """Median-free simple timing of `reps` complete walks on one path."""
+    import numpy as np
+    import torch
+
+    from paper_1104_1824_amd import snp
+
+    h = snp.snp_load(system, path=path, frontier_cap=cap, stop_at_cap=stop, max_rows=out_cap, chunk=chunk,
+                     profile=True)
+    c0 = torch.tensor(np.asarray(system.c0, dtype=np.int32), device="cuda")
+    out = torch.empty((out_cap, system.m), dtype=torch.int32, device="cuda")
+    snp.snp_run(h, c0, depth, out, out_cap)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = snp.snp_run(h, c0, depth, out, out_cap)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    h.close()
+    st = r["level_stats"]
+    ns = sum(s_["ns_expand"] for s_ in st)
+    expanded = sum(s_["expanded"] for s_ in st)
+    rb = system.m * 4
+    return dict(ms_per_walk=round(dt * 1e3, 3), new_configs=int(r["n_configs"] - 1),
+                configs_per_s=round((r["n_configs"] - 1) / dt, 1), levels=r["level_sizes"].tolist(),
+                expand_us=round(ns / 1e3, 1), expand_gbs=round(expanded * (rb + 20) / max(ns, 1), 1),
+                stage_us={k: round(sum(s_["ns_" + k] for s_ in st) / 1e3, 1)
+                          for k in ("psi", "expand", "insert", "flags", "commit")})
+
+
+def extras_int8_and_batched():
+    """Secondary measurements: the int8 matrix-core form next to the sparse form
+    (plain-sparse workload and the dense m=512 workload), and the batched
+    deterministic launch (256 systems x 10k steps)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1104_1824_amd import snp
+
+    out = {}
+    s2 = synth.config_system(2, 0)
+    out["plain_sparse_int8_path"] = walk_timing(s2, snp.SNP_PATH_INT8, 100000, 1000, True, 1 << 17, 200000, 10)
+    s3 = synth.config_system(3, 0)
+    dense = {}
+    for name, path, reps in (("int8", snp.SNP_PATH_INT8, 3), ("sparse", snp.SNP_PATH_SPARSE, 1)):
+        log(f"dense m=512 workload, {name} path")
+        dense[name] = walk_timing(s3, path, 1000000, 3, False, 1 << 20, 3100000, reps)
+    dense["speedup_int8_over_sparse"] = round(dense["sparse"]["ms_per_walk"] / dense["int8"]["ms_per_walk"], 2)
+    dense["workload"] = ("dense_int8: m=512, 3 rules/neuron (r=1536), p in [0,4] (M entries in [-4,4]), "
+                         "out-degree 64, C0 in [0,4], int32; BFS depth 3, frontier_cap 1e6 per level (seed 0)")
+    out["dense_int8"] = dense
+    log("batched deterministic launch, 256 systems x 10k steps")
+    systems = synth.batched_systems(0, 256)
+    b = snp.snp_batch_load(systems)
+    off = snp.snp_batch_offsets(b)
+    c0 = torch.from_numpy(np.concatenate([x.c0 for x in systems]).astype(np.int32)).cuda()
+    fin = torch.empty(int(off[-1]), dtype=torch.int32, device="cuda")
+    snp.snp_batch_run(b, c0, 10000, fin)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        snp.snp_batch_run(b, c0, 10000, fin)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    b.close()
+    out["batched"] = dict(
+        workload="batched_uneven: 256 systems, m in [16,1024], 1-3 rules and out-degree 2-32 per neuron, "
+                 "10k deterministic steps each, one launch (seeds 0-255)",
+        ms_per_launch=round(dt * 1e3, 3), system_steps=256 * 10000,
+        configs_per_s=round(256 * 10000 / dt, 1))
+    return out
+
+
 def roofline(system, results):
     """Roofline of the expansion kernel: its algorithmic bytes over its device
     time.  Algorithmic bytes per launch = children computed x (row bytes written
@@ -120,6 +195,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the int8 / dense / batched side measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X; --gpus must be 1", file=sys.stderr)
@@ -139,6 +215,9 @@ def main():
     log(f"levels {sizes}, {new_per_step} new configurations per step, {dt / args.steps * 1e3:.3f} ms/step")
     rl = roofline(system, results)
     log(f"stage us/step {rl['stage_us_per_step']}")
+    extras = None
+    if not args.no_extras:
+        extras = extras_int8_and_batched()
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on the same workload")
@@ -169,6 +248,7 @@ def main():
         "dominant_kernel": {k: rl[k] for k in ("kernel", "dominant_stage", "bytes_per_launch", "avg_launch_us",
                                                 "launches_per_step", "stage_us_per_step")},
         "cpu_baseline": cpu,
+        "extras": extras,
     }
     print(json.dumps(line), flush=True)
 

@@ -91,7 +91,7 @@ typedef enum {
 typedef struct {
     int32_t m;                  /* neurons, 1 <= m <= 4608 */
     int32_t r;                  /* rules, >= 0 */
-    const int32_t *rule_neuron; /* [r] owner neuron (0-based), non-decreasing; <= 32 rules per neuron */
+    const int32_t *rule_neuron; /* [r] owner neuron (0-based), non-decreasing; <= 16 rules per neuron */
     const int32_t *rule_i;      /* [r] E = a^i (a^j)*: i >= 1 */
     const int32_t *rule_j;      /* [r] j >= 0 (0: E = a^i exactly) */
     const int32_t *rule_c;      /* [r] spikes consumed, 1 <= c <= 65535 */
@@ -130,8 +130,11 @@ typedef struct {
 /* Per-level counters of one expansion. */
 typedef struct {
     int64_t parents;         /* frontier configurations */
-    int64_t halting_parents; /* parents where no rule applies */
-    int64_t children_total;  /* sum of Psi over the parents, saturated at 2^62 */
+    int64_t halting_parents; /* parents where no rule applies, counted up to the parent of the last
+                                child the level enumerated (all parents when the level was not cut
+                                short by frontier_cap or child_budget) */
+    int64_t children_total;  /* sum of Psi over the parents examined (a prefix of the frontier
+                                large enough for the children enumerated), saturated at 2^62 */
     int64_t enumerated;      /* children in canonical order up to where the level stopped:
                                 the cap-filling child, the budget, or all of them */
     int64_t new_configs;     /* configurations recorded for the level */

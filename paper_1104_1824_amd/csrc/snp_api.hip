@@ -35,7 +35,7 @@ snp_status fail(snp_status st, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail(SNP_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-constexpr int kMaxRulesPerNeuron = 32;  // applicable-rule masks are 32-bit
+constexpr int kMaxRulesPerNeuron = 16;  // applicable-rule masks are 16-bit (plus 16 bits of twin marks)
 constexpr int kMaxNeurons = 4608;       // per-wave LDS state of the expansion kernel (14 B per neuron) <= 64 KiB
 constexpr long long kInf = LLONG_MAX / 4;
 
@@ -87,13 +87,19 @@ struct snp_system {
 
     // per-frontier and per-chunk buffers
     u64 *d_psi = nullptr, *d_off = nullptr, *d_sc_sums = nullptr, *d_sc_pre = nullptr;
+    uint8_t* d_hflag = nullptr;  // per parent: 1 when no rule applies
     void* d_stage = nullptr;
     u64* d_hash = nullptr;
     int* d_cpar = nullptr;
     u64* d_ct = nullptr;
     uint32_t *d_slot = nullptr, *d_flag = nullptr, *d_pos = nullptr, *d_fsums = nullptr, *d_fpre = nullptr;
     uint32_t* d_cand = nullptr;
-    snp::DevCounters* d_ctr = nullptr;
+    // counters: a ring of slots, one per device pass, zeroed once per kRing passes
+    static constexpr int kRing = 64;
+    snp::DevCounters* d_ring = nullptr;
+    snp::DevCounters* d_ctr = nullptr;  // slot of the current pass
+    long long pass = 0;
+    u64* d_T = nullptr;                 // children of the examined frontier prefix (device)
     snp::DevCounters* h_ctr = nullptr;
 
     // caller-driven walk (snp_reset / snp_expand): the handle's own row store
@@ -110,7 +116,7 @@ struct snp_system {
     ~snp_system() {
         void* ptrs[] = {d_nrule_ptr, d_rules, d_in_ptr, d_in_src, d_M8, d_R, d_hM, d_table, d_row_slot, d_psi, d_off,
                         d_sc_sums, d_sc_pre, d_stage, d_hash, d_cpar, d_ct, d_slot, d_flag, d_pos,
-                        d_fsums, d_fpre, d_ctr, d_store, d_cand};
+                        d_fsums, d_fpre, d_ring, d_store, d_cand, d_hflag, d_T};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         if (h_ctr) (void)hipHostFree(h_ctr);
@@ -228,18 +234,35 @@ snp_status read_counters(snp_system* S) {
     return SNP_OK;
 }
 
+// Start a device pass: move to the next counter slot (zeroing the ring when it
+// wraps, i.e. one fill per kRing passes instead of one per pass).
 snp_status clear_counters(snp_system* S) {
-    HIPCHK(hipMemsetAsync(S->d_ctr, 0, sizeof(snp::DevCounters), S->stream));
+    const int slot = (int)(S->pass % snp_system::kRing);
+    if (slot == 0)
+        HIPCHK(hipMemsetAsync(S->d_ring, 0, sizeof(snp::DevCounters) * snp_system::kRing, S->stream));
+    S->d_ctr = S->d_ring + slot;
+    ++S->pass;
     return SNP_OK;
 }
 
-// Empty the visited set and insert rows [0, rows) of the row store.
-snp_status rebuild_table(snp_system* S, const void* arena, long long rows) {
+// Empty the visited set and insert rows [0, rows) of the row store, in the
+// current counter slot.
+snp_status fill_table(snp_system* S, const void* arena, long long rows) {
     HIPCHK(snp::launch_fill_u64(S->d_table, (long long)S->slots, snp::kEmpty, S->stream));
     HIPCHK(snp::launch_rows_insert(S->elem_bytes, S->m, S->d_R, S->d_table, S->slots - 1, arena, 0, rows,
                                    S->opt.hash_mask ? S->opt.hash_mask : ~0ULL, S->d_row_slot, S->d_ctr,
                                    S->stream));
     S->tombs = 0;
+    return SNP_OK;
+}
+
+// The same as a device pass of its own (drops the tombstones of a long walk).
+snp_status rebuild_table(snp_system* S, const void* arena, long long rows) {
+    snp_status st;
+    if ((st = clear_counters(S))) return st;
+    if ((st = fill_table(S, arena, rows))) return st;
+    if ((st = read_counters(S))) return st;
+    if (S->h_ctr->probe_fail) return fail(SNP_ERR_DEVICE, "visited set: no free slot");
     return SNP_OK;
 }
 
@@ -250,7 +273,7 @@ snp_status start_walk(snp_system* S, const void* c0_dev, void* arena) {
     if ((st = clear_counters(S))) return st;
     if (arena != c0_dev) HIPCHK(hipMemcpyAsync(arena, c0_dev, row_bytes(S), hipMemcpyDeviceToDevice, S->stream));
     HIPCHK(snp::launch_check_rows(S->elem_bytes, arena, S->m, S->count_max, S->d_ctr, S->stream));
-    if ((st = rebuild_table(S, arena, 1))) return st;
+    if ((st = fill_table(S, arena, 1))) return st;
     if ((st = read_counters(S))) return st;
     if (S->h_ctr->overflow) return fail(SNP_ERR_OVERFLOW, "C0 holds a count outside the count type's range");
     if (S->h_ctr->probe_fail) return fail(SNP_ERR_DEVICE, "visited set: no free slot");
@@ -297,36 +320,58 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         return SNP_OK;
     }
     const u64 hmask = S->opt.hash_mask ? S->opt.hash_mask : ~0ULL;
+    const long long rb = row_bytes(S);
 
-    // Psi per parent and its exclusive prefix sum
-    if ((st = clear_counters(S))) return st;
-    if ((st = mark(S, 0))) return st;
-    HIPCHK(snp::launch_psi(S->elem_bytes, S->dsys, io.frontier, io.n, S->opt.expand_max_count, S->d_psi, S->d_ctr,
-                           S->stream));
-    HIPCHK(snp::launch_scan_u64(S->d_psi, S->d_off, io.n, S->d_sc_sums, S->d_sc_pre, &S->d_ctr->total, S->stream));
-    if ((st = mark(S, 1))) return st;
-    if ((st = read_counters(S))) return st;
-    if (S->opt.profile && (st = add_elapsed(S, 0, 1, &stt.ns_psi))) return st;
-    const u64 T = S->h_ctr->total;
-    stt.halting_parents = (long long)S->h_ctr->halting;
-    stt.children_total = (long long)T;
+    // Psi and child offsets are computed for a growing prefix [0, P) of the
+    // frontier, only as far as the chunks need children: a level stopped by
+    // its cap usually reaches a small fraction of its parents.  An extension of
+    // the prefix runs in the same device pass as the chunk that needs it; the
+    // chunk kernels read the prefix's child count on the device and stop there,
+    // so a pass costs one host synchronisation.
+    long long P = 0;
+    u64 T = 0;                  // children of parents [0, P) (saturated), known after each pass
+    long long halting_all = 0;  // halting parents in [0, P)
+    auto launch_extension = [&]() -> snp_status {
+        const long long P1 = std::min(io.n, P + std::max<long long>(4096, P));
+        HIPCHK(snp::launch_psi(S->elem_bytes, S->dsys, (const char*)io.frontier + P * rb, P1 - P,
+                               S->opt.expand_max_count, S->d_psi + P, S->d_hflag + P, S->d_ctr, S->stream));
+        HIPCHK(snp::launch_scan_u64(S->d_psi + P, S->d_off + P, P1 - P, S->d_sc_sums, S->d_sc_pre, S->d_T,
+                                    P == 0 ? nullptr : S->d_T, &S->d_ctr->psi_total, S->stream));
+        P = P1;
+        return SNP_OK;
+    };
     const u64 budget = S->opt.child_budget > 0 ? (u64)S->opt.child_budget : ~0ULL;
-    const u64 T_eff = std::min(T, budget);
 
     const long long cap_limit = std::min(io.limit_cap, io.arena_cap - io.level_base);
     const long long limit = std::min(io.limit_sem, cap_limit);
     const bool sem_binds = io.limit_sem <= cap_limit;
     long long count = 0;
     u64 G = 0;
-    u64 enumerated = T_eff;
-    bool cap_hit = false;
-    while (G < T_eff) {
-        long long B = (long long)std::min<u64>((u64)S->chunk_max, T_eff - G);
+    u64 enumerated = 0;
+    bool cap_hit = false, budget_hit = false;
+    long long p_end = -1;  // parents up to the last enumerated child's (for the halting count)
+    for (;;) {
+        if (G >= budget) {  // the budget is spent: is anything left?
+            while (T <= G && P < io.n) {
+                if ((st = clear_counters(S))) return st;
+                if ((st = launch_extension())) return st;
+                if ((st = read_counters(S))) return st;
+                T = S->h_ctr->psi_total;
+                halting_all += (long long)S->h_ctr->halting;
+            }
+            budget_hit = T > G;
+            break;
+        }
+        u64 want = (u64)S->chunk_max;
         if (io.limit_sem < kInf) {
             const double ratio = std::max(S->new_ratio, 1.0 / 64.0);
-            const double want = (double)(io.limit_sem - count) / ratio * 1.1 + 1024.0;
-            if (want < (double)B) B = std::max<long long>((long long)want, std::min<long long>(B, 4096));
+            const double w = (double)(io.limit_sem - count) / ratio * 1.1 + 1024.0;
+            if (w < (double)want) want = (u64)std::max<double>(w, 4096.0);
         }
+        want = std::min(want, budget - G);
+        const bool ext = P < io.n && T - G < want;
+        if (!ext && T <= G) break;  // every child of the frontier was enumerated
+        const long long B = (long long)(ext ? want : std::min<u64>(want, T - G));  // upper bound when extending
         // keep the table at most half full (tombstones included)
         const long long live = io.level_base + count;
         if ((u64)(live + S->tombs + B) * 2 > S->slots) {
@@ -335,34 +380,42 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
                 return fail(SNP_ERR_CAPACITY, "visited set too small for %lld rows", live + B);
         }
         if ((st = clear_counters(S))) return st;
-        snp::ChunkArgs ca{io.frontier, io.n, S->d_psi, S->d_off, G, B, S->d_stage, S->d_hash, S->d_cpar, S->d_ct,
-                          hmask, S->d_ctr};
         if ((st = mark(S, 0))) return st;
+        if (ext && (st = launch_extension())) return st;
+        if ((st = mark(S, 1))) return st;
+        snp::ChunkArgs ca{io.frontier, P, S->d_psi, S->d_off, G, B, S->d_stage, S->d_hash, S->d_cpar, S->d_ct,
+                          hmask, S->d_ctr, S->d_T};
         if (use_int8) HIPCHK(snp::launch_expand_int8(S->elem_bytes, S->dsys, ca, S->stream));
         else HIPCHK(snp::launch_expand_sparse(S->elem_bytes, S->dsys, ca, S->stream));
-        if ((st = mark(S, 1))) return st;
-        snp::TableArgs ta{S->d_table, S->slots - 1, io.arena, S->d_stage, S->d_hash, S->d_slot, B, S->d_ctr,
-                          S->d_cand};
-        HIPCHK(snp::launch_insert(S->elem_bytes, S->m, ta, S->stream));
         if ((st = mark(S, 2))) return st;
-        HIPCHK(snp::launch_flags(S->d_table, S->d_slot, B, S->d_flag, S->stream));
-        HIPCHK(snp::launch_scan_u32(S->d_flag, S->d_pos, B, S->d_fsums, S->d_fpre, &S->d_ctr->total, S->stream));
+        snp::TableArgs ta{S->d_table, S->slots - 1, io.arena, S->d_stage, S->d_hash, S->d_slot, B, S->d_ctr,
+                          S->d_cand, S->d_cpar};
+        HIPCHK(snp::launch_insert(S->elem_bytes, S->m, ta, S->stream));
         if ((st = mark(S, 3))) return st;
+        HIPCHK(snp::launch_flags(S->d_table, S->d_slot, S->d_cpar, B, S->d_ctr, S->d_flag, S->stream));
+        HIPCHK(snp::launch_scan_u32(S->d_flag, S->d_pos, B, S->d_fsums, S->d_fpre, &S->d_ctr->total, S->stream));
+        if ((st = mark(S, 4))) return st;
         snp::CommitArgs cm{S->d_table, S->d_table, S->d_slot, S->d_hash, S->d_pos, S->d_flag, S->d_stage,
                            S->d_cpar, S->d_ct, B, io.arena, io.level_base, count, limit, io.row2, io.par_out,
                            io.par_out_base, io.par_value_base, io.t_out, S->d_row_slot, S->d_ctr};
         HIPCHK(snp::launch_commit(S->elem_bytes, S->m, cm, S->stream));
-        if ((st = mark(S, 4))) return st;
+        if ((st = mark(S, 5))) return st;
         if ((st = read_counters(S))) return st;
         if (S->opt.profile) {
-            if ((st = add_elapsed(S, 0, 1, &stt.ns_expand))) return st;
-            if ((st = add_elapsed(S, 1, 2, &stt.ns_insert))) return st;
-            if ((st = add_elapsed(S, 2, 3, &stt.ns_flags))) return st;
-            if ((st = add_elapsed(S, 3, 4, &stt.ns_commit))) return st;
+            if ((st = add_elapsed(S, 0, 1, &stt.ns_psi))) return st;
+            if ((st = add_elapsed(S, 1, 2, &stt.ns_expand))) return st;
+            if ((st = add_elapsed(S, 2, 3, &stt.ns_insert))) return st;
+            if ((st = add_elapsed(S, 3, 4, &stt.ns_flags))) return st;
+            if ((st = add_elapsed(S, 4, 5, &stt.ns_commit))) return st;
         }
-        ++stt.chunks;
-        stt.expanded += B;
         const snp::DevCounters c = *S->h_ctr;
+        if (ext) {
+            T = c.psi_total;
+            halting_all += (long long)c.halting;
+        }
+        const long long Beff = (long long)c.beff;
+        if (Beff > 0) ++stt.chunks;
+        stt.expanded += Beff;
         const long long new_total = (long long)c.total;
         const long long avail = limit - count;
         const long long committed = std::min(new_total, avail);
@@ -373,11 +426,12 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
             *count_out = count;
             return fail(SNP_ERR_OVERFLOW, "a child configuration holds a count above %lld", S->count_max);
         }
-        S->new_ratio = (double)new_total / (double)B;
+        if (Beff > 0) S->new_ratio = (double)new_total / (double)Beff;
         if (new_total >= avail && sem_binds && avail > 0) {
             count = limit;
             cap_hit = true;
             enumerated = G + c.cap_g;
+            p_end = (long long)c.cap_par + 1;
             break;
         }
         if (new_total > avail) {
@@ -386,12 +440,30 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
             return fail(SNP_ERR_CAPACITY, "level needs more than %lld rows", cap_limit);
         }
         count += new_total;
-        G += (u64)B;
+        G += (u64)Beff;
+        enumerated = G;
+        if (G >= budget && Beff > 0) {  // parent of the last child within the budget
+            int last = 0;
+            HIPCHK(hipMemcpyAsync(&last, S->d_cpar + (Beff - 1), sizeof(int), hipMemcpyDeviceToHost, S->stream));
+            HIPCHK(hipStreamSynchronize(S->stream));
+            p_end = (long long)(last < 0 ? -1 - last : last) + 1;  // a twin holds -1 - parent
+        }
     }
+    // halting parents up to the parent of the last enumerated child (all parents
+    // when the level was not cut short by the cap or the budget)
+    if (cap_hit || budget_hit) {
+        if ((st = clear_counters(S))) return st;
+        HIPCHK(snp::launch_count_flags(S->d_hflag, p_end, &S->d_ctr->count, S->stream));
+        if ((st = read_counters(S))) return st;
+        stt.halting_parents = (long long)S->h_ctr->count;
+    } else {
+        stt.halting_parents = halting_all;
+    }
+    stt.children_total = (long long)T;
     stt.enumerated = (long long)enumerated;
     stt.new_configs = count;
     stt.truncated = cap_hit ? 1 : 0;
-    stt.budget_hit = (!cap_hit && T > budget) ? 1 : 0;
+    stt.budget_hit = budget_hit ? 1 : 0;
     if (out) *out = stt;
     *count_out = count;
     return SNP_OK;
@@ -525,6 +597,7 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     LOADCHK(dmalloc(&S->d_row_slot, sizeof(uint32_t) * S->max_rows));
     const long long F = S->max_frontier;
     LOADCHK(dmalloc(&S->d_psi, sizeof(u64) * F));
+    LOADCHK(dmalloc(&S->d_hflag, (size_t)F));
     LOADCHK(dmalloc(&S->d_off, sizeof(u64) * F));
     const long long ft = snp::scan_tiles(std::max(F, S->chunk_max)) + 1;
     LOADCHK(dmalloc(&S->d_sc_sums, sizeof(u64) * ft));
@@ -540,7 +613,9 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     LOADCHK(dmalloc(&S->d_pos, sizeof(uint32_t) * C));
     LOADCHK(dmalloc(&S->d_fsums, sizeof(uint32_t) * ft));
     LOADCHK(dmalloc(&S->d_fpre, sizeof(uint32_t) * ft));
-    LOADCHK(dmalloc(&S->d_ctr, sizeof(snp::DevCounters)));
+    LOADCHK(dmalloc(&S->d_ring, sizeof(snp::DevCounters) * snp_system::kRing));
+    LOADCHK(dmalloc(&S->d_T, sizeof(u64)));
+    S->d_ctr = S->d_ring;
     LOADCHK(hipHostMalloc((void**)&S->h_ctr, sizeof(snp::DevCounters), hipHostMallocDefault));
     if (opt.profile)
         for (hipEvent_t& e : S->ev) LOADCHK(hipEventCreate(&e));

@@ -120,6 +120,31 @@ __device__ __forceinline__ u64 row_hash_wave(const T* row, const u64* R, int m, 
     return wave_sum_u64(h);
 }
 
+// Twin rules: two rules of one neuron with the same consumption c and the same
+// production p have identical rows of M_Pi (Definition 2), so a child that
+// fires the later one of two applicable twins equals the child that fires the
+// earlier one with every other choice unchanged, which has a smaller index t:
+// it is never a first occurrence.  Digit d of a neuron is "canonical" when no
+// earlier applicable rule of the neuron is its twin.
+__device__ __forceinline__ uint32_t canonical_mask(const int4* rules, int r0, uint32_t app) {
+    uint32_t cm = 0;
+    int d = 0;
+    for (uint32_t a = app; a; a &= a - 1, ++d) {
+        const int q = __ffs(a) - 1;
+        const int4 R = rules[r0 + q];
+        bool canon = true;
+        for (uint32_t b = app & ((1u << q) - 1); b; b &= b - 1) {
+            const int4 Q = rules[r0 + __ffs(b) - 1];
+            if (Q.z == R.z && Q.w == R.w) {
+                canon = false;
+                break;
+            }
+        }
+        cm |= canon ? (1u << d) : 0u;
+    }
+    return cm;
+}
+
 // Mixed-radix decode of child index t (Algorithm 2 II-3 order: the last neuron
 // is the least significant digit; a neuron with omega <= 1 has one value).
 // Lane L owns the contiguous neurons [L*Q, L*Q + Q); the place value of its

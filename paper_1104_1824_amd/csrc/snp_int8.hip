@@ -142,8 +142,11 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int m = s.m;
     const long long b0 = (long long)blockIdx.x * kTile;
-    if (b0 >= a.B) return;  // whole block
-    const int rows = (int)min((long long)kTile, a.B - b0);
+    const u64 tot = *a.Tdev;
+    const long long Beff = tot > a.g0 ? (long long)min((u64)a.B, tot - a.g0) : 0;
+    if (blockIdx.x == 0 && tid == 0) a.ctr->beff = (u64)Beff;
+    if (b0 >= Beff) return;  // whole block
+    const int rows = (int)min((long long)kTile, Beff - b0);
     Lds L = carve(smem, m, NT);
     const T* F = (const T*)a.frontier;
     T* stage = (T*)a.stage;

@@ -31,6 +31,10 @@ struct DevCounters {
     u64 tombs;         // entries turned into tombstones by this pass
     u64 total;         // scan total (children of the frontier / new children of a chunk)
     u64 ncand;         // children whose probe met an entry with their tag (row compare pending)
+    u64 cap_par;       // parent (frontier index) of the child that filled the cap
+    u64 count;         // scratch count (halting parents of a frontier prefix)
+    u64 beff;          // children the chunk really covers: min(B, children of the prefix - g0)
+    u64 psi_total;     // children of the frontier prefix after this pass's extension
     u64 pad;
 };
 
@@ -58,10 +62,11 @@ struct ChunkArgs {
     long long B;
     void* stage;           // [B] child rows
     u64* hash;             // [B]
-    int* cpar;             // [B] parent index in the frontier
+    int* cpar;             // [B] parent index p in the frontier; -1 - p for a twin child
     u64* ct;               // [B] child index within the parent
     u64 hash_mask;
     DevCounters* ctr;
+    const u64* Tdev;       // children of the frontier prefix [0, n): the chunk stops there
 };
 
 // Insert/commit arguments.
@@ -75,6 +80,7 @@ struct TableArgs {
     long long B;
     DevCounters* ctr;
     uint32_t* cand;        // [B] children waiting for a row compare
+    const int* cpar;       // [B] parent of each child; negative marks a twin (skipped)
 };
 
 struct CommitArgs {
@@ -143,9 +149,10 @@ hipError_t launch_batch_det(int elem_bytes, int npt, const BatchArgs& a, int n_s
 hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st);
 
 hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, long long n,
-                      long long expand_max, u64* psi, DevCounters* ctr, hipStream_t st);
+                      long long expand_max, u64* psi, uint8_t* halt_flag, DevCounters* ctr, hipStream_t st);
 hipError_t launch_scan_u64(const u64* in, u64* out, long long n, u64* tile_sums, u64* tile_pre,
-                           u64* total, hipStream_t st);
+                           u64* total, const u64* base_dev, u64* total_copy, hipStream_t st);
+hipError_t launch_count_flags(const uint8_t* flags, long long n, u64* out, hipStream_t st);
 hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, long long n, uint32_t* tile_sums,
                            uint32_t* tile_pre, u64* total, hipStream_t st);
 long long scan_tiles(long long n);
@@ -153,7 +160,8 @@ hipError_t launch_expand_int8(int elem_bytes, const DevSystem& s, const ChunkArg
 size_t int8_lds(int m, int nt);
 hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st);
 hipError_t launch_insert(int elem_bytes, int m, const TableArgs& a, hipStream_t st);
-hipError_t launch_flags(const u64* table, const uint32_t* slot, long long B, uint32_t* flag, hipStream_t st);
+hipError_t launch_flags(const u64* table, const uint32_t* slot, const int* cpar, long long B, const DevCounters* ctr,
+                        uint32_t* flag, hipStream_t st);
 hipError_t launch_commit(int elem_bytes, int m, const CommitArgs& a, hipStream_t st);
 hipError_t launch_fill_u64(u64* p, long long n, u64 v, hipStream_t st);
 hipError_t launch_rows_insert(int elem_bytes, int m, const u64* R, u64* table, u64 slot_mask, const void* arena,

@@ -34,7 +34,8 @@ __device__ __forceinline__ u64 wave_satprod(u64 x) {
 template <typename T, bool TBL_LDS>
 __global__ __launch_bounds__(256) void k_psi(DevSystem s, const T* __restrict__ F, long long n,
                                              long long expand_max, u64* __restrict__ psi,
-                                             DevCounters* __restrict__ ctr, int parents_per_wave) {
+                                             uint8_t* __restrict__ halt_flag, DevCounters* __restrict__ ctr,
+                                             int parents_per_wave) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int m = s.m;
@@ -78,14 +79,17 @@ __global__ __launch_bounds__(256) void k_psi(DevSystem s, const T* __restrict__ 
         const bool wover = __any(over);
         u64 prod = sat_mul(sat_mul(sat_pow(2, c2), sat_pow(3, c3)), sat_pow(4, c4));
         if (__any(big)) prod = sat_mul(prod, wave_satprod(bigprod));
-        if (lane == 0) psi[p] = (!wany || wover) ? 0 : prod;
+        if (lane == 0) {
+            psi[p] = (!wany || wover) ? 0 : prod;
+            halt_flag[p] = wany ? 0 : 1;
+        }
         halting += wany ? 0u : 1u;
     }
     if (lane == 0 && halting) atomicAdd(&ctr->halting, (u64)halting);
 }
 
 hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, long long n,
-                      long long expand_max, u64* psi, DevCounters* ctr, hipStream_t st) {
+                      long long expand_max, u64* psi, uint8_t* halt_flag, DevCounters* ctr, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     const size_t tbl = (size_t)s.r * 16 + (size_t)(s.m + 1) * 4;
     const bool tbl_lds = tbl <= (size_t)(32 * 1024);
@@ -97,7 +101,7 @@ hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, 
     const size_t lds = tbl_lds ? tbl : 0;
 #define SNP_PSI(TT, L)                                                                                       \
     hipLaunchKernelGGL((k_psi<TT, L>), dim3(blocks), dim3(256), lds, st, s, (const TT*)frontier, n, expand_max, \
-                       psi, ctr, ppw)
+                       psi, halt_flag, ctr, ppw)
     if (elem_bytes == 4) {
         if (tbl_lds) SNP_PSI(int32_t, true);
         else SNP_PSI(int32_t, false);
@@ -156,11 +160,12 @@ __global__ __launch_bounds__(256) void k_scan_tiles(const V* __restrict__ in, V*
 
 template <typename V, bool SAT>
 __global__ __launch_bounds__(1024) void k_scan_sums(const V* __restrict__ sums, V* __restrict__ pre,
-                                                    long long ntiles, u64* __restrict__ total) {
+                                                    long long ntiles, u64* total, const u64* base_dev,
+                                                    u64* total_copy) {
     __shared__ V wsum[16];
     __shared__ V carry_s;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (threadIdx.x == 0) carry_s = 0;
+    if (threadIdx.x == 0) carry_s = base_dev ? (V)*base_dev : (V)0;
     __syncthreads();
     for (long long b = 0; b < ntiles; b += 1024) {
         const long long i = b + threadIdx.x;
@@ -182,7 +187,10 @@ __global__ __launch_bounds__(1024) void k_scan_sums(const V* __restrict__ sums, 
         if (threadIdx.x == 1023) carry_s = vadd<V, SAT>(wpre, incl);
         __syncthreads();
     }
-    if (threadIdx.x == 0) *total = (u64)carry_s;
+    if (threadIdx.x == 0) {
+        *total = (u64)carry_s;
+        if (total_copy) *total_copy = (u64)carry_s;
+    }
 }
 
 template <typename V, bool SAT>
@@ -193,25 +201,41 @@ __global__ __launch_bounds__(256) void k_scan_add(V* __restrict__ out, const V* 
 
 long long scan_tiles(long long n) { return (n + kScanTile - 1) / kScanTile; }
 
+// out[i] = base + sum of in[0 .. i); *total = base + sum of in, where base is
+// read on the device (*base_dev, 0 when null) and may be the same word as total.
 template <typename V, bool SAT>
 static hipError_t scan_impl(const V* in, V* out, long long n, V* tile_sums, V* tile_pre, u64* total,
-                            hipStream_t st) {
+                            const u64* base_dev, u64* total_copy, hipStream_t st) {
     const long long nt = scan_tiles(n);
     if (nt > 0) hipLaunchKernelGGL((k_scan_tiles<V, SAT>), dim3((unsigned)nt), dim3(256), 0, st, in, out, tile_sums, n);
-    hipLaunchKernelGGL((k_scan_sums<V, SAT>), dim3(1), dim3(1024), 0, st, tile_sums, tile_pre, nt, total);
-    if (nt > 1)
+    hipLaunchKernelGGL((k_scan_sums<V, SAT>), dim3(1), dim3(1024), 0, st, tile_sums, tile_pre, nt, total, base_dev,
+                       total_copy);
+    if (nt > 1 || (nt == 1 && base_dev))
         hipLaunchKernelGGL((k_scan_add<V, SAT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, out, tile_pre, n);
     return hipGetLastError();
 }
 
 hipError_t launch_scan_u64(const u64* in, u64* out, long long n, u64* tile_sums, u64* tile_pre, u64* total,
-                           hipStream_t st) {
-    return scan_impl<u64, true>(in, out, n, tile_sums, tile_pre, total, st);
+                           const u64* base_dev, u64* total_copy, hipStream_t st) {
+    return scan_impl<u64, true>(in, out, n, tile_sums, tile_pre, total, base_dev, total_copy, st);
 }
 
 hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, long long n, uint32_t* tile_sums,
                            uint32_t* tile_pre, u64* total, hipStream_t st) {
-    return scan_impl<uint32_t, false>(in, out, n, tile_sums, tile_pre, total, st);
+    return scan_impl<uint32_t, false>(in, out, n, tile_sums, tile_pre, total, nullptr, nullptr, st);
+}
+
+__global__ __launch_bounds__(256) void k_count_flags(const uint8_t* __restrict__ f, long long n, u64* out) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    const bool v = i < n && f[i] != 0;
+    const u64 bm = __ballot(v);
+    if ((threadIdx.x & 63) == 0 && bm) atomicAdd(out, (u64)__popcll(bm));
+}
+
+hipError_t launch_count_flags(const uint8_t* flags, long long n, u64* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count_flags, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, flags, n, out);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -245,11 +269,12 @@ struct Tables {
 };
 
 // Fired rule of neuron j packed as (c << 16) | p (both <= 65535, checked at load); 0 when none.
+// am[j]: applicable-rule mask in the low 16 bits, canonical digits in the high 16.
 __device__ __forceinline__ void set_fired(const Tables& tb, int j, const uint8_t* om, const uint32_t* am,
                                           const uint8_t* dg, uint32_t* cp) {
     uint32_t v = 0;
     if (om[j]) {
-        const int4 R = tb.rules[tb.nrp[j] + nth_bit(am[j], dg[j])];
+        const int4 R = tb.rules[tb.nrp[j] + nth_bit(am[j] & 0xFFFFu, dg[j])];
         v = ((uint32_t)R.z << 16) | (uint32_t)R.w;
     }
     cp[j] = v;
@@ -269,9 +294,18 @@ __device__ __forceinline__ void load_parent(const Tables& tb, int m, const T* ro
                 mask |= 1u << (q - r0);
                 ++w;
             }
-        am[j] = mask;
+        am[j] = mask | (w >= 2 ? canonical_mask(tb.rules, r0, mask) << 16 : 0xFFFF0000u);
         om[j] = (uint8_t)w;
     }
+}
+
+// True when some neuron's digit picks the later of two applicable twins.
+__device__ __forceinline__ bool wave_any_twin(int m, int lane, const uint8_t* om, const uint32_t* am,
+                                              const uint8_t* dg) {
+    bool nc = false;
+    for (int j = lane; j < m; j += 64)
+        if (om[j] >= 2 && !((am[j] >> (16 + dg[j])) & 1u)) nc = true;
+    return __any(nc);
 }
 
 __host__ __device__ __forceinline__ size_t table_lds_bytes(const DevSystem& s, int nnz) {
@@ -308,7 +342,10 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
     }
     const long long wave = (long long)blockIdx.x * (blockDim.x >> 6) + wid;
     const long long b0 = wave * run;
-    if (b0 >= a.B) return;
+    const u64 tot = *a.Tdev;
+    const long long Beff = tot > a.g0 ? (long long)min((u64)a.B, tot - a.g0) : 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctr->beff = (u64)Beff;
+    if (b0 >= Beff) return;
     unsigned char* base = wave_base + (size_t)wid * wave_stride;
     int* par = (int*)base;
     uint32_t* cp = (uint32_t*)(par + m);
@@ -317,7 +354,7 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
     uint8_t* dg = om + m;
     const T* F = (const T*)a.frontier;
     T* stage = (T*)a.stage;
-    const int cnt = (int)min((long long)run, a.B - b0);
+    const int cnt = (int)min((long long)run, Beff - b0);
 
     // parent of the first child: last p with off[p] <= g (it has Psi > 0),
     // found by a 64-ary search: every lane probes one point per round
@@ -347,7 +384,14 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
         wave_lds_sync();
         u64 h = 0;
         T* out = stage + b * (long long)m;
-        for (int j = lane; j < m; j += 64) {
+        const bool twin = wave_any_twin(m, lane, om, am, dg);
+        if (twin) {  // a duplicate by construction: no row, no probe; cpar = -1 - parent
+            if (lane == 0) {
+                a.cpar[b] = -1 - (int)p;
+                a.ct[b] = t;
+            }
+        }
+        for (int j = lane; j < m && !twin; j += 64) {
             long long v = (long long)par[j] - (long long)(cp[j] >> 16);
             const int e1 = tb.inp[j + 1];
             for (int e = tb.inp[j]; e < e1; ++e) v += cp[tb.ins[e]] & 0xFFFFu;
@@ -356,7 +400,7 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
             h += hterm((uint32_t)v, tb.R[j]);
         }
         h = wave_sum_u64(h);
-        if (lane == 0) {
+        if (lane == 0 && !twin) {
             a.hash[b] = fmix64(h) & a.hash_mask;
             a.cpar[b] = (int)p;
             a.ct[b] = t;
@@ -449,8 +493,10 @@ __device__ __forceinline__ const T* entry_row(const TableArgs& a, uint32_t ref, 
 template <typename T>
 __global__ __launch_bounds__(256) void k_insert_probe(int m, TableArgs a) {
     const long long b = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long Beff = (long long)a.ctr->beff;
     bool queue = false;
-    if (b < a.B) {
+    if (b < Beff && a.cpar[b] < 0) a.slot[b] = 0;  // twin: never a first occurrence
+    else if (b < Beff) {
         const u64 h = a.hash[b];
         const uint32_t tag = (uint32_t)(h >> 32);
         const u64 mine = ((u64)tag << 32) | (kStageBase + (uint32_t)b);
@@ -549,15 +595,18 @@ hipError_t launch_insert(int elem_bytes, int m, const TableArgs& a, hipStream_t 
 }
 
 __global__ __launch_bounds__(256) void k_flags(const u64* __restrict__ table, const uint32_t* __restrict__ slot,
-                                               long long B, uint32_t* __restrict__ flag) {
+                                               const int* __restrict__ cpar, long long B,
+                                               const DevCounters* __restrict__ ctr, uint32_t* __restrict__ flag) {
     const long long b = (long long)blockIdx.x * 256 + threadIdx.x;
     if (b >= B) return;
-    flag[b] = ((uint32_t)table[slot[b]] == kStageBase + (uint32_t)b) ? 1u : 0u;
+    flag[b] = (b < (long long)ctr->beff && cpar[b] >= 0 && (uint32_t)table[slot[b]] == kStageBase + (uint32_t)b)
+                  ? 1u : 0u;
 }
 
-hipError_t launch_flags(const u64* table, const uint32_t* slot, long long B, uint32_t* flag, hipStream_t st) {
+hipError_t launch_flags(const u64* table, const uint32_t* slot, const int* cpar, long long B, const DevCounters* ctr,
+                        uint32_t* flag, hipStream_t st) {
     if (B <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_flags, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, table, slot, B, flag);
+    hipLaunchKernelGGL(k_flags, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, table, slot, cpar, B, ctr, flag);
     return hipGetLastError();
 }
 
@@ -586,7 +635,10 @@ __global__ __launch_bounds__(256) void k_commit(int upr /* units per row */, Com
             a.row_slot[A] = sl;
             if (a.par_out) a.par_out[a.par_out_base + local] = (long long)a.cpar[b] + a.par_value_base;
             if (a.t_out) a.t_out[a.par_out_base + local] = (long long)a.ct[b];
-            if (local == a.limit - 1) a.ctr->cap_g = (u64)b + 1;
+            if (local == a.limit - 1) {
+                a.ctr->cap_g = (u64)b + 1;
+                a.ctr->cap_par = (u64)a.cpar[b];
+            }
         } else {
             a.table[sl] = kTomb;
         }

@@ -71,7 +71,7 @@ def _ex(**over):
     (dict(rules=[(0, 1, 1, 1, -1)]), "p must be >= 0"),
     (dict(rules=[(5, 1, 1, 1, 1)]), "out of range"),
     (dict(syn=[(0, 7)]), "out of range"),
-    (dict(rules=[(0, 1, 1, 1, 1)] * 33), "more than 32 rules"),
+    (dict(rules=[(0, 1, 1, 1, 1)] * 17), "more than 16 rules"),
 ])
 def test_load_rejects_malformed(bad, needle):
     st, msg = _load_status(_ex(**bad))

@@ -223,3 +223,46 @@ def test_nondefault_stream(gpu, oracle_mod):
         g = gpu_bfs(s, max_depth=3, frontier_cap=1000, out_capacity=8192, stream=side)
     torch.cuda.synchronize()
     assert_same_bfs(g, oracle_mod.bfs(s, max_depth=3, frontier_cap=1000))
+
+
+@pytest.mark.parametrize("path", [snp.SNP_PATH_SPARSE, snp.SNP_PATH_INT8])
+def test_caps_budgets_many_seeds(gpu, oracle_mod, path):
+    """Small caps and budgets cut levels in the middle of a parent's children:
+    truncation, enumeration counts, halting counts and stop reasons agree."""
+    for seed in range(0, 100, 3):
+        s = synth.config_system(1, seed)
+        for kw in (dict(frontier_cap=1), dict(frontier_cap=3, stop_at_cap=True), dict(child_budget=2),
+                   dict(child_budget=5, frontier_cap=2)):
+            note(f"path {path} tiny seed {seed} {kw}")
+            assert_same_bfs(gpu_bfs(s, max_depth=6, out_capacity=256, chunk=4096, path=path, **kw),
+                            oracle_mod.bfs(s, max_depth=6, **kw))
+
+
+def test_table_rebuilds(gpu, oracle_mod):
+    """Many capped levels leave tombstones (truncated children) until the visited
+    set is rebuilt from the row store; results stay exact."""
+    s = synth.config_system(2, 0)
+    for path in (snp.SNP_PATH_SPARSE, snp.SNP_PATH_INT8):
+        note(f"table rebuilds, path {path}")
+        g = gpu_bfs(s, max_depth=30, frontier_cap=10, out_capacity=400, max_rows=400, chunk=4096, path=path)
+        assert_same_bfs(g, oracle_mod.bfs(s, max_depth=30, frontier_cap=10))
+
+
+def twin_system():
+    """Neurons whose applicable rules share (c, p): children picking a later twin
+    repeat an earlier child (identical rows of M_Pi, Definition 2)."""
+    rules = [(0, 1, 1, 1, 1), (0, 2, 0, 1, 1), (0, 1, 2, 1, 1), (0, 3, 0, 2, 1),
+             (1, 1, 1, 1, 1), (1, 1, 0, 1, 1), (1, 2, 1, 2, 0),
+             (2, 1, 1, 1, 2), (2, 1, 1, 1, 2), (3, 1, 1, 1, 1)]
+    syn = [(0, 1), (1, 2), (2, 0), (2, 3), (3, 0), (0, 2)]
+    return synth.make_system(4, rules, syn, [3, 2, 1, 1], name="twins")
+
+
+@pytest.mark.parametrize("path", [snp.SNP_PATH_SPARSE, snp.SNP_PATH_INT8])
+def test_twin_rules(gpu, oracle_mod, path):
+    s = twin_system()
+    for kw in (dict(), dict(child_budget=3), dict(child_budget=7, frontier_cap=4), dict(frontier_cap=5),
+               dict(frontier_cap=2, stop_at_cap=True)):
+        note(f"twin rules, path {path}, {kw}")
+        assert_same_bfs(gpu_bfs(s, max_depth=12, out_capacity=4096, chunk=4096, path=path, **kw),
+                        oracle_mod.bfs(s, max_depth=12, **kw))
