@@ -123,7 +123,10 @@ typedef struct {
                                  ANDed with it (forces collisions; results do not change) */
     int32_t profile;          /* nonzero: time every stage with HIP events on the handle's
                                  stream and report it in snp_expand_stats.ns_* */
-    int32_t reserved;         /* must be 0 */
+    int32_t int8_max_k;       /* int8 path: most rule columns (1..128) one segment of children
+                                 may put on the matrix cores, 0: 128; segments that need more
+                                 take the per-child sparse form (smaller values force it;
+                                 results do not change) */
     void *stream;             /* hipStream_t for all work of the handle; NULL: default */
 } snp_options;
 

@@ -224,7 +224,7 @@ snp_status validate_options(const snp_options* o) {
     if (o->max_rows < 1 || o->max_rows >= (long long)snp::kStageBase)
         return fail(SNP_ERR_INVALID, "max_rows must be in [1, 2^31)");
     if (o->chunk > (long long)snp::kMaxChunk) return fail(SNP_ERR_INVALID, "chunk above 2^30");
-    if (o->reserved != 0) return fail(SNP_ERR_INVALID, "reserved option field must be 0");
+    if (o->int8_max_k < 0 || o->int8_max_k > 128) return fail(SNP_ERR_INVALID, "int8_max_k must be in 0..128");
     return SNP_OK;
 }
 
@@ -384,7 +384,7 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         if (ext && (st = launch_extension())) return st;
         if ((st = mark(S, 1))) return st;
         snp::ChunkArgs ca{io.frontier, P, S->d_psi, S->d_off, G, B, S->d_stage, S->d_hash, S->d_cpar, S->d_ct,
-                          hmask, S->d_ctr, S->d_T};
+                          hmask, S->d_ctr, S->d_T, S->opt.int8_max_k > 0 ? S->opt.int8_max_k : 128};
         if (use_int8) HIPCHK(snp::launch_expand_int8(S->elem_bytes, S->dsys, ca, S->stream));
         else HIPCHK(snp::launch_expand_sparse(S->elem_bytes, S->dsys, ca, S->stream));
         if ((st = mark(S, 2))) return st;

@@ -19,6 +19,12 @@
 // Segments whose V needs more than 64 neurons or 128 rule columns fall back
 // to the sparse pull for each of their children.
 //
+// Children that fire the later of two twin rules (same neuron, same c and p)
+// repeat an earlier child of the same parent and are only marked: a segment
+// whose fixed digits already pick a later twin is skipped whole, and within a
+// segment the digit walk that builds D(t) also tells which rows are twins;
+// their rows are not stored and never reach the visited set.
+//
 // MFMA operand layout (checked on the device): lane l supplies row l % 16 of
 // A and column l % 16 of B, with the 16 int8 of lane group l / 16 covering
 // K columns 16 * (l / 16) .. + 15; the 16x16 int32 result lands in lane l as
@@ -40,7 +46,7 @@ struct Lds {
     uint8_t* om;   // [m] omega per neuron
     uint8_t* dg;   // [m] digits of the child being computed by the sparse pull
     uint8_t* dgb;  // [m] digits of the last child of the segment
-    uint16_t* am;  // [m] applicable-rule mask (<= 16 rules per neuron)
+    uint32_t* am;  // [m] applicable-rule mask (<= 16 rules per neuron) | canonical digits << 16
     uint16_t* cp;  // [m] fired (c << 8 | p) of the child being computed
     int8_t* D;     // [kTile][kKMax]
     int8_t* MT;    // [NT][kMTStride]
@@ -49,6 +55,7 @@ struct Lds {
     int* kbase;    // [kVMax] first K column of every neuron of V
     u64* rowh;     // [kTile] H of every row of the tile
     u64* wsum;     // [4]
+    u64* misc;     // [0] reference digits of V that pick a later twin, [1] twin rows of the tile
     int* sc;       // scalars: [0] jstar, [1] nv, [2] kvar
 };
 
@@ -56,10 +63,10 @@ __host__ __device__ __forceinline__ size_t align16(size_t x) { return (x + 15) &
 
 __host__ __device__ __forceinline__ size_t int8_lds_bytes(int m, int nt) {
     size_t o = align16((size_t)3 * m);
-    o += align16((size_t)2 * m) + align16((size_t)2 * m);
+    o += align16((size_t)4 * m) + align16((size_t)2 * m);
     o += (size_t)kTile * kKMax + (size_t)nt * kMTStride;
     o += align16((size_t)kKMax * 4) + (size_t)kVMax * 4 * 2;
-    o += (size_t)kTile * 8 + 4 * 8 + 4 * 4;
+    o += (size_t)kTile * 8 + 6 * 8 + 4 * 4;
     return align16(o);
 }
 
@@ -70,8 +77,8 @@ __device__ __forceinline__ Lds carve(unsigned char* smem, int m, int nt) {
     L.dg = smem + m;
     L.dgb = smem + 2 * m;
     o = align16((size_t)3 * m);
-    L.am = (uint16_t*)(smem + o);
-    o += align16((size_t)2 * m);
+    L.am = (uint32_t*)(smem + o);
+    o += align16((size_t)4 * m);
     L.cp = (uint16_t*)(smem + o);
     o += align16((size_t)2 * m);
     L.D = (int8_t*)(smem + o);
@@ -88,12 +95,25 @@ __device__ __forceinline__ Lds carve(unsigned char* smem, int m, int nt) {
     o += (size_t)kTile * 8;
     L.wsum = (u64*)(smem + o);
     o += 4 * 8;
+    L.misc = (u64*)(smem + o);
+    o += 2 * 8;
     L.sc = (int*)(smem + o);
     return L;
 }
 
-__device__ __forceinline__ int rule_of(const DevSystem& s, const uint16_t* am, int j, int d) {
-    return s.nrule_ptr[j] + nth_bit(am[j], d);
+__device__ __forceinline__ int rule_of(const DevSystem& s, const uint32_t* am, int j, int d) {
+    return s.nrule_ptr[j] + nth_bit(am[j] & 0xFFFFu, d);
+}
+
+__device__ __forceinline__ bool later_twin(const Lds& L, int j, int d) {
+    return L.om[j] >= 2 && !((L.am[j] >> (16 + d)) & 1u);
+}
+
+// True (in every thread) when the digits in L.dg pick a later twin somewhere.
+__device__ __forceinline__ bool block_any_twin(const Lds& L, int m) {
+    bool nc = false;
+    for (int j = threadIdx.x; j < m; j += blockDim.x) nc |= later_twin(L, j, L.dg[j]);
+    return __syncthreads_or(nc);
 }
 
 // Block-wide sum of a 64-bit value (256 threads); every thread gets the total.
@@ -151,6 +171,7 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a) {
     const T* F = (const T*)a.frontier;
     T* stage = (T*)a.stage;
     bool ovf = false;
+    if (tid == 0) L.misc[1] = 0;
 
     // parent of the tile's first child: 64-ary search over the offsets
     const u64 g = a.g0 + (u64)b0;
@@ -185,7 +206,7 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a) {
                     mask |= 1u << (q - r0);
                     ++w;
                 }
-            L.am[j] = (uint16_t)mask;
+            L.am[j] = mask | (w >= 2 ? canonical_mask(s.rules, r0, mask) << 16 : 0xFFFF0000u);
             L.om[j] = (uint8_t)w;
         }
         if (tid == 0) L.sc[0] = m;
@@ -203,7 +224,10 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a) {
         if (myj < m) atomicMin(&L.sc[0], myj);
         __syncthreads();
         const int jstar = L.sc[0];
-        // 4. V (neurons with omega >= 2 from jstar on) and its rule columns
+        // 4. V (neurons with omega >= 2 from jstar on) and its rule columns;
+        //    do the fixed digits (before jstar) pick a later twin?
+        bool fixed_nc = false;
+        for (int j = tid; j < jstar; j += blockDim.x) fixed_nc |= later_twin(L, j, L.dg[j]);
         if (wid == 0) {
             int nv = 0;
             for (int base = jstar; base < m; base += 64) {
@@ -224,114 +248,145 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a) {
             }
             const int kb = incl - w;
             const int kvar = __shfl(incl, 63);
+            bool rnc = false;
             if (lane < min(nv, kVMax)) {
                 L.kbase[lane] = kb;
                 const int j = L.vlist[lane];
                 for (int d = 0; d < w && kb + d < kKMax; ++d) L.klist[kb + d] = rule_of(s, L.am, j, d);
+                rnc = later_twin(L, j, L.dg[j]);
             }
+            const u64 refnc = __ballot(rnc);
             if (lane == 0) {
                 L.sc[1] = nv;
                 L.sc[2] = kvar;
+                L.misc[0] = refnc;
             }
         }
-        __syncthreads();
+        const bool seg_twin = __syncthreads_or(fixed_nc);
         const int nv = L.sc[1];
         const int kvar = L.sc[2];
-        const bool mfma = nv <= kVMax && kvar <= kKMax;
+        const bool mfma = nv <= kVMax && kvar <= a.kmax;
+        const u64 seg_rows = (len == 64 ? ~0ULL : ((1ULL << len) - 1)) << c;
 
-        // 5. reference child (first of the segment) by the sparse pull
         T* refrow = stage + (b0 + c) * (long long)m;
-        const u64 href = sparse_child<T>(s, L, P, refrow, ovf);
-        if (tid == 0) L.rowh[c] = href;
-
-        if (!mfma) {
-            // sparse pull for every other child of the segment
-            for (int rr = c + 1; rr < cend; ++rr) {
-                __syncthreads();
-                if (wid == 0) decode_digits(m, lane, ta + (u64)(rr - c), L.om, L.dg);
-                __syncthreads();
+        if (seg_twin) {
+            // every child of the segment repeats an earlier one
+            if (tid == 0) L.misc[1] |= seg_rows;
+        } else if (!mfma) {
+            // sparse pull for every child of the segment that is not a twin
+            for (int rr = c; rr < cend; ++rr) {
+                if (rr > c) {
+                    __syncthreads();
+                    if (wid == 0) decode_digits(m, lane, ta + (u64)(rr - c), L.om, L.dg);
+                    __syncthreads();
+                }
+                if (block_any_twin(L, m)) {
+                    if (tid == 0) L.misc[1] |= 1ULL << rr;
+                    continue;
+                }
                 const u64 h = sparse_child<T>(s, L, P, stage + (b0 + rr) * (long long)m, ovf);
                 if (tid == 0) L.rowh[rr] = h;
             }
-        } else if (len > 1) {
-            // 6. D rows and row hashes
-            for (int q = tid; q < kTile * kKMax / 4; q += blockDim.x) ((int*)L.D)[q] = 0;
-            __syncthreads();
-            if (tid > c && tid < cend) {
-                const int row = tid;
-                u64 delta = (u64)(row - c);
-                u64 h = href;
-                for (int i = nv - 1; i >= 0 && delta != 0; --i) {
-                    const int j = L.vlist[i];
-                    const u64 w = L.om[j];
-                    const int d0 = L.dg[j];
-                    const u64 x = (u64)d0 + delta;
-                    const int d1 = (int)(x % w);
-                    delta = x / w;
-                    if (d1 != d0) {
-                        const int k1 = L.kbase[i] + d1, k0 = L.kbase[i] + d0;
-                        L.D[row * kKMax + k1] = 1;
-                        L.D[row * kKMax + k0] = -1;
-                        h += s.hM[L.klist[k1]] - s.hM[L.klist[k0]];
+        } else {
+            // 5. reference child (first of the segment) by the sparse pull
+            const u64 href = sparse_child<T>(s, L, P, refrow, ovf);
+            if (tid == 0) L.rowh[c] = href;
+            if (len == 1) {
+                if (tid == 0 && L.misc[0]) L.misc[1] |= 1ULL << c;
+            } else {
+                // 6. D rows and row hashes
+                for (int q = tid; q < kTile * kKMax / 4; q += blockDim.x) ((int*)L.D)[q] = 0;
+                __syncthreads();
+                if (wid == 0) {
+                    const u64 refnc = L.misc[0];
+                    bool tw = false;
+                    if (tid > c && tid < cend) {
+                        const int row = tid;
+                        u64 delta = (u64)(row - c);
+                        u64 h = href;
+                        int i = nv - 1;
+                        for (; i >= 0 && delta != 0; --i) {
+                            const int j = L.vlist[i];
+                            const u64 w = L.om[j];
+                            const int d0 = L.dg[j];
+                            const u64 x = (u64)d0 + delta;
+                            const int d1 = (int)(x % w);
+                            delta = x / w;
+                            tw |= later_twin(L, j, d1);
+                            if (d1 != d0) {
+                                const int k1 = L.kbase[i] + d1, k0 = L.kbase[i] + d0;
+                                L.D[row * kKMax + k1] = 1;
+                                L.D[row * kKMax + k0] = -1;
+                                h += s.hM[L.klist[k1]] - s.hM[L.klist[k0]];
+                            }
+                        }
+                        // neurons 0 .. i of V keep the reference digits
+                        if (i >= 0) tw |= (refnc & ((2ULL << i) - 1)) != 0;
+                        L.rowh[row] = h;
+                    } else if (tid == c) {
+                        tw = refnc != 0;
                     }
+                    const u64 bm = __ballot(tw);
+                    if (lane == 0) L.misc[1] |= bm;
                 }
-                L.rowh[row] = h;
-            }
-            const int kpad = (kvar + 63) & ~63;
-            // 7. column tiles: stage M_V transposed, multiply, add the reference row
-            for (int n0 = 0; n0 < m; n0 += NT) {
-                __syncthreads();
-                for (int q = tid; q < kpad * NT; q += blockDim.x) {
-                    const int k = q / NT, n = q - k * NT;
-                    int8_t v = 0;
-                    if (k < kvar && n0 + n < m) v = s.M8[(long long)L.klist[k] * m + n0 + n];
-                    L.MT[n * kMTStride + k] = v;
-                }
-                __syncthreads();
-                constexpr int CB = NT / 64;  // 16-column blocks per wave
-                v4i acc[4][CB];
-#pragma unroll
-                for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-                    for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = v4i{0, 0, 0, 0};
-                const int colw = wid * (NT / 4);
-                for (int ks = 0; ks < kpad; ks += 64) {
-                    v4i af[4], bf[CB];
+                const int kpad = (kvar + 63) & ~63;
+                // 7. column tiles: stage M_V transposed, multiply, add the reference row
+                for (int n0 = 0; n0 < m; n0 += NT) {
+                    __syncthreads();
+                    for (int q = tid; q < kpad * NT; q += blockDim.x) {
+                        const int k = q / NT, n = q - k * NT;
+                        int8_t v = 0;
+                        if (k < kvar && n0 + n < m) v = s.M8[(long long)L.klist[k] * m + n0 + n];
+                        L.MT[n * kMTStride + k] = v;
+                    }
+                    __syncthreads();
+                    const u64 twm = L.misc[1];
+                    constexpr int CB = NT / 64;  // 16-column blocks per wave
+                    v4i acc[4][CB];
 #pragma unroll
                     for (int rb = 0; rb < 4; ++rb)
-                        af[rb] = *(const v4i*)&L.D[(16 * rb + (lane & 15)) * kKMax + ks + 16 * (lane >> 4)];
 #pragma unroll
-                    for (int cb = 0; cb < CB; ++cb)
-                        bf[cb] = *(const v4i*)&L.MT[(colw + 16 * cb + (lane & 15)) * kMTStride + ks + 16 * (lane >> 4)];
+                        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = v4i{0, 0, 0, 0};
+                    const int colw = wid * (NT / 4);
+                    for (int ks = 0; ks < kpad; ks += 64) {
+                        v4i af[4], bf[CB];
 #pragma unroll
-                    for (int rb = 0; rb < 4; ++rb)
+                        for (int rb = 0; rb < 4; ++rb)
+                            af[rb] = *(const v4i*)&L.D[(16 * rb + (lane & 15)) * kKMax + ks + 16 * (lane >> 4)];
 #pragma unroll
                         for (int cb = 0; cb < CB; ++cb)
-                            acc[rb][cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[rb], bf[cb], acc[rb][cb], 0, 0, 0);
-                }
+                            bf[cb] = *(const v4i*)&L.MT[(colw + 16 * cb + (lane & 15)) * kMTStride + ks + 16 * (lane >> 4)];
 #pragma unroll
-                for (int cb = 0; cb < CB; ++cb) {
-                    const int col = n0 + colw + 16 * cb + (lane & 15);
-                    if (col >= m) continue;
-                    const long long refv = (long long)refrow[col];
+                        for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-                    for (int rb = 0; rb < 4; ++rb)
+                            for (int cb = 0; cb < CB; ++cb)
+                                acc[rb][cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[rb], bf[cb], acc[rb][cb], 0, 0, 0);
+                    }
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int row = 16 * rb + 4 * (lane >> 4) + i;
-                            if (row <= c || row >= cend) continue;
-                            const long long v = refv + acc[rb][cb][i];
-                            ovf |= (v < 0) | (v > s.count_max);
-                            stage[(b0 + row) * (long long)m + col] = (T)v;
-                        }
+                    for (int cb = 0; cb < CB; ++cb) {
+                        const int col = n0 + colw + 16 * cb + (lane & 15);
+                        if (col >= m) continue;
+                        const long long refv = (long long)refrow[col];
+#pragma unroll
+                        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                const int row = 16 * rb + 4 * (lane >> 4) + i;
+                                if (row <= c || row >= cend || ((twm >> row) & 1)) continue;
+                                const long long v = refv + acc[rb][cb][i];
+                                ovf |= (v < 0) | (v > s.count_max);
+                                stage[(b0 + row) * (long long)m + col] = (T)v;
+                            }
+                    }
                 }
             }
         }
         __syncthreads();
-        // 8. per-row outputs of the segment
+        // 8. per-row outputs of the segment; a twin row holds -1 - parent
         if (tid >= c && tid < cend) {
-            a.hash[b0 + tid] = fmix64(L.rowh[tid]) & a.hash_mask;
-            a.cpar[b0 + tid] = (int)p;
+            const bool tw = (L.misc[1] >> tid) & 1;
+            if (!tw) a.hash[b0 + tid] = fmix64(L.rowh[tid]) & a.hash_mask;
+            a.cpar[b0 + tid] = tw ? -1 - (int)p : (int)p;
             a.ct[b0 + tid] = ta + (u64)(tid - c);
         }
         // next segment: next parent with children

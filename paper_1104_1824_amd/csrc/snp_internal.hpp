@@ -67,6 +67,7 @@ struct ChunkArgs {
     u64 hash_mask;
     DevCounters* ctr;
     const u64* Tdev;       // children of the frontier prefix [0, n): the chunk stops there
+    int kmax;              // int8 form: most rule columns a segment may put on the matrix cores
 };
 
 // Insert/commit arguments.

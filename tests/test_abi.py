@@ -93,6 +93,8 @@ def test_load_rejects_bad_options():
     assert st == 1 and "max_rows" in msg
     st, msg = _load_status(synth.paper_example(), path=7)
     assert st == 1
+    st, msg = _load_status(synth.paper_example(), int8_max_k=129)
+    assert st == 1 and "int8_max_k" in msg
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

@@ -85,3 +85,25 @@ def test_int8_range_fallback(gpu, oracle_mod):
     assert all(st["int8_fallback"] == 1 and st["path_used"] == snp.SNP_PATH_SPARSE
                for st in g["level_stats"] if st["parents"])
     assert_same_bfs(g, oracle_mod.bfs(big, max_depth=5))
+
+
+@pytest.mark.parametrize("kmax", [1, 5, 16])
+def test_int8_per_child_segments(gpu, oracle_mod, kmax):
+    """Segments over int8_max_k rule columns take the per-child sparse form
+    inside the int8 kernel (twin skip included); results do not change."""
+    from tests.test_gpu_parity import twin_system
+
+    for seed in range(0, 40, 3):
+        s = synth.config_system(1, seed)
+        note(f"int8 per-child segments kmax {kmax}: tiny seed {seed}")
+        assert_same_bfs(gpu_bfs(s, max_depth=8, out_capacity=4096, chunk=4096, path=INT8, int8_max_k=kmax),
+                        oracle_mod.bfs(s, max_depth=8))
+    tw = twin_system()
+    for kw in (dict(), dict(child_budget=3), dict(frontier_cap=2, stop_at_cap=True)):
+        note(f"int8 per-child segments kmax {kmax}: twins {kw}")
+        assert_same_bfs(gpu_bfs(tw, max_depth=12, out_capacity=4096, path=INT8, int8_max_k=kmax, **kw),
+                        oracle_mod.bfs(tw, max_depth=12, **kw))
+    s = synth.config_system(3, 2)
+    note(f"int8 per-child segments kmax {kmax}: dense recipe seed 2")
+    assert_same_bfs(gpu_bfs(s, max_depth=2, frontier_cap=1500, out_capacity=4000, path=INT8, int8_max_k=kmax),
+                    oracle_mod.bfs(s, max_depth=2, frontier_cap=1500))
