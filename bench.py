@@ -189,6 +189,18 @@ def cpu_baseline(system, run_opts, budget_s=12.0):
                        f"single-threaded C oracle, {dt:.1f} s")
 
 
+def copy_calibration(nbytes=1 << 30, reps=5):
+    import torch
+
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        torch.add(src, 0, out=dst)  # one elementwise kernel: reads and writes nbytes
+    torch.cuda.synchronize()
+    log(f"copy calibration: {reps} launches, each reads {nbytes} B and writes {nbytes} B")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,7 +208,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the int8 / dense / batched side measurements")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reads 1 GiB, writes 1 GiB) five times, to scale "
+                         "FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X; --gpus must be 1", file=sys.stderr)
         sys.exit(2)

@@ -525,7 +525,8 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     std::vector<int4> rules(d->r);
     for (int k = 0; k < d->r; ++k) rules[k] = make_int4(d->rule_i[k], d->rule_j[k], d->rule_c[k], d->rule_p[k]);
     // in-synapses of every neuron (column view of the synapse part of M)
-    std::vector<int> in_ptr(d->m + 1, 0), in_src(d->n_syn), fill(d->m, 0);
+    // (one padding entry, so kernels may read in_src[0] of a system without synapses)
+    std::vector<int> in_ptr(d->m + 1, 0), in_src(std::max(1, d->n_syn), 0), fill(d->m, 0);
     for (int e = 0; e < d->n_syn; ++e) in_ptr[d->syn_dst[e] + 1]++;
     for (int n = 0; n < d->m; ++n) in_ptr[n + 1] += in_ptr[n];
     for (int e = 0; e < d->n_syn; ++e) {
@@ -549,11 +550,11 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     LOADCHK(dmalloc(&S->d_nrule_ptr, sizeof(int) * (d->m + 1)));
     LOADCHK(dmalloc(&S->d_rules, sizeof(int4) * d->r));
     LOADCHK(dmalloc(&S->d_in_ptr, sizeof(int) * (d->m + 1)));
-    LOADCHK(dmalloc(&S->d_in_src, sizeof(int) * d->n_syn));
+    LOADCHK(dmalloc(&S->d_in_src, sizeof(int) * in_src.size()));
     LOADCHK(up(S->d_nrule_ptr, nrule_ptr.data(), sizeof(int) * (d->m + 1)));
     LOADCHK(up(S->d_rules, rules.data(), sizeof(int4) * d->r));
     LOADCHK(up(S->d_in_ptr, in_ptr.data(), sizeof(int) * (d->m + 1)));
-    LOADCHK(up(S->d_in_src, in_src.data(), sizeof(int) * d->n_syn));
+    LOADCHK(up(S->d_in_src, in_src.data(), sizeof(int) * in_src.size()));
     // hash weights R[n] and the hash H of every row of M_Pi (Definition 2 rows,
     // entries sign-extended, arithmetic mod 2^64)
     std::vector<u64> R(d->m), hM(d->r);
@@ -589,8 +590,10 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     // the matrix-core form writes the row and amortises one pull over a 64-child tile
     S->sparse_work = (double)d->m + (double)d->n_syn;
     S->int8_work = (double)d->m * 1.5 + ((double)d->m + (double)d->n_syn) / 64.0;
+    int max_in = 0;
+    for (int n = 0; n < d->m; ++n) max_in = std::max(max_in, in_ptr[n + 1] - in_ptr[n]);
     S->dsys = snp::DevSystem{d->m, d->r, S->d_nrule_ptr, S->d_rules, S->d_in_ptr, S->d_in_src, d->n_syn, S->d_M8,
-                             S->count_max, S->d_R, S->d_hM};
+                             S->count_max, S->d_R, S->d_hM, max_in};
 
     S->slots = next_pow2((u64)std::max<long long>(1024, 2 * (S->max_rows + 2 * S->chunk_max)));
     LOADCHK(dmalloc(&S->d_table, sizeof(u64) * S->slots));

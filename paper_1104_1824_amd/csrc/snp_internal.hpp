@@ -50,6 +50,7 @@ struct DevSystem {
     long long count_max;
     const u64* R;          // [m] hash weights: R[n] = mix64((n + 1) * gamma)
     const u64* hM;         // [r] H of every row of M_Pi (entries sign-extended, mod 2^64)
+    int max_in;            // largest in-degree of a neuron
 };
 
 // One chunk of children [g0, g0 + B) of the frontier.

@@ -266,3 +266,39 @@ def test_twin_rules(gpu, oracle_mod, path):
         note(f"twin rules, path {path}, {kw}")
         assert_same_bfs(gpu_bfs(s, max_depth=12, out_capacity=4096, chunk=4096, path=path, **kw),
                         oracle_mod.bfs(s, max_depth=12, **kw))
+
+
+def hub_system(m=24, seed=5):
+    """Every neuron feeds neuron 0 (in-degree m - 1 > 16): small m on the
+    general expansion kernel rather than the one-neuron-per-lane kernel."""
+    base = synth.config_system(1, seed)
+    rules = []
+    for n in range(m):
+        rules.append((n, 1, 1, 1, 1))
+        if n % 3 == 0:
+            rules.append((n, 2, 1, 2, 1))
+        if n % 4 == 1:
+            rules.append((n, 1, 0, 1, 0))
+    syn = [(n, 0) for n in range(1, m)] + [(0, n) for n in range(1, m, 2)] + [(n, n + 1) for n in range(1, m - 1)]
+    c0 = [(3 * n + int(base.c0[n % base.m])) % 4 for n in range(m)]
+    return synth.make_system(m, rules, syn, c0, name="hub")
+
+
+@pytest.mark.parametrize("path", [snp.SNP_PATH_SPARSE, snp.SNP_PATH_INT8])
+def test_high_in_degree(gpu, oracle_mod, path):
+    s = hub_system()
+    for kw in (dict(frontier_cap=3000), dict(frontier_cap=500, stop_at_cap=True), dict(child_budget=777)):
+        note(f"hub system (in-degree 23), path {path}, {kw}")
+        assert_same_bfs(gpu_bfs(s, max_depth=6, out_capacity=20000, chunk=4096, path=path, **kw),
+                        oracle_mod.bfs(s, max_depth=6, **kw))
+
+
+@pytest.mark.parametrize("path", [snp.SNP_PATH_SPARSE, snp.SNP_PATH_INT8])
+def test_uint16_counts_small_m(gpu, oracle_mod, path):
+    """uint16 rows on the small-m kernels (plain-sparse recipe re-typed)."""
+    for seed in (0, 3):
+        s = synth.config_system(2, seed)
+        u = synth.make_system(s.m, s.rules(), list(zip(s.syn_src, s.syn_dst)), s.c0, count_type="u16")
+        note(f"uint16 plain sparse seed {seed}, path {path}")
+        kw = dict(max_depth=1000, frontier_cap=20000, stop_at_cap=True)
+        assert_same_bfs(gpu_bfs(u, out_capacity=60000, path=path, **kw), oracle_mod.bfs(u, **kw))
