@@ -444,26 +444,41 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
 }
 
 // ---------------------------------------------------------------------------
-// Expansion, one neuron per lane (m <= 64, in-degree <= kLaneMaxIn): the walk
-// of k_expand_sparse with the whole per-wave state in registers.  Lane j holds
-// neuron j's parent count, applicable-rule mask (canonical digits in the high
-// half), omega, digit and fired (c << 16 | p), plus the lanes of its
-// in-synapse sources; the pull reads the sources' fired (c, p) across lanes
-// (ds_bpermute), the odometer step is one ballot, and the per-child outputs
-// are gathered in lane k % 64 and stored 64 at a time.  A parent change costs
-// no memory round trip: Psi of the next 64 parents and the next parent's row
-// are fetched ahead of use.
+// Expansion, one neuron per lane (m <= 64, in-degree <= kLaneMaxIn).  Lane j
+// holds neuron j's parent count, applicable-rule mask (canonical digits in the
+// high half), omega and digit, the consumption c, production p and row hash
+// H(M_k) of its fired rule k, and the set of its in-synapse sources as a
+// 64-bit lane mask.  The child row is kept as w = C + production received
+// (so C' = w - c).  Consecutive children of one parent differ only in the
+// digits the odometer step changes (the last neuron with omega >= 2 that can
+// step up and every later neuron with omega >= 2), so the next child follows
+// from those neurons alone: a changed neuron s with production change dp adds
+// dp to every lane whose source mask holds s.  The row hash follows by
+// linearity, H(C + S.M) = H(C) + sum of H(M_k) over the fired rules k, on the
+// scalar unit.  The first child of a parent or of a run is computed in full by
+// a pull over the in-synapses (ds_bpermute).  Per-child outputs are gathered
+// in lane k % 64 and stored 64 at a time; the next parent's row and the Psi
+// of the next 64 parents are fetched ahead of use.
 // ---------------------------------------------------------------------------
 constexpr int kLaneMaxIn = 16;
 
-// Ends the wait for a loaded register here: the per-child loop then never waits
-// on the row stores it has in flight (one vector-memory counter covers both).
+// Ends the wait for a loaded register here, so that the per-child loop never
+// waits on the row stores it has in flight (one counter covers both).
 __device__ __forceinline__ void settle(int v) { asm volatile("" ::"v"(v)); }
 
-__device__ __forceinline__ uint32_t lane_fired(const int4* rules, int r0, uint32_t am, int om, int d) {
-    if (om == 0) return 0u;
-    const int4 R = rules[r0 + nth_bit(am & 0xFFFFu, d)];
-    return ((uint32_t)R.z << 16) | (uint32_t)R.w;
+// c, p and H(M_k) of the rule digit d picks (0 when no rule applies).
+__device__ __forceinline__ void lane_fired(const int4* rules, const u64* hrow, int r0, uint32_t am, int om, int d,
+                                           uint32_t& c, uint32_t& p, u64& hv) {
+    c = 0;
+    p = 0;
+    hv = 0;
+    if (om > 0) {
+        const int k = r0 + nth_bit(am & 0xFFFFu, d);
+        const int4 R = rules[k];
+        c = (uint32_t)R.z;
+        p = (uint32_t)R.w;
+        hv = hrow[k];
+    }
 }
 
 __device__ __forceinline__ void lane_applicable(const int4* rules, int r0, int r1, int x, uint32_t& am, int& om) {
@@ -478,10 +493,17 @@ __device__ __forceinline__ void lane_applicable(const int4* rules, int r0, int r
     om = w;
 }
 
+__device__ __forceinline__ u64 readlane64(u64 v, int j) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, j);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), j);
+    return ((u64)hi << 32) | lo;
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a, int run) {
+__global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     int4* l_rules = (int4*)smem;
+    u64* l_hM = (u64*)(l_rules + s.r);
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
     const int m = s.m;
@@ -494,17 +516,48 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a, i
     int e0 = s.in_ptr[jl], deg = s.in_ptr[jl + 1] - e0;
     u64 Rj = s.R[jl];
     if (!act) r0 = r1 = e0 = deg = 0, Rj = 0;
+    // The chunk ends at the children known on the device; the grid strides
+    // over runs of consecutive children, about one run per wave.
     const u64 tot = *a.Tdev;
     const long long Beff = tot > a.g0 ? (long long)min((u64)a.B, tot - a.g0) : 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctr->beff = (u64)Beff;
-    const long long b0 = ((long long)blockIdx.x * (blockDim.x >> 6) + wid) * run;
-    const bool live = b0 < Beff;  // wave-uniform
+    const long long wpb = blockDim.x >> 6;
+    const long long nwaves = (long long)gridDim.x * wpb;
+    const int run = (int)max(4LL, min(1024LL, (Beff + nwaves - 1) / nwaves));
+    const long long nruns = (Beff + run - 1) / run;
+    if ((long long)blockIdx.x * wpb >= nruns) return;  // the whole block
+    for (int q = threadIdx.x; q < s.r; q += blockDim.x) {
+        l_rules[q] = s.rules[q];
+        l_hM[q] = s.hM[q];
+    }
+    __syncthreads();
+    const long long wave0 = (long long)blockIdx.x * wpb + wid;
+    if (wave0 >= nruns) return;
 
-    // parent of the first child (64-ary search, one probe per lane per round)
-    const u64 g = a.g0 + (u64)b0;
-    long long lo = 0;
-    if (live) {
-        long long hi = a.n;
+    // in-synapse sources: ds_bpermute byte addresses and a lane mask (in_src
+    // holds at least one entry)
+    int saddr[kLaneMaxIn];
+    const int elast = max(0, s.nnz_in - 1);
+#pragma unroll
+    for (int e = 0; e < kLaneMaxIn; ++e) saddr[e] = s.in_src[min(e0 + e, elast)];
+    u64 inmask = 0;
+#pragma unroll
+    for (int e = 0; e < kLaneMaxIn; ++e) {
+        if (e < deg) inmask |= 1ULL << saddr[e];
+        saddr[e] = (e < deg) ? 4 * saddr[e] : 0;
+    }
+
+    const T* F = (const T*)a.frontier;
+    T* stage = (T*)a.stage;
+    const long long n = a.n;
+    const uint32_t cmax = (uint32_t)s.count_max;
+    bool ovf = false;
+    for (long long rw = wave0; rw < nruns; rw += nwaves) {
+        const long long b0 = rw * run;
+        const int cnt = (int)min((long long)run, Beff - b0);
+        // parent of the first child (64-ary search, one probe per lane per round)
+        const u64 g = a.g0 + (u64)b0;
+        long long lo = 0, hi = n;
         while (hi - lo > 1) {
             const long long step = (hi - lo + 63) / 64;
             const long long idx = lo + (long long)lane * step;
@@ -513,139 +566,149 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a, i
             lo = lo + (long long)(63 - __clzll((long long)mask)) * step;
             hi = min(hi, lo + step);
         }
-    }
-    for (int q = threadIdx.x; q < s.r; q += blockDim.x) l_rules[q] = s.rules[q];
-    __syncthreads();
-    if (!live) return;
 
-    // in-synapse sources as ds_bpermute byte addresses (lane 0 past the in-degree;
-    // in_src holds at least one entry)
-    int saddr[kLaneMaxIn];
-    const int elast = max(0, s.nnz_in - 1);
-#pragma unroll
-    for (int e = 0; e < kLaneMaxIn; ++e) saddr[e] = s.in_src[min(e0 + e, elast)];
-#pragma unroll
-    for (int e = 0; e < kLaneMaxIn; ++e) saddr[e] = (e < deg) ? 4 * saddr[e] : 0;
-
-    const T* F = (const T*)a.frontier;
-    T* stage = (T*)a.stage;
-    const int cnt = (int)min((long long)run, Beff - b0);
-    const long long n = a.n;
-
-    // Psi window: parents pbase .. pbase + 63; the current parent is lane cur
-    long long p = uni_ll(lo);
-    long long pbase = p;
-    int cur = 0;
-    u64 pw = a.psi[min(pbase + lane, n - 1)];
-    if (pbase + lane >= n) pw = 0;
-    u64 t = uni64(g - a.off[p]);
-    int x = (int)F[p * (long long)m + jl];
-    settle(x);
-    u64 psi_p = uni64(__shfl(pw, 0));
-    // next parent with children, and its row fetched ahead
-    long long pf_p = -1;
-    int pf_x = 0;
-    {
-        const u64 nb = __ballot(pw > 0 && lane > cur);
-        if (nb) {
-            pf_p = pbase + __builtin_ctzll(nb);
-            pf_x = (int)F[pf_p * (long long)m + jl];
-        }
-    }
-    uint32_t am;
-    int om;
-    lane_applicable(l_rules, r0, r1, x, am, om);
-    // digits of child t: place value of lane j = product of max(1, omega) over lanes after j
-    int dg = 0;
-    if (t != 0) {
-        const u64 w1 = (u64)max(1, om);
-        u64 incl = w1;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const u64 y = __shfl_down(incl, o);
-            if (lane + o < 64) incl = sat_mul(incl, y);
-        }
-        u64 after = __shfl_down(incl, 1);
-        if (lane == 63) after = 1;
-        dg = (after > t) ? 0 : (int)((t / after) % w1);
-    }
-    uint32_t cp = lane_fired(l_rules, r0, am, om, dg);
-
-    u64 o_hash = 0, o_ct = 0;
-    int o_par = 0;
-    bool ovf = false;
-    for (int k = 0; k < cnt; ++k) {
-        const long long b = b0 + k;
-        const bool twin = __ballot(act && om >= 2 && !((am >> (16 + dg)) & 1u)) != 0;
-        u64 h = 0;
-        if (!twin) {
-            long long v = (long long)x - (long long)(cp >> 16);
-#pragma unroll
-            for (int e = 0; e < kLaneMaxIn; ++e) {
-                if (e < kin) {
-                    const uint32_t y = (uint32_t)__builtin_amdgcn_ds_bpermute(saddr[e], (int)cp);
-                    if (e < deg) v += y & 0xFFFFu;
-                }
-            }
-            if (act) {
-                ovf |= (v < 0) | (v > s.count_max);
-                stage[b * m + lane] = (T)v;
-                h = hterm((uint32_t)v, Rj);
-            }
-            h = wave_sum_u64(h);
-        }
-        if (lane == (k & 63)) {
-            o_hash = fmix64(h) & a.hash_mask;
-            o_par = twin ? -1 - (int)p : (int)p;
-            o_ct = t;
-        }
-        if ((k & 63) == 63 || k + 1 == cnt) {
-            const long long bb = b0 + (k & ~63) + lane;
-            if (lane <= (k & 63)) {
-                a.hash[bb] = o_hash;
-                a.cpar[bb] = o_par;
-                a.ct[bb] = o_ct;
-            }
-        }
-        if (k + 1 == cnt) break;
-        ++t;
-        if (t < psi_p) {
-            // odometer: the last neuron with a digit below omega - 1 steps up,
-            // every later neuron with omega >= 2 resets
-            const u64 bm = __ballot(act && om >= 2 && dg < om - 1);
-            const int J = bm ? 63 - __clzll((long long)bm) : 64;
-            if (lane >= J && om >= 2) {
-                dg = (lane == J) ? dg + 1 : 0;
-                cp = lane_fired(l_rules, r0, am, om, dg);
-            }
-        } else {
-            // next parent with Psi > 0
-            u64 nb = __ballot(pw > 0 && lane > cur);
-            while (nb == 0) {
-                pbase += 64;
-                if (pbase >= n) break;
-                pw = a.psi[min(pbase + lane, n - 1)];
-                if (pbase + lane >= n) pw = 0;
-                cur = -1;
-                nb = __ballot(pw > 0);
-            }
-            if (nb == 0) break;  // unreachable while g0 + B <= sum of Psi
-            cur = __builtin_ctzll(nb);
-            p = pbase + cur;
-            psi_p = uni64(__shfl(pw, cur));
-            t = 0;
-            if (p == pf_p) x = pf_x;
-            else x = (int)F[p * (long long)m + jl];
-            settle(x);
-            const u64 nb2 = __ballot(pw > 0 && lane > cur);
-            pf_p = -1;
-            if (nb2) {
-                pf_p = pbase + __builtin_ctzll(nb2);
+        // Psi window: parents pbase .. pbase + 63; the current parent is lane cur
+        long long p = uni_ll(lo);
+        long long pbase = p;
+        int cur = 0;
+        u64 pw = a.psi[min(pbase + lane, n - 1)];
+        if (pbase + lane >= n) pw = 0;
+        u64 t = uni64(g - a.off[p]);
+        int x = (int)F[p * (long long)m + jl];
+        settle(x);
+        u64 psi_p = uni64(__shfl(pw, 0));
+        // next parent with children, and its row fetched ahead
+        long long pf_p = -1;
+        int pf_x = 0;
+        {
+            const u64 nb = __ballot(pw > 0 && lane > cur);
+            if (nb) {
+                pf_p = pbase + __builtin_ctzll(nb);
                 pf_x = (int)F[pf_p * (long long)m + jl];
             }
-            lane_applicable(l_rules, r0, r1, x, am, om);
-            dg = 0;
-            cp = lane_fired(l_rules, r0, am, om, 0);
+        }
+        uint32_t am;
+        int om;
+        lane_applicable(l_rules, r0, r1, x, am, om);
+        // digits of child t: place value of lane j = product of max(1, omega) over later lanes
+        int dg = 0;
+        if (t != 0) {
+            const u64 w1 = (u64)max(1, om);
+            u64 incl = w1;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const u64 y = __shfl_down(incl, o);
+                if (lane + o < 64) incl = sat_mul(incl, y);
+            }
+            u64 after = __shfl_down(incl, 1);
+            if (lane == 63) after = 1;
+            dg = (after > t) ? 0 : (int)((t / after) % w1);
+        }
+        uint32_t c, pp;
+        u64 hv;
+        lane_fired(l_rules, l_hM, r0, am, om, dg, c, pp, hv);
+        // the child in full: w = C + production received; H by linearity
+        uint32_t wv = (uint32_t)x;
+#pragma unroll
+        for (int e = 0; e < kLaneMaxIn; ++e) {
+            if (e < kin) {
+                const uint32_t y = (uint32_t)__builtin_amdgcn_ds_bpermute(saddr[e], (int)pp);
+                if (e < deg) wv += y;
+            }
+        }
+        u64 Hs = wave_sum_u64(act ? (u64)(uint32_t)x * Rj + hv : 0);
+        u64 v2 = __ballot(act && om >= 2);
+
+        u64 o_hash = 0, o_ct = 0;
+        int o_par = 0;
+        for (int k = 0; k < cnt; ++k) {
+            const long long b = b0 + k;
+            const bool twin = __ballot(act && om >= 2 && !((am >> (16 + dg)) & 1u)) != 0;
+            if (!twin && act) {
+                const uint32_t v = wv - c;
+                ovf |= (wv < c) | (v > cmax);
+                stage[b * m + lane] = (T)v;
+            }
+            if (lane == (k & 63)) {
+                o_hash = fmix64(Hs) & a.hash_mask;
+                o_par = twin ? -1 - (int)p : (int)p;
+                o_ct = t;
+            }
+            if ((k & 63) == 63 || k + 1 == cnt) {
+                const long long bb = b0 + (k & ~63) + lane;
+                if (lane <= (k & 63)) {
+                    a.hash[bb] = o_hash;
+                    a.cpar[bb] = o_par;
+                    a.ct[bb] = o_ct;
+                }
+            }
+            if (k + 1 == cnt) break;
+            ++t;
+            if (t < psi_p) {
+                // odometer: lane J (the last that can step up) steps up, every
+                // later lane with omega >= 2 resets to 0
+                const u64 bm = __ballot(act && om >= 2 && dg < om - 1);
+                if (bm == 0) break;  // unreachable while t < Psi
+                const int J = 63 - __clzll((long long)bm);
+                const u64 chg = (1ULL << J) | (v2 & ~((2ULL << J) - 1));
+                uint32_t dp = 0;
+                u64 dh = 0;
+                if ((chg >> lane) & 1) {
+                    dg = (lane == J) ? dg + 1 : 0;
+                    uint32_t c2, p2;
+                    u64 h2;
+                    lane_fired(l_rules, l_hM, r0, am, om, dg, c2, p2, h2);
+                    dp = p2 - pp;
+                    dh = h2 - hv;
+                    c = c2;
+                    pp = p2;
+                    hv = h2;
+                }
+                for (u64 q = chg; q; q &= q - 1) {
+                    const int j = __builtin_ctzll(q);
+                    Hs += readlane64(dh, j);
+                    const uint32_t dpj = __builtin_amdgcn_readlane(dp, j);
+                    if (dpj != 0 && ((inmask >> j) & 1)) wv += dpj;
+                }
+            } else {
+                // next parent with Psi > 0
+                u64 nb = __ballot(pw > 0 && lane > cur);
+                while (nb == 0) {
+                    pbase += 64;
+                    if (pbase >= n) break;
+                    pw = a.psi[min(pbase + lane, n - 1)];
+                    if (pbase + lane >= n) pw = 0;
+                    cur = -1;
+                    nb = __ballot(pw > 0);
+                }
+                if (nb == 0) break;  // unreachable while g0 + B <= sum of Psi
+                cur = __builtin_ctzll(nb);
+                p = pbase + cur;
+                psi_p = uni64(__shfl(pw, cur));
+                t = 0;
+                if (p == pf_p) x = pf_x;
+                else x = (int)F[p * (long long)m + jl];
+                settle(x);
+                const u64 nb2 = __ballot(pw > 0 && lane > cur);
+                pf_p = -1;
+                if (nb2) {
+                    pf_p = pbase + __builtin_ctzll(nb2);
+                    pf_x = (int)F[pf_p * (long long)m + jl];
+                }
+                lane_applicable(l_rules, r0, r1, x, am, om);
+                dg = 0;
+                lane_fired(l_rules, l_hM, r0, am, om, 0, c, pp, hv);
+                wv = (uint32_t)x;
+#pragma unroll
+                for (int e = 0; e < kLaneMaxIn; ++e) {
+                    if (e < kin) {
+                        const uint32_t y = (uint32_t)__builtin_amdgcn_ds_bpermute(saddr[e], (int)pp);
+                        if (e < deg) wv += y;
+                    }
+                }
+                Hs = wave_sum_u64(act ? (u64)(uint32_t)x * Rj + hv : 0);
+                v2 = __ballot(act && om >= 2);
+            }
         }
     }
     if (__any(ovf) && lane == 0) atomicOr((unsigned long long*)&a.ctr->overflow, 1ULL);
@@ -653,14 +716,14 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a, i
 
 hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st) {
     if (a.B <= 0) return hipSuccess;
-    if (s.m <= 64 && s.max_in <= kLaneMaxIn && (size_t)s.r * 16 <= 48 * 1024) {
-        // about two waves per SIMD slot of the GPU, 4 to 64 children each
-        const int run = (int)std::max<long long>(4, std::min<long long>(64, (a.B + 16383) / 16384));
-        const long long waves = (a.B + run - 1) / run;
+    if (s.m <= 64 && s.max_in <= kLaneMaxIn && (size_t)s.r * 24 <= 48 * 1024) {
+        // at most one wave per SIMD slot of the GPU; runs of 4 to 64 children
+        // are handed out on the device, where the chunk's true size is known
+        const long long waves = std::min<long long>((a.B + 3) / 4, 8192);
         const unsigned blocks = (unsigned)((waves + 3) / 4);
-        const size_t lds = (size_t)std::max(1, s.r) * 16;
-        if (elem_bytes == 4) hipLaunchKernelGGL((k_expand_lane<int32_t>), dim3(blocks), dim3(256), lds, st, s, a, run);
-        else hipLaunchKernelGGL((k_expand_lane<uint16_t>), dim3(blocks), dim3(256), lds, st, s, a, run);
+        const size_t lds = (size_t)std::max(1, s.r) * 24;
+        if (elem_bytes == 4) hipLaunchKernelGGL((k_expand_lane<int32_t>), dim3(blocks), dim3(256), lds, st, s, a);
+        else hipLaunchKernelGGL((k_expand_lane<uint16_t>), dim3(blocks), dim3(256), lds, st, s, a);
         return hipGetLastError();
     }
     const int stride = ((kLdsBytesPerNeuron * s.m) + 15) & ~15;
