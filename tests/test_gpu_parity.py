@@ -302,3 +302,14 @@ def test_uint16_counts_small_m(gpu, oracle_mod, path):
         note(f"uint16 plain sparse seed {seed}, path {path}")
         kw = dict(max_depth=1000, frontier_cap=20000, stop_at_cap=True)
         assert_same_bfs(gpu_bfs(u, out_capacity=60000, path=path, **kw), oracle_mod.bfs(u, **kw))
+
+
+@pytest.mark.parametrize("path", [snp.SNP_PATH_SPARSE, snp.SNP_PATH_INT8])
+def test_halting_counts_after_cut(gpu, oracle_mod, path):
+    """Levels cut by the cap with halting parents past the cut: the halting
+    statistic counts parents up to the last enumerated child's parent."""
+    for seed in (49, 93, 97):
+        s = synth.config_system(1, seed)
+        note(f"halting after cut: tiny seed {seed}, path {path}")
+        assert_same_bfs(gpu_bfs(s, max_depth=8, out_capacity=256, chunk=4096, path=path, frontier_cap=3),
+                        oracle_mod.bfs(s, max_depth=8, frontier_cap=3))

@@ -280,6 +280,58 @@ def test_cap_truncation_definition(oracle_mod, seed, cap):
         frontier = list(res.level(k))
 
 
+def _halting_by_regex(sys, C):
+    """No rule applies anywhere (applicability by Python's regex engine)."""
+    for k in range(sys.r):
+        i, j, c = int(sys.rule_i[k]), int(sys.rule_j[k]), int(sys.rule_c[k])
+        pat = f"a{{{i}}}" if j == 0 else f"a{{{i}}}(?:a{{{j}}})*"
+        n = int(C[int(sys.rule_neuron[k])])
+        if n >= c and re.fullmatch(pat, "a" * n):
+            return False
+    return True
+
+
+# seeds 49, 93 and 97 with cap 3 have halting parents after a level's cut,
+# where "up to the last enumerated child's parent" differs from "all parents"
+@pytest.mark.parametrize("seed,kw", [(3, dict(frontier_cap=2)), (8, dict(frontier_cap=3)), (19, dict(child_budget=4)),
+                                     (27, dict(child_budget=3, frontier_cap=2)), (33, dict()), (54, dict(frontier_cap=1)),
+                                     (49, dict(frontier_cap=3)), (93, dict(frontier_cap=3)), (97, dict(frontier_cap=3))])
+def test_level_statistics_definition(oracle_mod, seed, kw):
+    """Per expanded level: `enumerated` counts children in canonical order up to
+    where the level stopped (the cap-filling child, the budget, or all), and
+    `halting` counts parents without an applicable rule up to the parent of the
+    last child enumerated (every parent when the level ran to its end)."""
+    sys = synth.config_system(1, seed)
+    res = oracle_mod.bfs(sys, max_depth=8, **kw)
+    cap, budget = kw.get("frontier_cap", 0), kw.get("child_budget", 0)
+    recorded = {tuple(res.rows[0].tolist())}
+    for k in range(res.n_levels):
+        if res.enumerated[k] == 0 and res.halting[k] == 0:
+            continue
+        frontier = res.level(k)
+        enumerated, new, last_par, cut = 0, [], -1, False
+        for q, par in enumerate(frontier):
+            rows, _, _ = oracle_mod.children(sys, par)
+            for x in rows.tolist():
+                if budget and enumerated == budget:
+                    cut = True
+                    break
+                enumerated += 1
+                last_par = q
+                if tuple(x) not in recorded and x not in new:
+                    new.append(x)
+                    if cap and len(new) == cap:
+                        cut = True
+                        break
+            if cut:
+                break
+        p_end = last_par + 1 if cut else len(frontier)
+        halting = sum(_halting_by_regex(sys, frontier[q]) for q in range(p_end))
+        assert int(res.enumerated[k]) == enumerated, (k, enumerated)
+        assert int(res.halting[k]) == halting, (k, halting)
+        recorded |= {tuple(x) for x in new}
+
+
 def test_budget_stops_level(oracle_mod):
     res = oracle_mod.bfs(EX, child_budget=1)
     assert [cfg(x) for x in res.rows] == ["2-1-1", "2-1-2"]
