@@ -239,8 +239,12 @@ typedef struct snp_batch snp_batch; /* opaque; owns the packed tables of all sys
 
 /* Load n >= 1 systems (host descriptions, copied).  All must share one
  * count_type.  Limits of this mode: m <= 4096, and i, j, c, p <= 255.
- * opt: NULL or options whose stream is used (other fields are ignored).
- * Errors: SNP_ERR_INVALID (as snp_load, plus the limits above), SNP_ERR_DEVICE. */
+ * opt: NULL or options; used are `stream`, and `chunk`, which here fixes the
+ *   threads per system (256, 512 or 1024; each thread owns up to 4 neurons).
+ *   chunk = 0: the first snp_batch_run times every fitting shape on a short
+ *   run of the batch and keeps the fastest.  Other fields are ignored.
+ * Errors: SNP_ERR_INVALID (as snp_load, plus the limits above, or a `chunk`
+ *   that does not fit), SNP_ERR_DEVICE. */
 snp_status snp_batch_load(const snp_desc *descs, int32_t n, const snp_options *opt, snp_batch **out);
 
 void snp_batch_free(snp_batch *b);
@@ -250,7 +254,13 @@ void snp_batch_free(snp_batch *b);
  * [offsets[k], offsets[k+1]).  offsets: host int64 [n + 1]. */
 snp_status snp_batch_offsets(const snp_batch *b, int64_t *offsets);
 
-/* Run every system from its C0 for at most `steps` steps in one launch.
+/* Launch shape in use: threads per system and neurons per thread (both 0
+ * before the first snp_batch_run picks them).  Outputs: host int32. */
+snp_status snp_batch_shape(const snp_batch *b, int32_t *threads, int32_t *neurons_per_thread);
+
+/* Run every system from its C0 for at most `steps` steps in one launch.  The
+ * launch is recorded once as a HIP graph and replayed while c0_dev,
+ * final_dev, steps and detect_repeats stay the same.
  *   c0_dev: device pointer, packed rows (offsets above).
  *   final_dev: device pointer, packed rows: the configuration after the last
  *     computed step (the halting one if the system halted).

@@ -126,14 +126,17 @@ struct snp_system {
 };
 
 struct snp_batch {
-    int n = 0, elem_bytes = 4, m_max = 0, r_max = 0, npt = 1;
+    int n = 0, elem_bytes = 4, m_max = 0, r_max = 0;
+    // launch shape: threads per system and neurons per thread (0: not tuned yet)
+    int threads = 0, npt = 0, forced_threads = 0;
+    std::vector<std::pair<int, int>> shapes;  // candidates (threads, npt)
     long long count_max = INT_MAX;
     hipStream_t stream = nullptr;
     std::vector<snp::BatchSys> sys;
     std::vector<long long> row_off;  // n + 1
     snp::BatchSys* d_sys = nullptr;
     uint32_t* d_rules = nullptr;
-    int *d_nrp = nullptr, *d_out_ptr = nullptr, *d_out_dst = nullptr;
+    int *d_nrp = nullptr, *d_in_ptr = nullptr, *d_in_src = nullptr;
     // per-run buffers, grown on demand
     int cap_steps = -1;
     void* d_ckpt = nullptr;
@@ -142,8 +145,21 @@ struct snp_batch {
     u64 table_slots = 0;
     int *d_halt = nullptr, *d_rep = nullptr, *d_done = nullptr;
     u64 *d_digest = nullptr, *d_err = nullptr;
+    // the run's launches (fill + kernel) as a graph, replayed while the key matches
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+    struct Key {
+        const void *c0, *fin;
+        int steps, detect, threads, npt, cap_steps;
+        bool operator==(const Key& o) const {
+            return c0 == o.c0 && fin == o.fin && steps == o.steps && detect == o.detect && threads == o.threads &&
+                   npt == o.npt && cap_steps == o.cap_steps;
+        }
+    } key{};
     ~snp_batch() {
-        void* ptrs[] = {d_sys, d_rules, d_nrp, d_out_ptr, d_out_dst, d_ckpt, d_hkey, d_hstep,
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        void* ptrs[] = {d_sys, d_rules, d_nrp, d_in_ptr, d_in_src, d_ckpt, d_hkey, d_hstep,
                         d_halt, d_rep, d_done, d_digest, d_err};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
@@ -741,16 +757,16 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
     std::vector<snp::BatchSys> sys(n);
     std::vector<long long> row_off(n + 1, 0);
     std::vector<uint32_t> rules;
-    std::vector<int> nrp, out_ptr, out_dst;
+    std::vector<int> nrp, in_ptr, in_src;
     int m_max = 0, r_max = 0;
     for (int k = 0; k < n; ++k) {
         const snp_desc* d = &descs[k];
         snp_status st = validate(d);
         if (st) return fail(st, "system %d: %s", k, g_err.c_str());
         if (d->count_type != ct) return fail(SNP_ERR_INVALID, "system %d: all systems must share count_type", k);
-        if (d->m > 4 * snp::batch_threads())
+        if (d->m > 4 * snp::batch_max_threads())
             return fail(SNP_ERR_INVALID, "system %d: m above %d is not supported in batched mode", k,
-                        4 * snp::batch_threads());
+                        4 * snp::batch_max_threads());
         for (int q = 0; q < d->r; ++q)
             if (d->rule_i[q] > 255 || d->rule_j[q] > 255 || d->rule_c[q] > 255 || d->rule_p[q] > 255)
                 return fail(SNP_ERR_INVALID, "system %d rule %d: batched mode needs i, j, c, p <= 255", k, q);
@@ -761,37 +777,55 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
         row_off[k + 1] = row_off[k] + d->m;
         B.rule_off = (int)rules.size();
         B.nrp_off = (int)nrp.size();
-        B.out_off = (int)out_dst.size();
+        B.in_off = (int)in_src.size();
         for (int q = 0; q < d->r; ++q)
             rules.push_back((uint32_t)d->rule_i[q] | ((uint32_t)d->rule_j[q] << 8) | ((uint32_t)d->rule_c[q] << 16) |
                             ((uint32_t)d->rule_p[q] << 24));
-        std::vector<int> cnt(d->m + 1, 0), ocnt(d->m + 1, 0);
+        std::vector<int> cnt(d->m + 1, 0), icnt(d->m + 1, 0);
         for (int q = 0; q < d->r; ++q) cnt[d->rule_neuron[q] + 1]++;
-        for (int e = 0; e < d->n_syn; ++e) ocnt[d->syn_src[e] + 1]++;
+        for (int e = 0; e < d->n_syn; ++e) icnt[d->syn_dst[e] + 1]++;
         for (int j = 0; j < d->m; ++j) {
             cnt[j + 1] += cnt[j];
-            ocnt[j + 1] += ocnt[j];
+            icnt[j + 1] += icnt[j];
         }
-        std::vector<int> dst(d->n_syn), fill(d->m, 0);
+        std::vector<int> src(d->n_syn), fill(d->m, 0);
         for (int e = 0; e < d->n_syn; ++e) {
-            const int src = d->syn_src[e];
-            dst[ocnt[src] + fill[src]++] = d->syn_dst[e];
+            const int dst = d->syn_dst[e];
+            src[icnt[dst] + fill[dst]++] = d->syn_src[e];
         }
         nrp.insert(nrp.end(), cnt.begin(), cnt.end());
-        out_ptr.insert(out_ptr.end(), ocnt.begin(), ocnt.end());
-        out_dst.insert(out_dst.end(), dst.begin(), dst.end());
+        in_ptr.insert(in_ptr.end(), icnt.begin(), icnt.end());
+        in_src.insert(in_src.end(), src.begin(), src.end());
         m_max = std::max(m_max, d->m);
         r_max = std::max(r_max, d->r);
     }
-    if (snp::batch_lds_bytes(m_max, r_max) > 64 * 1024)
+    // launch shapes: threads per system and neurons per thread (1, 2 or 4)
+    std::vector<std::pair<int, int>> shapes;
+    for (int th : {256, 512, 1024}) {
+        int npt = (m_max + th - 1) / th;
+        npt = npt <= 1 ? 1 : (npt <= 2 ? 2 : (npt <= 4 ? 4 : 0));
+        if (npt && snp::batch_lds_bytes(m_max, r_max, th) <= 64 * 1024) shapes.push_back({th, npt});
+    }
+    const int forced = opt ? (int)opt->chunk : 0;
+    if (forced) {
+        std::vector<std::pair<int, int>> keep;
+        for (auto& sh : shapes)
+            if (sh.first == forced) keep.push_back(sh);
+        if (keep.empty())
+            return fail(SNP_ERR_INVALID, "batched mode: %d threads per system do not fit this batch "
+                        "(use 256, 512 or 1024, with m <= 4 x threads)", forced);
+        shapes = keep;
+    }
+    if (shapes.empty())
         return fail(SNP_ERR_INVALID, "batched mode: the largest system needs more than 64 KiB of LDS");
     snp_batch* b = new snp_batch();
+    b->shapes = shapes;
+    b->forced_threads = forced;
     b->n = n;
     b->elem_bytes = ct == SNP_COUNT_U16 ? 2 : 4;
     b->count_max = ct == SNP_COUNT_U16 ? 65535 : INT_MAX;
     b->m_max = m_max;
     b->r_max = r_max;
-    b->npt = m_max <= snp::batch_threads() ? 1 : (m_max <= 2 * snp::batch_threads() ? 2 : 4);
     b->stream = opt ? (hipStream_t)opt->stream : nullptr;
     b->sys = sys;
     b->row_off = row_off;
@@ -806,8 +840,8 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
     BLOADCHK(dmalloc(&b->d_sys, sizeof(snp::BatchSys) * n));
     BLOADCHK(dmalloc(&b->d_rules, sizeof(uint32_t) * rules.size()));
     BLOADCHK(dmalloc(&b->d_nrp, sizeof(int) * nrp.size()));
-    BLOADCHK(dmalloc(&b->d_out_ptr, sizeof(int) * out_ptr.size()));
-    BLOADCHK(dmalloc(&b->d_out_dst, sizeof(int) * out_dst.size()));
+    BLOADCHK(dmalloc(&b->d_in_ptr, sizeof(int) * in_ptr.size()));
+    BLOADCHK(dmalloc(&b->d_in_src, sizeof(int) * std::max<size_t>(1, in_src.size())));
     BLOADCHK(dmalloc(&b->d_halt, sizeof(int) * n));
     BLOADCHK(dmalloc(&b->d_rep, sizeof(int) * n));
     BLOADCHK(dmalloc(&b->d_done, sizeof(int) * n));
@@ -815,9 +849,10 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
     BLOADCHK(dmalloc(&b->d_err, sizeof(u64) * n));
     if (!rules.empty()) BLOADCHK(hipMemcpy(b->d_rules, rules.data(), sizeof(uint32_t) * rules.size(), hipMemcpyHostToDevice));
     BLOADCHK(hipMemcpy(b->d_nrp, nrp.data(), sizeof(int) * nrp.size(), hipMemcpyHostToDevice));
-    BLOADCHK(hipMemcpy(b->d_out_ptr, out_ptr.data(), sizeof(int) * out_ptr.size(), hipMemcpyHostToDevice));
-    if (!out_dst.empty())
-        BLOADCHK(hipMemcpy(b->d_out_dst, out_dst.data(), sizeof(int) * out_dst.size(), hipMemcpyHostToDevice));
+    BLOADCHK(hipMemcpy(b->d_in_ptr, in_ptr.data(), sizeof(int) * in_ptr.size(), hipMemcpyHostToDevice));
+    if (!in_src.empty())
+        BLOADCHK(hipMemcpy(b->d_in_src, in_src.data(), sizeof(int) * in_src.size(), hipMemcpyHostToDevice));
+    BLOADCHK(hipStreamCreate(&b->cap_stream));
 #undef BLOADCHK
     *out = b;
     return SNP_OK;
@@ -829,6 +864,14 @@ snp_status snp_batch_offsets(const snp_batch* b, int64_t* offsets) {
     g_err.clear();
     if (!b || !offsets) return fail(SNP_ERR_INVALID, "batch and offsets are required");
     for (int k = 0; k <= b->n; ++k) offsets[k] = b->row_off[k];
+    return SNP_OK;
+}
+
+snp_status snp_batch_shape(const snp_batch* b, int32_t* threads, int32_t* neurons_per_thread) {
+    g_err.clear();
+    if (!b || !threads || !neurons_per_thread) return fail(SNP_ERR_INVALID, "batch and outputs are required");
+    *threads = b->threads;
+    *neurons_per_thread = b->npt;
     return SNP_OK;
 }
 
@@ -862,12 +905,68 @@ snp_status snp_batch_run(snp_batch* b, const void* c0_dev, int32_t steps, int32_
         HIPCHK(hipMemcpy(b->d_sys, b->sys.data(), sizeof(snp::BatchSys) * b->n, hipMemcpyHostToDevice));
         b->cap_steps = steps;
     }
-    if (detect_repeats)
-        HIPCHK(snp::launch_fill_i32(b->d_hstep, (long long)b->table_slots * b->n, -1, b->stream));
-    snp::BatchArgs a{b->d_sys, b->d_rules, b->d_nrp, b->d_out_ptr, b->d_out_dst, c0_dev, final_dev, b->d_ckpt,
+    snp::BatchArgs a{b->d_sys, b->d_rules, b->d_nrp, b->d_in_ptr, b->d_in_src, c0_dev, final_dev, b->d_ckpt,
                      b->d_hkey, b->d_hstep, b->table_slots, b->m_max, b->r_max, steps, detect_repeats ? 1 : 0,
                      b->count_max, b->d_halt, b->d_rep, b->d_done, b->d_digest, b->d_err};
-    HIPCHK(snp::launch_batch_det(b->elem_bytes, b->npt, a, b->n, b->stream));
+    auto enqueue = [&](hipStream_t st, int threads, int npt) -> hipError_t {
+        if (detect_repeats) {
+            const hipError_t e = snp::launch_fill_i32(b->d_hstep, (long long)b->table_slots * b->n, -1, st);
+            if (e != hipSuccess) return e;
+        }
+        return snp::launch_batch_det(b->elem_bytes, threads, npt, a, b->n, st);
+    };
+    if (!b->threads) {
+        // tune once per batch: time every candidate shape on a short run of this batch
+        if (b->shapes.size() == 1) {
+            b->threads = b->shapes[0].first;
+            b->npt = b->shapes[0].second;
+        } else {
+            hipEvent_t e0, e1;
+            HIPCHK(hipEventCreate(&e0));
+            HIPCHK(hipEventCreate(&e1));
+            snp::BatchArgs trial = a;
+            trial.steps = std::min(steps, 2 * interval);
+            float best = 0.f;
+            hipError_t err = hipSuccess;
+            for (auto& sh : b->shapes) {
+                float ms = 0.f;
+                const snp::BatchArgs keep = a;
+                a = trial;
+                err = enqueue(b->stream, sh.first, sh.second);  // warm-up
+                if (err == hipSuccess) err = hipEventRecord(e0, b->stream);
+                if (err == hipSuccess) err = enqueue(b->stream, sh.first, sh.second);
+                if (err == hipSuccess) err = hipEventRecord(e1, b->stream);
+                if (err == hipSuccess) err = hipEventSynchronize(e1);
+                if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+                a = keep;
+                if (err != hipSuccess) break;
+                if (!b->threads || ms < best) {
+                    best = ms;
+                    b->threads = sh.first;
+                    b->npt = sh.second;
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            HIPCHK(err);
+        }
+    }
+    const snp_batch::Key key{c0_dev, final_dev, steps, detect_repeats ? 1 : 0, b->threads, b->npt, b->cap_steps};
+    if (!b->exec || !(key == b->key)) {
+        if (b->exec) HIPCHK(hipGraphExecDestroy(b->exec));
+        b->exec = nullptr;
+        hipGraph_t graph = nullptr;
+        HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+        const hipError_t le = enqueue(b->cap_stream, b->threads, b->npt);
+        const hipError_t ce = hipStreamEndCapture(b->cap_stream, &graph);
+        HIPCHK(le);
+        HIPCHK(ce);
+        const hipError_t ie = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(ie);
+        b->key = key;
+    }
+    HIPCHK(hipGraphLaunch(b->exec, b->stream));
     std::vector<u64> err(b->n);
     HIPCHK(hipMemcpyAsync(halt_step, b->d_halt, sizeof(int) * b->n, hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipMemcpyAsync(first_repeat, b->d_rep, sizeof(int) * b->n, hipMemcpyDeviceToHost, b->stream));

@@ -4,34 +4,34 @@
 // clock; the first of Algorithm 2's spiking vectors), C_{k+1} = C_k + S_k.M
 // (Equation next-config), until the step limit or a halting configuration.
 //
-// One workgroup of 1024 threads runs one system; thread t owns neurons
-// t, t + 1024, ... (NPT per thread).  Counts, rule ranges and the first
-// kOutReg out-synapses of every owned neuron live in registers; the block
-// shares the packed rule table and double-buffered spike accumulators in LDS.
-// A step: pick the fired rule, add p into the accumulator of every target (LDS
-// atomics), one barrier (which also tells whether any neuron fired), then
-// C' = C - c + received and the accumulator entry is cleared.  Step k uses
-// buffer k & 1, so the barrier of step k+1 separates step k's reads from step
-// k+2's adds into the same buffer.
+// One workgroup of TPB threads runs one system; thread t owns neurons
+// t, t + TPB, ... (NPT per thread).  Counts, rule ranges and the first kInReg
+// in-synapse sources of every owned neuron live in registers; the block shares
+// the packed rule table and double-buffered production words in LDS.  A step:
+// every neuron writes the production p of its fired rule (0: none), one
+// barrier (which also tells whether any neuron fired), then every neuron pulls
+// C' = C - c + sum of p over its in-synapses.  Step k uses buffer k & 1, so
+// the barrier of step k+1 separates step k's reads from step k+2's writes.
+// TPB and NPT are picked per batch by timing the candidates (host side).
 //
 // Trajectory checksum: H(C) = sum_n C[n] * R_n (mod 2^64) with R_n the
-// SplitMix64 stream (seed 0); digest = sum_k mix64(H(C_k) + k * gamma).
-// First repeat: every kBatch steps the block stores a checkpoint row and looks
-// the batch's H values up in a per-system open-addressing set of earlier H
-// values (and within the batch); a candidate pair (l, k) is confirmed by
-// re-simulating C_l and C_k from their checkpoints and comparing the rows.  A
-// candidate whose rows differ (two configurations with one 64-bit H) is
-// reported as an error, never guessed.
+// SplitMix64 stream (seed 0); digest = sum_k mix64(H(C_k) + k * gamma).  Each
+// step leaves one partial sum per wave in LDS; the block adds them up once
+// every kBatch steps.  First repeat: at those boundaries the block stores a
+// checkpoint row and looks the batch's H values up in a per-system
+// open-addressing set of earlier H values (and within the batch); a candidate
+// pair (l, k) is confirmed by re-simulating C_l and C_k from their
+// checkpoints and comparing the rows.  A candidate whose rows differ (two
+// configurations with one 64-bit H) is reported as an error, never guessed.
 #include "snp_internal.hpp"
 
 namespace snp {
 
 namespace {
 
-constexpr int kThreads = 1024;
-constexpr int kWaves = kThreads / 64;
-constexpr int kOutReg = 32;  // out-synapses per neuron held in registers
-constexpr int kBatch = 64;   // steps between checkpoints / repeat checks
+constexpr int kInReg = 32;     // in-synapses per neuron held in registers
+constexpr int kBatch = 64;     // steps between checkpoints / repeat checks
+constexpr int kMaxThreads = 1024;
 constexpr u64 kGamma = 0x9E3779B97F4A7C15ULL;
 
 __device__ __forceinline__ u64 mix64(u64 z) {
@@ -74,17 +74,17 @@ template <int NPT>
 struct Neurons {
     int cnt[NPT];          // current spike count
     int rs[NPT], rn[NPT];  // rules: lrules[rs .. rs + rn)
-    int os[NPT], on[NPT];  // out-synapses: out_dst[os .. os + on)
-    uint32_t reg_out[NPT][kOutReg / 2];  // first kOutReg targets, two u16 per word
+    int is[NPT], in[NPT];  // in-synapse sources: in_src[is .. is + in)
+    uint32_t reg_in[NPT][kInReg / 2];  // first kInReg sources, two u16 per word
     u64 R[NPT];            // H weights
     bool valid[NPT];
 };
 
-// One step of the deterministic branch on accumulator buffer acc.  Returns
-// (block-wide) whether any neuron fired; when none fired nothing changes.
-template <int NPT>
-__device__ __forceinline__ bool det_step(Neurons<NPT>& N, const uint32_t* lrules, int* acc,
-                                         const int* __restrict__ out_dst, long long count_max, bool& ovf) {
+// One step of the deterministic branch; prod is this step's production buffer.
+// Returns (block-wide) whether any neuron fired; when none fired nothing changes.
+template <int TPB, int NPT>
+__device__ __forceinline__ bool det_step(Neurons<NPT>& N, const uint32_t* lrules, int* prod,
+                                         const int* __restrict__ in_src, long long count_max, bool& ovf) {
     int fc[NPT];
     bool any = false;
 #pragma unroll
@@ -101,25 +101,22 @@ __device__ __forceinline__ bool det_step(Neurons<NPT>& N, const uint32_t* lrules
                     break;
                 }
             }
-        }
-        if (fp != 0) {
-#pragma unroll
-            for (int e = 0; e < kOutReg; ++e)
-                if (e < N.on[q]) {
-                    const uint32_t w = N.reg_out[q][e >> 1];
-                    const int d = (e & 1) ? (int)(w >> 16) : (int)(w & 0xFFFFu);
-                    atomicAdd(&acc[d], fp);
-                }
-            for (int e = kOutReg; e < N.on[q]; ++e) atomicAdd(&acc[out_dst[N.os[q] + e]], fp);
+            prod[threadIdx.x + q * TPB] = fp;
         }
     }
     if (__syncthreads_or(any) == 0) return false;
 #pragma unroll
     for (int q = 0; q < NPT; ++q) {
         if (!N.valid[q]) continue;
-        const int j = threadIdx.x + q * kThreads;
-        const long long v = (long long)N.cnt[q] - fc[q] + acc[j];
-        acc[j] = 0;
+        int recv = 0;
+#pragma unroll
+        for (int e = 0; e < kInReg; ++e)
+            if (e < N.in[q]) {
+                const uint32_t w = N.reg_in[q][e >> 1];
+                recv += prod[(e & 1) ? (int)(w >> 16) : (int)(w & 0xFFFFu)];
+            }
+        for (int e = kInReg; e < N.in[q]; ++e) recv += prod[in_src[N.is[q] + e]];
+        const long long v = (long long)N.cnt[q] - fc[q] + recv;
         ovf |= (v < 0) | (v > count_max);
         N.cnt[q] = (int)v;
     }
@@ -135,83 +132,121 @@ __device__ __forceinline__ u64 h_partial(const Neurons<NPT>& N) {
     return h;
 }
 
-template <typename T, int NPT>
+template <typename T, int TPB, int NPT>
 __device__ __forceinline__ void load_counts(Neurons<NPT>& N, const T* row) {
 #pragma unroll
     for (int q = 0; q < NPT; ++q)
-        if (N.valid[q]) N.cnt[q] = (int)row[threadIdx.x + q * kThreads];
+        if (N.valid[q]) N.cnt[q] = (int)row[threadIdx.x + q * TPB];
 }
 
-template <typename T, int NPT>
+template <typename T, int TPB, int NPT>
 __device__ __forceinline__ void store_counts(const Neurons<NPT>& N, T* row) {
 #pragma unroll
     for (int q = 0; q < NPT; ++q)
-        if (N.valid[q]) row[threadIdx.x + q * kThreads] = (T)N.cnt[q];
+        if (N.valid[q]) row[threadIdx.x + q * TPB] = (T)N.cnt[q];
 }
 
 // Block-wide H of the current counts (every thread gets it).
-template <int NPT>
-__device__ __forceinline__ u64 block_hash(const Neurons<NPT>& N, u64* wpart) {
+template <int TPB, int NPT>
+__device__ __forceinline__ u64 block_hash(const Neurons<NPT>& N, u64* bpart) {
     const u64 w = wave_sum64(h_partial(N));
-    if ((threadIdx.x & 63) == 0) wpart[threadIdx.x >> 6] = w;
+    if ((threadIdx.x & 63) == 0) bpart[threadIdx.x >> 6] = w;
     __syncthreads();
     u64 h = 0;
-    for (int q = 0; q < kWaves; ++q) h += wpart[q];
-    __syncthreads();  // wpart may be rewritten afterwards
+    for (int q = 0; q < TPB / 64; ++q) h += bpart[q];
+    __syncthreads();  // bpart may be rewritten afterwards
     return h;
+}
+
+struct BatchLds {
+    uint32_t* lrules;  // [r_max]
+    int* prod0;        // [m4]
+    int* prod1;        // [m4]
+    int* xrow;         // [m4] a configuration under verification
+    u64* wpart;        // [(kBatch + 1) * waves]: per-wave partial H of every step of the batch
+    u64* bpart;        // [waves]
+    u64* hring;        // [kBatch + 1]: H(C_{batch_start + i})
+    u64* term;         // [kBatch + 1]: digest terms of the batch
+    int* cand;         // [kBatch + 1]: earliest step with an equal H
+};
+
+__host__ __device__ __forceinline__ size_t lds_layout(int m_max, int r_max, int waves, unsigned char* base,
+                                                      BatchLds* L) {
+    const size_t r4 = ((size_t)r_max + 3) & ~(size_t)3;
+    const size_t m4 = ((size_t)m_max + 3) & ~(size_t)3;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char* p = base ? base + o : nullptr;
+        o += (bytes + 15) & ~(size_t)15;
+        return p;
+    };
+    unsigned char* p_rules = take(r4 * 4);
+    unsigned char* p_prod0 = take(m4 * 4);
+    unsigned char* p_prod1 = take(m4 * 4);
+    unsigned char* p_xrow = take(m4 * 4);
+    unsigned char* p_wpart = take((size_t)(kBatch + 1) * waves * 8);
+    unsigned char* p_bpart = take((size_t)waves * 8);
+    unsigned char* p_hring = take((kBatch + 1) * 8);
+    unsigned char* p_term = take((kBatch + 1) * 8);
+    unsigned char* p_cand = take((kBatch + 1) * 4);
+    if (L) {
+        L->lrules = (uint32_t*)p_rules;
+        L->prod0 = (int*)p_prod0;
+        L->prod1 = (int*)p_prod1;
+        L->xrow = (int*)p_xrow;
+        L->wpart = (u64*)p_wpart;
+        L->bpart = (u64*)p_bpart;
+        L->hring = (u64*)p_hring;
+        L->term = (u64*)p_term;
+        L->cand = (int*)p_cand;
+    }
+    return o;
 }
 
 }  // namespace
 
-size_t batch_lds_bytes(int m_max, int r_max) {
-    const size_t r4 = ((size_t)r_max + 3) & ~(size_t)3;
-    const size_t m4 = ((size_t)m_max + 3) & ~(size_t)3;
-    return r4 * 4 + m4 * 4 * 3 + kWaves * 8 + (kBatch + 1) * 8 + (kBatch + 1) * 4 + 64;
+size_t batch_lds_bytes(int m_max, int r_max, int threads) {
+    return lds_layout(m_max, r_max, threads / 64, nullptr, nullptr);
 }
 
-int batch_threads() { return kThreads; }
+int batch_max_threads() { return kMaxThreads; }
 int batch_interval() { return kBatch; }
 
-template <typename T, int NPT>
-__global__ __launch_bounds__(kThreads) void k_batch_det(BatchArgs a) {
+template <typename T, int TPB, int NPT>
+__global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int W = TPB / 64;
     const int sys = blockIdx.x;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const BatchSys B = a.sys[sys];
-    const int m4 = (a.m_max + 3) & ~3;
-    uint32_t* lrules = (uint32_t*)smem;                       // [r_max]
-    int* acc0 = (int*)(lrules + ((a.r_max + 3) & ~3));        // [m4]
-    int* acc1 = acc0 + m4;                                    // [m4]
-    int* xrow = acc1 + m4;                                    // [m4] a configuration under verification
-    u64* wpart = (u64*)(xrow + m4);                           // [kWaves]
-    u64* hring = wpart + kWaves;                              // [kBatch + 1]: H(C_{batch_start + i})
-    int* cand = (int*)(hring + kBatch + 1);                   // [kBatch + 1]: earliest step with equal H
+    BatchLds L;
+    lds_layout(a.m_max, a.r_max, W, smem, &L);
 
-    for (int q = threadIdx.x; q < B.r; q += kThreads) lrules[q] = a.rules[B.rule_off + q];
-    for (int q = threadIdx.x; q < 2 * m4; q += kThreads) acc0[q] = 0;
+    for (int q = threadIdx.x; q < B.r; q += TPB) L.lrules[q] = a.rules[B.rule_off + q];
 
     Neurons<NPT> N;
     const T* c0 = (const T*)a.c0 + B.row_off;
 #pragma unroll
     for (int q = 0; q < NPT; ++q) {
-        const int j = threadIdx.x + q * kThreads;
+        const int j = threadIdx.x + q * TPB;
         N.valid[q] = j < B.m;
         N.cnt[q] = 0;
-        N.rs[q] = N.rn[q] = N.os[q] = N.on[q] = 0;
+        N.rs[q] = N.rn[q] = N.is[q] = N.in[q] = 0;
         N.R[q] = 0;
 #pragma unroll
-        for (int e = 0; e < kOutReg / 2; ++e) N.reg_out[q][e] = 0;
+        for (int e = 0; e < kInReg / 2; ++e) N.reg_in[q][e] = 0;
         if (N.valid[q]) {
             N.cnt[q] = (int)c0[j];
             N.rs[q] = a.nrp[B.nrp_off + j];
             N.rn[q] = a.nrp[B.nrp_off + j + 1] - N.rs[q];
-            N.os[q] = B.out_off + a.out_ptr[B.nrp_off + j];
-            N.on[q] = a.out_ptr[B.nrp_off + j + 1] - a.out_ptr[B.nrp_off + j];
+            N.is[q] = B.in_off + a.in_ptr[B.nrp_off + j];
+            N.in[q] = a.in_ptr[B.nrp_off + j + 1] - a.in_ptr[B.nrp_off + j];
             N.R[q] = mix64((u64)(j + 1) * kGamma);
 #pragma unroll
-            for (int e = 0; e < kOutReg; ++e)
-                if (e < N.on[q]) {
-                    const uint32_t d = (uint32_t)a.out_dst[N.os[q] + e] & 0xFFFFu;
-                    N.reg_out[q][e >> 1] |= (e & 1) ? (d << 16) : d;
+            for (int e = 0; e < kInReg; ++e)
+                if (e < N.in[q]) {
+                    const uint32_t s = (uint32_t)a.in_src[N.is[q] + e] & 0xFFFFu;
+                    N.reg_in[q][e >> 1] |= (e & 1) ? (s << 16) : s;
                 }
         }
     }
@@ -222,21 +257,20 @@ __global__ __launch_bounds__(kThreads) void k_batch_det(BatchArgs a) {
     const int steps = a.steps;
     __syncthreads();
 
-    store_counts<T, NPT>(N, ckpt);
-    const u64 h0 = block_hash<NPT>(N, wpart);
-    u64 digest = mix64(h0);
-    if (threadIdx.x == 0) hring[0] = h0;
+    store_counts<T, TPB, NPT>(N, ckpt);
+    const u64 h0 = block_hash<TPB, NPT>(N, L.bpart);
+    u64 digest = mix64(h0);  // meaningful in thread 0
+    if (threadIdx.x == 0) L.hring[0] = h0;
     int k = 0, batch_start = 0, halt = -1, first_rep = -1;
     bool ovf = false, collision = false;
 
     for (;;) {
         bool done = k >= steps;
         if (!done) {
-            if (det_step<NPT>(N, lrules, (k & 1) ? acc1 : acc0, a.out_dst, a.count_max, ovf)) {
+            if (det_step<TPB, NPT>(N, L.lrules, (k & 1) ? L.prod1 : L.prod0, a.in_src, a.count_max, ovf)) {
                 ++k;
-                const u64 h = block_hash<NPT>(N, wpart);
-                digest += mix64(h + (u64)k * kGamma);
-                if (threadIdx.x == 0) hring[k - batch_start] = h;
+                const u64 hw = wave_sum64(h_partial(N));
+                if (lane == 0) L.wpart[(k - batch_start) * W + wid] = hw;
             } else {
                 halt = k;
                 done = true;
@@ -246,57 +280,71 @@ __global__ __launch_bounds__(kThreads) void k_batch_det(BatchArgs a) {
 
         // ---- batch boundary (or end of run) ----
         const int nb = k - batch_start;  // H(C_{batch_start + i}) in hring[i], i = 0 .. nb
-        if (done) store_counts<T, NPT>(N, (T*)a.final_out + B.row_off);
-        else store_counts<T, NPT>(N, ckpt + (long long)(k / kBatch) * B.ckpt_stride);
+        if (done) store_counts<T, TPB, NPT>(N, (T*)a.final_out + B.row_off);
+        else store_counts<T, TPB, NPT>(N, ckpt + (long long)(k / kBatch) * B.ckpt_stride);
+        __syncthreads();  // the batch's per-wave partials are complete
+        {
+            const int i = threadIdx.x;
+            if (i >= 1 && i <= nb) {
+                u64 h = 0;
+                for (int w = 0; w < W; ++w) h += L.wpart[i * W + w];
+                L.hring[i] = h;
+                L.term[i] = mix64(h + (u64)(batch_start + i) * kGamma);
+            }
+        }
         __syncthreads();
+        if (wid == 0) {
+            const u64 s = wave_sum64(lane < nb ? L.term[lane + 1] : 0);
+            if (lane == 0) digest += s;
+        }
         bool resimulated = false;
         if (first_rep < 0 && a.detect_repeats) {
             const int first_new = (batch_start == 0) ? 0 : 1;  // H(C_batch_start) is already in the set
             const int i = threadIdx.x;
-            if (i <= kBatch) cand[i] = -1;
+            if (i <= kBatch) L.cand[i] = -1;
             __syncthreads();
             if (i >= first_new && i <= nb) {  // earlier batches: read-only probes
-                const u64 key = hring[i];
+                const u64 key = L.hring[i];
                 u64 s = (key * kGamma) >> 17;
                 for (u64 it = 0; it <= hmask; ++it, ++s) {
                     const int st = hstep[s & hmask];
                     if (st < 0) break;
                     if (hkey[s & hmask] == key) {
-                        cand[i] = st;
+                        L.cand[i] = st;
                         break;
                     }
                 }
-                if (cand[i] < 0)  // within this batch
+                if (L.cand[i] < 0)  // within this batch
                     for (int l = 0; l < i; ++l)
-                        if (hring[l] == key) {
-                            cand[i] = batch_start + l;
+                        if (L.hring[l] == key) {
+                            L.cand[i] = batch_start + l;
                             break;
                         }
             }
             __syncthreads();
             // confirm candidates in step order by re-simulating both rows
             for (int q = first_new; q <= nb && first_rep < 0; ++q) {
-                const int l = cand[q];
+                const int l = L.cand[q];
                 if (l < 0) continue;
                 const int kk = batch_start + q;
                 resimulated = true;
-                load_counts<T, NPT>(N, ckpt + (long long)(l / kBatch) * B.ckpt_stride);
+                load_counts<T, TPB, NPT>(N, ckpt + (long long)(l / kBatch) * B.ckpt_stride);
                 for (int t = (l / kBatch) * kBatch; t < l; ++t)
-                    det_step<NPT>(N, lrules, (t & 1) ? acc1 : acc0, a.out_dst, a.count_max, ovf);
-                store_counts<int, NPT>(N, xrow);
-                load_counts<T, NPT>(N, ckpt + (long long)(kk / kBatch) * B.ckpt_stride);
+                    det_step<TPB, NPT>(N, L.lrules, (t & 1) ? L.prod1 : L.prod0, a.in_src, a.count_max, ovf);
+                store_counts<int, TPB, NPT>(N, L.xrow);
+                load_counts<T, TPB, NPT>(N, ckpt + (long long)(kk / kBatch) * B.ckpt_stride);
                 for (int t = (kk / kBatch) * kBatch; t < kk; ++t)
-                    det_step<NPT>(N, lrules, (t & 1) ? acc1 : acc0, a.out_dst, a.count_max, ovf);
+                    det_step<TPB, NPT>(N, L.lrules, (t & 1) ? L.prod1 : L.prod0, a.in_src, a.count_max, ovf);
                 bool diff = false;
 #pragma unroll
                 for (int u = 0; u < NPT; ++u)
-                    if (N.valid[u]) diff |= (xrow[threadIdx.x + u * kThreads] != N.cnt[u]);
+                    if (N.valid[u]) diff |= (L.xrow[threadIdx.x + u * TPB] != N.cnt[u]);
                 if (__syncthreads_or(diff) == 0) first_rep = kk;
                 else collision = true;
             }
             // insert the first occurrence of every new H value
-            if (i >= first_new && i <= nb && cand[i] < 0) {
-                const u64 key = hring[i];
+            if (i >= first_new && i <= nb && L.cand[i] < 0) {
+                const u64 key = L.hring[i];
                 u64 s = (key * kGamma) >> 17;
                 for (u64 it = 0; it <= hmask; ++it, ++s)
                     if (atomicCAS(&hstep[s & hmask], -1, batch_start + i) == -1) {
@@ -307,11 +355,9 @@ __global__ __launch_bounds__(kThreads) void k_batch_det(BatchArgs a) {
             __syncthreads();
         }
         if (done) break;
-        if (resimulated) {  // back to the configuration at step k
-            load_counts<T, NPT>(N, ckpt + (long long)(k / kBatch) * B.ckpt_stride);
-            for (int q = threadIdx.x; q < 2 * m4; q += kThreads) acc0[q] = 0;
-        }
-        if (threadIdx.x == 0) hring[0] = hring[nb];
+        if (resimulated)  // back to the configuration at step k
+            load_counts<T, TPB, NPT>(N, ckpt + (long long)(k / kBatch) * B.ckpt_stride);
+        if (threadIdx.x == 0) L.hring[0] = L.hring[nb];
         batch_start = k;
         __syncthreads();
     }
@@ -326,20 +372,29 @@ __global__ __launch_bounds__(kThreads) void k_batch_det(BatchArgs a) {
     }
 }
 
-hipError_t launch_batch_det(int elem_bytes, int npt, const BatchArgs& a, int n_sys, hipStream_t st) {
+hipError_t launch_batch_det(int elem_bytes, int threads, int npt, const BatchArgs& a, int n_sys, hipStream_t st) {
     if (n_sys <= 0) return hipSuccess;
-    const size_t lds = batch_lds_bytes(a.m_max, a.r_max);
-#define SNP_BATCH(TT, NN) \
-    hipLaunchKernelGGL((k_batch_det<TT, NN>), dim3(n_sys), dim3(kThreads), lds, st, a)
-    if (elem_bytes == 4) {
-        if (npt == 1) SNP_BATCH(int32_t, 1);
-        else if (npt == 2) SNP_BATCH(int32_t, 2);
-        else SNP_BATCH(int32_t, 4);
-    } else {
-        if (npt == 1) SNP_BATCH(uint16_t, 1);
-        else if (npt == 2) SNP_BATCH(uint16_t, 2);
-        else SNP_BATCH(uint16_t, 4);
-    }
+    const size_t lds = batch_lds_bytes(a.m_max, a.r_max, threads);
+#define SNP_BATCH(TT, TPB, NN) \
+    hipLaunchKernelGGL((k_batch_det<TT, TPB, NN>), dim3(n_sys), dim3(TPB), lds, st, a)
+#define SNP_BATCH_NPT(TT, TPB)                      \
+    do {                                            \
+        if (npt == 1) SNP_BATCH(TT, TPB, 1);        \
+        else if (npt == 2) SNP_BATCH(TT, TPB, 2);   \
+        else SNP_BATCH(TT, TPB, 4);                 \
+    } while (0)
+#define SNP_BATCH_TPB(TT)                                  \
+    do {                                                   \
+        if (threads == 256) SNP_BATCH_NPT(TT, 256);        \
+        else if (threads == 512) SNP_BATCH_NPT(TT, 512);   \
+        else SNP_BATCH_NPT(TT, 1024);                      \
+    } while (0)
+    if (!((threads == 256 || threads == 512 || threads == 1024) && (npt == 1 || npt == 2 || npt == 4)))
+        return hipErrorInvalidValue;
+    if (elem_bytes == 4) SNP_BATCH_TPB(int32_t);
+    else SNP_BATCH_TPB(uint16_t);
+#undef SNP_BATCH_TPB
+#undef SNP_BATCH_NPT
 #undef SNP_BATCH
     return hipGetLastError();
 }

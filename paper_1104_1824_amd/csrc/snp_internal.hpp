@@ -114,8 +114,8 @@ struct BatchSys {
     int m, r;
     long long row_off;      // first element of the system's row in packed row buffers
     int rule_off;           // first packed rule of the system
-    int nrp_off;            // first entry of the system's (m+1)-long rule and out-synapse offsets
-    int out_off;            // first out-synapse target of the system
+    int nrp_off;            // first entry of the system's (m+1)-long rule and in-synapse offsets
+    int in_off;             // first in-synapse source of the system
     long long ckpt_off;     // first element of the system's checkpoint rows
     long long ckpt_stride;  // elements per checkpoint row (m)
     long long table_off;    // first slot of the system's H set
@@ -125,8 +125,8 @@ struct BatchArgs {
     const BatchSys* sys;
     const uint32_t* rules;  // packed (i | j << 8 | c << 16 | p << 24)
     const int* nrp;         // per system: rules of neuron n are [nrp[n], nrp[n+1]) (system-relative)
-    const int* out_ptr;     // per system: out-synapses of neuron n are out_dst[out_off + out_ptr[n] ..)
-    const int* out_dst;
+    const int* in_ptr;      // per system: in-synapses of neuron n are in_src[in_off + in_ptr[n] ..)
+    const int* in_src;
     const void* c0;
     void* final_out;
     void* ckpt;
@@ -144,10 +144,10 @@ struct BatchArgs {
     u64* err;               // bit 0: overflow; bit 1: two configurations with one 64-bit H
 };
 
-size_t batch_lds_bytes(int m_max, int r_max);
-int batch_threads();
+size_t batch_lds_bytes(int m_max, int r_max, int threads);
+int batch_max_threads();
 int batch_interval();
-hipError_t launch_batch_det(int elem_bytes, int npt, const BatchArgs& a, int n_sys, hipStream_t st);
+hipError_t launch_batch_det(int elem_bytes, int threads, int npt, const BatchArgs& a, int n_sys, hipStream_t st);
 hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st);
 
 hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, long long n,

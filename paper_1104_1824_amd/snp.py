@@ -20,10 +20,11 @@ SNP_OK, SNP_ERR_INVALID, SNP_ERR_OVERFLOW, SNP_ERR_CAPACITY, SNP_ERR_BUDGET, SNP
 SNP_COUNT_I32, SNP_COUNT_U16 = 0, 1
 SNP_PATH_AUTO, SNP_PATH_SPARSE, SNP_PATH_INT8 = 0, 1, 2
 STOP_NAMES = {0: "EMPTY_FRONTIER", 1: "ALL_HALTING", 2: "DEPTH", 3: "CAP", 4: "BUDGET"}
+SNP_STOP_EMPTY_FRONTIER, SNP_STOP_ALL_HALTING, SNP_STOP_DEPTH, SNP_STOP_CAP, SNP_STOP_BUDGET = 0, 1, 2, 3, 4
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OVERFLOW", 3: "CAPACITY", 4: "BUDGET", 5: "DEVICE"}
 
 EXPORTED = ("snp_load", "snp_free", "snp_last_error", "snp_row_bytes", "snp_reset", "snp_expand", "snp_run",
-            "snp_batch_load", "snp_batch_free", "snp_batch_offsets", "snp_batch_run")
+            "snp_batch_load", "snp_batch_free", "snp_batch_offsets", "snp_batch_shape", "snp_batch_run")
 
 
 class SnpError(RuntimeError):
@@ -104,6 +105,8 @@ def lib():
         L.snp_batch_free.restype = None
         L.snp_batch_offsets.argtypes = [P, P]
         L.snp_batch_offsets.restype = I32
+        L.snp_batch_shape.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+        L.snp_batch_shape.restype = I32
         L.snp_batch_run.argtypes = [P, P, I32, I32, P, P, P, P, P]
         L.snp_batch_run.restype = I32
         _lib = L
@@ -265,11 +268,14 @@ class BatchHandle:
             pass
 
 
-def snp_batch_load(systems, stream=None) -> BatchHandle:
+def snp_batch_load(systems, stream=None, threads: int = 0) -> BatchHandle:
+    """snp_batch_load; ``threads`` (256, 512 or 1024) fixes the threads per
+    system, 0 lets the first run pick the fastest shape."""
     keep = []
     descs = (snp_desc * len(systems))(*[_desc(s, keep) for s in systems])
     o = snp_options()
     o.max_rows = 1
+    o.chunk = int(threads)
     o.stream = _stream_ptr(stream) or None
     out = ctypes.c_void_p()
     _check(lib().snp_batch_load(descs, len(systems), ctypes.byref(o), ctypes.byref(out)), "snp_batch_load")
@@ -284,6 +290,13 @@ def snp_batch_offsets(b: BatchHandle) -> np.ndarray:
     off = np.zeros(b.n + 1, dtype=np.int64)
     _check(lib().snp_batch_offsets(b.ptr, off.ctypes.data), "snp_batch_offsets")
     return off
+
+
+def snp_batch_shape(b: BatchHandle):
+    """(threads per system, neurons per thread) in use; (0, 0) before the first run."""
+    th, npt = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().snp_batch_shape(b.ptr, ctypes.byref(th), ctypes.byref(npt)), "snp_batch_shape")
+    return th.value, npt.value
 
 
 def snp_batch_run(b: BatchHandle, c0_dev, steps: int, final_dev, detect_repeats: bool = True) -> dict:

@@ -29,10 +29,10 @@ def path(m):
     return synth.make_system(m, rules, syn, c0, name=f"path{m}")
 
 
-def run_batch(systems, steps, detect=True):
+def run_batch(systems, steps, detect=True, threads=0):
     import torch
 
-    b = snp.snp_batch_load(systems)
+    b = snp.snp_batch_load(systems, threads=threads)
     try:
         off = snp.snp_batch_offsets(b)
         dt = torch.int16 if systems[0].count_type == "u16" else torch.int32
@@ -125,3 +125,52 @@ def test_batch_without_repeat_detection(gpu, oracle_mod):
     res = run_batch(systems, 250, detect=False)
     check_against_oracle(oracle_mod, systems, 250, res, detect=False)
     assert res["first_repeat"].tolist() == [-1, -1, -1]
+
+
+@pytest.mark.parametrize("threads", [256, 512, 1024])
+def test_batch_every_launch_shape(gpu, oracle_mod, threads):
+    """Each fixed launch shape (threads per system; up to 4 neurons per thread)
+    gives the oracle's results; the autotuned shape is one of them."""
+    systems = synth.batched_systems(3, 12) + [ring(100), path(70), synth.paper_example()]
+    systems = [s for s in systems if s.m <= 4 * threads]
+    note(f"batch shape {threads} threads, {len(systems)} systems, 700 steps")
+    check_against_oracle(oracle_mod, systems, 700, run_batch(systems, 700, threads=threads))
+
+
+def test_batch_graph_replays(gpu, oracle_mod):
+    """The recorded launch is replayed on later calls (with other GPU work in
+    between); every replay matches the first, eager-built result and the oracle."""
+    import torch
+
+    systems = synth.batched_systems(5, 10) + [ring(64), path(40)]
+    b = snp.snp_batch_load(systems)
+    try:
+        off = snp.snp_batch_offsets(b)
+        c0 = torch.from_numpy(np.concatenate([s.c0 for s in systems]).astype(np.int32)).cuda()
+        fin = torch.empty(int(off[-1]), dtype=torch.int32, device="cuda")
+        results = []
+        for rep, steps in enumerate((300, 300, 300, 130, 300)):
+            note(f"graph replay {rep}, steps {steps}")
+            junk = torch.randn(1 << 20, device="cuda").sum()  # unrelated work between replays
+            torch.cuda.synchronize()
+            fin.fill_(-1)
+            res = snp.snp_batch_run(b, c0, steps, fin)
+            res["final"] = fin.cpu().numpy().copy()
+            results.append((steps, res))
+            assert float(junk) == float(junk)
+        th, npt = snp.snp_batch_shape(b)
+        assert th in (256, 512, 1024) and npt in (1, 2, 4)
+    finally:
+        b.close()
+    base = results[0][1]
+    for steps, res in results:
+        if steps == 300:
+            for k in ("halt_step", "first_repeat", "steps_done", "digest", "final"):
+                assert np.array_equal(res[k], base[k]), k
+    for steps in (300, 130):
+        res = [r for s_, r in results if s_ == steps][0]
+        fin_rows = [res["final"][off[k]: off[k + 1]] for k in range(len(systems))]
+        for k, s in enumerate(systems):
+            d = oracle_mod.deterministic(s, steps)
+            assert fin_rows[k].tolist() == d.final.tolist()
+            assert int(res["digest"][k]) == d.digest and int(res["first_repeat"][k]) == d.first_repeat

@@ -1,0 +1,161 @@
+"""Full-size runs of the dense (m=512, cap 1e6, depth 3) and large (m=4096,
+uint16, cap 4e6) workloads, too big for the oracle to redo whole.  They are
+checked on outputs the oracle computes one by one and on properties that hold
+at any size:
+
+* level sizes and the stop reason;
+* every sampled row equals the oracle's child (Algorithm 2 order) of its
+  recorded parent, at its recorded child index;
+* within a level, (parent, child index) strictly increases (first occurrence
+  in canonical order) and parents belong to the level before;
+* all recorded rows are distinct;
+* the child just before a sampled row in canonical order (same parent, index
+  minus one) is recorded somewhere (no enumerated child is lost), and so is
+  every child of the parents before each level's first recorded child;
+* the int8 and sparse forms give the same rows bit for bit (dense workload),
+  and level 1 equals the oracle's level 1 in full.
+"""
+import numpy as np
+import pytest
+
+import synth
+from paper_1104_1824_amd import snp
+from tests.gpu_helpers import dev_dtype, from_device_rows, note, to_device_rows
+
+pytestmark = pytest.mark.gpu
+
+
+def run_full(system, path, cap, depth, out_cap, chunk=1 << 20):
+    import torch
+
+    h = snp.snp_load(system, path=path, frontier_cap=cap, max_rows=out_cap, chunk=chunk)
+    try:
+        c0 = to_device_rows(system, system.c0)
+        out = torch.empty((out_cap, system.m), dtype=dev_dtype(system), device="cuda")
+        par = torch.empty(out_cap, dtype=torch.int64, device="cuda")
+        chi = torch.empty(out_cap, dtype=torch.int64, device="cuda")
+        res = snp.snp_run(h, c0, depth, out, out_cap, parent_of=par, child_of=chi)
+    finally:
+        h.close()
+    n = res["n_configs"]
+    return res, out[:n], par[:n], chi[:n]
+
+
+def row_keys(system, rows, seed=12345, chunk_bytes=1 << 30):
+    """A 64-bit key per row (sum of count x random odd weight, wrapping), on the
+    GPU; independent of the library's own hash."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    w = torch.from_numpy(rng.integers(-(1 << 62), 1 << 62, size=system.m, dtype=np.int64) | 1).cuda()
+    n = rows.shape[0]
+    keys = torch.empty(n, dtype=torch.int64, device="cuda")
+    step = max(1, chunk_bytes // (8 * system.m))
+    for a in range(0, n, step):
+        x = rows[a: a + step].to(torch.int64)
+        if system.count_type == "u16":
+            x = x & 0xFFFF
+        keys[a: a + step] = (x * w).sum(dim=1)
+    return keys, w.cpu().numpy()
+
+
+def host_key(row, w):
+    with np.errstate(over="ignore"):
+        return int(np.sum(np.asarray(row, dtype=np.int64) * w, dtype=np.int64))
+
+
+def check_walk(oracle_mod, system, res, rows, par, chi, n_samples, seed):
+    import torch
+
+    sizes = res["level_sizes"].tolist()
+    bounds = np.concatenate([[0], np.cumsum(sizes)])
+    # canonical order and parents in the previous level
+    for k in range(1, len(sizes)):
+        a, b = int(bounds[k]), int(bounds[k + 1])
+        p, t = par[a:b], chi[a:b]
+        assert int(p.min()) >= int(bounds[k - 1]) and int(p.max()) < a, k
+        assert bool((t < (1 << 40)).all()) and int(p.max()) < (1 << 23)
+        key = p * (1 << 40) + t
+        assert bool((key[1:] > key[:-1]).all()), f"level {k} not in canonical order"
+    # all rows distinct
+    keys, w = row_keys(system, rows)
+    sk, order = torch.sort(keys)
+    dup = torch.nonzero(sk[1:] == sk[:-1]).flatten()
+    for d in dup.tolist()[:1000]:
+        i, j = int(order[d]), int(order[d + 1])
+        assert not torch.equal(rows[i], rows[j]), f"rows {i} and {j} are equal"
+    sk_host = sk.cpu().numpy()
+    order_host = order.cpu().numpy()
+
+    def recorded(row):
+        kk = host_key(row, w)
+        lo = np.searchsorted(sk_host, kk, side="left")
+        hi = np.searchsorted(sk_host, kk, side="right")
+        for q in range(lo, hi):
+            got = from_device_rows(system, rows[int(order_host[q])].unsqueeze(0))[0]
+            if np.array_equal(got, row):
+                return True
+        return False
+
+    par_h = par.cpu().numpy()
+    chi_h = chi.cpu().numpy()
+    # the enumeration of each level starts at its first parents: every parent
+    # before the first recorded child's parent has all its children recorded
+    for k in range(1, len(sizes)):
+        first = int(bounds[k])
+        lo_prev, p_first = int(bounds[k - 1]), int(par_h[first])
+        assert p_first - lo_prev <= 64, (k, p_first - lo_prev)
+        for q in range(lo_prev, p_first):
+            prow = from_device_rows(system, rows[q].unsqueeze(0))[0]
+            _, _, psi = oracle_mod.children(system, prow, max_out=1)
+            assert psi <= 4096, (k, q, psi)
+            if psi:
+                crows, _, _ = oracle_mod.children(system, prow, max_out=psi)
+                assert all(recorded(x) for x in crows), (k, q)
+        if chi_h[first] > 0:  # children before it, of the same parent, are recorded
+            prow = from_device_rows(system, rows[p_first].unsqueeze(0))[0]
+            for t in range(max(0, int(chi_h[first]) - 64), int(chi_h[first])):
+                assert recorded(oracle_mod.child_at(system, prow, t)), (k, t)
+    rng = np.random.default_rng(seed)
+    picks = rng.integers(1, rows.shape[0], size=n_samples)
+    for q in picks.tolist():
+        p, t = int(par_h[q]), int(chi_h[q])
+        prow = from_device_rows(system, rows[p].unsqueeze(0))[0]
+        want = oracle_mod.child_at(system, prow, t)
+        got = from_device_rows(system, rows[q].unsqueeze(0))[0]
+        assert np.array_equal(got, want), f"row {q} (parent {p}, t {t}) differs from the oracle's child"
+        if t > 0:
+            assert recorded(oracle_mod.child_at(system, prow, t - 1)), f"child ({p}, {t - 1}) missing"
+
+
+def test_dense_full_size(gpu, oracle_mod):
+    import torch
+
+    s = synth.config_system(3, 0)
+    note("full size: dense m=512, cap 1e6, depth 3, int8")
+    res, rows, par, chi = run_full(s, snp.SNP_PATH_INT8, 1000000, 3, 3000001)
+    assert res["level_sizes"].tolist() == [1, 1000000, 1000000, 1000000]
+    assert res["stop_reason"] == snp.SNP_STOP_DEPTH
+    note("full size: dense, sampled checks")
+    check_walk(oracle_mod, s, res, rows, par, chi, n_samples=300, seed=1)
+    note("full size: dense, sparse form on the same input")
+    res2, rows2, par2, chi2 = run_full(s, snp.SNP_PATH_SPARSE, 1000000, 3, 3000001)
+    assert res2["level_sizes"].tolist() == res["level_sizes"].tolist()
+    assert torch.equal(rows, rows2) and torch.equal(par, par2) and torch.equal(chi, chi2)
+    del rows2, par2, chi2
+    note("full size: dense, level 1 against the oracle")
+    want = oracle_mod.bfs(s, max_depth=1, frontier_cap=1000000)
+    assert want.level_sizes.tolist() == [1, 1000000]
+    got = from_device_rows(s, rows[:1000001])
+    assert np.array_equal(got, want.rows)
+    assert par[:1000001].cpu().numpy().tolist() == want.parent.tolist()
+    assert chi[:1000001].cpu().numpy().tolist() == want.tindex.tolist()
+
+
+def test_large_full_size(gpu, oracle_mod):
+    s = synth.config_system(5, 0)
+    note("full size: large m=4096 uint16, cap 4e6, depth 2, automatic path")
+    res, rows, par, chi = run_full(s, snp.SNP_PATH_AUTO, 4000000, 2, 8000001, chunk=1 << 19)
+    assert res["level_sizes"].tolist() == [1, 4000000, 4000000]
+    note("full size: large, sampled checks")
+    check_walk(oracle_mod, s, res, rows, par, chi, n_samples=200, seed=2)
