@@ -136,6 +136,7 @@ struct snp_batch {
     std::vector<long long> row_off;  // n + 1
     snp::BatchSys* d_sys = nullptr;
     uint32_t* d_rules = nullptr;
+    uint32_t* d_magic = nullptr;
     int *d_nrp = nullptr, *d_in_ptr = nullptr, *d_in_src = nullptr;
     // per-run buffers, grown on demand
     int cap_steps = -1;
@@ -159,7 +160,7 @@ struct snp_batch {
     ~snp_batch() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
-        void* ptrs[] = {d_sys, d_rules, d_nrp, d_in_ptr, d_in_src, d_ckpt, d_hkey, d_hstep,
+        void* ptrs[] = {d_sys, d_rules, d_magic, d_nrp, d_in_ptr, d_in_src, d_ckpt, d_hkey, d_hstep,
                         d_halt, d_rep, d_done, d_digest, d_err};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
@@ -748,6 +749,16 @@ snp_status snp_run(snp_system* S, const void* c0_dev, int32_t max_depth, void* o
     return SNP_OK;
 }
 
+// Multiplier m of the exact quotient x / d for every 32-bit x and 2 <= d < 2^8
+// (Granlund and Montgomery, 1994): with l = ceil(log2 d) and t = mulhi(m, x),
+// x / d = (t + ((x - t) >> 1)) >> (l - 1).  0 for d < 2 (not used).
+static uint32_t div_magic(uint32_t d) {
+    if (d < 2) return 0;
+    uint32_t l = 0;
+    while ((1u << l) < d) ++l;
+    return (uint32_t)(((1ULL << 32) * ((1ULL << l) - d)) / d + 1);
+}
+
 snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* opt, snp_batch** out) {
     g_err.clear();
     if (!out) return fail(SNP_ERR_INVALID, "out is NULL");
@@ -756,7 +767,7 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
     const int ct = descs[0].count_type;
     std::vector<snp::BatchSys> sys(n);
     std::vector<long long> row_off(n + 1, 0);
-    std::vector<uint32_t> rules;
+    std::vector<uint32_t> rules, magic;
     std::vector<int> nrp, in_ptr, in_src;
     int m_max = 0, r_max = 0;
     for (int k = 0; k < n; ++k) {
@@ -778,6 +789,8 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
         B.rule_off = (int)rules.size();
         B.nrp_off = (int)nrp.size();
         B.in_off = (int)in_src.size();
+        for (int q = 0; q < d->r; ++q)
+            magic.push_back(div_magic((uint32_t)d->rule_j[q]));
         for (int q = 0; q < d->r; ++q)
             rules.push_back((uint32_t)d->rule_i[q] | ((uint32_t)d->rule_j[q] << 8) | ((uint32_t)d->rule_c[q] << 16) |
                             ((uint32_t)d->rule_p[q] << 24));
@@ -839,6 +852,7 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
     } while (0)
     BLOADCHK(dmalloc(&b->d_sys, sizeof(snp::BatchSys) * n));
     BLOADCHK(dmalloc(&b->d_rules, sizeof(uint32_t) * rules.size()));
+    BLOADCHK(dmalloc(&b->d_magic, sizeof(uint32_t) * std::max<size_t>(1, magic.size())));
     BLOADCHK(dmalloc(&b->d_nrp, sizeof(int) * nrp.size()));
     BLOADCHK(dmalloc(&b->d_in_ptr, sizeof(int) * in_ptr.size()));
     BLOADCHK(dmalloc(&b->d_in_src, sizeof(int) * std::max<size_t>(1, in_src.size())));
@@ -848,6 +862,7 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
     BLOADCHK(dmalloc(&b->d_digest, sizeof(u64) * n));
     BLOADCHK(dmalloc(&b->d_err, sizeof(u64) * n));
     if (!rules.empty()) BLOADCHK(hipMemcpy(b->d_rules, rules.data(), sizeof(uint32_t) * rules.size(), hipMemcpyHostToDevice));
+    if (!magic.empty()) BLOADCHK(hipMemcpy(b->d_magic, magic.data(), sizeof(uint32_t) * magic.size(), hipMemcpyHostToDevice));
     BLOADCHK(hipMemcpy(b->d_nrp, nrp.data(), sizeof(int) * nrp.size(), hipMemcpyHostToDevice));
     BLOADCHK(hipMemcpy(b->d_in_ptr, in_ptr.data(), sizeof(int) * in_ptr.size(), hipMemcpyHostToDevice));
     if (!in_src.empty())
@@ -905,7 +920,7 @@ snp_status snp_batch_run(snp_batch* b, const void* c0_dev, int32_t steps, int32_
         HIPCHK(hipMemcpy(b->d_sys, b->sys.data(), sizeof(snp::BatchSys) * b->n, hipMemcpyHostToDevice));
         b->cap_steps = steps;
     }
-    snp::BatchArgs a{b->d_sys, b->d_rules, b->d_nrp, b->d_in_ptr, b->d_in_src, c0_dev, final_dev, b->d_ckpt,
+    snp::BatchArgs a{b->d_sys, b->d_rules, b->d_magic, b->d_nrp, b->d_in_ptr, b->d_in_src, c0_dev, final_dev, b->d_ckpt,
                      b->d_hkey, b->d_hstep, b->table_slots, b->m_max, b->r_max, steps, detect_repeats ? 1 : 0,
                      b->count_max, b->d_halt, b->d_rep, b->d_done, b->d_digest, b->d_err};
     auto enqueue = [&](hipStream_t st, int threads, int npt) -> hipError_t {

@@ -63,27 +63,36 @@ __device__ __forceinline__ u64 wave_sum64(u64 v) {
 #undef SNP_DPP64
 
 // Packed rule (i | j << 8 | c << 16 | p << 24): a^n in L(a^i (a^j)*) and n >= c.
-__device__ __forceinline__ bool applies_packed(int n, uint32_t R) {
+// (n - i) mod j by the exact multiply-shift quotient with the rule's
+// multiplier M (Granlund-Montgomery; every 32-bit x, 2 <= j < 256); no branch.
+__device__ __forceinline__ bool applies_packed(int n, uint32_t R, uint32_t M) {
     const int i = R & 0xFF, j = (R >> 8) & 0xFF, c = (R >> 16) & 0xFF;
-    if (n < i || n < c) return false;
-    if (j == 0) return n == i;
-    return ((uint32_t)(n - i) % (uint32_t)j) == 0;
+    const uint32_t x = (uint32_t)(n - i);
+    const uint32_t l = 32u - (uint32_t)__clz(max(j, 2) - 1);
+    const uint32_t t = __umulhi(M, x);
+    const uint32_t q = (t + ((x - t) >> 1)) >> (l - 1);
+    const bool mod0 = j == 0 ? x == 0 : (j == 1 ? true : x == q * (uint32_t)j);
+    return n >= i && n >= c && mod0;
 }
 
 template <int NPT>
 struct Neurons {
     int cnt[NPT];          // current spike count
     int rs[NPT], rn[NPT];  // rules: lrules[rs .. rs + rn)
+    int rw[NPT];           // the wave's largest rule count (uniform)
     int is[NPT], in[NPT];  // in-synapse sources: in_src[is .. is + in)
-    uint32_t reg_in[NPT][kInReg / 2];  // first kInReg sources, two u16 per word
+    uint32_t reg_in[NPT][kInReg / 2];  // first kInReg sources, two u16 per word (zero slot past in)
+    int kw[NPT];           // the wave's largest in-degree held in registers (uniform)
     u64 R[NPT];            // H weights
     bool valid[NPT];
 };
 
 // One step of the deterministic branch; prod is this step's production buffer.
-// Returns (block-wide) whether any neuron fired; when none fired nothing changes.
+// Returns whether a neuron of this wave fired.  When no neuron of the block
+// fires (a halting configuration) the step changes nothing, so halting is
+// detected afterwards, once per batch of steps, from the waves' records.
 template <int TPB, int NPT>
-__device__ __forceinline__ bool det_step(Neurons<NPT>& N, const uint32_t* lrules, int* prod,
+__device__ __forceinline__ bool det_step(Neurons<NPT>& N, const uint32_t* lrules, const uint32_t* lmagic, int* prod,
                                          const int* __restrict__ in_src, long long count_max, bool& ovf) {
     int fc[NPT];
     bool any = false;
@@ -91,36 +100,45 @@ __device__ __forceinline__ bool det_step(Neurons<NPT>& N, const uint32_t* lrules
     for (int q = 0; q < NPT; ++q) {
         fc[q] = 0;
         int fp = 0;
-        if (N.valid[q]) {
-            for (int k = 0; k < N.rn[q]; ++k) {
-                const uint32_t R = lrules[N.rs[q] + k];
-                if (applies_packed(N.cnt[q], R)) {
-                    fc[q] = (R >> 16) & 0xFF;
-                    fp = (int)(R >> 24);
-                    any = true;
-                    break;
-                }
-            }
-            prod[threadIdx.x + q * TPB] = fp;
+        // first applicable rule, over the wave's largest rule count (no early exit)
+        bool found = false;
+        for (int k = 0; k < N.rw[q]; ++k) {
+            const int kk = N.rs[q] + min(k, max(N.rn[q] - 1, 0));
+            const uint32_t R = lrules[kk];
+            const bool ok = !found && k < N.rn[q] && applies_packed(N.cnt[q], R, lmagic[kk]);
+            fc[q] = ok ? (int)((R >> 16) & 0xFF) : fc[q];
+            fp = ok ? (int)(R >> 24) : fp;
+            found |= ok;
         }
+        any |= found;
+        if (N.valid[q]) prod[threadIdx.x + q * TPB] = fp;
     }
-    if (__syncthreads_or(any) == 0) return false;
+    const bool wave_fired = __any(any);
+    __syncthreads();
 #pragma unroll
     for (int q = 0; q < NPT; ++q) {
         if (!N.valid[q]) continue;
+        // unconditional reads, issued together (sources past the in-degree read
+        // a slot that always holds 0); half of them only when the wave needs them
         int recv = 0;
 #pragma unroll
-        for (int e = 0; e < kInReg; ++e)
-            if (e < N.in[q]) {
+        for (int e = 0; e < kInReg / 2; e += 2) {
+            const uint32_t w = N.reg_in[q][e >> 1];
+            recv += prod[w & 0xFFFFu] + prod[w >> 16];
+        }
+        if (N.kw[q] > kInReg / 2) {
+#pragma unroll
+            for (int e = kInReg / 2; e < kInReg; e += 2) {
                 const uint32_t w = N.reg_in[q][e >> 1];
-                recv += prod[(e & 1) ? (int)(w >> 16) : (int)(w & 0xFFFFu)];
+                recv += prod[w & 0xFFFFu] + prod[w >> 16];
             }
+        }
         for (int e = kInReg; e < N.in[q]; ++e) recv += prod[in_src[N.is[q] + e]];
         const long long v = (long long)N.cnt[q] - fc[q] + recv;
         ovf |= (v < 0) | (v > count_max);
         N.cnt[q] = (int)v;
     }
-    return true;
+    return wave_fired;
 }
 
 template <int NPT>
@@ -160,6 +178,7 @@ __device__ __forceinline__ u64 block_hash(const Neurons<NPT>& N, u64* bpart) {
 
 struct BatchLds {
     uint32_t* lrules;  // [r_max]
+    uint32_t* lmagic;  // [r_max]
     int* prod0;        // [m4]
     int* prod1;        // [m4]
     int* xrow;         // [m4] a configuration under verification
@@ -168,6 +187,7 @@ struct BatchLds {
     u64* hring;        // [kBatch + 1]: H(C_{batch_start + i})
     u64* term;         // [kBatch + 1]: digest terms of the batch
     int* cand;         // [kBatch + 1]: earliest step with an equal H
+    u64* fired;        // [waves]: steps of the batch where a neuron of the wave fired
 };
 
 __host__ __device__ __forceinline__ size_t lds_layout(int m_max, int r_max, int waves, unsigned char* base,
@@ -181,16 +201,19 @@ __host__ __device__ __forceinline__ size_t lds_layout(int m_max, int r_max, int 
         return p;
     };
     unsigned char* p_rules = take(r4 * 4);
-    unsigned char* p_prod0 = take(m4 * 4);
-    unsigned char* p_prod1 = take(m4 * 4);
+    unsigned char* p_magic = take(r4 * 4);
+    unsigned char* p_prod0 = take(m4 * 4 + 16);  // slot m4 always holds 0
+    unsigned char* p_prod1 = take(m4 * 4 + 16);
     unsigned char* p_xrow = take(m4 * 4);
     unsigned char* p_wpart = take((size_t)(kBatch + 1) * waves * 8);
     unsigned char* p_bpart = take((size_t)waves * 8);
     unsigned char* p_hring = take((kBatch + 1) * 8);
     unsigned char* p_term = take((kBatch + 1) * 8);
     unsigned char* p_cand = take((kBatch + 1) * 4);
+    unsigned char* p_fired = take((size_t)waves * 8);
     if (L) {
         L->lrules = (uint32_t*)p_rules;
+        L->lmagic = (uint32_t*)p_magic;
         L->prod0 = (int*)p_prod0;
         L->prod1 = (int*)p_prod1;
         L->xrow = (int*)p_xrow;
@@ -199,6 +222,7 @@ __host__ __device__ __forceinline__ size_t lds_layout(int m_max, int r_max, int 
         L->hring = (u64*)p_hring;
         L->term = (u64*)p_term;
         L->cand = (int*)p_cand;
+        L->fired = (u64*)p_fired;
     }
     return o;
 }
@@ -222,7 +246,12 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
     BatchLds L;
     lds_layout(a.m_max, a.r_max, W, smem, &L);
 
-    for (int q = threadIdx.x; q < B.r; q += TPB) L.lrules[q] = a.rules[B.rule_off + q];
+    for (int q = threadIdx.x; q < B.r; q += TPB) {
+        L.lrules[q] = a.rules[B.rule_off + q];
+        L.lmagic[q] = a.magic[B.rule_off + q];
+    }
+    const int zslot = (a.m_max + 3) & ~3;
+    if (threadIdx.x == 0) L.prod0[zslot] = L.prod1[zslot] = 0;
 
     Neurons<NPT> N;
     const T* c0 = (const T*)a.c0 + B.row_off;
@@ -234,7 +263,7 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
         N.rs[q] = N.rn[q] = N.is[q] = N.in[q] = 0;
         N.R[q] = 0;
 #pragma unroll
-        for (int e = 0; e < kInReg / 2; ++e) N.reg_in[q][e] = 0;
+        for (int e = 0; e < kInReg / 2; ++e) N.reg_in[q][e] = ((uint32_t)zslot << 16) | (uint32_t)zslot;
         if (N.valid[q]) {
             N.cnt[q] = (int)c0[j];
             N.rs[q] = a.nrp[B.nrp_off + j];
@@ -246,9 +275,18 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
             for (int e = 0; e < kInReg; ++e)
                 if (e < N.in[q]) {
                     const uint32_t s = (uint32_t)a.in_src[N.is[q] + e] & 0xFFFFu;
-                    N.reg_in[q][e >> 1] |= (e & 1) ? (s << 16) : s;
+                    uint32_t& w = N.reg_in[q][e >> 1];
+                    w = (e & 1) ? ((w & 0xFFFFu) | (s << 16)) : ((w & 0xFFFF0000u) | s);
                 }
         }
+        int kw = min(N.in[q], kInReg), rw = N.rn[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            kw = max(kw, __shfl_xor(kw, o));
+            rw = max(rw, __shfl_xor(rw, o));
+        }
+        N.kw[q] = kw;
+        N.rw[q] = rw;
     }
     T* ckpt = (T*)a.ckpt + B.ckpt_off;  // row q = the configuration at step q * kBatch
     u64* hkey = a.hkey + B.table_off;
@@ -263,23 +301,38 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
     if (threadIdx.x == 0) L.hring[0] = h0;
     int k = 0, batch_start = 0, halt = -1, first_rep = -1;
     bool ovf = false, collision = false;
+    u64 fired = 0;  // bit i: a neuron of this wave fired at the step from C_{batch_start + i}
 
     for (;;) {
         bool done = k >= steps;
         if (!done) {
-            if (det_step<TPB, NPT>(N, L.lrules, (k & 1) ? L.prod1 : L.prod0, a.in_src, a.count_max, ovf)) {
-                ++k;
-                const u64 hw = wave_sum64(h_partial(N));
-                if (lane == 0) L.wpart[(k - batch_start) * W + wid] = hw;
-            } else {
-                halt = k;
-                done = true;
-            }
+            const bool wf = det_step<TPB, NPT>(N, L.lrules, L.lmagic, (k & 1) ? L.prod1 : L.prod0, a.in_src, a.count_max, ovf);
+            fired |= (wf ? 1ULL : 0ULL) << (k - batch_start);
+            ++k;
+            const u64 hw = wave_sum64(h_partial(N));
+            if (lane == 0) L.wpart[(k - batch_start) * W + wid] = hw;
         }
         if (!done && k - batch_start < kBatch) continue;
 
         // ---- batch boundary (or end of run) ----
-        const int nb = k - batch_start;  // H(C_{batch_start + i}) in hring[i], i = 0 .. nb
+        int nb = k - batch_start;  // H(C_{batch_start + i}) in hring[i], i = 0 .. nb
+        // the first configuration of the batch where no neuron fired is halting;
+        // the steps computed after it changed nothing
+        if (lane == 0) L.fired[wid] = fired;
+        __syncthreads();
+        {
+            u64 fm = 0;
+            for (int w = 0; w < W; ++w) fm |= L.fired[w];
+            const u64 stepped = nb >= 64 ? ~0ULL : ((1ULL << nb) - 1);
+            const u64 idle = ~fm & stepped;
+            if (idle) {
+                nb = __builtin_ctzll(idle);
+                k = batch_start + nb;
+                halt = k;
+                done = true;
+            }
+        }
+        fired = 0;
         if (done) store_counts<T, TPB, NPT>(N, (T*)a.final_out + B.row_off);
         else store_counts<T, TPB, NPT>(N, ckpt + (long long)(k / kBatch) * B.ckpt_stride);
         __syncthreads();  // the batch's per-wave partials are complete
@@ -330,11 +383,11 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
                 resimulated = true;
                 load_counts<T, TPB, NPT>(N, ckpt + (long long)(l / kBatch) * B.ckpt_stride);
                 for (int t = (l / kBatch) * kBatch; t < l; ++t)
-                    det_step<TPB, NPT>(N, L.lrules, (t & 1) ? L.prod1 : L.prod0, a.in_src, a.count_max, ovf);
+                    det_step<TPB, NPT>(N, L.lrules, L.lmagic, (t & 1) ? L.prod1 : L.prod0, a.in_src, a.count_max, ovf);
                 store_counts<int, TPB, NPT>(N, L.xrow);
                 load_counts<T, TPB, NPT>(N, ckpt + (long long)(kk / kBatch) * B.ckpt_stride);
                 for (int t = (kk / kBatch) * kBatch; t < kk; ++t)
-                    det_step<TPB, NPT>(N, L.lrules, (t & 1) ? L.prod1 : L.prod0, a.in_src, a.count_max, ovf);
+                    det_step<TPB, NPT>(N, L.lrules, L.lmagic, (t & 1) ? L.prod1 : L.prod0, a.in_src, a.count_max, ovf);
                 bool diff = false;
 #pragma unroll
                 for (int u = 0; u < NPT; ++u)

@@ -124,6 +124,7 @@ struct BatchSys {
 struct BatchArgs {
     const BatchSys* sys;
     const uint32_t* rules;  // packed (i | j << 8 | c << 16 | p << 24)
+    const uint32_t* magic;  // per rule: multiplier for an exact (n - i) / j (j >= 2; 0 otherwise)
     const int* nrp;         // per system: rules of neuron n are [nrp[n], nrp[n+1]) (system-relative)
     const int* in_ptr;      // per system: in-synapses of neuron n are in_src[in_off + in_ptr[n] ..)
     const int* in_src;

@@ -613,7 +613,7 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
         for (int e = 0; e < kLaneMaxIn; ++e) {
             if (e < kin) {
                 const uint32_t y = (uint32_t)__builtin_amdgcn_ds_bpermute(saddr[e], (int)pp);
-                if (e < deg) wv += y;
+                wv += (e < deg) ? y : 0u;
             }
         }
         u64 Hs = wave_sum_u64(act ? (u64)(uint32_t)x * Rj + hv : 0);
@@ -703,7 +703,7 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
                 for (int e = 0; e < kLaneMaxIn; ++e) {
                     if (e < kin) {
                         const uint32_t y = (uint32_t)__builtin_amdgcn_ds_bpermute(saddr[e], (int)pp);
-                        if (e < deg) wv += y;
+                        wv += (e < deg) ? y : 0u;
                     }
                 }
                 Hs = wave_sum_u64(act ? (u64)(uint32_t)x * Rj + hv : 0);
