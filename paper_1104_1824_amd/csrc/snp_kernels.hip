@@ -444,23 +444,30 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
 }
 
 // ---------------------------------------------------------------------------
-// Expansion, one neuron per lane (m <= 64, in-degree <= kLaneMaxIn).  Lane j
-// holds neuron j's parent count, applicable-rule mask (canonical digits in the
-// high half), omega and digit, the consumption c, production p and row hash
-// H(M_k) of its fired rule k, and the set of its in-synapse sources as a
-// 64-bit lane mask.  The child row is kept as w = C + production received
-// (so C' = w - c).  Consecutive children of one parent differ only in the
-// digits the odometer step changes (the last neuron with omega >= 2 that can
-// step up and every later neuron with omega >= 2), so the next child follows
-// from those neurons alone: a changed neuron s with production change dp adds
-// dp to every lane whose source mask holds s.  The row hash follows by
-// linearity, H(C + S.M) = H(C) + sum of H(M_k) over the fired rules k, on the
-// scalar unit.  The first child of a parent or of a run is computed in full by
-// a pull over the in-synapses (ds_bpermute).  Per-child outputs are gathered
-// in lane k % 64 and stored 64 at a time; the next parent's row and the Psi
-// of the next 64 parents are fetched ahead of use.
+// Expansion, one neuron per lane (m <= 64, in-degree <= kLaneMaxIn).  A wave
+// walks runs of consecutive children; a run is cut into segments of one
+// parent each.  Within a segment t_a .. t_b only the digits of V, the neurons
+// with omega >= 2 from the most significant digit where t_a and t_b differ
+// on, ever change, so:
+//   * the first child (the reference) is computed in full, by a pull over the
+//     in-synapses (ds_bpermute) with lane j holding neuron j;
+//   * for every neuron v of V and digit d, lane j keeps in LDS the change
+//     T[v][d][j] that v firing its d-th applicable rule makes to neuron j
+//     (-c on j = v, +p on the targets of v), and H(M_k) of that rule;
+//   * the next child follows by the odometer step over V alone: each changed
+//     neuron adds T[v][new] - T[v][old] per lane and its hash difference to
+//     the row hash (H is linear in the row), which stays on the scalar unit.
+// A child then costs a few vector instructions and one coalesced row store.
+// Counts are kept offset by 2^16 in 32 bits, so negative and too large values
+// stay ordered for the range check (a running minimum and maximum).  A
+// segment whose tables would not fit is cut in half until they do (a single
+// child needs none).  Per-child outputs are gathered in lane k % 64 and
+// stored 64 at a time; the next parent's row and the Psi of the next 64
+// parents are fetched ahead of use.
 // ---------------------------------------------------------------------------
 constexpr int kLaneMaxIn = 16;
+constexpr int kLaneTab = 32;              // table rows per wave: sum of omega over V
+constexpr uint32_t kLaneOff = 1u << 16;   // count offset (c <= 65535)
 
 // Ends the wait for a loaded register here, so that the per-child loop never
 // waits on the row stores it has in flight (one counter covers both).
@@ -506,6 +513,8 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
     u64* l_hM = (u64*)(l_rules + s.r);
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
+    uint32_t* l_tab = (uint32_t*)(smem + (size_t)s.r * 24) + (size_t)wid * (kLaneTab * 64 + 4 * kLaneTab);
+    u64* l_htab = (u64*)(l_tab + kLaneTab * 64);  // [kLaneTab]
     const int m = s.m;
     const bool act = lane < m;
     const int kin = s.max_in;
@@ -523,7 +532,7 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctr->beff = (u64)Beff;
     const long long wpb = blockDim.x >> 6;
     const long long nwaves = (long long)gridDim.x * wpb;
-    const int run = (int)max(4LL, min(1024LL, (Beff + nwaves - 1) / nwaves));
+    const int run = (int)max(4LL, min(4096LL, (Beff + nwaves - 1) / nwaves));
     const long long nruns = (Beff + run - 1) / run;
     if ((long long)blockIdx.x * wpb >= nruns) return;  // the whole block
     for (int q = threadIdx.x; q < s.r; q += blockDim.x) {
@@ -550,8 +559,8 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
     const T* F = (const T*)a.frontier;
     T* stage = (T*)a.stage;
     const long long n = a.n;
-    const uint32_t cmax = (uint32_t)s.count_max;
-    bool ovf = false;
+    const uint32_t hi_ok = (uint32_t)s.count_max + kLaneOff;
+    uint32_t vmin = kLaneOff, vmax = kLaneOff;  // range of the stored counts (offset)
     for (long long rw = wave0; rw < nruns; rw += nwaves) {
         const long long b0 = rw * run;
         const int cnt = (int)min((long long)run, Beff - b0);
@@ -590,9 +599,14 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
         uint32_t am;
         int om;
         lane_applicable(l_rules, r0, r1, x, am, om);
-        // digits of child t: place value of lane j = product of max(1, omega) over later lanes
-        int dg = 0;
-        if (t != 0) {
+
+        u64 o_hash = 0, o_ct = 0;
+        int o_par = 0;
+        int k = 0;
+        while (k < cnt) {
+            // ---- a segment: children t .. t + len - 1 of parent p ----
+            int len = (int)min((u64)(cnt - k), psi_p - t);
+            // place value of lane j: product of max(1, omega) over later lanes
             const u64 w1 = (u64)max(1, om);
             u64 incl = w1;
 #pragma unroll
@@ -602,75 +616,157 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
             }
             u64 after = __shfl_down(incl, 1);
             if (lane == 63) after = 1;
-            dg = (after > t) ? 0 : (int)((t / after) % w1);
-        }
-        uint32_t c, pp;
-        u64 hv;
-        lane_fired(l_rules, l_hM, r0, am, om, dg, c, pp, hv);
-        // the child in full: w = C + production received; H by linearity
-        uint32_t wv = (uint32_t)x;
+            const u64 qa = after > t ? 0 : t / after;
+            const int dg0 = (int)(qa % w1);
+            // V: neurons with omega >= 2 from the most significant digit that
+            // changes inside the segment; halve the segment until its tables fit
+            u64 vmask;
+            int nt;
+            for (;;) {
+                const u64 tb = t + (u64)(len - 1);
+                const u64 qb = after > tb ? 0 : tb / after;
+                const u64 dif = __ballot(act && qa != qb);
+                const int jstar = dif ? __builtin_ctzll(dif) : 64;
+                vmask = __ballot(act && om >= 2 && lane >= jstar);
+                nt = (int)wave_sum_u32((vmask >> lane) & 1 ? (uint32_t)om : 0u);
+                if (nt <= kLaneTab && __popcll(vmask) <= 16) break;
+                len = (len + 1) / 2;
+            }
+            const bool inV = (vmask >> lane) & 1;
+            // table base of every V lane: omega summed over earlier V lanes
+            uint32_t tb_incl = inV ? (uint32_t)om : 0u;
 #pragma unroll
-        for (int e = 0; e < kLaneMaxIn; ++e) {
-            if (e < kin) {
-                const uint32_t y = (uint32_t)__builtin_amdgcn_ds_bpermute(saddr[e], (int)pp);
-                wv += (e < deg) ? y : 0u;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(tb_incl, o);
+                if (lane >= o) tb_incl += y;
             }
-        }
-        u64 Hs = wave_sum_u64(act ? (u64)(uint32_t)x * Rj + hv : 0);
-        u64 v2 = __ballot(act && om >= 2);
+            const int tbase = (int)tb_incl - (inV ? om : 0);
+            // the reference child (digits dg0) in full
+            int dg = dg0;
+            uint32_t c, pp;
+            u64 hv;
+            lane_fired(l_rules, l_hM, r0, am, om, dg, c, pp, hv);
+            uint32_t wv = (uint32_t)x;
+#pragma unroll
+            for (int e = 0; e < kLaneMaxIn; ++e) {
+                if (e < kin) {
+                    const uint32_t y = (uint32_t)__builtin_amdgcn_ds_bpermute(saddr[e], (int)pp);
+                    wv += (e < deg) ? y : 0u;
+                }
+            }
+            uint32_t val = wv - c + kLaneOff;
+            u64 Hs = wave_sum_u64(act ? (u64)(uint32_t)x * Rj + hv : 0);
+            // Step tables.  T[v][d][j]: change to neuron j when V neuron v fires its
+            // d-th applicable rule (-c on j = v, +p on the targets of v).  One
+            // odometer step moves the last V neuron that can step up from d to
+            // d + 1 and resets every later V neuron from its top digit to 0, so
+            // its whole effect is one row per (v, d):
+            //   U[v][d] = T[v][d+1] - T[v][d] + sum over later V neurons v' of
+            //             (T[v'][0] - T[v'][top]),
+            // built in place over T (likewise for the hash and the count of
+            // digits that pick a later twin).  The digits of V are packed in
+            // 4-bit fields of one scalar word, the last V neuron lowest.
+            const int nv = __popcll(vmask);
+            const int vi = __popcll(vmask & ((1ULL << lane) - 1));  // position in V (V lanes)
+            uint32_t* l_nt = (uint32_t*)(l_htab + kLaneTab);           // [kLaneTab]
+            u64 f = 0, fmax = 0;
+            int ubase = 0;  // lane q: first row of the V neuron in field q
+            for (u64 vq = vmask; vq; vq &= vq - 1) {
+                const int v = __builtin_ctzll(vq);
+                const int wv_ = __builtin_amdgcn_readlane(om, v);
+                const int r0v = __builtin_amdgcn_readlane(r0, v);
+                const uint32_t amv = __builtin_amdgcn_readlane(am, v);
+                const int base = __builtin_amdgcn_readlane(tbase, v);
+                const int field = nv - 1 - __builtin_amdgcn_readlane(vi, v);
+                f |= (u64)__builtin_amdgcn_readlane(dg0, v) << (4 * field);
+                fmax |= (u64)(wv_ - 1) << (4 * field);
+                ubase = (lane == field) ? base : ubase;
+                const bool tgt = (inmask >> v) & 1;
+                for (int d = 0; d < wv_; ++d) {
+                    const int kr = r0v + nth_bit(amv & 0xFFFFu, d);
+                    const int4 R = l_rules[kr];
+                    l_tab[(base + d) * 64 + lane] = (lane == v ? (uint32_t)(-R.z) : 0u) + (tgt ? (uint32_t)R.w : 0u);
+                    if (lane == 0) {
+                        l_htab[base + d] = l_hM[kr];
+                        l_nt[base + d] = ((amv >> (16 + d)) & 1u) ? 0u : 1u;
+                    }
+                }
+            }
+            wave_lds_sync();
+            {
+                uint32_t S = 0, nS = 0;
+                u64 hS = 0;
+                for (u64 vq = vmask; vq; vq &= ~(1ULL << (63 - __clzll((long long)vq)))) {
+                    const int v = 63 - __clzll((long long)vq);  // from the last V neuron back
+                    const int wv_ = __builtin_amdgcn_readlane(om, v);
+                    const int base = __builtin_amdgcn_readlane(tbase, v);
+                    const uint32_t t0 = l_tab[base * 64 + lane], tl = l_tab[(base + wv_ - 1) * 64 + lane];
+                    const u64 h0 = l_htab[base], hl = l_htab[base + wv_ - 1];
+                    const uint32_t n0 = l_nt[base], nl = l_nt[base + wv_ - 1];
+                    uint32_t tcur = t0, ncur = n0;
+                    u64 hcur = h0;
+                    for (int d = 0; d + 1 < wv_; ++d) {
+                        const uint32_t tn = l_tab[(base + d + 1) * 64 + lane];
+                        const u64 hn = l_htab[base + d + 1];
+                        const uint32_t nn = l_nt[base + d + 1];
+                        wave_lds_sync();
+                        l_tab[(base + d) * 64 + lane] = tn - tcur + S;
+                        if (lane == 0) {
+                            l_htab[base + d] = hn - hcur + hS;
+                            l_nt[base + d] = nn - ncur + nS;
+                        }
+                        tcur = tn;
+                        hcur = hn;
+                        ncur = nn;
+                    }
+                    S += t0 - tl;
+                    hS += h0 - hl;
+                    nS += n0 - nl;
+                }
+            }
+            wave_lds_sync();
+            // twins: a non-V neuron picking a later twin makes the whole segment
+            // twins; V neurons count their non-canonical digits
+            const bool nc = act && om >= 2 && !((am >> (16 + dg0)) & 1u);
+            const bool fixed_twin = __ballot(nc && !inV) != 0;
+            uint32_t vnc = (uint32_t)__popcll(__ballot(nc && inV));
 
-        u64 o_hash = 0, o_ct = 0;
-        int o_par = 0;
-        for (int k = 0; k < cnt; ++k) {
-            const long long b = b0 + k;
-            const bool twin = __ballot(act && om >= 2 && !((am >> (16 + dg)) & 1u)) != 0;
-            if (!twin && act) {
-                const uint32_t v = wv - c;
-                ovf |= (wv < c) | (v > cmax);
-                stage[b * m + lane] = (T)v;
-            }
-            if (lane == (k & 63)) {
-                o_hash = fmix64(Hs) & a.hash_mask;
-                o_par = twin ? -1 - (int)p : (int)p;
-                o_ct = t;
-            }
-            if ((k & 63) == 63 || k + 1 == cnt) {
-                const long long bb = b0 + (k & ~63) + lane;
-                if (lane <= (k & 63)) {
-                    a.hash[bb] = o_hash;
-                    a.cpar[bb] = o_par;
-                    a.ct[bb] = o_ct;
+            for (int i = 0; i < len; ++i) {
+                const long long b = b0 + k + i;
+                const bool twin = fixed_twin || vnc != 0;
+                if (!twin && act) {
+                    stage[b * m + lane] = (T)(val - kLaneOff);
+                    vmin = min(vmin, val);
+                    vmax = max(vmax, val);
                 }
+                const int kk = (k + i) & 63;
+                const u64 hk = fmix64(Hs) & a.hash_mask;  // uniform: scalar unit
+                const bool mine = lane == kk;
+                o_hash = mine ? hk : o_hash;
+                o_par = mine ? (twin ? -1 - (int)p : (int)p) : o_par;
+                o_ct = mine ? t + (u64)i : o_ct;
+                if (kk == 63 || k + i + 1 == cnt) {
+                    const long long bb = b0 + ((k + i) & ~63) + lane;
+                    if (lane <= kk) {
+                        a.hash[bb] = o_hash;
+                        a.cpar[bb] = o_par;
+                        a.ct[bb] = o_ct;
+                    }
+                }
+                if (i + 1 == len) break;
+                // odometer step on the packed digits: the lowest field below its
+                // top steps up, the fields under it reset (f != fmax inside the segment)
+                const int J4 = __builtin_ctzll(f ^ fmax) & ~3;
+                const int row = __builtin_amdgcn_readlane(ubase, J4 >> 2) + (int)((f >> J4) & 15u);
+                f = (f & ~((1ULL << J4) - 1)) + (1ULL << J4);
+                val += l_tab[row * 64 + lane];
+                Hs += l_htab[row];
+                vnc += l_nt[row];
             }
-            if (k + 1 == cnt) break;
-            ++t;
-            if (t < psi_p) {
-                // odometer: lane J (the last that can step up) steps up, every
-                // later lane with omega >= 2 resets to 0
-                const u64 bm = __ballot(act && om >= 2 && dg < om - 1);
-                if (bm == 0) break;  // unreachable while t < Psi
-                const int J = 63 - __clzll((long long)bm);
-                const u64 chg = (1ULL << J) | (v2 & ~((2ULL << J) - 1));
-                uint32_t dp = 0;
-                u64 dh = 0;
-                if ((chg >> lane) & 1) {
-                    dg = (lane == J) ? dg + 1 : 0;
-                    uint32_t c2, p2;
-                    u64 h2;
-                    lane_fired(l_rules, l_hM, r0, am, om, dg, c2, p2, h2);
-                    dp = p2 - pp;
-                    dh = h2 - hv;
-                    c = c2;
-                    pp = p2;
-                    hv = h2;
-                }
-                for (u64 q = chg; q; q &= q - 1) {
-                    const int j = __builtin_ctzll(q);
-                    Hs += readlane64(dh, j);
-                    const uint32_t dpj = __builtin_amdgcn_readlane(dp, j);
-                    if (dpj != 0 && ((inmask >> j) & 1)) wv += dpj;
-                }
-            } else {
+            k += len;
+            t += (u64)len;
+            if (k >= cnt) break;
+            if (t >= psi_p) {
                 // next parent with Psi > 0
                 u64 nb = __ballot(pw > 0 && lane > cur);
                 while (nb == 0) {
@@ -696,32 +792,22 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
                     pf_x = (int)F[pf_p * (long long)m + jl];
                 }
                 lane_applicable(l_rules, r0, r1, x, am, om);
-                dg = 0;
-                lane_fired(l_rules, l_hM, r0, am, om, 0, c, pp, hv);
-                wv = (uint32_t)x;
-#pragma unroll
-                for (int e = 0; e < kLaneMaxIn; ++e) {
-                    if (e < kin) {
-                        const uint32_t y = (uint32_t)__builtin_amdgcn_ds_bpermute(saddr[e], (int)pp);
-                        wv += (e < deg) ? y : 0u;
-                    }
-                }
-                Hs = wave_sum_u64(act ? (u64)(uint32_t)x * Rj + hv : 0);
-                v2 = __ballot(act && om >= 2);
             }
+            wave_lds_sync();  // the tables are rebuilt for the next segment
         }
     }
+    const bool ovf = vmin < kLaneOff || vmax > hi_ok;
     if (__any(ovf) && lane == 0) atomicOr((unsigned long long*)&a.ctr->overflow, 1ULL);
 }
 
 hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st) {
     if (a.B <= 0) return hipSuccess;
-    if (s.m <= 64 && s.max_in <= kLaneMaxIn && (size_t)s.r * 24 <= 48 * 1024) {
+    if (s.m <= 64 && s.max_in <= kLaneMaxIn && (size_t)s.r * 24 <= 24 * 1024) {
         // at most one wave per SIMD slot of the GPU; runs of 4 to 64 children
         // are handed out on the device, where the chunk's true size is known
         const long long waves = std::min<long long>((a.B + 3) / 4, 8192);
         const unsigned blocks = (unsigned)((waves + 3) / 4);
-        const size_t lds = (size_t)std::max(1, s.r) * 24;
+        const size_t lds = (size_t)std::max(1, s.r) * 24 + 4 * (size_t)(kLaneTab * 64 + 4 * kLaneTab) * 4;
         if (elem_bytes == 4) hipLaunchKernelGGL((k_expand_lane<int32_t>), dim3(blocks), dim3(256), lds, st, s, a);
         else hipLaunchKernelGGL((k_expand_lane<uint16_t>), dim3(blocks), dim3(256), lds, st, s, a);
         return hipGetLastError();
