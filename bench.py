@@ -61,7 +61,7 @@ def run_gpu(system, run_opts, steps, warmup):
 
 
 def walk_timing(system, path, cap, depth, stop, chunk, out_cap, reps):
-    """Median-free simple timing of `reps` complete walks on one path."""
+    """Mean time of `reps` complete walks on one path (after one untimed walk)."""
     import numpy as np
     import torch
 
@@ -69,8 +69,10 @@ def walk_timing(system, path, cap, depth, stop, chunk, out_cap, reps):
 
     h = snp.snp_load(system, path=path, frontier_cap=cap, stop_at_cap=stop, max_rows=out_cap, chunk=chunk,
                      profile=True)
-    c0 = torch.tensor(np.asarray(system.c0, dtype=np.int32), device="cuda")
-    out = torch.empty((out_cap, system.m), dtype=torch.int32, device="cuda")
+    u16 = system.count_type == "u16"
+    c0 = np.asarray(system.c0, dtype=np.int64)
+    c0 = torch.from_numpy(c0.astype(np.uint16).view(np.int16) if u16 else c0.astype(np.int32)).cuda()
+    out = torch.empty((out_cap, system.m), dtype=torch.int16 if u16 else torch.int32, device="cuda")
     snp.snp_run(h, c0, depth, out, out_cap)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -82,7 +84,7 @@ def walk_timing(system, path, cap, depth, stop, chunk, out_cap, reps):
     st = r["level_stats"]
     ns = sum(s_["ns_expand"] for s_ in st)
     expanded = sum(s_["expanded"] for s_ in st)
-    rb = system.m * 4
+    rb = system.m * (2 if u16 else 4)
     return dict(ms_per_walk=round(dt * 1e3, 3), new_configs=int(r["n_configs"] - 1),
                 configs_per_s=round((r["n_configs"] - 1) / dt, 1), levels=r["level_sizes"].tolist(),
                 expand_us=round(ns / 1e3, 1), expand_gbs=round(expanded * (rb + 20) / max(ns, 1), 1),
@@ -90,19 +92,20 @@ def walk_timing(system, path, cap, depth, stop, chunk, out_cap, reps):
                           for k in ("psi", "expand", "insert", "flags", "commit")})
 
 
-def extras_int8_and_batched():
-    """Secondary measurements: the int8 matrix-core form next to the sparse form
-    (plain-sparse workload and the dense m=512 workload), and the batched
-    deterministic launch (256 systems x 10k steps)."""
-    import numpy as np
-    import torch
-
+def extra_plain_int8():
+    """The plain-sparse workload on the int8 matrix-core form."""
     import synth
     from paper_1104_1824_amd import snp
 
-    out = {}
-    s2 = synth.config_system(2, 0)
-    out["plain_sparse_int8_path"] = walk_timing(s2, snp.SNP_PATH_INT8, 100000, 1000, True, 1 << 17, 200000, 10)
+    log("plain sparse workload, int8 path")
+    return walk_timing(synth.config_system(2, 0), snp.SNP_PATH_INT8, 100000, 1000, True, 1 << 17, 200000, 10)
+
+
+def extra_dense():
+    """Dense m=512 workload: the int8 matrix-core form next to the sparse form."""
+    import synth
+    from paper_1104_1824_amd import snp
+
     s3 = synth.config_system(3, 0)
     dense = {}
     for name, path, reps in (("int8", snp.SNP_PATH_INT8, 3), ("sparse", snp.SNP_PATH_SPARSE, 1)):
@@ -111,7 +114,29 @@ def extras_int8_and_batched():
     dense["speedup_int8_over_sparse"] = round(dense["sparse"]["ms_per_walk"] / dense["int8"]["ms_per_walk"], 2)
     dense["workload"] = ("dense_int8: m=512, 3 rules/neuron (r=1536), p in [0,4] (M entries in [-4,4]), "
                          "out-degree 64, C0 in [0,4], int32; BFS depth 3, frontier_cap 1e6 per level (seed 0)")
-    out["dense_int8"] = dense
+    return dense
+
+
+def extra_large():
+    """Large exploration: m=4096, uint16, depth 3, cap 4e6 per level, automatic path."""
+    import synth
+    from paper_1104_1824_amd import snp
+
+    log("large m=4096 uint16 workload, automatic path, depth 3, cap 4e6")
+    r = walk_timing(synth.config_system(5, 0), snp.SNP_PATH_AUTO, 4000000, 3, False, 1 << 19, 12000001, 1)
+    r["workload"] = ("large: m=4096, 4 rules/neuron (r=16384), out-degree 16, C0 in [0,8], uint16; BFS depth 3, "
+                     "frontier_cap 4e6 per level (seed 0)")
+    return r
+
+
+def extra_batched():
+    """The batched deterministic launch (256 systems x 10k steps)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1104_1824_amd import snp
+
     log("batched deterministic launch, 256 systems x 10k steps")
     systems = synth.batched_systems(0, 256)
     b = snp.snp_batch_load(systems)
@@ -126,20 +151,48 @@ def extras_int8_and_batched():
         snp.snp_batch_run(b, c0, 10000, fin)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
+    shape = snp.snp_batch_shape(b)
     b.close()
-    out["batched"] = dict(
+    return dict(
         workload="batched_uneven: 256 systems, m in [16,1024], 1-3 rules and out-degree 2-32 per neuron, "
                  "10k deterministic steps each, one launch (seeds 0-255)",
         ms_per_launch=round(dt * 1e3, 3), system_steps=256 * 10000,
-        configs_per_s=round(256 * 10000 / dt, 1))
-    return out
+        system_steps_per_s=round(256 * 10000 / dt, 1),
+        threads_per_system=shape[0], neurons_per_thread=shape[1])
+
+
+EXTRAS = {"plain_sparse_int8_path": extra_plain_int8, "dense_int8": extra_dense, "large": extra_large,
+          "batched": extra_batched}
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_expand_lane_plain_sparse_m64_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1104_1824_amd", "csrc", "snp_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the expansion kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter runs (scaled by the copy calibration), or
+    None when the kernel source changed since they were taken."""
+    import hashlib
+
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    fields = {}
+    for ln in open(TRAFFIC_FILE):
+        if ":" in ln and ln.strip().startswith("- `"):
+            k, v = ln.strip()[3:].split("`:", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
 
 
 def roofline(system, results):
     """Roofline of the expansion kernel: its algorithmic bytes over its device
     time.  Algorithmic bytes per launch = children computed x (row bytes written
     + 20 B of per-child hash, parent index and child index); parent rows, read
-    once per run of children, are not counted."""
+    once per segment of children, are not counted."""
     rb = system.m * 4
     tot = dict(psi=0, expand=0, insert=0, flags=0, commit=0)
     launches = 0
@@ -154,14 +207,14 @@ def roofline(system, results):
     bytes_expand = children * (rb + 20)
     achieved = bytes_expand / max(1, tot["expand"])  # bytes per ns = GB/s
     return dict(
-        kernel="k_expand_sparse",
+        kernel="k_expand_lane",
         dominant_stage=max(tot, key=tot.get),
         bound="hbm",
         achieved=round(achieved, 2),
         peak=HBM_PEAK_GBS,
         unit="GB/s",
         frac=round(achieved / HBM_PEAK_GBS, 4),
-        traffic=None,
+        traffic=measured_traffic(),
         bytes_per_launch=round(bytes_expand / max(1, launches)),
         avg_launch_us=round(tot["expand"] / max(1, launches) / 1e3, 3),
         launches_per_step=launches // max(1, steps),
@@ -208,12 +261,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the int8 / dense / batched side measurements")
+    ap.add_argument("--only", choices=sorted(EXTRAS), help="run only this side measurement and print it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reads 1 GiB, writes 1 GiB) five times, to scale "
                          "FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.only:
+        print(json.dumps({args.only: EXTRAS[args.only]()}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X; --gpus must be 1", file=sys.stderr)
@@ -235,7 +292,7 @@ def main():
     log(f"stage us/step {rl['stage_us_per_step']}")
     extras = None
     if not args.no_extras:
-        extras = extras_int8_and_batched()
+        extras = {name: fn() for name, fn in EXTRAS.items()}
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on the same workload")
