@@ -43,7 +43,7 @@ def run_gpu(system, run_opts, steps, warmup):
 
     cap = 200000
     h = snp.snp_load(system, path=snp.SNP_PATH_SPARSE, frontier_cap=run_opts["frontier_cap"],
-                     stop_at_cap=run_opts["stop_at_cap"], max_rows=cap, chunk=1 << 17, profile=True)
+                     stop_at_cap=run_opts["stop_at_cap"], max_rows=cap, chunk=1 << 17, profile=1)
     c0 = torch.tensor(system.c0, dtype=torch.int32, device="cuda")
     out = torch.empty((cap, system.m), dtype=torch.int32, device="cuda")
     res = None
@@ -68,7 +68,7 @@ def walk_timing(system, path, cap, depth, stop, chunk, out_cap, reps):
     from paper_1104_1824_amd import snp
 
     h = snp.snp_load(system, path=path, frontier_cap=cap, stop_at_cap=stop, max_rows=out_cap, chunk=chunk,
-                     profile=True)
+                     profile=2)
     u16 = system.count_type == "u16"
     c0 = np.asarray(system.c0, dtype=np.int64)
     c0 = torch.from_numpy(c0.astype(np.uint16).view(np.int16) if u16 else c0.astype(np.int32)).cuda()
@@ -194,21 +194,19 @@ def roofline(system, results):
     + 20 B of per-child hash, parent index and child index); parent rows, read
     once per segment of children, are not counted."""
     rb = system.m * 4
-    tot = dict(psi=0, expand=0, insert=0, flags=0, commit=0)
+    ns = 0
     launches = 0
     children = 0
     for r in results:
         for st in r["level_stats"]:
-            for k in tot:
-                tot[k] += st["ns_" + k]
+            ns += st["ns_expand"]
             launches += st["chunks"]
             children += st["expanded"]
     steps = len(results)
     bytes_expand = children * (rb + 20)
-    achieved = bytes_expand / max(1, tot["expand"])  # bytes per ns = GB/s
+    achieved = bytes_expand / max(1, ns)  # bytes per ns = GB/s
     return dict(
         kernel="k_expand_lane",
-        dominant_stage=max(tot, key=tot.get),
         bound="hbm",
         achieved=round(achieved, 2),
         peak=HBM_PEAK_GBS,
@@ -216,9 +214,9 @@ def roofline(system, results):
         frac=round(achieved / HBM_PEAK_GBS, 4),
         traffic=measured_traffic(),
         bytes_per_launch=round(bytes_expand / max(1, launches)),
-        avg_launch_us=round(tot["expand"] / max(1, launches) / 1e3, 3),
+        avg_launch_us=round(ns / max(1, launches) / 1e3, 3),
         launches_per_step=launches // max(1, steps),
-        stage_us_per_step={k: round(v / 1e3 / max(1, steps), 2) for k, v in tot.items()},
+        expand_us_per_step=round(ns / 1e3 / max(1, steps), 2),
     )
 
 
@@ -289,7 +287,7 @@ def main():
     value = args.steps * new_per_step / dt
     log(f"levels {sizes}, {new_per_step} new configurations per step, {dt / args.steps * 1e3:.3f} ms/step")
     rl = roofline(system, results)
-    log(f"stage us/step {rl['stage_us_per_step']}")
+    log(f"expansion kernel {rl['expand_us_per_step']} us per step")
     extras = None
     if not args.no_extras:
         extras = {name: fn() for name, fn in EXTRAS.items()}
@@ -320,8 +318,8 @@ def main():
             "parallelism": "single GPU",
         },
         "roofline": {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
-        "dominant_kernel": {k: rl[k] for k in ("kernel", "dominant_stage", "bytes_per_launch", "avg_launch_us",
-                                                "launches_per_step", "stage_us_per_step")},
+        "dominant_kernel": {k: rl[k] for k in ("kernel", "bytes_per_launch", "avg_launch_us", "launches_per_step",
+                                                "expand_us_per_step")},
         "cpu_baseline": cpu,
         "extras": extras,
     }

@@ -121,8 +121,9 @@ typedef struct {
     int64_t chunk;            /* most children expanded per device pass; 0: automatic */
     uint64_t hash_mask;       /* 0: full 64-bit configuration hash; otherwise the hash is
                                  ANDed with it (forces collisions; results do not change) */
-    int32_t profile;          /* nonzero: time every stage with HIP events on the handle's
-                                 stream and report it in snp_expand_stats.ns_* */
+    int32_t profile;          /* 1: time the child expansion kernel with HIP events on the
+                                 handle's stream (snp_expand_stats.ns_expand); >= 2: time every
+                                 stage (every ns_* field); 0: no events */
     int32_t int8_max_k;       /* int8 path: most rule columns (1..128) one segment of children
                                  may put on the matrix cores, 0: 128; segments that need more
                                  take the per-child sparse form (smaller values force it;
@@ -148,10 +149,10 @@ typedef struct {
     int32_t budget_hit;      /* 1: child_budget ran out with children left */
     int32_t path_used;       /* snp_path of the last chunk (SPARSE or INT8) */
     int32_t int8_fallback;   /* 1: INT8 was requested but M does not fit int8 */
-    /* Device time of each stage summed over the level's passes, in ns, when the
-     * handle was loaded with profile != 0 (else 0): applicability + Psi and its
-     * prefix sum; child expansion (S.M + C); visited-set insert; first-occurrence
-     * flags and their prefix sum; ordered commit. */
+    /* Device time of each stage summed over the level's passes, in ns (0 when
+     * not timed; see snp_options.profile): applicability + Psi and its prefix
+     * sum; child expansion (S.M + C); visited-set insert; first-occurrence flags
+     * and their prefix sum; ordered commit. */
     int64_t ns_psi, ns_expand, ns_insert, ns_flags, ns_commit;
 } snp_expand_stats;
 

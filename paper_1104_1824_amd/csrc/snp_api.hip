@@ -229,8 +229,10 @@ snp_status add_elapsed(snp_system* S, int a, int b, int64_t* acc) {
     return SNP_OK;
 }
 
+// Stage marks 0..5; profile 1 records only 1 and 2 (around the expansion kernel).
 snp_status mark(snp_system* S, int k) {
-    if (S->opt.profile) HIPCHK(hipEventRecord(S->ev[k], S->stream));
+    if (S->opt.profile >= 2 || (S->opt.profile == 1 && (k == 1 || k == 2)))
+        HIPCHK(hipEventRecord(S->ev[k], S->stream));
     return SNP_OK;
 }
 
@@ -418,7 +420,9 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         HIPCHK(snp::launch_commit(S->elem_bytes, S->m, cm, S->stream));
         if ((st = mark(S, 5))) return st;
         if ((st = read_counters(S))) return st;
-        if (S->opt.profile) {
+        if (S->opt.profile == 1) {
+            if ((st = add_elapsed(S, 1, 2, &stt.ns_expand))) return st;
+        } else if (S->opt.profile >= 2) {
             if ((st = add_elapsed(S, 0, 1, &stt.ns_psi))) return st;
             if ((st = add_elapsed(S, 1, 2, &stt.ns_expand))) return st;
             if ((st = add_elapsed(S, 2, 3, &stt.ns_insert))) return st;

@@ -803,9 +803,10 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
 hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st) {
     if (a.B <= 0) return hipSuccess;
     if (s.m <= 64 && s.max_in <= kLaneMaxIn && (size_t)s.r * 24 <= 24 * 1024) {
-        // at most one wave per SIMD slot of the GPU; runs of 4 to 64 children
-        // are handed out on the device, where the chunk's true size is known
-        const long long waves = std::min<long long>((a.B + 3) / 4, 8192);
+        // one generation of resident waves (the LDS tables allow 16 per CU);
+        // runs of 4 to 4096 children are handed out on the device, where the
+        // chunk's true size is known
+        const long long waves = std::min<long long>((a.B + 3) / 4, 4096);
         const unsigned blocks = (unsigned)((waves + 3) / 4);
         const size_t lds = (size_t)std::max(1, s.r) * 24 + 4 * (size_t)(kLaneTab * 64 + 4 * kLaneTab) * 4;
         if (elem_bytes == 4) hipLaunchKernelGGL((k_expand_lane<int32_t>), dim3(blocks), dim3(256), lds, st, s, a);

@@ -174,7 +174,7 @@ def _stream_ptr(stream):
 
 def snp_load(system, *, path: int = SNP_PATH_AUTO, stop_at_cap: bool = False, frontier_cap: int = 0,
              child_budget: int = 0, expand_max_count: int = -1, max_rows: int = 1 << 20,
-             max_frontier: int = 0, chunk: int = 0, hash_mask: int = 0, profile: bool = False,
+             max_frontier: int = 0, chunk: int = 0, hash_mask: int = 0, profile: int = 0,
              int8_max_k: int = 0, stream=None, M: Optional[np.ndarray] = None) -> Handle:
     """snp_load.  ``system`` has m, rule_neuron/i/j/c/p, syn_src/dst and
     count_type ("i32" or "u16") attributes; ``stream`` is a torch.cuda.Stream
@@ -185,7 +185,7 @@ def snp_load(system, *, path: int = SNP_PATH_AUTO, stop_at_cap: bool = False, fr
     sp = _stream_ptr(stream)
     o = snp_options(int(path), int(bool(stop_at_cap)), int(frontier_cap), int(child_budget),
                     int(expand_max_count), int(max_rows), int(max_frontier), int(chunk),
-                    int(hash_mask) & ((1 << 64) - 1), int(bool(profile)), int(int8_max_k), sp or None)
+                    int(hash_mask) & ((1 << 64) - 1), int(profile), int(int8_max_k), sp or None)
     out = ctypes.c_void_p()
     _check(lib().snp_load(ctypes.byref(d), ctypes.byref(o), ctypes.byref(out)), "snp_load")
     return Handle(out.value, arrs, int(system.m), ct)
