@@ -222,7 +222,10 @@ snp_status snp_expand(snp_system *sys, const void *frontier_dev, int64_t n, void
  *     within its parent (canonical order), -1 for C0.
  * Errors: SNP_ERR_CAPACITY when out_capacity, max_levels or max_rows is too
  *   small (rows and levels written so far stay valid and *n_configs, *n_levels
- *   say how many); SNP_ERR_OVERFLOW as for snp_expand. */
+ *   say how many); SNP_ERR_OVERFLOW as for snp_expand, and when C0 holds a
+ *   count outside the type's range (C0 is checked on the device together
+ *   with the first level, so that level costs no wait of its own; the outputs
+ *   are then not meaningful). */
 snp_status snp_run(snp_system *sys, const void *c0_dev, int32_t max_depth, void *out_dev,
                    int64_t out_capacity, int64_t *n_configs, int64_t *level_sizes, int32_t max_levels,
                    int32_t *n_levels, int32_t *stop_reason, snp_expand_stats *level_stats,

@@ -94,13 +94,15 @@ struct snp_system {
     u64* d_ct = nullptr;
     uint32_t *d_slot = nullptr, *d_flag = nullptr, *d_pos = nullptr, *d_fsums = nullptr, *d_fpre = nullptr;
     uint32_t* d_cand = nullptr;
-    // counters: a ring of slots, one per device pass, zeroed once per kRing passes
+    // counters: a ring of slots, one per device pass, zeroed once per kRing passes,
+    // and one more slot (index kRing) for the checks made when a walk starts
     static constexpr int kRing = 64;
     snp::DevCounters* d_ring = nullptr;
     snp::DevCounters* d_ctr = nullptr;  // slot of the current pass
     long long pass = 0;
     u64* d_T = nullptr;                 // children of the examined frontier prefix (device)
-    snp::DevCounters* h_ctr = nullptr;
+    snp::DevCounters* h_ctr = nullptr;  // [2]: the pass read last, the walk start
+    bool start_pending = false;         // the walk start's checks are not read yet
 
     // caller-driven walk (snp_reset / snp_expand): the handle's own row store
     void* d_store = nullptr;
@@ -247,9 +249,20 @@ snp_status validate_options(const snp_options* o) {
     return SNP_OK;
 }
 
+// Copy the current pass's counters to the host and wait for the stream.  The
+// checks of a walk start still unread ride along and are reported first.
 snp_status read_counters(snp_system* S) {
+    const bool start = S->start_pending;
+    if (start)
+        HIPCHK(hipMemcpyAsync(S->h_ctr + 1, S->d_ring + snp_system::kRing, sizeof(snp::DevCounters),
+                              hipMemcpyDeviceToHost, S->stream));
     HIPCHK(hipMemcpyAsync(S->h_ctr, S->d_ctr, sizeof(snp::DevCounters), hipMemcpyDeviceToHost, S->stream));
     HIPCHK(hipStreamSynchronize(S->stream));
+    if (start) {
+        S->start_pending = false;
+        if (S->h_ctr[1].overflow) return fail(SNP_ERR_OVERFLOW, "C0 holds a count outside the count type's range");
+        if (S->h_ctr[1].probe_fail) return fail(SNP_ERR_DEVICE, "visited set: no free slot");
+    }
     return SNP_OK;
 }
 
@@ -264,13 +277,12 @@ snp_status clear_counters(snp_system* S) {
     return SNP_OK;
 }
 
-// Empty the visited set and insert rows [0, rows) of the row store, in the
-// current counter slot.
-snp_status fill_table(snp_system* S, const void* arena, long long rows) {
+// Empty the visited set and insert rows [0, rows) of the row store, counting
+// in ctr.
+snp_status fill_table(snp_system* S, const void* arena, long long rows, snp::DevCounters* ctr) {
     HIPCHK(snp::launch_fill_u64(S->d_table, (long long)S->slots, snp::kEmpty, S->stream));
     HIPCHK(snp::launch_rows_insert(S->elem_bytes, S->m, S->d_R, S->d_table, S->slots - 1, arena, 0, rows,
-                                   S->opt.hash_mask ? S->opt.hash_mask : ~0ULL, S->d_row_slot, S->d_ctr,
-                                   S->stream));
+                                   S->opt.hash_mask ? S->opt.hash_mask : ~0ULL, S->d_row_slot, ctr, S->stream));
     S->tombs = 0;
     return SNP_OK;
 }
@@ -279,24 +291,27 @@ snp_status fill_table(snp_system* S, const void* arena, long long rows) {
 snp_status rebuild_table(snp_system* S, const void* arena, long long rows) {
     snp_status st;
     if ((st = clear_counters(S))) return st;
-    if ((st = fill_table(S, arena, rows))) return st;
+    if ((st = fill_table(S, arena, rows, S->d_ctr))) return st;
     if ((st = read_counters(S))) return st;
     if (S->h_ctr->probe_fail) return fail(SNP_ERR_DEVICE, "visited set: no free slot");
     return SNP_OK;
 }
 
-// Record C0 as the only visited configuration, stored at arena row 0.
-snp_status start_walk(snp_system* S, const void* c0_dev, void* arena) {
+// Record C0 as the only visited configuration, stored at arena row 0.  Its
+// range check counts in the walk-start slot; with `wait` false the result is
+// read (and a bad C0 reported) by the next read_counters, so the first level
+// costs no synchronisation of its own.  The kernels never index memory by a
+// count, so a level expanded from a bad C0 stays in bounds before the error.
+snp_status start_walk(snp_system* S, const void* c0_dev, void* arena, bool wait) {
     if (!c0_dev) return fail(SNP_ERR_INVALID, "c0 is NULL");
-    snp_status st;
-    if ((st = clear_counters(S))) return st;
+    snp::DevCounters* sc = S->d_ring + snp_system::kRing;
+    HIPCHK(hipMemsetAsync(sc, 0, sizeof(snp::DevCounters), S->stream));
     if (arena != c0_dev) HIPCHK(hipMemcpyAsync(arena, c0_dev, row_bytes(S), hipMemcpyDeviceToDevice, S->stream));
-    HIPCHK(snp::launch_check_rows(S->elem_bytes, arena, S->m, S->count_max, S->d_ctr, S->stream));
-    if ((st = fill_table(S, arena, 1))) return st;
-    if ((st = read_counters(S))) return st;
-    if (S->h_ctr->overflow) return fail(SNP_ERR_OVERFLOW, "C0 holds a count outside the count type's range");
-    if (S->h_ctr->probe_fail) return fail(SNP_ERR_DEVICE, "visited set: no free slot");
-    return SNP_OK;
+    HIPCHK(snp::launch_check_rows(S->elem_bytes, arena, S->m, S->count_max, sc, S->stream));
+    snp_status st;
+    if ((st = fill_table(S, arena, 1, sc))) return st;
+    S->start_pending = true;
+    return wait ? read_counters(S) : SNP_OK;
 }
 
 struct LevelIO {
@@ -368,7 +383,8 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
     u64 G = 0;
     u64 enumerated = 0;
     bool cap_hit = false, budget_hit = false;
-    long long p_end = -1;  // parents up to the last enumerated child's (for the halting count)
+    long long p_end = -1;  // parents up to the last child within the budget (for the halting count)
+    long long halting_cap = -1;  // halting parents up to the cap's child's parent, counted in its pass
     for (;;) {
         if (G >= budget) {  // the budget is spent: is anything left?
             while (T <= G && P < io.n) {
@@ -411,13 +427,18 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
                           S->d_cand, S->d_cpar};
         HIPCHK(snp::launch_insert(S->elem_bytes, S->m, ta, S->stream));
         if ((st = mark(S, 3))) return st;
-        HIPCHK(snp::launch_flags(S->d_table, S->d_slot, S->d_cpar, B, S->d_ctr, S->d_flag, S->stream));
-        HIPCHK(snp::launch_scan_u32(S->d_flag, S->d_pos, B, S->d_fsums, S->d_fpre, &S->d_ctr->total, S->stream));
+        HIPCHK(snp::launch_flags(S->d_table, S->d_slot, S->d_cpar, B, S->d_ctr, S->d_flag, S->d_pos, S->d_fsums,
+                                 S->d_fpre, S->stream));
         if ((st = mark(S, 4))) return st;
-        snp::CommitArgs cm{S->d_table, S->d_table, S->d_slot, S->d_hash, S->d_pos, S->d_flag, S->d_stage,
+        snp::CommitArgs cm{S->d_table, S->d_table, S->d_slot, S->d_hash, S->d_pos, S->d_flag, S->d_fsums, S->d_fpre,
+                           S->d_stage,
                            S->d_cpar, S->d_ct, B, io.arena, io.level_base, count, limit, io.row2, io.par_out,
                            io.par_out_base, io.par_value_base, io.t_out, S->d_row_slot, S->d_ctr};
         HIPCHK(snp::launch_commit(S->elem_bytes, S->m, cm, S->stream));
+        // when this pass may fill the cap, count the halting parents up to the
+        // parent of the cap's child in the same pass (no extra synchronisation)
+        const bool may_cap = sem_binds && B >= limit - count;
+        if (may_cap) HIPCHK(snp::launch_count_flags_cap(S->d_hflag, P, S->d_ctr, S->stream));
         if ((st = mark(S, 5))) return st;
         if ((st = read_counters(S))) return st;
         if (S->opt.profile == 1) {
@@ -452,7 +473,7 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
             count = limit;
             cap_hit = true;
             enumerated = G + c.cap_g;
-            p_end = (long long)c.cap_par + 1;
+            halting_cap = (long long)c.count;
             break;
         }
         if (new_total > avail) {
@@ -472,7 +493,9 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
     }
     // halting parents up to the parent of the last enumerated child (all parents
     // when the level was not cut short by the cap or the budget)
-    if (cap_hit || budget_hit) {
+    if (cap_hit) {
+        stt.halting_parents = halting_cap;
+    } else if (budget_hit) {
         if ((st = clear_counters(S))) return st;
         HIPCHK(snp::launch_count_flags(S->d_hflag, p_end, &S->d_ctr->count, S->stream));
         if ((st = read_counters(S))) return st;
@@ -637,10 +660,10 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     LOADCHK(dmalloc(&S->d_pos, sizeof(uint32_t) * C));
     LOADCHK(dmalloc(&S->d_fsums, sizeof(uint32_t) * ft));
     LOADCHK(dmalloc(&S->d_fpre, sizeof(uint32_t) * ft));
-    LOADCHK(dmalloc(&S->d_ring, sizeof(snp::DevCounters) * snp_system::kRing));
+    LOADCHK(dmalloc(&S->d_ring, sizeof(snp::DevCounters) * (snp_system::kRing + 1)));
     LOADCHK(dmalloc(&S->d_T, sizeof(u64)));
     S->d_ctr = S->d_ring;
-    LOADCHK(hipHostMalloc((void**)&S->h_ctr, sizeof(snp::DevCounters), hipHostMallocDefault));
+    LOADCHK(hipHostMalloc((void**)&S->h_ctr, 2 * sizeof(snp::DevCounters), hipHostMallocDefault));
     if (opt.profile)
         for (hipEvent_t& e : S->ev) LOADCHK(hipEventCreate(&e));
 #undef LOADCHK
@@ -653,7 +676,7 @@ snp_status snp_reset(snp_system* S, const void* c0_dev) {
     if (!S) return fail(SNP_ERR_INVALID, "handle is NULL");
     if (!S->d_store) HIPCHK(dmalloc(&S->d_store, (size_t)(S->max_rows * row_bytes(S))));
     S->walk_active = false;
-    snp_status st = start_walk(S, c0_dev, S->d_store);
+    snp_status st = start_walk(S, c0_dev, S->d_store, true);
     if (st) return st;
     S->walk_active = true;
     S->walk_rows = 1;
@@ -701,7 +724,7 @@ snp_status snp_run(snp_system* S, const void* c0_dev, int32_t max_depth, void* o
     S->walk_active = false;
     if (level_stats) memset(level_stats, 0, sizeof(snp_expand_stats) * (size_t)max_levels);
     const long long rb = row_bytes(S);
-    snp_status st = start_walk(S, c0_dev, out_dev);
+    snp_status st = start_walk(S, c0_dev, out_dev, false);
     if (st) return st;
     if (parent_of) HIPCHK(hipMemsetAsync(parent_of, 0xFF, sizeof(int64_t), S->stream));  // -1 for C0
     if (child_of) HIPCHK(hipMemsetAsync(child_of, 0xFF, sizeof(int64_t), S->stream));
@@ -749,6 +772,7 @@ snp_status snp_run(snp_system* S, const void* c0_dev, int32_t max_depth, void* o
         if (count == 0) { stop = SNP_STOP_EMPTY_FRONTIER; break; }
     }
     *stop_reason = stop;
+    if (S->start_pending) return read_counters(S);  // no level ran: check C0 now
     HIPCHK(hipStreamSynchronize(S->stream));
     return SNP_OK;
 }

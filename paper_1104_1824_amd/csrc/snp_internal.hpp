@@ -90,8 +90,10 @@ struct CommitArgs {
     u64* table;
     const uint32_t* slot;
     const u64* hash;
-    const uint32_t* pos;   // [B] exclusive scan of the new-child flags
+    const uint32_t* pos;   // [B] exclusive scan of the new-child flags within each scan tile
     const uint32_t* flag;  // [B] 1: child is the first occurrence of a new configuration
+    const uint32_t* tile_sums;  // [tiles] flags of every scan tile
+    const uint32_t* tile_pre;   // [tiles] exclusive scan of tile_sums (filled only for many tiles)
     const void* stage;
     const int* cpar;
     const u64* ct;
@@ -156,15 +158,14 @@ hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, 
 hipError_t launch_scan_u64(const u64* in, u64* out, long long n, u64* tile_sums, u64* tile_pre,
                            u64* total, const u64* base_dev, u64* total_copy, hipStream_t st);
 hipError_t launch_count_flags(const uint8_t* flags, long long n, u64* out, hipStream_t st);
-hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, long long n, uint32_t* tile_sums,
-                           uint32_t* tile_pre, u64* total, hipStream_t st);
+hipError_t launch_count_flags_cap(const uint8_t* flags, long long n, DevCounters* ctr, hipStream_t st);
 long long scan_tiles(long long n);
 hipError_t launch_expand_int8(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st);
 size_t int8_lds(int m, int nt);
 hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st);
 hipError_t launch_insert(int elem_bytes, int m, const TableArgs& a, hipStream_t st);
-hipError_t launch_flags(const u64* table, const uint32_t* slot, const int* cpar, long long B, const DevCounters* ctr,
-                        uint32_t* flag, hipStream_t st);
+hipError_t launch_flags(const u64* table, const uint32_t* slot, const int* cpar, long long B, DevCounters* ctr,
+                        uint32_t* flag, uint32_t* pos, uint32_t* tile_sums, uint32_t* tile_pre, hipStream_t st);
 hipError_t launch_commit(int elem_bytes, int m, const CommitArgs& a, hipStream_t st);
 hipError_t launch_fill_u64(u64* p, long long n, u64 v, hipStream_t st);
 hipError_t launch_rows_insert(int elem_bytes, int m, const u64* R, u64* table, u64 slot_mask, const void* arena,

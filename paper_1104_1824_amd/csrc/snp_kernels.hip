@@ -220,10 +220,7 @@ hipError_t launch_scan_u64(const u64* in, u64* out, long long n, u64* tile_sums,
     return scan_impl<u64, true>(in, out, n, tile_sums, tile_pre, total, base_dev, total_copy, st);
 }
 
-hipError_t launch_scan_u32(const uint32_t* in, uint32_t* out, long long n, uint32_t* tile_sums,
-                           uint32_t* tile_pre, u64* total, hipStream_t st) {
-    return scan_impl<uint32_t, false>(in, out, n, tile_sums, tile_pre, total, nullptr, nullptr, st);
-}
+
 
 __global__ __launch_bounds__(256) void k_count_flags(const uint8_t* __restrict__ f, long long n, u64* out) {
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -235,6 +232,24 @@ __global__ __launch_bounds__(256) void k_count_flags(const uint8_t* __restrict__
 hipError_t launch_count_flags(const uint8_t* flags, long long n, u64* out, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_count_flags, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, flags, n, out);
+    return hipGetLastError();
+}
+
+// The same count over flags [0, cap_par + 1) when the pass's commit filled the
+// cap (cap_g != 0), else nothing; n bounds the flags computed so far.
+__global__ __launch_bounds__(256) void k_count_flags_cap(const uint8_t* __restrict__ f, long long n,
+                                                         DevCounters* ctr) {
+    if (ctr->cap_g == 0) return;
+    const long long lim = min(n, (long long)ctr->cap_par + 1);
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    const bool v = i < lim && f[i] != 0;
+    const u64 bm = __ballot(v);
+    if ((threadIdx.x & 63) == 0 && bm) atomicAdd((unsigned long long*)&ctr->count, (u64)__popcll(bm));
+}
+
+hipError_t launch_count_flags_cap(const uint8_t* flags, long long n, DevCounters* ctr, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count_flags_cap, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, flags, n, ctr);
     return hipGetLastError();
 }
 
@@ -962,19 +977,59 @@ hipError_t launch_insert(int elem_bytes, int m, const TableArgs& a, hipStream_t 
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_flags(const u64* __restrict__ table, const uint32_t* __restrict__ slot,
-                                               const int* __restrict__ cpar, long long B,
-                                               const DevCounters* __restrict__ ctr, uint32_t* __restrict__ flag) {
-    const long long b = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (b >= B) return;
-    flag[b] = (b < (long long)ctr->beff && cpar[b] >= 0 && (uint32_t)table[slot[b]] == kStageBase + (uint32_t)b)
-                  ? 1u : 0u;
+// Up to this many scan tiles, every commit block sums the tile counts before
+// its own tile itself (one wave, a few loads each), so the flags need no
+// separate scan of tile sums.
+constexpr long long kCommitTiles = 1024;
+
+// New-child flags of a chunk: flag[b] = 1 when child b is enumerated
+// (b < beff), not a twin, and owns its visited-set entry.  Within each tile
+// of kScanTile children, pos[b] = flags before b and tile_sums[tile] = all
+// flags of the tile.
+__global__ __launch_bounds__(256) void k_flag_tiles(const u64* __restrict__ table, const uint32_t* __restrict__ slot,
+                                                    const int* __restrict__ cpar, long long B,
+                                                    const DevCounters* __restrict__ ctr, uint32_t* __restrict__ flag,
+                                                    uint32_t* __restrict__ pos, uint32_t* __restrict__ tile_sums) {
+    __shared__ uint32_t wsum[4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const long long beff = min(B, (long long)ctr->beff);
+    const long long base = (long long)blockIdx.x * kScanTile + threadIdx.x * 4;
+    uint32_t f[4], loc[4], run = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const long long b = base + i;
+        f[i] = (b < beff && cpar[b] >= 0 && (uint32_t)table[slot[b]] == kStageBase + (uint32_t)b) ? 1u : 0u;
+        loc[i] = run;
+        run += f[i];
+    }
+    uint32_t incl = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    uint32_t tpre = incl - run;
+    for (int w = 0; w < wid; ++w) tpre += wsum[w];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (base + i < B) {
+            flag[base + i] = f[i];
+            pos[base + i] = tpre + loc[i];
+        }
+    if (threadIdx.x == 255) tile_sums[blockIdx.x] = tpre + run;
 }
 
-hipError_t launch_flags(const u64* table, const uint32_t* slot, const int* cpar, long long B, const DevCounters* ctr,
-                        uint32_t* flag, hipStream_t st) {
+hipError_t launch_flags(const u64* table, const uint32_t* slot, const int* cpar, long long B, DevCounters* ctr,
+                        uint32_t* flag, uint32_t* pos, uint32_t* tile_sums, uint32_t* tile_pre, hipStream_t st) {
     if (B <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_flags, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, table, slot, cpar, B, ctr, flag);
+    const long long nt = scan_tiles(B);
+    hipLaunchKernelGGL(k_flag_tiles, dim3((unsigned)nt), dim3(256), 0, st, table, slot, cpar, B, ctr, flag, pos,
+                       tile_sums);
+    if (nt > kCommitTiles)  // the commit reads the tile prefix (and the host the total) from here
+        hipLaunchKernelGGL((k_scan_sums<uint32_t, false>), dim3(1), dim3(1024), 0, st, tile_sums, tile_pre, nt,
+                           (u64*)&ctr->total, nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -986,13 +1041,39 @@ hipError_t launch_flags(const u64* table, const uint32_t* slot, const int* cpar,
 template <typename U>
 __global__ __launch_bounds__(256) void k_commit(int upr /* units per row */, CommitArgs a) {
     __shared__ int srcb[256];
+    __shared__ uint32_t s_pre;
     const long long b0 = (long long)blockIdx.x * 256;
     const long long b = b0 + threadIdx.x;
-    const uint32_t p0 = a.pos[b0];
+    const long long tile = b0 / kScanTile;
+    if (threadIdx.x < 64) {
+        // new children of the chunk before this block's tile; block 0 also
+        // records the chunk's total
+        uint32_t pre;
+        if (a.tile_pre) {
+            pre = a.tile_pre[tile];
+        } else {
+            const long long nt = (a.B + kScanTile - 1) / kScanTile;
+            const long long upto = blockIdx.x == 0 ? nt : tile;
+            uint32_t sp = 0, sa = 0;
+            for (long long q = threadIdx.x; q < upto; q += 64) {
+                const uint32_t v = a.tile_sums[q];
+                sp += q < tile ? v : 0u;
+                sa += v;
+            }
+            pre = wave_sum_u32(sp);
+            if (blockIdx.x == 0) {
+                const uint32_t all = wave_sum_u32(sa);
+                if (threadIdx.x == 0) a.ctr->total = all;
+            }
+        }
+        if (threadIdx.x == 0) s_pre = pre;
+    }
+    __syncthreads();
+    const uint32_t p0 = s_pre + a.pos[b0];
     bool isnew = false;
     if (b < a.B && a.flag[b]) {
         isnew = true;
-        const uint32_t pb = a.pos[b];
+        const uint32_t pb = s_pre + a.pos[b];
         srcb[pb - p0] = threadIdx.x;
         const long long local = a.level_count + (long long)pb;
         const uint32_t sl = a.slot[b];
@@ -1027,8 +1108,10 @@ __global__ __launch_bounds__(256) void k_commit(int upr /* units per row */, Com
     }
 }
 
-hipError_t launch_commit(int elem_bytes, int m, const CommitArgs& a, hipStream_t st) {
-    if (a.B <= 0) return hipSuccess;
+hipError_t launch_commit(int elem_bytes, int m, const CommitArgs& a_in, hipStream_t st) {
+    if (a_in.B <= 0) return hipSuccess;
+    CommitArgs a = a_in;
+    if (scan_tiles(a.B) <= kCommitTiles) a.tile_pre = nullptr;  // the blocks sum the tile counts themselves
     const size_t rb = (size_t)m * elem_bytes;
     const uintptr_t al = (uintptr_t)a.stage | (uintptr_t)a.arena | (uintptr_t)a.row2;
     const unsigned blocks = (unsigned)((a.B + 255) / 256);

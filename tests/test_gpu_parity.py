@@ -73,6 +73,20 @@ def test_chunk_invariance(gpu, oracle_mod):
         assert_same_bfs(g, want)
 
 
+def test_many_scan_tiles(gpu, oracle_mod):
+    """Chunks of more than 1024 scan tiles (over 2^20 children) take the
+    separate scan of tile counts; smaller ones sum them inside the commit."""
+    s = synth.config_system(2, 0)
+    want = oracle_mod.bfs(s, max_depth=3, frontier_cap=1200000, stop_at_cap=True)
+    assert want.level_sizes.tolist() == [1, 128, 48384, 1200000]
+    for chunk in (1 << 21, 0):
+        note(f"plain seed 0, cap 1.2e6, depth 3, chunk={chunk}")
+        g = gpu_bfs(s, max_depth=3, frontier_cap=1200000, stop_at_cap=True, out_capacity=1300000, chunk=chunk)
+        # the last level's first chunk is sized for 1.2e6 new rows: above 2^20
+        assert g["level_stats"][2]["expanded"] > (1 << 20)
+        assert_same_bfs(g, want)
+
+
 @pytest.mark.parametrize("seed", [0, 7, 19, 42])
 def test_hash_collisions(gpu, oracle_mod, seed):
     """A 4-bit hash makes nearly every probe a tag match: full-row compares
@@ -138,6 +152,34 @@ def test_overflow(gpu, oracle_mod):
     note("int32 at the edge, no overflow")
     s = synth.make_system(2, [(1, 1, 1, 1, 1)], [(1, 0)], [2**31 - 2, 1])
     assert_same_bfs(gpu_bfs(s, max_depth=3, out_capacity=16), oracle_mod.bfs(s, max_depth=3))
+
+
+def test_bad_c0(gpu, oracle_mod):
+    """A C0 count outside the count type's range is an overflow error, whether
+    or not a level runs before it is read; the handle stays usable."""
+    import torch
+
+    s = synth.config_system(1, 3)
+    bad = np.asarray(s.c0, dtype=np.int64).copy()
+    bad[s.m // 2] = -1
+    h = snp.snp_load(s, path=snp.SNP_PATH_SPARSE, max_rows=1 << 12)
+    try:
+        out = torch.empty((1 << 12, s.m), dtype=torch.int32, device="cuda")
+        for depth in (0, 1, 4, -1):
+            note(f"bad C0, max_depth {depth}")
+            with pytest.raises(snp.SnpError) as e:
+                snp.snp_run(h, to_device_rows(s, bad), depth, out, 1 << 12)
+            assert e.value.status == snp.SNP_ERR_OVERFLOW and "C0" in e.value.message
+        with pytest.raises(snp.SnpError) as e:
+            snp.snp_reset(h, to_device_rows(s, bad))
+        assert e.value.status == snp.SNP_ERR_OVERFLOW and "C0" in e.value.message
+        note("good C0 on the same handle")
+        res = snp.snp_run(h, to_device_rows(s, s.c0), 4, out, 1 << 12)
+        want = oracle_mod.bfs(s, max_depth=4)
+        assert res["level_sizes"].tolist() == want.level_sizes.tolist()
+        assert np.array_equal(from_device_rows(s, out[:res["n_configs"]]), want.rows)
+    finally:
+        h.close()
 
 
 def test_all_halting(gpu, oracle_mod):
