@@ -214,8 +214,9 @@ snp_status snp_expand(snp_system *sys, const void *frontier_dev, int64_t n, void
  *   level_sizes: host int64 [max_levels]: rows of every level; *n_levels (host)
  *     receives the number of levels (an expansion that yields nothing adds none).
  *   *stop_reason (host): snp_stop.
- *   level_stats: nullable host [max_levels]: counters of the expansion of each
- *     level (zeros for a level that was not expanded).
+ *   level_stats: nullable host [max_levels]: entries [0, *n_levels) receive the
+ *     counters of the expansion of each level (zeros for a level that was not
+ *     expanded); later entries are left as they are.
  *   parent_of: nullable device int64 [out_capacity]: row index (in out_dev) of
  *     the parent of every row, -1 for C0.
  *   child_of: nullable device int64 [out_capacity]: child index t of every row

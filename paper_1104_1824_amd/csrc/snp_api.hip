@@ -297,22 +297,29 @@ snp_status rebuild_table(snp_system* S, const void* arena, long long rows) {
     return SNP_OK;
 }
 
-// Record C0 as the only visited configuration, stored at arena row 0.  Its
+// Record C0 as the only visited configuration, stored at arena row 0 (parent
+// and child index -1 in par0 / chi0 when given).  Its
 // range check counts in the walk-start slot; with `wait` false the result is
 // read (and a bad C0 reported) by the next read_counters, so the first level
 // costs no synchronisation of its own.  The kernels never index memory by a
 // count, so a level expanded from a bad C0 stays in bounds before the error.
-snp_status start_walk(snp_system* S, const void* c0_dev, void* arena, bool wait) {
+snp_status start_walk(snp_system* S, const void* c0_dev, void* arena, bool wait, long long* par0 = nullptr,
+                      long long* chi0 = nullptr) {
     if (!c0_dev) return fail(SNP_ERR_INVALID, "c0 is NULL");
-    snp::DevCounters* sc = S->d_ring + snp_system::kRing;
-    HIPCHK(hipMemsetAsync(sc, 0, sizeof(snp::DevCounters), S->stream));
-    if (arena != c0_dev) HIPCHK(hipMemcpyAsync(arena, c0_dev, row_bytes(S), hipMemcpyDeviceToDevice, S->stream));
-    HIPCHK(snp::launch_check_rows(S->elem_bytes, arena, S->m, S->count_max, sc, S->stream));
-    snp_status st;
-    if ((st = fill_table(S, arena, 1, sc))) return st;
+    const char *c = (const char*)c0_dev, *a = (const char*)arena;
+    if (c != a && c < a + row_bytes(S) && a < c + row_bytes(S))
+        return fail(SNP_ERR_INVALID, "c0 overlaps row 0 of the row store without being it");
+    HIPCHK(snp::launch_start_walk(S->elem_bytes, S->m, S->d_R, S->d_table, S->slots - 1, c0_dev, arena, S->count_max,
+                                  S->opt.hash_mask ? S->opt.hash_mask : ~0ULL, S->d_row_slot,
+                                  S->d_ring + snp_system::kRing, par0, chi0, S->stream));
+    S->tombs = 0;
     S->start_pending = true;
     return wait ? read_counters(S) : SNP_OK;
 }
+
+// Up to this many parents the commit block that fills the cap counts the
+// halting parents itself (a few loads per thread).
+constexpr long long kCommitHaltMax = 1 << 16;
 
 struct LevelIO {
     const void* frontier;
@@ -433,12 +440,14 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         snp::CommitArgs cm{S->d_table, S->d_table, S->d_slot, S->d_hash, S->d_pos, S->d_flag, S->d_fsums, S->d_fpre,
                            S->d_stage,
                            S->d_cpar, S->d_ct, B, io.arena, io.level_base, count, limit, io.row2, io.par_out,
-                           io.par_out_base, io.par_value_base, io.t_out, S->d_row_slot, S->d_ctr};
-        HIPCHK(snp::launch_commit(S->elem_bytes, S->m, cm, S->stream));
+                           io.par_out_base, io.par_value_base, io.t_out, S->d_row_slot, S->d_ctr, nullptr};
         // when this pass may fill the cap, count the halting parents up to the
-        // parent of the cap's child in the same pass (no extra synchronisation)
+        // parent of the cap's child in the same pass (no extra synchronisation):
+        // in the commit block that fills it, or for many parents in a kernel of its own
         const bool may_cap = sem_binds && B >= limit - count;
-        if (may_cap) HIPCHK(snp::launch_count_flags_cap(S->d_hflag, P, S->d_ctr, S->stream));
+        if (may_cap && P <= kCommitHaltMax) cm.hflag = S->d_hflag;
+        HIPCHK(snp::launch_commit(S->elem_bytes, S->m, cm, S->stream));
+        if (may_cap && P > kCommitHaltMax) HIPCHK(snp::launch_count_flags_cap(S->d_hflag, P, S->d_ctr, S->stream));
         if ((st = mark(S, 5))) return st;
         if ((st = read_counters(S))) return st;
         if (S->opt.profile == 1) {
@@ -722,12 +731,17 @@ snp_status snp_run(snp_system* S, const void* c0_dev, int32_t max_depth, void* o
     *n_levels = 0;
     *stop_reason = SNP_STOP_DEPTH;
     S->walk_active = false;
-    if (level_stats) memset(level_stats, 0, sizeof(snp_expand_stats) * (size_t)max_levels);
     const long long rb = row_bytes(S);
-    snp_status st = start_walk(S, c0_dev, out_dev, false);
+    snp_status st = start_walk(S, c0_dev, out_dev, false, (long long*)parent_of, (long long*)child_of);
     if (st) return st;
-    if (parent_of) HIPCHK(hipMemsetAsync(parent_of, 0xFF, sizeof(int64_t), S->stream));  // -1 for C0
-    if (child_of) HIPCHK(hipMemsetAsync(child_of, 0xFF, sizeof(int64_t), S->stream));
+    // level_stats entries [0, *n_levels): each expansion writes its own, the
+    // rest (levels that were not expanded) are zeroed on the way out
+    int32_t written = 0;
+    auto done = [&](snp_status r) -> snp_status {
+        if (level_stats)
+            for (int32_t k = written; k < std::min(*n_levels, max_levels); ++k) level_stats[k] = snp_expand_stats{};
+        return r;
+    };
     const long long arena_cap = std::min<long long>(out_capacity, S->max_rows);
     long long rows = 1, lv_begin = 0, lv_end = 1;
     int32_t levels = 1;
@@ -743,7 +757,7 @@ snp_status snp_run(snp_system* S, const void* c0_dev, int32_t max_depth, void* o
         }
         if (levels >= max_levels) {
             HIPCHK(hipStreamSynchronize(S->stream));
-            return fail(SNP_ERR_CAPACITY, "more than max_levels = %d levels", max_levels);
+            return done(fail(SNP_ERR_CAPACITY, "more than max_levels = %d levels", max_levels));
         }
         LevelIO io{(const char*)out_dev + lv_begin * rb, lv_end - lv_begin, out_dev, rows, arena_cap,
                    S->opt.frontier_cap > 0 ? S->opt.frontier_cap : kInf, kInf, nullptr, (long long*)parent_of,
@@ -753,10 +767,11 @@ snp_status snp_run(snp_system* S, const void* c0_dev, int32_t max_depth, void* o
         st = expand_level(S, io, &es, &count);
         if (st) {
             if (st == SNP_ERR_CAPACITY && rows + count > arena_cap)
-                return fail(SNP_ERR_CAPACITY, "run needs more than %lld rows (out_capacity or max_rows)", arena_cap);
-            return st;
+                st = fail(SNP_ERR_CAPACITY, "run needs more than %lld rows (out_capacity or max_rows)", arena_cap);
+            return done(st);
         }
         if (level_stats) level_stats[depth] = es;
+        written = depth + 1;
         const bool all_halting = es.halting_parents == es.parents;
         if (count > 0) {
             level_sizes[levels++] = count;
@@ -772,9 +787,9 @@ snp_status snp_run(snp_system* S, const void* c0_dev, int32_t max_depth, void* o
         if (count == 0) { stop = SNP_STOP_EMPTY_FRONTIER; break; }
     }
     *stop_reason = stop;
-    if (S->start_pending) return read_counters(S);  // no level ran: check C0 now
+    if (S->start_pending) return done(read_counters(S));  // no level ran: check C0 now
     HIPCHK(hipStreamSynchronize(S->stream));
-    return SNP_OK;
+    return done(SNP_OK);
 }
 
 // Multiplier m of the exact quotient x / d for every 32-bit x and 2 <= d < 2^8

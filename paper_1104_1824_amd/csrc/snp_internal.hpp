@@ -109,6 +109,8 @@ struct CommitArgs {
     long long* t_out;      // nullable child index output
     uint32_t* row_slot;    // [max_rows] slot of every row-store row
     DevCounters* ctr;
+    const uint8_t* hflag;  // nullable halting flags of the frontier: the block that fills the
+                           // cap counts them up to the cap child's parent into ctr->count
 };
 
 // Deterministic batched run: one system per workgroup.
@@ -168,12 +170,13 @@ hipError_t launch_flags(const u64* table, const uint32_t* slot, const int* cpar,
                         uint32_t* flag, uint32_t* pos, uint32_t* tile_sums, uint32_t* tile_pre, hipStream_t st);
 hipError_t launch_commit(int elem_bytes, int m, const CommitArgs& a, hipStream_t st);
 hipError_t launch_fill_u64(u64* p, long long n, u64 v, hipStream_t st);
+hipError_t launch_start_walk(int elem_bytes, int m, const u64* R, u64* table, u64 slot_mask, const void* c0,
+                             void* arena, long long count_max, u64 hash_mask, uint32_t* row_slot, DevCounters* sc,
+                             long long* par0, long long* chi0, hipStream_t st);
 hipError_t launch_rows_insert(int elem_bytes, int m, const u64* R, u64* table, u64 slot_mask, const void* arena,
                               long long first, long long count, u64 hash_mask, uint32_t* row_slot,
                               DevCounters* ctr, hipStream_t st);
 hipError_t launch_rollback(const uint32_t* row_slot, u64* table, long long first, long long count,
                            hipStream_t st);
-hipError_t launch_check_rows(int elem_bytes, const void* rows, long long n_elems, long long count_max,
-                             DevCounters* ctr, hipStream_t st);
 
 }  // namespace snp

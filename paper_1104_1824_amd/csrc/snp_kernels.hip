@@ -1042,9 +1042,11 @@ template <typename U>
 __global__ __launch_bounds__(256) void k_commit(int upr /* units per row */, CommitArgs a) {
     __shared__ int srcb[256];
     __shared__ uint32_t s_pre;
+    __shared__ int s_cap_par;
     const long long b0 = (long long)blockIdx.x * 256;
     const long long b = b0 + threadIdx.x;
     const long long tile = b0 / kScanTile;
+    if (threadIdx.x == 64) s_cap_par = -1;
     if (threadIdx.x < 64) {
         // new children of the chunk before this block's tile; block 0 also
         // records the chunk's total
@@ -1087,12 +1089,20 @@ __global__ __launch_bounds__(256) void k_commit(int upr /* units per row */, Com
             if (local == a.limit - 1) {
                 a.ctr->cap_g = (u64)b + 1;
                 a.ctr->cap_par = (u64)a.cpar[b];
+                s_cap_par = a.cpar[b];
             }
         } else {
             a.table[sl] = kTomb;
         }
     }
     const int nnew = __syncthreads_count(isnew);
+    if (a.hflag && s_cap_par >= 0) {
+        // this block filled the cap: halting parents up to the cap child's parent
+        uint32_t c = 0;
+        for (int i = threadIdx.x; i <= s_cap_par; i += 256) c += a.hflag[i];
+        c = wave_sum_u32(c);
+        if ((threadIdx.x & 63) == 0 && c) atomicAdd((unsigned long long*)&a.ctr->count, (u64)c);
+    }
     const long long first_local = a.level_count + (long long)p0;
     const int ncopy = (int)max(0LL, min((long long)nnew, a.limit - first_local));
     const U* src = (const U*)a.stage + b0 * upr;
@@ -1189,6 +1199,64 @@ hipError_t launch_rows_insert(int elem_bytes, int m, const u64* R, u64* table, u
     return hipGetLastError();
 }
 
+// The start of a walk in one launch: the visited set holds C0 alone (row 0
+// of the row store) and the walk-start counters are set.  Every block hashes
+// C0 (one wave) and fills its share of the table with empty entries, except
+// C0's home slot, which takes C0's entry; block 0 also copies C0 to row 0
+// (when the row store is elsewhere), records its slot, checks its range and
+// writes -1 as C0's parent and child index when those outputs are given.
+template <typename T>
+__global__ __launch_bounds__(256) void k_start_walk(int m, const u64* __restrict__ R, u64* __restrict__ table,
+                                                    u64 slot_mask, const T* __restrict__ c0, T* __restrict__ arena,
+                                                    long long count_max, u64 hash_mask,
+                                                    uint32_t* __restrict__ row_slot, DevCounters* __restrict__ sc,
+                                                    long long* par0, long long* chi0) {
+    __shared__ u64 s_slot, s_entry;
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < 64) {
+        const u64 h = fmix64(row_hash_wave<T>(c0, R, m, lane)) & hash_mask;
+        if (lane == 0) {
+            s_slot = h & slot_mask;
+            s_entry = (h >> 32) << 32;  // tag, reference row 0
+        }
+    }
+    __syncthreads();
+    const u64 home = s_slot, entry = s_entry;
+    const u64 nslots = slot_mask + 1;
+    for (u64 i = (u64)blockIdx.x * 256 + threadIdx.x; i < nslots; i += (u64)gridDim.x * 256)
+        table[i] = i == home ? entry : kEmpty;
+    if (blockIdx.x != 0) return;
+    bool bad = false;
+    for (int j = threadIdx.x; j < m; j += 256) {
+        const T x = c0[j];
+        if (arena != c0) arena[j] = x;
+        const long long v = (long long)x;
+        bad |= v < 0 || v > count_max;
+    }
+    const int nbad = __syncthreads_count(bad);
+    if (threadIdx.x == 0) {
+        row_slot[0] = (uint32_t)home;
+        if (par0) *par0 = -1;
+        if (chi0) *chi0 = -1;
+        DevCounters z{};
+        z.overflow = nbad ? 1 : 0;
+        *sc = z;
+    }
+}
+
+hipError_t launch_start_walk(int elem_bytes, int m, const u64* R, u64* table, u64 slot_mask, const void* c0,
+                             void* arena, long long count_max, u64 hash_mask, uint32_t* row_slot, DevCounters* sc,
+                             long long* par0, long long* chi0, hipStream_t st) {
+    const unsigned blocks = (unsigned)std::min<u64>((slot_mask + 256) / 256, 4096);
+    if (elem_bytes == 4)
+        hipLaunchKernelGGL(k_start_walk<int32_t>, dim3(blocks), dim3(256), 0, st, m, R, table, slot_mask,
+                           (const int32_t*)c0, (int32_t*)arena, count_max, hash_mask, row_slot, sc, par0, chi0);
+    else
+        hipLaunchKernelGGL(k_start_walk<uint16_t>, dim3(blocks), dim3(256), 0, st, m, R, table, slot_mask,
+                           (const uint16_t*)c0, (uint16_t*)arena, count_max, hash_mask, row_slot, sc, par0, chi0);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_rollback(const uint32_t* __restrict__ row_slot, u64* __restrict__ table,
                                                   long long first, long long count) {
     const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -1199,28 +1267,6 @@ hipError_t launch_rollback(const uint32_t* row_slot, u64* table, long long first
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_rollback, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, row_slot, table, first,
                        count);
-    return hipGetLastError();
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_check_rows(const T* __restrict__ rows, long long n, long long count_max,
-                                                    DevCounters* ctr) {
-    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const long long v = (long long)rows[i];
-    if (v < 0 || v > count_max) atomicOr((unsigned long long*)&ctr->overflow, 1ULL);
-}
-
-hipError_t launch_check_rows(int elem_bytes, const void* rows, long long n_elems, long long count_max,
-                             DevCounters* ctr, hipStream_t st) {
-    if (n_elems <= 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((n_elems + 255) / 256);
-    if (elem_bytes == 4)
-        hipLaunchKernelGGL(k_check_rows<int32_t>, dim3(blocks), dim3(256), 0, st, (const int32_t*)rows, n_elems,
-                           count_max, ctr);
-    else
-        hipLaunchKernelGGL(k_check_rows<uint16_t>, dim3(blocks), dim3(256), 0, st, (const uint16_t*)rows, n_elems,
-                           count_max, ctr);
     return hipGetLastError();
 }
 

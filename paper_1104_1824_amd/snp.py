@@ -139,6 +139,12 @@ class Handle:
         self._keep = keep
         self.m = m
         self.count_type = count_type
+        self._run_bufs = None  # (max_levels, sizes, stats) reused by snp_run
+
+    def run_buffers(self, max_levels: int):
+        if self._run_bufs is None or self._run_bufs[0] != max_levels:
+            self._run_bufs = (max_levels, np.zeros(max_levels, dtype=np.int64), (snp_expand_stats * max_levels)())
+        return self._run_bufs[1], self._run_bufs[2]
 
     def close(self):
         if self.ptr:
@@ -223,8 +229,9 @@ def snp_run(h: Handle, c0_dev, max_depth: int, out_dev, out_capacity: int, max_l
     n_configs = ctypes.c_int64(0)
     n_levels = ctypes.c_int32(0)
     stop = ctypes.c_int32(0)
-    sizes = np.zeros(max_levels, dtype=np.int64)
-    stats = (snp_expand_stats * max_levels)() if with_stats else None
+    sizes, stats = h.run_buffers(max_levels)
+    if not with_stats:
+        stats = None
     status = lib().snp_run(h.ptr, _ptr(c0_dev), int(max_depth), _ptr(out_dev), int(out_capacity),
                            ctypes.byref(n_configs), sizes.ctypes.data, int(max_levels), ctypes.byref(n_levels),
                            ctypes.byref(stop), ctypes.cast(stats, ctypes.c_void_p) if stats is not None else None,
