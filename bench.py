@@ -9,8 +9,9 @@ the GPU through the C ABI.  The value is new (deduplicated) configurations
 per second over the timed steps; inputs are resident in HBM before timing.
 
 The JSON line also carries the roofline of the dominant kernel (device time
-from HIP events recorded by the library on its stream inside the timed
-region) and the CPU oracle timed on a bounded sample of the same workload.
+from HIP events recorded by the library on its stream just before and after
+each of its launches inside the timed region) and the CPU oracle timed on a
+bounded sample of the same workload.
 """
 import argparse
 import json

@@ -121,9 +121,11 @@ typedef struct {
     int64_t chunk;            /* most children expanded per device pass; 0: automatic */
     uint64_t hash_mask;       /* 0: full 64-bit configuration hash; otherwise the hash is
                                  ANDed with it (forces collisions; results do not change) */
-    int32_t profile;          /* 1: time the child expansion kernel with HIP events on the
-                                 handle's stream (snp_expand_stats.ns_expand); >= 2: time every
-                                 stage (every ns_* field); 0: no events */
+    int32_t profile;          /* 1: time the child expansion kernel with HIP events recorded
+                                 on the handle's stream just before and after each launch
+                                 (snp_expand_stats.ns_expand); >= 2: time every stage (every
+                                 ns_* field); 0: no events.  The events are created for timing
+                                 only (no system-scope fence when one is reached). */
     int32_t int8_max_k;       /* int8 path: most rule columns (1..128) one segment of children
                                  may put on the matrix cores, 0: 128; segments that need more
                                  take the per-child sparse form (smaller values force it;

@@ -70,6 +70,7 @@ struct snp_system {
     int4* d_rules = nullptr;
     int* d_in_ptr = nullptr;
     int* d_in_src = nullptr;
+    int* d_in_lane = nullptr;
     int8_t* d_M8 = nullptr;  // r x m int8 copy of M_Pi when every entry fits (int8 path)
     u64* d_R = nullptr;      // hash weights
     u64* d_hM = nullptr;     // H of every row of M_Pi
@@ -116,7 +117,7 @@ struct snp_system {
     hipEvent_t ev[kStages + 1] = {};
 
     ~snp_system() {
-        void* ptrs[] = {d_nrule_ptr, d_rules, d_in_ptr, d_in_src, d_M8, d_R, d_hM, d_table, d_row_slot, d_psi, d_off,
+        void* ptrs[] = {d_nrule_ptr, d_rules, d_in_ptr, d_in_src, d_in_lane, d_M8, d_R, d_hM, d_table, d_row_slot, d_psi, d_off,
                         d_sc_sums, d_sc_pre, d_stage, d_hash, d_cpar, d_ct, d_slot, d_flag, d_pos,
                         d_fsums, d_fpre, d_ring, d_store, d_cand, d_hflag, d_T};
         for (void* p : ptrs)
@@ -249,6 +250,16 @@ snp_status validate_options(const snp_options* o) {
     return SNP_OK;
 }
 
+// Wait for a stream by polling it: a pass's counters are awaited many times
+// per walk, each a few tens of microseconds after the launch, and a blocking
+// wait adds the wake-up of a sleeping thread to every one of them.
+hipError_t wait_stream(hipStream_t st) {
+    hipError_t e;
+    while ((e = hipStreamQuery(st)) == hipErrorNotReady) {
+    }
+    return e;
+}
+
 // Copy the current pass's counters to the host and wait for the stream.  The
 // checks of a walk start still unread ride along and are reported first.
 snp_status read_counters(snp_system* S) {
@@ -257,7 +268,7 @@ snp_status read_counters(snp_system* S) {
         HIPCHK(hipMemcpyAsync(S->h_ctr + 1, S->d_ring + snp_system::kRing, sizeof(snp::DevCounters),
                               hipMemcpyDeviceToHost, S->stream));
     HIPCHK(hipMemcpyAsync(S->h_ctr, S->d_ctr, sizeof(snp::DevCounters), hipMemcpyDeviceToHost, S->stream));
-    HIPCHK(hipStreamSynchronize(S->stream));
+    HIPCHK(wait_stream(S->stream));
     if (start) {
         S->start_pending = false;
         if (S->h_ctr[1].overflow) return fail(SNP_ERR_OVERFLOW, "C0 holds a count outside the count type's range");
@@ -645,8 +656,15 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     S->int8_work = (double)d->m * 1.5 + ((double)d->m + (double)d->n_syn) / 64.0;
     int max_in = 0;
     for (int n = 0; n < d->m; ++n) max_in = std::max(max_in, in_ptr[n + 1] - in_ptr[n]);
+    // lane-major in-synapse table of the one-neuron-per-lane expansion
+    std::vector<int> in_lane(16 * 64, -1);
+    if (d->m <= 64 && max_in <= 16)
+        for (int n = 0; n < d->m; ++n)
+            for (int e = 0; e < in_ptr[n + 1] - in_ptr[n]; ++e) in_lane[e * 64 + n] = in_src[in_ptr[n] + e];
+    LOADCHK(dmalloc(&S->d_in_lane, sizeof(int) * in_lane.size()));
+    LOADCHK(up(S->d_in_lane, in_lane.data(), sizeof(int) * in_lane.size()));
     S->dsys = snp::DevSystem{d->m, d->r, S->d_nrule_ptr, S->d_rules, S->d_in_ptr, S->d_in_src, d->n_syn, S->d_M8,
-                             S->count_max, S->d_R, S->d_hM, max_in};
+                             S->count_max, S->d_R, S->d_hM, max_in, S->d_in_lane};
 
     S->slots = next_pow2((u64)std::max<long long>(1024, 2 * (S->max_rows + 2 * S->chunk_max)));
     LOADCHK(dmalloc(&S->d_table, sizeof(u64) * S->slots));
@@ -674,7 +692,8 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     S->d_ctr = S->d_ring;
     LOADCHK(hipHostMalloc((void**)&S->h_ctr, 2 * sizeof(snp::DevCounters), hipHostMallocDefault));
     if (opt.profile)
-        for (hipEvent_t& e : S->ev) LOADCHK(hipEventCreate(&e));
+        // timing only: no system-scope fence when an event is reached
+        for (hipEvent_t& e : S->ev) LOADCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
 #undef LOADCHK
     *out = S;
     return SNP_OK;

@@ -85,6 +85,50 @@ __device__ __forceinline__ u64 wave_sum_u64(u64 v) {
 
 __device__ __forceinline__ int wave_max_i32(int x) { return (int)wave_max_u32((uint32_t)(x + 1)) - 1; }
 
+// Inclusive prefix sums over the lanes (lane i: lanes 0 .. i), the partial
+// results of the same DPP pattern; all 64 lanes active.
+__device__ __forceinline__ uint32_t wave_incl_u32(uint32_t v) {
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false);
+    return v;
+}
+
+__device__ __forceinline__ u64 wave_incl_u64(u64 v) {
+    SNP_DPP_ADD64(v, 0x111, 0xf, true);
+    SNP_DPP_ADD64(v, 0x112, 0xf, true);
+    SNP_DPP_ADD64(v, 0x114, 0xf, true);
+    SNP_DPP_ADD64(v, 0x118, 0xf, true);
+    SNP_DPP_ADD64(v, 0x142, 0xa, false);
+    SNP_DPP_ADD64(v, 0x143, 0xc, false);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t sat_mul32(uint32_t a, uint32_t b) {  // a, b >= 1
+    return __umulhi(a, b) ? 0xFFFFFFFFu : a * b;
+}
+
+// Product over the lanes after this one (lane i: lanes i+1 .. 63, 1 for lane
+// 63) of factors >= 1, saturated at 2^32 - 1: products along each row of 16
+// by DPP row shifts toward lower lanes (lanes past the row's end read 1), the
+// row products of later rows multiplied in from scalars, then a wave shift by
+// one lane.  All 64 lanes active.
+__device__ __forceinline__ uint32_t wave_after_prod_sat32(uint32_t v) {
+    v = sat_mul32(v, (uint32_t)__builtin_amdgcn_update_dpp(1u, v, 0x101, 0xf, 0xf, false));  // row_shl:1
+    v = sat_mul32(v, (uint32_t)__builtin_amdgcn_update_dpp(1u, v, 0x102, 0xf, 0xf, false));  // row_shl:2
+    v = sat_mul32(v, (uint32_t)__builtin_amdgcn_update_dpp(1u, v, 0x104, 0xf, 0xf, false));  // row_shl:4
+    v = sat_mul32(v, (uint32_t)__builtin_amdgcn_update_dpp(1u, v, 0x108, 0xf, 0xf, false));  // row_shl:8
+    const uint32_t r1 = __builtin_amdgcn_readlane(v, 16), r2 = __builtin_amdgcn_readlane(v, 32);
+    const uint32_t r3 = __builtin_amdgcn_readlane(v, 48);
+    const uint32_t p23 = sat_mul32(r2, r3), p123 = sat_mul32(r1, p23);
+    const int row = (int)(__lane_id() >> 4);
+    v = sat_mul32(v, row == 0 ? p123 : row == 1 ? p23 : row == 2 ? r3 : 1u);
+    return (uint32_t)__builtin_amdgcn_update_dpp(1u, v, 0x130, 0xf, 0xf, false);  // wave_shl:1
+}
+
 // Rule applicability: a^n in L(a^i (a^j)*) and n >= c.
 __device__ __forceinline__ bool rule_applies(int n, const int4 R) {
     if (n < R.x || n < R.z) return false;

@@ -51,6 +51,8 @@ struct DevSystem {
     const u64* R;          // [m] hash weights: R[n] = mix64((n + 1) * gamma)
     const u64* hM;         // [r] H of every row of M_Pi (entries sign-extended, mod 2^64)
     int max_in;            // largest in-degree of a neuron
+    const int* in_lane;    // [16 * 64] in-synapse e of neuron j at e * 64 + j (-1: none),
+                           // filled when m <= 64 and max_in <= 16
 };
 
 // One chunk of children [g0, g0 + B) of the frontier.

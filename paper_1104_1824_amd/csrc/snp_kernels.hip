@@ -203,9 +203,18 @@ long long scan_tiles(long long n) { return (n + kScanTile - 1) / kScanTile; }
 
 // out[i] = base + sum of in[0 .. i); *total = base + sum of in, where base is
 // read on the device (*base_dev, 0 when null) and may be the same word as total.
+// Up to this many elements one block scans them directly (k_scan_sums walks
+// them 1024 at a time with a carried base): one launch instead of two or three.
+constexpr long long kSmallScan = 8192;
+
 template <typename V, bool SAT>
 static hipError_t scan_impl(const V* in, V* out, long long n, V* tile_sums, V* tile_pre, u64* total,
                             const u64* base_dev, u64* total_copy, hipStream_t st) {
+    if (n <= kSmallScan) {
+        hipLaunchKernelGGL((k_scan_sums<V, SAT>), dim3(1), dim3(1024), 0, st, in, out, n, total, base_dev,
+                           total_copy);
+        return hipGetLastError();
+    }
     const long long nt = scan_tiles(n);
     if (nt > 0) hipLaunchKernelGGL((k_scan_tiles<V, SAT>), dim3((unsigned)nt), dim3(256), 0, st, in, out, tile_sums, n);
     hipLaunchKernelGGL((k_scan_sums<V, SAT>), dim3(1), dim3(1024), 0, st, tile_sums, tile_pre, nt, total, base_dev,
@@ -466,18 +475,19 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
 // on, ever change, so:
 //   * the first child (the reference) is computed in full, by a pull over the
 //     in-synapses (ds_bpermute) with lane j holding neuron j;
-//   * for every neuron v of V and digit d, lane j keeps in LDS the change
-//     T[v][d][j] that v firing its d-th applicable rule makes to neuron j
-//     (-c on j = v, +p on the targets of v), and H(M_k) of that rule;
-//   * the next child follows by the odometer step over V alone: each changed
-//     neuron adds T[v][new] - T[v][old] per lane and its hash difference to
-//     the row hash (H is linear in the row), which stays on the scalar unit.
-// A child then costs a few vector instructions and one coalesced row store.
+//   * every odometer step over V has one table row U (lane j: the change to
+//     neuron j) in LDS, with its hash change (H is linear in the row) and its
+//     change of the later-twin digit count kept in the row's lane;
+//   * for up to 64 children at a time, lane l finds the step from child l to
+//     l + 1 from the digits of its V value, prefix sums over the lanes give
+//     every child's hash and twin count, and the hash, parent and child index
+//     of the 64 children are stored at once;
+//   * then the children's rows follow one after the other: one LDS row added
+//     and one coalesced row store each.
 // Counts are kept offset by 2^16 in 32 bits, so negative and too large values
 // stay ordered for the range check (a running minimum and maximum).  A
 // segment whose tables would not fit is cut in half until they do (a single
-// child needs none).  Per-child outputs are gathered in lane k % 64 and
-// stored 64 at a time; the next parent's row and the Psi of the next 64
+// child needs none).  The next parent's row and the Psi of the next 64
 // parents are fetched ahead of use.
 // ---------------------------------------------------------------------------
 constexpr int kLaneMaxIn = 16;
@@ -487,6 +497,14 @@ constexpr uint32_t kLaneOff = 1u << 16;   // count offset (c <= 65535)
 // Ends the wait for a loaded register here, so that the per-child loop never
 // waits on the row stores it has in flight (one counter covers both).
 __device__ __forceinline__ void settle(int v) { asm volatile("" ::"v"(v)); }
+
+// y / w for y < 2^20 and 2 <= w <= 16: a float reciprocal estimate is within
+// one of the quotient there, and one correction makes it exact.
+__device__ __forceinline__ uint32_t udiv_small(uint32_t y, uint32_t w) {
+    uint32_t q = (uint32_t)((float)y * __builtin_amdgcn_rcpf((float)w));
+    const int r = (int)(y - q * w);
+    return r < 0 ? q - 1 : (r >= (int)w ? q + 1 : q);
+}
 
 // c, p and H(M_k) of the rule digit d picks (0 when no rule applies).
 __device__ __forceinline__ void lane_fired(const int4* rules, const u64* hrow, int r0, uint32_t am, int om, int d,
@@ -528,8 +546,7 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
     u64* l_hM = (u64*)(l_rules + s.r);
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
-    uint32_t* l_tab = (uint32_t*)(smem + (size_t)s.r * 24) + (size_t)wid * (kLaneTab * 64 + 4 * kLaneTab);
-    u64* l_htab = (u64*)(l_tab + kLaneTab * 64);  // [kLaneTab]
+    uint32_t* l_tab = (uint32_t*)(smem + (size_t)s.r * 24) + (size_t)wid * (kLaneTab * 64);
     const int m = s.m;
     const bool act = lane < m;
     const int kin = s.max_in;
@@ -537,9 +554,13 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
     // select) so that no load waits inside a branch.
     const int jl = min(lane, m - 1);
     int r0 = s.nrule_ptr[jl], r1 = s.nrule_ptr[jl + 1];
-    int e0 = s.in_ptr[jl], deg = s.in_ptr[jl + 1] - e0;
     u64 Rj = s.R[jl];
-    if (!act) r0 = r1 = e0 = deg = 0, Rj = 0;
+    // in-synapse sources of neuron `lane` from the lane-major table (-1: none),
+    // independent of the other loads
+    int saddr[kLaneMaxIn];
+#pragma unroll
+    for (int e = 0; e < kLaneMaxIn; ++e) saddr[e] = e < kin ? s.in_lane[e * 64 + lane] : -1;
+    if (!act) r0 = r1 = 0, Rj = 0;
     // The chunk ends at the children known on the device; the grid strides
     // over runs of consecutive children, about one run per wave.
     const u64 tot = *a.Tdev;
@@ -558,17 +579,16 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
     const long long wave0 = (long long)blockIdx.x * wpb + wid;
     if (wave0 >= nruns) return;
 
-    // in-synapse sources: ds_bpermute byte addresses and a lane mask (in_src
-    // holds at least one entry)
-    int saddr[kLaneMaxIn];
-    const int elast = max(0, s.nnz_in - 1);
-#pragma unroll
-    for (int e = 0; e < kLaneMaxIn; ++e) saddr[e] = s.in_src[min(e0 + e, elast)];
+    // in-synapses: ds_bpermute byte addresses, which of them exist, and a
+    // mask of the source neurons
     u64 inmask = 0;
+    uint32_t emask = 0;
 #pragma unroll
     for (int e = 0; e < kLaneMaxIn; ++e) {
-        if (e < deg) inmask |= 1ULL << saddr[e];
-        saddr[e] = (e < deg) ? 4 * saddr[e] : 0;
+        const bool ok = saddr[e] >= 0;
+        if (ok) inmask |= 1ULL << saddr[e];
+        emask |= ok ? 1u << e : 0u;
+        saddr[e] = ok ? 4 * saddr[e] : 0;
     }
 
     const T* F = (const T*)a.frontier;
@@ -615,31 +635,46 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
         int om;
         lane_applicable(l_rules, r0, r1, x, am, om);
 
-        u64 o_hash = 0, o_ct = 0;
-        int o_par = 0;
         int k = 0;
         while (k < cnt) {
             // ---- a segment: children t .. t + len - 1 of parent p ----
             int len = (int)min((u64)(cnt - k), psi_p - t);
-            // place value of lane j: product of max(1, omega) over later lanes
-            const u64 w1 = (u64)max(1, om);
-            u64 incl = w1;
+            // place value of lane j: product of max(1, omega) over later lanes.
+            // Digit j of child index x is (x / place_j) mod max(1, omega_j).  When
+            // Psi of the parent fits 32 bits so does every index of the segment,
+            // and place values saturated at 2^32 - 1 still compare right with
+            // them: the whole decomposition then runs in 32-bit arithmetic.
+            const bool narrow = psi_p <= 0xFFFFFFFFull;  // uniform
+            const uint32_t w1 = (uint32_t)max(1, om);
+            u64 after = 1;
+            if (narrow) {
+                after = wave_after_prod_sat32(w1);
+            } else {
+                u64 incl = w1;
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const u64 y = __shfl_down(incl, o);
-                if (lane + o < 64) incl = sat_mul(incl, y);
+                for (int o = 1; o < 64; o <<= 1) {
+                    const u64 y = __shfl_down(incl, o);
+                    if (lane + o < 64) incl = sat_mul(incl, y);
+                }
+                const u64 a64 = __shfl_down(incl, 1);
+                after = lane == 63 ? 1 : a64;
             }
-            u64 after = __shfl_down(incl, 1);
-            if (lane == 63) after = 1;
-            const u64 qa = after > t ? 0 : t / after;
-            const int dg0 = (int)(qa % w1);
+            auto quot = [&](u64 x) -> u64 {
+                if (narrow) {
+                    const uint32_t x32 = (uint32_t)x, a32 = (uint32_t)after;
+                    return a32 > x32 ? 0u : x32 / a32;
+                }
+                return after > x ? 0 : x / after;
+            };
+            const u64 qa = quot(t);
+            const int dg0 = narrow ? (int)((uint32_t)qa % w1) : (int)(qa % w1);
             // V: neurons with omega >= 2 from the most significant digit that
             // changes inside the segment; halve the segment until its tables fit
             u64 vmask;
             int nt;
             for (;;) {
                 const u64 tb = t + (u64)(len - 1);
-                const u64 qb = after > tb ? 0 : tb / after;
+                const u64 qb = quot(tb);
                 const u64 dif = __ballot(act && qa != qb);
                 const int jstar = dif ? __builtin_ctzll(dif) : 64;
                 vmask = __ballot(act && om >= 2 && lane >= jstar);
@@ -649,12 +684,7 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
             }
             const bool inV = (vmask >> lane) & 1;
             // table base of every V lane: omega summed over earlier V lanes
-            uint32_t tb_incl = inV ? (uint32_t)om : 0u;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t y = __shfl_up(tb_incl, o);
-                if (lane >= o) tb_incl += y;
-            }
+            const uint32_t tb_incl = wave_incl_u32(inV ? (uint32_t)om : 0u);
             const int tbase = (int)tb_incl - (inV ? om : 0);
             // the reference child (digits dg0) in full
             int dg = dg0;
@@ -666,7 +696,7 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
             for (int e = 0; e < kLaneMaxIn; ++e) {
                 if (e < kin) {
                     const uint32_t y = (uint32_t)__builtin_amdgcn_ds_bpermute(saddr[e], (int)pp);
-                    wv += (e < deg) ? y : 0u;
+                    wv += ((emask >> e) & 1) ? y : 0u;
                 }
             }
             uint32_t val = wv - c + kLaneOff;
@@ -678,65 +708,61 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
             // its whole effect is one row per (v, d):
             //   U[v][d] = T[v][d+1] - T[v][d] + sum over later V neurons v' of
             //             (T[v'][0] - T[v'][top]),
-            // built in place over T (likewise for the hash and the count of
-            // digits that pick a later twin).  The digits of V are packed in
-            // 4-bit fields of one scalar word, the last V neuron lowest.
-            const int nv = __popcll(vmask);
-            const int vi = __popcll(vmask & ((1ULL << lane) - 1));  // position in V (V lanes)
-            uint32_t* l_nt = (uint32_t*)(l_htab + kLaneTab);           // [kLaneTab]
-            u64 f = 0, fmax = 0;
-            int ubase = 0;  // lane q: first row of the V neuron in field q
+            // likewise for the row hash (H is linear in the row) and for the
+            // count of digits that pick a later twin.  Row r = tbase_v + d: lane r
+            // first fetches the rule of row r, then one pass over the rows, last V
+            // neuron first, writes the U rows to LDS (lane = neuron) and leaves
+            // the hash and twin-count changes of row r in lane r.
+            int rv = 0, rd = 0, rb = 0, rw = 0;  // lane r < nt: V neuron, digit, its first row, omega
             for (u64 vq = vmask; vq; vq &= vq - 1) {
                 const int v = __builtin_ctzll(vq);
-                const int wv_ = __builtin_amdgcn_readlane(om, v);
-                const int r0v = __builtin_amdgcn_readlane(r0, v);
-                const uint32_t amv = __builtin_amdgcn_readlane(am, v);
-                const int base = __builtin_amdgcn_readlane(tbase, v);
-                const int field = nv - 1 - __builtin_amdgcn_readlane(vi, v);
-                f |= (u64)__builtin_amdgcn_readlane(dg0, v) << (4 * field);
-                fmax |= (u64)(wv_ - 1) << (4 * field);
-                ubase = (lane == field) ? base : ubase;
-                const bool tgt = (inmask >> v) & 1;
-                for (int d = 0; d < wv_; ++d) {
-                    const int kr = r0v + nth_bit(amv & 0xFFFFu, d);
-                    const int4 R = l_rules[kr];
-                    l_tab[(base + d) * 64 + lane] = (lane == v ? (uint32_t)(-R.z) : 0u) + (tgt ? (uint32_t)R.w : 0u);
-                    if (lane == 0) {
-                        l_htab[base + d] = l_hM[kr];
-                        l_nt[base + d] = ((amv >> (16 + d)) & 1u) ? 0u : 1u;
-                    }
-                }
+                const int b = __builtin_amdgcn_readlane(tbase, v);
+                const int w = __builtin_amdgcn_readlane(om, v);
+                const bool own = lane >= b && lane < b + w;
+                rv = own ? v : rv;
+                rd = own ? lane - b : rd;
+                rb = own ? b : rb;
+                rw = own ? w : rw;
             }
-            wave_lds_sync();
+            // (shuffles run on every lane: a source lane must not be masked off)
+            const bool isrow = lane < nt;
+            const uint32_t amr = (uint32_t)__shfl((int)am, rv);
+            const int r0r = __shfl(r0, rv);
+            const int kr = isrow ? r0r + nth_bit(amr & 0xFFFFu, rd) : 0;
+            const int4 Rr = l_rules[kr];
+            const u64 hr = isrow ? l_hM[kr] : 0;
+            const uint32_t ncr = isrow && !((amr >> (16 + rd)) & 1u) ? 1u : 0u;
+            // hash and twin-count rows, lane-parallel: row r (not a top digit)
+            // takes h[r+1] - h[r] plus, over the later V neurons, h[0] - h[top];
+            // those sums are suffix sums over the rows from the next neuron's first
+            const int rtop = max(rb + rw - 1, 0);
+            const u64 htop = __shfl(hr, rtop), hnext = __shfl(hr, min(lane + 1, 63));
+            const uint32_t ntop = (uint32_t)__shfl((int)ncr, rtop), nnext = (uint32_t)__shfl((int)ncr, min(lane + 1, 63));
+            const u64 e1 = isrow && rd == 0 ? hr - htop : 0;
+            const uint32_t n1 = isrow && rd == 0 ? ncr - ntop : 0u;
+            // suffix sums (rows r .. 63) as total - prefix + own term
+            const u64 ph = wave_incl_u64(e1);
+            const uint32_t pn = wave_incl_u32(n1);
+            const u64 eh = readlane64(ph, 63) - ph + e1;
+            const uint32_t en = (uint32_t)__builtin_amdgcn_readlane((int)pn, 63) - pn + n1;
+            const int nxt = rb + rw;  // <= nt <= 32: rows from there on sum to the later neurons'
+            const u64 hU = hnext - hr + __shfl(eh, nxt);
+            const uint32_t nU = nnext - ncr + (uint32_t)__shfl((int)en, nxt);
+            // the U rows, lane = neuron j, rows from the last down (later V
+            // neurons first): Sv sums T[v'][0] - T[v'][top] over the later ones
+            const int rflag = (rd == rw - 1 ? 1 : 0) | (rd == 0 ? 2 : 0);
             {
-                uint32_t S = 0, nS = 0;
-                u64 hS = 0;
-                for (u64 vq = vmask; vq; vq &= ~(1ULL << (63 - __clzll((long long)vq)))) {
-                    const int v = 63 - __clzll((long long)vq);  // from the last V neuron back
-                    const int wv_ = __builtin_amdgcn_readlane(om, v);
-                    const int base = __builtin_amdgcn_readlane(tbase, v);
-                    const uint32_t t0 = l_tab[base * 64 + lane], tl = l_tab[(base + wv_ - 1) * 64 + lane];
-                    const u64 h0 = l_htab[base], hl = l_htab[base + wv_ - 1];
-                    const uint32_t n0 = l_nt[base], nl = l_nt[base + wv_ - 1];
-                    uint32_t tcur = t0, ncur = n0;
-                    u64 hcur = h0;
-                    for (int d = 0; d + 1 < wv_; ++d) {
-                        const uint32_t tn = l_tab[(base + d + 1) * 64 + lane];
-                        const u64 hn = l_htab[base + d + 1];
-                        const uint32_t nn = l_nt[base + d + 1];
-                        wave_lds_sync();
-                        l_tab[(base + d) * 64 + lane] = tn - tcur + S;
-                        if (lane == 0) {
-                            l_htab[base + d] = hn - hcur + hS;
-                            l_nt[base + d] = nn - ncur + nS;
-                        }
-                        tcur = tn;
-                        hcur = hn;
-                        ncur = nn;
-                    }
-                    S += t0 - tl;
-                    hS += h0 - hl;
-                    nS += n0 - nl;
+                uint32_t Sv = 0, Tprev = 0, Ttop = 0;
+                for (int r = nt - 1; r >= 0; --r) {
+                    const int v = __builtin_amdgcn_readlane(rv, r);
+                    const uint32_t cr = (uint32_t)__builtin_amdgcn_readlane(Rr.z, r);
+                    const uint32_t pr = (uint32_t)__builtin_amdgcn_readlane(Rr.w, r);
+                    const int fl = __builtin_amdgcn_readlane(rflag, r);
+                    const uint32_t Tr = (lane == v ? 0u - cr : 0u) + (((inmask >> v) & 1) ? pr : 0u);
+                    if (fl & 1) Ttop = Tr;  // top digit: never steps up
+                    else l_tab[r * 64 + lane] = Tprev - Tr + Sv;
+                    if (fl & 2) Sv += Tr - Ttop;
+                    Tprev = Tr;
                 }
             }
             wave_lds_sync();
@@ -744,39 +770,73 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
             // twins; V neurons count their non-canonical digits
             const bool nc = act && om >= 2 && !((am >> (16 + dg0)) & 1u);
             const bool fixed_twin = __ballot(nc && !inV) != 0;
-            uint32_t vnc = (uint32_t)__popcll(__ballot(nc && inV));
-
-            for (int i = 0; i < len; ++i) {
-                const long long b = b0 + k + i;
-                const bool twin = fixed_twin || vnc != 0;
-                if (!twin && act) {
-                    stage[b * m + lane] = (T)(val - kLaneOff);
-                    vmin = min(vmin, val);
-                    vmax = max(vmax, val);
+            // the reference child's digits over V as one mixed-radix number (the
+            // last V neuron lowest); it stays below the product of omega over V
+            // (< 2^17 for tables of at most 32 rows) for the whole segment
+            uint32_t x0 = 0;
+            for (u64 vq = vmask; vq; vq &= vq - 1) {
+                const int v = __builtin_ctzll(vq);
+                x0 = x0 * (uint32_t)__builtin_amdgcn_readlane(om, v) + (uint32_t)__builtin_amdgcn_readlane(dg0, v);
+            }
+            u64 Hc = uni64(Hs);  // hash of the chunk's first child
+            uint32_t vc = __builtin_amdgcn_readfirstlane((uint32_t)__popcll(__ballot(nc && inV)));
+            int rowc = 0;        // step row into the chunk's first child (chunks after the first)
+            len = __builtin_amdgcn_readfirstlane(len);
+            T* srow = stage + (b0 + k) * (long long)m + lane;
+            for (int c0 = 0; c0 < len; c0 += 64) {
+                const int nch = min(64, len - c0);
+                // lane l: the odometer step from child c0 + l to c0 + l + 1, found
+                // from the digits of its V value (the lowest digit below its top
+                // steps up; U row tbase + digit of that neuron)
+                const bool step = c0 + lane + 1 < len;
+                uint32_t y = x0 + (uint32_t)(c0 + lane);
+                int row = 0;
+                bool carry = true;
+                for (u64 vq = vmask; vq && __any(carry && step);) {
+                    const int v = 63 - __clzll((long long)vq);  // lowest digit first
+                    vq &= ~(1ULL << v);
+                    const uint32_t w = (uint32_t)__builtin_amdgcn_readlane(om, v);
+                    const int bv = __builtin_amdgcn_readlane(tbase, v);
+                    const uint32_t q = udiv_small(y, w);
+                    const uint32_t dgt = y - q * w;
+                    const bool here = carry && dgt != w - 1;
+                    row = here ? bv + (int)dgt : row;
+                    carry = carry && !here;
+                    y = q;
                 }
-                const int kk = (k + i) & 63;
-                const u64 hk = fmix64(Hs) & a.hash_mask;  // uniform: scalar unit
-                const bool mine = lane == kk;
-                o_hash = mine ? hk : o_hash;
-                o_par = mine ? (twin ? -1 - (int)p : (int)p) : o_par;
-                o_ct = mine ? t + (u64)i : o_ct;
-                if (kk == 63 || k + i + 1 == cnt) {
-                    const long long bb = b0 + ((k + i) & ~63) + lane;
-                    if (lane <= kk) {
-                        a.hash[bb] = o_hash;
-                        a.cpar[bb] = o_par;
-                        a.ct[bb] = o_ct;
+                // hash and twin count of child c0 + l: the chunk's first child's
+                // plus the changes of the steps of lanes before l
+                const u64 hrow = __shfl(hU, row);
+                const uint32_t nrow = (uint32_t)__shfl((int)nU, row);
+                const u64 hstep = step ? hrow : 0;
+                const uint32_t nstep = step ? nrow : 0u;
+                const u64 hin = wave_incl_u64(hstep);
+                const uint32_t nin = wave_incl_u32(nstep);
+                const bool mine = lane < nch;
+                const bool twin = fixed_twin || vc + (nin - nstep) != 0;
+                if (mine) {
+                    const long long bq = b0 + k + c0 + lane;
+                    a.hash[bq] = fmix64(Hc + (hin - hstep)) & a.hash_mask;
+                    a.cpar[bq] = twin ? -1 - (int)p : (int)p;
+                    a.ct[bq] = t + (u64)(c0 + lane);
+                }
+                const u64 twins = __ballot(twin && mine);
+                Hc += readlane64(hin, 63);
+                vc += (uint32_t)__builtin_amdgcn_readlane((int)nin, 63);
+                // the rows, one child after the other: one table row per step,
+                // read one child ahead
+                uint32_t u = c0 > 0 ? l_tab[rowc * 64 + lane] : 0u;
+                for (int l = 0; l < nch; ++l) {
+                    val += u;
+                    if (l + 1 < nch) u = l_tab[__builtin_amdgcn_readlane(row, l) * 64 + lane];
+                    if (!((twins >> l) & 1) && act) {
+                        *srow = (T)(val - kLaneOff);
+                        vmin = min(vmin, val);
+                        vmax = max(vmax, val);
                     }
+                    srow += m;
                 }
-                if (i + 1 == len) break;
-                // odometer step on the packed digits: the lowest field below its
-                // top steps up, the fields under it reset (f != fmax inside the segment)
-                const int J4 = __builtin_ctzll(f ^ fmax) & ~3;
-                const int row = __builtin_amdgcn_readlane(ubase, J4 >> 2) + (int)((f >> J4) & 15u);
-                f = (f & ~((1ULL << J4) - 1)) + (1ULL << J4);
-                val += l_tab[row * 64 + lane];
-                Hs += l_htab[row];
-                vnc += l_nt[row];
+                rowc = __builtin_amdgcn_readlane(row, 63);
             }
             k += len;
             t += (u64)len;
@@ -823,7 +883,7 @@ hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkA
         // chunk's true size is known
         const long long waves = std::min<long long>((a.B + 3) / 4, 4096);
         const unsigned blocks = (unsigned)((waves + 3) / 4);
-        const size_t lds = (size_t)std::max(1, s.r) * 24 + 4 * (size_t)(kLaneTab * 64 + 4 * kLaneTab) * 4;
+        const size_t lds = (size_t)std::max(1, s.r) * 24 + 4 * (size_t)(kLaneTab * 64) * 4;
         if (elem_bytes == 4) hipLaunchKernelGGL((k_expand_lane<int32_t>), dim3(blocks), dim3(256), lds, st, s, a);
         else hipLaunchKernelGGL((k_expand_lane<uint16_t>), dim3(blocks), dim3(256), lds, st, s, a);
         return hipGetLastError();

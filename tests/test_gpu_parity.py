@@ -355,3 +355,43 @@ def test_halting_counts_after_cut(gpu, oracle_mod, path):
         note(f"halting after cut: tiny seed {seed}, path {path}")
         assert_same_bfs(gpu_bfs(s, max_depth=8, out_capacity=256, chunk=4096, path=path, frontier_cap=3),
                         oracle_mod.bfs(s, max_depth=8, frontier_cap=3))
+
+
+def wide_psi_system(m):
+    """Every neuron holds 2 applicable rules (c = 1 and c = 2, p = 1) and 2
+    in-synapses, so Psi(C0) = 2^m, far beyond 2^32, and child t has a closed
+    form: neuron j fires its second rule iff bit m-1-j of t is set (Algorithm 2
+    II-3, neuron 1 most significant), giving C0[n] + 2 - 1 - bit_n(t)."""
+    rules = []
+    for n in range(m):
+        rules += [(n, 1, 1, 1, 1), (n, 2, 1, 2, 1)]
+    syn = [(n, (n + 1) % m) for n in range(m)] + [(n, (n + 7) % m) for n in range(m)]
+    c0 = [5 + (n % 3) for n in range(m)]
+    return synth.make_system(m, rules, syn, c0, name=f"wide_psi_m{m}")
+
+
+@pytest.mark.parametrize("m,path", [(40, snp.SNP_PATH_SPARSE), (80, snp.SNP_PATH_SPARSE), (40, snp.SNP_PATH_INT8)])
+def test_psi_beyond_32_bits(gpu, m, path):
+    """Parents with Psi > 2^32 (64-bit digit decomposition).  The oracle
+    enumerates every child to count Psi, so at 2^m children these runs are
+    checked against the closed form instead: level 1 is children 0 .. cap-1
+    of C0 (all distinct), level 2 the same children of level 1's first row."""
+    s = wide_psi_system(m)
+    cap = 3000
+    note(f"Psi = 2^{m}, path {path}")
+    g = gpu_bfs(s, max_depth=2, frontier_cap=cap, stop_at_cap=False, out_capacity=1 + 2 * cap, path=path)
+    assert g["level_sizes"].tolist() == [1, cap, cap]
+    st = g["level_stats"]
+    # children counts saturate at 2^62
+    assert st[0]["children_total"] == min(2 ** m, 2 ** 62)
+    assert st[0]["enumerated"] == cap and st[0]["halting_parents"] == 0
+    assert st[1]["enumerated"] == cap
+    c0 = np.asarray(s.c0, dtype=np.int64)
+    t = np.arange(cap, dtype=np.int64)
+    bits = (t[:, None] >> (m - 1 - np.arange(m))[None, :]) & 1
+    lvl1 = c0[None, :] + 1 - bits
+    lvl2 = lvl1[0][None, :] + 1 - bits
+    assert np.array_equal(g["rows"][1:1 + cap], lvl1)
+    assert np.array_equal(g["rows"][1 + cap:], lvl2)
+    assert g["parent"].tolist() == [-1] + [0] * cap + [1] * cap
+    assert g["tindex"].tolist() == [-1] + list(range(cap)) * 2
