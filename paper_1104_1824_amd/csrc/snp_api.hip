@@ -385,10 +385,17 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
     long long halting_all = 0;  // halting parents in [0, P)
     auto launch_extension = [&]() -> snp_status {
         const long long P1 = std::min(io.n, P + std::max<long long>(4096, P));
-        HIPCHK(snp::launch_psi(S->elem_bytes, S->dsys, (const char*)io.frontier + P * rb, P1 - P,
-                               S->opt.expand_max_count, S->d_psi + P, S->d_hflag + P, S->d_ctr, S->stream));
-        HIPCHK(snp::launch_scan_u64(S->d_psi + P, S->d_off + P, P1 - P, S->d_sc_sums, S->d_sc_pre, S->d_T,
-                                    P == 0 ? nullptr : S->d_T, &S->d_ctr->psi_total, S->stream));
+        const char* f = (const char*)io.frontier + P * rb;
+        if (snp::psi_scan_fits(P1 - P)) {  // a few parents: one launch
+            HIPCHK(snp::launch_psi_scan_small(S->elem_bytes, S->dsys, f, P1 - P, S->opt.expand_max_count,
+                                              S->d_psi + P, S->d_hflag + P, S->d_off + P,
+                                              P == 0 ? nullptr : S->d_T, S->d_T, S->d_ctr, S->stream));
+        } else {
+            HIPCHK(snp::launch_psi(S->elem_bytes, S->dsys, f, P1 - P, S->opt.expand_max_count, S->d_psi + P,
+                                   S->d_hflag + P, S->d_ctr, S->stream));
+            HIPCHK(snp::launch_scan_u64(S->d_psi + P, S->d_off + P, P1 - P, S->d_sc_sums, S->d_sc_pre, S->d_T,
+                                        P == 0 ? nullptr : S->d_T, &S->d_ctr->psi_total, S->stream));
+        }
         P = P1;
         return SNP_OK;
     };

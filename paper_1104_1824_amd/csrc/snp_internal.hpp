@@ -159,6 +159,13 @@ hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st);
 
 hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, long long n,
                       long long expand_max, u64* psi, uint8_t* halt_flag, DevCounters* ctr, hipStream_t st);
+bool psi_scan_fits(long long n);  // launch_psi_scan_small takes n parents
+// Psi, halting flags and offsets of n (psi_scan_fits) parents in one launch;
+// offsets start at *base_dev (nullable: 0); the new total goes to *total_dev
+// and ctr->psi_total, the halting parents are added to ctr->halting.
+hipError_t launch_psi_scan_small(int elem_bytes, const DevSystem& s, const void* frontier, long long n,
+                                 long long expand_max, u64* psi, uint8_t* halt_flag, u64* off, const u64* base_dev,
+                                 u64* total_dev, DevCounters* ctr, hipStream_t st);
 hipError_t launch_scan_u64(const u64* in, u64* out, long long n, u64* tile_sums, u64* tile_pre,
                            u64* total, const u64* base_dev, u64* total_copy, hipStream_t st);
 hipError_t launch_count_flags(const uint8_t* flags, long long n, u64* out, hipStream_t st);

@@ -31,6 +31,62 @@ __device__ __forceinline__ u64 wave_satprod(u64 x) {
     return x;
 }
 
+// Psi of one parent (Algorithm 2: the product over neurons of the number of
+// applicable rules, a neuron without one counting 1; 0 when no neuron has an
+// applicable rule, or when a count exceeds expand_max), one wave, lane per
+// neuron; halting = no rule applies anywhere.
+template <typename T>
+__device__ __forceinline__ u64 parent_psi(const T* row, int m, const int* nrp, const int4* rules, long long expand_max,
+                                          int lane, bool& halting) {
+    uint32_t c2 = 0, c3 = 0, c4 = 0;
+    bool any = false, over = false, big = false;
+    u64 bigprod = 1;
+    for (int base = 0; base < m; base += 64) {
+        const int j = base + lane;
+        int w = 0;
+        if (j < m) {
+            const int x = (int)row[j];
+            const int r1 = nrp[j + 1];
+            for (int q = nrp[j]; q < r1; ++q) w += rule_applies(x, rules[q]) ? 1 : 0;
+            over |= (expand_max >= 0 && (long long)x > expand_max);
+        }
+        any |= (w > 0);
+        c2 += __popcll(__ballot(w == 2));
+        c3 += __popcll(__ballot(w == 3));
+        c4 += __popcll(__ballot(w == 4));
+        if (w > 4) {
+            big = true;
+            bigprod = sat_mul(bigprod, (u64)w);
+        }
+    }
+    const bool wany = __any(any);
+    const bool wover = __any(over);
+    u64 prod = sat_mul(sat_mul(sat_pow(2, c2), sat_pow(3, c3)), sat_pow(4, c4));
+    if (__any(big)) prod = sat_mul(prod, wave_satprod(bigprod));
+    halting = !wany;
+    return (!wany || wover) ? 0 : prod;
+}
+
+// Rules and rule offsets staged in LDS when they fit (else read from global).
+struct PsiTables {
+    const int* nrp;
+    const int4* rules;
+};
+
+template <bool TBL_LDS>
+__device__ __forceinline__ PsiTables stage_psi_tables(const DevSystem& s, unsigned char* smem) {
+    if constexpr (TBL_LDS) {
+        int4* l_rules = (int4*)smem;
+        int* l_nrp = (int*)(l_rules + s.r);
+        for (int q = threadIdx.x; q < s.r; q += blockDim.x) l_rules[q] = s.rules[q];
+        for (int q = threadIdx.x; q <= s.m; q += blockDim.x) l_nrp[q] = s.nrule_ptr[q];
+        __syncthreads();
+        return PsiTables{l_nrp, l_rules};
+    } else {
+        return PsiTables{s.nrule_ptr, s.rules};
+    }
+}
+
 template <typename T, bool TBL_LDS>
 __global__ __launch_bounds__(256) void k_psi(DevSystem s, const T* __restrict__ F, long long n,
                                              long long expand_max, u64* __restrict__ psi,
@@ -38,54 +94,73 @@ __global__ __launch_bounds__(256) void k_psi(DevSystem s, const T* __restrict__ 
                                              int parents_per_wave) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
-    const int m = s.m;
-    const int* nrp = s.nrule_ptr;
-    const int4* rules = s.rules;
-    if constexpr (TBL_LDS) {
-        int4* l_rules = (int4*)smem;
-        int* l_nrp = (int*)(l_rules + s.r);
-        for (int q = threadIdx.x; q < s.r; q += blockDim.x) l_rules[q] = s.rules[q];
-        for (int q = threadIdx.x; q <= m; q += blockDim.x) l_nrp[q] = s.nrule_ptr[q];
-        __syncthreads();
-        nrp = l_nrp;
-        rules = l_rules;
-    }
+    const PsiTables tb = stage_psi_tables<TBL_LDS>(s, smem);
     const long long w0 = ((long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * parents_per_wave;
     unsigned halting = 0;
     for (long long p = w0; p < min(n, w0 + parents_per_wave); ++p) {
-        const T* row = F + p * (long long)m;
-        uint32_t c2 = 0, c3 = 0, c4 = 0;
-        bool any = false, over = false, big = false;
-        u64 bigprod = 1;
-        for (int base = 0; base < m; base += 64) {
-            const int j = base + lane;
-            int w = 0;
-            if (j < m) {
-                const int x = (int)row[j];
-                const int r1 = nrp[j + 1];
-                for (int q = nrp[j]; q < r1; ++q) w += rule_applies(x, rules[q]) ? 1 : 0;
-                over |= (expand_max >= 0 && (long long)x > expand_max);
-            }
-            any |= (w > 0);
-            c2 += __popcll(__ballot(w == 2));
-            c3 += __popcll(__ballot(w == 3));
-            c4 += __popcll(__ballot(w == 4));
-            if (w > 4) {
-                big = true;
-                bigprod = sat_mul(bigprod, (u64)w);
-            }
-        }
-        const bool wany = __any(any);
-        const bool wover = __any(over);
-        u64 prod = sat_mul(sat_mul(sat_pow(2, c2), sat_pow(3, c3)), sat_pow(4, c4));
-        if (__any(big)) prod = sat_mul(prod, wave_satprod(bigprod));
+        bool h;
+        const u64 v = parent_psi<T>(F + p * (long long)s.m, s.m, tb.nrp, tb.rules, expand_max, lane, h);
         if (lane == 0) {
-            psi[p] = (!wany || wover) ? 0 : prod;
-            halt_flag[p] = wany ? 0 : 1;
+            psi[p] = v;
+            halt_flag[p] = h ? 1 : 0;
         }
-        halting += wany ? 0u : 1u;
+        halting += h ? 1u : 0u;
     }
     if (lane == 0 && halting) atomicAdd(&ctr->halting, (u64)halting);
+}
+
+// Psi of at most kPsiScanSmall parents and their exclusive prefix sums in one
+// block: the waves take the parents in turn, then the block scans them from
+// the base *base_dev (the children of the frontier before them, saturated),
+// writing the new total to *total_dev and to ctr->psi_total.
+constexpr int kPsiScanSmall = 1024;
+
+template <typename T, bool TBL_LDS>
+__global__ __launch_bounds__(1024) void k_psi_scan_small(DevSystem s, const T* __restrict__ F, int n,
+                                                         long long expand_max, u64* __restrict__ psi,
+                                                         uint8_t* __restrict__ halt_flag, u64* __restrict__ off,
+                                                         const u64* base_dev, u64* total_dev,
+                                                         DevCounters* __restrict__ ctr) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ u64 wsum[16];
+    __shared__ u64 l_psi[kPsiScanSmall];
+    __shared__ u64 s_base;  // read before the total (possibly the same word) is written
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_base = base_dev ? *base_dev : 0;
+    const PsiTables tb = stage_psi_tables<TBL_LDS>(s, smem);
+    unsigned halting = 0;
+    for (int p = wid; p < n; p += 16) {
+        bool h;
+        const u64 v = parent_psi<T>(F + (long long)p * s.m, s.m, tb.nrp, tb.rules, expand_max, lane, h);
+        if (lane == 0) {
+            l_psi[p] = v;
+            psi[p] = v;
+            halt_flag[p] = h ? 1 : 0;
+        }
+        halting += h ? 1u : 0u;
+    }
+    if (lane == 0 && halting) atomicAdd(&ctr->halting, (u64)halting);
+    __syncthreads();
+    const int i = threadIdx.x;
+    const u64 x = i < n ? l_psi[i] : 0;
+    u64 incl = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const u64 y = __shfl_up(incl, o);
+        if (lane >= o) incl = sat_add(incl, y);
+    }
+    u64 excl = __shfl_up(incl, 1);  // (not incl - x: sums may have saturated)
+    if (lane == 0) excl = 0;
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    u64 pre = s_base;
+    for (int w = 0; w < wid; ++w) pre = sat_add(pre, wsum[w]);
+    if (i < n) off[i] = sat_add(pre, excl);
+    if (i == 1023) {
+        const u64 tot = sat_add(pre, incl);
+        *total_dev = tot;
+        ctr->psi_total = tot;
+    }
 }
 
 hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, long long n,
@@ -110,6 +185,29 @@ hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, 
         else SNP_PSI(uint16_t, false);
     }
 #undef SNP_PSI
+    return hipGetLastError();
+}
+
+bool psi_scan_fits(long long n) { return n > 0 && n <= kPsiScanSmall; }
+
+hipError_t launch_psi_scan_small(int elem_bytes, const DevSystem& s, const void* frontier, long long n,
+                                 long long expand_max, u64* psi, uint8_t* halt_flag, u64* off, const u64* base_dev,
+                                 u64* total_dev, DevCounters* ctr, hipStream_t st) {
+    if (!psi_scan_fits(n)) return hipErrorInvalidValue;
+    const size_t tbl = (size_t)s.r * 16 + (size_t)(s.m + 1) * 4;
+    const bool tbl_lds = tbl <= (size_t)(32 * 1024);
+    const size_t lds = tbl_lds ? tbl : 0;
+#define SNP_PSS(TT, L)                                                                                     \
+    hipLaunchKernelGGL((k_psi_scan_small<TT, L>), dim3(1), dim3(1024), lds, st, s, (const TT*)frontier, (int)n, \
+                       expand_max, psi, halt_flag, off, base_dev, total_dev, ctr)
+    if (elem_bytes == 4) {
+        if (tbl_lds) SNP_PSS(int32_t, true);
+        else SNP_PSS(int32_t, false);
+    } else {
+        if (tbl_lds) SNP_PSS(uint16_t, true);
+        else SNP_PSS(uint16_t, false);
+    }
+#undef SNP_PSS
     return hipGetLastError();
 }
 

@@ -70,6 +70,17 @@ class snp_expand_stats(ctypes.Structure):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
 
 
+# the same layout as a numpy record, to read many entries at once
+_STATS_NAMES = tuple(name for name, _ in snp_expand_stats._fields_)
+_STATS_DTYPE = np.dtype([(name, np.int64 if ct is ctypes.c_int64 else np.int32)
+                         for name, ct in snp_expand_stats._fields_], align=True)
+assert _STATS_DTYPE.itemsize == ctypes.sizeof(snp_expand_stats)
+
+
+def _stats_list(stats, n: int) -> list:
+    return [dict(zip(_STATS_NAMES, row)) for row in np.frombuffer(stats, dtype=_STATS_DTYPE, count=n).tolist()]
+
+
 _lib = None
 
 
@@ -245,7 +256,7 @@ def snp_run(h: Handle, c0_dev, max_depth: int, out_dev, out_capacity: int, max_l
         n_configs=int(n_configs.value),
         level_sizes=sizes[:L].copy(),
         stop_reason=int(stop.value),
-        level_stats=[stats[k].as_dict() for k in range(L)] if stats is not None else None,
+        level_stats=_stats_list(stats, L) if stats is not None else None,
     )
 
 

@@ -104,3 +104,17 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(snp, "library_path", lambda: str(tmp_path / "missing.so"))
     with pytest.raises(FileNotFoundError):
         snp.lib()
+
+
+def test_stats_record_layout():
+    """The binding reads level statistics through a numpy record of the same
+    layout as snp_expand_stats: both views agree field by field."""
+    import ctypes
+
+    from paper_1104_1824_amd import snp
+
+    stats = (snp.snp_expand_stats * 3)()
+    for k in range(3):
+        for i, (name, ct) in enumerate(snp.snp_expand_stats._fields_):
+            setattr(stats[k], name, (k + 1) * 1000 + i - (7 if ct is ctypes.c_int32 else 0))
+    assert snp._stats_list(stats, 3) == [stats[k].as_dict() for k in range(3)]
