@@ -25,6 +25,9 @@ if ROOT not in sys.path:
 
 METRIC = "new configurations/sec (deduped) per BFS step; int8-MFMA/batched vs plain sparse"
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+# bytes per child of the one-neuron-per-lane expansion besides its row: key 8,
+# parent 4, child index 8, probe slot 4, visited-set entry 8
+LANE_CHILD_EXTRA = 32
 
 
 def log(msg):
@@ -192,8 +195,10 @@ def measured_traffic():
 def roofline(system, results):
     """Roofline of the expansion kernel: its algorithmic bytes over its device
     time.  Algorithmic bytes per launch = children computed x (row bytes written
-    + 20 B of per-child hash, parent index and child index); parent rows, read
-    once per segment of children, are not counted."""
+    + 20 B of per-child key, parent index and child index + 12 B of its
+    visited-set probe: the slot index and the entry it writes); parent rows,
+    read once per segment of children, and the entry read by the probe's
+    compare-and-swap are not counted."""
     rb = system.m * 4
     ns = 0
     launches = 0
@@ -204,7 +209,7 @@ def roofline(system, results):
             launches += st["chunks"]
             children += st["expanded"]
     steps = len(results)
-    bytes_expand = children * (rb + 20)
+    bytes_expand = children * (rb + LANE_CHILD_EXTRA)
     achieved = bytes_expand / max(1, ns)  # bytes per ns = GB/s
     return dict(
         kernel="k_expand_lane",

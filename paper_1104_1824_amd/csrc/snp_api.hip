@@ -444,13 +444,15 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         if (ext && (st = launch_extension())) return st;
         if ((st = mark(S, 1))) return st;
         snp::ChunkArgs ca{io.frontier, P, S->d_psi, S->d_off, G, B, S->d_stage, S->d_hash, S->d_cpar, S->d_ct,
-                          hmask, S->d_ctr, S->d_T, S->opt.int8_max_k > 0 ? S->opt.int8_max_k : 128};
+                          hmask, S->d_ctr, S->d_T, S->opt.int8_max_k > 0 ? S->opt.int8_max_k : 128,
+                          S->d_table, S->slots - 1, S->d_slot, S->d_cand};
+        bool probed = false;
         if (use_int8) HIPCHK(snp::launch_expand_int8(S->elem_bytes, S->dsys, ca, S->stream));
-        else HIPCHK(snp::launch_expand_sparse(S->elem_bytes, S->dsys, ca, S->stream));
+        else HIPCHK(snp::launch_expand_sparse(S->elem_bytes, S->dsys, ca, S->stream, &probed));
         if ((st = mark(S, 2))) return st;
         snp::TableArgs ta{S->d_table, S->slots - 1, io.arena, S->d_stage, S->d_hash, S->d_slot, B, S->d_ctr,
                           S->d_cand, S->d_cpar};
-        HIPCHK(snp::launch_insert(S->elem_bytes, S->m, ta, S->stream));
+        HIPCHK(snp::launch_insert(S->elem_bytes, S->m, ta, S->stream, !probed));
         if ((st = mark(S, 3))) return st;
         HIPCHK(snp::launch_flags(S->d_table, S->d_slot, S->d_cpar, B, S->d_ctr, S->d_flag, S->d_pos, S->d_fsums,
                                  S->d_fpre, S->stream));

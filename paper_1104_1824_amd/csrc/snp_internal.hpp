@@ -71,6 +71,12 @@ struct ChunkArgs {
     DevCounters* ctr;
     const u64* Tdev;       // children of the frontier prefix [0, n): the chunk stops there
     int kmax;              // int8 form: most rule columns a segment may put on the matrix cores
+    // visited-set probe done by the expansion itself (the one-neuron-per-lane
+    // form); null table: the probe runs as a kernel of its own
+    u64* table;
+    u64 slot_mask;
+    uint32_t* slot;        // [B]
+    uint32_t* cand;        // [B]
 };
 
 // Insert/commit arguments.
@@ -173,8 +179,11 @@ hipError_t launch_count_flags_cap(const uint8_t* flags, long long n, DevCounters
 long long scan_tiles(long long n);
 hipError_t launch_expand_int8(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st);
 size_t int8_lds(int m, int nt);
-hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st);
-hipError_t launch_insert(int elem_bytes, int m, const TableArgs& a, hipStream_t st);
+// *probed: the launch also probed the visited set for every child (a.table set)
+hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st,
+                                bool* probed);
+// probe false: the children were probed by the expansion; only the row compares run
+hipError_t launch_insert(int elem_bytes, int m, const TableArgs& a, hipStream_t st, bool probe);
 hipError_t launch_flags(const u64* table, const uint32_t* slot, const int* cpar, long long B, DevCounters* ctr,
                         uint32_t* flag, uint32_t* pos, uint32_t* tile_sums, uint32_t* tile_pre, hipStream_t st);
 hipError_t launch_commit(int elem_bytes, int m, const CommitArgs& a, hipStream_t st);

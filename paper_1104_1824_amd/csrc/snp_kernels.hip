@@ -912,11 +912,21 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
                 const uint32_t nin = wave_incl_u32(nstep);
                 const bool mine = lane < nch;
                 const bool twin = fixed_twin || vc + (nin - nstep) != 0;
+                const long long bq = b0 + k + c0 + lane;
+                const u64 key = fmix64(Hc + (hin - hstep)) & a.hash_mask;
+                // visited-set probe of child bq: the CAS on its home slot is
+                // issued here and its answer read after the rows are written
+                // (twins never own an entry)
+                const bool probe = mine && !twin && a.table != nullptr;
+                const u64 me = ((key >> 32) << 32) | (u64)(kStageBase + (uint32_t)bq);
+                u64 psl = key & a.slot_mask;
+                u64 first = kEmpty;
                 if (mine) {
-                    const long long bq = b0 + k + c0 + lane;
-                    a.hash[bq] = fmix64(Hc + (hin - hstep)) & a.hash_mask;
+                    a.hash[bq] = key;
                     a.cpar[bq] = twin ? -1 - (int)p : (int)p;
                     a.ct[bq] = t + (u64)(c0 + lane);
+                    if (probe) first = atomicCAS(&a.table[psl], kEmpty, me);
+                    else if (a.table) a.slot[bq] = 0;
                 }
                 const u64 twins = __ballot(twin && mine);
                 Hc += readlane64(hin, 63);
@@ -935,6 +945,37 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
                     srow += m;
                 }
                 rowc = __builtin_amdgcn_readlane(row, 63);
+                // finish the probes: the first empty slot taken, or the first
+                // entry with the child's tag (queued for a row compare)
+                bool queue = false;
+                if (probe) {
+                    const uint32_t tag = (uint32_t)(key >> 32);
+                    u64 e = first;
+                    bool placed = false;
+                    for (u64 it = 0;;) {
+                        if (e == kEmpty) {  // this child's CAS on slot psl succeeded
+                            placed = true;
+                            break;
+                        }
+                        if (e != kTomb && (uint32_t)(e >> 32) == tag) {
+                            queue = placed = true;
+                            break;
+                        }
+                        if (++it > a.slot_mask) break;
+                        psl = (psl + 1) & a.slot_mask;
+                        e = __hip_atomic_load(&a.table[psl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (e == kEmpty) e = atomicCAS(&a.table[psl], kEmpty, me);
+                    }
+                    a.slot[bq] = placed ? (uint32_t)psl : 0u;
+                    if (!placed) atomicOr((unsigned long long*)&a.ctr->probe_fail, 1ULL);
+                }
+                const u64 qm = __ballot(queue);
+                if (qm) {
+                    u64 qbase = 0;
+                    if (lane == 0) qbase = atomicAdd((unsigned long long*)&a.ctr->ncand, (u64)__popcll(qm));
+                    qbase = __shfl(qbase, 0);
+                    if (queue) a.cand[qbase + __popcll(qm & ((1ULL << lane) - 1))] = (uint32_t)bq;
+                }
             }
             k += len;
             t += (u64)len;
@@ -973,9 +1014,12 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
     if (__any(ovf) && lane == 0) atomicOr((unsigned long long*)&a.ctr->overflow, 1ULL);
 }
 
-hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st) {
+hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st,
+                                bool* probed) {
+    *probed = false;
     if (a.B <= 0) return hipSuccess;
     if (s.m <= 64 && s.max_in <= kLaneMaxIn && (size_t)s.r * 24 <= 24 * 1024) {
+        *probed = a.table != nullptr;
         // one generation of resident waves (the LDS tables allow 16 per CU);
         // runs of 4 to 4096 children are handed out on the device, where the
         // chunk's true size is known
@@ -1120,16 +1164,16 @@ __global__ __launch_bounds__(256) void k_insert_compare(int m, TableArgs a) {
     }
 }
 
-hipError_t launch_insert(int elem_bytes, int m, const TableArgs& a, hipStream_t st) {
+hipError_t launch_insert(int elem_bytes, int m, const TableArgs& a, hipStream_t st, bool probe) {
     if (a.B <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)((a.B + 255) / 256);
     // compare pass: enough waves to cover the device, each looping over the queue
     const unsigned cblocks = (unsigned)std::min<long long>((a.B + 3) / 4, 4096);
     if (elem_bytes == 4) {
-        hipLaunchKernelGGL(k_insert_probe<int32_t>, dim3(blocks), dim3(256), 0, st, m, a);
+        if (probe) hipLaunchKernelGGL(k_insert_probe<int32_t>, dim3(blocks), dim3(256), 0, st, m, a);
         hipLaunchKernelGGL(k_insert_compare<int32_t>, dim3(cblocks), dim3(256), 0, st, m, a);
     } else {
-        hipLaunchKernelGGL(k_insert_probe<uint16_t>, dim3(blocks), dim3(256), 0, st, m, a);
+        if (probe) hipLaunchKernelGGL(k_insert_probe<uint16_t>, dim3(blocks), dim3(256), 0, st, m, a);
         hipLaunchKernelGGL(k_insert_compare<uint16_t>, dim3(cblocks), dim3(256), 0, st, m, a);
     }
     return hipGetLastError();
