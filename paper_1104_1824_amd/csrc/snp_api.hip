@@ -386,7 +386,7 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
     auto launch_extension = [&]() -> snp_status {
         const long long P1 = std::min(io.n, P + std::max<long long>(4096, P));
         const char* f = (const char*)io.frontier + P * rb;
-        if (snp::psi_scan_fits(P1 - P)) {  // a few parents: one launch
+        if (snp::psi_scan_fits(S->dsys, P1 - P)) {  // a few small parents: one launch
             HIPCHK(snp::launch_psi_scan_small(S->elem_bytes, S->dsys, f, P1 - P, S->opt.expand_max_count,
                                               S->d_psi + P, S->d_hflag + P, S->d_off + P,
                                               P == 0 ? nullptr : S->d_T, S->d_T, S->d_ctr, S->stream));

@@ -165,7 +165,7 @@ hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st);
 
 hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, long long n,
                       long long expand_max, u64* psi, uint8_t* halt_flag, DevCounters* ctr, hipStream_t st);
-bool psi_scan_fits(long long n);  // launch_psi_scan_small takes n parents
+bool psi_scan_fits(const DevSystem& s, long long n);  // launch_psi_scan_small takes n parents (m <= 64)
 // Psi, halting flags and offsets of n (psi_scan_fits) parents in one launch;
 // offsets start at *base_dev (nullable: 0); the new total goes to *total_dev
 // and ctr->psi_total, the halting parents are added to ctr->halting.

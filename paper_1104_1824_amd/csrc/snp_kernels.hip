@@ -18,9 +18,14 @@ namespace snp {
 // product over neurons of max(1, omega_n), saturated; 0 when no rule applies
 // anywhere (halting) or when the parent exceeds the expansion count limit.
 // ---------------------------------------------------------------------------
+// b^e, saturated (square and multiply: at most 7 rounds for e < 128)
 __device__ __forceinline__ u64 sat_pow(u64 b, uint32_t e) {
     u64 r = 1;
-    for (uint32_t q = 0; q < e && r < kPsiSat; ++q) r = sat_mul(r, b);
+    while (e) {
+        if (e & 1) r = sat_mul(r, b);
+        e >>= 1;
+        if (e) b = sat_mul(b, b);
+    }
     return r;
 }
 
@@ -35,36 +40,49 @@ __device__ __forceinline__ u64 wave_satprod(u64 x) {
 // applicable rules, a neuron without one counting 1; 0 when no neuron has an
 // applicable rule, or when a count exceeds expand_max), one wave, lane per
 // neuron; halting = no rule applies anywhere.
-template <typename T>
-__device__ __forceinline__ u64 parent_psi(const T* row, int m, const int* nrp, const int4* rules, long long expand_max,
-                                          int lane, bool& halting) {
+struct PsiAcc {
     uint32_t c2 = 0, c3 = 0, c4 = 0;
     bool any = false, over = false, big = false;
     u64 bigprod = 1;
-    for (int base = 0; base < m; base += 64) {
-        const int j = base + lane;
-        int w = 0;
-        if (j < m) {
-            const int x = (int)row[j];
-            const int r1 = nrp[j + 1];
-            for (int q = nrp[j]; q < r1; ++q) w += rule_applies(x, rules[q]) ? 1 : 0;
-            over |= (expand_max >= 0 && (long long)x > expand_max);
-        }
-        any |= (w > 0);
-        c2 += __popcll(__ballot(w == 2));
-        c3 += __popcll(__ballot(w == 3));
-        c4 += __popcll(__ballot(w == 4));
-        if (w > 4) {
-            big = true;
-            bigprod = sat_mul(bigprod, (u64)w);
-        }
+};
+
+// Neuron j (< m) holding x spikes: its applicable rules, into the wave's tallies.
+__device__ __forceinline__ void psi_add_neuron(PsiAcc& A, int x, int j, int m, const int* nrp, const int4* rules,
+                                               long long expand_max) {
+    int w = 0;
+    if (j < m) {
+        const int r1 = nrp[j + 1];
+        for (int q = nrp[j]; q < r1; ++q) w += rule_applies(x, rules[q]) ? 1 : 0;
+        A.over |= (expand_max >= 0 && (long long)x > expand_max);
     }
-    const bool wany = __any(any);
-    const bool wover = __any(over);
-    u64 prod = sat_mul(sat_mul(sat_pow(2, c2), sat_pow(3, c3)), sat_pow(4, c4));
-    if (__any(big)) prod = sat_mul(prod, wave_satprod(bigprod));
+    A.any |= (w > 0);
+    A.c2 += __popcll(__ballot(w == 2));
+    A.c3 += __popcll(__ballot(w == 3));
+    A.c4 += __popcll(__ballot(w == 4));
+    if (w > 4) {
+        A.big = true;
+        A.bigprod = sat_mul(A.bigprod, (u64)w);
+    }
+}
+
+__device__ __forceinline__ u64 psi_finish(const PsiAcc& A, bool& halting) {
+    const bool wany = __any(A.any);
+    const bool wover = __any(A.over);
+    u64 prod = sat_mul(sat_pow(2, A.c2 + 2 * A.c4), sat_pow(3, A.c3));  // 4^c4 = 2^(2 c4)
+    if (__any(A.big)) prod = sat_mul(prod, wave_satprod(A.bigprod));
     halting = !wany;
     return (!wany || wover) ? 0 : prod;
+}
+
+template <typename T>
+__device__ __forceinline__ u64 parent_psi(const T* row, int m, const int* nrp, const int4* rules, long long expand_max,
+                                          int lane, bool& halting) {
+    PsiAcc A;
+    for (int base = 0; base < m; base += 64) {
+        const int j = base + lane;
+        psi_add_neuron(A, j < m ? (int)row[j] : 0, j, m, nrp, rules, expand_max);
+    }
+    return psi_finish(A, halting);
 }
 
 // Rules and rule offsets staged in LDS when they fit (else read from global).
@@ -109,11 +127,11 @@ __global__ __launch_bounds__(256) void k_psi(DevSystem s, const T* __restrict__ 
     if (lane == 0 && halting) atomicAdd(&ctr->halting, (u64)halting);
 }
 
-// Psi of at most kPsiScanSmall parents and their exclusive prefix sums in one
-// block: the waves take the parents in turn, then the block scans them from
-// the base *base_dev (the children of the frontier before them, saturated),
-// writing the new total to *total_dev and to ctr->psi_total.
-constexpr int kPsiScanSmall = 1024;
+// Psi of at most kPsiScanSmall parents (m <= 64) and their exclusive prefix
+// sums in one block: a wave per parent, then the block scans them from the
+// base *base_dev (the children of the frontier before them,
+// saturated), writing the new total to *total_dev and to ctr->psi_total.
+constexpr int kPsiScanSmall = 16;  // one parent per wave: more would serialise their latency
 
 template <typename T, bool TBL_LDS>
 __global__ __launch_bounds__(1024) void k_psi_scan_small(DevSystem s, const T* __restrict__ F, int n,
@@ -128,16 +146,32 @@ __global__ __launch_bounds__(1024) void k_psi_scan_small(DevSystem s, const T* _
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (threadIdx.x == 0) s_base = base_dev ? *base_dev : 0;
     const PsiTables tb = stage_psi_tables<TBL_LDS>(s, smem);
+    // m <= 64: a parent is one count per lane
+    constexpr int kPre = (kPsiScanSmall + 15) / 16;
     unsigned halting = 0;
-    for (int p = wid; p < n; p += 16) {
-        bool h;
-        const u64 v = parent_psi<T>(F + (long long)p * s.m, s.m, tb.nrp, tb.rules, expand_max, lane, h);
-        if (lane == 0) {
-            l_psi[p] = v;
-            psi[p] = v;
-            halt_flag[p] = h ? 1 : 0;
+    const int m = s.m;
+    for (int p0 = wid; p0 < n; p0 += 16 * kPre) {
+        int xs[kPre];
+#pragma unroll
+        for (int q = 0; q < kPre; ++q) {
+            const int p = p0 + 16 * q;
+            xs[q] = (p < n && lane < m) ? (int)F[(long long)p * m + lane] : 0;
         }
-        halting += h ? 1u : 0u;
+#pragma unroll
+        for (int q = 0; q < kPre; ++q) {
+            const int p = p0 + 16 * q;
+            if (p >= n) break;
+            PsiAcc A;
+            psi_add_neuron(A, xs[q], lane, m, tb.nrp, tb.rules, expand_max);
+            bool h;
+            const u64 v = psi_finish(A, h);
+            if (lane == 0) {
+                l_psi[p] = v;
+                psi[p] = v;
+                halt_flag[p] = h ? 1 : 0;
+            }
+            halting += h ? 1u : 0u;
+        }
     }
     if (lane == 0 && halting) atomicAdd(&ctr->halting, (u64)halting);
     __syncthreads();
@@ -188,12 +222,12 @@ hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, 
     return hipGetLastError();
 }
 
-bool psi_scan_fits(long long n) { return n > 0 && n <= kPsiScanSmall; }
+bool psi_scan_fits(const DevSystem& s, long long n) { return s.m <= 64 && n > 0 && n <= kPsiScanSmall; }
 
 hipError_t launch_psi_scan_small(int elem_bytes, const DevSystem& s, const void* frontier, long long n,
                                  long long expand_max, u64* psi, uint8_t* halt_flag, u64* off, const u64* base_dev,
                                  u64* total_dev, DevCounters* ctr, hipStream_t st) {
-    if (!psi_scan_fits(n)) return hipErrorInvalidValue;
+    if (!psi_scan_fits(s, n)) return hipErrorInvalidValue;
     const size_t tbl = (size_t)s.r * 16 + (size_t)(s.m + 1) * 4;
     const bool tbl_lds = tbl <= (size_t)(32 * 1024);
     const size_t lds = tbl_lds ? tbl : 0;
@@ -301,9 +335,9 @@ long long scan_tiles(long long n) { return (n + kScanTile - 1) / kScanTile; }
 
 // out[i] = base + sum of in[0 .. i); *total = base + sum of in, where base is
 // read on the device (*base_dev, 0 when null) and may be the same word as total.
-// Up to this many elements one block scans them directly (k_scan_sums walks
-// them 1024 at a time with a carried base): one launch instead of two or three.
-constexpr long long kSmallScan = 8192;
+// Up to this many elements one block scans them directly (one pass of
+// k_scan_sums with the carried base): one launch instead of two or three.
+constexpr long long kSmallScan = 1024;
 
 template <typename V, bool SAT>
 static hipError_t scan_impl(const V* in, V* out, long long n, V* tile_sums, V* tile_pre, u64* total,
