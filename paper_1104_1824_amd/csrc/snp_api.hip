@@ -111,6 +111,7 @@ struct snp_system {
     long long walk_rows = 0;
 
     double new_ratio = 1.0;  // new / enumerated of the last chunk (chunk sizing)
+    double psi_per_parent = 0.0;  // children per examined parent of the last level (0: none yet)
 
     // stage timing (profile option): event pairs around psi+scan, expand, insert, flags+scan, commit
     static constexpr int kStages = 5;
@@ -383,8 +384,16 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
     long long P = 0;
     u64 T = 0;                  // children of parents [0, P) (saturated), known after each pass
     long long halting_all = 0;  // halting parents in [0, P)
-    auto launch_extension = [&]() -> snp_status {
-        const long long P1 = std::min(io.n, P + std::max<long long>(4096, P));
+    // The first extension of a level covers 4096 parents, or fewer (not under
+    // 1024) when the last level's children per parent say that enough for the
+    // first chunk lie in fewer; later ones double the prefix.
+    auto launch_extension = [&](u64 want) -> snp_status {
+        long long grow = std::max<long long>(4096, P);
+        if (P == 0 && want > 0 && S->psi_per_parent > 0.0) {
+            const double need = (double)want / S->psi_per_parent * 1.5 + 64.0;
+            grow = std::min<long long>(grow, std::max<long long>(1024, (long long)need));
+        }
+        const long long P1 = std::min(io.n, P + grow);
         const char* f = (const char*)io.frontier + P * rb;
         if (snp::psi_scan_fits(S->dsys, P1 - P)) {  // a few small parents: one launch
             HIPCHK(snp::launch_psi_scan_small(S->elem_bytes, S->dsys, f, P1 - P, S->opt.expand_max_count,
@@ -414,7 +423,7 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         if (G >= budget) {  // the budget is spent: is anything left?
             while (T <= G && P < io.n) {
                 if ((st = clear_counters(S))) return st;
-                if ((st = launch_extension())) return st;
+                if ((st = launch_extension(0))) return st;
                 if ((st = read_counters(S))) return st;
                 T = S->h_ctr->psi_total;
                 halting_all += (long long)S->h_ctr->halting;
@@ -441,7 +450,7 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         }
         if ((st = clear_counters(S))) return st;
         if ((st = mark(S, 0))) return st;
-        if (ext && (st = launch_extension())) return st;
+        if (ext && (st = launch_extension(want))) return st;
         if ((st = mark(S, 1))) return st;
         snp::ChunkArgs ca{io.frontier, P, S->d_psi, S->d_off, G, B, S->d_stage, S->d_hash, S->d_cpar, S->d_ct,
                           hmask, S->d_ctr, S->d_T, S->opt.int8_max_k > 0 ? S->opt.int8_max_k : 128,
@@ -532,6 +541,7 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
     } else {
         stt.halting_parents = halting_all;
     }
+    if (P > 0) S->psi_per_parent = (double)T / (double)P;
     stt.children_total = (long long)T;
     stt.enumerated = (long long)enumerated;
     stt.new_configs = count;
