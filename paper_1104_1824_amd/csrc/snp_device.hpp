@@ -208,10 +208,22 @@ __device__ __forceinline__ void decode_digits(int m, int lane, u64 t, const uint
     u64 after = __shfl_down(incl, 1);
     if (lane == 63) after = 1;
     u64 tl = (after > t) ? 0 : t / after;
-    for (int j = j1 - 1; j >= j0; --j) {
-        const uint32_t w = (uint32_t)max(1, (int)om[j]);
-        dg[j] = (uint8_t)(tl % w);
-        tl /= w;
+    if (tl == 0) {  // every digit of this lane's neurons is 0 (the usual case far from the end)
+        for (int j = j0; j < j1; ++j) dg[j] = 0;
+    } else if (tl <= 0xFFFFFFFFull) {  // 32-bit divisions suffice
+        uint32_t t32 = (uint32_t)tl;
+        for (int j = j1 - 1; j >= j0; --j) {
+            const uint32_t w = (uint32_t)max(1, (int)om[j]);
+            const uint32_t q = t32 / w;
+            dg[j] = (uint8_t)(t32 - q * w);
+            t32 = q;
+        }
+    } else {
+        for (int j = j1 - 1; j >= j0; --j) {
+            const uint32_t w = (uint32_t)max(1, (int)om[j]);
+            dg[j] = (uint8_t)(tl % w);
+            tl /= w;
+        }
     }
 }
 

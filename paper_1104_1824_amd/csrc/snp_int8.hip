@@ -144,7 +144,17 @@ __device__ __forceinline__ u64 sparse_child(const DevSystem& s, const Lds& L, co
     for (int j = threadIdx.x; j < m; j += blockDim.x) {
         long long v = (long long)P[j] - (long long)(L.cp[j] >> 8);
         const int e1 = s.in_ptr[j + 1];
-        for (int e = s.in_ptr[j]; e < e1; ++e) v += L.cp[s.in_src[e]] & 0xFF;
+        int e = s.in_ptr[j];
+        // the source indices come from global memory: eight loads in flight
+        // before their LDS reads
+        for (; e + 8 <= e1; e += 8) {
+            int src[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) src[q] = s.in_src[e + q];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v += L.cp[src[q]] & 0xFF;
+        }
+        for (; e < e1; ++e) v += L.cp[s.in_src[e]] & 0xFF;
         ovf |= (v < 0) | (v > s.count_max);
         out[j] = (T)v;
         h += hterm((uint32_t)v, s.R[j]);
@@ -302,14 +312,14 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a) {
                     bool tw = false;
                     if (tid > c && tid < cend) {
                         const int row = tid;
-                        u64 delta = (u64)(row - c);
+                        uint32_t delta = (uint32_t)(row - c);  // < 64: 32-bit arithmetic throughout
                         u64 h = href;
                         int i = nv - 1;
                         for (; i >= 0 && delta != 0; --i) {
                             const int j = L.vlist[i];
-                            const u64 w = L.om[j];
+                            const uint32_t w = L.om[j];
                             const int d0 = L.dg[j];
-                            const u64 x = (u64)d0 + delta;
+                            const uint32_t x = (uint32_t)d0 + delta;
                             const int d1 = (int)(x % w);
                             delta = x / w;
                             tw |= later_twin(L, j, d1);
