@@ -192,8 +192,10 @@ __device__ __forceinline__ uint32_t canonical_mask(const int4* rules, int r0, ui
 // Mixed-radix decode of child index t (Algorithm 2 II-3 order: the last neuron
 // is the least significant digit; a neuron with omega <= 1 has one value).
 // Lane L owns the contiguous neurons [L*Q, L*Q + Q); the place value of its
-// block is a suffix product across lanes (saturated at 2^62, above any t).
-__device__ __forceinline__ void decode_digits(int m, int lane, u64 t, const uint8_t* om, uint8_t* dg) {
+// block is a suffix product across lanes (saturated at 2^62, above any t),
+// which depends on the parent only (digit_place) and can be kept across
+// decodes of children of one parent (decode_digits_at).
+__device__ __forceinline__ u64 digit_place(int m, int lane, const uint8_t* om) {
     const int Q = (m + 63) >> 6;
     const int j0 = lane * Q;
     const int j1 = min(m, j0 + Q);
@@ -207,6 +209,13 @@ __device__ __forceinline__ void decode_digits(int m, int lane, u64 t, const uint
     }
     u64 after = __shfl_down(incl, 1);
     if (lane == 63) after = 1;
+    return after;
+}
+
+__device__ __forceinline__ void decode_digits_at(int m, int lane, u64 t, const uint8_t* om, uint8_t* dg, u64 after) {
+    const int Q = (m + 63) >> 6;
+    const int j0 = lane * Q;
+    const int j1 = min(m, j0 + Q);
     u64 tl = (after > t) ? 0 : t / after;
     if (tl == 0) {  // every digit of this lane's neurons is 0 (the usual case far from the end)
         for (int j = j0; j < j1; ++j) dg[j] = 0;
@@ -225,6 +234,10 @@ __device__ __forceinline__ void decode_digits(int m, int lane, u64 t, const uint
             tl /= w;
         }
     }
+}
+
+__device__ __forceinline__ void decode_digits(int m, int lane, u64 t, const uint8_t* om, uint8_t* dg) {
+    decode_digits_at(m, lane, t, om, dg, digit_place(m, lane, om));
 }
 
 }  // namespace snp

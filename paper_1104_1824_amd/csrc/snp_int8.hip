@@ -167,36 +167,48 @@ __device__ __forceinline__ u64 sparse_child(const DevSystem& s, const Lds& L, co
 size_t int8_lds(int m, int nt) { return int8_lds_bytes(m, nt); }
 
 template <typename T, int NT>
-__global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a) {
+__global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, int tiles_per_block) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int m = s.m;
-    const long long b0 = (long long)blockIdx.x * kTile;
+    const long long tile0 = (long long)blockIdx.x * tiles_per_block;
     const u64 tot = *a.Tdev;
     const long long Beff = tot > a.g0 ? (long long)min((u64)a.B, tot - a.g0) : 0;
     if (blockIdx.x == 0 && tid == 0) a.ctr->beff = (u64)Beff;
-    if (b0 >= Beff) return;  // whole block
-    const int rows = (int)min((long long)kTile, Beff - b0);
+    if (tile0 * kTile >= Beff) return;  // whole block
     Lds L = carve(smem, m, NT);
     const T* F = (const T*)a.frontier;
     T* stage = (T*)a.stage;
     bool ovf = false;
-    if (tid == 0) L.misc[1] = 0;
 
-    // parent of the tile's first child: 64-ary search over the offsets
-    const u64 g = a.g0 + (u64)b0;
-    long long lo = 0, hi = a.n;
-    while (hi - lo > 1) {
-        const long long step = (hi - lo + 63) / 64;
-        const long long idx = lo + (long long)lane * step;
-        const bool ok = idx < hi && a.off[idx] <= g;
-        const u64 mask = __ballot(ok);
-        lo = lo + (long long)(63 - __clzll((long long)mask)) * step;
-        hi = min(hi, lo + step);
+    // parent of the first tile's first child: 64-ary search over the offsets;
+    // later tiles go on from where the previous one stopped
+    long long p;
+    u64 ta;
+    {
+        const u64 g = a.g0 + (u64)(tile0 * kTile);
+        long long lo = 0, hi = a.n;
+        while (hi - lo > 1) {
+            const long long step = (hi - lo + 63) / 64;
+            const long long idx = lo + (long long)lane * step;
+            const bool ok = idx < hi && a.off[idx] <= g;
+            const u64 mask = __ballot(ok);
+            lo = lo + (long long)(63 - __clzll((long long)mask)) * step;
+            hi = min(hi, lo + step);
+        }
+        p = lo;  // every wave computes the same value
+        ta = g - a.off[p];
     }
-    long long p = lo;  // every wave computes the same value
-    u64 ta = g - a.off[p];
+    // the parent whose applicability is in L.om / L.am (and whose digit
+    // place values wave 0 holds): consecutive tiles mostly share it
+    long long have_p = -1;
+    u64 place = 0;
 
+    for (int tt = 0; tt < tiles_per_block; ++tt) {
+    const long long b0 = (tile0 + tt) * kTile;
+    if (b0 >= Beff) break;
+    const int rows = (int)min((long long)kTile, Beff - b0);
+    if (tid == 0) L.misc[1] = 0;
     int c = 0;
     while (c < rows) {
         const u64 psi_p = a.psi[p];
@@ -205,26 +217,31 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a) {
         const u64 tb = ta + (u64)(len - 1);
         const T* P = F + p * (long long)m;
 
-        // 1. applicability of the parent
-        for (int j = tid; j < m; j += blockDim.x) {
-            const int x = (int)P[j];
-            uint32_t mask = 0;
-            int w = 0;
-            const int r0 = s.nrule_ptr[j], r1 = s.nrule_ptr[j + 1];
-            for (int q = r0; q < r1; ++q)
-                if (rule_applies(x, s.rules[q])) {
-                    mask |= 1u << (q - r0);
-                    ++w;
-                }
-            L.am[j] = mask | (w >= 2 ? canonical_mask(s.rules, r0, mask) << 16 : 0xFFFF0000u);
-            L.om[j] = (uint8_t)w;
+        // 1. applicability of the parent (kept while the parent stays)
+        const bool fresh = p != have_p;
+        if (fresh) {
+            for (int j = tid; j < m; j += blockDim.x) {
+                const int x = (int)P[j];
+                uint32_t mask = 0;
+                int w = 0;
+                const int r0 = s.nrule_ptr[j], r1 = s.nrule_ptr[j + 1];
+                for (int q = r0; q < r1; ++q)
+                    if (rule_applies(x, s.rules[q])) {
+                        mask |= 1u << (q - r0);
+                        ++w;
+                    }
+                L.am[j] = mask | (w >= 2 ? canonical_mask(s.rules, r0, mask) << 16 : 0xFFFF0000u);
+                L.om[j] = (uint8_t)w;
+            }
+            have_p = p;
         }
         if (tid == 0) L.sc[0] = m;
         __syncthreads();
         // 2. digits of the first and last child of the segment
         if (wid == 0) {
-            decode_digits(m, lane, ta, L.om, L.dg);
-            decode_digits(m, lane, tb, L.om, L.dgb);
+            if (fresh) place = digit_place(m, lane, L.om);
+            decode_digits_at(m, lane, ta, L.om, L.dg, place);
+            decode_digits_at(m, lane, tb, L.om, L.dgb, place);
         }
         __syncthreads();
         // 3. most significant differing digit
@@ -399,26 +416,34 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a) {
             a.cpar[b0 + tid] = tw ? -1 - (int)p : (int)p;
             a.ct[b0 + tid] = ta + (u64)(tid - c);
         }
-        // next segment: next parent with children
+        // next segment: the rest of this parent's children, else the next
+        // parent with children
         c = cend;
-        if (c < rows) {
+        ta += (u64)len;
+        if (ta >= psi_p) {
             ++p;
             while (p < a.n && a.psi[p] == 0) ++p;
-            if (p >= a.n) break;  // unreachable while g0 + B <= sum of Psi
             ta = 0;
         }
         __syncthreads();
+        if (c < rows && p >= a.n) break;  // unreachable while g0 + B <= sum of Psi
+    }
+    if (p >= a.n) break;
     }
     if (__syncthreads_or(ovf) && tid == 0) atomicOr((unsigned long long*)&a.ctr->overflow, 1ULL);
 }
 
 hipError_t launch_expand_int8(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st) {
     if (a.B <= 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((a.B + kTile - 1) / kTile);
+    // consecutive tiles per block (they mostly share a parent), keeping about
+    // two rounds of resident blocks
+    const long long tiles = (a.B + kTile - 1) / kTile;
+    const int tpb = (int)std::max<long long>(1, std::min<long long>(16, tiles / 2048));
+    const unsigned blocks = (unsigned)((tiles + tpb - 1) / tpb);
     const bool wide = int8_lds_bytes(s.m, 128) <= 64 * 1024;
     const size_t lds = int8_lds_bytes(s.m, wide ? 128 : 64);
     if (lds > 64 * 1024) return hipErrorInvalidValue;
-#define SNP_I8(TT, NN) hipLaunchKernelGGL((k_expand_int8<TT, NN>), dim3(blocks), dim3(256), lds, st, s, a)
+#define SNP_I8(TT, NN) hipLaunchKernelGGL((k_expand_int8<TT, NN>), dim3(blocks), dim3(256), lds, st, s, a, tpb)
     if (elem_bytes == 4) {
         if (wide) SNP_I8(int32_t, 128);
         else SNP_I8(int32_t, 64);
