@@ -28,6 +28,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # bytes per child of the one-neuron-per-lane expansion besides its row: key 8,
 # parent 4, child index 8, probe slot 4, visited-set entry 8
 LANE_CHILD_EXTRA = 32
+TWIN_CHILD_BYTES = 12  # a twin child: parent 4 and child index 8 only
 
 
 def log(msg):
@@ -88,10 +89,14 @@ def walk_timing(system, path, cap, depth, stop, chunk, out_cap, reps):
     st = r["level_stats"]
     ns = sum(s_["ns_expand"] for s_ in st)
     expanded = sum(s_["expanded"] for s_ in st)
+    twins = sum(s_["twins"] for s_ in st)
     rb = system.m * (2 if u16 else 4)
+    # a child writes its row, key, parent and index; a twin child only its
+    # parent and index
+    moved = (expanded - twins) * (rb + 20) + twins * TWIN_CHILD_BYTES
     return dict(ms_per_walk=round(dt * 1e3, 3), new_configs=int(r["n_configs"] - 1),
                 configs_per_s=round((r["n_configs"] - 1) / dt, 1), levels=r["level_sizes"].tolist(),
-                expand_us=round(ns / 1e3, 1), expand_gbs=round(expanded * (rb + 20) / max(ns, 1), 1),
+                expand_us=round(ns / 1e3, 1), expand_gbs=round(moved / max(ns, 1), 1), twins=int(twins),
                 stage_us={k: round(sum(s_["ns_" + k] for s_ in st) / 1e3, 1)
                           for k in ("psi", "expand", "insert", "flags", "commit")})
 
@@ -203,13 +208,15 @@ def roofline(system, results):
     ns = 0
     launches = 0
     children = 0
+    twins = 0
     for r in results:
         for st in r["level_stats"]:
             ns += st["ns_expand"]
             launches += st["chunks"]
             children += st["expanded"]
+            twins += st["twins"]
     steps = len(results)
-    bytes_expand = children * (rb + LANE_CHILD_EXTRA)
+    bytes_expand = (children - twins) * (rb + LANE_CHILD_EXTRA) + twins * TWIN_CHILD_BYTES
     achieved = bytes_expand / max(1, ns)  # bytes per ns = GB/s
     return dict(
         kernel="k_expand_lane",

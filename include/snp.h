@@ -146,6 +146,9 @@ typedef struct {
     int64_t new_configs;     /* configurations recorded for the level */
     int64_t expanded;        /* children computed on the device (>= enumerated: the pass that
                                 fills the cap runs to its end) */
+    int64_t twins;           /* of those, children that fire the later of two twin rules (same
+                                neuron, same c and p): they repeat an earlier child, so only
+                                their parent and child index are written */
     int64_t chunks;          /* device passes used */
     int32_t truncated;       /* 1: the level reached frontier_cap */
     int32_t budget_hit;      /* 1: child_budget ran out with children left */

@@ -496,6 +496,7 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         const long long Beff = (long long)c.beff;
         if (Beff > 0) ++stt.chunks;
         stt.expanded += Beff;
+        stt.twins += (long long)c.twins;
         const long long new_total = (long long)c.total;
         const long long avail = limit - count;
         const long long committed = std::min(new_total, avail);

@@ -203,6 +203,7 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
     // place values wave 0 holds): consecutive tiles mostly share it
     long long have_p = -1;
     u64 place = 0;
+    uint32_t ntwin = 0;  // twin children of this block's tiles (thread 0)
 
     for (int tt = 0; tt < tiles_per_block; ++tt) {
     const long long b0 = (tile0 + tt) * kTile;
@@ -410,6 +411,7 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
         }
         __syncthreads();
         // 8. per-row outputs of the segment; a twin row holds -1 - parent
+        if (tid == 0) ntwin += (uint32_t)__popcll(L.misc[1] & seg_rows);
         if (tid >= c && tid < cend) {
             const bool tw = (L.misc[1] >> tid) & 1;
             if (!tw) a.hash[b0 + tid] = fmix64(L.rowh[tid]) & a.hash_mask;
@@ -431,6 +433,7 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
     if (p >= a.n) break;
     }
     if (__syncthreads_or(ovf) && tid == 0) atomicOr((unsigned long long*)&a.ctr->overflow, 1ULL);
+    if (tid == 0 && ntwin) atomicAdd((unsigned long long*)&a.ctr->twins, (u64)ntwin);
 }
 
 hipError_t launch_expand_int8(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st) {

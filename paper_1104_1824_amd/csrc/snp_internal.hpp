@@ -35,7 +35,7 @@ struct DevCounters {
     u64 count;         // scratch count (halting parents of a frontier prefix)
     u64 beff;          // children the chunk really covers: min(B, children of the prefix - g0)
     u64 psi_total;     // children of the frontier prefix after this pass's extension
-    u64 pad;
+    u64 twins;         // children of the chunk that fire a later twin rule
 };
 
 // Device-side description of a loaded system.

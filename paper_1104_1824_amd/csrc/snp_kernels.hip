@@ -535,12 +535,14 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
     for (int j = lane; j < m; j += 64) set_fired(tb, j, om, am, dg, cp);
 
     bool ovf = false;
+    uint32_t ntwin = 0;  // twin children of this wave's run
     for (int k = 0; k < cnt; ++k) {
         const long long b = b0 + k;
         wave_lds_sync();
         u64 h = 0;
         T* out = stage + b * (long long)m;
         const bool twin = wave_any_twin(m, lane, om, am, dg);
+        ntwin += twin ? 1u : 0u;
         if (twin) {  // a duplicate by construction: no row, no probe; cpar = -1 - parent
             if (lane == 0) {
                 a.cpar[b] = -1 - (int)p;
@@ -597,6 +599,7 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
         }
     }
     if (__any(ovf) && lane == 0) atomicOr((unsigned long long*)&a.ctr->overflow, 1ULL);
+    if (lane == 0 && ntwin) atomicAdd((unsigned long long*)&a.ctr->twins, (u64)ntwin);
 }
 
 // ---------------------------------------------------------------------------
@@ -728,6 +731,7 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
     const long long n = a.n;
     const uint32_t hi_ok = (uint32_t)s.count_max + kLaneOff;
     uint32_t vmin = kLaneOff, vmax = kLaneOff;  // range of the stored counts (offset)
+    uint32_t ntwin = 0;                         // twin children of this wave (uniform)
     for (long long rw = wave0; rw < nruns; rw += nwaves) {
         const long long b0 = rw * run;
         const int cnt = (int)min((long long)run, Beff - b0);
@@ -963,6 +967,7 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
                     else if (a.table) a.slot[bq] = 0;
                 }
                 const u64 twins = __ballot(twin && mine);
+                ntwin += (uint32_t)__popcll(twins);
                 Hc += readlane64(hin, 63);
                 vc += (uint32_t)__builtin_amdgcn_readlane((int)nin, 63);
                 // the rows, one child after the other: one table row per step,
@@ -1046,6 +1051,7 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
     }
     const bool ovf = vmin < kLaneOff || vmax > hi_ok;
     if (__any(ovf) && lane == 0) atomicOr((unsigned long long*)&a.ctr->overflow, 1ULL);
+    if (lane == 0 && ntwin) atomicAdd((unsigned long long*)&a.ctr->twins, (u64)ntwin);
 }
 
 hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st,

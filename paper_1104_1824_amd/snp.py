@@ -59,7 +59,8 @@ class snp_expand_stats(ctypes.Structure):
     _fields_ = [
         ("parents", ctypes.c_int64), ("halting_parents", ctypes.c_int64),
         ("children_total", ctypes.c_int64), ("enumerated", ctypes.c_int64),
-        ("new_configs", ctypes.c_int64), ("expanded", ctypes.c_int64), ("chunks", ctypes.c_int64),
+        ("new_configs", ctypes.c_int64), ("expanded", ctypes.c_int64), ("twins", ctypes.c_int64),
+        ("chunks", ctypes.c_int64),
         ("truncated", ctypes.c_int32), ("budget_hit", ctypes.c_int32),
         ("path_used", ctypes.c_int32), ("int8_fallback", ctypes.c_int32),
         ("ns_psi", ctypes.c_int64), ("ns_expand", ctypes.c_int64), ("ns_insert", ctypes.c_int64),

@@ -300,14 +300,48 @@ def twin_system():
     return synth.make_system(4, rules, syn, [3, 2, 1, 1], name="twins")
 
 
+def twin_children(oracle_mod, system, parent):
+    """Children of `parent` that fire the later of two applicable rules of one
+    neuron with equal (c, p), counted from the oracle's spiking vectors and a
+    regex test of applicability (the definition of E = a^i(a^j)*)."""
+    import re
+
+    def applies(k, n):
+        i, j, c = int(system.rule_i[k]), int(system.rule_j[k]), int(system.rule_c[k])
+        return n >= c and re.fullmatch(f"a{{{i}}}(?:a{{{j}}})*", "a" * n) is not None
+
+    _, _, psi = oracle_mod.children(system, parent, max_out=1)
+    if psi == 0:
+        return 0
+    _, S, _ = oracle_mod.children(system, parent, max_out=psi)
+    later = np.zeros(len(system.rule_i), dtype=bool)
+    for k in range(len(system.rule_i)):
+        n = int(system.rule_neuron[k])
+        if not applies(k, int(parent[n])):
+            continue
+        for q in range(k):
+            if (int(system.rule_neuron[q]) == n and applies(q, int(parent[n]))
+                    and system.rule_c[q] == system.rule_c[k] and system.rule_p[q] == system.rule_p[k]):
+                later[k] = True
+    return int(np.count_nonzero((S[:, later] != 0).any(axis=1)))
+
+
 @pytest.mark.parametrize("path", [snp.SNP_PATH_SPARSE, snp.SNP_PATH_INT8])
 def test_twin_rules(gpu, oracle_mod, path):
     s = twin_system()
     for kw in (dict(), dict(child_budget=3), dict(child_budget=7, frontier_cap=4), dict(frontier_cap=5),
                dict(frontier_cap=2, stop_at_cap=True)):
         note(f"twin rules, path {path}, {kw}")
-        assert_same_bfs(gpu_bfs(s, max_depth=12, out_capacity=4096, chunk=4096, path=path, **kw),
-                        oracle_mod.bfs(s, max_depth=12, **kw))
+        g = gpu_bfs(s, max_depth=12, out_capacity=4096, chunk=4096, path=path, **kw)
+        want = oracle_mod.bfs(s, max_depth=12, **kw)
+        assert_same_bfs(g, want)
+        if not kw:  # no level cut short: every child of every parent is computed
+            bounds = np.concatenate([[0], np.cumsum(want.level_sizes)])
+            for d, st in enumerate(g["level_stats"][: len(want.level_sizes)]):
+                if st["parents"] == 0:
+                    continue
+                rows = want.rows[bounds[d]: bounds[d + 1]]
+                assert st["twins"] == sum(twin_children(oracle_mod, s, r) for r in rows), d
 
 
 def hub_system(m=24, seed=5):
