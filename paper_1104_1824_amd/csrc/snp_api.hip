@@ -95,15 +95,16 @@ struct snp_system {
     u64* d_ct = nullptr;
     uint32_t *d_slot = nullptr, *d_flag = nullptr, *d_pos = nullptr, *d_fsums = nullptr, *d_fpre = nullptr;
     uint32_t* d_cand = nullptr;
-    // counters: a ring of slots, one per device pass, zeroed once per kRing passes,
-    // and one more slot (index kRing) for the checks made when a walk starts
+    // counters: a ring of slots, one per device pass, zeroed once per kRing
+    // passes; a walk's start writes the slot its first pass then uses
     static constexpr int kRing = 64;
     snp::DevCounters* d_ring = nullptr;
     snp::DevCounters* d_ctr = nullptr;  // slot of the current pass
     long long pass = 0;
     u64* d_T = nullptr;                 // children of the examined frontier prefix (device)
-    snp::DevCounters* h_ctr = nullptr;  // [2]: the pass read last, the walk start
+    snp::DevCounters* h_ctr = nullptr;  // the pass read last
     bool start_pending = false;         // the walk start's checks are not read yet
+    bool slot_ready = false;            // the current slot was set by the walk start: reuse it
 
     // caller-driven walk (snp_reset / snp_expand): the handle's own row store
     void* d_store = nullptr;
@@ -262,18 +263,13 @@ hipError_t wait_stream(hipStream_t st) {
 }
 
 // Copy the current pass's counters to the host and wait for the stream.  The
-// checks of a walk start still unread ride along and are reported first.
+// checks of a walk start still unread (in the same slot) are reported first.
 snp_status read_counters(snp_system* S) {
-    const bool start = S->start_pending;
-    if (start)
-        HIPCHK(hipMemcpyAsync(S->h_ctr + 1, S->d_ring + snp_system::kRing, sizeof(snp::DevCounters),
-                              hipMemcpyDeviceToHost, S->stream));
     HIPCHK(hipMemcpyAsync(S->h_ctr, S->d_ctr, sizeof(snp::DevCounters), hipMemcpyDeviceToHost, S->stream));
     HIPCHK(wait_stream(S->stream));
-    if (start) {
+    if (S->start_pending) {
         S->start_pending = false;
-        if (S->h_ctr[1].overflow) return fail(SNP_ERR_OVERFLOW, "C0 holds a count outside the count type's range");
-        if (S->h_ctr[1].probe_fail) return fail(SNP_ERR_DEVICE, "visited set: no free slot");
+        if (S->h_ctr->c0_bad) return fail(SNP_ERR_OVERFLOW, "C0 holds a count outside the count type's range");
     }
     return SNP_OK;
 }
@@ -281,6 +277,10 @@ snp_status read_counters(snp_system* S) {
 // Start a device pass: move to the next counter slot (zeroing the ring when it
 // wraps, i.e. one fill per kRing passes instead of one per pass).
 snp_status clear_counters(snp_system* S) {
+    if (S->slot_ready) {  // set up by the walk start, which counted nothing else
+        S->slot_ready = false;
+        return SNP_OK;
+    }
     const int slot = (int)(S->pass % snp_system::kRing);
     if (slot == 0)
         HIPCHK(hipMemsetAsync(S->d_ring, 0, sizeof(snp::DevCounters) * snp_system::kRing, S->stream));
@@ -310,9 +310,9 @@ snp_status rebuild_table(snp_system* S, const void* arena, long long rows) {
 }
 
 // Record C0 as the only visited configuration, stored at arena row 0 (parent
-// and child index -1 in par0 / chi0 when given).  Its
-// range check counts in the walk-start slot; with `wait` false the result is
-// read (and a bad C0 reported) by the next read_counters, so the first level
+// and child index -1 in par0 / chi0 when given).  Its range check goes to the
+// counter slot that the first pass then uses; with `wait` false the result is
+// read (and a bad C0 reported) by that pass's counter read, so the first level
 // costs no synchronisation of its own.  The kernels never index memory by a
 // count, so a level expanded from a bad C0 stays in bounds before the error.
 snp_status start_walk(snp_system* S, const void* c0_dev, void* arena, bool wait, long long* par0 = nullptr,
@@ -321,9 +321,13 @@ snp_status start_walk(snp_system* S, const void* c0_dev, void* arena, bool wait,
     const char *c = (const char*)c0_dev, *a = (const char*)arena;
     if (c != a && c < a + row_bytes(S) && a < c + row_bytes(S))
         return fail(SNP_ERR_INVALID, "c0 overlaps row 0 of the row store without being it");
+    S->slot_ready = false;
+    snp_status st;
+    if ((st = clear_counters(S))) return st;  // the slot the first pass will use
     HIPCHK(snp::launch_start_walk(S->elem_bytes, S->m, S->d_R, S->d_table, S->slots - 1, c0_dev, arena, S->count_max,
-                                  S->opt.hash_mask ? S->opt.hash_mask : ~0ULL, S->d_row_slot,
-                                  S->d_ring + snp_system::kRing, par0, chi0, S->stream));
+                                  S->opt.hash_mask ? S->opt.hash_mask : ~0ULL, S->d_row_slot, S->d_ctr, par0,
+                                  chi0, S->stream));
+    S->slot_ready = true;
     S->tombs = 0;
     S->start_pending = true;
     return wait ? read_counters(S) : SNP_OK;
@@ -707,10 +711,10 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     LOADCHK(dmalloc(&S->d_pos, sizeof(uint32_t) * C));
     LOADCHK(dmalloc(&S->d_fsums, sizeof(uint32_t) * ft));
     LOADCHK(dmalloc(&S->d_fpre, sizeof(uint32_t) * ft));
-    LOADCHK(dmalloc(&S->d_ring, sizeof(snp::DevCounters) * (snp_system::kRing + 1)));
+    LOADCHK(dmalloc(&S->d_ring, sizeof(snp::DevCounters) * snp_system::kRing));
     LOADCHK(dmalloc(&S->d_T, sizeof(u64)));
     S->d_ctr = S->d_ring;
-    LOADCHK(hipHostMalloc((void**)&S->h_ctr, 2 * sizeof(snp::DevCounters), hipHostMallocDefault));
+    LOADCHK(hipHostMalloc((void**)&S->h_ctr, sizeof(snp::DevCounters), hipHostMallocDefault));
     if (opt.profile)
         // timing only: no system-scope fence when an event is reached
         for (hipEvent_t& e : S->ev) LOADCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));

@@ -36,6 +36,7 @@ struct DevCounters {
     u64 beff;          // children the chunk really covers: min(B, children of the prefix - g0)
     u64 psi_total;     // children of the frontier prefix after this pass's extension
     u64 twins;         // children of the chunk that fire a later twin rule
+    u64 c0_bad;        // walk start: C0 holds a count outside the count type's range
 };
 
 // Device-side description of a loaded system.

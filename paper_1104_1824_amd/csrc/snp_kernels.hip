@@ -1481,7 +1481,7 @@ __global__ __launch_bounds__(256) void k_start_walk(int m, const u64* __restrict
         if (par0) *par0 = -1;
         if (chi0) *chi0 = -1;
         DevCounters z{};
-        z.overflow = nbad ? 1 : 0;
+        z.c0_bad = nbad ? 1 : 0;
         *sc = z;
     }
 }
