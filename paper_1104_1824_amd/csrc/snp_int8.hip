@@ -439,9 +439,9 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
 hipError_t launch_expand_int8(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st) {
     if (a.B <= 0) return hipSuccess;
     // consecutive tiles per block (they mostly share a parent), keeping about
-    // two rounds of resident blocks
+    // four rounds of resident blocks for balance
     const long long tiles = (a.B + kTile - 1) / kTile;
-    const int tpb = (int)std::max<long long>(1, std::min<long long>(16, tiles / 2048));
+    const int tpb = (int)std::max<long long>(1, std::min<long long>(16, tiles / 4096));
     const unsigned blocks = (unsigned)((tiles + tpb - 1) / tpb);
     const bool wide = int8_lds_bytes(s.m, 128) <= 64 * 1024;
     const size_t lds = int8_lds_bytes(s.m, wide ? 128 : 64);
