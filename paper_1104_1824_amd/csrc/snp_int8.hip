@@ -204,6 +204,10 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
     long long have_p = -1;
     u64 place = 0;
     uint32_t ntwin = 0;  // twin children of this block's tiles (thread 0)
+    // children [.., twin_end) of parent twin_p are all twins: a digit of a
+    // neuron above the ones that change there picks a later twin rule
+    long long twin_p = -1;
+    u64 twin_end = 0;
 
     for (int tt = 0; tt < tiles_per_block; ++tt) {
     const long long b0 = (tile0 + tt) * kTile;
@@ -217,6 +221,24 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
         const int cend = c + len;
         const u64 tb = ta + (u64)(len - 1);
         const T* P = F + p * (long long)m;
+
+        if (p == twin_p && tb < twin_end) {
+            // inside a known run of twins: only their parent and child index
+            if (tid >= c && tid < cend) {
+                a.cpar[b0 + tid] = -1 - (int)p;
+                a.ct[b0 + tid] = ta + (u64)(tid - c);
+            }
+            if (tid == 0) ntwin += (uint32_t)len;
+            c = cend;
+            ta += (u64)len;
+            if (ta >= psi_p) {
+                ++p;
+                while (p < a.n && a.psi[p] == 0) ++p;
+                ta = 0;
+            }
+            if (c < rows && p >= a.n) break;  // unreachable while g0 + B <= sum of Psi
+            continue;
+        }
 
         // 1. applicability of the parent (kept while the parent stays)
         const bool fresh = p != have_p;
@@ -236,7 +258,10 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
             }
             have_p = p;
         }
-        if (tid == 0) L.sc[0] = m;
+        if (tid == 0) {
+            L.sc[0] = m;
+            L.sc[3] = m;
+        }
         __syncthreads();
         // 2. digits of the first and last child of the segment
         if (wid == 0) {
@@ -255,7 +280,13 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
         // 4. V (neurons with omega >= 2 from jstar on) and its rule columns;
         //    do the fixed digits (before jstar) pick a later twin?
         bool fixed_nc = false;
-        for (int j = tid; j < jstar; j += blockDim.x) fixed_nc |= later_twin(L, j, L.dg[j]);
+        int first_nc = m;  // most significant fixed digit that picks a later twin
+        for (int j = tid; j < jstar; j += blockDim.x)
+            if (later_twin(L, j, L.dg[j])) {
+                fixed_nc = true;
+                first_nc = min(first_nc, j);
+            }
+        if (first_nc < m) atomicMin(&L.sc[3], first_nc);
         if (wid == 0) {
             int nv = 0;
             for (int base = jstar; base < m; base += 64) {
@@ -298,8 +329,24 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
 
         T* refrow = stage + (b0 + c) * (long long)m;
         if (seg_twin) {
-            // every child of the segment repeats an earlier one
+            // every child of the segment repeats an earlier one, and so does
+            // every child up to the next change of digit J = sc[3]: the run
+            // ends at (ta / place_J + 1) * place_J, place_J being the product
+            // of omega over the neurons after J (saturated)
             if (tid == 0) L.misc[1] |= seg_rows;
+            if (wid == 0) {
+                const int J = L.sc[3];
+                const int Q = (m + 63) >> 6;
+                const int owner = J / Q;
+                u64 pj = place;  // this lane's block place value, times its neurons after J
+                for (int j = J + 1; j < min(m, owner * Q + Q); ++j) pj = sat_mul(pj, (u64)max(1, (int)L.om[j]));
+                pj = __shfl(pj, owner);
+                const u64 end = pj >= kPsiSat ? kPsiSat : (ta / pj + 1) * pj;
+                if (lane == 0) L.wsum[3] = min(end, psi_p);
+            }
+            __syncthreads();
+            twin_p = p;
+            twin_end = L.wsum[3];
         } else if (!mfma) {
             // sparse pull for every child of the segment that is not a twin
             for (int rr = c; rr < cend; ++rr) {
@@ -438,14 +485,16 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
 
 hipError_t launch_expand_int8(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st) {
     if (a.B <= 0) return hipSuccess;
-    // consecutive tiles per block (they mostly share a parent), keeping about
-    // four rounds of resident blocks for balance
-    const long long tiles = (a.B + kTile - 1) / kTile;
-    const int tpb = (int)std::max<long long>(1, std::min<long long>(16, tiles / 4096));
-    const unsigned blocks = (unsigned)((tiles + tpb - 1) / tpb);
     const bool wide = int8_lds_bytes(s.m, 128) <= 64 * 1024;
     const size_t lds = int8_lds_bytes(s.m, wide ? 128 : 64);
     if (lds > 64 * 1024) return hipErrorInvalidValue;
+    // consecutive tiles per block (they mostly share a parent, and runs of
+    // twins carry over), keeping about four rounds of resident blocks (LDS
+    // bounds them: 160 KiB per CU, 256 CUs) for balance
+    const long long tiles = (a.B + kTile - 1) / kTile;
+    const long long resident = 256LL * std::max<long long>(1, (160 * 1024) / (long long)lds);
+    const int tpb = (int)std::max<long long>(1, std::min<long long>(16, tiles / (4 * resident)));
+    const unsigned blocks = (unsigned)((tiles + tpb - 1) / tpb);
 #define SNP_I8(TT, NN) hipLaunchKernelGGL((k_expand_int8<TT, NN>), dim3(blocks), dim3(256), lds, st, s, a, tpb)
     if (elem_bytes == 4) {
         if (wide) SNP_I8(int32_t, 128);
