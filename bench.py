@@ -132,7 +132,8 @@ def extra_large():
     from paper_1104_1824_amd import snp
 
     log("large m=4096 uint16 workload, automatic path, depth 3, cap 4e6")
-    r = walk_timing(synth.config_system(5, 0), snp.SNP_PATH_AUTO, 4000000, 3, False, 1 << 19, 12000001, 1)
+    # chunks of 2^22 children (34 GB of staged rows): few passes over the long runs of twins
+    r = walk_timing(synth.config_system(5, 0), snp.SNP_PATH_AUTO, 4000000, 3, False, 1 << 22, 12000001, 1)
     r["workload"] = ("large: m=4096, 4 rules/neuron (r=16384), out-degree 16, C0 in [0,8], uint16; BFS depth 3, "
                      "frontier_cap 4e6 per level (seed 0)")
     return r
