@@ -1350,13 +1350,26 @@ __global__ __launch_bounds__(256) void k_commit(int upr /* units per row */, Com
     const U* src = (const U*)a.stage + b0 * upr;
     U* dst = (U*)a.arena + (a.level_base + first_local) * upr;
     U* dst2 = a.row2 ? (U*)a.row2 + first_local * upr : nullptr;
-    const int total = ncopy * upr;
-    for (int v = threadIdx.x; v < total; v += 256) {
-        const int i = v / upr;
-        const int o = v - i * upr;
-        const U x = src[(long long)srcb[i] * upr + o];
-        dst[v] = x;
-        if (dst2) dst2[v] = x;
+    if (upr <= 256) {
+        // thread t copies unit o of rows i0, i0 + per, ...: row and unit are
+        // fixed per thread, so the loop has no division
+        const int per = 256 / upr;
+        const int i0 = threadIdx.x / upr, o = threadIdx.x - i0 * upr;
+        if (i0 < per)
+            for (int i = i0; i < ncopy; i += per) {
+                const U x = src[(long long)srcb[i] * upr + o];
+                dst[(long long)i * upr + o] = x;
+                if (dst2) dst2[(long long)i * upr + o] = x;
+            }
+    } else {
+        for (int i = 0; i < ncopy; ++i) {
+            const long long s0 = (long long)srcb[i] * upr, d0 = (long long)i * upr;
+            for (int o = threadIdx.x; o < upr; o += 256) {
+                const U x = src[s0 + o];
+                dst[d0 + o] = x;
+                if (dst2) dst2[d0 + o] = x;
+            }
+        }
     }
 }
 
