@@ -143,6 +143,21 @@ def _ptr(t) -> Optional[int]:
     return t.data_ptr()
 
 
+class _RunBuffers:
+    """Host outputs of snp_run with their addresses taken once."""
+
+    def __init__(self, max_levels: int):
+        self.max_levels = max_levels
+        self.sizes = np.zeros(max_levels, dtype=np.int64)
+        self.stats = (snp_expand_stats * max_levels)()
+        self.n_configs, self.n_levels, self.stop = ctypes.c_int64(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        self.p_sizes = self.sizes.ctypes.data
+        self.p_stats = ctypes.addressof(self.stats)
+        self.r_configs = ctypes.byref(self.n_configs)
+        self.r_levels = ctypes.byref(self.n_levels)
+        self.r_stop = ctypes.byref(self.stop)
+
+
 class Handle:
     """An loaded system (snp_system*); freed by close() or garbage collection."""
 
@@ -151,12 +166,12 @@ class Handle:
         self._keep = keep
         self.m = m
         self.count_type = count_type
-        self._run_bufs = None  # (max_levels, sizes, stats) reused by snp_run
+        self._run = None  # output buffers of snp_run, reused while max_levels stays
 
-    def run_buffers(self, max_levels: int):
-        if self._run_bufs is None or self._run_bufs[0] != max_levels:
-            self._run_bufs = (max_levels, np.zeros(max_levels, dtype=np.int64), (snp_expand_stats * max_levels)())
-        return self._run_bufs[1], self._run_bufs[2]
+    def run_buffers(self, max_levels: int) -> "_RunBuffers":
+        if self._run is None or self._run.max_levels != max_levels:
+            self._run = _RunBuffers(max_levels)
+        return self._run
 
     def close(self):
         if self.ptr:
@@ -238,26 +253,20 @@ def snp_expand(h: Handle, frontier_dev, n: int, next_dev, next_capacity: int, pa
 def snp_run(h: Handle, c0_dev, max_depth: int, out_dev, out_capacity: int, max_levels: int = 4096,
             parent_of=None, child_of=None, with_stats: bool = True) -> dict:
     """Returns dict(n_configs, level_sizes, stop_reason, level_stats)."""
-    n_configs = ctypes.c_int64(0)
-    n_levels = ctypes.c_int32(0)
-    stop = ctypes.c_int32(0)
-    sizes, stats = h.run_buffers(max_levels)
-    if not with_stats:
-        stats = None
-    status = lib().snp_run(h.ptr, _ptr(c0_dev), int(max_depth), _ptr(out_dev), int(out_capacity),
-                           ctypes.byref(n_configs), sizes.ctypes.data, int(max_levels), ctypes.byref(n_levels),
-                           ctypes.byref(stop), ctypes.cast(stats, ctypes.c_void_p) if stats is not None else None,
+    rb = h.run_buffers(max_levels)
+    status = lib().snp_run(h.ptr, _ptr(c0_dev), int(max_depth), _ptr(out_dev), int(out_capacity), rb.r_configs,
+                           rb.p_sizes, int(max_levels), rb.r_levels, rb.r_stop, rb.p_stats if with_stats else None,
                            _ptr(parent_of), _ptr(child_of))
     if status != SNP_OK:
         err = SnpError(status, "snp_run", lib().snp_last_error().decode())
-        err.n_configs = int(n_configs.value)
+        err.n_configs = int(rb.n_configs.value)
         raise err
-    L = int(n_levels.value)
+    L = int(rb.n_levels.value)
     return dict(
-        n_configs=int(n_configs.value),
-        level_sizes=sizes[:L].copy(),
-        stop_reason=int(stop.value),
-        level_stats=_stats_list(stats, L) if stats is not None else None,
+        n_configs=int(rb.n_configs.value),
+        level_sizes=rb.sizes[:L].copy(),
+        stop_reason=int(rb.stop.value),
+        level_stats=_stats_list(rb.stats, L) if with_stats else None,
     )
 
 
