@@ -316,7 +316,7 @@ snp_status rebuild_table(snp_system* S, const void* arena, long long rows) {
 // costs no synchronisation of its own.  The kernels never index memory by a
 // count, so a level expanded from a bad C0 stays in bounds before the error.
 snp_status start_walk(snp_system* S, const void* c0_dev, void* arena, bool wait, long long* par0 = nullptr,
-                      long long* chi0 = nullptr) {
+                      long long* chi0 = nullptr, bool psi_c0 = false) {
     if (!c0_dev) return fail(SNP_ERR_INVALID, "c0 is NULL");
     const char *c = (const char*)c0_dev, *a = (const char*)arena;
     if (c != a && c < a + row_bytes(S) && a < c + row_bytes(S))
@@ -326,7 +326,8 @@ snp_status start_walk(snp_system* S, const void* c0_dev, void* arena, bool wait,
     if ((st = clear_counters(S))) return st;  // the slot the first pass will use
     HIPCHK(snp::launch_start_walk(S->elem_bytes, S->m, S->d_R, S->d_table, S->slots - 1, c0_dev, arena, S->count_max,
                                   S->opt.hash_mask ? S->opt.hash_mask : ~0ULL, S->d_row_slot, S->d_ctr, par0,
-                                  chi0, S->stream));
+                                  chi0, S->dsys, S->opt.expand_max_count, psi_c0 ? S->d_psi : nullptr, S->d_hflag,
+                                  S->d_off, S->d_T, S->stream));
     S->slot_ready = true;
     S->tombs = 0;
     S->start_pending = true;
@@ -350,6 +351,7 @@ struct LevelIO {
     long long par_out_base;
     long long par_value_base;
     long long* t_out;
+    bool c0_psi = false;    // the frontier is C0, whose Psi the walk start computed
 };
 
 snp_status rollback_level(snp_system* S, long long first, long long count) {
@@ -422,6 +424,10 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
     u64 enumerated = 0;
     bool cap_hit = false, budget_hit = false;
     long long p_end = -1;  // parents up to the last child within the budget (for the halting count)
+    // C0's Psi, halting flag and offset come from the walk start, into the
+    // counters of this level's first pass: that pass extends by nothing
+    bool start_ext = io.c0_psi && S->slot_ready;
+    if (start_ext) P = 1;
     long long halting_cap = -1;  // halting parents up to the cap's child's parent, counted in its pass
     for (;;) {
         if (G >= budget) {  // the budget is spent: is anything left?
@@ -442,19 +448,24 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
             if (w < (double)want) want = (u64)std::max<double>(w, 4096.0);
         }
         want = std::min(want, budget - G);
-        const bool ext = P < io.n && T - G < want;
+        const bool ext = start_ext || (P < io.n && T - G < want);
         if (!ext && T <= G) break;  // every child of the frontier was enumerated
         const long long B = (long long)(ext ? want : std::min<u64>(want, T - G));  // upper bound when extending
         // keep the table at most half full (tombstones included)
         const long long live = io.level_base + count;
         if ((u64)(live + S->tombs + B) * 2 > S->slots) {
+            if (start_ext) {  // the rebuild takes the start's counters: compute C0's Psi in the pass
+                start_ext = false;
+                P = 0;
+            }
             if ((st = rebuild_table(S, io.arena, live))) return st;
             if ((u64)(live + B) * 2 > S->slots)
                 return fail(SNP_ERR_CAPACITY, "visited set too small for %lld rows", live + B);
         }
         if ((st = clear_counters(S))) return st;
         if ((st = mark(S, 0))) return st;
-        if (ext && (st = launch_extension(want))) return st;
+        if (ext && !start_ext && (st = launch_extension(want))) return st;
+        start_ext = false;
         if ((st = mark(S, 1))) return st;
         snp::ChunkArgs ca{io.frontier, P, S->d_psi, S->d_off, G, B, S->d_stage, S->d_hash, S->d_cpar, S->d_ct,
                           hmask, S->d_ctr, S->d_T, S->opt.int8_max_k > 0 ? S->opt.int8_max_k : 128,
@@ -775,7 +786,7 @@ snp_status snp_run(snp_system* S, const void* c0_dev, int32_t max_depth, void* o
     *stop_reason = SNP_STOP_DEPTH;
     S->walk_active = false;
     const long long rb = row_bytes(S);
-    snp_status st = start_walk(S, c0_dev, out_dev, false, (long long*)parent_of, (long long*)child_of);
+    snp_status st = start_walk(S, c0_dev, out_dev, false, (long long*)parent_of, (long long*)child_of, true);
     if (st) return st;
     // level_stats entries [0, *n_levels): each expansion writes its own, the
     // rest (levels that were not expanded) are zeroed on the way out
@@ -804,7 +815,7 @@ snp_status snp_run(snp_system* S, const void* c0_dev, int32_t max_depth, void* o
         }
         LevelIO io{(const char*)out_dev + lv_begin * rb, lv_end - lv_begin, out_dev, rows, arena_cap,
                    S->opt.frontier_cap > 0 ? S->opt.frontier_cap : kInf, kInf, nullptr, (long long*)parent_of,
-                   rows, lv_begin, (long long*)child_of};
+                   rows, lv_begin, (long long*)child_of, depth == 0};
         snp_expand_stats es{};
         long long count = 0;
         st = expand_level(S, io, &es, &count);

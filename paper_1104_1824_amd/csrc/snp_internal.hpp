@@ -191,7 +191,8 @@ hipError_t launch_commit(int elem_bytes, int m, const CommitArgs& a, hipStream_t
 hipError_t launch_fill_u64(u64* p, long long n, u64 v, hipStream_t st);
 hipError_t launch_start_walk(int elem_bytes, int m, const u64* R, u64* table, u64 slot_mask, const void* c0,
                              void* arena, long long count_max, u64 hash_mask, uint32_t* row_slot, DevCounters* sc,
-                             long long* par0, long long* chi0, hipStream_t st);
+                             long long* par0, long long* chi0, const DevSystem& s, long long expand_max, u64* psi0,
+                             uint8_t* hflag0, u64* off0, u64* Tdev, hipStream_t st);
 hipError_t launch_rows_insert(int elem_bytes, int m, const u64* R, u64* table, u64 slot_mask, const void* arena,
                               long long first, long long count, u64 hash_mask, uint32_t* row_slot,
                               DevCounters* ctr, hipStream_t st);

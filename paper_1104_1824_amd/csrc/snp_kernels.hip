@@ -1455,7 +1455,7 @@ hipError_t launch_rows_insert(int elem_bytes, int m, const u64* R, u64* table, u
 }
 
 // The start of a walk in one launch: the visited set holds C0 alone (row 0
-// of the row store) and the walk-start counters are set.  Every block hashes
+// of the row store) and the counters of the walk's first pass are set.  Every block hashes
 // C0 (one wave) and fills its share of the table with empty entries, except
 // C0's home slot, which takes C0's entry; block 0 also copies C0 to row 0
 // (when the row store is elsewhere), records its slot, checks its range and
@@ -1465,7 +1465,9 @@ __global__ __launch_bounds__(256) void k_start_walk(int m, const u64* __restrict
                                                     u64 slot_mask, const T* __restrict__ c0, T* __restrict__ arena,
                                                     long long count_max, u64 hash_mask,
                                                     uint32_t* __restrict__ row_slot, DevCounters* __restrict__ sc,
-                                                    long long* par0, long long* chi0) {
+                                                    long long* par0, long long* chi0, const int* nrp,
+                                                    const int4* rules, long long expand_max, u64* psi0,
+                                                    uint8_t* hflag0, u64* off0, u64* Tdev) {
     __shared__ u64 s_slot, s_entry;
     const int lane = threadIdx.x & 63;
     if (threadIdx.x < 64) {
@@ -1489,26 +1491,42 @@ __global__ __launch_bounds__(256) void k_start_walk(int m, const u64* __restrict
         bad |= v < 0 || v > count_max;
     }
     const int nbad = __syncthreads_count(bad);
+    // Psi of C0 (the first level's only parent), its halting flag and offset,
+    // when asked: the first pass then needs no Psi launch of its own
+    u64 psi_c0 = 0;
+    bool halt_c0 = false;
+    if (psi0 && threadIdx.x < 64) psi_c0 = parent_psi<T>(c0, m, nrp, rules, expand_max, lane, halt_c0);
     if (threadIdx.x == 0) {
         row_slot[0] = (uint32_t)home;
         if (par0) *par0 = -1;
         if (chi0) *chi0 = -1;
         DevCounters z{};
         z.c0_bad = nbad ? 1 : 0;
+        if (psi0) {
+            psi0[0] = psi_c0;
+            hflag0[0] = halt_c0 ? 1 : 0;
+            off0[0] = 0;
+            *Tdev = psi_c0;
+            z.psi_total = psi_c0;
+            z.halting = halt_c0 ? 1 : 0;
+        }
         *sc = z;
     }
 }
 
 hipError_t launch_start_walk(int elem_bytes, int m, const u64* R, u64* table, u64 slot_mask, const void* c0,
                              void* arena, long long count_max, u64 hash_mask, uint32_t* row_slot, DevCounters* sc,
-                             long long* par0, long long* chi0, hipStream_t st) {
+                             long long* par0, long long* chi0, const DevSystem& s, long long expand_max, u64* psi0,
+                             uint8_t* hflag0, u64* off0, u64* Tdev, hipStream_t st) {
     const unsigned blocks = (unsigned)std::min<u64>((slot_mask + 256) / 256, 4096);
     if (elem_bytes == 4)
         hipLaunchKernelGGL(k_start_walk<int32_t>, dim3(blocks), dim3(256), 0, st, m, R, table, slot_mask,
-                           (const int32_t*)c0, (int32_t*)arena, count_max, hash_mask, row_slot, sc, par0, chi0);
+                           (const int32_t*)c0, (int32_t*)arena, count_max, hash_mask, row_slot, sc, par0, chi0,
+                           s.nrule_ptr, s.rules, expand_max, psi0, hflag0, off0, Tdev);
     else
         hipLaunchKernelGGL(k_start_walk<uint16_t>, dim3(blocks), dim3(256), 0, st, m, R, table, slot_mask,
-                           (const uint16_t*)c0, (uint16_t*)arena, count_max, hash_mask, row_slot, sc, par0, chi0);
+                           (const uint16_t*)c0, (uint16_t*)arena, count_max, hash_mask, row_slot, sc, par0, chi0,
+                           s.nrule_ptr, s.rules, expand_max, psi0, hflag0, off0, Tdev);
     return hipGetLastError();
 }
 

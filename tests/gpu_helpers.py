@@ -1,6 +1,7 @@
 """Helpers of the GPU tests: run the HIP library through its C ABI on torch
 buffers and compare with the oracle on the same seeded inputs."""
 import sys
+import time
 
 import numpy as np
 
@@ -10,7 +11,7 @@ from paper_1104_1824_amd import snp
 
 def note(msg):
     """Name the case on stdout before each GPU step (a fault then names it)."""
-    print(f"[gpu] {msg}", flush=True)
+    print(f"[gpu] {time.strftime('%H:%M:%S')} {msg}", flush=True)
     sys.stdout.flush()
 
 
