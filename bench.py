@@ -285,7 +285,7 @@ def main():
         print(json.dumps({args.only: EXTRAS[args.only]()}), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X; --gpus must be 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs on a single MI355X, so --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     import torch
 
