@@ -1,21 +1,27 @@
 """Benchmark: new configurations per second of the breadth-first expansion.
 
-One step is one complete breadth-first walk of the plain-sparse workload
-(seeded synthetic system, m = 64 neurons, 2 rules per neuron, out-degree 4,
-C0 uniform in [0, 4], int32 counts) from C0 until a level reaches 100,000
-configurations: every level runs applicability + Psi, the prefix sum, the
-expansion C' = C + S.M, the visited-set insert and the ordered commit, all on
-the GPU through the C ABI.  The value is new (deduplicated) configurations
-per second over the timed steps; inputs are resident in HBM before timing.
+One step is one complete breadth-first walk of the dense int8 workload (seeded
+synthetic system, m = 512 neurons, 3 rules per neuron, E = a^i (a^j)* with
+i in [1,4], j in [0,3], p in [0,4] so that M_Pi's entries lie in [-4, 4],
+out-degree 64, C0 uniform in [0, 4], int32 counts, seed 0) from C0 to depth 3
+with every level truncated to its first 1e6 new configurations: every level
+runs applicability + Psi, the prefix sums, the expansion C' = C + S.M on the
+int8 matrix cores, the visited-set insert and the ordered commit, all on the
+GPU through the C ABI.  The value is new (deduplicated) configurations per
+second over the timed steps; inputs are resident in HBM before timing.
 
 The JSON line also carries the roofline of the dominant kernel (device time
-from HIP events recorded by the library on its stream just before and after
-each of its launches inside the timed region) and the CPU oracle timed on a
-bounded sample of the same workload.
+from HIP events the library records on its stream just before and after each
+launch of it, inside the timed region), its int8 matrix-core utilisation, the
+same walk on the plain sparse form (the speedup the metric names), the CPU
+oracle timed on a bounded sample of the same workload, and secondary lines
+for the plain-sparse, batched and large workloads, each with its own roofline
+and CPU baseline.
 """
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -24,123 +30,239 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "new configurations/sec (deduped) per BFS step; int8-MFMA/batched vs plain sparse"
-HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
+INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 matrix cores, published (no sparsity)
+# Vector ALU: 256 CUs x 128 lanes x 2.4 GHz = 78.6e12 32-bit integer operations per
+# second (one op per lane per clock; the published fp32 157.3 TFLOP/s counts an FMA as 2)
+VALU_PEAK_GOPS = 256 * 128 * 2.4
+CU_PEAK_GOPS = 128 * 2.4
+ENTRY_BYTES = 16             # visited-set entry written per new configuration
 # bytes per child of the one-neuron-per-lane expansion besides its row: key 8,
 # parent 4, child index 8, probe slot 4, visited-set entry 8
 LANE_CHILD_EXTRA = 32
-TWIN_CHILD_BYTES = 12  # a twin child: parent 4 and child index 8 only
+TWIN_CHILD_BYTES = 12        # a twin child: parent 4 and child index 8 only
+
+DENSE_WORKLOAD = ("dense_int8: seeded SN P system m=512, 3 rules/neuron (r=1536), E=a^i(a^j)* i in [1,4] "
+                  "j in [0,3], p in [0,4] (M entries in [-4,4], int8), out-degree 64, C0 in [0,4], int32 "
+                  "counts; BFS depth 3, frontier_cap 1e6 per level, chunks of 2^20 children (seed 0)")
+PLAIN_WORKLOAD = ("plain_sparse: m=64, 2 rules/neuron (r=128), i in [1,4] j in [0,3] p in {0,1}, out-degree 4, "
+                  "C0 in [0,4], int32; BFS until a level reaches 1e5 configurations (seed 0)")
+LARGE_WORKLOAD = ("large: m=4096, 4 rules/neuron (r=16384), out-degree 16, C0 in [0,8], uint16; BFS depth 3, "
+                  "frontier_cap 4e6 per level, chunks of 2^22 children (seed 0)")
+BATCH_WORKLOAD = ("batched_uneven: 256 systems, m in [16,1024], 1-3 rules and out-degree 2-32 per neuron, "
+                  "10k deterministic steps each, one graph-replayed launch (seeds 0-255)")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def plain_sparse_workload(seed=0):
-    import synth
-
-    return synth.config_system(2, seed), dict(frontier_cap=100000, stop_at_cap=True, max_depth=1000)
-
-
-def run_gpu(system, run_opts, steps, warmup):
-    import torch
-
-    from paper_1104_1824_amd import snp
-
-    cap = 200000
-    h = snp.snp_load(system, path=snp.SNP_PATH_SPARSE, frontier_cap=run_opts["frontier_cap"],
-                     stop_at_cap=run_opts["stop_at_cap"], max_rows=cap, chunk=1 << 17, profile=1)
-    c0 = torch.tensor(system.c0, dtype=torch.int32, device="cuda")
-    out = torch.empty((cap, system.m), dtype=torch.int32, device="cuda")
-    res = None
-    for _ in range(warmup):
-        res = snp.snp_run(h, c0, run_opts["max_depth"], out, cap)
-    torch.cuda.synchronize()
-    results = []
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        results.append(snp.snp_run(h, c0, run_opts["max_depth"], out, cap))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    h.close()
-    return results, t1 - t0, res
+def host_info():
+    model = platform.processor() or ""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(nproc=os.cpu_count(), cpu_model=model)
 
 
-def walk_timing(system, path, cap, depth, stop, chunk, out_cap, reps):
-    """Mean time of `reps` complete walks on one path (after one untimed walk)."""
+def device_rows(system, rows):
     import numpy as np
     import torch
 
+    a = np.asarray(rows, dtype=np.int64)
+    a = a.astype(np.uint16).view(np.int16) if system.count_type == "u16" else a.astype(np.int32)
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+class Walk:
+    """A loaded handle plus its device buffers, for timed snp_run calls."""
+
+    def __init__(self, system, path, cap, depth, stop, chunk, out_cap, profile):
+        import torch
+
+        from paper_1104_1824_amd import snp
+
+        self.snp, self.system, self.depth, self.out_cap = snp, system, depth, out_cap
+        self.h = snp.snp_load(system, path=path, frontier_cap=cap, stop_at_cap=stop, max_rows=out_cap, chunk=chunk,
+                              profile=profile)
+        self.c0 = device_rows(system, system.c0)
+        dt = torch.int16 if system.count_type == "u16" else torch.int32
+        self.out = torch.empty((out_cap, system.m), dtype=dt, device="cuda")
+
+    def run(self):
+        return self.snp.snp_run(self.h, self.c0, self.depth, self.out, self.out_cap)
+
+    def timed(self, steps, warmup):
+        import torch
+
+        for _ in range(warmup):
+            self.run()
+        torch.cuda.synchronize()
+        results = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            results.append(self.run())
+        torch.cuda.synchronize()
+        return results, time.perf_counter() - t0
+
+    def close(self):
+        self.h.close()
+        del self.out
+
+
+def totals(results, key):
+    return sum(st[key] for r in results for st in r["level_stats"])
+
+
+def hbm_roofline(results, kernel, bytes_per_new, rb, twins_written=False):
+    """Roofline of the expansion kernel: algorithmic bytes over its device time
+    (HIP events around each launch).  Algorithmic bytes = every new configuration's
+    row plus its visited-set entry (bytes_per_new); with twins_written, the
+    one-neuron-per-lane form's own per-child bytes instead (rows of every child
+    computed, plus records)."""
+    ns = totals(results, "ns_expand")
+    launches = totals(results, "chunks")
+    if twins_written:
+        children, twins = totals(results, "expanded"), totals(results, "twins")
+        moved = (children - twins) * (rb + LANE_CHILD_EXTRA) + twins * TWIN_CHILD_BYTES
+    else:
+        moved = totals(results, "new_configs") * bytes_per_new
+    achieved = moved / max(1, ns)  # bytes per ns = GB/s
+    steps = max(1, len(results))
+    return dict(
+        roofline=dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None),
+        dominant_kernel=dict(kernel=kernel, launches_per_step=launches // steps,
+                             bytes_per_launch=round(moved / max(1, launches)),
+                             avg_launch_us=round(ns / max(1, launches) / 1e3, 3),
+                             kernel_us_per_step=round(ns / 1e3 / steps, 2)),
+    )
+
+
+def mfma_util(results):
+    ops = totals(results, "mfma_ops")
+    ns = totals(results, "ns_expand")
+    tops = ops / max(1, ns) / 1e3  # ops per ns = Gop/s; / 1e3 = Top/s
+    return dict(ops_per_step=ops // max(1, len(results)), achieved_tops=round(tops, 3), peak_tops=INT8_PEAK_TOPS,
+                frac=round(tops / INT8_PEAK_TOPS, 6))
+
+
+# ---------------------------------------------------------------------------
+# headline: the dense workload on the int8 matrix cores
+# ---------------------------------------------------------------------------
+def dense_system():
+    import synth
+
+    return synth.config_system(3, 0)
+
+
+def run_dense(steps, warmup):
     from paper_1104_1824_amd import snp
 
-    h = snp.snp_load(system, path=path, frontier_cap=cap, stop_at_cap=stop, max_rows=out_cap, chunk=chunk,
-                     profile=2)
-    u16 = system.count_type == "u16"
-    c0 = np.asarray(system.c0, dtype=np.int64)
-    c0 = torch.from_numpy(c0.astype(np.uint16).view(np.int16) if u16 else c0.astype(np.int32)).cuda()
-    out = torch.empty((out_cap, system.m), dtype=torch.int16 if u16 else torch.int32, device="cuda")
-    snp.snp_run(h, c0, depth, out, out_cap)
-    torch.cuda.synchronize()
+    s = dense_system()
+    log(f"dense m=512 seed 0, int8 path: warmup {warmup}, steps {steps}")
+    w = Walk(s, snp.SNP_PATH_INT8, 1000000, 3, False, 1 << 20, 3000001, profile=1)
+    results, dt = w.timed(steps, warmup)
+    w.close()
+    new = results[-1]["n_configs"] - 1
+    assert all(r["n_configs"] - 1 == new for r in results)
+    log(f"levels {results[-1]['level_sizes'].tolist()}, {new} new per walk, {dt / steps * 1e3:.3f} ms/walk")
+    return s, results, dt
+
+
+def run_dense_sparse(reps=1):
+    from paper_1104_1824_amd import snp
+
+    log("dense m=512 seed 0, plain sparse path (the speedup's reference)")
+    w = Walk(dense_system(), snp.SNP_PATH_SPARSE, 1000000, 3, False, 1 << 20, 3000001, profile=1)
+    results, dt = w.timed(reps, 1)
+    w.close()
+    return dict(ms_per_walk=round(dt / reps * 1e3, 3), new_configs=int(results[-1]["n_configs"] - 1),
+                configs_per_s=round((results[-1]["n_configs"] - 1) * reps / dt, 1))
+
+
+def cpu_dense(budget_s=10.0):
+    """The oracle on level 1 of the dense workload, capped at 1e5 new
+    configurations (about 3e5 children enumerated), repeated for budget_s."""
+    import oracle
+
+    oracle.build(force=False)
+    s = dense_system()
+    n_new, runs = 0, 0
     t0 = time.perf_counter()
-    for _ in range(reps):
-        r = snp.snp_run(h, c0, depth, out, out_cap)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
-    h.close()
-    st = r["level_stats"]
-    ns = sum(s_["ns_expand"] for s_ in st)
-    expanded = sum(s_["expanded"] for s_ in st)
-    twins = sum(s_["twins"] for s_ in st)
-    rb = system.m * (2 if u16 else 4)
-    # a child writes its row, key, parent and index; a twin child only its
-    # parent and index
-    moved = (expanded - twins) * (rb + 20) + twins * TWIN_CHILD_BYTES
-    return dict(ms_per_walk=round(dt * 1e3, 3), new_configs=int(r["n_configs"] - 1),
-                configs_per_s=round((r["n_configs"] - 1) / dt, 1), levels=r["level_sizes"].tolist(),
-                expand_us=round(ns / 1e3, 1), expand_gbs=round(moved / max(ns, 1), 1), twins=int(twins),
-                stage_us={k: round(sum(s_["ns_" + k] for s_ in st) / 1e3, 1)
-                          for k in ("psi", "expand", "insert", "flags", "commit")})
+    while True:
+        res = oracle.bfs(s, max_depth=1, frontier_cap=100000, rows_cap=100001)
+        n_new += int(res.level_sizes[1:].sum())
+        runs += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=round(n_new / dt, 1), unit="configs/s", cores=1, kind="oracle",
+                sample=f"{runs} x level 1 of the same workload capped at 1e5 new configurations (seed 0), "
+                       f"single-threaded C oracle, {dt:.1f} s", host=host_info())
 
 
-def extra_plain_int8():
-    """The plain-sparse workload on the int8 matrix-core form."""
+# ---------------------------------------------------------------------------
+# secondary: plain sparse, batched, large
+# ---------------------------------------------------------------------------
+def cpu_plain(budget_s=5.0):
+    import oracle
+    import synth
+
+    oracle.build(force=False)
+    s = synth.config_system(2, 0)
+    n_new, runs, t0 = 0, 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        res = oracle.bfs(s, max_depth=1000, frontier_cap=100000, stop_at_cap=True, rows_cap=1 << 18)
+        n_new += int(res.level_sizes[1:].sum())
+        runs += 1
+    dt = time.perf_counter() - t0
+    return dict(value=round(n_new / dt, 1), unit="configs/s", cores=1, kind="oracle",
+                sample=f"{runs} complete walks of the same workload, single-threaded, {dt:.1f} s")
+
+
+def cpu_large():
+    import oracle
+    import synth
+
+    oracle.build(force=False)
+    s = synth.config_system(5, 0)
+    t0 = time.perf_counter()
+    res = oracle.bfs(s, max_depth=1, frontier_cap=2000, rows_cap=2001)
+    dt = time.perf_counter() - t0
+    return dict(value=round(int(res.level_sizes[1:].sum()) / dt, 1), unit="configs/s", cores=1, kind="oracle",
+                sample=f"level 1 of the same workload capped at 2000 new configurations "
+                       f"({int(res.enumerated[0])} children enumerated), single-threaded, {dt:.1f} s")
+
+
+def plain_line(steps=50, warmup=5, cpu=None):
     import synth
     from paper_1104_1824_amd import snp
 
-    log("plain sparse workload, int8 path")
-    return walk_timing(synth.config_system(2, 0), snp.SNP_PATH_INT8, 100000, 1000, True, 1 << 17, 200000, 10)
+    s = synth.config_system(2, 0)
+    log("plain sparse m=64 seed 0, sparse path")
+    w = Walk(s, snp.SNP_PATH_SPARSE, 100000, 1000, True, 1 << 17, 200000, profile=1)
+    results, dt = w.timed(steps, warmup)
+    w.close()
+    new = results[-1]["n_configs"] - 1
+    line = dict(workload=PLAIN_WORKLOAD, value=round(steps * new / dt, 1), unit="configs/s",
+                ms_per_step=round(dt / steps * 1e3, 4), levels=results[-1]["level_sizes"].tolist(), dtype="int32")
+    line.update(hbm_roofline(results, "k_expand_lane", None, s.m * 4, twins_written=True))
+    line["cpu_baseline"] = cpu
+    return line
 
 
-def extra_dense():
-    """Dense m=512 workload: the int8 matrix-core form next to the sparse form."""
-    import synth
-    from paper_1104_1824_amd import snp
-
-    s3 = synth.config_system(3, 0)
-    dense = {}
-    for name, path, reps in (("int8", snp.SNP_PATH_INT8, 3), ("sparse", snp.SNP_PATH_SPARSE, 1)):
-        log(f"dense m=512 workload, {name} path")
-        dense[name] = walk_timing(s3, path, 1000000, 3, False, 1 << 20, 3100000, reps)
-    dense["speedup_int8_over_sparse"] = round(dense["sparse"]["ms_per_walk"] / dense["int8"]["ms_per_walk"], 2)
-    dense["workload"] = ("dense_int8: m=512, 3 rules/neuron (r=1536), p in [0,4] (M entries in [-4,4]), "
-                         "out-degree 64, C0 in [0,4], int32; BFS depth 3, frontier_cap 1e6 per level (seed 0)")
-    return dense
+def batch_work(systems):
+    """Algorithmic integer operations per step of every system: one
+    applicability test per rule, one gather per synapse, one update per neuron."""
+    return [s.r + s.n_syn + s.m for s in systems]
 
 
-def extra_large():
-    """Large exploration: m=4096, uint16, depth 3, cap 4e6 per level, automatic path."""
-    import synth
-    from paper_1104_1824_amd import snp
-
-    log("large m=4096 uint16 workload, automatic path, depth 3, cap 4e6")
-    # chunks of 2^22 children (34 GB of staged rows): few passes over the long runs of twins
-    r = walk_timing(synth.config_system(5, 0), snp.SNP_PATH_AUTO, 4000000, 3, False, 1 << 22, 12000001, 1)
-    r["workload"] = ("large: m=4096, 4 rules/neuron (r=16384), out-degree 16, C0 in [0,8], uint16; BFS depth 3, "
-                     "frontier_cap 4e6 per level (seed 0)")
-    return r
-
-
-def extra_batched():
-    """The batched deterministic launch (256 systems x 10k steps)."""
+def batched_line(reps=3, cpu=None):
     import numpy as np
     import torch
 
@@ -153,105 +275,88 @@ def extra_batched():
     off = snp.snp_batch_offsets(b)
     c0 = torch.from_numpy(np.concatenate([x.c0 for x in systems]).astype(np.int32)).cuda()
     fin = torch.empty(int(off[-1]), dtype=torch.int32, device="cuda")
-    snp.snp_batch_run(b, c0, 10000, fin)
+    res = snp.snp_batch_run(b, c0, 10000, fin)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    reps = 3
     for _ in range(reps):
-        snp.snp_batch_run(b, c0, 10000, fin)
+        res = snp.snp_batch_run(b, c0, 10000, fin)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
     shape = snp.snp_batch_shape(b)
     b.close()
-    return dict(
-        workload="batched_uneven: 256 systems, m in [16,1024], 1-3 rules and out-degree 2-32 per neuron, "
-                 "10k deterministic steps each, one launch (seeds 0-255)",
-        ms_per_launch=round(dt * 1e3, 3), system_steps=256 * 10000,
-        system_steps_per_s=round(256 * 10000 / dt, 1),
-        threads_per_system=shape[0], neurons_per_thread=shape[1])
+    done = res["steps_done"].astype(np.int64)
+    steps_total = int(done.sum())
+    work = np.asarray(batch_work(systems), dtype=np.int64) * done
+    # the launch cannot end before the whole batch's work at the chip's vector
+    # rate, nor before the largest system's work at one CU's rate
+    t_min = max(work.sum() / (VALU_PEAK_GOPS * 1e9), work.max() / (CU_PEAK_GOPS * 1e9))
+    line = dict(workload=BATCH_WORKLOAD, value=round(steps_total / dt, 1), unit="system-steps/s",
+                ms_per_launch=round(dt * 1e3, 3), dtype="int32", threads_per_system=shape[0],
+                neurons_per_thread=shape[1],
+                roofline=dict(bound="alu", achieved=round(work.sum() / dt / 1e9, 2),
+                              peak=round(work.sum() / t_min / 1e9, 2), unit="Gop/s",
+                              frac=round(t_min / dt, 4), traffic=None,
+                              critical_path_ms=round(t_min * 1e3, 3),
+                              largest_system_ops=int(work.max()), total_ops=int(work.sum())),
+                cpu_baseline=cpu)
+    return line
 
 
-EXTRAS = {"plain_sparse_int8_path": extra_plain_int8, "dense_int8": extra_dense, "large": extra_large,
-          "batched": extra_batched}
-
-
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_expand_lane_plain_sparse_m64_traffic.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1104_1824_amd", "csrc", "snp_kernels.hip")
-
-
-def measured_traffic():
-    """HBM bytes per launch of the expansion kernel from the committed
-    FETCH_SIZE / WRITE_SIZE counter runs (scaled by the copy calibration), or
-    None when the kernel source changed since they were taken."""
-    import hashlib
-
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    fields = {}
-    for ln in open(TRAFFIC_FILE):
-        if ":" in ln and ln.strip().startswith("- `"):
-            k, v = ln.strip()[3:].split("`:", 1)
-            fields[k.strip()] = v.strip().strip("`")
-    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if fields.get("kernel_source_sha256") != sha:
-        return None
-    return int(fields["traffic_bytes_per_launch"])
-
-
-def roofline(system, results):
-    """Roofline of the expansion kernel: its algorithmic bytes over its device
-    time.  Algorithmic bytes per launch = children computed x (row bytes written
-    + 20 B of per-child key, parent index and child index + 12 B of its
-    visited-set probe: the slot index and the entry it writes); parent rows,
-    read once per segment of children, and the entry read by the probe's
-    compare-and-swap are not counted."""
-    rb = system.m * 4
-    ns = 0
-    launches = 0
-    children = 0
-    twins = 0
-    for r in results:
-        for st in r["level_stats"]:
-            ns += st["ns_expand"]
-            launches += st["chunks"]
-            children += st["expanded"]
-            twins += st["twins"]
-    steps = len(results)
-    bytes_expand = (children - twins) * (rb + LANE_CHILD_EXTRA) + twins * TWIN_CHILD_BYTES
-    achieved = bytes_expand / max(1, ns)  # bytes per ns = GB/s
-    return dict(
-        kernel="k_expand_lane",
-        bound="hbm",
-        achieved=round(achieved, 2),
-        peak=HBM_PEAK_GBS,
-        unit="GB/s",
-        frac=round(achieved / HBM_PEAK_GBS, 4),
-        traffic=measured_traffic(),
-        bytes_per_launch=round(bytes_expand / max(1, launches)),
-        avg_launch_us=round(ns / max(1, launches) / 1e3, 3),
-        launches_per_step=launches // max(1, steps),
-        expand_us_per_step=round(ns / 1e3 / max(1, steps), 2),
-    )
-
-
-def cpu_baseline(system, run_opts, budget_s=12.0):
+def _det(seed):
     import oracle
+    import synth
+
+    return oracle.deterministic(synth.batched_systems(seed, 1)[0], 10000).steps_done
+
+
+def cpu_batched(sample=16):
+    """The oracle's single-branch runs: the first `sample` systems on one core,
+    and all 256 on a pool of forked processes (one system per task).  Run
+    before this process touches the GPU."""
+    import multiprocessing
+
+    import oracle
+    import synth
 
     oracle.build(force=False)
-    n_new = 0
-    runs = 0
+    systems = synth.batched_systems(0, 256)
+    log(f"batched: CPU oracle, {sample} systems on one core")
     t0 = time.perf_counter()
-    while True:
-        res = oracle.bfs(system, max_depth=run_opts["max_depth"], frontier_cap=run_opts["frontier_cap"],
-                         stop_at_cap=run_opts["stop_at_cap"], rows_cap=1 << 18)
-        n_new += int(res.level_sizes[1:].sum())
-        runs += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return dict(value=round(n_new / dt, 1), unit="configs/s", cores=1, kind="oracle",
-                sample=f"{runs} complete BFS walks of the same workload (plain sparse seed 0), "
-                       f"single-threaded C oracle, {dt:.1f} s")
+    steps1 = sum(oracle.deterministic(s, 10000).steps_done for s in systems[:sample])
+    dt1 = time.perf_counter() - t0
+    workers = max(1, min(12, os.cpu_count() or 1))
+    log(f"batched: CPU oracle, 256 systems on {workers} processes")
+    t0 = time.perf_counter()
+    with multiprocessing.get_context("fork").Pool(workers) as pool:
+        stepsn = sum(pool.map(_det, range(len(systems))))
+    dtn = time.perf_counter() - t0
+    return dict(value=round(steps1 / dt1, 1), unit="system-steps/s", cores=1, kind="oracle",
+                sample=f"systems 0-{sample - 1} of the same batch, 10k steps each, single-threaded, {dt1:.1f} s",
+                multi_core=dict(value=round(stepsn / dtn, 1), cores=workers,
+                                sample=f"all 256 systems, one per task, {dtn:.1f} s"))
+
+
+def large_line(cpu=None):
+    import synth
+    from paper_1104_1824_amd import snp
+
+    s = synth.config_system(5, 0)
+    log("large m=4096 uint16, automatic path, depth 3, cap 4e6")
+    w = Walk(s, snp.SNP_PATH_AUTO, 4000000, 3, False, 1 << 22, 12000001, profile=1)
+    results, dt = w.timed(1, 0)
+    w.close()
+    new = results[-1]["n_configs"] - 1
+    line = dict(workload=LARGE_WORKLOAD, value=round(new / dt, 1), unit="configs/s", ms_per_step=round(dt * 1e3, 3),
+                levels=results[-1]["level_sizes"].tolist(), dtype="uint16",
+                twins=totals(results, "twins"), expanded=totals(results, "expanded"))
+    line.update(hbm_roofline(results, "k_expand_int8", s.m * 2 + ENTRY_BYTES, s.m * 2))
+    line["mfma"] = mfma_util(results)
+    line["cpu_baseline"] = cpu
+    return line
+
+
+SECONDARY = {"plain_sparse": plain_line, "batched": batched_line, "large": large_line}
+CPU_BASELINES = {"dense": cpu_dense, "plain_sparse": cpu_plain, "batched": cpu_batched, "large": cpu_large}
 
 
 def copy_calibration(nbytes=1 << 30, reps=5):
@@ -269,73 +374,78 @@ def copy_calibration(nbytes=1 << 30, reps=5):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the int8 / dense / batched side measurements")
-    ap.add_argument("--only", choices=sorted(EXTRAS), help="run only this side measurement and print it")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the plain-sparse / batched / large lines")
+    ap.add_argument("--only", choices=sorted(SECONDARY) + ["dense"],
+                    help="run only this workload (no CPU baseline) and print its line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reads 1 GiB, writes 1 GiB) five times, to scale "
                          "FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
-    if args.copy_calibration:
-        copy_calibration()
-        return
-    if args.only:
-        print(json.dumps({args.only: EXTRAS[args.only]()}), flush=True)
-        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library runs on a single MI355X, so --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    # the CPU oracle runs first, before this process touches the GPU (its
+    # process pool is forked from here)
+    cpus = {}
+    if not args.no_cpu_baseline and not args.only:
+        for name, fn in CPU_BASELINES.items():
+            if name != "dense" and args.no_secondary:
+                continue
+            log(f"{name}: CPU oracle")
+            cpus[name] = fn()
     import torch
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
-    system, run_opts = plain_sparse_workload(0)
-    log(f"plain sparse seed 0: m={system.m} r={system.r} syn={system.n_syn}; warmup {args.warmup}, steps {args.steps}")
-    results, dt, _ = run_gpu(system, run_opts, args.steps, args.warmup)
-    new_per_step = results[-1]["n_configs"] - 1
-    sizes = results[-1]["level_sizes"].tolist()
-    assert all(r["n_configs"] - 1 == new_per_step for r in results)
-    value = args.steps * new_per_step / dt
-    log(f"levels {sizes}, {new_per_step} new configurations per step, {dt / args.steps * 1e3:.3f} ms/step")
-    rl = roofline(system, results)
-    log(f"expansion kernel {rl['expand_us_per_step']} us per step")
-    extras = None
-    if not args.no_extras:
-        extras = {name: fn() for name, fn in EXTRAS.items()}
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle on the same workload")
-        cpu = cpu_baseline(system, run_opts)
+    if args.only and args.only != "dense":
+        print(json.dumps({args.only: SECONDARY[args.only]()}), flush=True)
+        return
+    s, results, dt = run_dense(args.steps, args.warmup)
+    if args.only == "dense":
+        print(json.dumps(dict(ms_per_step=round(dt / args.steps * 1e3, 4),
+                              **hbm_roofline(results, "k_expand_int8", s.m * 4 + ENTRY_BYTES, s.m * 4))), flush=True)
+        return
+    new = results[-1]["n_configs"] - 1
+    rl = hbm_roofline(results, "k_expand_int8", s.m * 4 + ENTRY_BYTES, s.m * 4)
+    sparse = run_dense_sparse()
+    ms = dt / args.steps * 1e3
+    secondary = None
+    if not args.no_secondary:
+        secondary = {name: fn(cpu=cpus.get(name)) for name, fn in SECONDARY.items()}
+    cpu = cpus.get("dense")
     line = {
         "metric": METRIC,
-        "value": round(value, 1),
+        "value": round(args.steps * new / dt, 1),
         "unit": "configs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "ms_per_step": round(ms, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32",
+        "dtype": "int8",
         "data": "synthetic",
         "config": {
-            "workload": "plain_sparse: seeded SN P system m=64, 2 rules/neuron (r=128), E=a^i(a^j)* "
-                        "i in [1,4] j in [0,3], out-degree 4, C0 in [0,4], int32; BFS until a level "
-                        "reaches 1e5 configurations (seed 0)",
-            "levels": sizes,
-            "new_configs_per_step": new_per_step,
-            "path": "sparse",
+            "workload": DENSE_WORKLOAD,
+            "levels": results[-1]["level_sizes"].tolist(),
+            "new_configs_per_step": new,
+            "path": "int8 matrix cores (int32 accumulation, int32 rows)",
             "parallelism": "single GPU",
         },
-        "roofline": {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
-        "dominant_kernel": {k: rl[k] for k in ("kernel", "bytes_per_launch", "avg_launch_us", "launches_per_step",
-                                                "expand_us_per_step")},
+        "roofline": rl["roofline"],
+        "dominant_kernel": rl["dominant_kernel"],
+        "mfma": mfma_util(results),
+        "vs_plain_sparse": dict(sparse, speedup=round(sparse["ms_per_walk"] / ms, 2)),
         "cpu_baseline": cpu,
-        "extras": extras,
+        "secondary": secondary,
     }
     print(json.dumps(line), flush=True)
 

@@ -130,6 +130,12 @@ typedef struct {
                                  may put on the matrix cores, 0: 128; segments that need more
                                  take the per-child sparse form (smaller values force it;
                                  results do not change) */
+    int32_t deterministic;    /* nonzero: every configuration has at most one child, the one
+                                 that fires the first applicable rule of every neuron (the first
+                                 spiking vector of Algorithm 2 step II-3), so a walk follows a
+                                 single branch of the computation tree (Section 2.1: one rule per
+                                 neuron, all neurons on a global clock) and ends at its first
+                                 repeated configuration (EMPTY_FRONTIER) or at a halting one */
     void *stream;             /* hipStream_t for all work of the handle; NULL: default */
 } snp_options;
 
@@ -144,12 +150,19 @@ typedef struct {
     int64_t enumerated;      /* children in canonical order up to where the level stopped:
                                 the cap-filling child, the budget, or all of them */
     int64_t new_configs;     /* configurations recorded for the level */
+    int64_t duplicates;      /* enumerated - new_configs: children equal to a configuration
+                                recorded before, at this level or an earlier one (Algorithm 1
+                                step IV membership test), twins included */
     int64_t expanded;        /* children computed on the device (>= enumerated: the pass that
                                 fills the cap runs to its end) */
     int64_t twins;           /* of those, children that fire the later of two twin rules (same
                                 neuron, same c and p): they repeat an earlier child, so only
                                 their parent and child index are written */
+    int64_t collisions;      /* visited-set probes that met an entry with the same 32-bit tag
+                                whose full row differed (settled by the row compare) */
     int64_t chunks;          /* device passes used */
+    int64_t mfma_ops;        /* int8 matrix-core multiply-adds issued by the level, x 2 (one
+                                16x16x64 instruction = 32768 integer operations) */
     int32_t truncated;       /* 1: the level reached frontier_cap */
     int32_t budget_hit;      /* 1: child_budget ran out with children left */
     int32_t path_used;       /* snp_path of the last chunk (SPARSE or INT8) */
@@ -181,8 +194,11 @@ const char *snp_last_error(void);
 /* Number of bytes of one row (m * size of the count type). */
 int64_t snp_row_bytes(const snp_system *sys);
 
-/* Start a caller-driven walk: forget every visited configuration and record
- * C0 (device pointer, one row) as level 0 in the handle's own row store.
+/* Start a caller-driven walk (Algorithm 1 step I: the initial configuration
+ * becomes the first entry of the list of produced configurations): forget
+ * every visited configuration and record C0 (device pointer, one row) as
+ * level 0 in the handle's own row store.  The row store (max_rows rows) is
+ * allocated on the first call.
  * Errors: SNP_ERR_OVERFLOW if C0 holds a count outside the type's range (only
  * negative counts can be out of range for int32 here). */
 snp_status snp_reset(snp_system *sys, const void *c0_dev);
@@ -289,6 +305,24 @@ snp_status snp_batch_shape(const snp_batch *b, int32_t *threads, int32_t *neuron
 snp_status snp_batch_run(snp_batch *b, const void *c0_dev, int32_t steps, int32_t detect_repeats,
                          void *final_dev, int32_t *halt_step, int32_t *first_repeat, int32_t *steps_done,
                          uint64_t *digest);
+
+/* Deterministic branch of n systems loaded with snp_load, in one launch
+ * (the batched mode above, built from the handles' descriptions on the first
+ * call with this list of handles and kept for later calls with the same list).
+ *   systems: host array of n handles, all with one count type.
+ *   c0_dev: host array of n device pointers, one row each.
+ *   steps: most steps per system, 0 <= steps <= 2^24.
+ *   final_dev: host array of n device pointers, one row each: the
+ *     configuration after the last computed step.
+ *   halt_step, first_repeat_step: host int32 [n]; trajectory_digest: host
+ *     uint64 [n]; as halt_step, first_repeat and digest of snp_batch_run
+ *     (repeat detection on).
+ * The batched mode's limits apply (m <= 4096; i, j, c, p <= 255).
+ * Errors: SNP_ERR_INVALID (NULL arguments, mixed count types, limits);
+ *   SNP_ERR_OVERFLOW; SNP_ERR_DEVICE. */
+snp_status snp_run_batch(snp_system *const *systems, int32_t n, const void *const *c0_dev, int32_t steps,
+                         void *const *final_dev, int32_t *halt_step, int32_t *first_repeat_step,
+                         uint64_t *trajectory_digest);
 
 #ifdef __cplusplus
 }

@@ -61,7 +61,7 @@ class _BfsOpts(ctypes.Structure):
     _fields_ = [
         ("max_depth", ctypes.c_int32), ("stop_at_cap", ctypes.c_int32),
         ("frontier_cap", ctypes.c_int64), ("child_budget", ctypes.c_int64),
-        ("expand_max_count", ctypes.c_int64),
+        ("expand_max_count", ctypes.c_int64), ("first_only", ctypes.c_int32), ("pad_", ctypes.c_int32),
     ]
 
 
@@ -200,16 +200,17 @@ class BfsResult:
 
 def bfs(sys, c0=None, max_depth: int = -1, frontier_cap: int = 0, child_budget: int = 0,
         expand_max_count: int = -1, stop_at_cap: bool = False, rows_cap: int = 1 << 12,
-        max_levels: int = 1 << 12) -> BfsResult:
+        max_levels: int = 1 << 12, deterministic: bool = False) -> BfsResult:
     """Algorithm 1 from C0: levels of new configurations in first-occurrence order.
 
     ``frontier_cap`` truncates every level to its first new configurations in
     enumeration order (truncated ones are not recorded); with ``stop_at_cap`` a
-    level that reaches the cap also ends the walk."""
+    level that reaches the cap also ends the walk.  ``deterministic`` keeps only
+    the first spiking vector of every configuration (a single branch)."""
     S = _Sys(sys)
     c0 = _i64(sys.c0 if c0 is None else c0)
     opts = _BfsOpts(int(max_depth), int(bool(stop_at_cap)), int(frontier_cap), int(child_budget),
-                    int(expand_max_count))
+                    int(expand_max_count), int(bool(deterministic)), 0)
     cap = int(rows_cap)
     while True:
         rows = np.zeros((cap, S.m), dtype=np.int64)

@@ -348,6 +348,9 @@ typedef struct {
     int64_t child_budget;     /* <= 0: none.  At most this many children are enumerated per level */
     int64_t expand_max_count; /* < 0: none.  A configuration holding more spikes than this in some
                                  neuron is recorded but not expanded */
+    int32_t first_only;       /* nonzero: only the first valid spiking vector of every configuration
+                                 (each neuron fires its first applicable rule): one branch */
+    int32_t pad_;
 } or_bfs_opts;
 
 typedef struct {
@@ -429,6 +432,7 @@ int or_bfs(const or_system *sys, const int64_t *c0, const or_bfs_opts *opt, or_b
                     if (opt->frontier_cap > 0 && added >= opt->frontier_cap) { cap_hit = 1; break; }
                 }
                 ++t;
+                if (opt->first_only) break; /* the single branch: Algorithm 2's first vector only */
                 enum_next(&E);
             }
             /* A budget that runs out exactly at the end of a parent is only "hit" when a

@@ -15,4 +15,5 @@ from .snp import (  # noqa: F401
     snp_reset,
     snp_row_bytes,
     snp_run,
+    snp_run_batch,
 )

@@ -6,7 +6,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -60,6 +62,11 @@ hipError_t dmalloc(P** p, size_t bytes) {
 
 struct snp_system {
     int m = 0, r = 0, elem_bytes = 4;
+    // the host description, kept for snp_run_batch (which packs the handles'
+    // systems into one batched launch), and an id no other handle ever gets
+    std::vector<int32_t> h_rn, h_ri, h_rj, h_rc, h_rp, h_ss, h_sd;
+    int32_t count_type = SNP_COUNT_I32;
+    unsigned long long uid = 0;
     long long count_max = INT_MAX;
     snp_options opt{};
     hipStream_t stream = nullptr;
@@ -75,6 +82,7 @@ struct snp_system {
     u64* d_R = nullptr;      // hash weights
     u64* d_hM = nullptr;     // H of every row of M_Pi
     bool int8_ready = false; // d_M8 built and the int8 kernel's limits hold
+    bool lane_form = false;  // m <= 64, in-degree <= 16: the one-neuron-per-lane expansion applies
     double sparse_work = 0;  // per-child work estimates of the two forms (path choice)
     double int8_work = 0;
     snp::DevSystem dsys{};
@@ -252,6 +260,15 @@ snp_status validate_options(const snp_options* o) {
     return SNP_OK;
 }
 
+// The visited set holds 2^k >= 2 (max_rows + 2 chunk) entries indexed by 32-bit
+// slots: max_rows + 2 chunk must not pass 2^31.
+snp_status validate_table_size(long long max_rows, long long chunk) {
+    if (max_rows + 2 * chunk > (1LL << 31))
+        return fail(SNP_ERR_INVALID, "max_rows + 2 * chunk = %lld exceeds 2^31 (visited-set slots are 32-bit)",
+                    max_rows + 2 * chunk);
+    return SNP_OK;
+}
+
 // Wait for a stream by polling it: a pass's counters are awaited many times
 // per walk, each a few tens of microseconds after the launch, and a blocking
 // wait adds the wake-up of a sleeping thread to every one of them.
@@ -369,7 +386,8 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
     stt.int8_fallback = (S->opt.path == SNP_PATH_INT8 && !S->int8_ready) ? 1 : 0;
     bool use_int8 = false;
     if (S->opt.path == SNP_PATH_INT8) use_int8 = S->int8_ready;
-    else if (S->opt.path == SNP_PATH_AUTO) use_int8 = S->int8_ready && S->int8_work < S->sparse_work;
+    else if (S->opt.path == SNP_PATH_AUTO)  // the one-neuron-per-lane form wins wherever it applies
+        use_int8 = S->int8_ready && !S->lane_form && S->int8_work < S->sparse_work;
     stt.path_used = use_int8 ? SNP_PATH_INT8 : SNP_PATH_SPARSE;
     if (io.n > S->max_frontier)
         return fail(SNP_ERR_CAPACITY, "frontier of %lld rows exceeds max_frontier %lld", io.n, S->max_frontier);
@@ -512,6 +530,8 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         if (Beff > 0) ++stt.chunks;
         stt.expanded += Beff;
         stt.twins += (long long)c.twins;
+        stt.collisions += (long long)c.collisions;
+        stt.mfma_ops += (long long)c.mfma * 32768;
         const long long new_total = (long long)c.total;
         const long long avail = limit - count;
         const long long committed = std::min(new_total, avail);
@@ -561,6 +581,7 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
     stt.children_total = (long long)T;
     stt.enumerated = (long long)enumerated;
     stt.new_configs = count;
+    stt.duplicates = (long long)enumerated - count;
     stt.truncated = cap_hit ? 1 : 0;
     stt.budget_hit = budget_hit ? 1 : 0;
     if (out) *out = stt;
@@ -616,6 +637,20 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     S->max_frontier = opt.max_frontier > 0 ? opt.max_frontier : opt.max_rows;
     const long long rb = row_bytes(S);
     S->chunk_max = opt.chunk > 0 ? opt.chunk : std::min<long long>(1 << 20, std::max<long long>(4096, (1LL << 28) / rb));
+    if ((st = validate_table_size(S->max_rows, S->chunk_max))) {
+        delete S;
+        return st;
+    }
+    static std::atomic<unsigned long long> next_uid{1};
+    S->uid = next_uid++;
+    S->count_type = d->count_type;
+    S->h_rn.assign(d->rule_neuron, d->rule_neuron + d->r);
+    S->h_ri.assign(d->rule_i, d->rule_i + d->r);
+    S->h_rj.assign(d->rule_j, d->rule_j + d->r);
+    S->h_rc.assign(d->rule_c, d->rule_c + d->r);
+    S->h_rp.assign(d->rule_p, d->rule_p + d->r);
+    S->h_ss.assign(d->syn_src, d->syn_src + d->n_syn);
+    S->h_sd.assign(d->syn_dst, d->syn_dst + d->n_syn);
 
     // rule tables (rules of a neuron are contiguous: validated order)
     std::vector<int> nrule_ptr(d->m + 1, 0);
@@ -698,8 +733,10 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
             for (int e = 0; e < in_ptr[n + 1] - in_ptr[n]; ++e) in_lane[e * 64 + n] = in_src[in_ptr[n] + e];
     LOADCHK(dmalloc(&S->d_in_lane, sizeof(int) * in_lane.size()));
     LOADCHK(up(S->d_in_lane, in_lane.data(), sizeof(int) * in_lane.size()));
+    S->lane_form = d->m <= 64 && max_in <= 16 && (size_t)d->r * 24 <= 24 * 1024;
     S->dsys = snp::DevSystem{d->m, d->r, S->d_nrule_ptr, S->d_rules, S->d_in_ptr, S->d_in_src, d->n_syn, S->d_M8,
-                             S->count_max, S->d_R, S->d_hM, max_in, S->d_in_lane};
+                             S->count_max, S->d_R, S->d_hM, max_in, S->d_in_lane,
+                             opt.deterministic ? 1ULL : snp::kPsiSat};
 
     S->slots = next_pow2((u64)std::max<long long>(1024, 2 * (S->max_rows + 2 * S->chunk_max)));
     LOADCHK(dmalloc(&S->d_table, sizeof(u64) * S->slots));
@@ -1092,6 +1129,89 @@ snp_status snp_batch_run(snp_batch* b, const void* c0_dev, int32_t steps, int32_
             return fail(SNP_ERR_DEVICE, "system %d: two configurations share a 64-bit hash; repeat detection "
                         "cannot vouch for its answer", k);
     }
+    return SNP_OK;
+}
+
+// snp_run_batch: the handles' systems packed into one batch, kept while the
+// list of handles (by id) stays the same.  The packed rows live in buffers of
+// their own, so the batch's recorded graph is replayed across calls.
+namespace {
+struct RunBatchCache {
+    std::vector<unsigned long long> uids;
+    snp_batch* b = nullptr;
+    int n = 0, elem_bytes = 4;
+    void* d_c0 = nullptr;        // packed C0 rows
+    void* d_fin = nullptr;       // packed final rows
+    void** d_ptrs = nullptr;     // [2n]: C0 sources, then final destinations
+    long long* d_off = nullptr;  // [n + 1] element offsets of the packed rows
+    std::vector<void*> h_ptrs;
+    void release() {
+        if (b) snp_batch_free(b);
+        void* ps[] = {d_c0, d_fin, d_ptrs, d_off};
+        for (void* p : ps)
+            if (p) (void)hipFree(p);
+        *this = RunBatchCache{};
+    }
+};
+// One per thread; its device buffers are replaced when the list of handles
+// changes and otherwise live until the process ends.
+thread_local RunBatchCache* g_rb = nullptr;
+}  // namespace
+
+snp_status snp_run_batch(snp_system* const* systems, int32_t n, const void* const* c0_dev, int32_t steps,
+                         void* const* final_dev, int32_t* halt_step, int32_t* first_repeat_step,
+                         uint64_t* trajectory_digest) {
+    g_err.clear();
+    if (!systems || n < 1 || !c0_dev || !final_dev || !halt_step || !first_repeat_step || !trajectory_digest)
+        return fail(SNP_ERR_INVALID, "systems, c0_dev, final_dev and every result array are required (n >= 1)");
+    for (int k = 0; k < n; ++k) {
+        if (!systems[k]) return fail(SNP_ERR_INVALID, "system %d is NULL", k);
+        if (!c0_dev[k] || !final_dev[k]) return fail(SNP_ERR_INVALID, "system %d: c0 or final is NULL", k);
+        if (systems[k]->count_type != systems[0]->count_type)
+            return fail(SNP_ERR_INVALID, "system %d: all systems must share one count type", k);
+    }
+    if (!g_rb) g_rb = new RunBatchCache();
+    RunBatchCache& C = *g_rb;
+    std::vector<unsigned long long> uids(n);
+    for (int k = 0; k < n; ++k) uids[k] = systems[k]->uid;
+    hipStream_t st = systems[0]->stream;
+    if (uids != C.uids || !C.b) {
+        C.release();
+        std::vector<snp_desc> descs(n);
+        for (int k = 0; k < n; ++k) {
+            const snp_system* S = systems[k];
+            descs[k] = snp_desc{S->m, S->r, S->h_rn.data(), S->h_ri.data(), S->h_rj.data(), S->h_rc.data(),
+                                S->h_rp.data(), (int32_t)S->h_ss.size(), S->h_ss.data(), S->h_sd.data(), nullptr,
+                                S->count_type};
+        }
+        snp_options o{};
+        o.max_rows = 1;
+        o.stream = st;
+        snp_status r = snp_batch_load(descs.data(), n, &o, &C.b);
+        if (r) return r;
+        C.n = n;
+        C.elem_bytes = C.b->elem_bytes;
+        const long long total = C.b->row_off[n];
+        HIPCHK(dmalloc(&C.d_c0, (size_t)std::max<long long>(1, total) * C.elem_bytes));
+        HIPCHK(dmalloc(&C.d_fin, (size_t)std::max<long long>(1, total) * C.elem_bytes));
+        HIPCHK(dmalloc(&C.d_ptrs, sizeof(void*) * 2 * n));
+        HIPCHK(dmalloc(&C.d_off, sizeof(long long) * (n + 1)));
+        HIPCHK(hipMemcpy(C.d_off, C.b->row_off.data(), sizeof(long long) * (n + 1), hipMemcpyHostToDevice));
+        C.h_ptrs.assign(2 * n, nullptr);
+        C.uids = uids;
+    }
+    for (int k = 0; k < n; ++k) {
+        C.h_ptrs[k] = const_cast<void*>(c0_dev[k]);
+        C.h_ptrs[n + k] = final_dev[k];
+    }
+    HIPCHK(hipMemcpyAsync(C.d_ptrs, C.h_ptrs.data(), sizeof(void*) * 2 * n, hipMemcpyHostToDevice, st));
+    HIPCHK(snp::launch_pack_rows((void* const*)C.d_ptrs, C.d_off, C.d_c0, n, C.elem_bytes, true, st));
+    std::vector<int32_t> done(n);
+    snp_status r = snp_batch_run(C.b, C.d_c0, steps, 1, C.d_fin, halt_step, first_repeat_step, done.data(),
+                                 trajectory_digest);
+    if (r) return r;
+    HIPCHK(snp::launch_pack_rows((void* const*)(C.d_ptrs + n), C.d_off, C.d_fin, n, C.elem_bytes, false, st));
+    HIPCHK(hipStreamSynchronize(st));
     return SNP_OK;
 }
 

@@ -204,6 +204,7 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
     long long have_p = -1;
     u64 place = 0;
     uint32_t ntwin = 0;  // twin children of this block's tiles (thread 0)
+    u64 nmfma = 0;       // matrix-core instructions of this block (thread 0)
     // children [.., twin_end) of parent twin_p are all twins: a digit of a
     // neuron above the ones that change there picks a later twin rule
     long long twin_p = -1;
@@ -405,6 +406,9 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
                     if (lane == 0) L.misc[1] |= bm;
                 }
                 const int kpad = (kvar + 63) & ~63;
+                // instructions this segment issues: (m / NT) column tiles x 4 waves x
+                // (kpad / 64) K steps x 4 row blocks x NT / 64 column blocks
+                if (tid == 0) nmfma += (u64)((m + NT - 1) / NT) * 4 * (kpad / 64) * 4 * (NT / 64);
                 // 7. column tiles: stage M_V transposed, multiply, add the reference row
                 for (int n0 = 0; n0 < m; n0 += NT) {
                     __syncthreads();
@@ -481,6 +485,7 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
     }
     if (__syncthreads_or(ovf) && tid == 0) atomicOr((unsigned long long*)&a.ctr->overflow, 1ULL);
     if (tid == 0 && ntwin) atomicAdd((unsigned long long*)&a.ctr->twins, (u64)ntwin);
+    if (tid == 0 && nmfma) atomicAdd((unsigned long long*)&a.ctr->mfma, nmfma);
 }
 
 hipError_t launch_expand_int8(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st) {

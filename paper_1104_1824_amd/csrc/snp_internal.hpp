@@ -37,6 +37,8 @@ struct DevCounters {
     u64 psi_total;     // children of the frontier prefix after this pass's extension
     u64 twins;         // children of the chunk that fire a later twin rule
     u64 c0_bad;        // walk start: C0 holds a count outside the count type's range
+    u64 collisions;    // probes that met an entry with their tag whose row differed
+    u64 mfma;          // int8 matrix-core instructions issued (16x16x64 each)
 };
 
 // Device-side description of a loaded system.
@@ -54,6 +56,8 @@ struct DevSystem {
     int max_in;            // largest in-degree of a neuron
     const int* in_lane;    // [16 * 64] in-synapse e of neuron j at e * 64 + j (-1: none),
                            // filled when m <= 64 and max_in <= 16
+    u64 psi_cap;           // largest Psi of a parent: 1 in deterministic mode (first spiking
+                           // vector only), kPsiSat otherwise
 };
 
 // One chunk of children [g0, g0 + B) of the frontier.
@@ -163,6 +167,11 @@ int batch_max_threads();
 int batch_interval();
 hipError_t launch_batch_det(int elem_bytes, int threads, int npt, const BatchArgs& a, int n_sys, hipStream_t st);
 hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st);
+// Copy n rows between separate buffers (ptrs[k]) and one packed buffer (row k at
+// element off[k] .. off[k+1]); to_packed selects the direction.  ptrs and off
+// are device arrays.
+hipError_t launch_pack_rows(void* const* ptrs, const long long* off, void* packed, int n, int elem_bytes,
+                            bool to_packed, hipStream_t st);
 
 hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, long long n,
                       long long expand_max, u64* psi, uint8_t* halt_flag, DevCounters* ctr, hipStream_t st);

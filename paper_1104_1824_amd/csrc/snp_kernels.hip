@@ -117,7 +117,8 @@ __global__ __launch_bounds__(256) void k_psi(DevSystem s, const T* __restrict__ 
     unsigned halting = 0;
     for (long long p = w0; p < min(n, w0 + parents_per_wave); ++p) {
         bool h;
-        const u64 v = parent_psi<T>(F + p * (long long)s.m, s.m, tb.nrp, tb.rules, expand_max, lane, h);
+        const u64 v = min(parent_psi<T>(F + p * (long long)s.m, s.m, tb.nrp, tb.rules, expand_max, lane, h),
+                          s.psi_cap);
         if (lane == 0) {
             psi[p] = v;
             halt_flag[p] = h ? 1 : 0;
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(1024) void k_psi_scan_small(DevSystem s, const T* _
             PsiAcc A;
             psi_add_neuron(A, xs[q], lane, m, tb.nrp, tb.rules, expand_max);
             bool h;
-            const u64 v = psi_finish(A, h);
+            const u64 v = min(psi_finish(A, h), s.psi_cap);
             if (lane == 0) {
                 l_psi[p] = v;
                 psi[p] = v;
@@ -1194,6 +1195,7 @@ __global__ __launch_bounds__(256) void k_insert_compare(int m, TableArgs a) {
                     done = true;
                     break;
                 }
+                if (lane == 0) atomicAdd((unsigned long long*)&a.ctr->collisions, 1ULL);
             }
             sl = (sl + 1) & a.slot_mask;
         }
@@ -1416,6 +1418,29 @@ hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Block k copies row k between its own buffer and the packed buffer.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack_rows(void* const* __restrict__ ptrs, const long long* __restrict__ off,
+                                                   T* __restrict__ packed, bool to_packed) {
+    const int k = blockIdx.x;
+    const long long a = off[k], len = off[k + 1] - a;
+    T* own = (T*)ptrs[k];
+    for (long long j = threadIdx.x; j < len; j += 256) {
+        if (to_packed) packed[a + j] = own[j];
+        else own[j] = packed[a + j];
+    }
+}
+
+hipError_t launch_pack_rows(void* const* ptrs, const long long* off, void* packed, int n, int elem_bytes,
+                            bool to_packed, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (elem_bytes == 4)
+        hipLaunchKernelGGL(k_pack_rows<int32_t>, dim3(n), dim3(256), 0, st, ptrs, off, (int32_t*)packed, to_packed);
+    else
+        hipLaunchKernelGGL(k_pack_rows<uint16_t>, dim3(n), dim3(256), 0, st, ptrs, off, (uint16_t*)packed, to_packed);
+    return hipGetLastError();
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_rows_insert(int m, const u64* R, u64* table, u64 slot_mask, const T* arena,
                                                      long long first, long long count, u64 hash_mask,
@@ -1466,8 +1491,8 @@ __global__ __launch_bounds__(256) void k_start_walk(int m, const u64* __restrict
                                                     long long count_max, u64 hash_mask,
                                                     uint32_t* __restrict__ row_slot, DevCounters* __restrict__ sc,
                                                     long long* par0, long long* chi0, const int* nrp,
-                                                    const int4* rules, long long expand_max, u64* psi0,
-                                                    uint8_t* hflag0, u64* off0, u64* Tdev) {
+                                                    const int4* rules, long long expand_max, u64 psi_cap,
+                                                    u64* psi0, uint8_t* hflag0, u64* off0, u64* Tdev) {
     __shared__ u64 s_slot, s_entry;
     const int lane = threadIdx.x & 63;
     if (threadIdx.x < 64) {
@@ -1495,7 +1520,7 @@ __global__ __launch_bounds__(256) void k_start_walk(int m, const u64* __restrict
     // when asked: the first pass then needs no Psi launch of its own
     u64 psi_c0 = 0;
     bool halt_c0 = false;
-    if (psi0 && threadIdx.x < 64) psi_c0 = parent_psi<T>(c0, m, nrp, rules, expand_max, lane, halt_c0);
+    if (psi0 && threadIdx.x < 64) psi_c0 = min(parent_psi<T>(c0, m, nrp, rules, expand_max, lane, halt_c0), psi_cap);
     if (threadIdx.x == 0) {
         row_slot[0] = (uint32_t)home;
         if (par0) *par0 = -1;
@@ -1522,11 +1547,11 @@ hipError_t launch_start_walk(int elem_bytes, int m, const u64* R, u64* table, u6
     if (elem_bytes == 4)
         hipLaunchKernelGGL(k_start_walk<int32_t>, dim3(blocks), dim3(256), 0, st, m, R, table, slot_mask,
                            (const int32_t*)c0, (int32_t*)arena, count_max, hash_mask, row_slot, sc, par0, chi0,
-                           s.nrule_ptr, s.rules, expand_max, psi0, hflag0, off0, Tdev);
+                           s.nrule_ptr, s.rules, expand_max, s.psi_cap, psi0, hflag0, off0, Tdev);
     else
         hipLaunchKernelGGL(k_start_walk<uint16_t>, dim3(blocks), dim3(256), 0, st, m, R, table, slot_mask,
                            (const uint16_t*)c0, (uint16_t*)arena, count_max, hash_mask, row_slot, sc, par0, chi0,
-                           s.nrule_ptr, s.rules, expand_max, psi0, hflag0, off0, Tdev);
+                           s.nrule_ptr, s.rules, expand_max, s.psi_cap, psi0, hflag0, off0, Tdev);
     return hipGetLastError();
 }
 

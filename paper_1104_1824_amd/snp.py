@@ -24,7 +24,8 @@ SNP_STOP_EMPTY_FRONTIER, SNP_STOP_ALL_HALTING, SNP_STOP_DEPTH, SNP_STOP_CAP, SNP
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OVERFLOW", 3: "CAPACITY", 4: "BUDGET", 5: "DEVICE"}
 
 EXPORTED = ("snp_load", "snp_free", "snp_last_error", "snp_row_bytes", "snp_reset", "snp_expand", "snp_run",
-            "snp_batch_load", "snp_batch_free", "snp_batch_offsets", "snp_batch_shape", "snp_batch_run")
+            "snp_batch_load", "snp_batch_free", "snp_batch_offsets", "snp_batch_shape", "snp_batch_run",
+            "snp_run_batch")
 
 
 class SnpError(RuntimeError):
@@ -51,7 +52,7 @@ class snp_options(ctypes.Structure):
         ("expand_max_count", ctypes.c_int64), ("max_rows", ctypes.c_int64),
         ("max_frontier", ctypes.c_int64), ("chunk", ctypes.c_int64),
         ("hash_mask", ctypes.c_uint64), ("profile", ctypes.c_int32), ("int8_max_k", ctypes.c_int32),
-        ("stream", ctypes.c_void_p),
+        ("deterministic", ctypes.c_int32), ("stream", ctypes.c_void_p),
     ]
 
 
@@ -59,8 +60,9 @@ class snp_expand_stats(ctypes.Structure):
     _fields_ = [
         ("parents", ctypes.c_int64), ("halting_parents", ctypes.c_int64),
         ("children_total", ctypes.c_int64), ("enumerated", ctypes.c_int64),
-        ("new_configs", ctypes.c_int64), ("expanded", ctypes.c_int64), ("twins", ctypes.c_int64),
-        ("chunks", ctypes.c_int64),
+        ("new_configs", ctypes.c_int64), ("duplicates", ctypes.c_int64), ("expanded", ctypes.c_int64),
+        ("twins", ctypes.c_int64), ("collisions", ctypes.c_int64), ("chunks", ctypes.c_int64),
+        ("mfma_ops", ctypes.c_int64),
         ("truncated", ctypes.c_int32), ("budget_hit", ctypes.c_int32),
         ("path_used", ctypes.c_int32), ("int8_fallback", ctypes.c_int32),
         ("ns_psi", ctypes.c_int64), ("ns_expand", ctypes.c_int64), ("ns_insert", ctypes.c_int64),
@@ -121,6 +123,8 @@ def lib():
         L.snp_batch_shape.restype = I32
         L.snp_batch_run.argtypes = [P, P, I32, I32, P, P, P, P, P]
         L.snp_batch_run.restype = I32
+        L.snp_run_batch.argtypes = [P, I32, P, I32, P, P, P, P]
+        L.snp_run_batch.restype = I32
         _lib = L
     return _lib
 
@@ -134,13 +138,35 @@ def _i32(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
 
 
-def _ptr(t) -> Optional[int]:
-    """Device pointer of a torch tensor (None stays None)."""
+def check_buffer(t, name: str, elem_bytes: int, min_elems: int):
+    """Host-side check of a buffer handed to the library: contiguous, elements of
+    the size the library reads or writes, and at least min_elems of them (the
+    kernels would otherwise run past the allocation)."""
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: device buffers must be contiguous")
+    if t.element_size() != elem_bytes:
+        raise ValueError(f"{name}: elements of {t.element_size()} bytes, the library uses {elem_bytes}")
+    if t.numel() < min_elems:
+        raise ValueError(f"{name}: {t.numel()} elements, at least {min_elems} needed")
+
+
+def _ptr(t, name: str = "buffer", elem_bytes: Optional[int] = None, min_elems: int = 0) -> Optional[int]:
+    """Device pointer of a torch tensor (None stays None), after checking that it
+    lives on the GPU and (when elem_bytes is given) its element size and length."""
     if t is None:
         return None
-    if not t.is_contiguous():
-        raise ValueError("device buffers must be contiguous")
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{name}: the library takes GPU (HIP) tensors, got one on {getattr(t, 'device', '?')}")
+    if elem_bytes is None:
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: device buffers must be contiguous")
+    else:
+        check_buffer(t, name, elem_bytes, min_elems)
     return t.data_ptr()
+
+
+def _eb(count_type: int) -> int:
+    return 2 if count_type == SNP_COUNT_U16 else 4
 
 
 class _RunBuffers:
@@ -208,7 +234,8 @@ def _stream_ptr(stream):
 def snp_load(system, *, path: int = SNP_PATH_AUTO, stop_at_cap: bool = False, frontier_cap: int = 0,
              child_budget: int = 0, expand_max_count: int = -1, max_rows: int = 1 << 20,
              max_frontier: int = 0, chunk: int = 0, hash_mask: int = 0, profile: int = 0,
-             int8_max_k: int = 0, stream=None, M: Optional[np.ndarray] = None) -> Handle:
+             int8_max_k: int = 0, deterministic: bool = False, stream=None,
+             M: Optional[np.ndarray] = None) -> Handle:
     """snp_load.  ``system`` has m, rule_neuron/i/j/c/p, syn_src/dst and
     count_type ("i32" or "u16") attributes; ``stream`` is a torch.cuda.Stream
     (None: torch's current stream)."""
@@ -218,7 +245,8 @@ def snp_load(system, *, path: int = SNP_PATH_AUTO, stop_at_cap: bool = False, fr
     sp = _stream_ptr(stream)
     o = snp_options(int(path), int(bool(stop_at_cap)), int(frontier_cap), int(child_budget),
                     int(expand_max_count), int(max_rows), int(max_frontier), int(chunk),
-                    int(hash_mask) & ((1 << 64) - 1), int(profile), int(int8_max_k), sp or None)
+                    int(hash_mask) & ((1 << 64) - 1), int(profile), int(int8_max_k), int(bool(deterministic)),
+                    sp or None)
     out = ctypes.c_void_p()
     _check(lib().snp_load(ctypes.byref(d), ctypes.byref(o), ctypes.byref(out)), "snp_load")
     return Handle(out.value, arrs, int(system.m), ct)
@@ -233,7 +261,7 @@ def snp_row_bytes(h: Handle) -> int:
 
 
 def snp_reset(h: Handle, c0_dev):
-    _check(lib().snp_reset(h.ptr, _ptr(c0_dev)), "snp_reset")
+    _check(lib().snp_reset(h.ptr, _ptr(c0_dev, "c0", _eb(h.count_type), h.m)), "snp_reset")
 
 
 def snp_expand(h: Handle, frontier_dev, n: int, next_dev, next_capacity: int, parent_of_next=None,
@@ -241,8 +269,11 @@ def snp_expand(h: Handle, frontier_dev, n: int, next_dev, next_capacity: int, pa
     """Returns (n_next, stats dict)."""
     n_next = ctypes.c_int64(0)
     st = snp_expand_stats()
-    status = lib().snp_expand(h.ptr, _ptr(frontier_dev), int(n), _ptr(next_dev), int(next_capacity),
-                              ctypes.byref(n_next), _ptr(parent_of_next), _ptr(child_of_next), ctypes.byref(st))
+    eb, n, cap = _eb(h.count_type), int(n), int(next_capacity)
+    status = lib().snp_expand(h.ptr, _ptr(frontier_dev, "frontier", eb, n * h.m), n,
+                              _ptr(next_dev, "next", eb, cap * h.m), cap, ctypes.byref(n_next),
+                              _ptr(parent_of_next, "parent_of_next", 8, cap),
+                              _ptr(child_of_next, "child_of_next", 8, cap), ctypes.byref(st))
     if status != SNP_OK:
         err = SnpError(status, "snp_expand", lib().snp_last_error().decode())
         err.n_next = int(n_next.value)
@@ -254,9 +285,11 @@ def snp_run(h: Handle, c0_dev, max_depth: int, out_dev, out_capacity: int, max_l
             parent_of=None, child_of=None, with_stats: bool = True) -> dict:
     """Returns dict(n_configs, level_sizes, stop_reason, level_stats)."""
     rb = h.run_buffers(max_levels)
-    status = lib().snp_run(h.ptr, _ptr(c0_dev), int(max_depth), _ptr(out_dev), int(out_capacity), rb.r_configs,
-                           rb.p_sizes, int(max_levels), rb.r_levels, rb.r_stop, rb.p_stats if with_stats else None,
-                           _ptr(parent_of), _ptr(child_of))
+    eb, cap = _eb(h.count_type), int(out_capacity)
+    status = lib().snp_run(h.ptr, _ptr(c0_dev, "c0", eb, h.m), int(max_depth), _ptr(out_dev, "out", eb, cap * h.m),
+                           cap, rb.r_configs, rb.p_sizes, int(max_levels), rb.r_levels, rb.r_stop,
+                           rb.p_stats if with_stats else None, _ptr(parent_of, "parent_of", 8, cap),
+                           _ptr(child_of, "child_of", 8, cap))
     if status != SNP_OK:
         err = SnpError(status, "snp_run", lib().snp_last_error().decode())
         err.n_configs = int(rb.n_configs.value)
@@ -283,6 +316,7 @@ class BatchHandle:
         self._keep = keep
         self.n = n
         self.count_type = count_type
+        self.total = None  # elements of the packed rows, read on first use
 
     def close(self):
         if self.ptr:
@@ -330,11 +364,35 @@ def snp_batch_shape(b: BatchHandle):
 def snp_batch_run(b: BatchHandle, c0_dev, steps: int, final_dev, detect_repeats: bool = True) -> dict:
     """Returns dict of numpy arrays: halt_step, first_repeat, steps_done, digest."""
     n = b.n
+    if b.total is None:
+        b.total = int(snp_batch_offsets(b)[-1])
+    eb = _eb(b.count_type)
     halt = np.zeros(n, dtype=np.int32)
     rep = np.zeros(n, dtype=np.int32)
     done = np.zeros(n, dtype=np.int32)
     dig = np.zeros(n, dtype=np.uint64)
-    _check(lib().snp_batch_run(b.ptr, _ptr(c0_dev), int(steps), int(bool(detect_repeats)), _ptr(final_dev),
-                               halt.ctypes.data, rep.ctypes.data, done.ctypes.data, dig.ctypes.data),
+    _check(lib().snp_batch_run(b.ptr, _ptr(c0_dev, "c0", eb, b.total), int(steps), int(bool(detect_repeats)),
+                               _ptr(final_dev, "final", eb, b.total), halt.ctypes.data, rep.ctypes.data,
+                               done.ctypes.data, dig.ctypes.data),
            "snp_batch_run")
     return dict(halt_step=halt, first_repeat=rep, steps_done=done, digest=dig)
+
+
+def snp_run_batch(handles, c0_list, steps: int, final_list) -> dict:
+    """snp_run_batch over handles from snp_load: one row per system in c0_list
+    and final_list (torch GPU tensors).  Returns dict of numpy arrays:
+    halt_step, first_repeat, digest."""
+    n = len(handles)
+    if len(c0_list) != n or len(final_list) != n:
+        raise ValueError("snp_run_batch: one c0 and one final buffer per handle")
+    hp = (ctypes.c_void_p * n)(*[h.ptr.value for h in handles])
+    cp = (ctypes.c_void_p * n)(*[_ptr(c, f"c0[{k}]", _eb(h.count_type), h.m)
+                                 for k, (h, c) in enumerate(zip(handles, c0_list))])
+    fp = (ctypes.c_void_p * n)(*[_ptr(f, f"final[{k}]", _eb(h.count_type), h.m)
+                                 for k, (h, f) in enumerate(zip(handles, final_list))])
+    halt = np.zeros(n, dtype=np.int32)
+    rep = np.zeros(n, dtype=np.int32)
+    dig = np.zeros(n, dtype=np.uint64)
+    _check(lib().snp_run_batch(hp, n, cp, int(steps), fp, halt.ctypes.data, rep.ctypes.data, dig.ctypes.data),
+           "snp_run_batch")
+    return dict(halt_step=halt, first_repeat=rep, digest=dig)

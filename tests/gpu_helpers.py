@@ -77,3 +77,7 @@ def assert_same_bfs(gres, ores, check_stats=True):
         L = len(ores.level_sizes)
         assert [s["enumerated"] for s in st[:L]] == ores.enumerated.tolist()
         assert [s["halting_parents"] for s in st[:L]] == ores.halting.tolist()
+        # children that repeat an earlier configuration: enumerated minus new
+        new = [int(ores.level_sizes[k + 1]) if k + 1 < L else 0 for k in range(L)]
+        dup = [int(e) - n if int(e) else 0 for e, n in zip(ores.enumerated.tolist(), new)]
+        assert [s["duplicates"] for s in st[:L]] == dup

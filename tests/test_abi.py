@@ -118,3 +118,113 @@ def test_stats_record_layout():
         for i, (name, ct) in enumerate(snp.snp_expand_stats._fields_):
             setattr(stats[k], name, (k + 1) * 1000 + i - (7 if ct is ctypes.c_int32 else 0))
     assert snp._stats_list(stats, 3) == [stats[k].as_dict() for k in range(3)]
+
+
+def _c_layout(struct, fields):
+    """Size and field offsets of a struct of include/snp.h, as the C compiler lays it out."""
+    import subprocess
+    import tempfile
+
+    lines = [f'printf("%zu\\n", sizeof({struct}));'] + [f'printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    src = "#include <stdio.h>\n#include <stddef.h>\n#include \"snp.h\"\nint main(void){" + "".join(lines) + "return 0;}\n"
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        out = subprocess.check_output([exe], text=True).split()
+    return [int(x) for x in out]
+
+
+@pytest.mark.parametrize("name", ["snp_desc", "snp_options", "snp_expand_stats"])
+def test_binding_struct_layout_matches_header(name):
+    """The ctypes structures of the binding have the C header's size and offsets."""
+    from paper_1104_1824_amd import snp
+
+    cls = getattr(snp, name)
+    fields = [f for f, _ in cls._fields_ if not f.endswith("_")]
+    got = _c_layout(name, fields)
+    assert got[0] == ctypes_sizeof(cls)
+    assert got[1:] == [getattr(cls, f).offset for f in fields]
+
+
+def ctypes_sizeof(cls):
+    import ctypes
+
+    return ctypes.sizeof(cls)
+
+
+def test_load_rejects_oversized_visited_set():
+    """max_rows + 2 * chunk above 2^31 would need more than 2^32 visited-set slots
+    (32-bit slot indices): rejected before any allocation."""
+    st, msg = _load_status(synth.paper_example(), max_rows=(1 << 31) - 10, chunk=1 << 20)
+    assert st == 1 and "2^31" in msg
+    st, msg = _load_status(synth.paper_example(), max_rows=(1 << 30) + 1, chunk=1 << 29)
+    assert st == 1 and "2^31" in msg
+
+
+class _FakeTensor:
+    """Stands in for a torch tensor in the binding's host-side checks."""
+
+    def __init__(self, numel, esize, contiguous=True, is_cuda=True):
+        self._n, self._e, self._c, self.is_cuda = numel, esize, contiguous, is_cuda
+        self.device = "cuda:0" if is_cuda else "cpu"
+
+    def numel(self):
+        return self._n
+
+    def element_size(self):
+        return self._e
+
+    def is_contiguous(self):
+        return self._c
+
+    def data_ptr(self):
+        return 4096
+
+
+def test_binding_rejects_bad_buffers():
+    """The binding refuses, before calling the library, buffers the kernels would
+    overrun or misread: host tensors, wrong element size, too few elements,
+    non-contiguous views."""
+    from paper_1104_1824_amd import snp
+
+    assert snp._ptr(None) is None
+    assert snp._ptr(_FakeTensor(640, 4), "out", 4, 640) == 4096
+    with pytest.raises(ValueError, match="GPU"):
+        snp._ptr(_FakeTensor(640, 4, is_cuda=False), "out", 4, 640)
+    with pytest.raises(ValueError, match="bytes"):
+        snp._ptr(_FakeTensor(640, 2), "out", 4, 640)
+    with pytest.raises(ValueError, match="at least 641"):
+        snp._ptr(_FakeTensor(640, 4), "out", 4, 641)
+    with pytest.raises(ValueError, match="contiguous"):
+        snp._ptr(_FakeTensor(640, 4, contiguous=False), "out", 4, 10)
+    import torch
+
+    with pytest.raises(ValueError, match="GPU"):
+        snp._ptr(torch.zeros(10, dtype=torch.int32), "c0", 4, 3)
+    snp.check_buffer(torch.zeros(12, dtype=torch.int64), "parent_of", 8, 12)
+    with pytest.raises(ValueError):
+        snp.check_buffer(torch.zeros(12, dtype=torch.int32), "parent_of", 8, 12)
+
+
+def test_binding_checks_before_the_call(monkeypatch):
+    """snp_run with a too-small out buffer raises in the binding, so the library
+    (here a stub that would record the call) is never reached."""
+    from paper_1104_1824_amd import snp
+
+    calls = []
+
+    class StubLib:
+        def __getattr__(self, name):
+            return lambda *a: calls.append(name) or 0
+
+    monkeypatch.setattr(snp, "_lib", StubLib())
+    h = snp.Handle.__new__(snp.Handle)
+    h.ptr, h.m, h.count_type, h._run, h._keep = None, 64, snp.SNP_COUNT_I32, None, []
+    with pytest.raises(ValueError, match="out"):
+        snp.snp_run(h, _FakeTensor(64, 4), 3, _FakeTensor(64 * 99, 4), 100)
+    with pytest.raises(ValueError, match="parent_of"):
+        snp.snp_run(h, _FakeTensor(64, 4), 3, _FakeTensor(64 * 100, 4), 100, parent_of=_FakeTensor(99, 8))
+    with pytest.raises(ValueError, match="frontier"):
+        snp.snp_expand(h, _FakeTensor(64 * 4, 4), 5, _FakeTensor(64 * 10, 4), 10)
+    assert calls == []

@@ -86,20 +86,62 @@ def test_batch_uneven_recipe_sample(gpu, oracle_mod):
     check_against_oracle(oracle_mod, systems, 1500, run_batch(systems, 1500))
 
 
-def test_batch_full_recipe_sampled(gpu, oracle_mod):
-    """The full batched workload (256 systems, 10k steps) in one launch; every
-    fourth-largest... a sample of systems checked against the oracle."""
+def golden_batch():
+    from tests.golden import make_golden
+
+    head, data = make_golden.read_table(make_golden.BATCH_FILE)
+    assert int(head["steps"]) == 10000 and len(data) == 256
+    return make_golden, data
+
+
+def test_batch_full_recipe_golden(gpu):
+    """The full batched workload (256 systems, 10k steps) in one launch, as the
+    bench runs it; every system against the oracle-written golden lines."""
+    make_golden, data = golden_batch()
     systems = synth.batched_systems(0, 256)
     note("batch of 256 uneven systems, 10000 steps")
     res = run_batch(systems, 10000)
-    sample = [0, 1, 2, 37, 101, 255]
-    sub = {k: systems[k] for k in sample}
-    for k, s in sub.items():
-        d = oracle_mod.deterministic(s, 10000)
-        assert res["final"][k].tolist() == d.final.tolist()
-        assert int(res["digest"][k]) == d.digest
-        assert int(res["first_repeat"][k]) == d.first_repeat
-        assert int(res["halt_step"][k]) == d.halt_step
+    for k, line in enumerate(data):
+        seed, m, fin, halt, rep, done, dig = line
+        assert int(seed) == k and int(m) == systems[k].m
+        got = make_golden.sha(np.ascontiguousarray(res["final"][k].astype("<i4")).tobytes())
+        assert got == fin, k
+        assert int(res["halt_step"][k]) == int(halt), k
+        assert int(res["first_repeat"][k]) == int(rep), k
+        assert int(res["steps_done"][k]) == int(done), k
+        assert int(res["digest"][k]) == int(dig), k
+
+
+def test_run_batch_entry_point(gpu, oracle_mod):
+    """snp_run_batch over handles from snp_load (one row buffer per system)
+    equals the oracle, on a first list, a second call with the same list (the
+    kept batch), and a different list."""
+    import torch
+
+    from tests.gpu_helpers import to_device_rows
+
+    def go(systems, steps):
+        hs = [snp.snp_load(s, max_rows=16) for s in systems]
+        try:
+            c0 = [to_device_rows(s, s.c0) for s in systems]
+            fin = [torch.full((s.m,), -1, dtype=torch.int32, device="cuda") for s in systems]
+            for rep in range(2):
+                note(f"snp_run_batch, {len(systems)} systems, {steps} steps, call {rep}")
+                res = snp.snp_run_batch(hs, c0, steps, fin)
+                for k, s in enumerate(systems):
+                    d = oracle_mod.deterministic(s, steps)
+                    assert fin[k].cpu().numpy().tolist() == d.final.tolist(), (rep, k)
+                    assert int(res["halt_step"][k]) == d.halt_step
+                    assert int(res["first_repeat"][k]) == d.first_repeat
+                    assert int(res["digest"][k]) == d.digest
+                for f in fin:
+                    f.fill_(-1)
+        finally:
+            for h in hs:
+                h.close()
+
+    go(synth.batched_systems(7, 6) + [ring(64), path(30), synth.paper_example()], 500)
+    go([synth.config_system(1, sd) for sd in range(12)], 300)
 
 
 def test_batch_uint16_and_overflow(gpu, oracle_mod):

@@ -133,36 +133,71 @@ def check_walk(oracle_mod, system, res, rows, par, chi, n_samples, seed):
             assert recorded(oracle_mod.child_at(system, prow, t - 1)), f"child ({p}, {t - 1}) missing"
 
 
-def test_dense_full_size(gpu, oracle_mod):
-    import torch
+def compare_with_golden_walk(res, rows, par, chi, path_name):
+    """Every 1024-row block of the walk (rows, and parent/child-index pairs)
+    against the oracle-written digests of tests/golden/dense_m512_s0_walk.txt."""
+    from tests.golden import make_golden
 
+    head, data = make_golden.read_table(make_golden.DENSE_FILE)
+    assert res["level_sizes"].tolist() == [int(x) for x in head["levels"].split()]
+    assert res["stop_reason"] == int(head["stop_reason"])
+    st = res["level_stats"]
+    L = len(res["level_sizes"])
+    assert [x["enumerated"] for x in st[:L]] == [int(x) for x in head["enumerated"].split()]
+    assert [x["halting_parents"] for x in st[:L]] == [int(x) for x in head["halting"].split()]
+    n = rows.shape[0]
+    blk = make_golden.BLOCK
+    assert len(data) == (n + blk - 1) // blk
+    step = 64 * blk  # blocks fetched from the device at a time
+    bad = []
+    for a in range(0, n, step):
+        b = min(n, a + step)
+        got = make_golden.block_digests(from_device_rows(SYS_DENSE(), rows[a:b]), par[a:b].cpu().numpy(),
+                                        chi[a:b].cpu().numpy())
+        for k, (dr, dp) in enumerate(got):
+            line = data[a // blk + k]
+            if (dr, dp) != (line[1], line[2]):
+                bad.append(int(line[0]))
+    assert not bad, f"{path_name}: {len(bad)} blocks differ from the oracle's digests, first {bad[:5]}"
+
+
+def SYS_DENSE():
+    return synth.config_system(3, 0)
+
+
+@pytest.mark.parametrize("path", [snp.SNP_PATH_INT8, snp.SNP_PATH_SPARSE, snp.SNP_PATH_AUTO])
+def test_dense_full_size_golden(gpu, path):
+    """The dense workload at full size (depth 3, cap 1e6, chunks of 2^20 as the
+    bench runs it), every row and provenance pair checked block by block against
+    the oracle's digests."""
+    s = SYS_DENSE()
+    note(f"full size: dense m=512, cap 1e6, depth 3, path {path}")
+    res, rows, par, chi = run_full(s, path, 1000000, 3, 3000001, chunk=1 << 20)
+    note(f"full size: dense, path {path}: block digests")
+    compare_with_golden_walk(res, rows, par, chi, f"path {path}")
+    if path == snp.SNP_PATH_AUTO:
+        assert all(x["path_used"] == snp.SNP_PATH_INT8 for x in res["level_stats"] if x["chunks"])
+
+
+def test_dense_full_size(gpu, oracle_mod):
     s = synth.config_system(3, 0)
     note("full size: dense m=512, cap 1e6, depth 3, int8")
     res, rows, par, chi = run_full(s, snp.SNP_PATH_INT8, 1000000, 3, 3000001)
     assert res["level_sizes"].tolist() == [1, 1000000, 1000000, 1000000]
     assert res["stop_reason"] == snp.SNP_STOP_DEPTH
     note("full size: dense, sampled checks")
-    check_walk(oracle_mod, s, res, rows, par, chi, n_samples=300, seed=1)
-    note("full size: dense, sparse form on the same input")
-    res2, rows2, par2, chi2 = run_full(s, snp.SNP_PATH_SPARSE, 1000000, 3, 3000001)
-    assert res2["level_sizes"].tolist() == res["level_sizes"].tolist()
-    assert torch.equal(rows, rows2) and torch.equal(par, par2) and torch.equal(chi, chi2)
-    del rows2, par2, chi2
-    note("full size: dense, level 1 against the oracle")
-    want = oracle_mod.bfs(s, max_depth=1, frontier_cap=1000000)
-    assert want.level_sizes.tolist() == [1, 1000000]
-    got = from_device_rows(s, rows[:1000001])
-    assert np.array_equal(got, want.rows)
-    assert par[:1000001].cpu().numpy().tolist() == want.parent.tolist()
-    assert chi[:1000001].cpu().numpy().tolist() == want.tindex.tolist()
+    check_walk(oracle_mod, s, res, rows, par, chi, n_samples=100, seed=1)
 
 
 def test_large_full_size(gpu, oracle_mod):
+    """The large workload exactly as the bench runs it: depth 3, cap 4e6 per
+    level, chunks of 2^22 children, automatic path."""
     s = synth.config_system(5, 0)
-    note("full size: large m=4096 uint16, cap 4e6, depth 2, automatic path")
-    res, rows, par, chi = run_full(s, snp.SNP_PATH_AUTO, 4000000, 2, 8000001, chunk=1 << 19)
-    assert res["level_sizes"].tolist() == [1, 4000000, 4000000]
+    note("full size: large m=4096 uint16, cap 4e6, depth 3, chunk 2^22, automatic path")
+    res, rows, par, chi = run_full(s, snp.SNP_PATH_AUTO, 4000000, 3, 12000001, chunk=1 << 22)
+    assert res["level_sizes"].tolist() == [1, 4000000, 4000000, 4000000]
+    assert res["stop_reason"] == snp.SNP_STOP_DEPTH
     note("full size: large, sampled checks")
     # each sample costs the oracle an enumeration of up to millions of spiking
     # vectors (about 0.6 s per sample on one host core)
-    check_walk(oracle_mod, s, res, rows, par, chi, n_samples=80, seed=2)
+    check_walk(oracle_mod, s, res, rows, par, chi, n_samples=60, seed=2)

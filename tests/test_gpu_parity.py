@@ -64,6 +64,47 @@ def test_plain_sparse_full(gpu, oracle_mod, seed):
     assert_same_bfs(g, oracle_mod.bfs(s, max_depth=1000, frontier_cap=100000, stop_at_cap=True))
 
 
+@pytest.mark.parametrize("seed", range(5))
+def test_plain_sparse_bench_options(gpu, oracle_mod, seed):
+    """The plain-sparse workload with exactly the options the bench times
+    (sparse path, chunks of 2^17, expansion timing events on)."""
+    note(f"plain sparse seed {seed}, bench options")
+    s = synth.config_system(2, seed)
+    g = gpu_bfs(s, max_depth=1000, frontier_cap=100000, stop_at_cap=True, out_capacity=200000, max_rows=200000,
+                chunk=1 << 17, profile=1)
+    assert_same_bfs(g, oracle_mod.bfs(s, max_depth=1000, frontier_cap=100000, stop_at_cap=True))
+
+
+def test_auto_path_choice(gpu, oracle_mod):
+    """AUTO takes the one-neuron-per-lane sparse form where it applies (m <= 64,
+    in-degree <= 16: the tiny and plain-sparse workloads) and the int8 matrix
+    cores on the dense workload."""
+    for cid, seed, kw, want in ((1, 5, dict(max_depth=8), SPARSE),
+                                (2, 0, dict(max_depth=1000, frontier_cap=20000, stop_at_cap=True), SPARSE),
+                                (3, 0, dict(max_depth=2, frontier_cap=2000), snp.SNP_PATH_INT8)):
+        note(f"auto path choice: recipe {cid} seed {seed}")
+        s = synth.config_system(cid, seed)
+        g = gpu_bfs(s, out_capacity=50000, path=snp.SNP_PATH_AUTO, **kw)
+        assert_same_bfs(g, oracle_mod.bfs(s, **kw))
+        assert all(x["path_used"] == want for x in g["level_stats"] if x["chunks"]), cid
+
+
+@pytest.mark.parametrize("path", [snp.SNP_PATH_SPARSE, snp.SNP_PATH_INT8])
+def test_deterministic_walk(gpu, oracle_mod, path):
+    """deterministic: one child per configuration (the first spiking vector),
+    i.e. the single-branch trajectory up to its first repeat or halting."""
+    cases = [(synth.paper_example(), dict(max_depth=40)), (synth.paper_example(True), dict()),
+             (synth.paper_example(True), dict(c0=[0, 1, 1]))]
+    cases += [(synth.config_system(1, sd), dict(max_depth=60)) for sd in range(0, 40, 3)]
+    cases += [(synth.config_system(2, 1), dict(max_depth=200)), (synth.config_system(3, 0), dict(max_depth=30))]
+    for s, kw in cases:
+        note(f"deterministic walk {s.name} {kw} path {path}")
+        g = gpu_bfs(s, out_capacity=512, deterministic=True, path=path, **kw)
+        want = oracle_mod.bfs(s, deterministic=True, **kw)
+        assert_same_bfs(g, want)
+        assert set(g["level_sizes"].tolist()) == {1}
+
+
 def test_chunk_invariance(gpu, oracle_mod):
     s = synth.config_system(2, 1)
     want = oracle_mod.bfs(s, max_depth=1000, frontier_cap=20000, stop_at_cap=True)
@@ -93,8 +134,11 @@ def test_hash_collisions(gpu, oracle_mod, seed):
     must keep the result exact."""
     note(f"hash mask 0xF, tiny seed {seed}")
     s = synth.config_system(1, seed)
-    assert_same_bfs(gpu_bfs(s, max_depth=8, out_capacity=4096, chunk=4096, hash_mask=0xF),
-                    oracle_mod.bfs(s, max_depth=8))
+    g = gpu_bfs(s, max_depth=8, out_capacity=4096, chunk=4096, hash_mask=0xF)
+    assert_same_bfs(g, oracle_mod.bfs(s, max_depth=8))
+    # with a 4-bit hash every tag is 0: rows that differ meet in the probes
+    if g["n_configs"] > 2:
+        assert sum(x["collisions"] for x in g["level_stats"]) > 0
     note(f"hash mask 0xF00000000000000F, plain seed {seed % 5}")
     s2 = synth.config_system(2, seed % 5)
     assert_same_bfs(gpu_bfs(s2, max_depth=3, frontier_cap=400, out_capacity=4096,

@@ -388,3 +388,100 @@ def test_deterministic_digest_structure(oracle_mod):
     want1 = (oracle_mod.mix64(oracle_mod.config_hash([0, 1, 1]))
              + oracle_mod.mix64(oracle_mod.config_hash([1, 0, 1]) + GAMMA)) % (1 << 64)
     assert d1.digest == want1
+
+
+# --------------------------------------------------------------------------
+# child_at: the child with index t equals row t of the full enumeration, for
+# every t < Psi, on every configuration a walk reaches; index Psi is refused.
+# --------------------------------------------------------------------------
+def _child_at_cases():
+    from tests.test_gpu_parity import twin_system
+
+    cases = [("paper", EX, 12), ("textbook", EX_TB, 12), ("twins", twin_system(), 6)]
+    cases += [(f"tiny{s}", synth.config_system(1, s), 6) for s in range(20)]
+    return cases
+
+
+@pytest.mark.parametrize("name,system,depth", _child_at_cases(), ids=lambda x: x if isinstance(x, str) else "")
+def test_child_at_equals_enumeration(oracle_mod, name, system, depth):
+    walk = oracle_mod.bfs(system, max_depth=depth, expand_max_count=9 if name == "paper" else -1)
+    for C in walk.rows[:60]:
+        rows, _, psi = oracle_mod.children(system, C, max_out=4096)
+        assert psi <= 4096
+        for t in range(psi):
+            assert oracle_mod.child_at(system, C, t).tolist() == rows[t].tolist(), (name, C.tolist(), t)
+        with pytest.raises(oracle_mod.OracleError):
+            oracle_mod.child_at(system, C, psi)
+
+
+def test_child_at_bruteforce_order(oracle_mod):
+    """child_at against the brute-force order of the valid 0/1 spiking vectors
+    (rule 1 most significant) with a dense C + S.M, on random tiny systems."""
+    for seed in range(10):
+        s = synth.config_system(1, seed)
+        M = oracle_mod.matrix_dense(s)
+        C = np.asarray(s.c0, dtype=np.int64)
+        valid = [v for v in _valid_vectors_bruteforce(s, C)]
+        for t, v in enumerate(valid):
+            want = C + np.asarray(v, dtype=np.int64) @ M
+            assert oracle_mod.child_at(s, C, t).tolist() == want.tolist()
+
+
+def _valid_vectors_bruteforce(s, C):
+    r = len(s.rule_i)
+    for bits in range(2 ** r - 1, -1, -1):
+        v = [(bits >> (r - 1 - k)) & 1 for k in range(r)]
+        ok = True
+        for n in range(s.m):
+            ks = [k for k in range(r) if s.rule_neuron[k] == n]
+            app = [k for k in ks if re.fullmatch(f"a{{{s.rule_i[k]}}}(?:a{{{s.rule_j[k]}}})*", "a" * int(C[n]))
+                   and C[n] >= s.rule_c[k]]
+            fired = [k for k in ks if v[k]]
+            if any(k not in app for k in fired) or len(fired) != (1 if app else 0):
+                ok = False
+                break
+        if ok:
+            yield v
+
+
+# --------------------------------------------------------------------------
+# Deterministic walk: the breadth-first walk that keeps only the first spiking
+# vector of every configuration is the single-branch trajectory, cut at its
+# first repeat (empty frontier) or at its halting configuration.
+# --------------------------------------------------------------------------
+def _trajectory(oracle_mod, s, steps, c0=None):
+    rows = [np.asarray(s.c0 if c0 is None else c0, dtype=np.int64)]
+    for k in range(1, steps + 1):
+        rows.append(oracle_mod.deterministic(s, k, c0=c0).final)
+    return rows
+
+
+def test_deterministic_walk_closed_forms(oracle_mod):
+    w = oracle_mod.bfs(EX, max_depth=30, deterministic=True)     # C_k = (2, 1, 1 + k)
+    assert w.level_sizes.tolist() == [1] * 31 and w.stop_reason == oracle_mod.STOP_DEPTH
+    assert [r.tolist() for r in w.rows] == [[2, 1, 1 + k] for k in range(31)]
+    assert w.tindex.tolist() == [-1] + [0] * 30
+    w = oracle_mod.bfs(EX_TB, deterministic=True)                 # (2,1,1) -> (2,1,2), a fixed point
+    assert [r.tolist() for r in w.rows] == [[2, 1, 1], [2, 1, 2]]
+    assert w.stop_reason == oracle_mod.STOP_EMPTY_FRONTIER
+    w = oracle_mod.bfs(EX_TB, c0=[0, 1, 1], deterministic=True)   # 011 -> 101 -> 100, halting
+    assert [r.tolist() for r in w.rows] == [[0, 1, 1], [1, 0, 1], [1, 0, 0]]
+    assert w.stop_reason == oracle_mod.STOP_ALL_HALTING
+
+
+@pytest.mark.parametrize("seed", range(0, 40, 3))
+def test_deterministic_walk_is_trajectory(oracle_mod, seed):
+    s = synth.config_system(1, seed)
+    d = oracle_mod.deterministic(s, 60)
+    w = oracle_mod.bfs(s, deterministic=True, max_depth=60)
+    traj = _trajectory(oracle_mod, s, d.steps_done)
+    if d.first_repeat >= 0:
+        n = d.first_repeat
+        assert w.stop_reason == oracle_mod.STOP_EMPTY_FRONTIER
+    elif d.halt_step >= 0:
+        n = d.halt_step + 1
+        assert w.stop_reason == oracle_mod.STOP_ALL_HALTING
+    else:
+        n = 61
+        assert w.stop_reason == oracle_mod.STOP_DEPTH
+    assert [r.tolist() for r in w.rows] == [r.tolist() for r in traj[:n]]
