@@ -136,14 +136,14 @@ def test_hash_collisions(gpu, oracle_mod, seed):
     s = synth.config_system(1, seed)
     g = gpu_bfs(s, max_depth=8, out_capacity=4096, chunk=4096, hash_mask=0xF)
     assert_same_bfs(g, oracle_mod.bfs(s, max_depth=8))
-    # with a 4-bit hash every tag is 0: rows that differ meet in the probes
-    if g["n_configs"] > 2:
-        assert sum(x["collisions"] for x in g["level_stats"]) > 0
     note(f"hash mask 0xF00000000000000F, plain seed {seed % 5}")
     s2 = synth.config_system(2, seed % 5)
-    assert_same_bfs(gpu_bfs(s2, max_depth=3, frontier_cap=400, out_capacity=4096,
-                            hash_mask=0xF00000000000000F),
-                    oracle_mod.bfs(s2, max_depth=3, frontier_cap=400))
+    g2 = gpu_bfs(s2, max_depth=3, frontier_cap=400, out_capacity=4096, hash_mask=0xF00000000000000F)
+    assert_same_bfs(g2, oracle_mod.bfs(s2, max_depth=3, frontier_cap=400))
+    # 16 home slots and 16 tags for about a thousand rows: probes meet entries
+    # with their tag whose rows differ (a tiny system may have too few rows for
+    # that, so the count is checked here)
+    assert sum(x["collisions"] for x in g2["level_stats"]) > 0
 
 
 def test_dense_recipe_small_cap(gpu, oracle_mod):
