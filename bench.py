@@ -40,7 +40,6 @@ ENTRY_BYTES = 16             # visited-set entry written per new configuration
 # bytes per child of the one-neuron-per-lane expansion besides its row: key 8,
 # parent 4, child index 8, probe slot 4, visited-set entry 8
 LANE_CHILD_EXTRA = 32
-TWIN_CHILD_BYTES = 12        # a twin child: parent 4 and child index 8 only
 
 DENSE_WORKLOAD = ("dense_int8: seeded SN P system m=512, 3 rules/neuron (r=1536), E=a^i(a^j)* i in [1,4] "
                   "j in [0,3], p in [0,4] (M entries in [-4,4], int8), out-degree 64, C0 in [0,4], int32 "
@@ -118,17 +117,16 @@ def totals(results, key):
     return sum(st[key] for r in results for st in r["level_stats"])
 
 
-def hbm_roofline(results, kernel, bytes_per_new, rb, twins_written=False):
+def hbm_roofline(results, kernel, bytes_per_new, rb, per_child=False):
     """Roofline of the expansion kernel: algorithmic bytes over its device time
     (HIP events around each launch).  Algorithmic bytes = every new configuration's
-    row plus its visited-set entry (bytes_per_new); with twins_written, the
-    one-neuron-per-lane form's own per-child bytes instead (rows of every child
-    computed, plus records)."""
+    row plus its visited-set entry (bytes_per_new); with per_child, the
+    one-neuron-per-lane form's own per-child bytes instead (the row of every
+    child computed, plus its records)."""
     ns = totals(results, "ns_expand")
     launches = totals(results, "chunks")
-    if twins_written:
-        children, twins = totals(results, "expanded"), totals(results, "twins")
-        moved = (children - twins) * (rb + LANE_CHILD_EXTRA) + twins * TWIN_CHILD_BYTES
+    if per_child:
+        moved = totals(results, "expanded") * (rb + LANE_CHILD_EXTRA)
     else:
         moved = totals(results, "new_configs") * bytes_per_new
     achieved = moved / max(1, ns)  # bytes per ns = GB/s
@@ -251,7 +249,7 @@ def plain_line(steps=50, warmup=5, cpu=None):
     new = results[-1]["n_configs"] - 1
     line = dict(workload=PLAIN_WORKLOAD, value=round(steps * new / dt, 1), unit="configs/s",
                 ms_per_step=round(dt / steps * 1e3, 4), levels=results[-1]["level_sizes"].tolist(), dtype="int32")
-    line.update(hbm_roofline(results, "k_expand_lane", None, s.m * 4, twins_written=True))
+    line.update(hbm_roofline(results, "k_expand_lane", None, s.m * 4, per_child=True))
     line["cpu_baseline"] = cpu
     return line
 

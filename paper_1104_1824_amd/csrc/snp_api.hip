@@ -96,6 +96,7 @@ struct snp_system {
 
     // per-frontier and per-chunk buffers
     u64 *d_psi = nullptr, *d_off = nullptr, *d_sc_sums = nullptr, *d_sc_pre = nullptr;
+    u64* d_psif = nullptr;  // per parent: all children (every valid spiking vector)
     uint8_t* d_hflag = nullptr;  // per parent: 1 when no rule applies
     void* d_stage = nullptr;
     u64* d_hash = nullptr;
@@ -109,7 +110,8 @@ struct snp_system {
     snp::DevCounters* d_ring = nullptr;
     snp::DevCounters* d_ctr = nullptr;  // slot of the current pass
     long long pass = 0;
-    u64* d_T = nullptr;                 // children of the examined frontier prefix (device)
+    u64* d_T = nullptr;                 // canonical children of the examined frontier prefix (device)
+    u64* d_Tend = nullptr;              // the chunks' end under a child budget (device)
     snp::DevCounters* h_ctr = nullptr;  // the pass read last
     bool start_pending = false;         // the walk start's checks are not read yet
     bool slot_ready = false;            // the current slot was set by the walk start: reuse it
@@ -129,7 +131,7 @@ struct snp_system {
     ~snp_system() {
         void* ptrs[] = {d_nrule_ptr, d_rules, d_in_ptr, d_in_src, d_in_lane, d_M8, d_R, d_hM, d_table, d_row_slot, d_psi, d_off,
                         d_sc_sums, d_sc_pre, d_stage, d_hash, d_cpar, d_ct, d_slot, d_flag, d_pos,
-                        d_fsums, d_fpre, d_ring, d_store, d_cand, d_hflag, d_T};
+                        d_fsums, d_fpre, d_ring, d_store, d_cand, d_hflag, d_T, d_psif, d_Tend};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         if (h_ctr) (void)hipHostFree(h_ctr);
@@ -343,8 +345,8 @@ snp_status start_walk(snp_system* S, const void* c0_dev, void* arena, bool wait,
     if ((st = clear_counters(S))) return st;  // the slot the first pass will use
     HIPCHK(snp::launch_start_walk(S->elem_bytes, S->m, S->d_R, S->d_table, S->slots - 1, c0_dev, arena, S->count_max,
                                   S->opt.hash_mask ? S->opt.hash_mask : ~0ULL, S->d_row_slot, S->d_ctr, par0,
-                                  chi0, S->dsys, S->opt.expand_max_count, psi_c0 ? S->d_psi : nullptr, S->d_hflag,
-                                  S->d_off, S->d_T, S->stream));
+                                  chi0, S->dsys, S->opt.expand_max_count, psi_c0 ? S->d_psi : nullptr, S->d_psif,
+                                  S->d_hflag, S->d_off, S->d_T, S->stream));
     S->slot_ready = true;
     S->tombs = 0;
     S->start_pending = true;
@@ -378,7 +380,21 @@ snp_status rollback_level(snp_system* S, long long first, long long count) {
     return SNP_OK;
 }
 
+// Joins a children count split at bit 31 (DevCounters::psif_lo / psif_hi),
+// saturated at 2^62.
+u64 join_full(u64 lo, u64 hi) {
+    if (hi >= (1ULL << 31)) return snp::kPsiSat;
+    const u64 v = (hi << 31) + lo;
+    return v >= snp::kPsiSat ? snp::kPsiSat : v;
+}
+
+u64 sat_add_host(u64 a, u64 b) { return std::min<u64>(snp::kPsiSat, a + b); }
+
 // One BFS level: children of io.frontier, deduplicated, committed in order.
+// Only canonical children are computed (a child firing the later of two twin
+// rules repeats an earlier child of the same parent, so it is never a first
+// occurrence); they are numbered level-wide in child order, and chunks cover
+// ranges of that numbering.
 snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out, long long* count_out) {
     snp_expand_stats stt{};
     *count_out = 0;
@@ -403,11 +419,17 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
     // frontier, only as far as the chunks need children: a level stopped by
     // its cap usually reaches a small fraction of its parents.  An extension of
     // the prefix runs in the same device pass as the chunk that needs it; the
-    // chunk kernels read the prefix's child count on the device and stop there,
-    // so a pass costs one host synchronisation.
+    // chunk kernels read the prefix's canonical child count on the device and
+    // stop there, so a pass costs one host synchronisation.
     long long P = 0;
-    u64 T = 0;                  // children of parents [0, P) (saturated), known after each pass
+    u64 T = 0;                  // canonical children of parents [0, P) (saturated), known after each pass
+    u64 Tf = 0;                 // all children of parents [0, P) (saturated)
+    u64 Tend = 0;               // canonical children the chunks may take: T, or the budget's clip
     long long halting_all = 0;  // halting parents in [0, P)
+    const bool has_budget = S->opt.child_budget > 0;
+    const u64 budget = has_budget ? (u64)S->opt.child_budget : ~0ULL;
+    long long bud_par = 0;      // parent of the budget's last child, + 1
+    u64* d_end = has_budget ? S->d_Tend : S->d_T;
     // The first extension of a level covers 4096 parents, or fewer (not under
     // 1024) when the last level's children per parent say that enough for the
     // first chunk lie in fewer; later ones double the prefix.
@@ -421,54 +443,54 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         const char* f = (const char*)io.frontier + P * rb;
         if (snp::psi_scan_fits(S->dsys, P1 - P)) {  // a few small parents: one launch
             HIPCHK(snp::launch_psi_scan_small(S->elem_bytes, S->dsys, f, P1 - P, S->opt.expand_max_count,
-                                              S->d_psi + P, S->d_hflag + P, S->d_off + P,
+                                              S->d_psi + P, S->d_psif + P, S->d_hflag + P, S->d_off + P,
                                               P == 0 ? nullptr : S->d_T, S->d_T, S->d_ctr, S->stream));
         } else {
             HIPCHK(snp::launch_psi(S->elem_bytes, S->dsys, f, P1 - P, S->opt.expand_max_count, S->d_psi + P,
-                                   S->d_hflag + P, S->d_ctr, S->stream));
+                                   S->d_psif + P, S->d_hflag + P, S->d_ctr, S->stream));
             HIPCHK(snp::launch_scan_u64(S->d_psi + P, S->d_off + P, P1 - P, S->d_sc_sums, S->d_sc_pre, S->d_T,
                                         P == 0 ? nullptr : S->d_T, &S->d_ctr->psi_total, S->stream));
         }
+        if (has_budget)
+            HIPCHK(snp::launch_budget_clip(S->elem_bytes, S->dsys, io.frontier, P1, S->d_psif, S->d_off, S->d_T,
+                                           budget, S->d_Tend, S->d_ctr, S->stream));
         P = P1;
         return SNP_OK;
     };
-    const u64 budget = S->opt.child_budget > 0 ? (u64)S->opt.child_budget : ~0ULL;
+    // after an extension pass: the prefix's totals
+    auto take_extension = [&](const snp::DevCounters& c) {
+        T = c.psi_total;
+        Tf = sat_add_host(Tf, join_full(c.psif_lo, c.psif_hi));
+        halting_all += (long long)c.halting;
+        Tend = has_budget ? c.tend : T;
+        if (has_budget && c.bud_par) bud_par = (long long)c.bud_par;
+    };
 
     const long long cap_limit = std::min(io.limit_cap, io.arena_cap - io.level_base);
     const long long limit = std::min(io.limit_sem, cap_limit);
     const bool sem_binds = io.limit_sem <= cap_limit;
     long long count = 0;
-    u64 G = 0;
-    u64 enumerated = 0;
+    u64 G = 0;                 // canonical children taken by the chunks so far
+    u64 enumerated = 0;        // children (all, in child order) up to where the level stopped
+    u64 canon_enumerated = 0;  // canonical ones among them
     bool cap_hit = false, budget_hit = false;
-    long long p_end = -1;  // parents up to the last child within the budget (for the halting count)
     // C0's Psi, halting flag and offset come from the walk start, into the
     // counters of this level's first pass: that pass extends by nothing
     bool start_ext = io.c0_psi && S->slot_ready;
     if (start_ext) P = 1;
     long long halting_cap = -1;  // halting parents up to the cap's child's parent, counted in its pass
     for (;;) {
-        if (G >= budget) {  // the budget is spent: is anything left?
-            while (T <= G && P < io.n) {
-                if ((st = clear_counters(S))) return st;
-                if ((st = launch_extension(0))) return st;
-                if ((st = read_counters(S))) return st;
-                T = S->h_ctr->psi_total;
-                halting_all += (long long)S->h_ctr->halting;
-            }
-            budget_hit = T > G;
-            break;
-        }
         u64 want = (u64)S->chunk_max;
         if (io.limit_sem < kInf) {
             const double ratio = std::max(S->new_ratio, 1.0 / 64.0);
             const double w = (double)(io.limit_sem - count) / ratio * 1.1 + 1024.0;
             if (w < (double)want) want = (u64)std::max<double>(w, 4096.0);
         }
-        want = std::min(want, budget - G);
-        const bool ext = start_ext || (P < io.n && T - G < want);
-        if (!ext && T <= G) break;  // every child of the frontier was enumerated
-        const long long B = (long long)(ext ? want : std::min<u64>(want, T - G));  // upper bound when extending
+        // the prefix needs no extension once it holds the budget's last child
+        const bool can_extend = P < io.n && !(has_budget && Tf >= budget);
+        const bool ext = start_ext || (can_extend && Tend - G < want);
+        if (!ext && Tend <= G) break;  // every child the level may take was enumerated
+        const long long B = (long long)(ext ? want : std::min<u64>(want, Tend - G));  // upper bound when extending
         // keep the table at most half full (tombstones included)
         const long long live = io.level_base + count;
         if ((u64)(live + S->tombs + B) * 2 > S->slots) {
@@ -483,33 +505,39 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         if ((st = clear_counters(S))) return st;
         if ((st = mark(S, 0))) return st;
         if (ext && !start_ext && (st = launch_extension(want))) return st;
+        const bool ext_c0 = start_ext;
         start_ext = false;
         if ((st = mark(S, 1))) return st;
         snp::ChunkArgs ca{io.frontier, P, S->d_psi, S->d_off, G, B, S->d_stage, S->d_hash, S->d_cpar, S->d_ct,
-                          hmask, S->d_ctr, S->d_T, S->opt.int8_max_k > 0 ? S->opt.int8_max_k : 128,
+                          hmask, S->d_ctr, d_end, S->opt.int8_max_k > 0 ? S->opt.int8_max_k : 128,
                           S->d_table, S->slots - 1, S->d_slot, S->d_cand};
+        if (ext_c0 && has_budget)  // C0's clip, from the Psi the walk start computed
+            HIPCHK(snp::launch_budget_clip(S->elem_bytes, S->dsys, io.frontier, 1, S->d_psif, S->d_off, S->d_T,
+                                           budget, S->d_Tend, S->d_ctr, S->stream));
         bool probed = false;
         if (use_int8) HIPCHK(snp::launch_expand_int8(S->elem_bytes, S->dsys, ca, S->stream));
         else HIPCHK(snp::launch_expand_sparse(S->elem_bytes, S->dsys, ca, S->stream, &probed));
         if ((st = mark(S, 2))) return st;
         snp::TableArgs ta{S->d_table, S->slots - 1, io.arena, S->d_stage, S->d_hash, S->d_slot, B, S->d_ctr,
-                          S->d_cand, S->d_cpar};
+                          S->d_cand};
         HIPCHK(snp::launch_insert(S->elem_bytes, S->m, ta, S->stream, !probed));
         if ((st = mark(S, 3))) return st;
-        HIPCHK(snp::launch_flags(S->d_table, S->d_slot, S->d_cpar, B, S->d_ctr, S->d_flag, S->d_pos, S->d_fsums,
-                                 S->d_fpre, S->stream));
+        HIPCHK(snp::launch_flags(S->d_table, S->d_slot, B, S->d_ctr, S->d_flag, S->d_pos, S->d_fsums, S->d_fpre,
+                                 S->stream));
         if ((st = mark(S, 4))) return st;
         snp::CommitArgs cm{S->d_table, S->d_table, S->d_slot, S->d_hash, S->d_pos, S->d_flag, S->d_fsums, S->d_fpre,
-                           S->d_stage,
-                           S->d_cpar, S->d_ct, B, io.arena, io.level_base, count, limit, io.row2, io.par_out,
-                           io.par_out_base, io.par_value_base, io.t_out, S->d_row_slot, S->d_ctr, nullptr};
-        // when this pass may fill the cap, count the halting parents up to the
-        // parent of the cap's child in the same pass (no extra synchronisation):
-        // in the commit block that fills it, or for many parents in a kernel of its own
+                           S->d_stage, S->d_cpar, S->d_ct, S->d_psif, B, io.arena, io.level_base, count, limit,
+                           io.row2, io.par_out, io.par_out_base, io.par_value_base, io.t_out, S->d_row_slot,
+                           S->d_ctr, nullptr};
+        // when this pass may fill the cap, count the halting parents (and the
+        // children of the parents) up to the parent of the cap's child in the
+        // same pass (no extra synchronisation): in the commit block that fills
+        // it, or for many parents in a kernel of its own
         const bool may_cap = sem_binds && B >= limit - count;
         if (may_cap && P <= kCommitHaltMax) cm.hflag = S->d_hflag;
         HIPCHK(snp::launch_commit(S->elem_bytes, S->m, cm, S->stream));
-        if (may_cap && P > kCommitHaltMax) HIPCHK(snp::launch_count_flags_cap(S->d_hflag, P, S->d_ctr, S->stream));
+        if (may_cap && P > kCommitHaltMax)
+            HIPCHK(snp::launch_count_flags_cap(S->d_hflag, S->d_psif, P, S->d_ctr, S->stream));
         if ((st = mark(S, 5))) return st;
         if ((st = read_counters(S))) return st;
         if (S->opt.profile == 1) {
@@ -522,14 +550,10 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
             if ((st = add_elapsed(S, 4, 5, &stt.ns_commit))) return st;
         }
         const snp::DevCounters c = *S->h_ctr;
-        if (ext) {
-            T = c.psi_total;
-            halting_all += (long long)c.halting;
-        }
+        if (ext) take_extension(c);
         const long long Beff = (long long)c.beff;
         if (Beff > 0) ++stt.chunks;
         stt.expanded += Beff;
-        stt.twins += (long long)c.twins;
         stt.collisions += (long long)c.collisions;
         stt.mfma_ops += (long long)c.mfma * 32768;
         const long long new_total = (long long)c.total;
@@ -546,7 +570,10 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         if (new_total >= avail && sem_binds && avail > 0) {
             count = limit;
             cap_hit = true;
-            enumerated = G + c.cap_g;
+            // the cap child: canonical index G + cap_g - 1; index among all
+            // children = all children of the parents before its parent + its t
+            canon_enumerated = G + c.cap_g;
+            enumerated = sat_add_host(sat_add_host(join_full(c.capf_lo, c.capf_hi), c.cap_t), 1);
             halting_cap = (long long)c.count;
             break;
         }
@@ -557,13 +584,20 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         }
         count += new_total;
         G += (u64)Beff;
-        enumerated = G;
-        if (G >= budget && Beff > 0) {  // parent of the last child within the budget
-            int last = 0;
-            HIPCHK(hipMemcpyAsync(&last, S->d_cpar + (Beff - 1), sizeof(int), hipMemcpyDeviceToHost, S->stream));
-            HIPCHK(hipStreamSynchronize(S->stream));
-            p_end = (long long)(last < 0 ? -1 - last : last) + 1;  // a twin holds -1 - parent
+    }
+    if (!cap_hit) {
+        canon_enumerated = G;
+        if (has_budget && Tf >= budget) {
+            // the budget's last child was reached: is any child left after it?
+            while (Tf <= budget && P < io.n) {
+                if ((st = clear_counters(S))) return st;
+                if ((st = launch_extension(0))) return st;
+                if ((st = read_counters(S))) return st;
+                take_extension(*S->h_ctr);
+            }
+            budget_hit = Tf > budget;
         }
+        enumerated = budget_hit ? budget : Tf;
     }
     // halting parents up to the parent of the last enumerated child (all parents
     // when the level was not cut short by the cap or the budget)
@@ -571,15 +605,16 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         stt.halting_parents = halting_cap;
     } else if (budget_hit) {
         if ((st = clear_counters(S))) return st;
-        HIPCHK(snp::launch_count_flags(S->d_hflag, p_end, &S->d_ctr->count, S->stream));
+        HIPCHK(snp::launch_count_flags(S->d_hflag, bud_par, &S->d_ctr->count, S->stream));
         if ((st = read_counters(S))) return st;
         stt.halting_parents = (long long)S->h_ctr->count;
     } else {
         stt.halting_parents = halting_all;
     }
     if (P > 0) S->psi_per_parent = (double)T / (double)P;
-    stt.children_total = (long long)T;
+    stt.children_total = (long long)Tf;
     stt.enumerated = (long long)enumerated;
+    stt.twins = (long long)(enumerated - std::min(enumerated, canon_enumerated));
     stt.new_configs = count;
     stt.duplicates = (long long)enumerated - count;
     stt.truncated = cap_hit ? 1 : 0;
@@ -743,6 +778,7 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     LOADCHK(dmalloc(&S->d_row_slot, sizeof(uint32_t) * S->max_rows));
     const long long F = S->max_frontier;
     LOADCHK(dmalloc(&S->d_psi, sizeof(u64) * F));
+    LOADCHK(dmalloc(&S->d_psif, sizeof(u64) * F));
     LOADCHK(dmalloc(&S->d_hflag, (size_t)F));
     LOADCHK(dmalloc(&S->d_off, sizeof(u64) * F));
     const long long ft = snp::scan_tiles(std::max(F, S->chunk_max)) + 1;
@@ -761,6 +797,7 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     LOADCHK(dmalloc(&S->d_fpre, sizeof(uint32_t) * ft));
     LOADCHK(dmalloc(&S->d_ring, sizeof(snp::DevCounters) * snp_system::kRing));
     LOADCHK(dmalloc(&S->d_T, sizeof(u64)));
+    LOADCHK(dmalloc(&S->d_Tend, sizeof(u64)));
     S->d_ctr = S->d_ring;
     LOADCHK(hipHostMalloc((void**)&S->h_ctr, sizeof(snp::DevCounters), hipHostMallocDefault));
     if (opt.profile)

@@ -189,6 +189,39 @@ __device__ __forceinline__ uint32_t canonical_mask(const int4* rules, int r0, ui
     return cm;
 }
 
+// Canonical enumeration.  A child is computed only when every neuron's digit
+// is canonical (twins never are: they repeat an earlier child); canonical
+// children are numbered u = 0, 1, ... in the same order as their child
+// indices t (Algorithm 2 II-3 order restricted to them), as a mixed-radix
+// number whose digit e of a neuron counts the canonical digits below its
+// digit.  kappa = number of canonical digits of a neuron (1 when omega <= 1:
+// its only value fires its one rule, or nothing).  am holds the applicable
+// rules in its low 16 bits and, for omega >= 2, the canonical digits above.
+__device__ __forceinline__ int kappa_of(uint32_t am, int om) { return om >= 2 ? __popc(am >> 16) : 1; }
+
+// Digit (ordinal among the applicable rules) of canonical digit e.
+__device__ __forceinline__ int canon_digit(uint32_t am, int om, int e) { return om >= 2 ? nth_bit(am >> 16, e) : 0; }
+
+// Saturating sum over the wave (values <= 2^62).
+__device__ __forceinline__ u64 wave_satsum(u64 x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = sat_add(x, __shfl_xor(x, o));
+    return x;
+}
+
+// Applicable-rule mask of a neuron holding x spikes (rules r0 .. r1 - 1) with
+// its canonical digits in the high 16 bits (omega >= 2), and omega.
+__device__ __forceinline__ uint32_t neuron_applicable(int x, int r0, int r1, const int4* rules, int& w) {
+    uint32_t mask = 0;
+    w = 0;
+    for (int q = r0; q < r1; ++q)
+        if (rule_applies(x, rules[q])) {
+            mask |= 1u << (q - r0);
+            ++w;
+        }
+    return mask | (w >= 2 ? canonical_mask(rules, r0, mask) << 16 : 0xFFFF0000u);
+}
+
 // Mixed-radix decode of child index t (Algorithm 2 II-3 order: the last neuron
 // is the least significant digit; a neuron with omega <= 1 has one value).
 // Lane L owns the contiguous neurons [L*Q, L*Q + Q); the place value of its
@@ -238,6 +271,65 @@ __device__ __forceinline__ void decode_digits_at(int m, int lane, u64 t, const u
 
 __device__ __forceinline__ void decode_digits(int m, int lane, u64 t, const uint8_t* om, uint8_t* dg) {
     decode_digits_at(m, lane, t, om, dg, digit_place(m, lane, om));
+}
+
+// Place values of the canonical digits (product of kappa over the later
+// neurons) and canonical decode, for the lane's block of neurons as in
+// digit_place / decode_digits_at.
+__device__ __forceinline__ u64 canon_place(int m, int lane, const uint8_t* om, const uint32_t* am) {
+    const int Q = (m + 63) >> 6;
+    const int j0 = lane * Q;
+    const int j1 = min(m, j0 + Q);
+    u64 bp = 1;
+    for (int j = j0; j < j1; ++j) bp = sat_mul(bp, (u64)kappa_of(am[j], om[j]));
+    u64 incl = bp;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const u64 y = __shfl_down(incl, o);
+        if (lane + o < 64) incl = sat_mul(incl, y);
+    }
+    u64 after = __shfl_down(incl, 1);
+    if (lane == 63) after = 1;
+    return after;
+}
+
+__device__ __forceinline__ void canon_decode(int m, int lane, u64 u, const uint8_t* om, const uint32_t* am,
+                                             uint8_t* eg, u64 after) {
+    const int Q = (m + 63) >> 6;
+    const int j0 = lane * Q;
+    const int j1 = min(m, j0 + Q);
+    u64 tl = (after > u) ? 0 : u / after;
+    for (int j = j1 - 1; j >= j0; --j) {
+        if (tl == 0) {
+            eg[j] = 0;
+            continue;
+        }
+        const uint32_t k = (uint32_t)kappa_of(am[j], om[j]);
+        eg[j] = (uint8_t)(tl % k);
+        tl /= k;
+    }
+}
+
+// Child index t of a canonical child whose canonical digits are eg: the sum
+// over neurons of digit * (product of max(1, omega) over the later neurons),
+// lane L summing its block [L*Q, L*Q + Q) and scaling by the block's place
+// value after_w (digit_place over omega).  Arithmetic is mod 2^64; it is exact
+// because every enumerated child has t < 2^62 (a saturated place value then
+// only ever meets digit 0).  All 64 lanes active; every lane gets t.
+__device__ __forceinline__ u64 child_index(int m, int lane, const uint8_t* om, const uint32_t* am, const uint8_t* eg,
+                                           u64 after_w) {
+    const int Q = (m + 63) >> 6;
+    const int j0 = lane * Q;
+    const int j1 = min(m, j0 + Q);
+    u64 v = 0, pl = 1;
+    for (int j = j1 - 1; j >= j0; --j) {
+        const int w = om[j];
+        if (w >= 2) {
+            v += (u64)canon_digit(am[j], w, eg[j]) * pl;
+            pl *= (u64)w;
+        }
+    }
+    return wave_sum_u64(v * after_w);
 }
 
 }  // namespace snp

@@ -34,11 +34,18 @@ struct DevCounters {
     u64 cap_par;       // parent (frontier index) of the child that filled the cap
     u64 count;         // scratch count (halting parents of a frontier prefix)
     u64 beff;          // children the chunk really covers: min(B, children of the prefix - g0)
-    u64 psi_total;     // children of the frontier prefix after this pass's extension
-    u64 twins;         // children of the chunk that fire a later twin rule
+    u64 psi_total;     // canonical children of the frontier prefix after this pass's extension
     u64 c0_bad;        // walk start: C0 holds a count outside the count type's range
     u64 collisions;    // probes that met an entry with their tag whose row differed
     u64 mfma;          // int8 matrix-core instructions issued (16x16x64 each)
+    u64 psif_lo;       // all children (every valid spiking vector) of the parents this pass
+    u64 psif_hi;       //   added to the prefix: sum of (Psi mod 2^31) and of (Psi >> 31)
+    u64 cap_t;         // child index t of the child that filled the cap
+    u64 capf_lo;       // all children of the parents before the cap child's parent, split
+    u64 capf_hi;       //   as psif_lo / psif_hi
+    u64 tend;          // canonical children the chunks may take: the prefix's, or fewer where
+                       // the child budget ends (the budget's clip)
+    u64 bud_par;       // budget clip: parent of the last child within the budget, + 1 (0: none)
 };
 
 // Device-side description of a loaded system.
@@ -60,21 +67,22 @@ struct DevSystem {
                            // vector only), kPsiSat otherwise
 };
 
-// One chunk of children [g0, g0 + B) of the frontier.
+// One chunk of canonical children [g0, g0 + B) of the frontier (canonical
+// children numbered parent by parent, each parent's in child-index order).
 struct ChunkArgs {
     const void* frontier;  // n rows
     long long n;
-    const u64* psi;        // [n] children per parent (0: none)
+    const u64* psi;        // [n] canonical children per parent (0: none)
     const u64* off;        // [n] exclusive prefix sums of psi
     u64 g0;
     long long B;
     void* stage;           // [B] child rows
     u64* hash;             // [B]
-    int* cpar;             // [B] parent index p in the frontier; -1 - p for a twin child
-    u64* ct;               // [B] child index within the parent
+    int* cpar;             // [B] parent index p in the frontier
+    u64* ct;               // [B] child index t within the parent (Algorithm 2 II-3 order)
     u64 hash_mask;
     DevCounters* ctr;
-    const u64* Tdev;       // children of the frontier prefix [0, n): the chunk stops there
+    const u64* Tdev;       // canonical children the chunks may take: the chunk stops there
     int kmax;              // int8 form: most rule columns a segment may put on the matrix cores
     // visited-set probe done by the expansion itself (the one-neuron-per-lane
     // form); null table: the probe runs as a kernel of its own
@@ -95,7 +103,6 @@ struct TableArgs {
     long long B;
     DevCounters* ctr;
     uint32_t* cand;        // [B] children waiting for a row compare
-    const int* cpar;       // [B] parent of each child; negative marks a twin (skipped)
 };
 
 struct CommitArgs {
@@ -110,6 +117,7 @@ struct CommitArgs {
     const void* stage;
     const int* cpar;
     const u64* ct;
+    const u64* psif;       // [n] all children of every parent (the cap child's index g)
     long long B;
     void* arena;           // row store
     long long level_base;  // row-store index of the level's first row
@@ -123,7 +131,8 @@ struct CommitArgs {
     uint32_t* row_slot;    // [max_rows] slot of every row-store row
     DevCounters* ctr;
     const uint8_t* hflag;  // nullable halting flags of the frontier: the block that fills the
-                           // cap counts them up to the cap child's parent into ctr->count
+                           // cap counts them up to the cap child's parent into ctr->count, and
+                           // sums psif before that parent into ctr->capf_lo / capf_hi
 };
 
 // Deterministic batched run: one system per workgroup.
@@ -173,19 +182,30 @@ hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st);
 hipError_t launch_pack_rows(void* const* ptrs, const long long* off, void* packed, int n, int elem_bytes,
                             bool to_packed, hipStream_t st);
 
+// Per parent: canonical children (psi), all children (psif), halting flag;
+// the sum of psif goes to ctr->psif_lo / psif_hi, the halting parents to ctr->halting.
 hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, long long n,
-                      long long expand_max, u64* psi, uint8_t* halt_flag, DevCounters* ctr, hipStream_t st);
+                      long long expand_max, u64* psi, u64* psif, uint8_t* halt_flag, DevCounters* ctr,
+                      hipStream_t st);
 bool psi_scan_fits(const DevSystem& s, long long n);  // launch_psi_scan_small takes n parents (m <= 64)
-// Psi, halting flags and offsets of n (psi_scan_fits) parents in one launch;
-// offsets start at *base_dev (nullable: 0); the new total goes to *total_dev
-// and ctr->psi_total, the halting parents are added to ctr->halting.
+// launch_psi and the offsets of the canonical counts of n (psi_scan_fits)
+// parents in one launch; offsets start at *base_dev (nullable: 0); the new
+// total goes to *total_dev and ctr->psi_total.
 hipError_t launch_psi_scan_small(int elem_bytes, const DevSystem& s, const void* frontier, long long n,
-                                 long long expand_max, u64* psi, uint8_t* halt_flag, u64* off, const u64* base_dev,
-                                 u64* total_dev, DevCounters* ctr, hipStream_t st);
+                                 long long expand_max, u64* psi, u64* psif, uint8_t* halt_flag, u64* off,
+                                 const u64* base_dev, u64* total_dev, DevCounters* ctr, hipStream_t st);
+// Child budget: the canonical children of the prefix [0, n) whose index g among
+// all children is below `budget`; *tend = min(*total, that count), ctr->tend
+// likewise, ctr->bud_par = parent of child budget - 1, plus 1 (0 when the
+// prefix holds no more than budget children).
+hipError_t launch_budget_clip(int elem_bytes, const DevSystem& s, const void* frontier, long long n,
+                              const u64* psif, const u64* off, const u64* total, u64 budget, u64* tend,
+                              DevCounters* ctr, hipStream_t st);
 hipError_t launch_scan_u64(const u64* in, u64* out, long long n, u64* tile_sums, u64* tile_pre,
                            u64* total, const u64* base_dev, u64* total_copy, hipStream_t st);
 hipError_t launch_count_flags(const uint8_t* flags, long long n, u64* out, hipStream_t st);
-hipError_t launch_count_flags_cap(const uint8_t* flags, long long n, DevCounters* ctr, hipStream_t st);
+hipError_t launch_count_flags_cap(const uint8_t* flags, const u64* psif, long long n, DevCounters* ctr,
+                                  hipStream_t st);
 long long scan_tiles(long long n);
 hipError_t launch_expand_int8(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st);
 size_t int8_lds(int m, int nt);
@@ -194,14 +214,14 @@ hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkA
                                 bool* probed);
 // probe false: the children were probed by the expansion; only the row compares run
 hipError_t launch_insert(int elem_bytes, int m, const TableArgs& a, hipStream_t st, bool probe);
-hipError_t launch_flags(const u64* table, const uint32_t* slot, const int* cpar, long long B, DevCounters* ctr,
-                        uint32_t* flag, uint32_t* pos, uint32_t* tile_sums, uint32_t* tile_pre, hipStream_t st);
+hipError_t launch_flags(const u64* table, const uint32_t* slot, long long B, DevCounters* ctr, uint32_t* flag,
+                        uint32_t* pos, uint32_t* tile_sums, uint32_t* tile_pre, hipStream_t st);
 hipError_t launch_commit(int elem_bytes, int m, const CommitArgs& a, hipStream_t st);
 hipError_t launch_fill_u64(u64* p, long long n, u64 v, hipStream_t st);
 hipError_t launch_start_walk(int elem_bytes, int m, const u64* R, u64* table, u64 slot_mask, const void* c0,
                              void* arena, long long count_max, u64 hash_mask, uint32_t* row_slot, DevCounters* sc,
                              long long* par0, long long* chi0, const DevSystem& s, long long expand_max, u64* psi0,
-                             uint8_t* hflag0, u64* off0, u64* Tdev, hipStream_t st);
+                             u64* psif0, uint8_t* hflag0, u64* off0, u64* Tdev, hipStream_t st);
 hipError_t launch_rows_insert(int elem_bytes, int m, const u64* R, u64* table, u64 slot_mask, const void* arena,
                               long long first, long long count, u64 hash_mask, uint32_t* row_slot,
                               DevCounters* ctr, hipStream_t st);

@@ -39,50 +39,135 @@ __device__ __forceinline__ u64 wave_satprod(u64 x) {
 // Psi of one parent (Algorithm 2: the product over neurons of the number of
 // applicable rules, a neuron without one counting 1; 0 when no neuron has an
 // applicable rule, or when a count exceeds expand_max), one wave, lane per
-// neuron; halting = no rule applies anywhere.
+// neuron; halting = no rule applies anywhere.  The same pass counts the
+// canonical children (the product of kappa, the canonical digits per neuron),
+// the only ones the expansion computes.
 struct PsiAcc {
-    uint32_t c2 = 0, c3 = 0, c4 = 0;
-    bool any = false, over = false, big = false;
-    u64 bigprod = 1;
+    uint32_t c2 = 0, c3 = 0, c4 = 0;  // neurons with omega = 2, 3, 4
+    uint32_t k2 = 0, k3 = 0, k4 = 0;  // neurons with kappa = 2, 3, 4
+    bool any = false, over = false, big = false, kbig = false;
+    u64 bigprod = 1, kbigprod = 1;
 };
 
 // Neuron j (< m) holding x spikes: its applicable rules, into the wave's tallies.
 __device__ __forceinline__ void psi_add_neuron(PsiAcc& A, int x, int j, int m, const int* nrp, const int4* rules,
                                                long long expand_max) {
-    int w = 0;
+    int w = 0, k = 1;
     if (j < m) {
-        const int r1 = nrp[j + 1];
-        for (int q = nrp[j]; q < r1; ++q) w += rule_applies(x, rules[q]) ? 1 : 0;
+        const uint32_t am = neuron_applicable(x, nrp[j], nrp[j + 1], rules, w);
+        k = kappa_of(am, w);
         A.over |= (expand_max >= 0 && (long long)x > expand_max);
     }
     A.any |= (w > 0);
     A.c2 += __popcll(__ballot(w == 2));
     A.c3 += __popcll(__ballot(w == 3));
     A.c4 += __popcll(__ballot(w == 4));
+    A.k2 += __popcll(__ballot(k == 2));
+    A.k3 += __popcll(__ballot(k == 3));
+    A.k4 += __popcll(__ballot(k == 4));
     if (w > 4) {
         A.big = true;
         A.bigprod = sat_mul(A.bigprod, (u64)w);
     }
+    if (k > 4) {
+        A.kbig = true;
+        A.kbigprod = sat_mul(A.kbigprod, (u64)k);
+    }
 }
 
-__device__ __forceinline__ u64 psi_finish(const PsiAcc& A, bool& halting) {
+// Children of a parent: full (every valid spiking vector) and canonical.
+struct PsiPair {
+    u64 full, canon;
+};
+
+__device__ __forceinline__ PsiPair psi_finish(const PsiAcc& A, bool& halting) {
     const bool wany = __any(A.any);
     const bool wover = __any(A.over);
     u64 prod = sat_mul(sat_pow(2, A.c2 + 2 * A.c4), sat_pow(3, A.c3));  // 4^c4 = 2^(2 c4)
     if (__any(A.big)) prod = sat_mul(prod, wave_satprod(A.bigprod));
+    u64 kprod = sat_mul(sat_pow(2, A.k2 + 2 * A.k4), sat_pow(3, A.k3));
+    if (__any(A.kbig)) kprod = sat_mul(kprod, wave_satprod(A.kbigprod));
     halting = !wany;
-    return (!wany || wover) ? 0 : prod;
+    if (!wany || wover) return PsiPair{0, 0};
+    return PsiPair{prod, kprod};
+}
+
+// Canonical children of the parent `row` whose child index t is below L
+// (1 <= L <= 2^62).  Digits count from the most significant neuron; with
+// (L - 1) written in the mixed radix of omega as digits l_n, a canonical child
+// has t < L iff its digits are lexicographically <= those of L - 1, so the
+// count is the sum, from the most significant neuron down to the first whose
+// digit l_n is not canonical (included), of (canonical digits below l_n) x
+// (product of kappa over the later neurons), plus one when every l_n is
+// canonical.  Only the last 64 neurons with omega >= 2 can have a nonzero l_n
+// (the 64 after any earlier one make its place value at least 2^64), so lane
+// q takes the q-th of them from the end.  One wave, all lanes active.
+template <typename T>
+__device__ u64 canon_rank(const T* row, int m, const int* nrp, const int4* rules, u64 L, int lane) {
+    int cnt = 0;  // neurons taken so far (uniform)
+    int myw = 1;
+    uint32_t mycm = 1;
+    for (int base = ((m - 1) >> 6) << 6; base >= 0 && cnt < 64; base -= 64) {
+        const int j = base + lane;
+        int w = 0;
+        uint32_t am = 0;
+        if (j < m) am = neuron_applicable((int)row[j], nrp[j], nrp[j + 1], rules, w);
+        const u64 bm = __ballot(w >= 2);
+        const int nb = __popcll(bm);
+        // lane q (cnt <= q < cnt + nb) takes the (q - cnt)-th set bit of bm from the top
+        const int pos = lane - cnt;
+        const bool take = pos >= 0 && pos < nb;
+        int src = 0;
+        if (take) {
+            u64 x = __builtin_bitreverse64(bm);  // bit i: lane 63 - i
+            for (int k = 0; k < pos; ++k) x &= x - 1;
+            src = 63 - __builtin_ctzll(x);
+        }
+        const int w_s = __shfl(w, src);
+        const uint32_t am_s = (uint32_t)__shfl((int)am, src);
+        if (take) {
+            myw = w_s;
+            mycm = am_s >> 16;
+        }
+        cnt = min(64, cnt + nb);
+    }
+    // place values over omega and kappa: products over the neurons after this one
+    // (lanes below), exclusive, saturated
+    const u64 wq = (u64)myw;
+    u64 pw = wq, pk = (u64)__popc(mycm & ((1u << myw) - 1));
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const u64 yw = __shfl_up(pw, o), yk = __shfl_up(pk, o);
+        if (lane >= o) {
+            pw = sat_mul(pw, yw);
+            pk = sat_mul(pk, yk);
+        }
+    }
+    u64 placew = __shfl_up(pw, 1), placek = __shfl_up(pk, 1);
+    if (lane == 0) placew = placek = 1;
+    const u64 lim = L - 1;
+    const int l = placew >= kPsiSat || placew > lim ? 0 : (int)((lim / placew) % wq);
+    const uint32_t below = mycm & ((1u << l) - 1);
+    const bool nc = !((mycm >> l) & 1u);
+    const u64 ncm = __ballot(nc);
+    const int qstop = ncm ? 63 - __clzll((long long)ncm) : -1;  // most significant non-canonical digit
+    const u64 term = lane >= qstop ? sat_mul((u64)__popc(below), placek) : 0;
+    return sat_add(wave_satsum(term), ncm ? 0 : 1);
 }
 
 template <typename T>
-__device__ __forceinline__ u64 parent_psi(const T* row, int m, const int* nrp, const int4* rules, long long expand_max,
-                                          int lane, bool& halting) {
+__device__ __forceinline__ PsiPair parent_psi(const T* row, int m, const int* nrp, const int4* rules,
+                                              long long expand_max, int lane, bool& halting) {
     PsiAcc A;
     for (int base = 0; base < m; base += 64) {
         const int j = base + lane;
         psi_add_neuron(A, j < m ? (int)row[j] : 0, j, m, nrp, rules, expand_max);
     }
-    return psi_finish(A, halting);
+    PsiPair r = psi_finish(A, halting);
+    // with 2^62 or more children some canonical ones may have t >= 2^62, past
+    // what a level enumerates: count only those below
+    if (r.full >= kPsiSat) r.canon = min(r.canon, canon_rank<T>(row, m, nrp, rules, kPsiSat, lane));
+    return r;
 }
 
 // Rules and rule offsets staged in LDS when they fit (else read from global).
@@ -105,9 +190,16 @@ __device__ __forceinline__ PsiTables stage_psi_tables(const DevSystem& s, unsign
     }
 }
 
+// Adds children counts (each <= 2^62) to ctr->psif_lo / psif_hi, split at bit
+// 31 so that neither sum can wrap; the host joins and saturates them.
+__device__ __forceinline__ void add_full_total(DevCounters* ctr, u64 lo, u64 hi) {
+    if (lo) atomicAdd((unsigned long long*)&ctr->psif_lo, lo);
+    if (hi) atomicAdd((unsigned long long*)&ctr->psif_hi, hi);
+}
+
 template <typename T, bool TBL_LDS>
 __global__ __launch_bounds__(256) void k_psi(DevSystem s, const T* __restrict__ F, long long n,
-                                             long long expand_max, u64* __restrict__ psi,
+                                             long long expand_max, u64* __restrict__ psi, u64* __restrict__ psif,
                                              uint8_t* __restrict__ halt_flag, DevCounters* __restrict__ ctr,
                                              int parents_per_wave) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -115,17 +207,22 @@ __global__ __launch_bounds__(256) void k_psi(DevSystem s, const T* __restrict__ 
     const PsiTables tb = stage_psi_tables<TBL_LDS>(s, smem);
     const long long w0 = ((long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * parents_per_wave;
     unsigned halting = 0;
+    u64 flo = 0, fhi = 0;
     for (long long p = w0; p < min(n, w0 + parents_per_wave); ++p) {
         bool h;
-        const u64 v = min(parent_psi<T>(F + p * (long long)s.m, s.m, tb.nrp, tb.rules, expand_max, lane, h),
-                          s.psi_cap);
+        const PsiPair v = parent_psi<T>(F + p * (long long)s.m, s.m, tb.nrp, tb.rules, expand_max, lane, h);
+        const u64 full = min(v.full, s.psi_cap);
         if (lane == 0) {
-            psi[p] = v;
+            psi[p] = min(v.canon, s.psi_cap);
+            psif[p] = full;
             halt_flag[p] = h ? 1 : 0;
         }
         halting += h ? 1u : 0u;
+        flo += full & 0x7FFFFFFFull;
+        fhi += full >> 31;
     }
     if (lane == 0 && halting) atomicAdd(&ctr->halting, (u64)halting);
+    if (lane == 0) add_full_total(ctr, flo, fhi);
 }
 
 // Psi of at most kPsiScanSmall parents (m <= 64) and their exclusive prefix
@@ -137,6 +234,7 @@ constexpr int kPsiScanSmall = 16;  // one parent per wave: more would serialise 
 template <typename T, bool TBL_LDS>
 __global__ __launch_bounds__(1024) void k_psi_scan_small(DevSystem s, const T* __restrict__ F, int n,
                                                          long long expand_max, u64* __restrict__ psi,
+                                                         u64* __restrict__ psif,
                                                          uint8_t* __restrict__ halt_flag, u64* __restrict__ off,
                                                          const u64* base_dev, u64* total_dev,
                                                          DevCounters* __restrict__ ctr) {
@@ -165,11 +263,17 @@ __global__ __launch_bounds__(1024) void k_psi_scan_small(DevSystem s, const T* _
             PsiAcc A;
             psi_add_neuron(A, xs[q], lane, m, tb.nrp, tb.rules, expand_max);
             bool h;
-            const u64 v = min(psi_finish(A, h), s.psi_cap);
+            PsiPair v2 = psi_finish(A, h);
+            if (v2.full >= kPsiSat)
+                v2.canon = min(v2.canon, canon_rank<T>(F + (long long)p * m, m, tb.nrp, tb.rules, kPsiSat, lane));
+            const u64 v = min(v2.canon, s.psi_cap);
+            const u64 full = min(v2.full, s.psi_cap);
             if (lane == 0) {
                 l_psi[p] = v;
                 psi[p] = v;
+                psif[p] = full;
                 halt_flag[p] = h ? 1 : 0;
+                add_full_total(ctr, full & 0x7FFFFFFFull, full >> 31);
             }
             halting += h ? 1u : 0u;
         }
@@ -199,7 +303,8 @@ __global__ __launch_bounds__(1024) void k_psi_scan_small(DevSystem s, const T* _
 }
 
 hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, long long n,
-                      long long expand_max, u64* psi, uint8_t* halt_flag, DevCounters* ctr, hipStream_t st) {
+                      long long expand_max, u64* psi, u64* psif, uint8_t* halt_flag, DevCounters* ctr,
+                      hipStream_t st) {
     if (n <= 0) return hipSuccess;
     const size_t tbl = (size_t)s.r * 16 + (size_t)(s.m + 1) * 4;
     const bool tbl_lds = tbl <= (size_t)(32 * 1024);
@@ -211,7 +316,7 @@ hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, 
     const size_t lds = tbl_lds ? tbl : 0;
 #define SNP_PSI(TT, L)                                                                                       \
     hipLaunchKernelGGL((k_psi<TT, L>), dim3(blocks), dim3(256), lds, st, s, (const TT*)frontier, n, expand_max, \
-                       psi, halt_flag, ctr, ppw)
+                       psi, psif, halt_flag, ctr, ppw)
     if (elem_bytes == 4) {
         if (tbl_lds) SNP_PSI(int32_t, true);
         else SNP_PSI(int32_t, false);
@@ -226,15 +331,15 @@ hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, 
 bool psi_scan_fits(const DevSystem& s, long long n) { return s.m <= 64 && n > 0 && n <= kPsiScanSmall; }
 
 hipError_t launch_psi_scan_small(int elem_bytes, const DevSystem& s, const void* frontier, long long n,
-                                 long long expand_max, u64* psi, uint8_t* halt_flag, u64* off, const u64* base_dev,
-                                 u64* total_dev, DevCounters* ctr, hipStream_t st) {
+                                 long long expand_max, u64* psi, u64* psif, uint8_t* halt_flag, u64* off,
+                                 const u64* base_dev, u64* total_dev, DevCounters* ctr, hipStream_t st) {
     if (!psi_scan_fits(s, n)) return hipErrorInvalidValue;
     const size_t tbl = (size_t)s.r * 16 + (size_t)(s.m + 1) * 4;
     const bool tbl_lds = tbl <= (size_t)(32 * 1024);
     const size_t lds = tbl_lds ? tbl : 0;
 #define SNP_PSS(TT, L)                                                                                     \
     hipLaunchKernelGGL((k_psi_scan_small<TT, L>), dim3(1), dim3(1024), lds, st, s, (const TT*)frontier, (int)n, \
-                       expand_max, psi, halt_flag, off, base_dev, total_dev, ctr)
+                       expand_max, psi, psif, halt_flag, off, base_dev, total_dev, ctr)
     if (elem_bytes == 4) {
         if (tbl_lds) SNP_PSS(int32_t, true);
         else SNP_PSS(int32_t, false);
@@ -377,42 +482,132 @@ hipError_t launch_count_flags(const uint8_t* flags, long long n, u64* out, hipSt
     return hipGetLastError();
 }
 
-// The same count over flags [0, cap_par + 1) when the pass's commit filled the
-// cap (cap_g != 0), else nothing; n bounds the flags computed so far.
-__global__ __launch_bounds__(256) void k_count_flags_cap(const uint8_t* __restrict__ f, long long n,
-                                                         DevCounters* ctr) {
+// The same count over flags [0, cap_par + 1), and the sum of all children
+// of parents [0, cap_par), when the pass's commit filled the cap (cap_g != 0),
+// else nothing; n bounds the flags computed so far.
+__global__ __launch_bounds__(256) void k_count_flags_cap(const uint8_t* __restrict__ f, const u64* __restrict__ psif,
+                                                         long long n, DevCounters* ctr) {
     if (ctr->cap_g == 0) return;
-    const long long lim = min(n, (long long)ctr->cap_par + 1);
+    const long long cp = (long long)ctr->cap_par;
+    const long long lim = min(n, cp + 1);
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     const bool v = i < lim && f[i] != 0;
+    const u64 full = i < min(n, cp) ? psif[i] : 0;
     const u64 bm = __ballot(v);
-    if ((threadIdx.x & 63) == 0 && bm) atomicAdd((unsigned long long*)&ctr->count, (u64)__popcll(bm));
+    const u64 flo = wave_sum_u64(full & 0x7FFFFFFFull), fhi = wave_sum_u64(full >> 31);
+    if ((threadIdx.x & 63) == 0) {
+        if (bm) atomicAdd((unsigned long long*)&ctr->count, (u64)__popcll(bm));
+        if (flo) atomicAdd((unsigned long long*)&ctr->capf_lo, flo);
+        if (fhi) atomicAdd((unsigned long long*)&ctr->capf_hi, fhi);
+    }
 }
 
-hipError_t launch_count_flags_cap(const uint8_t* flags, long long n, DevCounters* ctr, hipStream_t st) {
+hipError_t launch_count_flags_cap(const uint8_t* flags, const u64* psif, long long n, DevCounters* ctr,
+                                  hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_count_flags_cap, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, flags, n, ctr);
+    hipLaunchKernelGGL(k_count_flags_cap, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, flags, psif, n, ctr);
+    return hipGetLastError();
+}
+
+// Child budget (one block).  The parents' full child counts are summed in
+// order to find the parent p_b holding child g = budget - 1; the canonical
+// children before the budget are then off[p_b] plus the canonical children of
+// p_b with child index below budget - (all children of the parents before
+// p_b), from canon_rank.  With no more than `budget` children in the prefix
+// the end stays the prefix's canonical total.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_budget_clip(DevSystem s, const T* __restrict__ F, long long n,
+                                                      const u64* __restrict__ psif, const u64* __restrict__ off,
+                                                      const u64* __restrict__ total, u64 budget, u64* tend,
+                                                      DevCounters* ctr) {
+    __shared__ u64 wsum[16];
+    __shared__ u64 s_carry;
+    __shared__ long long s_pb;
+    __shared__ u64 s_before;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (threadIdx.x == 0) {
+        s_carry = 0;
+        s_pb = -1;
+    }
+    __syncthreads();
+    for (long long b = 0; b < n; b += 1024) {
+        const long long i = b + threadIdx.x;
+        const u64 x = i < n ? psif[i] : 0;
+        u64 incl = x;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const u64 y = __shfl_up(incl, o);
+            if (lane >= o) incl = sat_add(incl, y);
+        }
+        u64 excl = __shfl_up(incl, 1);
+        if (lane == 0) excl = 0;
+        if (lane == 63) wsum[wid] = incl;
+        __syncthreads();
+        u64 pre = s_carry;
+        for (int w = 0; w < wid; ++w) pre = sat_add(pre, wsum[w]);
+        const u64 before = sat_add(pre, excl);  // children of the parents before i
+        // parent i holds child budget - 1 when before < budget <= before + x
+        if (i < n && x > 0 && before < budget && budget <= sat_add(before, x)) {
+            s_pb = i;
+            s_before = before;
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) s_carry = sat_add(pre, incl);
+        __syncthreads();
+        if (s_pb >= 0) break;
+    }
+    const u64 T0 = *total;
+    if (s_pb < 0) {  // the prefix holds no more than budget children
+        if (threadIdx.x == 0) {
+            *tend = T0;
+            ctr->tend = T0;
+        }
+        return;
+    }
+    if (wid == 0) {
+        const long long pb = s_pb;
+        const u64 rank = canon_rank<T>(F + pb * (long long)s.m, s.m, s.nrule_ptr, s.rules, budget - s_before, lane);
+        if (lane == 0) {
+            const u64 e = min(T0, sat_add(off[pb], rank));
+            *tend = e;
+            ctr->tend = e;
+            ctr->bud_par = (u64)pb + 1;
+        }
+    }
+}
+
+hipError_t launch_budget_clip(int elem_bytes, const DevSystem& s, const void* frontier, long long n,
+                              const u64* psif, const u64* off, const u64* total, u64 budget, u64* tend,
+                              DevCounters* ctr, hipStream_t st) {
+    if (elem_bytes == 4)
+        hipLaunchKernelGGL(k_budget_clip<int32_t>, dim3(1), dim3(1024), 0, st, s, (const int32_t*)frontier, n, psif,
+                           off, total, budget, tend, ctr);
+    else
+        hipLaunchKernelGGL(k_budget_clip<uint16_t>, dim3(1), dim3(1024), 0, st, s, (const uint16_t*)frontier, n,
+                           psif, off, total, budget, tend, ctr);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Expansion, sparse form.  Every wave owns a run of consecutive children
-// g0 + b0 .. g0 + b0 + run - 1.  Per wave, LDS holds the parent row, the
-// applicable-rule mask and count omega of every neuron, the current digit of
-// every neuron, and the consumption c and production p of every neuron's
-// fired rule.  When the rule table and the in-synapse lists are small they are
-// staged once per block in LDS as well, so the per-child loop touches no
-// global memory except the row it writes.
+// Expansion, sparse form.  Every wave owns a run of consecutive canonical
+// children g0 + b0 .. g0 + b0 + run - 1.  Per wave, LDS holds the parent row,
+// the applicable-rule mask (with the canonical digits) and count omega of
+// every neuron, the current canonical digit of every neuron, and the
+// consumption c and production p of every neuron's fired rule.  When the rule
+// table and the in-synapse lists are small they are staged once per block in
+// LDS as well, so the per-child loop touches no global memory except the row
+// it writes.
 //
 //   decode (once per run): place value of each lane's block of neurons is a
-//     suffix product across lanes; digits follow by division.
-//   advance (per child): add one to the mixed-radix number: the last neuron
-//     with omega >= 2 whose digit is below omega - 1 steps up and every later
-//     neuron with omega >= 2 resets to 0; only those neurons refresh their
-//     fired (c, p).  Past the last child of a parent the wave moves to the
-//     next parent with Psi > 0, digits all 0.
+//     suffix product of kappa across lanes; canonical digits follow by division.
+//   advance (per child): add one to the mixed-radix number of canonical
+//     digits: the last neuron with kappa >= 2 whose digit is below kappa - 1
+//     steps up and every later neuron with kappa >= 2 resets to 0; only those
+//     neurons refresh their fired (c, p).  Past the last canonical child of a
+//     parent the wave moves to the next parent with one, digits all 0.
 //   child (per child): C'[d] = C[d] - c(fired rule of d) + sum over in-synapses
-//     (s, d) of p(fired rule of s): the nonzero entries of column d of S.M.
+//     (s, d) of p(fired rule of s): the nonzero entries of column d of S.M;
+//     its child index t from the digits (child_index).
 // ---------------------------------------------------------------------------
 constexpr int kLdsBytesPerNeuron = 4 /*par*/ + 4 /*c:p*/ + 4 /*mask*/ + 1 /*omega*/ + 1 /*digit*/;
 constexpr int kTableLdsLimit = 24 * 1024;
@@ -425,13 +620,14 @@ struct Tables {
     const u64* R;      // [m] hash weights
 };
 
-// Fired rule of neuron j packed as (c << 16) | p (both <= 65535, checked at load); 0 when none.
-// am[j]: applicable-rule mask in the low 16 bits, canonical digits in the high 16.
+// Fired rule of neuron j (canonical digit eg[j]) packed as (c << 16) | p (both
+// <= 65535, checked at load); 0 when none.
 __device__ __forceinline__ void set_fired(const Tables& tb, int j, const uint8_t* om, const uint32_t* am,
-                                          const uint8_t* dg, uint32_t* cp) {
+                                          const uint8_t* eg, uint32_t* cp) {
     uint32_t v = 0;
     if (om[j]) {
-        const int4 R = tb.rules[tb.nrp[j] + nth_bit(am[j] & 0xFFFFu, dg[j])];
+        const int d = canon_digit(am[j], om[j], eg[j]);
+        const int4 R = tb.rules[tb.nrp[j] + nth_bit(am[j] & 0xFFFFu, d)];
         v = ((uint32_t)R.z << 16) | (uint32_t)R.w;
     }
     cp[j] = v;
@@ -443,26 +639,10 @@ __device__ __forceinline__ void load_parent(const Tables& tb, int m, const T* ro
     for (int j = lane; j < m; j += 64) {
         const int x = (int)row[j];
         par[j] = x;
-        uint32_t mask = 0;
-        int w = 0;
-        const int r0 = tb.nrp[j], r1 = tb.nrp[j + 1];
-        for (int q = r0; q < r1; ++q)
-            if (rule_applies(x, tb.rules[q])) {
-                mask |= 1u << (q - r0);
-                ++w;
-            }
-        am[j] = mask | (w >= 2 ? canonical_mask(tb.rules, r0, mask) << 16 : 0xFFFF0000u);
+        int w;
+        am[j] = neuron_applicable(x, tb.nrp[j], tb.nrp[j + 1], tb.rules, w);
         om[j] = (uint8_t)w;
     }
-}
-
-// True when some neuron's digit picks the later of two applicable twins.
-__device__ __forceinline__ bool wave_any_twin(int m, int lane, const uint8_t* om, const uint32_t* am,
-                                              const uint8_t* dg) {
-    bool nc = false;
-    for (int j = lane; j < m; j += 64)
-        if (om[j] >= 2 && !((am[j] >> (16 + dg[j])) & 1u)) nc = true;
-    return __any(nc);
 }
 
 __host__ __device__ __forceinline__ size_t table_lds_bytes(const DevSystem& s, int nnz) {
@@ -508,13 +688,13 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
     uint32_t* cp = (uint32_t*)(par + m);
     uint32_t* am = cp + m;
     uint8_t* om = (uint8_t*)(am + m);
-    uint8_t* dg = om + m;
+    uint8_t* eg = om + m;
     const T* F = (const T*)a.frontier;
     T* stage = (T*)a.stage;
     const int cnt = (int)min((long long)run, Beff - b0);
 
-    // parent of the first child: last p with off[p] <= g (it has Psi > 0),
-    // found by a 64-ary search: every lane probes one point per round
+    // parent of the first child: last p with off[p] <= g (it has a canonical
+    // child), found by a 64-ary search: every lane probes one point per round
     const u64 g = a.g0 + (u64)b0;
     long long lo = 0, hi = a.n;  // off[lo] <= g; the answer lies in [lo, hi)
     while (hi - lo > 1) {
@@ -527,30 +707,22 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
         hi = min(hi, lo + step);
     }
     long long p = uni_ll(lo);
-    u64 t = uni64(g - a.off[p]);
+    u64 u = uni64(g - a.off[p]);
     u64 psi_p = uni64(a.psi[p]);
     load_parent<T>(tb, m, F + p * (long long)m, lane, par, am, om);
     wave_lds_sync();
-    decode_digits(m, lane, t, om, dg);
+    u64 place_w = digit_place(m, lane, om);  // place values of child indices (omega)
+    canon_decode(m, lane, u, om, am, eg, canon_place(m, lane, om, am));
     wave_lds_sync();
-    for (int j = lane; j < m; j += 64) set_fired(tb, j, om, am, dg, cp);
+    for (int j = lane; j < m; j += 64) set_fired(tb, j, om, am, eg, cp);
 
     bool ovf = false;
-    uint32_t ntwin = 0;  // twin children of this wave's run
     for (int k = 0; k < cnt; ++k) {
         const long long b = b0 + k;
         wave_lds_sync();
         u64 h = 0;
         T* out = stage + b * (long long)m;
-        const bool twin = wave_any_twin(m, lane, om, am, dg);
-        ntwin += twin ? 1u : 0u;
-        if (twin) {  // a duplicate by construction: no row, no probe; cpar = -1 - parent
-            if (lane == 0) {
-                a.cpar[b] = -1 - (int)p;
-                a.ct[b] = t;
-            }
-        }
-        for (int j = lane; j < m && !twin; j += 64) {
+        for (int j = lane; j < m; j += 64) {
             long long v = (long long)par[j] - (long long)(cp[j] >> 16);
             const int e1 = tb.inp[j + 1];
             for (int e = tb.inp[j]; e < e1; ++e) v += cp[tb.ins[e]] & 0xFFFFu;
@@ -559,64 +731,66 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
             h += hterm((uint32_t)v, tb.R[j]);
         }
         h = wave_sum_u64(h);
-        if (lane == 0 && !twin) {
+        const u64 t = child_index(m, lane, om, am, eg, place_w);
+        if (lane == 0) {
             a.hash[b] = fmix64(h) & a.hash_mask;
             a.cpar[b] = (int)p;
             a.ct[b] = t;
         }
         if (k + 1 < cnt) {
-            ++t;
-            wave_lds_sync();  // every lane has read cp before it changes
-            if (t >= psi_p) {
+            ++u;
+            wave_lds_sync();  // every lane has read cp and eg before they change
+            if (u >= psi_p) {
                 ++p;
                 while (p < a.n && a.psi[p] == 0) ++p;
                 p = uni_ll(p);
                 if (p >= a.n) break;  // unreachable while g0 + B <= sum of Psi
-                t = 0;
+                u = 0;
                 psi_p = uni64(a.psi[p]);
                 load_parent<T>(tb, m, F + p * (long long)m, lane, par, am, om);
+                wave_lds_sync();
+                place_w = digit_place(m, lane, om);
                 for (int j = lane; j < m; j += 64) {
-                    dg[j] = 0;
-                    set_fired(tb, j, om, am, dg, cp);
+                    eg[j] = 0;
+                    set_fired(tb, j, om, am, eg, cp);
                 }
             } else {
                 int myJ = -1;
                 for (int j = lane; j < m; j += 64) {
-                    const int w = om[j];
-                    if (w >= 2 && dg[j] < w - 1) myJ = j;
+                    const int kp = kappa_of(am[j], om[j]);
+                    if (kp >= 2 && eg[j] < kp - 1) myJ = j;
                 }
                 const int J = wave_max_i32(myJ);
                 for (int j = lane; j < m; j += 64) {
-                    const int w = om[j];
+                    const int kp = kappa_of(am[j], om[j]);
                     if (j == J) {
-                        dg[j] = (uint8_t)(dg[j] + 1);
-                        set_fired(tb, j, om, am, dg, cp);
-                    } else if (w >= 2 && j > J) {
-                        dg[j] = 0;
-                        set_fired(tb, j, om, am, dg, cp);
+                        eg[j] = (uint8_t)(eg[j] + 1);
+                        set_fired(tb, j, om, am, eg, cp);
+                    } else if (kp >= 2 && j > J) {
+                        eg[j] = 0;
+                        set_fired(tb, j, om, am, eg, cp);
                     }
                 }
             }
         }
     }
     if (__any(ovf) && lane == 0) atomicOr((unsigned long long*)&a.ctr->overflow, 1ULL);
-    if (lane == 0 && ntwin) atomicAdd((unsigned long long*)&a.ctr->twins, (u64)ntwin);
 }
 
 // ---------------------------------------------------------------------------
 // Expansion, one neuron per lane (m <= 64, in-degree <= kLaneMaxIn).  A wave
-// walks runs of consecutive children; a run is cut into segments of one
-// parent each.  Within a segment t_a .. t_b only the digits of V, the neurons
-// with omega >= 2 from the most significant digit where t_a and t_b differ
-// on, ever change, so:
+// walks runs of consecutive canonical children; a run is cut into segments of
+// one parent each.  Within a segment u_a .. u_b only the canonical digits of
+// V, the neurons with kappa >= 2 from the most significant digit where u_a
+// and u_b differ on, ever change, so:
 //   * the first child (the reference) is computed in full, by a pull over the
 //     in-synapses (ds_bpermute) with lane j holding neuron j;
 //   * every odometer step over V has one table row U (lane j: the change to
-//     neuron j) in LDS, with its hash change (H is linear in the row) and its
-//     change of the later-twin digit count kept in the row's lane;
+//     neuron j) in LDS, with its hash change and its child-index change (both
+//     are linear in the digits) kept in the row's lane;
 //   * for up to 64 children at a time, lane l finds the step from child l to
 //     l + 1 from the digits of its V value, prefix sums over the lanes give
-//     every child's hash and twin count, and the hash, parent and child index
+//     every child's hash and child index, and the hash, parent and child index
 //     of the 64 children are stored at once;
 //   * then the children's rows follow one after the other: one LDS row added
 //     and one coalesced row store each.
@@ -627,7 +801,7 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
 // parents are fetched ahead of use.
 // ---------------------------------------------------------------------------
 constexpr int kLaneMaxIn = 16;
-constexpr int kLaneTab = 32;              // table rows per wave: sum of omega over V
+constexpr int kLaneTab = 32;              // table rows per wave: sum of kappa over V
 constexpr uint32_t kLaneOff = 1u << 16;   // count offset (c <= 65535)
 
 // Ends the wait for a loaded register here, so that the per-child loop never
@@ -642,14 +816,14 @@ __device__ __forceinline__ uint32_t udiv_small(uint32_t y, uint32_t w) {
     return r < 0 ? q - 1 : (r >= (int)w ? q + 1 : q);
 }
 
-// c, p and H(M_k) of the rule digit d picks (0 when no rule applies).
-__device__ __forceinline__ void lane_fired(const int4* rules, const u64* hrow, int r0, uint32_t am, int om, int d,
+// c, p and H(M_k) of the rule canonical digit e picks (0 when no rule applies).
+__device__ __forceinline__ void lane_fired(const int4* rules, const u64* hrow, int r0, uint32_t am, int om, int e,
                                            uint32_t& c, uint32_t& p, u64& hv) {
     c = 0;
     p = 0;
     hv = 0;
     if (om > 0) {
-        const int k = r0 + nth_bit(am & 0xFFFFu, d);
+        const int k = r0 + nth_bit(am & 0xFFFFu, canon_digit(am, om, e));
         const int4 R = rules[k];
         c = (uint32_t)R.z;
         p = (uint32_t)R.w;
@@ -657,22 +831,23 @@ __device__ __forceinline__ void lane_fired(const int4* rules, const u64* hrow, i
     }
 }
 
-__device__ __forceinline__ void lane_applicable(const int4* rules, int r0, int r1, int x, uint32_t& am, int& om) {
-    uint32_t mask = 0;
-    int w = 0;
-    for (int q = r0; q < r1; ++q)
-        if (rule_applies(x, rules[q])) {
-            mask |= 1u << (q - r0);
-            ++w;
-        }
-    am = mask | (w >= 2 ? canonical_mask(rules, r0, mask) << 16 : 0xFFFF0000u);
-    om = w;
-}
-
 __device__ __forceinline__ u64 readlane64(u64 v, int j) {
     const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, j);
     const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), j);
     return ((u64)hi << 32) | lo;
+}
+
+// Product over the lanes after this one of factors >= 1, saturated at 2^62
+// (lane 63: 1).
+__device__ __forceinline__ u64 wave_after_prod64(u64 w) {
+    u64 incl = w;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const u64 y = __shfl_down(incl, o);
+        if (__lane_id() + o < 64) incl = sat_mul(incl, y);
+    }
+    const u64 a64 = __shfl_down(incl, 1);
+    return __lane_id() == 63 ? 1 : a64;
 }
 
 template <typename T>
@@ -732,7 +907,6 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
     const long long n = a.n;
     const uint32_t hi_ok = (uint32_t)s.count_max + kLaneOff;
     uint32_t vmin = kLaneOff, vmax = kLaneOff;  // range of the stored counts (offset)
-    uint32_t ntwin = 0;                         // twin children of this wave (uniform)
     for (long long rw = wave0; rw < nruns; rw += nwaves) {
         const long long b0 = rw * run;
         const int cnt = (int)min((long long)run, Beff - b0);
@@ -754,7 +928,7 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
         int cur = 0;
         u64 pw = a.psi[min(pbase + lane, n - 1)];
         if (pbase + lane >= n) pw = 0;
-        u64 t = uni64(g - a.off[p]);
+        u64 u = uni64(g - a.off[p]);
         int x = (int)F[p * (long long)m + jl];
         settle(x);
         u64 psi_p = uni64(__shfl(pw, 0));
@@ -770,60 +944,55 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
         }
         uint32_t am;
         int om;
-        lane_applicable(l_rules, r0, r1, x, am, om);
+        am = neuron_applicable(x, r0, r1, l_rules, om);
+        // kappa of this lane's neuron and the place value of its digit in the
+        // child index (product of max(1, omega) over later lanes)
+        int kp = kappa_of(am, om);
+        u64 place_w = wave_after_prod64((u64)max(1, om));
 
         int k = 0;
         while (k < cnt) {
-            // ---- a segment: children t .. t + len - 1 of parent p ----
-            int len = (int)min((u64)(cnt - k), psi_p - t);
-            // place value of lane j: product of max(1, omega) over later lanes.
-            // Digit j of child index x is (x / place_j) mod max(1, omega_j).  When
-            // Psi of the parent fits 32 bits so does every index of the segment,
-            // and place values saturated at 2^32 - 1 still compare right with
-            // them: the whole decomposition then runs in 32-bit arithmetic.
+            // ---- a segment: canonical children u .. u + len - 1 of parent p ----
+            int len = (int)min((u64)(cnt - k), psi_p - u);
+            // place value of lane j over canonical digits: product of kappa over
+            // later lanes.  Digit j of canonical index y is (y / place_j) mod
+            // kappa_j.  When the parent's canonical count fits 32 bits so does
+            // every index of the segment, and place values saturated at 2^32 - 1
+            // still compare right with them: the whole decomposition then runs
+            // in 32-bit arithmetic.
             const bool narrow = psi_p <= 0xFFFFFFFFull;  // uniform
-            const uint32_t w1 = (uint32_t)max(1, om);
+            const uint32_t w1 = (uint32_t)kp;
             u64 after = 1;
-            if (narrow) {
-                after = wave_after_prod_sat32(w1);
-            } else {
-                u64 incl = w1;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const u64 y = __shfl_down(incl, o);
-                    if (lane + o < 64) incl = sat_mul(incl, y);
-                }
-                const u64 a64 = __shfl_down(incl, 1);
-                after = lane == 63 ? 1 : a64;
-            }
-            auto quot = [&](u64 x) -> u64 {
+            if (narrow) after = wave_after_prod_sat32(w1);
+            else after = wave_after_prod64(w1);
+            auto quot = [&](u64 y) -> u64 {
                 if (narrow) {
-                    const uint32_t x32 = (uint32_t)x, a32 = (uint32_t)after;
-                    return a32 > x32 ? 0u : x32 / a32;
+                    const uint32_t y32 = (uint32_t)y, a32 = (uint32_t)after;
+                    return a32 > y32 ? 0u : y32 / a32;
                 }
-                return after > x ? 0 : x / after;
+                return after > y ? 0 : y / after;
             };
-            const u64 qa = quot(t);
+            const u64 qa = quot(u);
             const int dg0 = narrow ? (int)((uint32_t)qa % w1) : (int)(qa % w1);
-            // V: neurons with omega >= 2 from the most significant digit that
+            // V: neurons with kappa >= 2 from the most significant digit that
             // changes inside the segment; halve the segment until its tables fit
             u64 vmask;
             int nt;
             for (;;) {
-                const u64 tb = t + (u64)(len - 1);
-                const u64 qb = quot(tb);
+                const u64 ub = u + (u64)(len - 1);
+                const u64 qb = quot(ub);
                 const u64 dif = __ballot(act && qa != qb);
                 const int jstar = dif ? __builtin_ctzll(dif) : 64;
-                vmask = __ballot(act && om >= 2 && lane >= jstar);
-                nt = (int)wave_sum_u32((vmask >> lane) & 1 ? (uint32_t)om : 0u);
+                vmask = __ballot(act && kp >= 2 && lane >= jstar);
+                nt = (int)wave_sum_u32((vmask >> lane) & 1 ? (uint32_t)kp : 0u);
                 if (nt <= kLaneTab && __popcll(vmask) <= 16) break;
                 len = (len + 1) / 2;
             }
             const bool inV = (vmask >> lane) & 1;
-            // table base of every V lane: omega summed over earlier V lanes
-            const uint32_t tb_incl = wave_incl_u32(inV ? (uint32_t)om : 0u);
-            const int tbase = (int)tb_incl - (inV ? om : 0);
-            // the reference child (digits dg0) in full
+            // table base of every V lane: kappa summed over earlier V lanes
+            const uint32_t tb_incl = wave_incl_u32(inV ? (uint32_t)kp : 0u);
+            const int tbase = (int)tb_incl - (inV ? kp : 0);
+            // the reference child (canonical digits dg0) in full, with its child index
             int dg = dg0;
             uint32_t c, pp;
             u64 hv;
@@ -838,23 +1007,24 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
             }
             uint32_t val = wv - c + kLaneOff;
             u64 Hs = wave_sum_u64(act ? (u64)(uint32_t)x * Rj + hv : 0);
-            // Step tables.  T[v][d][j]: change to neuron j when V neuron v fires its
-            // d-th applicable rule (-c on j = v, +p on the targets of v).  One
-            // odometer step moves the last V neuron that can step up from d to
-            // d + 1 and resets every later V neuron from its top digit to 0, so
-            // its whole effect is one row per (v, d):
-            //   U[v][d] = T[v][d+1] - T[v][d] + sum over later V neurons v' of
+            const u64 Ts = wave_sum_u64(act ? (u64)canon_digit(am, om, dg0) * place_w : 0);
+            // Step tables.  T[v][e][j]: change to neuron j when V neuron v fires its
+            // e-th canonical rule (-c on j = v, +p on the targets of v).  One
+            // odometer step moves the last V neuron that can step up from e to
+            // e + 1 and resets every later V neuron from its top digit to 0, so
+            // its whole effect is one row per (v, e):
+            //   U[v][e] = T[v][e+1] - T[v][e] + sum over later V neurons v' of
             //             (T[v'][0] - T[v'][top]),
-            // likewise for the row hash (H is linear in the row) and for the
-            // count of digits that pick a later twin.  Row r = tbase_v + d: lane r
-            // first fetches the rule of row r, then one pass over the rows, last V
-            // neuron first, writes the U rows to LDS (lane = neuron) and leaves
-            // the hash and twin-count changes of row r in lane r.
-            int rv = 0, rd = 0, rb = 0, rw = 0;  // lane r < nt: V neuron, digit, its first row, omega
+            // likewise for the row hash and for the child index (both linear in
+            // the digits).  Row r = tbase_v + e: lane r first fetches the rule of
+            // row r, then one pass over the rows, last V neuron first, writes the
+            // U rows to LDS (lane = neuron) and leaves the hash and child-index
+            // changes of row r in lane r.
+            int rv = 0, rd = 0, rb = 0, rw = 0;  // lane r < nt: V neuron, canonical digit, its first row, kappa
             for (u64 vq = vmask; vq; vq &= vq - 1) {
                 const int v = __builtin_ctzll(vq);
                 const int b = __builtin_amdgcn_readlane(tbase, v);
-                const int w = __builtin_amdgcn_readlane(om, v);
+                const int w = __builtin_amdgcn_readlane(kp, v);
                 const bool own = lane >= b && lane < b + w;
                 rv = own ? v : rv;
                 rd = own ? lane - b : rd;
@@ -864,27 +1034,30 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
             // (shuffles run on every lane: a source lane must not be masked off)
             const bool isrow = lane < nt;
             const uint32_t amr = (uint32_t)__shfl((int)am, rv);
+            const int omr = __shfl(om, rv);
             const int r0r = __shfl(r0, rv);
-            const int kr = isrow ? r0r + nth_bit(amr & 0xFFFFu, rd) : 0;
+            const u64 plr = __shfl(place_w, rv);
+            const int dr = canon_digit(amr, omr, rd);
+            const int kr = isrow ? r0r + nth_bit(amr & 0xFFFFu, dr) : 0;
             const int4 Rr = l_rules[kr];
             const u64 hr = isrow ? l_hM[kr] : 0;
-            const uint32_t ncr = isrow && !((amr >> (16 + rd)) & 1u) ? 1u : 0u;
-            // hash and twin-count rows, lane-parallel: row r (not a top digit)
-            // takes h[r+1] - h[r] plus, over the later V neurons, h[0] - h[top];
+            const u64 tr = isrow ? (u64)dr * plr : 0;
+            // hash and child-index rows, lane-parallel: row r (not a top digit)
+            // takes x[r+1] - x[r] plus, over the later V neurons, x[0] - x[top];
             // those sums are suffix sums over the rows from the next neuron's first
             const int rtop = max(rb + rw - 1, 0);
             const u64 htop = __shfl(hr, rtop), hnext = __shfl(hr, min(lane + 1, 63));
-            const uint32_t ntop = (uint32_t)__shfl((int)ncr, rtop), nnext = (uint32_t)__shfl((int)ncr, min(lane + 1, 63));
+            const u64 ttop = __shfl(tr, rtop), tnext = __shfl(tr, min(lane + 1, 63));
             const u64 e1 = isrow && rd == 0 ? hr - htop : 0;
-            const uint32_t n1 = isrow && rd == 0 ? ncr - ntop : 0u;
+            const u64 f1 = isrow && rd == 0 ? tr - ttop : 0;
             // suffix sums (rows r .. 63) as total - prefix + own term
             const u64 ph = wave_incl_u64(e1);
-            const uint32_t pn = wave_incl_u32(n1);
+            const u64 pt = wave_incl_u64(f1);
             const u64 eh = readlane64(ph, 63) - ph + e1;
-            const uint32_t en = (uint32_t)__builtin_amdgcn_readlane((int)pn, 63) - pn + n1;
+            const u64 et = readlane64(pt, 63) - pt + f1;
             const int nxt = rb + rw;  // <= nt <= 32: rows from there on sum to the later neurons'
             const u64 hU = hnext - hr + __shfl(eh, nxt);
-            const uint32_t nU = nnext - ncr + (uint32_t)__shfl((int)en, nxt);
+            const u64 tU = tnext - tr + __shfl(et, nxt);
             // the U rows, lane = neuron j, rows from the last down (later V
             // neurons first): Sv sums T[v'][0] - T[v'][top] over the later ones
             const int rflag = (rd == rw - 1 ? 1 : 0) | (rd == 0 ? 2 : 0);
@@ -903,20 +1076,17 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
                 }
             }
             wave_lds_sync();
-            // twins: a non-V neuron picking a later twin makes the whole segment
-            // twins; V neurons count their non-canonical digits
-            const bool nc = act && om >= 2 && !((am >> (16 + dg0)) & 1u);
-            const bool fixed_twin = __ballot(nc && !inV) != 0;
-            // the reference child's digits over V as one mixed-radix number (the
-            // last V neuron lowest); it stays below the product of omega over V
-            // (< 2^17 for tables of at most 32 rows) for the whole segment
+            // the reference child's canonical digits over V as one mixed-radix
+            // number (the last V neuron lowest); it stays below the product of
+            // kappa over V (< 2^17 for tables of at most 32 rows) for the whole
+            // segment
             uint32_t x0 = 0;
             for (u64 vq = vmask; vq; vq &= vq - 1) {
                 const int v = __builtin_ctzll(vq);
-                x0 = x0 * (uint32_t)__builtin_amdgcn_readlane(om, v) + (uint32_t)__builtin_amdgcn_readlane(dg0, v);
+                x0 = x0 * (uint32_t)__builtin_amdgcn_readlane(kp, v) + (uint32_t)__builtin_amdgcn_readlane(dg0, v);
             }
             u64 Hc = uni64(Hs);  // hash of the chunk's first child
-            uint32_t vc = __builtin_amdgcn_readfirstlane((uint32_t)__popcll(__ballot(nc && inV)));
+            u64 Tc = uni64(Ts);  // its child index
             int rowc = 0;        // step row into the chunk's first child (chunks after the first)
             len = __builtin_amdgcn_readfirstlane(len);
             T* srow = stage + (b0 + k) * (long long)m + lane;
@@ -932,7 +1102,7 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
                 for (u64 vq = vmask; vq && __any(carry && step);) {
                     const int v = 63 - __clzll((long long)vq);  // lowest digit first
                     vq &= ~(1ULL << v);
-                    const uint32_t w = (uint32_t)__builtin_amdgcn_readlane(om, v);
+                    const uint32_t w = (uint32_t)__builtin_amdgcn_readlane(kp, v);
                     const int bv = __builtin_amdgcn_readlane(tbase, v);
                     const uint32_t q = udiv_small(y, w);
                     const uint32_t dgt = y - q * w;
@@ -941,43 +1111,38 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
                     carry = carry && !here;
                     y = q;
                 }
-                // hash and twin count of child c0 + l: the chunk's first child's
+                // hash and child index of child c0 + l: the chunk's first child's
                 // plus the changes of the steps of lanes before l
                 const u64 hrow = __shfl(hU, row);
-                const uint32_t nrow = (uint32_t)__shfl((int)nU, row);
+                const u64 trow = __shfl(tU, row);
                 const u64 hstep = step ? hrow : 0;
-                const uint32_t nstep = step ? nrow : 0u;
+                const u64 tstep = step ? trow : 0;
                 const u64 hin = wave_incl_u64(hstep);
-                const uint32_t nin = wave_incl_u32(nstep);
+                const u64 tin = wave_incl_u64(tstep);
                 const bool mine = lane < nch;
-                const bool twin = fixed_twin || vc + (nin - nstep) != 0;
                 const long long bq = b0 + k + c0 + lane;
                 const u64 key = fmix64(Hc + (hin - hstep)) & a.hash_mask;
                 // visited-set probe of child bq: the CAS on its home slot is
                 // issued here and its answer read after the rows are written
-                // (twins never own an entry)
-                const bool probe = mine && !twin && a.table != nullptr;
+                const bool probe = mine && a.table != nullptr;
                 const u64 me = ((key >> 32) << 32) | (u64)(kStageBase + (uint32_t)bq);
                 u64 psl = key & a.slot_mask;
                 u64 first = kEmpty;
                 if (mine) {
                     a.hash[bq] = key;
-                    a.cpar[bq] = twin ? -1 - (int)p : (int)p;
-                    a.ct[bq] = t + (u64)(c0 + lane);
+                    a.cpar[bq] = (int)p;
+                    a.ct[bq] = Tc + (tin - tstep);
                     if (probe) first = atomicCAS(&a.table[psl], kEmpty, me);
-                    else if (a.table) a.slot[bq] = 0;
                 }
-                const u64 twins = __ballot(twin && mine);
-                ntwin += (uint32_t)__popcll(twins);
                 Hc += readlane64(hin, 63);
-                vc += (uint32_t)__builtin_amdgcn_readlane((int)nin, 63);
+                Tc += readlane64(tin, 63);
                 // the rows, one child after the other: one table row per step,
                 // read one child ahead
-                uint32_t u = c0 > 0 ? l_tab[rowc * 64 + lane] : 0u;
+                uint32_t uv = c0 > 0 ? l_tab[rowc * 64 + lane] : 0u;
                 for (int l = 0; l < nch; ++l) {
-                    val += u;
-                    if (l + 1 < nch) u = l_tab[__builtin_amdgcn_readlane(row, l) * 64 + lane];
-                    if (!((twins >> l) & 1) && act) {
+                    val += uv;
+                    if (l + 1 < nch) uv = l_tab[__builtin_amdgcn_readlane(row, l) * 64 + lane];
+                    if (act) {
                         *srow = (T)(val - kLaneOff);
                         vmin = min(vmin, val);
                         vmax = max(vmax, val);
@@ -1018,10 +1183,10 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
                 }
             }
             k += len;
-            t += (u64)len;
+            u += (u64)len;
             if (k >= cnt) break;
-            if (t >= psi_p) {
-                // next parent with Psi > 0
+            if (u >= psi_p) {
+                // next parent with canonical children
                 u64 nb = __ballot(pw > 0 && lane > cur);
                 while (nb == 0) {
                     pbase += 64;
@@ -1035,7 +1200,7 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
                 cur = __builtin_ctzll(nb);
                 p = pbase + cur;
                 psi_p = uni64(__shfl(pw, cur));
-                t = 0;
+                u = 0;
                 if (p == pf_p) x = pf_x;
                 else x = (int)F[p * (long long)m + jl];
                 settle(x);
@@ -1045,14 +1210,15 @@ __global__ __launch_bounds__(256) void k_expand_lane(DevSystem s, ChunkArgs a) {
                     pf_p = pbase + __builtin_ctzll(nb2);
                     pf_x = (int)F[pf_p * (long long)m + jl];
                 }
-                lane_applicable(l_rules, r0, r1, x, am, om);
+                am = neuron_applicable(x, r0, r1, l_rules, om);
+                kp = kappa_of(am, om);
+                place_w = wave_after_prod64((u64)max(1, om));
             }
             wave_lds_sync();  // the tables are rebuilt for the next segment
         }
     }
     const bool ovf = vmin < kLaneOff || vmax > hi_ok;
     if (__any(ovf) && lane == 0) atomicOr((unsigned long long*)&a.ctr->overflow, 1ULL);
-    if (lane == 0 && ntwin) atomicAdd((unsigned long long*)&a.ctr->twins, (u64)ntwin);
 }
 
 hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkArgs& a, hipStream_t st,
@@ -1121,8 +1287,7 @@ __global__ __launch_bounds__(256) void k_insert_probe(int m, TableArgs a) {
     const long long b = (long long)blockIdx.x * 256 + threadIdx.x;
     const long long Beff = (long long)a.ctr->beff;
     bool queue = false;
-    if (b < Beff && a.cpar[b] < 0) a.slot[b] = 0;  // twin: never a first occurrence
-    else if (b < Beff) {
+    if (b < Beff) {
         const u64 h = a.hash[b];
         const uint32_t tag = (uint32_t)(h >> 32);
         const u64 mine = ((u64)tag << 32) | (kStageBase + (uint32_t)b);
@@ -1227,13 +1392,13 @@ hipError_t launch_insert(int elem_bytes, int m, const TableArgs& a, hipStream_t 
 constexpr long long kCommitTiles = 1024;
 
 // New-child flags of a chunk: flag[b] = 1 when child b is enumerated
-// (b < beff), not a twin, and owns its visited-set entry.  Within each tile
-// of kScanTile children, pos[b] = flags before b and tile_sums[tile] = all
-// flags of the tile.
+// (b < beff) and owns its visited-set entry.  Within each tile of kScanTile
+// children, pos[b] = flags before b and tile_sums[tile] = all flags of the
+// tile.
 __global__ __launch_bounds__(256) void k_flag_tiles(const u64* __restrict__ table, const uint32_t* __restrict__ slot,
-                                                    const int* __restrict__ cpar, long long B,
-                                                    const DevCounters* __restrict__ ctr, uint32_t* __restrict__ flag,
-                                                    uint32_t* __restrict__ pos, uint32_t* __restrict__ tile_sums) {
+                                                    long long B, const DevCounters* __restrict__ ctr,
+                                                    uint32_t* __restrict__ flag, uint32_t* __restrict__ pos,
+                                                    uint32_t* __restrict__ tile_sums) {
     __shared__ uint32_t wsum[4];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const long long beff = min(B, (long long)ctr->beff);
@@ -1242,7 +1407,7 @@ __global__ __launch_bounds__(256) void k_flag_tiles(const u64* __restrict__ tabl
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const long long b = base + i;
-        f[i] = (b < beff && cpar[b] >= 0 && (uint32_t)table[slot[b]] == kStageBase + (uint32_t)b) ? 1u : 0u;
+        f[i] = (b < beff && (uint32_t)table[slot[b]] == kStageBase + (uint32_t)b) ? 1u : 0u;
         loc[i] = run;
         run += f[i];
     }
@@ -1265,11 +1430,11 @@ __global__ __launch_bounds__(256) void k_flag_tiles(const u64* __restrict__ tabl
     if (threadIdx.x == 255) tile_sums[blockIdx.x] = tpre + run;
 }
 
-hipError_t launch_flags(const u64* table, const uint32_t* slot, const int* cpar, long long B, DevCounters* ctr,
-                        uint32_t* flag, uint32_t* pos, uint32_t* tile_sums, uint32_t* tile_pre, hipStream_t st) {
+hipError_t launch_flags(const u64* table, const uint32_t* slot, long long B, DevCounters* ctr, uint32_t* flag,
+                        uint32_t* pos, uint32_t* tile_sums, uint32_t* tile_pre, hipStream_t st) {
     if (B <= 0) return hipSuccess;
     const long long nt = scan_tiles(B);
-    hipLaunchKernelGGL(k_flag_tiles, dim3((unsigned)nt), dim3(256), 0, st, table, slot, cpar, B, ctr, flag, pos,
+    hipLaunchKernelGGL(k_flag_tiles, dim3((unsigned)nt), dim3(256), 0, st, table, slot, B, ctr, flag, pos,
                        tile_sums);
     if (nt > kCommitTiles)  // the commit reads the tile prefix (and the host the total) from here
         hipLaunchKernelGGL((k_scan_sums<uint32_t, false>), dim3(1), dim3(1024), 0, st, tile_sums, tile_pre, nt,
@@ -1333,6 +1498,7 @@ __global__ __launch_bounds__(256) void k_commit(int upr /* units per row */, Com
             if (local == a.limit - 1) {
                 a.ctr->cap_g = (u64)b + 1;
                 a.ctr->cap_par = (u64)a.cpar[b];
+                a.ctr->cap_t = a.ct[b];
                 s_cap_par = a.cpar[b];
             }
         } else {
@@ -1341,11 +1507,26 @@ __global__ __launch_bounds__(256) void k_commit(int upr /* units per row */, Com
     }
     const int nnew = __syncthreads_count(isnew);
     if (a.hflag && s_cap_par >= 0) {
-        // this block filled the cap: halting parents up to the cap child's parent
+        // this block filled the cap: halting parents up to the cap child's
+        // parent, and all children of the parents before it
         uint32_t c = 0;
-        for (int i = threadIdx.x; i <= s_cap_par; i += 256) c += a.hflag[i];
+        u64 flo = 0, fhi = 0;
+        for (int i = threadIdx.x; i <= s_cap_par; i += 256) {
+            c += a.hflag[i];
+            if (i < s_cap_par) {
+                const u64 f = a.psif[i];
+                flo += f & 0x7FFFFFFFull;
+                fhi += f >> 31;
+            }
+        }
         c = wave_sum_u32(c);
-        if ((threadIdx.x & 63) == 0 && c) atomicAdd((unsigned long long*)&a.ctr->count, (u64)c);
+        flo = wave_sum_u64(flo);
+        fhi = wave_sum_u64(fhi);
+        if ((threadIdx.x & 63) == 0) {
+            if (c) atomicAdd((unsigned long long*)&a.ctr->count, (u64)c);
+            if (flo) atomicAdd((unsigned long long*)&a.ctr->capf_lo, flo);
+            if (fhi) atomicAdd((unsigned long long*)&a.ctr->capf_hi, fhi);
+        }
     }
     const long long first_local = a.level_count + (long long)p0;
     const int ncopy = (int)max(0LL, min((long long)nnew, a.limit - first_local));
@@ -1492,7 +1673,7 @@ __global__ __launch_bounds__(256) void k_start_walk(int m, const u64* __restrict
                                                     uint32_t* __restrict__ row_slot, DevCounters* __restrict__ sc,
                                                     long long* par0, long long* chi0, const int* nrp,
                                                     const int4* rules, long long expand_max, u64 psi_cap,
-                                                    u64* psi0, uint8_t* hflag0, u64* off0, u64* Tdev) {
+                                                    u64* psi0, u64* psif0, uint8_t* hflag0, u64* off0, u64* Tdev) {
     __shared__ u64 s_slot, s_entry;
     const int lane = threadIdx.x & 63;
     if (threadIdx.x < 64) {
@@ -1518,9 +1699,9 @@ __global__ __launch_bounds__(256) void k_start_walk(int m, const u64* __restrict
     const int nbad = __syncthreads_count(bad);
     // Psi of C0 (the first level's only parent), its halting flag and offset,
     // when asked: the first pass then needs no Psi launch of its own
-    u64 psi_c0 = 0;
+    PsiPair psi_c0{0, 0};
     bool halt_c0 = false;
-    if (psi0 && threadIdx.x < 64) psi_c0 = min(parent_psi<T>(c0, m, nrp, rules, expand_max, lane, halt_c0), psi_cap);
+    if (psi0 && threadIdx.x < 64) psi_c0 = parent_psi<T>(c0, m, nrp, rules, expand_max, lane, halt_c0);
     if (threadIdx.x == 0) {
         row_slot[0] = (uint32_t)home;
         if (par0) *par0 = -1;
@@ -1528,11 +1709,15 @@ __global__ __launch_bounds__(256) void k_start_walk(int m, const u64* __restrict
         DevCounters z{};
         z.c0_bad = nbad ? 1 : 0;
         if (psi0) {
-            psi0[0] = psi_c0;
+            const u64 canon = min(psi_c0.canon, psi_cap), full = min(psi_c0.full, psi_cap);
+            psi0[0] = canon;
+            psif0[0] = full;
             hflag0[0] = halt_c0 ? 1 : 0;
             off0[0] = 0;
-            *Tdev = psi_c0;
-            z.psi_total = psi_c0;
+            *Tdev = canon;
+            z.psi_total = canon;
+            z.psif_lo = full & 0x7FFFFFFFull;
+            z.psif_hi = full >> 31;
             z.halting = halt_c0 ? 1 : 0;
         }
         *sc = z;
@@ -1542,16 +1727,16 @@ __global__ __launch_bounds__(256) void k_start_walk(int m, const u64* __restrict
 hipError_t launch_start_walk(int elem_bytes, int m, const u64* R, u64* table, u64 slot_mask, const void* c0,
                              void* arena, long long count_max, u64 hash_mask, uint32_t* row_slot, DevCounters* sc,
                              long long* par0, long long* chi0, const DevSystem& s, long long expand_max, u64* psi0,
-                             uint8_t* hflag0, u64* off0, u64* Tdev, hipStream_t st) {
+                             u64* psif0, uint8_t* hflag0, u64* off0, u64* Tdev, hipStream_t st) {
     const unsigned blocks = (unsigned)std::min<u64>((slot_mask + 256) / 256, 4096);
     if (elem_bytes == 4)
         hipLaunchKernelGGL(k_start_walk<int32_t>, dim3(blocks), dim3(256), 0, st, m, R, table, slot_mask,
                            (const int32_t*)c0, (int32_t*)arena, count_max, hash_mask, row_slot, sc, par0, chi0,
-                           s.nrule_ptr, s.rules, expand_max, s.psi_cap, psi0, hflag0, off0, Tdev);
+                           s.nrule_ptr, s.rules, expand_max, s.psi_cap, psi0, psif0, hflag0, off0, Tdev);
     else
         hipLaunchKernelGGL(k_start_walk<uint16_t>, dim3(blocks), dim3(256), 0, st, m, R, table, slot_mask,
                            (const uint16_t*)c0, (uint16_t*)arena, count_max, hash_mask, row_slot, sc, par0, chi0,
-                           s.nrule_ptr, s.rules, expand_max, s.psi_cap, psi0, hflag0, off0, Tdev);
+                           s.nrule_ptr, s.rules, expand_max, s.psi_cap, psi0, psif0, hflag0, off0, Tdev);
     return hipGetLastError();
 }
 

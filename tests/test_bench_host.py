@@ -27,15 +27,16 @@ def test_roofline_new_rows():
     assert r["dominant_kernel"]["launches_per_step"] == 2
 
 
-def test_roofline_lane_form_twins_and_steps():
-    # two steps of two launches; 10 of the 1000 children of a step are twins
-    # (12 bytes each), the rest write a 256-byte row + 32 bytes: 285240 bytes per step
-    step = dict(level_stats=[_level(100000, 1, 400, 0), _level(185240, 1, 600, 10)])
-    r = bench.hbm_roofline([step, step], "k_expand_lane", None, 256, twins_written=True)
+def test_roofline_lane_form_per_child_and_steps():
+    # two steps of two launches; each of the 1000 children computed in a step
+    # writes a 256-byte row + 32 bytes (twins are never computed, so the
+    # level's twin count adds nothing): 288000 bytes per step
+    step = dict(level_stats=[_level(100000, 1, 400, 0), _level(188000, 1, 600, 10)])
+    r = bench.hbm_roofline([step, step], "k_expand_lane", None, 256, per_child=True)
     assert r["roofline"]["achieved"] == 1.0
     assert r["dominant_kernel"]["launches_per_step"] == 2
-    assert r["dominant_kernel"]["bytes_per_launch"] == 285240 // 2
-    assert r["dominant_kernel"]["kernel_us_per_step"] == 285.24
+    assert r["dominant_kernel"]["bytes_per_launch"] == 288000 // 2
+    assert r["dominant_kernel"]["kernel_us_per_step"] == 288.0
 
 
 def test_mfma_utilisation():
