@@ -306,6 +306,27 @@ snp_status snp_batch_run(snp_batch *b, const void *c0_dev, int32_t steps, int32_
                          void *final_dev, int32_t *halt_step, int32_t *first_repeat, int32_t *steps_done,
                          uint64_t *digest);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same run
+ * as snp_batch_run, with the same arguments and results, but every scratch
+ * buffer of the run (per-system results, checkpoint rows, H sets) lives in
+ * one static device array of the library (32 MiB, held by every device the
+ * library runs on until the process ends), and the call makes no allocation
+ * of any kind: no hipMalloc or hipFree, no HIP graph, no events.  The launch
+ * shape is the one an earlier snp_batch_run on this batch picked, else the
+ * widest candidate (no timing).
+ * Every call on one device shares that device's array: calls that overlap on
+ * one device (other threads, other streams) race and must not be made.  The
+ * H sets are cleared by a kernel at the start of every call; every other
+ * result is written in full by the run.
+ * Errors: SNP_ERR_CAPACITY when the run needs more scratch than the array
+ *   holds (about (4 + 2 n) x 64 B for n systems, plus steps / 64 + 1
+ *   checkpoint rows of every system, plus 12 x 2^ceil(log2(2 steps + 2)) B per
+ *   system with repeat detection); otherwise as snp_batch_run. */
+snp_status snp_batch_run_static(snp_batch *b, const void *c0_dev, int32_t steps, int32_t detect_repeats,
+                                void *final_dev, int32_t *halt_step, int32_t *first_repeat,
+                                int32_t *steps_done, uint64_t *digest);
+
 /* Deterministic branch of n systems loaded with snp_load, in one launch
  * (the batched mode above, built from the handles' descriptions on the first
  * call with this list of handles and kept for later calls with the same list).

@@ -9,6 +9,7 @@
 #include <atomic>
 #include <climits>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -155,6 +156,7 @@ struct snp_batch {
     int *d_nrp = nullptr, *d_in_ptr = nullptr, *d_in_src = nullptr;
     // per-run buffers, grown on demand
     int cap_steps = -1;
+    long long ckpt_rows = 0;
     void* d_ckpt = nullptr;
     u64* d_hkey = nullptr;
     int* d_hstep = nullptr;
@@ -920,6 +922,12 @@ snp_status snp_run(snp_system* S, const void* c0_dev, int32_t max_depth, void* o
     return done(SNP_OK);
 }
 
+// Checkpoint rows per system of a deterministic run of `steps` steps (one
+// every batch_interval() steps, step 0 included), and slots per system of its
+// H set (at most half full).
+static long long batch_ckpt_rows(int steps) { return steps / snp::batch_interval() + 1; }
+static u64 batch_table_slots(int steps) { return next_pow2((u64)std::max(64, 2 * (steps + 1))); }
+
 // Multiplier m of the exact quotient x / d for every 32-bit x and 2 <= d < 2^8
 // (Granlund and Montgomery, 1994): with l = ceil(log2 d) and t = mulhi(m, x),
 // x / d = (t + ((x - t) >> 1)) >> (l - 1).  0 for d < 2 (not used).
@@ -1034,6 +1042,7 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
     BLOADCHK(dmalloc(&b->d_err, sizeof(u64) * n));
     if (!rules.empty()) BLOADCHK(hipMemcpy(b->d_rules, rules.data(), sizeof(uint32_t) * rules.size(), hipMemcpyHostToDevice));
     if (!magic.empty()) BLOADCHK(hipMemcpy(b->d_magic, magic.data(), sizeof(uint32_t) * magic.size(), hipMemcpyHostToDevice));
+    BLOADCHK(hipMemcpy(b->d_sys, sys.data(), sizeof(snp::BatchSys) * n, hipMemcpyHostToDevice));
     BLOADCHK(hipMemcpy(b->d_nrp, nrp.data(), sizeof(int) * nrp.size(), hipMemcpyHostToDevice));
     BLOADCHK(hipMemcpy(b->d_in_ptr, in_ptr.data(), sizeof(int) * in_ptr.size(), hipMemcpyHostToDevice));
     if (!in_src.empty())
@@ -1076,24 +1085,16 @@ snp_status snp_batch_run(snp_batch* b, const void* c0_dev, int32_t steps, int32_
         b->d_ckpt = nullptr;
         b->d_hkey = nullptr;
         b->d_hstep = nullptr;
-        const long long rows = steps / interval + 1;
-        long long ck = 0;
-        for (int k = 0; k < b->n; ++k) {
-            b->sys[k].ckpt_off = ck;
-            b->sys[k].ckpt_stride = b->sys[k].m;
-            ck += rows * b->sys[k].m;
-        }
-        b->table_slots = next_pow2((u64)std::max(64, 2 * (steps + 1)));
-        for (int k = 0; k < b->n; ++k) b->sys[k].table_off = (long long)k * (long long)b->table_slots;
-        HIPCHK(dmalloc(&b->d_ckpt, (size_t)ck * b->elem_bytes));
+        b->ckpt_rows = batch_ckpt_rows(steps);
+        b->table_slots = batch_table_slots(steps);
+        HIPCHK(dmalloc(&b->d_ckpt, (size_t)(b->ckpt_rows * b->row_off[b->n]) * b->elem_bytes));
         HIPCHK(dmalloc(&b->d_hkey, sizeof(u64) * b->table_slots * b->n));
         HIPCHK(dmalloc(&b->d_hstep, sizeof(int) * b->table_slots * b->n));
-        HIPCHK(hipMemcpy(b->d_sys, b->sys.data(), sizeof(snp::BatchSys) * b->n, hipMemcpyHostToDevice));
         b->cap_steps = steps;
     }
     snp::BatchArgs a{b->d_sys, b->d_rules, b->d_magic, b->d_nrp, b->d_in_ptr, b->d_in_src, c0_dev, final_dev, b->d_ckpt,
-                     b->d_hkey, b->d_hstep, b->table_slots, b->m_max, b->r_max, steps, detect_repeats ? 1 : 0,
-                     b->count_max, b->d_halt, b->d_rep, b->d_done, b->d_digest, b->d_err};
+                     b->ckpt_rows, b->d_hkey, b->d_hstep, b->table_slots, b->m_max, b->r_max, steps,
+                     detect_repeats ? 1 : 0, b->count_max, b->d_halt, b->d_rep, b->d_done, b->d_digest, b->d_err};
     auto enqueue = [&](hipStream_t st, int threads, int npt) -> hipError_t {
         if (detect_repeats) {
             const hipError_t e = snp::launch_fill_i32(b->d_hstep, (long long)b->table_slots * b->n, -1, st);
@@ -1253,3 +1254,112 @@ snp_status snp_run_batch(snp_system* const* systems, int32_t n, const void* cons
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// snp_batch_run_static: the deterministic batched run with every scratch
+// buffer (per-system results, checkpoint rows, H sets) carved from one
+// file-scope device array, so that the call allocates nothing.  Each device
+// the library runs on holds its own copy of the array until the process ends;
+// its address is looked up once per device and kept.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (the array's name in host
+// code is not a device address).
+snp_status static_scratch(unsigned char** out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SNP_ERR_DEVICE, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(SNP_ERR_DEVICE, "no device address for the static scratch array");
+        g_scratch_dev[dev] = p;
+    }
+    *out = (unsigned char*)g_scratch_dev[dev];
+    return SNP_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+}  // namespace
+
+extern "C" snp_status snp_batch_run_static(snp_batch* b, const void* c0_dev, int32_t steps, int32_t detect_repeats,
+                                           void* final_dev, int32_t* halt_step, int32_t* first_repeat,
+                                           int32_t* steps_done, uint64_t* digest) {
+    g_err.clear();
+    if (!b) return fail(SNP_ERR_INVALID, "batch is NULL");
+    if (!c0_dev || !final_dev || !halt_step || !first_repeat || !steps_done || !digest)
+        return fail(SNP_ERR_INVALID, "c0, final and every result array are required");
+    if (steps < 0 || steps > (1 << 24)) return fail(SNP_ERR_INVALID, "steps must be in [0, 2^24]");
+    const int n = b->n;
+    const long long rows = batch_ckpt_rows(steps);
+    const u64 slots = batch_table_slots(steps);
+    // layout: halt, first repeat, steps done (int32 each), digest, error bits
+    // (uint64 each), checkpoint rows, then the H sets (repeat detection only)
+    size_t o = 0;
+    const size_t o_halt = o;
+    o = align256(o + sizeof(int) * n);
+    const size_t o_rep = o;
+    o = align256(o + sizeof(int) * n);
+    const size_t o_done = o;
+    o = align256(o + sizeof(int) * n);
+    const size_t o_dig = o;
+    o = align256(o + sizeof(u64) * n);
+    const size_t o_err = o;
+    o = align256(o + sizeof(u64) * n);
+    const size_t o_ckpt = o;
+    o = align256(o + (size_t)(rows * b->row_off[n]) * b->elem_bytes);
+    const size_t o_hstep = o, o_hkey = align256(o + sizeof(int) * slots * n);
+    if (detect_repeats) o = align256(o_hkey + sizeof(u64) * slots * n);
+    if (o > kStaticScratchBytes)
+        return fail(SNP_ERR_CAPACITY, "snp_batch_run_static: %d systems x %d steps need %zu bytes of scratch, above "
+                    "the static %zu (use snp_batch_run, or fewer systems or steps)", n, steps, o,
+                    kStaticScratchBytes);
+    unsigned char* base = nullptr;
+    snp_status st = static_scratch(&base);
+    if (st) return st;
+    // launch shape: the one an earlier snp_batch_run tuned, else the widest that fits
+    // (timing candidates would create events)
+    int threads = b->threads, npt = b->npt;
+    if (!threads) {
+        threads = b->shapes.back().first;
+        npt = b->shapes.back().second;
+    }
+    int* d_halt = (int*)(base + o_halt);
+    int* d_rep = (int*)(base + o_rep);
+    int* d_done = (int*)(base + o_done);
+    u64* d_dig = (u64*)(base + o_dig);
+    u64* d_err = (u64*)(base + o_err);
+    int* d_hstep = (int*)(base + o_hstep);
+    snp::BatchArgs a{b->d_sys, b->d_rules, b->d_magic, b->d_nrp, b->d_in_ptr, b->d_in_src, c0_dev, final_dev,
+                     base + o_ckpt, rows, (u64*)(base + o_hkey), d_hstep, slots, b->m_max, b->r_max, steps,
+                     detect_repeats ? 1 : 0, b->count_max, d_halt, d_rep, d_done, d_dig, d_err};
+    // every result is written by the kernel; the H sets start empty (-1), cleared by a fill kernel
+    if (detect_repeats) HIPCHK(snp::launch_fill_i32(d_hstep, (long long)slots * n, -1, b->stream));
+    HIPCHK(snp::launch_batch_det(b->elem_bytes, threads, npt, a, n, b->stream));
+    HIPCHK(hipMemcpyAsync(halt_step, d_halt, sizeof(int) * n, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipMemcpyAsync(first_repeat, d_rep, sizeof(int) * n, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipMemcpyAsync(steps_done, d_done, sizeof(int) * n, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipMemcpyAsync(digest, d_dig, sizeof(u64) * n, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    // the error bits, 64 systems per copy into a buffer on the stack
+    for (int k0 = 0; k0 < n; k0 += 64) {
+        u64 e[64];
+        const int cnt = std::min(64, n - k0);
+        HIPCHK(hipMemcpy(e, d_err + k0, sizeof(u64) * cnt, hipMemcpyDeviceToHost));
+        for (int q = 0; q < cnt; ++q) {
+            if (e[q] & 1) return fail(SNP_ERR_OVERFLOW, "system %d: a count left the count type's range", k0 + q);
+            if (e[q] & 2)
+                return fail(SNP_ERR_DEVICE, "system %d: two configurations share a 64-bit hash; repeat detection "
+                            "cannot vouch for its answer", k0 + q);
+        }
+    }
+    return SNP_OK;
+}

@@ -288,9 +288,9 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
         N.kw[q] = kw;
         N.rw[q] = rw;
     }
-    T* ckpt = (T*)a.ckpt + B.ckpt_off;  // row q = the configuration at step q * kBatch
-    u64* hkey = a.hkey + B.table_off;
-    int* hstep = a.hstep + B.table_off;  // -1: empty slot
+    T* ckpt = (T*)a.ckpt + a.ckpt_rows * B.row_off;  // row q = the configuration at step q * kBatch
+    u64* hkey = a.hkey + (u64)sys * a.table_slots;
+    int* hstep = a.hstep + (u64)sys * a.table_slots;  // -1: empty slot
     const u64 hmask = a.table_slots - 1;
     const int steps = a.steps;
     __syncthreads();
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
         }
         fired = 0;
         if (done) store_counts<T, TPB, NPT>(N, (T*)a.final_out + B.row_off);
-        else store_counts<T, TPB, NPT>(N, ckpt + (long long)(k / kBatch) * B.ckpt_stride);
+        else store_counts<T, TPB, NPT>(N, ckpt + (long long)(k / kBatch) * B.m);
         __syncthreads();  // the batch's per-wave partials are complete
         {
             const int i = threadIdx.x;
@@ -381,11 +381,11 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
                 if (l < 0) continue;
                 const int kk = batch_start + q;
                 resimulated = true;
-                load_counts<T, TPB, NPT>(N, ckpt + (long long)(l / kBatch) * B.ckpt_stride);
+                load_counts<T, TPB, NPT>(N, ckpt + (long long)(l / kBatch) * B.m);
                 for (int t = (l / kBatch) * kBatch; t < l; ++t)
                     det_step<TPB, NPT>(N, L.lrules, L.lmagic, (t & 1) ? L.prod1 : L.prod0, a.in_src, a.count_max, ovf);
                 store_counts<int, TPB, NPT>(N, L.xrow);
-                load_counts<T, TPB, NPT>(N, ckpt + (long long)(kk / kBatch) * B.ckpt_stride);
+                load_counts<T, TPB, NPT>(N, ckpt + (long long)(kk / kBatch) * B.m);
                 for (int t = (kk / kBatch) * kBatch; t < kk; ++t)
                     det_step<TPB, NPT>(N, L.lrules, L.lmagic, (t & 1) ? L.prod1 : L.prod0, a.in_src, a.count_max, ovf);
                 bool diff = false;
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
         }
         if (done) break;
         if (resimulated)  // back to the configuration at step k
-            load_counts<T, TPB, NPT>(N, ckpt + (long long)(k / kBatch) * B.ckpt_stride);
+            load_counts<T, TPB, NPT>(N, ckpt + (long long)(k / kBatch) * B.m);
         if (threadIdx.x == 0) L.hring[0] = L.hring[nb];
         batch_start = k;
         __syncthreads();

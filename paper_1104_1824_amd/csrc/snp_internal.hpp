@@ -142,9 +142,6 @@ struct BatchSys {
     int rule_off;           // first packed rule of the system
     int nrp_off;            // first entry of the system's (m+1)-long rule and in-synapse offsets
     int in_off;             // first in-synapse source of the system
-    long long ckpt_off;     // first element of the system's checkpoint rows
-    long long ckpt_stride;  // elements per checkpoint row (m)
-    long long table_off;    // first slot of the system's H set
 };
 
 struct BatchArgs {
@@ -156,8 +153,10 @@ struct BatchArgs {
     const int* in_src;
     const void* c0;
     void* final_out;
-    void* ckpt;
-    u64* hkey;
+    void* ckpt;             // system k's checkpoint rows (m elements each) start at element
+                            // ckpt_rows * row_off of system k
+    long long ckpt_rows;    // checkpoint rows per system
+    u64* hkey;              // system k's H set: slots k * table_slots .. + table_slots
     int* hstep;
     u64 table_slots;        // per system, power of two
     int m_max, r_max;

@@ -25,6 +25,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OVERFLOW", 3: "CAPACITY", 4: "BUDGET"
 
 EXPORTED = ("snp_load", "snp_free", "snp_last_error", "snp_row_bytes", "snp_reset", "snp_expand", "snp_run",
             "snp_batch_load", "snp_batch_free", "snp_batch_offsets", "snp_batch_shape", "snp_batch_run",
+            "snp_batch_run_static",
             "snp_run_batch")
 
 
@@ -123,6 +124,8 @@ def lib():
         L.snp_batch_shape.restype = I32
         L.snp_batch_run.argtypes = [P, P, I32, I32, P, P, P, P, P]
         L.snp_batch_run.restype = I32
+        L.snp_batch_run_static.argtypes = [P, P, I32, I32, P, P, P, P, P]
+        L.snp_batch_run_static.restype = I32
         L.snp_run_batch.argtypes = [P, I32, P, I32, P, P, P, P]
         L.snp_run_batch.restype = I32
         _lib = L
@@ -375,6 +378,24 @@ def snp_batch_run(b: BatchHandle, c0_dev, steps: int, final_dev, detect_repeats:
                                _ptr(final_dev, "final", eb, b.total), halt.ctypes.data, rep.ctypes.data,
                                done.ctypes.data, dig.ctypes.data),
            "snp_batch_run")
+    return dict(halt_step=halt, first_repeat=rep, steps_done=done, digest=dig)
+
+
+def snp_batch_run_static(b: BatchHandle, c0_dev, steps: int, final_dev, detect_repeats: bool = True) -> dict:
+    """snp_batch_run with the library's static scratch (no device allocation).
+    Returns dict of numpy arrays: halt_step, first_repeat, steps_done, digest."""
+    n = b.n
+    if b.total is None:
+        b.total = int(snp_batch_offsets(b)[-1])
+    eb = _eb(b.count_type)
+    halt = np.zeros(n, dtype=np.int32)
+    rep = np.zeros(n, dtype=np.int32)
+    done = np.zeros(n, dtype=np.int32)
+    dig = np.zeros(n, dtype=np.uint64)
+    _check(lib().snp_batch_run_static(b.ptr, _ptr(c0_dev, "c0", eb, b.total), int(steps), int(bool(detect_repeats)),
+                                      _ptr(final_dev, "final", eb, b.total), halt.ctypes.data, rep.ctypes.data,
+                                      done.ctypes.data, dig.ctypes.data),
+           "snp_batch_run_static")
     return dict(halt_step=halt, first_repeat=rep, steps_done=done, digest=dig)
 
 
