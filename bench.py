@@ -80,7 +80,7 @@ def device_rows(system, rows):
 class Walk:
     """A loaded handle plus its device buffers, for timed snp_run calls."""
 
-    def __init__(self, system, path, cap, depth, stop, chunk, out_cap, profile):
+    def __init__(self, system, path, cap, depth, stop, chunk, out_cap, profile, tune=False):
         import torch
 
         from paper_1104_1824_amd import snp
@@ -91,6 +91,8 @@ class Walk:
         self.c0 = device_rows(system, system.c0)
         dt = torch.int16 if system.count_type == "u16" else torch.int32
         self.out = torch.empty((out_cap, system.m), dtype=dt, device="cuda")
+        # launch settings timed on this very walk, before (and outside) the timed region
+        self.tuning = snp.snp_autotune(self.h, self.c0, depth, self.out, out_cap) if tune else None
 
     def run(self):
         return self.snp.snp_run(self.h, self.c0, self.depth, self.out, self.out_cap)
@@ -158,29 +160,32 @@ def dense_system():
     return synth.config_system(3, 0)
 
 
-def run_dense(steps, warmup):
+def run_dense(steps, warmup, tune):
     from paper_1104_1824_amd import snp
 
     s = dense_system()
     log(f"dense m=512 seed 0, int8 path: warmup {warmup}, steps {steps}")
-    w = Walk(s, snp.SNP_PATH_INT8, 1000000, 3, False, 1 << 20, 3000001, profile=1)
+    w = Walk(s, snp.SNP_PATH_INT8, 1000000, 3, False, 1 << 20, 3000001, profile=1, tune=tune)
+    if w.tuning:
+        log(f"tuned launch settings: {w.tuning}")
     results, dt = w.timed(steps, warmup)
     w.close()
+    results[-1]["tuning"] = w.tuning
     new = results[-1]["n_configs"] - 1
     assert all(r["n_configs"] - 1 == new for r in results)
     log(f"levels {results[-1]['level_sizes'].tolist()}, {new} new per walk, {dt / steps * 1e3:.3f} ms/walk")
     return s, results, dt
 
 
-def run_dense_sparse(reps=1):
+def run_dense_sparse(reps=1, tune=True):
     from paper_1104_1824_amd import snp
 
     log("dense m=512 seed 0, plain sparse path (the speedup's reference)")
-    w = Walk(dense_system(), snp.SNP_PATH_SPARSE, 1000000, 3, False, 1 << 20, 3000001, profile=1)
+    w = Walk(dense_system(), snp.SNP_PATH_SPARSE, 1000000, 3, False, 1 << 20, 3000001, profile=1, tune=tune)
     results, dt = w.timed(reps, 1)
     w.close()
     return dict(ms_per_walk=round(dt / reps * 1e3, 3), new_configs=int(results[-1]["n_configs"] - 1),
-                configs_per_s=round((results[-1]["n_configs"] - 1) * reps / dt, 1))
+                configs_per_s=round((results[-1]["n_configs"] - 1) * reps / dt, 1), tuning=w.tuning)
 
 
 def cpu_dense(budget_s=10.0):
@@ -237,18 +242,19 @@ def cpu_large():
                        f"({int(res.enumerated[0])} children enumerated), single-threaded, {dt:.1f} s")
 
 
-def plain_line(steps=50, warmup=5, cpu=None):
+def plain_line(steps=50, warmup=5, cpu=None, tune=True):
     import synth
     from paper_1104_1824_amd import snp
 
     s = synth.config_system(2, 0)
     log("plain sparse m=64 seed 0, sparse path")
-    w = Walk(s, snp.SNP_PATH_SPARSE, 100000, 1000, True, 1 << 17, 200000, profile=1)
+    w = Walk(s, snp.SNP_PATH_SPARSE, 100000, 1000, True, 1 << 17, 200000, profile=1, tune=tune)
     results, dt = w.timed(steps, warmup)
     w.close()
     new = results[-1]["n_configs"] - 1
     line = dict(workload=PLAIN_WORKLOAD, value=round(steps * new / dt, 1), unit="configs/s",
-                ms_per_step=round(dt / steps * 1e3, 4), levels=results[-1]["level_sizes"].tolist(), dtype="int32")
+                ms_per_step=round(dt / steps * 1e3, 4), levels=results[-1]["level_sizes"].tolist(), dtype="int32",
+                tuning=w.tuning)
     line.update(hbm_roofline(results, "k_expand_lane", None, s.m * 4, per_child=True))
     line["cpu_baseline"] = cpu
     return line
@@ -334,19 +340,20 @@ def cpu_batched(sample=16):
                                 sample=f"all 256 systems, one per task, {dtn:.1f} s"))
 
 
-def large_line(cpu=None):
+def large_line(cpu=None, tune=True):
     import synth
     from paper_1104_1824_amd import snp
 
     s = synth.config_system(5, 0)
     log("large m=4096 uint16, automatic path, depth 3, cap 4e6")
-    w = Walk(s, snp.SNP_PATH_AUTO, 4000000, 3, False, 1 << 22, 12000001, profile=1)
-    results, dt = w.timed(1, 0)
+    w = Walk(s, snp.SNP_PATH_AUTO, 4000000, 3, False, 1 << 22, 12000001, profile=1, tune=tune)
+    results, dt = w.timed(3, 1)
     w.close()
     new = results[-1]["n_configs"] - 1
-    line = dict(workload=LARGE_WORKLOAD, value=round(new / dt, 1), unit="configs/s", ms_per_step=round(dt * 1e3, 3),
-                levels=results[-1]["level_sizes"].tolist(), dtype="uint16",
-                twins=totals(results, "twins"), expanded=totals(results, "expanded"))
+    line = dict(workload=LARGE_WORKLOAD, value=round(3 * new / dt, 1), unit="configs/s",
+                ms_per_step=round(dt / 3 * 1e3, 3), levels=results[-1]["level_sizes"].tolist(), dtype="uint16",
+                twins=totals(results, "twins"), expanded=totals(results, "expanded"), tuning=w.tuning,
+                int8_passes=totals(results, "int8_chunks"), passes=totals(results, "chunks"))
     line.update(hbm_roofline(results, "k_expand_int8", s.m * 2 + ENTRY_BYTES, s.m * 2))
     line["mfma"] = mfma_util(results)
     line["cpu_baseline"] = cpu
@@ -376,6 +383,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the plain-sparse / batched / large lines")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the library's built-in launch settings (no autotuning before the timed walks)")
     ap.add_argument("--only", choices=sorted(SECONDARY) + ["dense"],
                     help="run only this workload (no CPU baseline) and print its line")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -405,18 +414,19 @@ def main():
     if args.only and args.only != "dense":
         print(json.dumps({args.only: SECONDARY[args.only]()}), flush=True)
         return
-    s, results, dt = run_dense(args.steps, args.warmup)
+    s, results, dt = run_dense(args.steps, args.warmup, not args.no_tune)
     if args.only == "dense":
         print(json.dumps(dict(ms_per_step=round(dt / args.steps * 1e3, 4),
                               **hbm_roofline(results, "k_expand_int8", s.m * 4 + ENTRY_BYTES, s.m * 4))), flush=True)
         return
     new = results[-1]["n_configs"] - 1
     rl = hbm_roofline(results, "k_expand_int8", s.m * 4 + ENTRY_BYTES, s.m * 4)
-    sparse = run_dense_sparse()
+    sparse = run_dense_sparse(tune=not args.no_tune)
     ms = dt / args.steps * 1e3
     secondary = None
     if not args.no_secondary:
-        secondary = {name: fn(cpu=cpus.get(name)) for name, fn in SECONDARY.items()}
+        secondary = {name: fn(cpu=cpus.get(name), **({} if name == "batched" else dict(tune=not args.no_tune)))
+                     for name, fn in SECONDARY.items()}
     cpu = cpus.get("dense")
     line = {
         "metric": METRIC,
@@ -436,6 +446,7 @@ def main():
             "levels": results[-1]["level_sizes"].tolist(),
             "new_configs_per_step": new,
             "path": "int8 matrix cores (int32 accumulation, int32 rows)",
+            "tuning": results[-1].get("tuning"),
             "parallelism": "single GPU",
         },
         "roofline": rl["roofline"],

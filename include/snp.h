@@ -70,7 +70,10 @@ typedef enum { SNP_COUNT_I32 = 0, SNP_COUNT_U16 = 1 } snp_count_t;
 
 /* How S . M is evaluated for a chunk of children.  Results are identical. */
 typedef enum {
-    SNP_PATH_AUTO = 0,   /* per chunk: int8 matrix cores when M fits int8 and the chunk is dense */
+    SNP_PATH_AUTO = 0,   /* per chunk: the int8 matrix-core form when M fits int8 and the chunk's
+                            parents have enough canonical children per parent for its segments
+                            (one reference pull per run of up to 64 consecutive children of a
+                            parent) to cost less than a pull per child; else the sparse form */
     SNP_PATH_SPARSE = 1, /* gather over the in-synapses of every neuron (int32 adds) */
     SNP_PATH_INT8 = 2    /* S (0/1) x M (int8) on MFMA with int32 accumulation; falls back to
                             SPARSE (stats.int8_fallback = 1) when some |M entry| > 127 */
@@ -161,11 +164,13 @@ typedef struct {
     int64_t collisions;      /* visited-set probes that met an entry with the same 32-bit tag
                                 whose full row differed (settled by the row compare) */
     int64_t chunks;          /* device passes used */
+    int64_t int8_chunks;     /* of those, passes that ran the int8 matrix-core form (the rest ran
+                                the sparse form; SNP_PATH_AUTO picks per pass) */
     int64_t mfma_ops;        /* int8 matrix-core multiply-adds issued by the level, x 2 (one
                                 16x16x64 instruction = 32768 integer operations) */
     int32_t truncated;       /* 1: the level reached frontier_cap */
     int32_t budget_hit;      /* 1: child_budget ran out with children left */
-    int32_t path_used;       /* snp_path of the last chunk (SPARSE or INT8) */
+    int32_t path_used;       /* snp_path of the last pass (SPARSE or INT8) */
     int32_t int8_fallback;   /* 1: INT8 was requested but M does not fit int8 */
     /* Device time of each stage summed over the level's passes, in ns (0 when
      * not timed; see snp_options.profile): applicability + Psi and its prefix
@@ -252,6 +257,47 @@ snp_status snp_run(snp_system *sys, const void *c0_dev, int32_t max_depth, void 
                    int64_t out_capacity, int64_t *n_configs, int64_t *level_sizes, int32_t max_levels,
                    int32_t *n_levels, int32_t *stop_reason, snp_expand_stats *level_stats,
                    int64_t *parent_of, int64_t *child_of);
+
+/* Launch settings of a handle's walk.  Results never depend on them (only
+ * timing does); 0 in a field means the library's built-in choice. */
+typedef struct {
+    int64_t chunk;       /* canonical children per device pass, 1 .. the handle's chunk
+                            (snp_options.chunk or its automatic value: the buffers' size) */
+    int32_t int8_tiles;  /* int8 form: consecutive 64-child tiles per workgroup, 0 .. 64 */
+    int32_t sparse_run;  /* sparse form (m > 64 or in-degree > 16): consecutive children per
+                            wave, 0 .. 1024 */
+} snp_tuning;
+
+/* The handle's current settings. */
+snp_status snp_get_tuning(const snp_system *sys, snp_tuning *out);
+
+/* Set the handle's settings (host pointer, copied).  Errors: SNP_ERR_INVALID for
+ * a field outside its range. */
+snp_status snp_set_tuning(snp_system *sys, const snp_tuning *tuning);
+
+/* Autotuner: times whole walks of this workload (snp_run with these arguments,
+ * the fastest of three after a warm-up, one for walks above 100 ms) under
+ * candidate settings, coordinate by coordinate: chunk = the handle's chunk and
+ * its halves down to 1/16 (not under 4096), then int8_tiles in {1, 2, 4, 8, 16}
+ * where the int8 form can run, then sparse_run in {4, 8, 16, 32, 64} where the
+ * sparse form can run.  The fastest is applied to the handle, returned in
+ * *best (nullable) with its walk time in *best_ms (ms, nullable), and, when
+ * cache_path (a file name) is non-NULL, recorded there: a JSON object
+ * {"snp_tuning_cache": 1, "entries": {key: {"chunk", "int8_tiles",
+ * "sparse_run", "ms"}}} whose key names the GPU architecture and hashes the
+ * system, the options that shape the walk and max_depth.  Other entries of the
+ * file are kept.  out_dev / out_capacity are snp_run's (the rows of the last
+ * walk stay there).
+ * Errors: those of snp_run; SNP_ERR_INVALID when cache_path exists and is not
+ * a tuning cache, or cannot be written. */
+snp_status snp_autotune(snp_system *sys, const void *c0_dev, int32_t max_depth, void *out_dev,
+                        int64_t out_capacity, const char *cache_path, snp_tuning *best, double *best_ms);
+
+/* Apply the settings recorded in cache_path for this handle's workload (the
+ * key snp_autotune uses, with this max_depth), if any: *found (host) = 1 when
+ * applied, 0 when the file or the key is missing.
+ * Errors: SNP_ERR_INVALID when the file is not a tuning cache. */
+snp_status snp_load_tuning(snp_system *sys, const char *cache_path, int32_t max_depth, int32_t *found);
 
 /* ------------------------------------------------------------------------- */
 /* Deterministic branch of many independent systems in one launch.            */

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB_NAME = "libsnp.so"
-SOURCES = ["snp_api.hip", "snp_kernels.hip", "snp_int8.hip", "snp_batch.hip"]
+SOURCES = ["snp_api.hip", "snp_tune.hip", "snp_kernels.hip", "snp_int8.hip", "snp_batch.hip"]
 ARCH = "gfx950"
 
 

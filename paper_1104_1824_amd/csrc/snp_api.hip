@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "snp.h"
+#include "snp_handle.hpp"
 #include "snp_internal.hpp"
 
 using snp::u64;
@@ -22,15 +23,31 @@ namespace {
 
 thread_local std::string g_err;
 
-snp_status fail(snp_status st, const char* fmt, ...) {
+void set_error_v(const char* fmt, va_list ap) {
     char buf[512];
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    g_err = buf;
+}
+
+snp_status fail(snp_status st, const char* fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    set_error_v(fmt, ap);
     va_end(ap);
-    g_err = buf;
     return st;
 }
+
+}  // namespace
+
+snp_status snp::set_error(snp_status st, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    set_error_v(fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+namespace {
 
 #define HIPCHK(expr)                                                                            \
     do {                                                                                        \
@@ -60,86 +77,6 @@ hipError_t dmalloc(P** p, size_t bytes) {
 }
 
 }  // namespace
-
-struct snp_system {
-    int m = 0, r = 0, elem_bytes = 4;
-    // the host description, kept for snp_run_batch (which packs the handles'
-    // systems into one batched launch), and an id no other handle ever gets
-    std::vector<int32_t> h_rn, h_ri, h_rj, h_rc, h_rp, h_ss, h_sd;
-    int32_t count_type = SNP_COUNT_I32;
-    unsigned long long uid = 0;
-    long long count_max = INT_MAX;
-    snp_options opt{};
-    hipStream_t stream = nullptr;
-    bool int8_ok = false;
-
-    // device tables
-    int* d_nrule_ptr = nullptr;
-    int4* d_rules = nullptr;
-    int* d_in_ptr = nullptr;
-    int* d_in_src = nullptr;
-    int* d_in_lane = nullptr;
-    int8_t* d_M8 = nullptr;  // r x m int8 copy of M_Pi when every entry fits (int8 path)
-    u64* d_R = nullptr;      // hash weights
-    u64* d_hM = nullptr;     // H of every row of M_Pi
-    bool int8_ready = false; // d_M8 built and the int8 kernel's limits hold
-    bool lane_form = false;  // m <= 64, in-degree <= 16: the one-neuron-per-lane expansion applies
-    double sparse_work = 0;  // per-child work estimates of the two forms (path choice)
-    double int8_work = 0;
-    snp::DevSystem dsys{};
-
-    // visited set
-    u64* d_table = nullptr;
-    u64 slots = 0;
-    long long tombs = 0;
-    uint32_t* d_row_slot = nullptr;
-    long long max_rows = 0, max_frontier = 0, chunk_max = 0;
-
-    // per-frontier and per-chunk buffers
-    u64 *d_psi = nullptr, *d_off = nullptr, *d_sc_sums = nullptr, *d_sc_pre = nullptr;
-    u64* d_psif = nullptr;  // per parent: all children (every valid spiking vector)
-    uint8_t* d_hflag = nullptr;  // per parent: 1 when no rule applies
-    void* d_stage = nullptr;
-    u64* d_hash = nullptr;
-    int* d_cpar = nullptr;
-    u64* d_ct = nullptr;
-    uint32_t *d_slot = nullptr, *d_flag = nullptr, *d_pos = nullptr, *d_fsums = nullptr, *d_fpre = nullptr;
-    uint32_t* d_cand = nullptr;
-    // counters: a ring of slots, one per device pass, zeroed once per kRing
-    // passes; a walk's start writes the slot its first pass then uses
-    static constexpr int kRing = 64;
-    snp::DevCounters* d_ring = nullptr;
-    snp::DevCounters* d_ctr = nullptr;  // slot of the current pass
-    long long pass = 0;
-    u64* d_T = nullptr;                 // canonical children of the examined frontier prefix (device)
-    u64* d_Tend = nullptr;              // the chunks' end under a child budget (device)
-    snp::DevCounters* h_ctr = nullptr;  // the pass read last
-    bool start_pending = false;         // the walk start's checks are not read yet
-    bool slot_ready = false;            // the current slot was set by the walk start: reuse it
-
-    // caller-driven walk (snp_reset / snp_expand): the handle's own row store
-    void* d_store = nullptr;
-    bool walk_active = false;
-    long long walk_rows = 0;
-
-    double new_ratio = 1.0;  // new / enumerated of the last chunk (chunk sizing)
-    double psi_per_parent = 0.0;  // children per examined parent of the last level (0: none yet)
-
-    // stage timing (profile option): event pairs around psi+scan, expand, insert, flags+scan, commit
-    static constexpr int kStages = 5;
-    hipEvent_t ev[kStages + 1] = {};
-
-    ~snp_system() {
-        void* ptrs[] = {d_nrule_ptr, d_rules, d_in_ptr, d_in_src, d_in_lane, d_M8, d_R, d_hM, d_table, d_row_slot, d_psi, d_off,
-                        d_sc_sums, d_sc_pre, d_stage, d_hash, d_cpar, d_ct, d_slot, d_flag, d_pos,
-                        d_fsums, d_fpre, d_ring, d_store, d_cand, d_hflag, d_T, d_psif, d_Tend};
-        for (void* p : ptrs)
-            if (p) (void)hipFree(p);
-        if (h_ctr) (void)hipHostFree(h_ctr);
-        for (hipEvent_t e : ev)
-            if (e) (void)hipEventDestroy(e);
-    }
-};
 
 struct snp_batch {
     int n = 0, elem_bytes = 4, m_max = 0, r_max = 0;
@@ -402,11 +339,21 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
     *count_out = 0;
     stt.parents = io.n;
     stt.int8_fallback = (S->opt.path == SNP_PATH_INT8 && !S->int8_ready) ? 1 : 0;
-    bool use_int8 = false;
-    if (S->opt.path == SNP_PATH_INT8) use_int8 = S->int8_ready;
-    else if (S->opt.path == SNP_PATH_AUTO)  // the one-neuron-per-lane form wins wherever it applies
-        use_int8 = S->int8_ready && !S->lane_form && S->int8_work < S->sparse_work;
-    stt.path_used = use_int8 ? SNP_PATH_INT8 : SNP_PATH_SPARSE;
+    // Form of a pass.  The int8 form computes one reference child per segment
+    // (consecutive canonical children of one parent, at most 64) by a pull and
+    // the rest on the matrix cores; with few canonical children per parent its
+    // segments shrink to single children and every child costs a pull plus the
+    // matrix-core overhead.  AUTO compares the two per child, with the
+    // segment length taken from the canonical children per parent of the
+    // prefix examined so far (of the last level before the first pass); the
+    // one-neuron-per-lane form is kept wherever it applies.
+    auto choose_int8 = [&](double per_parent) -> bool {
+        if (S->opt.path == SNP_PATH_INT8) return S->int8_ready;
+        if (S->opt.path != SNP_PATH_AUTO || !S->int8_ready || S->lane_form) return false;
+        const double seg = std::max(1.0, std::min(64.0, per_parent));
+        return S->pull_work / seg + S->int8_row_work < S->pull_work;
+    };
+    stt.path_used = choose_int8(64.0) ? SNP_PATH_INT8 : SNP_PATH_SPARSE;
     if (io.n > S->max_frontier)
         return fail(SNP_ERR_CAPACITY, "frontier of %lld rows exceeds max_frontier %lld", io.n, S->max_frontier);
     snp_status st;
@@ -482,7 +429,7 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
     if (start_ext) P = 1;
     long long halting_cap = -1;  // halting parents up to the cap's child's parent, counted in its pass
     for (;;) {
-        u64 want = (u64)S->chunk_max;
+        u64 want = (u64)S->chunk_eff;
         if (io.limit_sem < kInf) {
             const double ratio = std::max(S->new_ratio, 1.0 / 64.0);
             const double w = (double)(io.limit_sem - count) / ratio * 1.1 + 1024.0;
@@ -504,6 +451,10 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
             if ((u64)(live + B) * 2 > S->slots)
                 return fail(SNP_ERR_CAPACITY, "visited set too small for %lld rows", live + B);
         }
+        // canonical children per parent: of the prefix examined by the earlier
+        // passes of the level, else of the last level (64 before any)
+        const double per_parent = G > 0 && P > 0 && T > 0 ? (double)T / (double)P
+                                  : (S->psi_per_parent > 0.0 ? S->psi_per_parent : 64.0);
         if ((st = clear_counters(S))) return st;
         if ((st = mark(S, 0))) return st;
         if (ext && !start_ext && (st = launch_extension(want))) return st;
@@ -512,11 +463,13 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         if ((st = mark(S, 1))) return st;
         snp::ChunkArgs ca{io.frontier, P, S->d_psi, S->d_off, G, B, S->d_stage, S->d_hash, S->d_cpar, S->d_ct,
                           hmask, S->d_ctr, d_end, S->opt.int8_max_k > 0 ? S->opt.int8_max_k : 128,
-                          S->d_table, S->slots - 1, S->d_slot, S->d_cand};
+                          S->tune_tiles, S->tune_run, S->d_table, S->slots - 1, S->d_slot, S->d_cand};
         if (ext_c0 && has_budget)  // C0's clip, from the Psi the walk start computed
             HIPCHK(snp::launch_budget_clip(S->elem_bytes, S->dsys, io.frontier, 1, S->d_psif, S->d_off, S->d_T,
                                            budget, S->d_Tend, S->d_ctr, S->stream));
         bool probed = false;
+        const bool use_int8 = choose_int8(per_parent);
+        stt.path_used = use_int8 ? SNP_PATH_INT8 : SNP_PATH_SPARSE;
         if (use_int8) HIPCHK(snp::launch_expand_int8(S->elem_bytes, S->dsys, ca, S->stream));
         else HIPCHK(snp::launch_expand_sparse(S->elem_bytes, S->dsys, ca, S->stream, &probed));
         if ((st = mark(S, 2))) return st;
@@ -555,6 +508,7 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         if (ext) take_extension(c);
         const long long Beff = (long long)c.beff;
         if (Beff > 0) ++stt.chunks;
+        if (Beff > 0 && stt.path_used == SNP_PATH_INT8) ++stt.int8_chunks;
         stt.expanded += Beff;
         stt.collisions += (long long)c.collisions;
         stt.mfma_ops += (long long)c.mfma * 32768;
@@ -674,6 +628,7 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     S->max_frontier = opt.max_frontier > 0 ? opt.max_frontier : opt.max_rows;
     const long long rb = row_bytes(S);
     S->chunk_max = opt.chunk > 0 ? opt.chunk : std::min<long long>(1 << 20, std::max<long long>(4096, (1LL << 28) / rb));
+    S->chunk_eff = S->chunk_max;
     if ((st = validate_table_size(S->max_rows, S->chunk_max))) {
         delete S;
         return st;
@@ -758,9 +713,9 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
         LOADCHK(up(S->d_M8, M8.data(), M8.size()));
     }
     // per-child work of the two forms: the pull visits every neuron and synapse;
-    // the matrix-core form writes the row and amortises one pull over a 64-child tile
-    S->sparse_work = (double)d->m + (double)d->n_syn;
-    S->int8_work = (double)d->m * 1.5 + ((double)d->m + (double)d->n_syn) / 64.0;
+    // the matrix-core form adds the row's matrix-core product and store
+    S->pull_work = (double)d->m + (double)d->n_syn;
+    S->int8_row_work = (double)d->m * 1.5;
     int max_in = 0;
     for (int n = 0; n < d->m; ++n) max_in = std::max(max_in, in_ptr[n + 1] - in_ptr[n]);
     // lane-major in-synapse table of the one-neuron-per-lane expansion

@@ -422,7 +422,8 @@ hipError_t launch_expand_int8(int elem_bytes, const DevSystem& s, const ChunkArg
     // bounds them: 160 KiB per CU, 256 CUs) for balance
     const long long tiles = (a.B + kTile - 1) / kTile;
     const long long resident = 256LL * std::max<long long>(1, (160 * 1024) / (long long)lds);
-    const int tpb = (int)std::max<long long>(1, std::min<long long>(16, tiles / (4 * resident)));
+    const int tpb = a.tiles > 0 ? std::min(a.tiles, 64)
+                                : (int)std::max<long long>(1, std::min<long long>(16, tiles / (4 * resident)));
     const unsigned blocks = (unsigned)((tiles + tpb - 1) / tpb);
 #define SNP_I8(TT, NN) hipLaunchKernelGGL((k_expand_int8<TT, NN>), dim3(blocks), dim3(256), lds, st, s, a, tpb)
     if (elem_bytes == 4) {

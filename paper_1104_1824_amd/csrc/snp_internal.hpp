@@ -84,6 +84,8 @@ struct ChunkArgs {
     DevCounters* ctr;
     const u64* Tdev;       // canonical children the chunks may take: the chunk stops there
     int kmax;              // int8 form: most rule columns a segment may put on the matrix cores
+    int tiles;             // int8 form: consecutive 64-child tiles per workgroup (0: automatic)
+    int run;               // sparse form: consecutive children per wave (0: automatic)
     // visited-set probe done by the expansion itself (the one-neuron-per-lane
     // form); null table: the probe runs as a kernel of its own
     u64* table;

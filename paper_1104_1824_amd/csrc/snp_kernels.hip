@@ -1247,6 +1247,7 @@ hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkA
     // runs short enough that the chunk spreads over the whole GPU
     int run = 4;
     while (run < 32 && (long long)run * 2 * 8192 <= a.B) run <<= 1;
+    if (a.run > 0) run = std::min(a.run, 1024);
     const long long waves = (a.B + run - 1) / run;
     const unsigned blocks = (unsigned)((waves + wpb - 1) / wpb);
     const size_t lds = (size_t)wpb * stride + (tbl_lds ? tbl : 0);

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OVERFLOW", 3: "CAPACITY", 4: "BUDGET"
 
 EXPORTED = ("snp_load", "snp_free", "snp_last_error", "snp_row_bytes", "snp_reset", "snp_expand", "snp_run",
             "snp_batch_load", "snp_batch_free", "snp_batch_offsets", "snp_batch_shape", "snp_batch_run",
-            "snp_batch_run_static",
+            "snp_batch_run_static", "snp_get_tuning", "snp_set_tuning", "snp_autotune", "snp_load_tuning",
             "snp_run_batch")
 
 
@@ -57,12 +57,20 @@ class snp_options(ctypes.Structure):
     ]
 
 
+class snp_tuning(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int64), ("int8_tiles", ctypes.c_int32), ("sparse_run", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
 class snp_expand_stats(ctypes.Structure):
     _fields_ = [
         ("parents", ctypes.c_int64), ("halting_parents", ctypes.c_int64),
         ("children_total", ctypes.c_int64), ("enumerated", ctypes.c_int64),
         ("new_configs", ctypes.c_int64), ("duplicates", ctypes.c_int64), ("expanded", ctypes.c_int64),
         ("twins", ctypes.c_int64), ("collisions", ctypes.c_int64), ("chunks", ctypes.c_int64),
+        ("int8_chunks", ctypes.c_int64),
         ("mfma_ops", ctypes.c_int64),
         ("truncated", ctypes.c_int32), ("budget_hit", ctypes.c_int32),
         ("path_used", ctypes.c_int32), ("int8_fallback", ctypes.c_int32),
@@ -126,6 +134,15 @@ def lib():
         L.snp_batch_run.restype = I32
         L.snp_batch_run_static.argtypes = [P, P, I32, I32, P, P, P, P, P]
         L.snp_batch_run_static.restype = I32
+        TP = ctypes.POINTER(snp_tuning)
+        L.snp_get_tuning.argtypes = [P, TP]
+        L.snp_get_tuning.restype = I32
+        L.snp_set_tuning.argtypes = [P, TP]
+        L.snp_set_tuning.restype = I32
+        L.snp_autotune.argtypes = [P, P, I32, P, I64, ctypes.c_char_p, TP, ctypes.POINTER(ctypes.c_double)]
+        L.snp_autotune.restype = I32
+        L.snp_load_tuning.argtypes = [P, ctypes.c_char_p, I32, ctypes.POINTER(I32)]
+        L.snp_load_tuning.restype = I32
         L.snp_run_batch.argtypes = [P, I32, P, I32, P, P, P, P]
         L.snp_run_batch.restype = I32
         _lib = L
@@ -188,7 +205,7 @@ class _RunBuffers:
 
 
 class Handle:
-    """An loaded system (snp_system*); freed by close() or garbage collection."""
+    """A loaded system (snp_system*); freed by close() or garbage collection."""
 
     def __init__(self, ptr: int, keep, m: int, count_type: int):
         self.ptr = ctypes.c_void_p(ptr)
@@ -304,6 +321,37 @@ def snp_run(h: Handle, c0_dev, max_depth: int, out_dev, out_capacity: int, max_l
         stop_reason=int(rb.stop.value),
         level_stats=_stats_list(rb.stats, L) if with_stats else None,
     )
+
+
+def snp_get_tuning(h: Handle) -> dict:
+    tu = snp_tuning()
+    _check(lib().snp_get_tuning(h.ptr, ctypes.byref(tu)), "snp_get_tuning")
+    return tu.as_dict()
+
+
+def snp_set_tuning(h: Handle, chunk: int = 0, int8_tiles: int = 0, sparse_run: int = 0):
+    tu = snp_tuning(int(chunk), int(int8_tiles), int(sparse_run))
+    _check(lib().snp_set_tuning(h.ptr, ctypes.byref(tu)), "snp_set_tuning")
+
+
+def snp_autotune(h: Handle, c0_dev, max_depth: int, out_dev, out_capacity: int,
+                 cache_path: Optional[str] = None) -> dict:
+    """snp_autotune; returns the settings applied plus their walk time "ms"."""
+    eb = _eb(h.count_type)
+    tu = snp_tuning()
+    ms = ctypes.c_double()
+    _check(lib().snp_autotune(h.ptr, _ptr(c0_dev, "c0", eb, h.m), int(max_depth),
+                              _ptr(out_dev, "out", eb, int(out_capacity) * h.m), int(out_capacity),
+                              cache_path.encode() if cache_path else None, ctypes.byref(tu), ctypes.byref(ms)),
+           "snp_autotune")
+    return dict(tu.as_dict(), ms=float(ms.value))
+
+
+def snp_load_tuning(h: Handle, cache_path: str, max_depth: int) -> bool:
+    found = ctypes.c_int32()
+    _check(lib().snp_load_tuning(h.ptr, cache_path.encode(), int(max_depth), ctypes.byref(found)),
+           "snp_load_tuning")
+    return bool(found.value)
 
 
 def torch_dtype(count_type: int):

@@ -40,13 +40,15 @@ def from_device_rows(system, t):
     return a.astype(np.int64)
 
 
-def gpu_bfs(system, max_depth=-1, out_capacity=1 << 16, c0=None, with_prov=True, **opts):
+def gpu_bfs(system, max_depth=-1, out_capacity=1 << 16, c0=None, with_prov=True, tuning=None, **opts):
     import torch
 
     opts.setdefault("path", snp.SNP_PATH_SPARSE)
     opts.setdefault("max_rows", out_capacity)
     h = snp.snp_load(system, **opts)
     try:
+        if tuning:
+            snp.snp_set_tuning(h, **{k: v for k, v in tuning.items() if k != "ms"})
         c0t = to_device_rows(system, system.c0 if c0 is None else c0)
         out = torch.empty((out_capacity, system.m), dtype=dev_dtype(system), device="cuda")
         par = torch.empty(out_capacity, dtype=torch.int64, device="cuda") if with_prov else None

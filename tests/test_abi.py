@@ -135,7 +135,7 @@ def _c_layout(struct, fields):
     return [int(x) for x in out]
 
 
-@pytest.mark.parametrize("name", ["snp_desc", "snp_options", "snp_expand_stats"])
+@pytest.mark.parametrize("name", ["snp_desc", "snp_options", "snp_expand_stats", "snp_tuning"])
 def test_binding_struct_layout_matches_header(name):
     """The ctypes structures of the binding have the C header's size and offsets."""
     from paper_1104_1824_amd import snp
