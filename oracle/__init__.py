@@ -61,7 +61,7 @@ class _BfsOpts(ctypes.Structure):
     _fields_ = [
         ("max_depth", ctypes.c_int32), ("stop_at_cap", ctypes.c_int32),
         ("frontier_cap", ctypes.c_int64), ("child_budget", ctypes.c_int64),
-        ("expand_max_count", ctypes.c_int64), ("first_only", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("expand_max_count", ctypes.c_int64), ("first_only", ctypes.c_int32), ("out_neuron", ctypes.c_int32),
     ]
 
 
@@ -200,20 +200,28 @@ class BfsResult:
 
 def bfs(sys, c0=None, max_depth: int = -1, frontier_cap: int = 0, child_budget: int = 0,
         expand_max_count: int = -1, stop_at_cap: bool = False, rows_cap: int = 1 << 12,
-        max_levels: int = 1 << 12, deterministic: bool = False) -> BfsResult:
+        max_levels: int = 1 << 12, deterministic: bool = False, out_neuron: int = 0) -> BfsResult:
     """Algorithm 1 from C0: levels of new configurations in first-occurrence order.
 
     ``frontier_cap`` truncates every level to its first new configurations in
     enumeration order (truncated ones are not recorded); with ``stop_at_cap`` a
     level that reaches the cap also ends the walk.  ``deterministic`` keeps only
-    the first spiking vector of every configuration (a single branch)."""
+    the first spiking vector of every configuration (a single branch).
+    ``out_neuron`` > 0 (1-based) follows that neuron's spikes to the
+    environment: rows carry two more entries (spikes sent, at most 2 counted;
+    steps from the first to the second), C0's being 0, 0 unless given."""
     S = _Sys(sys)
     c0 = _i64(sys.c0 if c0 is None else c0)
+    width = S.m + (2 if out_neuron else 0)
+    if c0.shape[0] == S.m and width > S.m:
+        c0 = np.concatenate([c0, np.zeros(2, dtype=np.int64)])
+    if c0.shape[0] != width:
+        raise ValueError(f"C0 has {c0.shape[0]} entries, rows have {width}")
     opts = _BfsOpts(int(max_depth), int(bool(stop_at_cap)), int(frontier_cap), int(child_budget),
-                    int(expand_max_count), int(bool(deterministic)), 0)
+                    int(expand_max_count), int(bool(deterministic)), int(out_neuron))
     cap = int(rows_cap)
     while True:
-        rows = np.zeros((cap, S.m), dtype=np.int64)
+        rows = np.zeros((cap, width), dtype=np.int64)
         parent = np.zeros(cap, dtype=np.int64)
         tindex = np.zeros(cap, dtype=np.int64)
         lv = np.zeros(max_levels, dtype=np.int64)
@@ -233,6 +241,13 @@ def bfs(sys, c0=None, max_depth: int = -1, frontier_cap: int = 0, child_budget: 
         n, L = int(res.n_configs), int(res.n_levels)
         return BfsResult(rows[:n].copy(), lv[:L].copy(), parent[:n].copy(), tindex[:n].copy(),
                          en[:L].copy(), ha[:L].copy(), int(res.stop_reason))
+
+
+def generated_numbers(res: BfsResult, m: int) -> list:
+    """The numbers a walk with an output neuron generated: the steps between the
+    output neuron's first two spikes, over every row whose train has both."""
+    rows = res.rows
+    return sorted({int(x) for x in rows[rows[:, m] >= 2, m + 1]})
 
 
 @dataclass

@@ -350,12 +350,43 @@ typedef struct {
                                  neuron is recorded but not expanded */
     int32_t first_only;       /* nonzero: only the first valid spiking vector of every configuration
                                  (each neuron fires its first applicable rule): one branch */
-    int32_t pad_;
+    int32_t out_neuron;       /* > 0: neuron out_neuron (1-based) is the output neuron, and every row
+                                 carries two more entries after the m counts: the spikes sent to the
+                                 environment so far (at most 2 counted) and the steps from the first
+                                 of them to the second (see out_track) */
 } or_bfs_opts;
+
+/* The output neuron's spike train (Definition 1: out, whose spikes go to the
+ * environment; Section 2.1: the number a computation generates is the time
+ * between the first two spikes the output neuron sends out).  A row's two
+ * extra entries (env, el) follow the train: q spikes leave at a step when the
+ * output neuron fires a rule producing q (0 when it fires nothing), and
+ *   env 0: env = min(2, q), el = 0;
+ *   env 1: env = min(2, 1 + q), el = el + 1;
+ *   env 2: unchanged (el is the number generated).
+ * A row with env = 2 is recorded but not expanded: what follows cannot change
+ * the number it generated. */
+static void out_track(const or_system *sys, const uint8_t *S, int32_t out, const int64_t *C, int64_t *child) {
+    const int32_t m = sys->m;
+    int64_t q = 0;
+    for (int32_t k = 0; k < sys->r; ++k)
+        if (S[k] && sys->rule_neuron[k] == out - 1) q = sys->rule_p[k];
+    const int64_t env = C[m], el = C[m + 1];
+    if (env == 0) {
+        child[m] = q < 2 ? q : 2;
+        child[m + 1] = 0;
+    } else if (env == 1) {
+        child[m] = 1 + q < 2 ? 1 + q : 2;
+        child[m + 1] = el + 1;
+    } else {
+        child[m] = env;
+        child[m + 1] = el;
+    }
+}
 
 typedef struct {
     /* caller-owned outputs */
-    int64_t *rows;        /* rows_cap * m */
+    int64_t *rows;        /* rows_cap rows of m entries (m + 2 with an output neuron) */
     int64_t rows_cap;
     int64_t *parent;      /* nullable, rows_cap: global index of the parent (-1 for C0) */
     int64_t *tindex;      /* nullable, rows_cap: index of the spiking vector among the parent's */
@@ -372,20 +403,23 @@ typedef struct {
 
 int or_bfs(const or_system *sys, const int64_t *c0, const or_bfs_opts *opt, or_bfs_result *res) {
     const int32_t m = sys->m;
+    const int32_t out = opt->out_neuron;
+    if (out < 0 || out > m) return OR_ERR_INVALID;
+    const int32_t w = m + (out > 0 ? 2 : 0); /* entries per row */
     int st = OR_OK;
-    for (int32_t n = 0; n < m; ++n)
+    for (int32_t n = 0; n < w; ++n)
         if (c0[n] < 0 || c0[n] > sys->count_max) return OR_ERR_OVERFLOW;
     if (res->rows_cap < 1 || res->max_levels < 1) return OR_ERR_CAPACITY;
     or_rows R = {0};
     if ((st = rows_build(sys, &R))) return st;
     uint8_t *S = malloc((size_t)(sys->r > 0 ? sys->r : 1));
-    int64_t *child = malloc(sizeof(int64_t) * (size_t)m);
+    int64_t *child = malloc(sizeof(int64_t) * (size_t)w);
     const int64_t *rows_view = res->rows;
     or_set H;
-    if (!S || !child || set_init(&H, m, &rows_view)) { rows_free(&R); free(S); free(child); return OR_ERR_NOMEM; }
+    if (!S || !child || set_init(&H, w, &rows_view)) { rows_free(&R); free(S); free(child); return OR_ERR_NOMEM; }
 
     /* level 0 = { C0 } */
-    memcpy(res->rows, c0, sizeof(int64_t) * (size_t)m);
+    memcpy(res->rows, c0, sizeof(int64_t) * (size_t)w);
     if (res->parent) res->parent[0] = -1;
     if (res->tindex) res->tindex[0] = -1;
     int64_t total = 1;
@@ -406,7 +440,7 @@ int or_bfs(const or_system *sys, const int64_t *c0, const or_bfs_opts *opt, or_b
         int64_t enumerated = 0, halting = 0, added = 0, last_par = -1;
         int all_halting = 1, budget_hit = 0, cap_hit = 0;
         for (int64_t par = lvl_begin; par < lvl_end && !cap_hit && !budget_hit && st == OR_OK; ++par) {
-            const int64_t *C = res->rows + par * m;
+            const int64_t *C = res->rows + par * w;
             or_enum E;
             if (enum_open(&E, sys, &R, C)) { enum_close(&E); st = OR_ERR_NOMEM; break; }
             if (!E.any) { enum_close(&E); continue; }
@@ -415,16 +449,21 @@ int or_bfs(const or_system *sys, const int64_t *c0, const or_bfs_opts *opt, or_b
             if (opt->expand_max_count >= 0)
                 for (int32_t n = 0; n < m; ++n)
                     if (C[n] > opt->expand_max_count) expand = 0;
+            if (out > 0 && C[m] >= 2) expand = 0; /* its number is generated */
             int64_t t = 0;
             while (expand && !E.done) {
                 if (opt->child_budget > 0 && enumerated >= opt->child_budget) { budget_hit = 1; break; }
                 enum_spiking_vector(&E, S);
                 if ((st = next_config(sys, &R, C, S, child))) break;
+                if (out > 0) {
+                    out_track(sys, S, out, C, child);
+                    if (child[m + 1] > sys->count_max) { st = OR_ERR_OVERFLOW; break; }
+                }
                 ++enumerated;
                 last_par = par;
                 if (set_find(&H, child) < 0) {
                     if (total >= res->rows_cap) { st = OR_ERR_CAPACITY; break; }
-                    memcpy(res->rows + total * m, child, sizeof(int64_t) * (size_t)m);
+                    memcpy(res->rows + total * w, child, sizeof(int64_t) * (size_t)w);
                     if (res->parent) res->parent[total] = par;
                     if (res->tindex) res->tindex[total] = t;
                     if ((st = set_insert(&H, total))) break;
@@ -446,7 +485,7 @@ int or_bfs(const or_system *sys, const int64_t *c0, const or_bfs_opts *opt, or_b
         const int64_t p_end = (cap_hit || budget_hit) ? last_par + 1 : lvl_end;
         for (int64_t par = lvl_begin; par < p_end; ++par) {
             or_enum E;
-            if (enum_open(&E, sys, &R, res->rows + par * m)) { enum_close(&E); st = OR_ERR_NOMEM; break; }
+            if (enum_open(&E, sys, &R, res->rows + par * w)) { enum_close(&E); st = OR_ERR_NOMEM; break; }
             if (!E.any) halting++;
             enum_close(&E);
         }

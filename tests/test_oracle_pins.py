@@ -485,3 +485,65 @@ def test_deterministic_walk_is_trajectory(oracle_mod, seed):
         n = 61
         assert w.stop_reason == oracle_mod.STOP_DEPTH
     assert [r.tolist() for r in w.rows] == [r.tolist() for r in traj[:n]]
+
+
+# ---------------------------------------------------------------------------
+# The output neuron (Definition 1's out): the numbers a system generates are
+# the steps between the first two spikes the output neuron sends to the
+# environment (Section 2.1; the example generates N - {1}).
+# ---------------------------------------------------------------------------
+def test_example_generates_n_minus_one(oracle_mod):
+    """Worked by hand under the textbook reading (E = a^k, rule 5 forgets two
+    spikes): sigma_3 spikes at step 1; sigma_1 picks rule 1 (back to 2-1-2,
+    sigma_3 forgetting) until it picks rule 2 at some step s >= 1, giving
+    1-1-2, then 2-0-1, whose step s + 2 sends the second spike: s + 1 for
+    every s >= 1, so the computations of at most D steps generate {2 .. D-1}."""
+    tb = synth.paper_example(True)
+    for D in range(1, 31):
+        res = oracle_mod.bfs(tb, max_depth=D, out_neuron=3)
+        assert oracle_mod.generated_numbers(res, 3) == list(range(2, D)), D
+    # rows never carry an elapsed count before the first spike
+    rows = oracle_mod.bfs(tb, max_depth=12, out_neuron=3).rows
+    assert (rows[rows[:, 3] == 0, 4] == 0).all()
+
+
+def _paths_generated(oracle_mod, s, out, depth):
+    """Brute force over every computation of at most `depth` steps (no
+    deduplication): the spike train of neuron `out` (1-based) along each path,
+    and the gap between its first two spikes."""
+    outs = [k for k in range(len(s.rule_neuron)) if int(s.rule_neuron[k]) == out - 1]
+    found = set()
+
+    def walk(C, d, times):
+        if len(times) >= 2:
+            found.add(times[1] - times[0])
+            return
+        if d == depth:
+            return
+        rows, S, psi = oracle_mod.children(s, C, max_out=4096)
+        assert psi <= 4096
+        for child, sv in zip(rows, S):
+            q = sum(int(s.rule_p[k]) for k in outs if sv[k])
+            walk(child, d + 1, times + [d + 1] * q)
+
+    walk(np.asarray(s.c0, dtype=np.int64), 0, [])
+    return sorted(found)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_generated_numbers_match_all_paths(oracle_mod, seed):
+    s = synth.config_system(1, seed)
+    for out in (1, 2, 3):
+        res = oracle_mod.bfs(s, max_depth=7, out_neuron=out)
+        assert oracle_mod.generated_numbers(res, s.m) == _paths_generated(oracle_mod, s, out, 7), (seed, out)
+
+
+def test_generated_numbers_of_the_example_match_all_paths(oracle_mod):
+    for textbook in (True, False):
+        s = synth.paper_example(textbook)
+        res = oracle_mod.bfs(s, max_depth=9, out_neuron=3)
+        assert oracle_mod.generated_numbers(res, 3) == _paths_generated(oracle_mod, s, 3, 9)
+    # the simulator's reading of the rule file (at least k spikes) also generates 1:
+    # sigma_3 may fire rule 4 again with 2 spikes right after its first spike
+    res = oracle_mod.bfs(synth.paper_example(False), max_depth=6, out_neuron=3)
+    assert oracle_mod.generated_numbers(res, 3)[0] == 1
