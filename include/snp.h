@@ -139,6 +139,18 @@ typedef struct {
                                  single branch of the computation tree (Section 2.1: one rule per
                                  neuron, all neurons on a global clock) and ends at its first
                                  repeated configuration (EMPTY_FRONTIER) or at a halting one */
+    int32_t out_neuron;       /* > 0: neuron out_neuron (1-based) is the output neuron (Definition 1,
+                                 out), and a row holds m + 2 entries: the m counts, then the
+                                 output neuron's spike train: the spikes it has sent to the
+                                 environment (at most 2 counted) and the steps from the first of
+                                 them to the second (0 before the first; after the second, the number
+                                 the computation generated, Section 2.1).  q spikes leave at a step
+                                 where the output neuron fires a rule producing q; with e spikes
+                                 sent and s steps counted before it: e = 0 gives (min(2, q), 0),
+                                 e = 1 gives (min(2, 1 + q), s + 1), e = 2 stays.  A configuration
+                                 whose train holds 2 spikes is recorded but not expanded.  Runs on
+                                 the sparse form (SNP_PATH_INT8 falls back, int8_fallback = 1);
+                                 0: off */
     void *stream;             /* hipStream_t for all work of the handle; NULL: default */
 } snp_options;
 
@@ -171,7 +183,8 @@ typedef struct {
     int32_t truncated;       /* 1: the level reached frontier_cap */
     int32_t budget_hit;      /* 1: child_budget ran out with children left */
     int32_t path_used;       /* snp_path of the last pass (SPARSE or INT8) */
-    int32_t int8_fallback;   /* 1: INT8 was requested but M does not fit int8 */
+    int32_t int8_fallback;   /* 1: INT8 was requested but M does not fit int8 (or an output neuron
+                                is followed, which only the sparse form does) */
     /* Device time of each stage summed over the level's passes, in ns (0 when
      * not timed; see snp_options.profile): applicability + Psi and its prefix
      * sum; child expansion (S.M + C); visited-set insert; first-occurrence flags

@@ -616,9 +616,25 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
             }
     }
 
+    // An output neuron adds two entries to every row (its spike train, read
+    // by the kernels): the device tables see two more neurons, without rules
+    // or synapses.
+    if (opt.out_neuron < 0 || opt.out_neuron > d->m)
+        return fail(SNP_ERR_INVALID, "out_neuron %d outside [0, m = %d]", opt.out_neuron, d->m);
+    snp_desc wide;
+    if (opt.out_neuron > 0) {
+        if (d->m + 2 > kMaxNeurons)
+            return fail(SNP_ERR_INVALID, "m + 2 (rows with the output neuron's spike train) above %d", kMaxNeurons);
+        wide = *d;
+        wide.m = d->m + 2;
+        wide.M = nullptr;
+        d = &wide;
+    }
+
     snp_system* S = new snp_system();
     S->m = d->m;
     S->r = d->r;
+    S->track = opt.out_neuron > 0 ? d->m - 2 : -1;
     S->elem_bytes = d->count_type == SNP_COUNT_U16 ? 2 : 4;
     S->count_max = d->count_type == SNP_COUNT_U16 ? 65535 : INT_MAX;
     S->opt = opt;
@@ -700,7 +716,7 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     LOADCHK(up(S->d_R, R.data(), sizeof(u64) * d->m));
     LOADCHK(up(S->d_hM, hM.data(), sizeof(u64) * d->r));
     // int8 copy of M_Pi for the matrix-core form (every |entry| <= 127, <= 16 rules per neuron)
-    S->int8_ready = int8_ok && max_rules <= 16 && opt.path != SNP_PATH_SPARSE &&
+    S->int8_ready = int8_ok && S->track < 0 && max_rules <= 16 && opt.path != SNP_PATH_SPARSE &&
                     snp::int8_lds(d->m, 64) <= 64 * 1024 && (size_t)d->r * d->m <= ((size_t)1 << 33);
     if (S->int8_ready) {
         std::vector<int8_t> M8((size_t)d->r * d->m, 0);
@@ -725,10 +741,11 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
             for (int e = 0; e < in_ptr[n + 1] - in_ptr[n]; ++e) in_lane[e * 64 + n] = in_src[in_ptr[n] + e];
     LOADCHK(dmalloc(&S->d_in_lane, sizeof(int) * in_lane.size()));
     LOADCHK(up(S->d_in_lane, in_lane.data(), sizeof(int) * in_lane.size()));
-    S->lane_form = d->m <= 64 && max_in <= 16 && (size_t)d->r * 24 <= 24 * 1024;
+    S->lane_form = S->track < 0 && d->m <= 64 && max_in <= 16 && (size_t)d->r * 24 <= 24 * 1024;
     S->dsys = snp::DevSystem{d->m, d->r, S->d_nrule_ptr, S->d_rules, S->d_in_ptr, S->d_in_src, d->n_syn, S->d_M8,
                              S->count_max, S->d_R, S->d_hM, max_in, S->d_in_lane,
-                             opt.deterministic ? 1ULL : snp::kPsiSat};
+                             opt.deterministic ? 1ULL : snp::kPsiSat, S->track,
+                             opt.out_neuron > 0 ? opt.out_neuron - 1 : -1};
 
     S->slots = next_pow2((u64)std::max<long long>(1024, 2 * (S->max_rows + 2 * S->chunk_max)));
     LOADCHK(dmalloc(&S->d_table, sizeof(u64) * S->slots));
@@ -1159,6 +1176,8 @@ snp_status snp_run_batch(snp_system* const* systems, int32_t n, const void* cons
         return fail(SNP_ERR_INVALID, "systems, c0_dev, final_dev and every result array are required (n >= 1)");
     for (int k = 0; k < n; ++k) {
         if (!systems[k]) return fail(SNP_ERR_INVALID, "system %d is NULL", k);
+        if (systems[k]->track >= 0)
+            return fail(SNP_ERR_INVALID, "system %d follows an output neuron: the batched mode does not", k);
         if (!c0_dev[k] || !final_dev[k]) return fail(SNP_ERR_INVALID, "system %d: c0 or final is NULL", k);
         if (systems[k]->count_type != systems[0]->count_type)
             return fail(SNP_ERR_INVALID, "system %d: all systems must share one count type", k);

@@ -21,6 +21,7 @@ snp_status set_error(snp_status st, const char* fmt, ...);
 
 struct snp_system {
     int m = 0, r = 0, elem_bytes = 4;
+    int track = -1;  // column of the output neuron's spike train in a row (-1: none); m counts it
     // the host description, kept for snp_run_batch (which packs the handles'
     // systems into one batched launch), and an id no other handle ever gets
     std::vector<int32_t> h_rn, h_ri, h_rj, h_rc, h_rp, h_ss, h_sd;

@@ -65,6 +65,11 @@ struct DevSystem {
                            // filled when m <= 64 and max_in <= 16
     u64 psi_cap;           // largest Psi of a parent: 1 in deterministic mode (first spiking
                            // vector only), kPsiSat otherwise
+    int track;             // >= 0: rows end with the output neuron's spike train, the spikes
+                           // sent to the environment (at most 2 counted) at column track and
+                           // the steps from the first to the second at track + 1; the m
+                           // above counts these two columns (neurons without rules or synapses)
+    int out;               // the output neuron (with track >= 0)
 };
 
 // One chunk of canonical children [g0, g0 + B) of the frontier (canonical

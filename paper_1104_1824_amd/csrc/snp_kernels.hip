@@ -49,14 +49,18 @@ struct PsiAcc {
     u64 bigprod = 1, kbigprod = 1;
 };
 
-// Neuron j (< m) holding x spikes: its applicable rules, into the wave's tallies.
+// Neuron j (< m) holding x spikes: its applicable rules, into the wave's
+// tallies.  A parent is not expanded (Psi = 0, not halting) when a neuron
+// holds more than expand_max spikes, or when its output spike train (columns
+// track, track + 1; track < 0: none) has two spikes: its number is generated.
 __device__ __forceinline__ void psi_add_neuron(PsiAcc& A, int x, int j, int m, const int* nrp, const int4* rules,
-                                               long long expand_max) {
+                                               long long expand_max, int track) {
     int w = 0, k = 1;
     if (j < m) {
         const uint32_t am = neuron_applicable(x, nrp[j], nrp[j + 1], rules, w);
         k = kappa_of(am, w);
-        A.over |= (expand_max >= 0 && (long long)x > expand_max);
+        const bool count = track < 0 || j < track;
+        A.over |= (count && expand_max >= 0 && (long long)x > expand_max) || (j == track && x >= 2);
     }
     A.any |= (w > 0);
     A.c2 += __popcll(__ballot(w == 2));
@@ -157,11 +161,11 @@ __device__ u64 canon_rank(const T* row, int m, const int* nrp, const int4* rules
 
 template <typename T>
 __device__ __forceinline__ PsiPair parent_psi(const T* row, int m, const int* nrp, const int4* rules,
-                                              long long expand_max, int lane, bool& halting) {
+                                              long long expand_max, int track, int lane, bool& halting) {
     PsiAcc A;
     for (int base = 0; base < m; base += 64) {
         const int j = base + lane;
-        psi_add_neuron(A, j < m ? (int)row[j] : 0, j, m, nrp, rules, expand_max);
+        psi_add_neuron(A, j < m ? (int)row[j] : 0, j, m, nrp, rules, expand_max, track);
     }
     PsiPair r = psi_finish(A, halting);
     // with 2^62 or more children some canonical ones may have t >= 2^62, past
@@ -210,7 +214,7 @@ __global__ __launch_bounds__(256) void k_psi(DevSystem s, const T* __restrict__ 
     u64 flo = 0, fhi = 0;
     for (long long p = w0; p < min(n, w0 + parents_per_wave); ++p) {
         bool h;
-        const PsiPair v = parent_psi<T>(F + p * (long long)s.m, s.m, tb.nrp, tb.rules, expand_max, lane, h);
+        const PsiPair v = parent_psi<T>(F + p * (long long)s.m, s.m, tb.nrp, tb.rules, expand_max, s.track, lane, h);
         const u64 full = min(v.full, s.psi_cap);
         if (lane == 0) {
             psi[p] = min(v.canon, s.psi_cap);
@@ -261,7 +265,7 @@ __global__ __launch_bounds__(1024) void k_psi_scan_small(DevSystem s, const T* _
             const int p = p0 + 16 * q;
             if (p >= n) break;
             PsiAcc A;
-            psi_add_neuron(A, xs[q], lane, m, tb.nrp, tb.rules, expand_max);
+            psi_add_neuron(A, xs[q], lane, m, tb.nrp, tb.rules, expand_max, s.track);
             bool h;
             PsiPair v2 = psi_finish(A, h);
             if (v2.full >= kPsiSat)
@@ -645,6 +649,18 @@ __device__ __forceinline__ void load_parent(const Tables& tb, int m, const T* ro
     }
 }
 
+// The output neuron's spike train of a child (column j = track: spikes sent
+// to the environment, at most 2 counted; j = track + 1: steps from the first
+// to the second), from the parent's (par) and the q spikes the output neuron
+// sends out with its fired rule (cp: (c << 16) | p, 0 when it fires nothing).
+__device__ __forceinline__ long long spike_train(const DevSystem& s, const int* par, const uint8_t* om,
+                                                 const uint32_t* cp, int j) {
+    const long long q = om[s.out] ? (long long)(cp[s.out] & 0xFFFFu) : 0;
+    const long long env = par[s.track], el = par[s.track + 1];
+    if (j == s.track) return env == 0 ? min(2LL, q) : env == 1 ? min(2LL, 1 + q) : env;
+    return env == 0 ? 0 : env == 1 ? el + 1 : el;
+}
+
 __host__ __device__ __forceinline__ size_t table_lds_bytes(const DevSystem& s, int nnz) {
     return ((size_t)((s.m + 1) & ~1) * 8 + (size_t)s.r * 16 + (size_t)(s.m + 1) * 8 + (size_t)nnz * 4 + 15) &
            ~(size_t)15;
@@ -726,6 +742,7 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
             long long v = (long long)par[j] - (long long)(cp[j] >> 16);
             const int e1 = tb.inp[j + 1];
             for (int e = tb.inp[j]; e < e1; ++e) v += cp[tb.ins[e]] & 0xFFFFu;
+            if (s.track >= 0 && j >= s.track) v = spike_train(s, par, om, cp, j);
             ovf |= (v < 0) | (v > s.count_max);
             out[j] = (T)v;
             h += hterm((uint32_t)v, tb.R[j]);
@@ -1225,7 +1242,7 @@ hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkA
                                 bool* probed) {
     *probed = false;
     if (a.B <= 0) return hipSuccess;
-    if (s.m <= 64 && s.max_in <= kLaneMaxIn && (size_t)s.r * 24 <= 24 * 1024) {
+    if (s.track < 0 && s.m <= 64 && s.max_in <= kLaneMaxIn && (size_t)s.r * 24 <= 24 * 1024) {
         *probed = a.table != nullptr;
         // one generation of resident waves (the LDS tables allow 16 per CU);
         // runs of 4 to 4096 children are handed out on the device, where the
@@ -1673,7 +1690,7 @@ __global__ __launch_bounds__(256) void k_start_walk(int m, const u64* __restrict
                                                     long long count_max, u64 hash_mask,
                                                     uint32_t* __restrict__ row_slot, DevCounters* __restrict__ sc,
                                                     long long* par0, long long* chi0, const int* nrp,
-                                                    const int4* rules, long long expand_max, u64 psi_cap,
+                                                    const int4* rules, long long expand_max, u64 psi_cap, int track,
                                                     u64* psi0, u64* psif0, uint8_t* hflag0, u64* off0, u64* Tdev) {
     __shared__ u64 s_slot, s_entry;
     const int lane = threadIdx.x & 63;
@@ -1702,7 +1719,7 @@ __global__ __launch_bounds__(256) void k_start_walk(int m, const u64* __restrict
     // when asked: the first pass then needs no Psi launch of its own
     PsiPair psi_c0{0, 0};
     bool halt_c0 = false;
-    if (psi0 && threadIdx.x < 64) psi_c0 = parent_psi<T>(c0, m, nrp, rules, expand_max, lane, halt_c0);
+    if (psi0 && threadIdx.x < 64) psi_c0 = parent_psi<T>(c0, m, nrp, rules, expand_max, track, lane, halt_c0);
     if (threadIdx.x == 0) {
         row_slot[0] = (uint32_t)home;
         if (par0) *par0 = -1;
@@ -1733,11 +1750,11 @@ hipError_t launch_start_walk(int elem_bytes, int m, const u64* R, u64* table, u6
     if (elem_bytes == 4)
         hipLaunchKernelGGL(k_start_walk<int32_t>, dim3(blocks), dim3(256), 0, st, m, R, table, slot_mask,
                            (const int32_t*)c0, (int32_t*)arena, count_max, hash_mask, row_slot, sc, par0, chi0,
-                           s.nrule_ptr, s.rules, expand_max, s.psi_cap, psi0, psif0, hflag0, off0, Tdev);
+                           s.nrule_ptr, s.rules, expand_max, s.psi_cap, s.track, psi0, psif0, hflag0, off0, Tdev);
     else
         hipLaunchKernelGGL(k_start_walk<uint16_t>, dim3(blocks), dim3(256), 0, st, m, R, table, slot_mask,
                            (const uint16_t*)c0, (uint16_t*)arena, count_max, hash_mask, row_slot, sc, par0, chi0,
-                           s.nrule_ptr, s.rules, expand_max, s.psi_cap, psi0, psif0, hflag0, off0, Tdev);
+                           s.nrule_ptr, s.rules, expand_max, s.psi_cap, s.track, psi0, psif0, hflag0, off0, Tdev);
     return hipGetLastError();
 }
 

@@ -53,7 +53,7 @@ class snp_options(ctypes.Structure):
         ("expand_max_count", ctypes.c_int64), ("max_rows", ctypes.c_int64),
         ("max_frontier", ctypes.c_int64), ("chunk", ctypes.c_int64),
         ("hash_mask", ctypes.c_uint64), ("profile", ctypes.c_int32), ("int8_max_k", ctypes.c_int32),
-        ("deterministic", ctypes.c_int32), ("stream", ctypes.c_void_p),
+        ("deterministic", ctypes.c_int32), ("out_neuron", ctypes.c_int32), ("stream", ctypes.c_void_p),
     ]
 
 
@@ -254,11 +254,12 @@ def _stream_ptr(stream):
 def snp_load(system, *, path: int = SNP_PATH_AUTO, stop_at_cap: bool = False, frontier_cap: int = 0,
              child_budget: int = 0, expand_max_count: int = -1, max_rows: int = 1 << 20,
              max_frontier: int = 0, chunk: int = 0, hash_mask: int = 0, profile: int = 0,
-             int8_max_k: int = 0, deterministic: bool = False, stream=None,
+             int8_max_k: int = 0, deterministic: bool = False, out_neuron: int = 0, stream=None,
              M: Optional[np.ndarray] = None) -> Handle:
     """snp_load.  ``system`` has m, rule_neuron/i/j/c/p, syn_src/dst and
     count_type ("i32" or "u16") attributes; ``stream`` is a torch.cuda.Stream
-    (None: torch's current stream)."""
+    (None: torch's current stream).  With ``out_neuron`` > 0 (1-based) rows
+    hold m + 2 entries (the output neuron's spike train after the counts)."""
     arrs = []
     d = _desc(system, arrs, M)
     ct = d.count_type
@@ -266,10 +267,10 @@ def snp_load(system, *, path: int = SNP_PATH_AUTO, stop_at_cap: bool = False, fr
     o = snp_options(int(path), int(bool(stop_at_cap)), int(frontier_cap), int(child_budget),
                     int(expand_max_count), int(max_rows), int(max_frontier), int(chunk),
                     int(hash_mask) & ((1 << 64) - 1), int(profile), int(int8_max_k), int(bool(deterministic)),
-                    sp or None)
+                    int(out_neuron), sp or None)
     out = ctypes.c_void_p()
     _check(lib().snp_load(ctypes.byref(d), ctypes.byref(o), ctypes.byref(out)), "snp_load")
-    return Handle(out.value, arrs, int(system.m), ct)
+    return Handle(out.value, arrs, int(system.m) + (2 if out_neuron else 0), ct)
 
 
 def snp_free(h: Handle):
