@@ -80,7 +80,7 @@ def device_rows(system, rows):
 class Walk:
     """A loaded handle plus its device buffers, for timed snp_run calls."""
 
-    def __init__(self, system, path, cap, depth, stop, chunk, out_cap, profile, tune=False):
+    def __init__(self, system, path, cap, depth, stop, chunk, out_cap, profile, tune=False, cache=None):
         import torch
 
         from paper_1104_1824_amd import snp
@@ -91,8 +91,13 @@ class Walk:
         self.c0 = device_rows(system, system.c0)
         dt = torch.int16 if system.count_type == "u16" else torch.int32
         self.out = torch.empty((out_cap, system.m), dtype=dt, device="cuda")
-        # launch settings timed on this very walk, before (and outside) the timed region
-        self.tuning = snp.snp_autotune(self.h, self.c0, depth, self.out, out_cap) if tune else None
+        # launch settings timed on this very walk, before (and outside) the timed region;
+        # with a cache file, settings found there are used as they are
+        self.tuning = None
+        if tune and cache and snp.snp_load_tuning(self.h, cache, depth):
+            self.tuning = dict(snp.snp_get_tuning(self.h), cached=True)
+        elif tune:
+            self.tuning = snp.snp_autotune(self.h, self.c0, depth, self.out, out_cap, cache)
 
     def run(self):
         return self.snp.snp_run(self.h, self.c0, self.depth, self.out, self.out_cap)
@@ -119,7 +124,37 @@ def totals(results, key):
     return sum(st[key] for r in results for st in r["level_stats"])
 
 
-def hbm_roofline(results, kernel, bytes_per_new, rb, per_child=False):
+# Source files of each measured kernel: the traffic a profiles/*_traffic.md
+# summary records is reported only while their SHA-256 is the one it names.
+KERNEL_SOURCES = {
+    "k_expand_int8": ["paper_1104_1824_amd/csrc/snp_int8.hip", "paper_1104_1824_amd/csrc/snp_device.hpp",
+                      "paper_1104_1824_amd/csrc/snp_internal.hpp"],
+    "k_expand_lane": ["paper_1104_1824_amd/csrc/snp_kernels.hip", "paper_1104_1824_amd/csrc/snp_device.hpp",
+                      "paper_1104_1824_amd/csrc/snp_internal.hpp"],
+}
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter
+    summaries (profiles/*_traffic.md), or None when none matches the current
+    kernel sources."""
+    import glob
+    import hashlib
+    import re
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kernel, []):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    want = h.hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
+        fields = dict(re.findall(r"^- `(\w+)`: `([^`]*)`", open(path).read(), re.M))
+        if fields.get("kernel") == kernel and fields.get("workload") == workload:
+            if fields.get("kernel_source_sha256") == want:
+                return int(fields["traffic_bytes_per_launch"])
+    return None
+
+
+def hbm_roofline(results, kernel, bytes_per_new, rb, per_child=False, workload=None):
     """Roofline of the expansion kernel: algorithmic bytes over its device time
     (HIP events around each launch).  Algorithmic bytes = every new configuration's
     row plus its visited-set entry (bytes_per_new); with per_child, the
@@ -135,7 +170,8 @@ def hbm_roofline(results, kernel, bytes_per_new, rb, per_child=False):
     steps = max(1, len(results))
     return dict(
         roofline=dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None),
+                      frac=round(achieved / HBM_PEAK_GBS, 4),
+                      traffic=measured_traffic(kernel, workload) if workload else None),
         dominant_kernel=dict(kernel=kernel, launches_per_step=launches // steps,
                              bytes_per_launch=round(moved / max(1, launches)),
                              avg_launch_us=round(ns / max(1, launches) / 1e3, 3),
@@ -160,12 +196,12 @@ def dense_system():
     return synth.config_system(3, 0)
 
 
-def run_dense(steps, warmup, tune):
+def run_dense(steps, warmup, tune, cache=None):
     from paper_1104_1824_amd import snp
 
     s = dense_system()
     log(f"dense m=512 seed 0, int8 path: warmup {warmup}, steps {steps}")
-    w = Walk(s, snp.SNP_PATH_INT8, 1000000, 3, False, 1 << 20, 3000001, profile=1, tune=tune)
+    w = Walk(s, snp.SNP_PATH_INT8, 1000000, 3, False, 1 << 20, 3000001, profile=1, tune=tune, cache=cache)
     if w.tuning:
         log(f"tuned launch settings: {w.tuning}")
     results, dt = w.timed(steps, warmup)
@@ -242,20 +278,20 @@ def cpu_large():
                        f"({int(res.enumerated[0])} children enumerated), single-threaded, {dt:.1f} s")
 
 
-def plain_line(steps=50, warmup=5, cpu=None, tune=True):
+def plain_line(steps=50, warmup=5, cpu=None, tune=True, cache=None):
     import synth
     from paper_1104_1824_amd import snp
 
     s = synth.config_system(2, 0)
     log("plain sparse m=64 seed 0, sparse path")
-    w = Walk(s, snp.SNP_PATH_SPARSE, 100000, 1000, True, 1 << 17, 200000, profile=1, tune=tune)
+    w = Walk(s, snp.SNP_PATH_SPARSE, 100000, 1000, True, 1 << 17, 200000, profile=1, tune=tune, cache=cache)
     results, dt = w.timed(steps, warmup)
     w.close()
     new = results[-1]["n_configs"] - 1
     line = dict(workload=PLAIN_WORKLOAD, value=round(steps * new / dt, 1), unit="configs/s",
                 ms_per_step=round(dt / steps * 1e3, 4), levels=results[-1]["level_sizes"].tolist(), dtype="int32",
                 tuning=w.tuning)
-    line.update(hbm_roofline(results, "k_expand_lane", None, s.m * 4, per_child=True))
+    line.update(hbm_roofline(results, "k_expand_lane", None, s.m * 4, per_child=True, workload="plain_sparse"))
     line["cpu_baseline"] = cpu
     return line
 
@@ -340,13 +376,13 @@ def cpu_batched(sample=16):
                                 sample=f"all 256 systems, one per task, {dtn:.1f} s"))
 
 
-def large_line(cpu=None, tune=True):
+def large_line(cpu=None, tune=True, cache=None):
     import synth
     from paper_1104_1824_amd import snp
 
     s = synth.config_system(5, 0)
     log("large m=4096 uint16, automatic path, depth 3, cap 4e6")
-    w = Walk(s, snp.SNP_PATH_AUTO, 4000000, 3, False, 1 << 22, 12000001, profile=1, tune=tune)
+    w = Walk(s, snp.SNP_PATH_AUTO, 4000000, 3, False, 1 << 22, 12000001, profile=1, tune=tune, cache=cache)
     results, dt = w.timed(3, 1)
     w.close()
     new = results[-1]["n_configs"] - 1
@@ -354,7 +390,7 @@ def large_line(cpu=None, tune=True):
                 ms_per_step=round(dt / 3 * 1e3, 3), levels=results[-1]["level_sizes"].tolist(), dtype="uint16",
                 twins=totals(results, "twins"), expanded=totals(results, "expanded"), tuning=w.tuning,
                 int8_passes=totals(results, "int8_chunks"), passes=totals(results, "chunks"))
-    line.update(hbm_roofline(results, "k_expand_int8", s.m * 2 + ENTRY_BYTES, s.m * 2))
+    line.update(hbm_roofline(results, "k_expand_int8", s.m * 2 + ENTRY_BYTES, s.m * 2, workload="large"))
     line["mfma"] = mfma_util(results)
     line["cpu_baseline"] = cpu
     return line
@@ -385,6 +421,9 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="skip the plain-sparse / batched / large lines")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the library's built-in launch settings (no autotuning before the timed walks)")
+    ap.add_argument("--tuning-cache", default=None,
+                    help="JSON tuning cache: settings recorded there for a workload are used without tuning, "
+                         "new ones are recorded")
     ap.add_argument("--only", choices=sorted(SECONDARY) + ["dense"],
                     help="run only this workload (no CPU baseline) and print its line")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -412,20 +451,23 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     if args.only and args.only != "dense":
-        print(json.dumps({args.only: SECONDARY[args.only]()}), flush=True)
+        kw = {} if args.only == "batched" else dict(tune=not args.no_tune, cache=args.tuning_cache)
+        print(json.dumps({args.only: SECONDARY[args.only](**kw)}), flush=True)
         return
-    s, results, dt = run_dense(args.steps, args.warmup, not args.no_tune)
+    s, results, dt = run_dense(args.steps, args.warmup, not args.no_tune, args.tuning_cache)
     if args.only == "dense":
         print(json.dumps(dict(ms_per_step=round(dt / args.steps * 1e3, 4),
-                              **hbm_roofline(results, "k_expand_int8", s.m * 4 + ENTRY_BYTES, s.m * 4))), flush=True)
+                              **hbm_roofline(results, "k_expand_int8", s.m * 4 + ENTRY_BYTES, s.m * 4,
+                                             workload="dense"))), flush=True)
         return
     new = results[-1]["n_configs"] - 1
-    rl = hbm_roofline(results, "k_expand_int8", s.m * 4 + ENTRY_BYTES, s.m * 4)
+    rl = hbm_roofline(results, "k_expand_int8", s.m * 4 + ENTRY_BYTES, s.m * 4, workload="dense")
     sparse = run_dense_sparse(tune=not args.no_tune)
     ms = dt / args.steps * 1e3
     secondary = None
     if not args.no_secondary:
-        secondary = {name: fn(cpu=cpus.get(name), **({} if name == "batched" else dict(tune=not args.no_tune)))
+        secondary = {name: fn(cpu=cpus.get(name), **({} if name == "batched" else
+                                                      dict(tune=not args.no_tune, cache=args.tuning_cache)))
                      for name, fn in SECONDARY.items()}
     cpu = cpus.get("dense")
     line = {
