@@ -129,10 +129,11 @@ typedef struct {
                                  (snp_expand_stats.ns_expand); >= 2: time every stage (every
                                  ns_* field); 0: no events.  The events are created for timing
                                  only (no system-scope fence when one is reached). */
-    int32_t int8_max_k;       /* int8 path: most rule columns (1..128) one segment of children
-                                 may put on the matrix cores, 0: 128; segments that need more
-                                 take the per-child sparse form (smaller values force it;
-                                 results do not change) */
+    int32_t int8_max_k;       /* int8 path: most rule columns one segment of children may put on
+                                 the matrix cores (1..128, values above 64 act as 64; 0: 64); a
+                                 segment that needs more is halved until it fits, a single child
+                                 being computed by the pull (smaller values force shorter
+                                 segments; results do not change) */
     int32_t deterministic;    /* nonzero: every configuration has at most one child, the one
                                  that fires the first applicable rule of every neuron (the first
                                  spiking vector of Algorithm 2 step II-3), so a walk follows a

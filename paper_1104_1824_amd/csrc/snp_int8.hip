@@ -1,6 +1,6 @@
 // Expansion on int8 matrix cores (gfx950 v_mfma_i32_16x16x64_i8).
 //
-// A block expands a tile of 64 consecutive canonical children (children whose
+// A block expands a tile of 256 consecutive canonical children (children whose
 // every digit is canonical: twins, which repeat an earlier child, are never
 // enumerated).  The tile is cut into segments of one parent each; within a
 // segment of canonical children u_a .. u_b only the least significant
@@ -13,14 +13,16 @@
 //
 // where M_V stacks the rows of M_Pi of the canonical rules of the neurons in
 // V and D(u) holds +1 at the rule a neuron of V fires in child u and -1 at the
-// rule it fires in child u_a (0 where they agree): a 64 x K int8 matrix times
+// rule it fires in child u_a (0 where they agree): a 256 x K int8 matrix times
 // a K x m int8 matrix with int32 accumulation, exact because every entry of
-// M_Pi fits int8 and K <= 128.  The reference child comes from the sparse
+// M_Pi fits int8 and K <= 64.  The reference child comes from the sparse
 // pull of Equation next-config; the hash of every row follows from linearity,
 // H(child(u)) = H(child(u_a)) + D(u) . H(M_V), without reading the row, and
 // so does its child index t (linear in the digits, with the place values of
-// the full mixed radix).  Segments whose V needs more than 64 neurons or 128
-// rule columns fall back to the sparse pull for each of their children.
+// the full mixed radix).  A segment whose V needs more than 64 neurons or 64
+// rule columns is halved until it fits; a single child is computed by the pull.
+// The transposed M_V of a column tile is staged once and serves the segment's
+// four 64-row quarters, each a 4 x (NT / 64) grid of 16 x 16 products per wave.
 //
 // MFMA operand layout (checked on the device): lane l supplies row l % 16 of
 // A and column l % 16 of B, with the 16 int8 of lane group l / 16 covering
@@ -34,8 +36,8 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-constexpr int kTile = 64;   // children per block
-constexpr int kKMax = 128;  // rule columns of V per segment on the MFMA path
+constexpr int kTile = 256;  // children per block tile (one per thread)
+constexpr int kKMax = 64;   // rule columns of V per segment on the MFMA path (one 64-deep K step)
 constexpr int kVMax = 64;   // neurons in V per segment on the MFMA path
 constexpr int kMTStride = kKMax + 16;  // bytes per column of the transposed M_V tile (padding vs bank conflicts)
 
@@ -52,7 +54,7 @@ struct Lds {
     int* kbase;    // [kVMax] first K column of every neuron of V
     u64* rowh;     // [kTile] H of every row of the tile
     u64* placev;   // [kVMax] place value (over omega) of every neuron of V
-    u64* wsum;     // [4]
+    u64* wsum;     // [5]: [0..3] block sums, [4] the reference child's index t
     int* sc;       // scalars: [0] jstar, [1] nv, [2] kvar
 };
 
@@ -63,7 +65,7 @@ __host__ __device__ __forceinline__ size_t int8_lds_bytes(int m, int nt) {
     o += align16((size_t)4 * m) + align16((size_t)2 * m);
     o += (size_t)kTile * kKMax + (size_t)nt * kMTStride;
     o += align16((size_t)kKMax * 4) + (size_t)kVMax * 4 * 2;
-    o += (size_t)kTile * 8 + (size_t)kVMax * 8 + 4 * 8 + 4 * 4;
+    o += (size_t)kTile * 8 + (size_t)kVMax * 8 + 5 * 8 + 4 * 4;
     return align16(o);
 }
 
@@ -93,7 +95,7 @@ __device__ __forceinline__ Lds carve(unsigned char* smem, int m, int nt) {
     L.placev = (u64*)(smem + o);
     o += (size_t)kVMax * 8;
     L.wsum = (u64*)(smem + o);
-    o += 4 * 8;
+    o += 5 * 8;
     L.sc = (int*)(smem + o);
     return L;
 }
@@ -169,6 +171,7 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
     const T* F = (const T*)a.frontier;
     T* stage = (T*)a.stage;
     bool ovf = false;
+    const int kmax = min(a.kmax, kKMax);
 
     // parent of the first tile's first child: 64-ary search over the offsets;
     // later tiles go on from where the previous one stopped
@@ -194,7 +197,7 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
     long long have_p = -1;
     u64 place_k = 0, place_w = 0;
     u64 nmfma = 0;  // matrix-core instructions of this block (thread 0)
-    u64 my_t = 0;   // wave 0, lane l: child index t of row l of the tile
+    u64 my_t = 0;   // thread r: child index t of row r of the tile
 
     for (int tt = 0; tt < tiles_per_block; ++tt) {
     const long long b0 = (tile0 + tt) * kTile;
@@ -203,9 +206,7 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
     int c = 0;
     while (c < rows) {
         const u64 psi_p = a.psi[p];
-        const int len = (int)min((u64)(rows - c), psi_p - ua);
-        const int cend = c + len;
-        const u64 ub = ua + (u64)(len - 1);
+        int len = (int)min((u64)(rows - c), psi_p - ua);
         const T* P = F + p * (long long)m;
 
         // 1. applicability of the parent (kept while the parent stays)
@@ -217,169 +218,157 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
                 L.om[j] = (uint8_t)w;
             }
             have_p = p;
-        }
-        if (tid == 0) L.sc[0] = m;
-        __syncthreads();
-        // 2. canonical digits of the first and last child of the segment
-        if (wid == 0) {
-            if (fresh) {
+            __syncthreads();
+            if (wid == 0) {
                 place_k = canon_place(m, lane, L.om, L.am);
                 place_w = digit_place(m, lane, L.om);
             }
-            canon_decode(m, lane, ua, L.om, L.am, L.dg, place_k);
-            canon_decode(m, lane, ub, L.om, L.am, L.dgb, place_k);
         }
-        __syncthreads();
-        // 3. most significant differing digit
-        int myj = m;
-        for (int j = tid; j < m; j += blockDim.x)
-            if (L.dg[j] != L.dgb[j]) myj = min(myj, j);
-        if (myj < m) atomicMin(&L.sc[0], myj);
-        __syncthreads();
-        const int jstar = L.sc[0];
-        // 4. V (neurons with kappa >= 2 from jstar on), its rule columns and
-        //    the place values of its neurons; the reference child's index
-        if (wid == 0) {
-            int nv = 0;
-            for (int base = jstar; base < m; base += 64) {
-                const int j = base + lane;
-                const bool pred = j < m && kappa(L, j) >= 2;
-                const u64 bm = __ballot(pred);
-                const int pos = nv + __popcll(bm & ((1ULL << lane) - 1));
-                if (pred && pos < kVMax) L.vlist[pos] = j;
-                nv += __popcll(bm);
+        // 2-4. digits of the segment's first and last child, V and its rule
+        //      columns; a segment whose V does not fit is halved until it does
+        int nv = 0, kvar = 0;
+        for (;;) {
+            if (tid == 0) L.sc[0] = m;
+            const u64 ub = ua + (u64)(len - 1);
+            if (wid == 0) {
+                canon_decode(m, lane, ua, L.om, L.am, L.dg, place_k);
+                canon_decode(m, lane, ub, L.om, L.am, L.dgb, place_k);
             }
-            const bool inv = lane < min(nv, kVMax);
-            const int jv = inv ? L.vlist[lane] : 0;
-            int w = inv ? kappa(L, jv) : 0;
-            int incl = w;
+            __syncthreads();
+            int myj = m;
+            for (int j = tid; j < m; j += blockDim.x)
+                if (L.dg[j] != L.dgb[j]) myj = min(myj, j);
+            if (myj < m) atomicMin(&L.sc[0], myj);
+            __syncthreads();
+            const int jstar = L.sc[0];
+            if (wid == 0) {
+                int cnt = 0;
+                for (int base = jstar; base < m; base += 64) {
+                    const int j = base + lane;
+                    const bool pred = j < m && kappa(L, j) >= 2;
+                    const u64 bm = __ballot(pred);
+                    const int pos = cnt + __popcll(bm & ((1ULL << lane) - 1));
+                    if (pred && pos < kVMax) L.vlist[pos] = j;
+                    cnt += __popcll(bm);
+                }
+                const bool inv = lane < min(cnt, kVMax);
+                const int jv = inv ? L.vlist[lane] : 0;
+                const int w = inv ? kappa(L, jv) : 0;
+                int incl = w;
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int y = __shfl_up(incl, o);
-                if (lane >= o) incl += y;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(incl, o);
+                    if (lane >= o) incl += y;
+                }
+                const int kb = incl - w;
+                const int kv = __shfl(incl, 63);
+                // place value of neuron jv: its block's (lane jv / Q of place_w)
+                // times omega of the block's neurons after it
+                const int Q = (m + 63) >> 6;
+                const u64 pb = __shfl(place_w, jv / Q);
+                if (inv) {
+                    L.kbase[lane] = kb;
+                    for (int d = 0; d < w && kb + d < kKMax; ++d) L.klist[kb + d] = rule_of(s, L, jv, d);
+                    u64 pl = pb;
+                    for (int j = jv + 1; j < min(m, (jv / Q) * Q + Q); ++j) pl *= (u64)max(1, (int)L.om[j]);
+                    L.placev[lane] = pl;
+                }
+                const u64 t_ref = child_index(m, lane, L.om, L.am, L.dg, place_w);
+                if (lane == 0) {
+                    L.sc[1] = cnt;
+                    L.sc[2] = kv;
+                    L.wsum[4] = t_ref;
+                }
             }
-            const int kb = incl - w;
-            const int kvar = __shfl(incl, 63);
-            // place value of neuron jv: its block's (lane jv / Q of place_w)
-            // times omega of the block's neurons after it
-            const int Q = (m + 63) >> 6;
-            const u64 pb = __shfl(place_w, jv / Q);
-            if (inv) {
-                L.kbase[lane] = kb;
-                for (int d = 0; d < w && kb + d < kKMax; ++d) L.klist[kb + d] = rule_of(s, L, jv, d);
-                u64 pl = pb;
-                for (int j = jv + 1; j < min(m, (jv / Q) * Q + Q); ++j) pl *= (u64)max(1, (int)L.om[j]);
-                L.placev[lane] = pl;
-            }
-            const u64 t_ref = child_index(m, lane, L.om, L.am, L.dg, place_w);
-            if (lane == c) my_t = t_ref;
-            if (lane == 0) {
-                L.sc[1] = nv;
-                L.sc[2] = kvar;
-            }
+            __syncthreads();
+            nv = L.sc[1];
+            kvar = L.sc[2];
+            if (len == 1 || (nv <= kVMax && kvar <= kmax)) break;
+            len = (len + 1) / 2;
+            __syncthreads();  // L.dg / L.dgb and the scalars are rewritten
         }
-        __syncthreads();
-        const int nv = L.sc[1];
-        const int kvar = L.sc[2];
-        const bool mfma = nv <= kVMax && kvar <= a.kmax;
+        const int cend = c + len;
+        if (tid == c) my_t = L.wsum[4];
 
+        // 5. reference child (first of the segment) by the sparse pull
         T* refrow = stage + (b0 + c) * (long long)m;
-        if (!mfma) {
-            // sparse pull for every child of the segment
-            for (int rr = c; rr < cend; ++rr) {
-                if (rr > c) {
-                    __syncthreads();
-                    if (wid == 0) {
-                        canon_decode(m, lane, ua + (u64)(rr - c), L.om, L.am, L.dg, place_k);
-                        const u64 tr = child_index(m, lane, L.om, L.am, L.dg, place_w);
-                        if (lane == rr) my_t = tr;
+        const u64 href = sparse_child<T>(s, L, P, refrow, ovf);
+        if (tid == 0) L.rowh[c] = href;
+        if (len > 1) {
+            // 6. D rows, row hashes and child indices (thread r: row r)
+            for (int q = tid; q < kTile * kKMax / 16; q += blockDim.x) ((int4*)L.D)[q] = make_int4(0, 0, 0, 0);
+            const u64 t_c = L.wsum[4];
+            __syncthreads();
+            if (tid > c && tid < cend) {
+                const int row = tid;
+                uint32_t delta = (uint32_t)(row - c);  // < 256: 32-bit arithmetic throughout
+                u64 h = href, tr = t_c;
+                for (int i = nv - 1; i >= 0 && delta != 0; --i) {
+                    const int j = L.vlist[i];
+                    const uint32_t w = (uint32_t)kappa(L, j);
+                    const int e0 = L.dg[j];
+                    const uint32_t x = (uint32_t)e0 + delta;
+                    const int e1 = (int)(x % w);
+                    delta = x / w;
+                    if (e1 != e0) {
+                        const int k1 = L.kbase[i] + e1, k0 = L.kbase[i] + e0;
+                        L.D[row * kKMax + k1] = 1;
+                        L.D[row * kKMax + k0] = -1;
+                        h += s.hM[L.klist[k1]] - s.hM[L.klist[k0]];
+                        const int om = L.om[j];
+                        tr += (u64)(long long)(canon_digit(L.am[j], om, e1) - canon_digit(L.am[j], om, e0)) *
+                              L.placev[i];
                     }
-                    __syncthreads();
                 }
-                const u64 h = sparse_child<T>(s, L, P, stage + (b0 + rr) * (long long)m, ovf);
-                if (tid == 0) L.rowh[rr] = h;
+                L.rowh[row] = h;
+                my_t = tr;
             }
-        } else {
-            // 5. reference child (first of the segment) by the sparse pull
-            const u64 href = sparse_child<T>(s, L, P, refrow, ovf);
-            if (tid == 0) L.rowh[c] = href;
-            if (len > 1) {
-                // 6. D rows, row hashes and child indices
-                for (int q = tid; q < kTile * kKMax / 4; q += blockDim.x) ((int*)L.D)[q] = 0;
+            // quarters of 64 rows that hold rows c + 1 .. cend - 1
+            const int q0 = (c + 1) >> 6, q1 = (cend - 1) >> 6;
+            // instructions this segment issues: (m / NT) column tiles x 4 waves x
+            // quarters x 4 row blocks x NT / 64 column blocks
+            if (tid == 0) nmfma += (u64)((m + NT - 1) / NT) * 4 * (q1 - q0 + 1) * 4 * (NT / 64);
+            // 7. column tiles: stage M_V transposed, then every quarter's product
+            //    plus the reference row
+            for (int n0 = 0; n0 < m; n0 += NT) {
                 __syncthreads();
-                // (the reference row's index comes from its lane: read with every lane active)
-                const u64 t_c = wid == 0 ? __shfl(my_t, c) : 0;
-                if (wid == 0 && tid > c && tid < cend) {
-                    const int row = tid;
-                    uint32_t delta = (uint32_t)(row - c);  // < 64: 32-bit arithmetic throughout
-                    u64 h = href, tr = t_c;
-                    for (int i = nv - 1; i >= 0 && delta != 0; --i) {
-                        const int j = L.vlist[i];
-                        const uint32_t w = (uint32_t)kappa(L, j);
-                        const int e0 = L.dg[j];
-                        const uint32_t x = (uint32_t)e0 + delta;
-                        const int e1 = (int)(x % w);
-                        delta = x / w;
-                        if (e1 != e0) {
-                            const int k1 = L.kbase[i] + e1, k0 = L.kbase[i] + e0;
-                            L.D[row * kKMax + k1] = 1;
-                            L.D[row * kKMax + k0] = -1;
-                            h += s.hM[L.klist[k1]] - s.hM[L.klist[k0]];
-                            const int om = L.om[j];
-                            tr += (u64)(long long)(canon_digit(L.am[j], om, e1) - canon_digit(L.am[j], om, e0)) *
-                                  L.placev[i];
-                        }
-                    }
-                    L.rowh[row] = h;
-                    my_t = tr;
+                for (int q = tid; q < kKMax * NT; q += blockDim.x) {
+                    const int k = q / NT, n = q - k * NT;
+                    int8_t v = 0;
+                    if (k < kvar && n0 + n < m) v = s.M8[(long long)L.klist[k] * m + n0 + n];
+                    L.MT[n * kMTStride + k] = v;
                 }
-                const int kpad = (kvar + 63) & ~63;
-                // instructions this segment issues: (m / NT) column tiles x 4 waves x
-                // (kpad / 64) K steps x 4 row blocks x NT / 64 column blocks
-                if (tid == 0) nmfma += (u64)((m + NT - 1) / NT) * 4 * (kpad / 64) * 4 * (NT / 64);
-                // 7. column tiles: stage M_V transposed, multiply, add the reference row
-                for (int n0 = 0; n0 < m; n0 += NT) {
-                    __syncthreads();
-                    for (int q = tid; q < kpad * NT; q += blockDim.x) {
-                        const int k = q / NT, n = q - k * NT;
-                        int8_t v = 0;
-                        if (k < kvar && n0 + n < m) v = s.M8[(long long)L.klist[k] * m + n0 + n];
-                        L.MT[n * kMTStride + k] = v;
-                    }
-                    __syncthreads();
-                    constexpr int CB = NT / 64;  // 16-column blocks per wave
+                __syncthreads();
+                constexpr int CB = NT / 64;  // 16-column blocks per wave
+                const int colw = wid * (NT / 4);
+                v4i bf[CB];
+                long long refv[CB];
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    bf[cb] = *(const v4i*)&L.MT[(colw + 16 * cb + (lane & 15)) * kMTStride + 16 * (lane >> 4)];
+                    const int col = n0 + colw + 16 * cb + (lane & 15);
+                    refv[cb] = col < m ? (long long)refrow[col] : 0;
+                }
+                for (int qr = q0; qr <= q1; ++qr) {
                     v4i acc[4][CB];
 #pragma unroll
-                    for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-                        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = v4i{0, 0, 0, 0};
-                    const int colw = wid * (NT / 4);
-                    for (int ks = 0; ks < kpad; ks += 64) {
-                        v4i af[4], bf[CB];
-#pragma unroll
-                        for (int rb = 0; rb < 4; ++rb)
-                            af[rb] = *(const v4i*)&L.D[(16 * rb + (lane & 15)) * kKMax + ks + 16 * (lane >> 4)];
+                    for (int rb = 0; rb < 4; ++rb) {
+                        const v4i af = *(const v4i*)&L.D[(64 * qr + 16 * rb + (lane & 15)) * kKMax + 16 * (lane >> 4)];
 #pragma unroll
                         for (int cb = 0; cb < CB; ++cb)
-                            bf[cb] = *(const v4i*)&L.MT[(colw + 16 * cb + (lane & 15)) * kMTStride + ks + 16 * (lane >> 4)];
-#pragma unroll
-                        for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-                            for (int cb = 0; cb < CB; ++cb)
-                                acc[rb][cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[rb], bf[cb], acc[rb][cb], 0, 0, 0);
+                            acc[rb][cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[cb], v4i{0, 0, 0, 0}, 0, 0, 0);
                     }
 #pragma unroll
                     for (int cb = 0; cb < CB; ++cb) {
                         const int col = n0 + colw + 16 * cb + (lane & 15);
                         if (col >= m) continue;
-                        const long long refv = (long long)refrow[col];
 #pragma unroll
                         for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
                             for (int i = 0; i < 4; ++i) {
-                                const int row = 16 * rb + 4 * (lane >> 4) + i;
+                                const int row = 64 * qr + 16 * rb + 4 * (lane >> 4) + i;
                                 if (row <= c || row >= cend) continue;
-                                const long long v = refv + acc[rb][cb][i];
+                                const long long v = refv[cb] + acc[rb][cb][i];
                                 ovf |= (v < 0) | (v > s.count_max);
                                 stage[(b0 + row) * (long long)m + col] = (T)v;
                             }
