@@ -1548,22 +1548,65 @@ __global__ __launch_bounds__(256) void k_commit(int upr /* units per row */, Com
     }
     const long long first_local = a.level_count + (long long)p0;
     const int ncopy = (int)max(0LL, min((long long)nnew, a.limit - first_local));
-    const U* src = (const U*)a.stage + b0 * upr;
-    U* dst = (U*)a.arena + (a.level_base + first_local) * upr;
-    U* dst2 = a.row2 ? (U*)a.row2 + first_local * upr : nullptr;
+    const U* __restrict__ src = (const U*)a.stage + b0 * upr;
+    U* __restrict__ dst = (U*)a.arena + (a.level_base + first_local) * upr;
+    U* __restrict__ dst2 = a.row2 ? (U*)a.row2 + first_local * upr : nullptr;
     if (upr <= 256) {
         // thread t copies unit o of rows i0, i0 + per, ...: row and unit are
-        // fixed per thread, so the loop has no division
+        // fixed per thread, so the loop has no division; four rows' loads are
+        // in flight before their stores
         const int per = 256 / upr;
         const int i0 = threadIdx.x / upr, o = threadIdx.x - i0 * upr;
-        if (i0 < per)
-            for (int i = i0; i < ncopy; i += per) {
+        if (i0 < per) {
+            int i = i0;
+            for (; i + 3 * per < ncopy; i += 4 * per) {
+                U x[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) x[k] = src[(long long)srcb[i + k * per] * upr + o];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) dst[(long long)(i + k * per) * upr + o] = x[k];
+                if (dst2)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) dst2[(long long)(i + k * per) * upr + o] = x[k];
+            }
+            for (; i < ncopy; i += per) {
                 const U x = src[(long long)srcb[i] * upr + o];
                 dst[(long long)i * upr + o] = x;
                 if (dst2) dst2[(long long)i * upr + o] = x;
             }
+        }
     } else {
-        for (int i = 0; i < ncopy; ++i) {
+        // rows of more than 256 units: two rows at a time, two units of each
+        // per thread, their four loads in flight before the stores
+        int i = 0;
+        for (; i + 1 < ncopy; i += 2) {
+            const long long s0 = (long long)srcb[i] * upr, s1 = (long long)srcb[i + 1] * upr;
+            const long long d0 = (long long)i * upr, d1 = d0 + upr;
+            for (int o = threadIdx.x; o < upr; o += 512) {
+                const bool two = o + 256 < upr;
+                const U x0 = src[s0 + o], x1 = src[s1 + o];
+                U y0 = x0, y1 = x1;
+                if (two) {
+                    y0 = src[s0 + o + 256];
+                    y1 = src[s1 + o + 256];
+                }
+                dst[d0 + o] = x0;
+                dst[d1 + o] = x1;
+                if (two) {
+                    dst[d0 + o + 256] = y0;
+                    dst[d1 + o + 256] = y1;
+                }
+                if (dst2) {
+                    dst2[d0 + o] = x0;
+                    dst2[d1 + o] = x1;
+                    if (two) {
+                        dst2[d0 + o + 256] = y0;
+                        dst2[d1 + o + 256] = y1;
+                    }
+                }
+            }
+        }
+        for (; i < ncopy; ++i) {
             const long long s0 = (long long)srcb[i] * upr, d0 = (long long)i * upr;
             for (int o = threadIdx.x; o < upr; o += 256) {
                 const U x = src[s0 + o];
