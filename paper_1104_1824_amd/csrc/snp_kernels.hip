@@ -1460,6 +1460,33 @@ hipError_t launch_flags(const u64* table, const uint32_t* slot, long long B, Dev
     return hipGetLastError();
 }
 
+// Row copies of the commit stream through the caches: the staged row is read
+// once and the stored one is not read again before the next level.
+template <typename U>
+__device__ __forceinline__ U stream_load(const U* p) {
+    if constexpr (sizeof(U) == 16) {
+        typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+        const v4u v = __builtin_nontemporal_load((const v4u*)p);
+        U r;
+        __builtin_memcpy(&r, &v, 16);
+        return r;
+    } else {
+        return __builtin_nontemporal_load(p);
+    }
+}
+
+template <typename U>
+__device__ __forceinline__ void stream_store(U* p, const U& x) {
+    if constexpr (sizeof(U) == 16) {
+        typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+        v4u v;
+        __builtin_memcpy(&v, &x, 16);
+        __builtin_nontemporal_store(v, (v4u*)p);
+    } else {
+        __builtin_nontemporal_store(x, p);
+    }
+}
+
 // Commit the new children of a chunk in canonical order: rows below the
 // level's limit are copied to the row store and their entries re-pointed at
 // it; the rest (past a cap) become tombstones, i.e. are not recorded.  One
@@ -1562,9 +1589,9 @@ __global__ __launch_bounds__(256) void k_commit(int upr /* units per row */, Com
             for (; i + 3 * per < ncopy; i += 4 * per) {
                 U x[4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) x[k] = src[(long long)srcb[i + k * per] * upr + o];
+                for (int k = 0; k < 4; ++k) x[k] = stream_load(src + (long long)srcb[i + k * per] * upr + o);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) dst[(long long)(i + k * per) * upr + o] = x[k];
+                for (int k = 0; k < 4; ++k) stream_store(dst + (long long)(i + k * per) * upr + o, x[k]);
                 if (dst2)
 #pragma unroll
                     for (int k = 0; k < 4; ++k) dst2[(long long)(i + k * per) * upr + o] = x[k];
