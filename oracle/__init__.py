@@ -53,7 +53,7 @@ class _System(ctypes.Structure):
         ("rule_neuron", ctypes.c_void_p), ("rule_i", ctypes.c_void_p), ("rule_j", ctypes.c_void_p),
         ("rule_c", ctypes.c_void_p), ("rule_p", ctypes.c_void_p),
         ("syn_src", ctypes.c_void_p), ("syn_dst", ctypes.c_void_p),
-        ("count_max", ctypes.c_int64),
+        ("count_max", ctypes.c_int64), ("rule_d", ctypes.c_void_p),
     ]
 
 
@@ -96,6 +96,8 @@ def _load():
         lib.or_mix64.restype = ctypes.c_uint64
         lib.or_config_hash.argtypes = [P, ctypes.c_int32]
         lib.or_config_hash.restype = ctypes.c_uint64
+        lib.or_row_width.argtypes = [ctypes.POINTER(_System), ctypes.c_int32]
+        lib.or_row_width.restype = ctypes.c_int32
         _lib = lib
     return _lib
 
@@ -114,10 +116,13 @@ class _Sys:
     def __init__(self, sys):
         self.arrs = [_i32(sys.rule_neuron), _i32(sys.rule_i), _i32(sys.rule_j), _i32(sys.rule_c),
                      _i32(sys.rule_p), _i32(sys.syn_src), _i32(sys.syn_dst)]
+        rd = getattr(sys, "rule_d", None)
+        self.rule_d = None if rd is None else _i32(rd)
         a = self.arrs
         self.s = _System(int(sys.m), int(a[0].shape[0]), int(a[5].shape[0]),
                          a[0].ctypes.data, a[1].ctypes.data, a[2].ctypes.data, a[3].ctypes.data,
-                         a[4].ctypes.data, a[5].ctypes.data, a[6].ctypes.data, int(sys.count_max))
+                         a[4].ctypes.data, a[5].ctypes.data, a[6].ctypes.data, int(sys.count_max),
+                         None if self.rule_d is None else self.rule_d.ctypes.data)
         self.m, self.r = int(sys.m), int(a[0].shape[0])
 
 
@@ -209,12 +214,14 @@ def bfs(sys, c0=None, max_depth: int = -1, frontier_cap: int = 0, child_budget: 
     the first spiking vector of every configuration (a single branch).
     ``out_neuron`` > 0 (1-based) follows that neuron's spikes to the
     environment: rows carry two more entries (spikes sent, at most 2 counted;
-    steps from the first to the second), C0's being 0, 0 unless given."""
+    steps from the first to the second), C0's being 0, 0 unless given.  A
+    system with ``rule_d`` (delays) adds (wait, pend) per neuron owning a rule
+    with a delay (``row_width``); a C0 of m entries starts them all open."""
     S = _Sys(sys)
     c0 = _i64(sys.c0 if c0 is None else c0)
-    width = S.m + (2 if out_neuron else 0)
+    width = row_width(sys, out_neuron)
     if c0.shape[0] == S.m and width > S.m:
-        c0 = np.concatenate([c0, np.zeros(2, dtype=np.int64)])
+        c0 = np.concatenate([c0, np.zeros(width - S.m, dtype=np.int64)])
     if c0.shape[0] != width:
         raise ValueError(f"C0 has {c0.shape[0]} entries, rows have {width}")
     opts = _BfsOpts(int(max_depth), int(bool(stop_at_cap)), int(frontier_cap), int(child_budget),
@@ -241,6 +248,16 @@ def bfs(sys, c0=None, max_depth: int = -1, frontier_cap: int = 0, child_budget: 
         n, L = int(res.n_configs), int(res.n_levels)
         return BfsResult(rows[:n].copy(), lv[:L].copy(), parent[:n].copy(), tindex[:n].copy(),
                          en[:L].copy(), ha[:L].copy(), int(res.stop_reason))
+
+
+def row_width(sys, out_neuron: int = 0) -> int:
+    """Entries per row of a walk: the m counts, 2 for an output neuron's spike
+    train, 2 (wait, pend) per neuron that owns a rule with a delay."""
+    S = _Sys(sys)
+    w = int(_load().or_row_width(ctypes.byref(S.s), int(out_neuron)))
+    if w < 0:
+        raise OracleError(ERR_NOMEM, "row_width")
+    return w
 
 
 def generated_numbers(res: BfsResult, m: int) -> list:

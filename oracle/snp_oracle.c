@@ -1,6 +1,8 @@
 /*
  * Plain CPU oracle for the breadth-first expansion of the computation tree of a
- * spiking neural P system without delays.
+ * spiking neural P system without delays, and of the variant with delays that
+ * the paper sets aside (Section 2.1, opening) in the form of the work it cites
+ * for SN P systems (stated at delay_step below).
  *
  * TEST INFRASTRUCTURE ONLY.  The tests, the smoke check and the benchmark's
  * CPU-baseline leg call this file; the simulator library never links, includes
@@ -22,7 +24,9 @@
  *   - a child is C' = C + S.M (Equation next-config);
  *   - the tree is walked breadth first with one global list of produced
  *     configurations, and a configuration produced before is not expanded again
- *     (Algorithm 1 step IV, second stopping criterion).
+ *     (Algorithm 1 step IV, second stopping criterion);
+ *   - with delays, a step follows the definition of a delayed rule directly
+ *     (delay_step), not through M.
  *
  * Readings taken where the paper is silent are stated next to the code that
  * takes them.
@@ -50,6 +54,7 @@ typedef struct {
     const int32_t *rule_neuron, *rule_i, *rule_j, *rule_c, *rule_p;
     const int32_t *syn_src, *syn_dst;
     int64_t count_max; /* largest spike count the element type holds */
+    const int32_t *rule_d; /* nullable: [r] delay of every rule (NULL: a system without delays) */
 } or_system;
 
 /* ------------------------------------------------------------------------- */
@@ -173,10 +178,16 @@ typedef struct {
     int32_t *app;     /* applicable rules, neuron by neuron */
     int32_t *digit;   /* current position of every neuron's loop */
     int32_t any;      /* some neuron has an applicable rule */
+    int32_t waiting;  /* with delays: some neuron is closed or about to send (wait >= 1) */
     int32_t done;
 } or_enum;
 
-static int enum_open(or_enum *E, const or_system *sys, const or_rows *R, const int64_t *C) {
+/* wait (nullable, m entries): with delays, the steps neuron n still waits
+ * before it sends its pending spikes (0: open).  A waiting neuron applies no
+ * rule.  A configuration has children when some neuron has an applicable rule
+ * or some neuron waits; when only the latter holds, its one child fires
+ * nothing (the countdown still moves). */
+static int enum_open(or_enum *E, const or_system *sys, const or_rows *R, const int64_t *C, const int64_t *wait) {
     E->sys = sys;
     E->start = malloc(sizeof(int32_t) * ((size_t)sys->m + 1));
     E->app = malloc(sizeof(int32_t) * (size_t)(sys->r > 0 ? sys->r : 1));
@@ -184,13 +195,18 @@ static int enum_open(or_enum *E, const or_system *sys, const or_rows *R, const i
     if (!E->start || !E->app || !E->digit) return OR_ERR_NOMEM;
     int32_t q = 0;
     E->any = 0;
+    E->waiting = 0;
     for (int32_t n = 0; n < sys->m; ++n) {
         E->start[n] = q;
+        if (wait && wait[n] >= 1) {
+            E->waiting = 1;
+            continue;
+        }
         q += applicable_rules(sys, R, n, C[n], E->app + q);
         if (q > E->start[n]) E->any = 1;
     }
     E->start[sys->m] = q;
-    E->done = !E->any; /* no applicable rule anywhere: halting, no child */
+    E->done = !E->any && !E->waiting; /* no applicable rule and nothing pending: halting, no child */
     return OR_OK;
 }
 
@@ -234,11 +250,12 @@ static int next_config(const or_system *sys, const or_rows *R, const int64_t *C,
  * S_out (nullable) receives the spiking vectors as 0/1 bytes, r per child. */
 int or_children(const or_system *sys, const int64_t *C, int64_t max_out, int64_t *out_rows,
                 uint8_t *S_out, int64_t *psi) {
+    if (sys->rule_d) return OR_ERR_INVALID; /* rows with delays carry more entries: or_bfs only */
     or_rows R = {0};
     or_enum E = {0};
     int st = rows_build(sys, &R);
     if (st) return st;
-    st = enum_open(&E, sys, &R, C);
+    st = enum_open(&E, sys, &R, C, NULL);
     uint8_t *S = malloc((size_t)(sys->r > 0 ? sys->r : 1));
     int64_t *tmp = malloc(sizeof(int64_t) * (size_t)sys->m);
     if (st || !S || !tmp) { rows_free(&R); enum_close(&E); free(S); free(tmp); return OR_ERR_NOMEM; }
@@ -262,11 +279,12 @@ int or_children(const or_system *sys, const int64_t *C, int64_t max_out, int64_t
 /* The child of C with index t in Algorithm 2 order (the odometer advanced t
  * times).  Returns OR_ERR_INVALID when C has fewer than t + 1 children. */
 int or_child_at(const or_system *sys, const int64_t *C, int64_t t, int64_t *out_row) {
+    if (sys->rule_d) return OR_ERR_INVALID; /* rows with delays carry more entries: or_bfs only */
     or_rows R = {0};
     or_enum E = {0};
     int st = rows_build(sys, &R);
     if (st) return st;
-    st = enum_open(&E, sys, &R, C);
+    st = enum_open(&E, sys, &R, C, NULL);
     uint8_t *S = malloc((size_t)(sys->r > 0 ? sys->r : 1));
     if (st || !S) { rows_free(&R); enum_close(&E); free(S); return OR_ERR_NOMEM; }
     for (int64_t q = 0; q < t && !E.done; ++q) enum_next(&E);
@@ -360,17 +378,14 @@ typedef struct {
  * environment; Section 2.1: the number a computation generates is the time
  * between the first two spikes the output neuron sends out).  A row's two
  * extra entries (env, el) follow the train: q spikes leave at a step when the
- * output neuron fires a rule producing q (0 when it fires nothing), and
+ * output neuron sends q (without delays: when it fires a rule producing q; 0
+ * when it fires nothing), and
  *   env 0: env = min(2, q), el = 0;
  *   env 1: env = min(2, 1 + q), el = el + 1;
  *   env 2: unchanged (el is the number generated).
  * A row with env = 2 is recorded but not expanded: what follows cannot change
  * the number it generated. */
-static void out_track(const or_system *sys, const uint8_t *S, int32_t out, const int64_t *C, int64_t *child) {
-    const int32_t m = sys->m;
-    int64_t q = 0;
-    for (int32_t k = 0; k < sys->r; ++k)
-        if (S[k] && sys->rule_neuron[k] == out - 1) q = sys->rule_p[k];
+static void out_track(int64_t q, int32_t m, const int64_t *C, int64_t *child) {
     const int64_t env = C[m], el = C[m + 1];
     if (env == 0) {
         child[m] = q < 2 ? q : 2;
@@ -384,15 +399,112 @@ static void out_track(const or_system *sys, const uint8_t *S, int32_t out, const
     }
 }
 
+/* ------------------------------------------------------------------------- */
+/* Delays.  The paper treats systems without delays only and points to the  */
+/* work it cites for the variant; this is that variant.  A rule              */
+/* E/a^c -> a^p; d with d >= 1 used at step s takes its c spikes at once;    */
+/* the neuron is then closed at steps s .. s+d-1 (it applies no rule, and    */
+/* spikes sent to it at those steps are lost), at step s+d it sends its p    */
+/* spikes along its synapses and is open again (it keeps the spikes it gets   */
+/* at that step, and applies no rule at it), and from step s+d+1 on it        */
+/* applies rules as before.  d = 0 is the step without delays.               */
+/*                                                                           */
+/* Readings: a neuron sending its delayed spikes at step s+d applies no rule  */
+/* at that step (its rule use spans steps s .. s+d, as a rule without delay   */
+/* spans its one step); the output neuron's spikes reach the environment at   */
+/* the step they are sent, whether the neuron is open or not.                */
+/*                                                                           */
+/* A configuration holds, besides the spike counts, the state of every       */
+/* neuron that owns a rule with d >= 1 ("delayed neuron"): wait, the steps    */
+/* until it sends (0: open), and pend, the spikes it will send.  A row is     */
+/* the m counts, then the output neuron's two entries (when followed), then   */
+/* (wait, pend) of every delayed neuron in neuron order.                     */
+/* ------------------------------------------------------------------------- */
+static int32_t rule_delay(const or_system *sys, int32_t k) { return sys->rule_d ? sys->rule_d[k] : 0; }
+
+/* col[n] = column of delayed neuron n's wait entry (pend follows it), -1 for
+ * the other neurons; the columns start at `first`.  Returns the row width. */
+static int32_t delay_columns(const or_system *sys, int32_t first, int32_t *col) {
+    int32_t w = first;
+    for (int32_t n = 0; n < sys->m; ++n) {
+        int delayed = 0;
+        for (int32_t k = 0; k < sys->r; ++k)
+            if (sys->rule_neuron[k] == n && rule_delay(sys, k) >= 1) delayed = 1;
+        col[n] = delayed ? w : -1;
+        if (delayed) w += 2;
+    }
+    return w;
+}
+
+/* Entries per row of a walk: m counts, 2 with an output neuron, 2 per delayed neuron. */
+int32_t or_row_width(const or_system *sys, int32_t out_neuron) {
+    int32_t *col = malloc(sizeof(int32_t) * (size_t)(sys->m > 0 ? sys->m : 1));
+    if (!col) return -1;
+    int32_t w = delay_columns(sys, sys->m + (out_neuron > 0 ? 2 : 0), col);
+    free(col);
+    return w;
+}
+
+/* One step with delays from row C under the spiking vector S (0/1 over the
+ * rules; waiting neurons fire nothing), into `child` (w entries; entries
+ * other than the counts and the delay states are copied from C).  emit
+ * receives the spikes every neuron sends at this step.  Returns
+ * OR_ERR_OVERFLOW when a count leaves [0, count_max]. */
+static int delay_step(const or_system *sys, const int32_t *col, int32_t w, const int64_t *C, const uint8_t *S,
+                      int64_t *emit, int32_t *fired, int64_t *child) {
+    const int32_t m = sys->m;
+    for (int32_t n = 0; n < m; ++n) fired[n] = -1;
+    for (int32_t k = 0; k < sys->r; ++k)
+        if (S[k]) fired[sys->rule_neuron[k]] = k;
+    memcpy(child, C, sizeof(int64_t) * (size_t)w);
+    /* spikes sent at this step: a rule without delay fired now, or the pending
+     * spikes of a neuron whose wait ends now */
+    for (int32_t n = 0; n < m; ++n) {
+        const int32_t k = fired[n];
+        const int64_t wait = col[n] >= 0 ? C[col[n]] : 0;
+        if (k >= 0 && rule_delay(sys, k) == 0) emit[n] = sys->rule_p[k];
+        else if (wait == 1) emit[n] = C[col[n] + 1];
+        else emit[n] = 0;
+    }
+    /* consumption, then delivery to the neurons open at this step */
+    for (int32_t n = 0; n < m; ++n)
+        if (fired[n] >= 0) child[n] -= sys->rule_c[fired[n]];
+    for (int32_t e = 0; e < sys->n_syn; ++e) {
+        const int32_t src = sys->syn_src[e], dst = sys->syn_dst[e];
+        const int32_t k = fired[dst];
+        const int64_t wait = col[dst] >= 0 ? C[col[dst]] : 0;
+        const int closed = (k >= 0 && rule_delay(sys, k) >= 1) || wait >= 2;
+        if (!closed) child[dst] += emit[src];
+    }
+    /* the delayed neurons' new state */
+    for (int32_t n = 0; n < m; ++n) {
+        if (col[n] < 0) continue;
+        const int32_t k = fired[n];
+        const int64_t wait = C[col[n]], pend = C[col[n] + 1];
+        if (k >= 0 && rule_delay(sys, k) >= 1) {
+            child[col[n]] = rule_delay(sys, k);
+            child[col[n] + 1] = sys->rule_p[k];
+        } else {
+            child[col[n]] = wait >= 1 ? wait - 1 : 0;
+            child[col[n] + 1] = wait >= 2 ? pend : 0;
+        }
+    }
+    for (int32_t n = 0; n < m; ++n)
+        if (child[n] < 0 || child[n] > sys->count_max) return OR_ERR_OVERFLOW;
+    return OR_OK;
+}
+
 typedef struct {
     /* caller-owned outputs */
-    int64_t *rows;        /* rows_cap rows of m entries (m + 2 with an output neuron) */
+    int64_t *rows;        /* rows_cap rows of or_row_width entries (m, + 2 with an output neuron,
+                             + 2 per delayed neuron) */
     int64_t rows_cap;
     int64_t *parent;      /* nullable, rows_cap: global index of the parent (-1 for C0) */
     int64_t *tindex;      /* nullable, rows_cap: index of the spiking vector among the parent's */
     int64_t *level_sizes; /* max_levels */
     int64_t *enumerated;  /* nullable, max_levels: children considered when expanding level k */
-    int64_t *halting;     /* nullable, max_levels: parents of level k with no applicable rule */
+    int64_t *halting;     /* nullable, max_levels: parents of level k with no child (no applicable
+                             rule, and with delays no neuron waiting) */
     int32_t max_levels;
     /* results */
     int32_t n_levels;
@@ -405,18 +517,26 @@ int or_bfs(const or_system *sys, const int64_t *c0, const or_bfs_opts *opt, or_b
     const int32_t m = sys->m;
     const int32_t out = opt->out_neuron;
     if (out < 0 || out > m) return OR_ERR_INVALID;
-    const int32_t w = m + (out > 0 ? 2 : 0); /* entries per row */
+    int32_t *col = malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    if (!col) return OR_ERR_NOMEM;
+    const int32_t w = delay_columns(sys, m + (out > 0 ? 2 : 0), col); /* entries per row */
     int st = OR_OK;
     for (int32_t n = 0; n < w; ++n)
-        if (c0[n] < 0 || c0[n] > sys->count_max) return OR_ERR_OVERFLOW;
-    if (res->rows_cap < 1 || res->max_levels < 1) return OR_ERR_CAPACITY;
+        if (c0[n] < 0 || c0[n] > sys->count_max) { free(col); return OR_ERR_OVERFLOW; }
+    if (res->rows_cap < 1 || res->max_levels < 1) { free(col); return OR_ERR_CAPACITY; }
     or_rows R = {0};
-    if ((st = rows_build(sys, &R))) return st;
+    if ((st = rows_build(sys, &R))) { free(col); return st; }
     uint8_t *S = malloc((size_t)(sys->r > 0 ? sys->r : 1));
     int64_t *child = malloc(sizeof(int64_t) * (size_t)w);
+    int64_t *wait = calloc((size_t)(m > 0 ? m : 1), sizeof(int64_t));
+    int64_t *emit = malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+    int32_t *fired = malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
     const int64_t *rows_view = res->rows;
     or_set H;
-    if (!S || !child || set_init(&H, w, &rows_view)) { rows_free(&R); free(S); free(child); return OR_ERR_NOMEM; }
+    if (!S || !child || !wait || !emit || !fired || set_init(&H, w, &rows_view)) {
+        rows_free(&R); free(S); free(child); free(wait); free(emit); free(fired); free(col);
+        return OR_ERR_NOMEM;
+    }
 
     /* level 0 = { C0 } */
     memcpy(res->rows, c0, sizeof(int64_t) * (size_t)w);
@@ -441,9 +561,10 @@ int or_bfs(const or_system *sys, const int64_t *c0, const or_bfs_opts *opt, or_b
         int all_halting = 1, budget_hit = 0, cap_hit = 0;
         for (int64_t par = lvl_begin; par < lvl_end && !cap_hit && !budget_hit && st == OR_OK; ++par) {
             const int64_t *C = res->rows + par * w;
+            for (int32_t n = 0; n < m; ++n) wait[n] = col[n] >= 0 ? C[col[n]] : 0;
             or_enum E;
-            if (enum_open(&E, sys, &R, C)) { enum_close(&E); st = OR_ERR_NOMEM; break; }
-            if (!E.any) { enum_close(&E); continue; }
+            if (enum_open(&E, sys, &R, C, wait)) { enum_close(&E); st = OR_ERR_NOMEM; break; }
+            if (E.done) { enum_close(&E); continue; } /* halting: no child */
             all_halting = 0;
             int expand = 1;
             if (opt->expand_max_count >= 0)
@@ -454,9 +575,17 @@ int or_bfs(const or_system *sys, const int64_t *c0, const or_bfs_opts *opt, or_b
             while (expand && !E.done) {
                 if (opt->child_budget > 0 && enumerated >= opt->child_budget) { budget_hit = 1; break; }
                 enum_spiking_vector(&E, S);
-                if ((st = next_config(sys, &R, C, S, child))) break;
+                int64_t q = 0; /* spikes the output neuron sends at this step */
+                if (sys->rule_d) {
+                    if ((st = delay_step(sys, col, w, C, S, emit, fired, child))) break;
+                    if (out > 0) q = emit[out - 1];
+                } else {
+                    if ((st = next_config(sys, &R, C, S, child))) break;
+                    for (int32_t k = 0; k < sys->r; ++k)
+                        if (S[k] && sys->rule_neuron[k] == out - 1) q = sys->rule_p[k];
+                }
                 if (out > 0) {
-                    out_track(sys, S, out, C, child);
+                    out_track(q, m, C, child);
                     if (child[m + 1] > sys->count_max) { st = OR_ERR_OVERFLOW; break; }
                 }
                 ++enumerated;
@@ -484,9 +613,11 @@ int or_bfs(const or_system *sys, const int64_t *c0, const or_bfs_opts *opt, or_b
          * level enumerated (all parents when the level was not cut short) */
         const int64_t p_end = (cap_hit || budget_hit) ? last_par + 1 : lvl_end;
         for (int64_t par = lvl_begin; par < p_end; ++par) {
+            const int64_t *C = res->rows + par * w;
+            for (int32_t n = 0; n < m; ++n) wait[n] = col[n] >= 0 ? C[col[n]] : 0;
             or_enum E;
-            if (enum_open(&E, sys, &R, res->rows + par * w)) { enum_close(&E); st = OR_ERR_NOMEM; break; }
-            if (!E.any) halting++;
+            if (enum_open(&E, sys, &R, C, wait)) { enum_close(&E); st = OR_ERR_NOMEM; break; }
+            if (E.done) halting++;
             enum_close(&E);
         }
         if (st) break;
@@ -506,7 +637,7 @@ int or_bfs(const or_system *sys, const int64_t *c0, const or_bfs_opts *opt, or_b
     res->n_levels = levels;
     res->n_configs = total;
     res->stop_reason = stop;
-    free(H.slot); rows_free(&R); free(S); free(child);
+    free(H.slot); rows_free(&R); free(S); free(child); free(wait); free(emit); free(fired); free(col);
     return st;
 }
 
@@ -548,6 +679,7 @@ static uint64_t step_digest(int64_t k, const int64_t *C, int32_t m) {
 int or_deterministic(const or_system *sys, const int64_t *c0, int32_t steps, int64_t *final_c,
                      int32_t *halt_step, int32_t *first_repeat, int32_t *steps_done, uint64_t *digest) {
     const int32_t m = sys->m;
+    if (sys->rule_d) return OR_ERR_INVALID; /* the trajectory checksum is defined without delays */
     for (int32_t n = 0; n < m; ++n)
         if (c0[n] < 0 || c0[n] > sys->count_max) return OR_ERR_OVERFLOW;
     or_rows R = {0};

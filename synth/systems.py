@@ -86,6 +86,7 @@ class System:
     count_type: str = "i32"
     name: str = ""
     meta: dict = field(default_factory=dict)
+    rule_d: Optional[np.ndarray] = None  # delay of every rule (None: a system without delays)
 
     @property
     def r(self) -> int:
@@ -117,9 +118,11 @@ def _arr(values) -> np.ndarray:
 
 
 def make_system(m, rules, syn, c0, count_type="i32", name="", meta=None) -> System:
-    """Build a System from python lists: rules = [(neuron, i, j, c, p)], syn = [(s, d)]."""
+    """Build a System from python lists: rules = [(neuron, i, j, c, p)] or
+    [(neuron, i, j, c, p, d)] with a delay d, syn = [(s, d)]."""
     rules = list(rules)
     syn = list(syn)
+    delays = any(len(x) > 5 for x in rules)
     return System(
         m=int(m),
         rule_neuron=_arr([x[0] for x in rules]),
@@ -133,6 +136,23 @@ def make_system(m, rules, syn, c0, count_type="i32", name="", meta=None) -> Syst
         count_type=count_type,
         name=name,
         meta=dict(meta or {}),
+        rule_d=_arr([x[5] if len(x) > 5 else 0 for x in rules]) if delays else None,
+    )
+
+
+def with_delays(system: System, seed: int, d_max: int = 2, num: int = 1, den: int = 2) -> System:
+    """Copy of ``system`` whose rules carry delays: for every rule in order, a
+    draw below ``den`` that is below ``num`` gives it a delay uniform in
+    [1, d_max], else 0 (stream seeded with ``6 << 32 | seed``)."""
+    rng = SplitMix64(_seed(6, seed))
+    d = []
+    for _ in range(system.r):
+        d.append(rng.uniform(1, d_max) if rng.below(den) < num else 0)
+    return System(
+        m=system.m, rule_neuron=system.rule_neuron, rule_i=system.rule_i, rule_j=system.rule_j,
+        rule_c=system.rule_c, rule_p=system.rule_p, syn_src=system.syn_src, syn_dst=system.syn_dst,
+        c0=system.c0, count_type=system.count_type, name=f"{system.name}_d{seed}",
+        meta=dict(system.meta, delay_seed=seed, d_max=d_max), rule_d=_arr(d),
     )
 
 
