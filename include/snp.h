@@ -105,6 +105,21 @@ typedef struct {
     const int32_t *M;           /* optional [r*m] row-major M_Pi; when non-NULL it must equal
                                    the Definition 2 matrix of the rules and synapses above */
     int32_t count_type;         /* snp_count_t */
+    const int32_t *rule_d;      /* optional [r] delays, 0 <= d <= 32767 (NULL: every d = 0).  The paper
+                                   treats systems without delays and leaves the variant to the work it
+                                   cites (Section 2.1, opening); here a rule E/a^c -> a^p; d with d >= 1
+                                   used at step s takes its c spikes at once, its neuron is closed at
+                                   steps s .. s+d-1 (it fires nothing, and spikes sent to it then are
+                                   lost), and at step s+d it sends its p spikes along its synapses,
+                                   keeps the spikes it receives at that step and fires nothing; it
+                                   fires again from step s+d+1.  Every neuron owning a rule with d >= 1
+                                   adds two entries to a row, after the counts and the output neuron's
+                                   spike train, in neuron order: wait (steps until it sends; 0: open)
+                                   and pend (the spikes it will send).  A configuration where no rule
+                                   applies but some neuron waits has one child (it fires nothing).
+                                   With delays a row holds at most 3640 entries, the sparse form runs
+                                   every pass (SNP_PATH_INT8 falls back, int8_fallback = 1), and the
+                                   batched mode is refused. */
 } snp_desc;
 
 typedef struct {

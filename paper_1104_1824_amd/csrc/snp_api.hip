@@ -57,6 +57,8 @@ namespace {
 
 constexpr int kMaxRulesPerNeuron = 16;  // applicable-rule masks are 16-bit (plus 16 bits of twin marks)
 constexpr int kMaxNeurons = 4608;       // per-wave LDS state of the expansion kernel (14 B per neuron) <= 64 KiB
+constexpr int kMaxDelayWidth = 3640;    // with delays, 18 B per row entry <= 64 KiB
+constexpr int kMaxDelay = 32767;        // a rule's delay (15 bits of the packed fired-rule word)
 constexpr long long kInf = LLONG_MAX / 4;
 
 u64 host_mix64(u64 z) {  // SplitMix64 output finaliser
@@ -150,6 +152,8 @@ snp_status validate(const snp_desc* d) {
             return fail(SNP_ERR_INVALID, "rule %d: c and p must be <= 65535", k);
         if (++per[n] > kMaxRulesPerNeuron)
             return fail(SNP_ERR_INVALID, "neuron %d has more than %d rules", n, kMaxRulesPerNeuron);
+        if (d->rule_d && (d->rule_d[k] < 0 || d->rule_d[k] > kMaxDelay))
+            return fail(SNP_ERR_INVALID, "rule %d: delay must be in [0, %d]", k, kMaxDelay);
     }
     std::vector<std::pair<int, int>> edges;
     edges.reserve(d->n_syn);
@@ -616,17 +620,41 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
             }
     }
 
-    // An output neuron adds two entries to every row (its spike train, read
-    // by the kernels): the device tables see two more neurons, without rules
-    // or synapses.
+    // An output neuron adds two entries to every row (its spike train), and
+    // with delays every neuron owning a rule with a delay adds two more (its
+    // wait and pending spikes), all read and written by the kernels: the
+    // device tables see that many more neurons, without rules or synapses.
     if (opt.out_neuron < 0 || opt.out_neuron > d->m)
         return fail(SNP_ERR_INVALID, "out_neuron %d outside [0, m = %d]", opt.out_neuron, d->m);
+    const int mcount = d->m;
+    const int dfirst = mcount + (opt.out_neuron > 0 ? 2 : 0);
+    std::vector<int> dlink;  // neuron -> its wait column (-1: none); state column -> its neuron
+    int width = dfirst;
+    if (d->rule_d) {
+        std::vector<char> delayed(mcount, 0);
+        for (int k = 0; k < d->r; ++k)
+            if (d->rule_d[k] > 0) delayed[d->rule_neuron[k]] = 1;
+        dlink.assign(mcount, -1);
+        for (int n = 0; n < mcount; ++n)
+            if (delayed[n]) {
+                dlink[n] = width;
+                width += 2;
+            }
+        if (width == dfirst) dlink.clear();  // every delay 0: the system without delays
+        else {
+            dlink.resize(width, -1);
+            for (int n = 0; n < mcount; ++n)
+                if (dlink[n] >= 0) dlink[dlink[n]] = dlink[dlink[n] + 1] = n;
+        }
+    }
+    const bool delays = !dlink.empty();
+    if (width > (delays ? kMaxDelayWidth : kMaxNeurons))
+        return fail(SNP_ERR_INVALID, "row width %d (counts, output spike train, delay states) above %d", width,
+                    delays ? kMaxDelayWidth : kMaxNeurons);
     snp_desc wide;
-    if (opt.out_neuron > 0) {
-        if (d->m + 2 > kMaxNeurons)
-            return fail(SNP_ERR_INVALID, "m + 2 (rows with the output neuron's spike train) above %d", kMaxNeurons);
+    if (width > mcount) {
         wide = *d;
-        wide.m = d->m + 2;
+        wide.m = width;
         wide.M = nullptr;
         d = &wide;
     }
@@ -634,7 +662,9 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     snp_system* S = new snp_system();
     S->m = d->m;
     S->r = d->r;
-    S->track = opt.out_neuron > 0 ? d->m - 2 : -1;
+    S->mcount = mcount;
+    S->delays = delays;
+    S->track = opt.out_neuron > 0 ? mcount : -1;
     S->elem_bytes = d->count_type == SNP_COUNT_U16 ? 2 : 4;
     S->count_max = d->count_type == SNP_COUNT_U16 ? 65535 : INT_MAX;
     S->opt = opt;
@@ -665,7 +695,10 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     for (int k = 0; k < d->r; ++k) nrule_ptr[d->rule_neuron[k] + 1]++;
     for (int n = 0; n < d->m; ++n) nrule_ptr[n + 1] += nrule_ptr[n];
     std::vector<int4> rules(d->r);
-    for (int k = 0; k < d->r; ++k) rules[k] = make_int4(d->rule_i[k], d->rule_j[k], d->rule_c[k], d->rule_p[k]);
+    // (with delays the last entry packs p and the delay d: p | d << 16)
+    for (int k = 0; k < d->r; ++k)
+        rules[k] = make_int4(d->rule_i[k], d->rule_j[k], d->rule_c[k],
+                             d->rule_p[k] | (delays ? d->rule_d[k] << 16 : 0));
     // in-synapses of every neuron (column view of the synapse part of M)
     // (one padding entry, so kernels may read in_src[0] of a system without synapses)
     std::vector<int> in_ptr(d->m + 1, 0), in_src(std::max(1, d->n_syn), 0), fill(d->m, 0);
@@ -697,6 +730,10 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     LOADCHK(up(S->d_rules, rules.data(), sizeof(int4) * d->r));
     LOADCHK(up(S->d_in_ptr, in_ptr.data(), sizeof(int) * (d->m + 1)));
     LOADCHK(up(S->d_in_src, in_src.data(), sizeof(int) * in_src.size()));
+    if (delays) {
+        LOADCHK(dmalloc(&S->d_dlink, sizeof(int) * dlink.size()));
+        LOADCHK(up(S->d_dlink, dlink.data(), sizeof(int) * dlink.size()));
+    }
     // hash weights R[n] and the hash H of every row of M_Pi (Definition 2 rows,
     // entries sign-extended, arithmetic mod 2^64)
     std::vector<u64> R(d->m), hM(d->r);
@@ -716,7 +753,7 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
     LOADCHK(up(S->d_R, R.data(), sizeof(u64) * d->m));
     LOADCHK(up(S->d_hM, hM.data(), sizeof(u64) * d->r));
     // int8 copy of M_Pi for the matrix-core form (every |entry| <= 127, <= 16 rules per neuron)
-    S->int8_ready = int8_ok && S->track < 0 && max_rules <= 16 && opt.path != SNP_PATH_SPARSE &&
+    S->int8_ready = int8_ok && S->track < 0 && !delays && max_rules <= 16 && opt.path != SNP_PATH_SPARSE &&
                     snp::int8_lds(d->m, 64) <= 64 * 1024 && (size_t)d->r * d->m <= ((size_t)1 << 33);
     if (S->int8_ready) {
         std::vector<int8_t> M8((size_t)d->r * d->m, 0);
@@ -741,11 +778,11 @@ snp_status snp_load(const snp_desc* d, const snp_options* o, snp_system** out) {
             for (int e = 0; e < in_ptr[n + 1] - in_ptr[n]; ++e) in_lane[e * 64 + n] = in_src[in_ptr[n] + e];
     LOADCHK(dmalloc(&S->d_in_lane, sizeof(int) * in_lane.size()));
     LOADCHK(up(S->d_in_lane, in_lane.data(), sizeof(int) * in_lane.size()));
-    S->lane_form = S->track < 0 && d->m <= 64 && max_in <= 16 && (size_t)d->r * 24 <= 24 * 1024;
+    S->lane_form = S->track < 0 && !delays && d->m <= 64 && max_in <= 16 && (size_t)d->r * 24 <= 24 * 1024;
     S->dsys = snp::DevSystem{d->m, d->r, S->d_nrule_ptr, S->d_rules, S->d_in_ptr, S->d_in_src, d->n_syn, S->d_M8,
                              S->count_max, S->d_R, S->d_hM, max_in, S->d_in_lane,
                              opt.deterministic ? 1ULL : snp::kPsiSat, S->track,
-                             opt.out_neuron > 0 ? opt.out_neuron - 1 : -1};
+                             opt.out_neuron > 0 ? opt.out_neuron - 1 : -1, S->d_dlink, mcount, dfirst};
 
     S->slots = next_pow2((u64)std::max<long long>(1024, 2 * (S->max_rows + 2 * S->chunk_max)));
     LOADCHK(dmalloc(&S->d_table, sizeof(u64) * S->slots));
@@ -929,9 +966,12 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
         if (d->m > 4 * snp::batch_max_threads())
             return fail(SNP_ERR_INVALID, "system %d: m above %d is not supported in batched mode", k,
                         4 * snp::batch_max_threads());
-        for (int q = 0; q < d->r; ++q)
+        for (int q = 0; q < d->r; ++q) {
             if (d->rule_i[q] > 255 || d->rule_j[q] > 255 || d->rule_c[q] > 255 || d->rule_p[q] > 255)
                 return fail(SNP_ERR_INVALID, "system %d rule %d: batched mode needs i, j, c, p <= 255", k, q);
+            if (d->rule_d && d->rule_d[q] != 0)
+                return fail(SNP_ERR_INVALID, "system %d rule %d: the batched mode has no delays", k, q);
+        }
         snp::BatchSys& B = sys[k];
         B.m = d->m;
         B.r = d->r;
@@ -1178,6 +1218,8 @@ snp_status snp_run_batch(snp_system* const* systems, int32_t n, const void* cons
         if (!systems[k]) return fail(SNP_ERR_INVALID, "system %d is NULL", k);
         if (systems[k]->track >= 0)
             return fail(SNP_ERR_INVALID, "system %d follows an output neuron: the batched mode does not", k);
+        if (systems[k]->delays)
+            return fail(SNP_ERR_INVALID, "system %d has rules with delays: the batched mode has none", k);
         if (!c0_dev[k] || !final_dev[k]) return fail(SNP_ERR_INVALID, "system %d: c0 or final is NULL", k);
         if (systems[k]->count_type != systems[0]->count_type)
             return fail(SNP_ERR_INVALID, "system %d: all systems must share one count type", k);

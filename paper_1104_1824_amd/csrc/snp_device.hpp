@@ -222,6 +222,17 @@ __device__ __forceinline__ uint32_t neuron_applicable(int x, int r0, int r1, con
     return mask | (w >= 2 ? canonical_mask(rules, r0, mask) << 16 : 0xFFFF0000u);
 }
 
+// With delays: the steps neuron j (< mcount) still waits before it sends its
+// delayed spikes (0: open).  dlink[j] is the column of its wait entry in a row
+// (-1: the neuron owns no rule with a delay); dlink null: a system without
+// delays.
+template <typename T>
+__device__ __forceinline__ int neuron_wait(const T* row, const int* dlink, int mcount, int j) {
+    if (!dlink || j >= mcount) return 0;
+    const int c = dlink[j];
+    return c >= 0 ? (int)row[c] : 0;
+}
+
 // Mixed-radix decode of child index t (Algorithm 2 II-3 order: the last neuron
 // is the least significant digit; a neuron with omega <= 1 has one value).
 // Lane L owns the contiguous neurons [L*Q, L*Q + Q); the place value of its

@@ -22,6 +22,8 @@ snp_status set_error(snp_status st, const char* fmt, ...);
 struct snp_system {
     int m = 0, r = 0, elem_bytes = 4;
     int track = -1;  // column of the output neuron's spike train in a row (-1: none); m counts it
+    int mcount = 0;  // neurons (spike-count columns); m is the row width
+    bool delays = false;  // some rule has a delay: rows carry (wait, pend) per delayed neuron
     // the host description, kept for snp_run_batch (which packs the handles'
     // systems into one batched launch), and an id no other handle ever gets
     std::vector<int32_t> h_rn, h_ri, h_rj, h_rc, h_rp, h_ss, h_sd;
@@ -38,6 +40,7 @@ struct snp_system {
     int* d_in_ptr = nullptr;
     int* d_in_src = nullptr;
     int* d_in_lane = nullptr;
+    int* d_dlink = nullptr;  // with delays: neuron -> wait column, state column -> neuron
     int8_t* d_M8 = nullptr;  // r x m int8 copy of M_Pi when every entry fits (int8 path)
     u64* d_R = nullptr;      // hash weights
     u64* d_hM = nullptr;     // H of every row of M_Pi
@@ -95,7 +98,7 @@ struct snp_system {
     ~snp_system() {
         void* ptrs[] = {d_nrule_ptr, d_rules, d_in_ptr, d_in_src, d_in_lane, d_M8, d_R, d_hM, d_table, d_row_slot, d_psi, d_off,
                         d_sc_sums, d_sc_pre, d_stage, d_hash, d_cpar, d_ct, d_slot, d_flag, d_pos,
-                        d_fsums, d_fpre, d_ring, d_store, d_cand, d_hflag, d_T, d_psif, d_Tend};
+                        d_fsums, d_fpre, d_ring, d_store, d_cand, d_hflag, d_T, d_psif, d_Tend, d_dlink};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         if (h_ctr) (void)hipHostFree(h_ctr);

@@ -52,7 +52,7 @@ struct DevCounters {
 struct DevSystem {
     int m, r;
     const int* nrule_ptr;  // [m+1] rules of neuron n: nrule_ptr[n] .. nrule_ptr[n+1]
-    const int4* rules;     // [r] (i, j, c, p)
+    const int4* rules;     // [r] (i, j, c, p) (with delays, p | (d << 16) in the last)
     const int* in_ptr;     // [m+1] in-synapses of neuron d: in_src[in_ptr[d] .. in_ptr[d+1])
     const int* in_src;     // sources of the in-synapses
     int nnz_in;            // number of synapses
@@ -70,6 +70,16 @@ struct DevSystem {
                            // the steps from the first to the second at track + 1; the m
                            // above counts these two columns (neurons without rules or synapses)
     int out;               // the output neuron (with track >= 0)
+    // Delays.  The first mcount columns of a row are spike counts; with delays
+    // every neuron owning a rule with a delay has two more columns from dfirst
+    // on: wait (steps until it sends its delayed spikes, 0: open) and pend
+    // (the spikes it will send).  dlink[j], j < mcount: column of neuron j's
+    // wait (-1: none); dlink[c], c >= dfirst: the neuron whose state column c
+    // holds.  rules[k].w then holds p | (d << 16).  dlink null: no delays
+    // (rules[k].w = p).
+    const int* dlink;
+    int mcount;
+    int dfirst;
 };
 
 // One chunk of canonical children [g0, g0 + B) of the frontier (canonical

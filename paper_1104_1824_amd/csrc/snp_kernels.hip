@@ -51,18 +51,22 @@ struct PsiAcc {
 
 // Neuron j (< m) holding x spikes: its applicable rules, into the wave's
 // tallies.  A parent is not expanded (Psi = 0, not halting) when a neuron
-// holds more than expand_max spikes, or when its output spike train (columns
-// track, track + 1; track < 0: none) has two spikes: its number is generated.
-__device__ __forceinline__ void psi_add_neuron(PsiAcc& A, int x, int j, int m, const int* nrp, const int4* rules,
-                                               long long expand_max, int track) {
+// holds more than expand_max spikes (the first mcount columns are spike
+// counts), or when its output spike train (columns track, track + 1;
+// track < 0: none) has two spikes: its number is generated.  With delays, a
+// neuron that waits (wt >= 1: closed, or sending its delayed spikes) applies
+// no rule, and the parent still has one child (the countdown moves on).
+__device__ __forceinline__ void psi_add_neuron(PsiAcc& A, int x, int wt, int j, int m, int mcount, const int* nrp,
+                                               const int4* rules, long long expand_max, int track) {
     int w = 0, k = 1;
     if (j < m) {
-        const uint32_t am = neuron_applicable(x, nrp[j], nrp[j + 1], rules, w);
-        k = kappa_of(am, w);
-        const bool count = track < 0 || j < track;
-        A.over |= (count && expand_max >= 0 && (long long)x > expand_max) || (j == track && x >= 2);
+        if (wt <= 0) {
+            const uint32_t am = neuron_applicable(x, nrp[j], nrp[j + 1], rules, w);
+            k = kappa_of(am, w);
+        }
+        A.over |= (j < mcount && expand_max >= 0 && (long long)x > expand_max) || (j == track && x >= 2);
     }
-    A.any |= (w > 0);
+    A.any |= (w > 0) || (wt > 0);
     A.c2 += __popcll(__ballot(w == 2));
     A.c3 += __popcll(__ballot(w == 3));
     A.c4 += __popcll(__ballot(w == 4));
@@ -107,7 +111,8 @@ __device__ __forceinline__ PsiPair psi_finish(const PsiAcc& A, bool& halting) {
 // (the 64 after any earlier one make its place value at least 2^64), so lane
 // q takes the q-th of them from the end.  One wave, all lanes active.
 template <typename T>
-__device__ u64 canon_rank(const T* row, int m, const int* nrp, const int4* rules, u64 L, int lane) {
+__device__ u64 canon_rank(const T* row, int m, const int* nrp, const int4* rules, const int* dlink, int mcount,
+                          u64 L, int lane) {
     int cnt = 0;  // neurons taken so far (uniform)
     int myw = 1;
     uint32_t mycm = 1;
@@ -115,7 +120,8 @@ __device__ u64 canon_rank(const T* row, int m, const int* nrp, const int4* rules
         const int j = base + lane;
         int w = 0;
         uint32_t am = 0;
-        if (j < m) am = neuron_applicable((int)row[j], nrp[j], nrp[j + 1], rules, w);
+        if (j < m && neuron_wait(row, dlink, mcount, j) <= 0)
+            am = neuron_applicable((int)row[j], nrp[j], nrp[j + 1], rules, w);
         const u64 bm = __ballot(w >= 2);
         const int nb = __popcll(bm);
         // lane q (cnt <= q < cnt + nb) takes the (q - cnt)-th set bit of bm from the top
@@ -161,16 +167,18 @@ __device__ u64 canon_rank(const T* row, int m, const int* nrp, const int4* rules
 
 template <typename T>
 __device__ __forceinline__ PsiPair parent_psi(const T* row, int m, const int* nrp, const int4* rules,
-                                              long long expand_max, int track, int lane, bool& halting) {
+                                              const int* dlink, int mcount, long long expand_max, int track,
+                                              int lane, bool& halting) {
     PsiAcc A;
     for (int base = 0; base < m; base += 64) {
         const int j = base + lane;
-        psi_add_neuron(A, j < m ? (int)row[j] : 0, j, m, nrp, rules, expand_max, track);
+        psi_add_neuron(A, j < m ? (int)row[j] : 0, j < m ? neuron_wait(row, dlink, mcount, j) : 0, j, m, mcount, nrp,
+                       rules, expand_max, track);
     }
     PsiPair r = psi_finish(A, halting);
     // with 2^62 or more children some canonical ones may have t >= 2^62, past
     // what a level enumerates: count only those below
-    if (r.full >= kPsiSat) r.canon = min(r.canon, canon_rank<T>(row, m, nrp, rules, kPsiSat, lane));
+    if (r.full >= kPsiSat) r.canon = min(r.canon, canon_rank<T>(row, m, nrp, rules, dlink, mcount, kPsiSat, lane));
     return r;
 }
 
@@ -214,7 +222,8 @@ __global__ __launch_bounds__(256) void k_psi(DevSystem s, const T* __restrict__ 
     u64 flo = 0, fhi = 0;
     for (long long p = w0; p < min(n, w0 + parents_per_wave); ++p) {
         bool h;
-        const PsiPair v = parent_psi<T>(F + p * (long long)s.m, s.m, tb.nrp, tb.rules, expand_max, s.track, lane, h);
+        const PsiPair v = parent_psi<T>(F + p * (long long)s.m, s.m, tb.nrp, tb.rules, s.dlink, s.mcount, expand_max,
+                                        s.track, lane, h);
         const u64 full = min(v.full, s.psi_cap);
         if (lane == 0) {
             psi[p] = min(v.canon, s.psi_cap);
@@ -265,11 +274,13 @@ __global__ __launch_bounds__(1024) void k_psi_scan_small(DevSystem s, const T* _
             const int p = p0 + 16 * q;
             if (p >= n) break;
             PsiAcc A;
-            psi_add_neuron(A, xs[q], lane, m, tb.nrp, tb.rules, expand_max, s.track);
+            const int wt = lane < m ? neuron_wait(F + (long long)p * m, s.dlink, s.mcount, lane) : 0;
+            psi_add_neuron(A, xs[q], wt, lane, m, s.mcount, tb.nrp, tb.rules, expand_max, s.track);
             bool h;
             PsiPair v2 = psi_finish(A, h);
             if (v2.full >= kPsiSat)
-                v2.canon = min(v2.canon, canon_rank<T>(F + (long long)p * m, m, tb.nrp, tb.rules, kPsiSat, lane));
+                v2.canon = min(v2.canon, canon_rank<T>(F + (long long)p * m, m, tb.nrp, tb.rules, s.dlink, s.mcount,
+                                                       kPsiSat, lane));
             const u64 v = min(v2.canon, s.psi_cap);
             const u64 full = min(v2.full, s.psi_cap);
             if (lane == 0) {
@@ -570,7 +581,8 @@ __global__ __launch_bounds__(1024) void k_budget_clip(DevSystem s, const T* __re
     }
     if (wid == 0) {
         const long long pb = s_pb;
-        const u64 rank = canon_rank<T>(F + pb * (long long)s.m, s.m, s.nrule_ptr, s.rules, budget - s_before, lane);
+        const u64 rank = canon_rank<T>(F + pb * (long long)s.m, s.m, s.nrule_ptr, s.rules, s.dlink, s.mcount,
+                                       budget - s_before, lane);
         if (lane == 0) {
             const u64 e = min(T0, sat_add(off[pb], rank));
             *tend = e;
@@ -624,38 +636,75 @@ struct Tables {
     const u64* R;      // [m] hash weights
 };
 
-// Fired rule of neuron j (canonical digit eg[j]) packed as (c << 16) | p (both
-// <= 65535, checked at load); 0 when none.
-__device__ __forceinline__ void set_fired(const Tables& tb, int j, const uint8_t* om, const uint32_t* am,
-                                          const uint8_t* eg, uint32_t* cp) {
-    uint32_t v = 0;
+// Fired rule of neuron j (canonical digit eg[j]) packed as (c << 16) | q, q
+// the spikes it sends at this step (c, q <= 65535, checked at load); 0 when it
+// fires nothing.  Without delays q = p of the fired rule.  With delays (dx
+// non-null): q = p for a rule without delay, the pending spikes of a neuron
+// whose wait ends now, else 0; and dx[j] = (closed << 31) | (d << 16) | p of
+// the fired rule (0 when none), closed meaning that spikes sent to j at this
+// step are lost (it fires a rule with a delay, or waits two steps or more).
+__device__ __forceinline__ void set_fired(const Tables& tb, const DevSystem& s, int j, const uint8_t* om,
+                                          const uint32_t* am, const uint8_t* eg, const int* par, uint32_t* cp,
+                                          uint32_t* dx) {
+    uint32_t c = 0, w = 0;
     if (om[j]) {
         const int d = canon_digit(am[j], om[j], eg[j]);
         const int4 R = tb.rules[tb.nrp[j] + nth_bit(am[j] & 0xFFFFu, d)];
-        v = ((uint32_t)R.z << 16) | (uint32_t)R.w;
+        c = (uint32_t)R.z;
+        w = (uint32_t)R.w;
     }
-    cp[j] = v;
+    if (!dx) {
+        cp[j] = (c << 16) | w;
+        return;
+    }
+    int wait = 0, pend = 0;
+    if (j < s.mcount) {
+        const int col = s.dlink[j];
+        if (col >= 0) {
+            wait = par[col];
+            pend = par[col + 1];
+        }
+    }
+    const uint32_t d = w >> 16, p = w & 0xFFFFu;
+    const uint32_t q = (om[j] && d == 0) ? p : (wait == 1 ? (uint32_t)pend : 0u);
+    const bool closed = d >= 1 || wait >= 2;
+    cp[j] = (c << 16) | q;
+    dx[j] = (closed ? 0x80000000u : 0u) | w;
 }
 
+// A parent's row into LDS with every neuron's applicable rules and omega (a
+// neuron that waits, with delays, has none).
 template <typename T>
-__device__ __forceinline__ void load_parent(const Tables& tb, int m, const T* row, int lane, int* par, uint32_t* am,
-                                            uint8_t* om) {
+__device__ __forceinline__ void load_parent(const Tables& tb, const DevSystem& s, int m, const T* row, int lane,
+                                            int* par, uint32_t* am, uint8_t* om) {
     for (int j = lane; j < m; j += 64) {
         const int x = (int)row[j];
         par[j] = x;
-        int w;
-        am[j] = neuron_applicable(x, tb.nrp[j], tb.nrp[j + 1], tb.rules, w);
+        int w = 0;
+        am[j] = neuron_wait(row, s.dlink, s.mcount, j) > 0 ? 0u
+                                                           : neuron_applicable(x, tb.nrp[j], tb.nrp[j + 1], tb.rules, w);
         om[j] = (uint8_t)w;
     }
+}
+
+// State column j (>= dfirst) of a child, with delays: a neuron firing a rule
+// with delay d >= 1 waits d steps to send its p spikes; otherwise the wait
+// counts down, and the pending spikes stay until the step that sends them.
+__device__ __forceinline__ long long delay_state(const DevSystem& s, const int* par, const uint32_t* dx, int j) {
+    const int n = s.dlink[j];
+    const int col = s.dlink[n];
+    const uint32_t f = dx[n] & 0x7FFFFFFFu;
+    const long long wait = par[col], pend = par[col + 1];
+    if (j == col) return (f >> 16) ? (long long)(f >> 16) : (wait >= 1 ? wait - 1 : 0);
+    return (f >> 16) ? (long long)(f & 0xFFFFu) : (wait >= 2 ? pend : 0);
 }
 
 // The output neuron's spike train of a child (column j = track: spikes sent
 // to the environment, at most 2 counted; j = track + 1: steps from the first
 // to the second), from the parent's (par) and the q spikes the output neuron
-// sends out with its fired rule (cp: (c << 16) | p, 0 when it fires nothing).
-__device__ __forceinline__ long long spike_train(const DevSystem& s, const int* par, const uint8_t* om,
-                                                 const uint32_t* cp, int j) {
-    const long long q = om[s.out] ? (long long)(cp[s.out] & 0xFFFFu) : 0;
+// sends out at this step (cp: (c << 16) | q).
+__device__ __forceinline__ long long spike_train(const DevSystem& s, const int* par, const uint32_t* cp, int j) {
+    const long long q = (long long)(cp[s.out] & 0xFFFFu);
     const long long env = par[s.track], el = par[s.track + 1];
     if (j == s.track) return env == 0 ? min(2LL, q) : env == 1 ? min(2LL, 1 + q) : env;
     return env == 0 ? 0 : env == 1 ? el + 1 : el;
@@ -666,7 +715,14 @@ __host__ __device__ __forceinline__ size_t table_lds_bytes(const DevSystem& s, i
            ~(size_t)15;
 }
 
-template <typename T, bool TBL_LDS>
+// Bytes of a wave's LDS in the sparse form: par, cp, am (4 B each), omega and
+// digit (1 B each) per column, and with delays dx (4 B, 4-aligned) per column.
+__host__ __device__ __forceinline__ int sparse_dx_offset(int m) { return (kLdsBytesPerNeuron * m + 3) & ~3; }
+__host__ __device__ __forceinline__ int sparse_wave_stride(int m, bool delay) {
+    return ((delay ? sparse_dx_offset(m) + 4 * m : kLdsBytesPerNeuron * m) + 15) & ~15;
+}
+
+template <typename T, bool TBL_LDS, bool DELAY>
 __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a, int run, int wave_stride) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
@@ -705,6 +761,7 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
     uint32_t* am = cp + m;
     uint8_t* om = (uint8_t*)(am + m);
     uint8_t* eg = om + m;
+    uint32_t* dx = DELAY ? (uint32_t*)(base + sparse_dx_offset(m)) : nullptr;
     const T* F = (const T*)a.frontier;
     T* stage = (T*)a.stage;
     const int cnt = (int)min((long long)run, Beff - b0);
@@ -725,12 +782,12 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
     long long p = uni_ll(lo);
     u64 u = uni64(g - a.off[p]);
     u64 psi_p = uni64(a.psi[p]);
-    load_parent<T>(tb, m, F + p * (long long)m, lane, par, am, om);
+    load_parent<T>(tb, s, m, F + p * (long long)m, lane, par, am, om);
     wave_lds_sync();
     u64 place_w = digit_place(m, lane, om);  // place values of child indices (omega)
     canon_decode(m, lane, u, om, am, eg, canon_place(m, lane, om, am));
     wave_lds_sync();
-    for (int j = lane; j < m; j += 64) set_fired(tb, j, om, am, eg, cp);
+    for (int j = lane; j < m; j += 64) set_fired(tb, s, j, om, am, eg, par, cp, dx);
 
     bool ovf = false;
     for (int k = 0; k < cnt; ++k) {
@@ -740,9 +797,12 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
         T* out = stage + b * (long long)m;
         for (int j = lane; j < m; j += 64) {
             long long v = (long long)par[j] - (long long)(cp[j] >> 16);
-            const int e1 = tb.inp[j + 1];
-            for (int e = tb.inp[j]; e < e1; ++e) v += cp[tb.ins[e]] & 0xFFFFu;
-            if (s.track >= 0 && j >= s.track) v = spike_train(s, par, om, cp, j);
+            if (!DELAY || !(dx[j] >> 31)) {  // with delays, spikes sent to a closed neuron are lost
+                const int e1 = tb.inp[j + 1];
+                for (int e = tb.inp[j]; e < e1; ++e) v += cp[tb.ins[e]] & 0xFFFFu;
+            }
+            if (DELAY && j >= s.dfirst) v = delay_state(s, par, dx, j);
+            else if (s.track >= 0 && j >= s.track) v = spike_train(s, par, cp, j);
             ovf |= (v < 0) | (v > s.count_max);
             out[j] = (T)v;
             h += hterm((uint32_t)v, tb.R[j]);
@@ -764,12 +824,12 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
                 if (p >= a.n) break;  // unreachable while g0 + B <= sum of Psi
                 u = 0;
                 psi_p = uni64(a.psi[p]);
-                load_parent<T>(tb, m, F + p * (long long)m, lane, par, am, om);
+                load_parent<T>(tb, s, m, F + p * (long long)m, lane, par, am, om);
                 wave_lds_sync();
                 place_w = digit_place(m, lane, om);
                 for (int j = lane; j < m; j += 64) {
                     eg[j] = 0;
-                    set_fired(tb, j, om, am, eg, cp);
+                    set_fired(tb, s, j, om, am, eg, par, cp, dx);
                 }
             } else {
                 int myJ = -1;
@@ -782,10 +842,10 @@ __global__ __launch_bounds__(256) void k_expand_sparse(DevSystem s, ChunkArgs a,
                     const int kp = kappa_of(am[j], om[j]);
                     if (j == J) {
                         eg[j] = (uint8_t)(eg[j] + 1);
-                        set_fired(tb, j, om, am, eg, cp);
+                        set_fired(tb, s, j, om, am, eg, par, cp, dx);
                     } else if (kp >= 2 && j > J) {
                         eg[j] = 0;
-                        set_fired(tb, j, om, am, eg, cp);
+                        set_fired(tb, s, j, om, am, eg, par, cp, dx);
                     }
                 }
             }
@@ -1242,7 +1302,7 @@ hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkA
                                 bool* probed) {
     *probed = false;
     if (a.B <= 0) return hipSuccess;
-    if (s.track < 0 && s.m <= 64 && s.max_in <= kLaneMaxIn && (size_t)s.r * 24 <= 24 * 1024) {
+    if (s.track < 0 && !s.dlink && s.m <= 64 && s.max_in <= kLaneMaxIn && (size_t)s.r * 24 <= 24 * 1024) {
         *probed = a.table != nullptr;
         // one generation of resident waves (the LDS tables allow 16 per CU);
         // runs of 4 to 4096 children are handed out on the device, where the
@@ -1254,7 +1314,8 @@ hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkA
         else hipLaunchKernelGGL((k_expand_lane<uint16_t>), dim3(blocks), dim3(256), lds, st, s, a);
         return hipGetLastError();
     }
-    const int stride = ((kLdsBytesPerNeuron * s.m) + 15) & ~15;
+    const bool delay = s.dlink != nullptr;
+    const int stride = sparse_wave_stride(s.m, delay);
     if ((size_t)stride > 64 * 1024) return hipErrorInvalidValue;  // m too large for this form
     const size_t tbl = table_lds_bytes(s, s.nnz_in);
     const bool tbl_lds = tbl <= (size_t)kTableLdsLimit;
@@ -1268,17 +1329,26 @@ hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkA
     const long long waves = (a.B + run - 1) / run;
     const unsigned blocks = (unsigned)((waves + wpb - 1) / wpb);
     const size_t lds = (size_t)wpb * stride + (tbl_lds ? tbl : 0);
+    const dim3 grid(blocks), block(64 * wpb);
+#define SNP_SPARSE(T_, L_, D_) hipLaunchKernelGGL((k_expand_sparse<T_, L_, D_>), grid, block, lds, st, s, a, run, stride)
     if (elem_bytes == 4) {
-        if (tbl_lds)
-            hipLaunchKernelGGL((k_expand_sparse<int32_t, true>), dim3(blocks), dim3(64 * wpb), lds, st, s, a, run, stride);
-        else
-            hipLaunchKernelGGL((k_expand_sparse<int32_t, false>), dim3(blocks), dim3(64 * wpb), lds, st, s, a, run, stride);
+        if (delay) {
+            if (tbl_lds) SNP_SPARSE(int32_t, true, true);
+            else SNP_SPARSE(int32_t, false, true);
+        } else {
+            if (tbl_lds) SNP_SPARSE(int32_t, true, false);
+            else SNP_SPARSE(int32_t, false, false);
+        }
     } else {
-        if (tbl_lds)
-            hipLaunchKernelGGL((k_expand_sparse<uint16_t, true>), dim3(blocks), dim3(64 * wpb), lds, st, s, a, run, stride);
-        else
-            hipLaunchKernelGGL((k_expand_sparse<uint16_t, false>), dim3(blocks), dim3(64 * wpb), lds, st, s, a, run, stride);
+        if (delay) {
+            if (tbl_lds) SNP_SPARSE(uint16_t, true, true);
+            else SNP_SPARSE(uint16_t, false, true);
+        } else {
+            if (tbl_lds) SNP_SPARSE(uint16_t, true, false);
+            else SNP_SPARSE(uint16_t, false, false);
+        }
     }
+#undef SNP_SPARSE
     return hipGetLastError();
 }
 
@@ -1760,7 +1830,8 @@ __global__ __launch_bounds__(256) void k_start_walk(int m, const u64* __restrict
                                                     long long count_max, u64 hash_mask,
                                                     uint32_t* __restrict__ row_slot, DevCounters* __restrict__ sc,
                                                     long long* par0, long long* chi0, const int* nrp,
-                                                    const int4* rules, long long expand_max, u64 psi_cap, int track,
+                                                    const int4* rules, const int* dlink, int mcount,
+                                                    long long expand_max, u64 psi_cap, int track,
                                                     u64* psi0, u64* psif0, uint8_t* hflag0, u64* off0, u64* Tdev) {
     __shared__ u64 s_slot, s_entry;
     const int lane = threadIdx.x & 63;
@@ -1789,7 +1860,8 @@ __global__ __launch_bounds__(256) void k_start_walk(int m, const u64* __restrict
     // when asked: the first pass then needs no Psi launch of its own
     PsiPair psi_c0{0, 0};
     bool halt_c0 = false;
-    if (psi0 && threadIdx.x < 64) psi_c0 = parent_psi<T>(c0, m, nrp, rules, expand_max, track, lane, halt_c0);
+    if (psi0 && threadIdx.x < 64)
+        psi_c0 = parent_psi<T>(c0, m, nrp, rules, dlink, mcount, expand_max, track, lane, halt_c0);
     if (threadIdx.x == 0) {
         row_slot[0] = (uint32_t)home;
         if (par0) *par0 = -1;
@@ -1820,11 +1892,13 @@ hipError_t launch_start_walk(int elem_bytes, int m, const u64* R, u64* table, u6
     if (elem_bytes == 4)
         hipLaunchKernelGGL(k_start_walk<int32_t>, dim3(blocks), dim3(256), 0, st, m, R, table, slot_mask,
                            (const int32_t*)c0, (int32_t*)arena, count_max, hash_mask, row_slot, sc, par0, chi0,
-                           s.nrule_ptr, s.rules, expand_max, s.psi_cap, s.track, psi0, psif0, hflag0, off0, Tdev);
+                           s.nrule_ptr, s.rules, s.dlink, s.mcount, expand_max, s.psi_cap, s.track, psi0, psif0,
+                           hflag0, off0, Tdev);
     else
         hipLaunchKernelGGL(k_start_walk<uint16_t>, dim3(blocks), dim3(256), 0, st, m, R, table, slot_mask,
                            (const uint16_t*)c0, (uint16_t*)arena, count_max, hash_mask, row_slot, sc, par0, chi0,
-                           s.nrule_ptr, s.rules, expand_max, s.psi_cap, s.track, psi0, psif0, hflag0, off0, Tdev);
+                           s.nrule_ptr, s.rules, s.dlink, s.mcount, expand_max, s.psi_cap, s.track, psi0, psif0,
+                           hflag0, off0, Tdev);
     return hipGetLastError();
 }
 

@@ -42,7 +42,7 @@ class snp_desc(ctypes.Structure):
         ("rule_neuron", ctypes.c_void_p), ("rule_i", ctypes.c_void_p), ("rule_j", ctypes.c_void_p),
         ("rule_c", ctypes.c_void_p), ("rule_p", ctypes.c_void_p),
         ("n_syn", ctypes.c_int32), ("syn_src", ctypes.c_void_p), ("syn_dst", ctypes.c_void_p),
-        ("M", ctypes.c_void_p), ("count_type", ctypes.c_int32),
+        ("M", ctypes.c_void_p), ("count_type", ctypes.c_int32), ("rule_d", ctypes.c_void_p),
     ]
 
 
@@ -239,9 +239,14 @@ def _desc(system, keep, M=None) -> snp_desc:
     if Mp is not None:
         keep.append(Mp)
     ct = SNP_COUNT_U16 if getattr(system, "count_type", "i32") == "u16" else SNP_COUNT_I32
+    rd = getattr(system, "rule_d", None)
+    rd = _i32(rd) if rd is not None else None
+    if rd is not None:
+        keep.append(rd)
     return snp_desc(int(system.m), int(arrs[0].shape[0]), arrs[0].ctypes.data, arrs[1].ctypes.data,
                     arrs[2].ctypes.data, arrs[3].ctypes.data, arrs[4].ctypes.data, int(arrs[5].shape[0]),
-                    arrs[5].ctypes.data, arrs[6].ctypes.data, Mp.ctypes.data if Mp is not None else None, ct)
+                    arrs[5].ctypes.data, arrs[6].ctypes.data, Mp.ctypes.data if Mp is not None else None, ct,
+                    rd.ctypes.data if rd is not None else None)
 
 
 def _stream_ptr(stream):
@@ -259,7 +264,9 @@ def snp_load(system, *, path: int = SNP_PATH_AUTO, stop_at_cap: bool = False, fr
     """snp_load.  ``system`` has m, rule_neuron/i/j/c/p, syn_src/dst and
     count_type ("i32" or "u16") attributes; ``stream`` is a torch.cuda.Stream
     (None: torch's current stream).  With ``out_neuron`` > 0 (1-based) rows
-    hold m + 2 entries (the output neuron's spike train after the counts)."""
+    hold m + 2 entries (the output neuron's spike train after the counts);
+    a system with ``rule_d`` (delays) adds (wait, pend) per neuron owning a
+    rule with a delay.  ``Handle.m`` is the row width the library reports."""
     arrs = []
     d = _desc(system, arrs, M)
     ct = d.count_type
@@ -270,7 +277,9 @@ def snp_load(system, *, path: int = SNP_PATH_AUTO, stop_at_cap: bool = False, fr
                     int(out_neuron), sp or None)
     out = ctypes.c_void_p()
     _check(lib().snp_load(ctypes.byref(d), ctypes.byref(o), ctypes.byref(out)), "snp_load")
-    return Handle(out.value, arrs, int(system.m) + (2 if out_neuron else 0), ct)
+    h = Handle(out.value, arrs, 0, ct)
+    h.m = int(lib().snp_row_bytes(h.ptr)) // _eb(ct)
+    return h
 
 
 def snp_free(h: Handle):

@@ -49,8 +49,11 @@ def gpu_bfs(system, max_depth=-1, out_capacity=1 << 16, c0=None, with_prov=True,
     try:
         if tuning:
             snp.snp_set_tuning(h, **{k: v for k, v in tuning.items() if k != "ms"})
-        c0t = to_device_rows(system, system.c0 if c0 is None else c0)
-        out = torch.empty((out_capacity, system.m), dtype=dev_dtype(system), device="cuda")
+        c0 = np.asarray(system.c0 if c0 is None else c0, dtype=np.int64)
+        if c0.shape[0] < h.m:  # extra row entries (output spike train, delay states) start at 0
+            c0 = np.concatenate([c0, np.zeros(h.m - c0.shape[0], dtype=np.int64)])
+        c0t = to_device_rows(system, c0)
+        out = torch.empty((out_capacity, h.m), dtype=dev_dtype(system), device="cuda")
         par = torch.empty(out_capacity, dtype=torch.int64, device="cuda") if with_prov else None
         chi = torch.empty(out_capacity, dtype=torch.int64, device="cuda") if with_prov else None
         res = snp.snp_run(h, c0t, max_depth, out, out_capacity, parent_of=par, child_of=chi)
