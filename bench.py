@@ -16,7 +16,7 @@ launch of it, inside the timed region), its int8 matrix-core utilisation, the
 same walk on the plain sparse form (the speedup the metric names), the CPU
 oracle timed on a bounded sample of the same workload, and secondary lines
 for the plain-sparse, batched and large workloads, each with its own roofline
-and CPU baseline.
+and CPU baseline, and one for the plain-sparse system with rule delays.
 """
 import argparse
 import json
@@ -40,6 +40,8 @@ ENTRY_BYTES = 16             # visited-set entry written per new configuration
 # bytes per child of the one-neuron-per-lane expansion besides its row: key 8,
 # parent 4, child index 8, probe slot 4, visited-set entry 8
 LANE_CHILD_EXTRA = 32
+# bytes per child of the sparse (pull) expansion besides its row: key 8, parent 4, child index 8
+SPARSE_CHILD_EXTRA = 20
 
 DENSE_WORKLOAD = ("dense_int8: seeded SN P system m=512, 3 rules/neuron (r=1536), E=a^i(a^j)* i in [1,4] "
                   "j in [0,3], p in [0,4] (M entries in [-4,4], int8), out-degree 64, C0 in [0,4], int32 "
@@ -48,6 +50,10 @@ PLAIN_WORKLOAD = ("plain_sparse: m=64, 2 rules/neuron (r=128), i in [1,4] j in [
                   "C0 in [0,4], int32; BFS until a level reaches 1e5 configurations (seed 0)")
 LARGE_WORKLOAD = ("large: m=4096, 4 rules/neuron (r=16384), out-degree 16, C0 in [0,8], uint16; BFS depth 3, "
                   "frontier_cap 4e6 per level, chunks of 2^22 children (seed 0)")
+DELAY_WORKLOAD = ("plain_sparse_delays: the plain_sparse system (m=64, seed 0) with rule delays: each rule gets "
+                  "one with probability 1/2, uniform in [1,3] (delay stream seed 0; 45 of 64 neurons delayed), "
+                  "rows of counts plus (wait, pend) per delayed neuron, int32; BFS until a level reaches 1e5 "
+                  "configurations")
 BATCH_WORKLOAD = ("batched_uneven: 256 systems, m in [16,1024], 1-3 rules and out-degree 2-32 per neuron, "
                   "10k deterministic steps each, one graph-replayed launch (seeds 0-255)")
 
@@ -81,6 +87,7 @@ class Walk:
     """A loaded handle plus its device buffers, for timed snp_run calls."""
 
     def __init__(self, system, path, cap, depth, stop, chunk, out_cap, profile, tune=False, cache=None):
+        import numpy as np
         import torch
 
         from paper_1104_1824_amd import snp
@@ -88,9 +95,11 @@ class Walk:
         self.snp, self.system, self.depth, self.out_cap = snp, system, depth, out_cap
         self.h = snp.snp_load(system, path=path, frontier_cap=cap, stop_at_cap=stop, max_rows=out_cap, chunk=chunk,
                               profile=profile)
-        self.c0 = device_rows(system, system.c0)
+        # rows may carry more entries than the m counts (delay states): width from the library
+        c0 = np.asarray(system.c0, dtype=np.int64)
+        self.c0 = device_rows(system, np.concatenate([c0, np.zeros(self.h.m - c0.shape[0], dtype=np.int64)]))
         dt = torch.int16 if system.count_type == "u16" else torch.int32
-        self.out = torch.empty((out_cap, system.m), dtype=dt, device="cuda")
+        self.out = torch.empty((out_cap, self.h.m), dtype=dt, device="cuda")
         # launch settings timed on this very walk, before (and outside) the timed region;
         # with a cache file, settings found there are used as they are
         self.tuning = None
@@ -131,6 +140,8 @@ KERNEL_SOURCES = {
                       "paper_1104_1824_amd/csrc/snp_internal.hpp"],
     "k_expand_lane": ["paper_1104_1824_amd/csrc/snp_kernels.hip", "paper_1104_1824_amd/csrc/snp_device.hpp",
                       "paper_1104_1824_amd/csrc/snp_internal.hpp"],
+    "k_expand_sparse": ["paper_1104_1824_amd/csrc/snp_kernels.hip", "paper_1104_1824_amd/csrc/snp_device.hpp",
+                        "paper_1104_1824_amd/csrc/snp_internal.hpp"],
 }
 
 
@@ -154,16 +165,16 @@ def measured_traffic(kernel, workload):
     return None
 
 
-def hbm_roofline(results, kernel, bytes_per_new, rb, per_child=False, workload=None):
+def hbm_roofline(results, kernel, bytes_per_new, rb, per_child=False, workload=None, child_extra=LANE_CHILD_EXTRA):
     """Roofline of the expansion kernel: algorithmic bytes over its device time
     (HIP events around each launch).  Algorithmic bytes = every new configuration's
     row plus its visited-set entry (bytes_per_new); with per_child, the
-    one-neuron-per-lane form's own per-child bytes instead (the row of every
-    child computed, plus its records)."""
+    expansion's own per-child bytes instead (the row of every child computed,
+    plus its records: child_extra bytes)."""
     ns = totals(results, "ns_expand")
     launches = totals(results, "chunks")
     if per_child:
-        moved = totals(results, "expanded") * (rb + LANE_CHILD_EXTRA)
+        moved = totals(results, "expanded") * (rb + child_extra)
     else:
         moved = totals(results, "new_configs") * bytes_per_new
     achieved = moved / max(1, ns)  # bytes per ns = GB/s
@@ -296,6 +307,47 @@ def plain_line(steps=50, warmup=5, cpu=None, tune=True, cache=None):
     return line
 
 
+def delay_system():
+    import synth
+    from synth.systems import with_delays
+
+    return with_delays(synth.config_system(2, 0), 0, d_max=3)
+
+
+def cpu_delays(budget_s=5.0):
+    import oracle
+
+    oracle.build(force=False)
+    s = delay_system()
+    n_new, runs, t0 = 0, 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        res = oracle.bfs(s, max_depth=1000, frontier_cap=100000, stop_at_cap=True, rows_cap=1 << 19)
+        n_new += int(res.level_sizes[1:].sum())
+        runs += 1
+    dt = time.perf_counter() - t0
+    return dict(value=round(n_new / dt, 1), unit="configs/s", cores=1, kind="oracle",
+                sample=f"{runs} complete walks of the same workload, single-threaded, {dt:.1f} s")
+
+
+def delays_line(steps=20, warmup=3, cpu=None, tune=True, cache=None):
+    from paper_1104_1824_amd import snp
+
+    s = delay_system()
+    log("plain sparse m=64 seed 0 with delays, sparse path")
+    w = Walk(s, snp.SNP_PATH_SPARSE, 100000, 1000, True, 1 << 17, 400000, profile=1, tune=tune, cache=cache)
+    rb = w.h.m * 4
+    results, dt = w.timed(steps, warmup)
+    w.close()
+    new = results[-1]["n_configs"] - 1
+    line = dict(workload=DELAY_WORKLOAD, value=round(steps * new / dt, 1), unit="configs/s",
+                ms_per_step=round(dt / steps * 1e3, 4), levels=results[-1]["level_sizes"].tolist(), dtype="int32",
+                row_entries=rb // 4, tuning=w.tuning)
+    line.update(hbm_roofline(results, "k_expand_sparse", None, rb, per_child=True, workload="delays",
+                             child_extra=SPARSE_CHILD_EXTRA))
+    line["cpu_baseline"] = cpu
+    return line
+
+
 def batch_work(systems):
     """Algorithmic integer operations per step of every system: one
     applicability test per rule, one gather per synapse, one update per neuron."""
@@ -396,8 +448,9 @@ def large_line(cpu=None, tune=True, cache=None):
     return line
 
 
-SECONDARY = {"plain_sparse": plain_line, "batched": batched_line, "large": large_line}
-CPU_BASELINES = {"dense": cpu_dense, "plain_sparse": cpu_plain, "batched": cpu_batched, "large": cpu_large}
+SECONDARY = {"plain_sparse": plain_line, "batched": batched_line, "large": large_line, "delays": delays_line}
+CPU_BASELINES = {"dense": cpu_dense, "plain_sparse": cpu_plain, "batched": cpu_batched, "large": cpu_large,
+                 "delays": cpu_delays}
 
 
 def copy_calibration(nbytes=1 << 30, reps=5):

@@ -132,3 +132,18 @@ def test_batched_mode_refuses_delays(gpu):
             snp.snp_run_batch([h], [c0], 3, [fin])
     finally:
         h.close()
+
+
+@pytest.mark.parametrize("tuning", [None, dict(chunk=1 << 15, int8_tiles=0, sparse_run=64),
+                                    dict(chunk=1 << 17, int8_tiles=0, sparse_run=4)])
+def test_bench_delay_workload(gpu, oracle_mod, tuning):
+    """The delays workload exactly as the benchmark times it (sparse path,
+    chunks of 2^17 children, expansion timing on, 400000 rows), with the
+    built-in launch settings and with settings the tuner can pick."""
+    import bench
+
+    s = bench.delay_system()
+    note(f"delays bench workload, tuning {tuning}")
+    g = gpu_bfs(s, max_depth=1000, frontier_cap=100000, stop_at_cap=True, out_capacity=400000, max_rows=400000,
+                chunk=1 << 17, profile=1, tuning=tuning)
+    assert_same_bfs(g, oracle_mod.bfs(s, max_depth=1000, frontier_cap=100000, stop_at_cap=True, rows_cap=1 << 19))
