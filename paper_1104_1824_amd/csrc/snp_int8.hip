@@ -329,49 +329,80 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
             // quarters x 4 row blocks x NT / 64 column blocks
             if (tid == 0) nmfma += (u64)((m + NT - 1) / NT) * 4 * (q1 - q0 + 1) * 4 * (NT / 64);
             // 7. column tiles: stage M_V transposed, then every quarter's product
-            //    plus the reference row
+            //    plus the reference row.  Only the kvar live rule columns are
+            //    staged: D is 0 in every later column, so whatever MT holds there
+            //    adds nothing.  With m a multiple of 16 a rule's slice of the tile
+            //    is read as 16-byte vectors.
             for (int n0 = 0; n0 < m; n0 += NT) {
                 __syncthreads();
-                for (int q = tid; q < kKMax * NT; q += blockDim.x) {
-                    const int k = q / NT, n = q - k * NT;
-                    int8_t v = 0;
-                    if (k < kvar && n0 + n < m) v = s.M8[(long long)L.klist[k] * m + n0 + n];
-                    L.MT[n * kMTStride + k] = v;
+                if ((m & 15) == 0) {
+                    constexpr int G = NT / 16;
+                    for (int q = tid; q < kvar * G; q += blockDim.x) {
+                        const int k = q / G, n = 16 * (q - k * G);
+                        if (n0 + n >= m) continue;
+                        const int4 v = *(const int4*)&s.M8[(long long)L.klist[k] * m + n0 + n];
+                        const int8_t* b = (const int8_t*)&v;
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) L.MT[(n + i) * kMTStride + k] = b[i];
+                    }
+                } else {
+                    for (int q = tid; q < kvar * NT; q += blockDim.x) {
+                        const int k = q / NT, n = q - k * NT;
+                        if (n0 + n < m) L.MT[n * kMTStride + k] = s.M8[(long long)L.klist[k] * m + n0 + n];
+                    }
                 }
                 __syncthreads();
+                // The product is taken transposed, (D . M_V)^T = M_V^T . D^T: the
+                // staged MT is the A operand and the D rows the B operand, so lane
+                // l ends with child row l % 16 of its 16-row block at the four
+                // consecutive columns 4 (l / 16) .. + 3 of each 16-column block,
+                // stored as one vector.
                 constexpr int CB = NT / 64;  // 16-column blocks per wave
                 const int colw = wid * (NT / 4);
-                v4i bf[CB];
-                long long refv[CB];
+                const bool vec = (m & 3) == 0;  // rows and 4-column groups aligned for vector access
+                v4i af[CB];
+                int refv[CB][4];
 #pragma unroll
                 for (int cb = 0; cb < CB; ++cb) {
-                    bf[cb] = *(const v4i*)&L.MT[(colw + 16 * cb + (lane & 15)) * kMTStride + 16 * (lane >> 4)];
-                    const int col = n0 + colw + 16 * cb + (lane & 15);
-                    refv[cb] = col < m ? (long long)refrow[col] : 0;
+                    af[cb] = *(const v4i*)&L.MT[(colw + 16 * cb + (lane & 15)) * kMTStride + 16 * (lane >> 4)];
+                    const int col0 = n0 + colw + 16 * cb + 4 * (lane >> 4);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) refv[cb][i] = col0 + i < m ? (int)refrow[col0 + i] : 0;
                 }
                 for (int qr = q0; qr <= q1; ++qr) {
-                    v4i acc[4][CB];
 #pragma unroll
                     for (int rb = 0; rb < 4; ++rb) {
-                        const v4i af = *(const v4i*)&L.D[(64 * qr + 16 * rb + (lane & 15)) * kKMax + 16 * (lane >> 4)];
+                        const int row = 64 * qr + 16 * rb + (lane & 15);
+                        const v4i bf = *(const v4i*)&L.D[row * kKMax + 16 * (lane >> 4)];
+                        v4i acc[CB];
 #pragma unroll
                         for (int cb = 0; cb < CB; ++cb)
-                            acc[rb][cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[cb], v4i{0, 0, 0, 0}, 0, 0, 0);
-                    }
+                            acc[cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[cb], bf, v4i{0, 0, 0, 0}, 0, 0, 0);
+                        if (row <= c || row >= cend) continue;
+                        T* out = stage + (b0 + row) * (long long)m;
 #pragma unroll
-                    for (int cb = 0; cb < CB; ++cb) {
-                        const int col = n0 + colw + 16 * cb + (lane & 15);
-                        if (col >= m) continue;
-#pragma unroll
-                        for (int rb = 0; rb < 4; ++rb)
+                        for (int cb = 0; cb < CB; ++cb) {
+                            const int col0 = n0 + colw + 16 * cb + 4 * (lane >> 4);
+                            long long v[4];
 #pragma unroll
                             for (int i = 0; i < 4; ++i) {
-                                const int row = 64 * qr + 16 * rb + 4 * (lane >> 4) + i;
-                                if (row <= c || row >= cend) continue;
-                                const long long v = refv[cb] + acc[rb][cb][i];
-                                ovf |= (v < 0) | (v > s.count_max);
-                                stage[(b0 + row) * (long long)m + col] = (T)v;
+                                v[i] = (long long)refv[cb][i] + acc[cb][i];
+                                ovf |= (col0 + i < m) & ((v[i] < 0) | (v[i] > s.count_max));
                             }
+                            if (vec && col0 + 3 < m) {
+                                if constexpr (sizeof(T) == 4) {
+                                    *(int4*)(out + col0) = make_int4((int)v[0], (int)v[1], (int)v[2], (int)v[3]);
+                                } else {
+                                    const uint2 pk = make_uint2((uint32_t)(uint16_t)v[0] | ((uint32_t)(uint16_t)v[1] << 16),
+                                                                (uint32_t)(uint16_t)v[2] | ((uint32_t)(uint16_t)v[3] << 16));
+                                    *(uint2*)(out + col0) = pk;
+                                }
+                            } else {
+#pragma unroll
+                                for (int i = 0; i < 4; ++i)
+                                    if (col0 + i < m) out[col0 + i] = (T)v[i];
+                            }
+                        }
                     }
                 }
             }
