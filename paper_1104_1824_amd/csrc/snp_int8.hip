@@ -21,6 +21,10 @@
 // so does its child index t (linear in the digits, with the place values of
 // the full mixed radix).  A segment whose V needs more than 64 neurons or 64
 // rule columns is halved until it fits; a single child is computed by the pull.
+// When a segment starts right after the block's previous one in the same
+// parent (consecutive tiles of a block mostly do), its reference child is the
+// previous segment's last child with the rows of M_Pi of the few neurons whose
+// digit changed swapped, instead of a full pull.
 // The transposed M_V of a column tile is staged once and serves the segment's
 // four 64-row quarters, each a 4 x (NT / 64) grid of 16 x 16 products per wave.
 //
@@ -40,13 +44,16 @@ constexpr int kTile = 256;  // children per block tile (one per thread)
 constexpr int kKMax = 64;   // rule columns of V per segment on the MFMA path (one 64-deep K step)
 constexpr int kVMax = 64;   // neurons in V per segment on the MFMA path
 constexpr int kMTStride = kKMax + 16;  // bytes per column of the transposed M_V tile (padding vs bank conflicts)
+constexpr int kIncMax = 32;  // most changed digits for a reference child derived from the previous segment's last
 
 struct Lds {
     uint8_t* om;   // [m] omega per neuron
     uint8_t* dg;   // [m] canonical digits of the child being computed by the sparse pull
     uint8_t* dgb;  // [m] canonical digits of the last child of the segment
     uint32_t* am;  // [m] applicable-rule mask (<= 16 rules per neuron) | canonical digits << 16
-    uint16_t* cp;  // [m] fired (c << 8 | p) of the child being computed
+    uint16_t* cp;  // [m] fired (c << 8 | p) of the child being computed by the pull
+    uint8_t* dp;   // [m] canonical digits of the previous segment's last child (shares cp's bytes:
+                   // needed only until the next reference child, which then needs no pull)
     int8_t* D;     // [kTile][kKMax]
     int8_t* MT;    // [NT][kMTStride]
     int* klist;    // [kKMax] rule of every K column
@@ -55,7 +62,10 @@ struct Lds {
     u64* rowh;     // [kTile] H of every row of the tile
     u64* placev;   // [kVMax] place value (over omega) of every neuron of V
     u64* wsum;     // [5]: [0..3] block sums, [4] the reference child's index t
-    int* sc;       // scalars: [0] jstar, [1] nv, [2] kvar
+    int* sc;       // scalars: [0] jstar, [1] nv, [2] kvar, [3] changed digits
+    int* chg;      // [kIncMax] neurons whose digit changed, then their old and new rules
+    int* k0;       //   (share D's bytes: used before D is filled)
+    int* k1;
 };
 
 __host__ __device__ __forceinline__ size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -79,8 +89,12 @@ __device__ __forceinline__ Lds carve(unsigned char* smem, int m, int nt) {
     L.am = (uint32_t*)(smem + o);
     o += align16((size_t)4 * m);
     L.cp = (uint16_t*)(smem + o);
+    L.dp = (uint8_t*)L.cp;
     o += align16((size_t)2 * m);
     L.D = (int8_t*)(smem + o);
+    L.chg = (int*)L.D;
+    L.k0 = L.chg + kIncMax;
+    L.k1 = L.k0 + kIncMax;
     o += (size_t)kTile * kKMax;
     L.MT = (int8_t*)(smem + o);
     o += (size_t)nt * kMTStride;
@@ -153,6 +167,35 @@ __device__ __forceinline__ u64 sparse_child(const DevSystem& s, const Lds& L, co
     return block_sum64(h, L.wsum);
 }
 
+// The child whose canonical digits are in L.dg from `prev`, the row of the
+// child of the same parent whose digits are in L.dp: every neuron j whose
+// digit differs (nch of them, listed in L.chg) trades the row of M_Pi of its
+// old rule for that of its new one (Equation next-config: the two children
+// differ by exactly those rows), read from the int8 copy of M_Pi; the row's H
+// follows from H(M_k) the same way.  Written to out; returns H (block-wide).
+template <typename T>
+__device__ __forceinline__ u64 delta_child(const DevSystem& s, const Lds& L, const T* prev, T* out, u64 hprev,
+                                           int nch, bool& ovf) {
+    const int m = s.m;
+    if ((int)threadIdx.x < nch) {
+        const int j = L.chg[threadIdx.x];
+        L.k0[threadIdx.x] = rule_of(s, L, j, L.dp[j]);
+        L.k1[threadIdx.x] = rule_of(s, L, j, L.dg[j]);
+    }
+    __syncthreads();
+    for (int n = threadIdx.x; n < m; n += blockDim.x) {
+        long long v = (long long)prev[n];
+        for (int q = 0; q < nch; ++q)
+            v += (int)s.M8[(long long)L.k1[q] * m + n] - (int)s.M8[(long long)L.k0[q] * m + n];
+        ovf |= (v < 0) | (v > s.count_max);
+        out[n] = (T)v;
+    }
+    u64 h = hprev;
+    for (int q = 0; q < nch; ++q) h += s.hM[L.k1[q]] - s.hM[L.k0[q]];
+    __syncthreads();  // L.k0 / L.k1 (D's bytes) are read before D is cleared
+    return h;
+}
+
 }  // namespace
 
 size_t int8_lds(int m, int nt) { return int8_lds_bytes(m, nt); }
@@ -198,6 +241,10 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
     u64 place_k = 0, place_w = 0;
     u64 nmfma = 0;  // matrix-core instructions of this block (thread 0)
     u64 my_t = 0;   // thread r: child index t of row r of the tile
+    // the block's previous segment: parent, canonical index and stage row of
+    // its last child, and that row's H (its digits are in L.dp)
+    long long last_p = -1, last_row = 0;
+    u64 last_u = 0, last_h = 0;
 
     for (int tt = 0; tt < tiles_per_block; ++tt) {
     const long long b0 = (tile0 + tt) * kTile;
@@ -290,9 +337,24 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
         const int cend = c + len;
         if (tid == c) my_t = L.wsum[4];
 
-        // 5. reference child (first of the segment) by the sparse pull
+        // 5. reference child (first of the segment): from the previous
+        //    segment's last child when that is its predecessor in this parent
+        //    and few digits differ, else by the sparse pull
         T* refrow = stage + (b0 + c) * (long long)m;
-        const u64 href = sparse_child<T>(s, L, P, refrow, ovf);
+        int nch = kIncMax + 1;
+        if (p == last_p && ua == last_u + 1) {
+            if (tid == 0) L.sc[3] = 0;
+            __syncthreads();
+            for (int j = tid; j < m; j += blockDim.x)
+                if (L.dg[j] != L.dp[j]) {
+                    const int q = atomicAdd(&L.sc[3], 1);
+                    if (q < kIncMax) L.chg[q] = j;
+                }
+            __syncthreads();
+            nch = L.sc[3];
+        }
+        const u64 href = nch <= kIncMax ? delta_child<T>(s, L, stage + last_row * (long long)m, refrow, last_h, nch, ovf)
+                                        : sparse_child<T>(s, L, P, refrow, ovf);
         if (tid == 0) L.rowh[c] = href;
         if (len > 1) {
             // 6. D rows, row hashes and child indices (thread r: row r)
@@ -414,6 +476,12 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
             a.cpar[b0 + tid] = (int)p;
             a.ct[b0 + tid] = my_t;
         }
+        // the last child of this segment, for the next reference child
+        for (int j = tid; j < m; j += blockDim.x) L.dp[j] = L.dgb[j];
+        last_p = p;
+        last_u = ua + (u64)(len - 1);
+        last_row = b0 + cend - 1;
+        last_h = L.rowh[cend - 1];
         // next segment: the rest of this parent's canonical children, else the
         // next parent with one
         c = cend;
