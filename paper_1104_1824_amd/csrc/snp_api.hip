@@ -432,6 +432,7 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
     bool start_ext = io.c0_psi && S->slot_ready;
     if (start_ext) P = 1;
     long long halting_cap = -1;  // halting parents up to the cap's child's parent, counted in its pass
+    bool redo_staged = false;    // the last pass was keys-first and failed its row check
     for (;;) {
         u64 want = (u64)S->chunk_eff;
         if (io.limit_sem < kInf) {
@@ -474,20 +475,45 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         bool probed = false;
         const bool use_int8 = choose_int8(per_parent);
         stt.path_used = use_int8 ? SNP_PATH_INT8 : SNP_PATH_SPARSE;
-        if (use_int8) HIPCHK(snp::launch_expand_int8(S->elem_bytes, S->dsys, ca, S->stream));
-        else HIPCHK(snp::launch_expand_sparse(S->elem_bytes, S->dsys, ca, S->stream, &probed));
-        if ((st = mark(S, 2))) return st;
+        // keys-first: keys, probe and flags, then every row once (new rows
+        // straight to the row store), then the row check
+        const bool direct = use_int8 && !redo_staged && io.row2 == nullptr && !S->opt.stage_rows;
         snp::TableArgs ta{S->d_table, S->slots - 1, io.arena, S->d_stage, S->d_hash, S->d_slot, B, S->d_ctr,
-                          S->d_cand};
-        HIPCHK(snp::launch_insert(S->elem_bytes, S->m, ta, S->stream, !probed));
-        if ((st = mark(S, 3))) return st;
-        HIPCHK(snp::launch_flags(S->d_table, S->d_slot, B, S->d_ctr, S->d_flag, S->d_pos, S->d_fsums, S->d_fpre,
-                                 S->stream));
+                          S->d_cand, direct ? 1 : 0};
+        if (direct) {
+            ca.mode = 1;
+            HIPCHK(snp::launch_expand_int8(S->elem_bytes, S->dsys, ca, S->stream));
+            HIPCHK(snp::launch_insert(S->elem_bytes, S->m, ta, S->stream, true));
+            HIPCHK(snp::launch_flags(S->d_table, S->d_slot, B, S->d_ctr, S->d_flag, S->d_pos, S->d_fsums,
+                                     S->d_fpre, S->stream, true));
+            if ((st = mark(S, 1))) return st;
+            ca.mode = 2;
+            ca.flag = S->d_flag;
+            ca.pos = S->d_pos;
+            ca.tile_pre = S->d_fpre;
+            ca.arena = io.arena;
+            ca.arena_row = io.level_base + count;
+            ca.limit_new = limit - count;
+            HIPCHK(snp::launch_expand_int8(S->elem_bytes, S->dsys, ca, S->stream));
+            if ((st = mark(S, 2))) return st;
+            const snp::VerifyArgs va{S->d_table, S->d_slot, S->d_stage, io.arena, S->d_flag, S->d_pos, S->d_fpre,
+                                     io.level_base + count, limit - count, B, S->d_ctr};
+            HIPCHK(snp::launch_verify(S->elem_bytes, S->m, va, S->stream));
+            if ((st = mark(S, 3))) return st;
+        } else {
+            if (use_int8) HIPCHK(snp::launch_expand_int8(S->elem_bytes, S->dsys, ca, S->stream));
+            else HIPCHK(snp::launch_expand_sparse(S->elem_bytes, S->dsys, ca, S->stream, &probed));
+            if ((st = mark(S, 2))) return st;
+            HIPCHK(snp::launch_insert(S->elem_bytes, S->m, ta, S->stream, !probed));
+            if ((st = mark(S, 3))) return st;
+            HIPCHK(snp::launch_flags(S->d_table, S->d_slot, B, S->d_ctr, S->d_flag, S->d_pos, S->d_fsums,
+                                     S->d_fpre, S->stream));
+        }
         if ((st = mark(S, 4))) return st;
         snp::CommitArgs cm{S->d_table, S->d_table, S->d_slot, S->d_hash, S->d_pos, S->d_flag, S->d_fsums, S->d_fpre,
                            S->d_stage, S->d_cpar, S->d_ct, S->d_psif, B, io.arena, io.level_base, count, limit,
                            io.row2, io.par_out, io.par_out_base, io.par_value_base, io.t_out, S->d_row_slot,
-                           S->d_ctr, nullptr};
+                           S->d_ctr, nullptr, direct ? 0 : 1};
         // when this pass may fill the cap, count the halting parents (and the
         // children of the parents) up to the parent of the cap's child in the
         // same pass (no extra synchronisation): in the commit block that fills
@@ -509,6 +535,21 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
             if ((st = add_elapsed(S, 4, 5, &stt.ns_commit))) return st;
         }
         const snp::DevCounters c = *S->h_ctr;
+        if (c.probe_fail) return fail(SNP_ERR_DEVICE, "visited set: probe found no free slot");
+        if (direct && c.verify_fail) {
+            // a key named a configuration whose row differs: undo the pass
+            // (the entries of the rows it recorded become tombstones, like those
+            // of new children past the limit) and redo it with staged rows
+            const long long new_total = (long long)c.total;
+            const long long committed = std::min(new_total, limit - count);
+            S->tombs += new_total - committed;
+            if (committed > 0 && (st = rollback_level(S, io.level_base + count, committed))) return st;
+            if (ext) take_extension(c);
+            ++stt.redone;
+            redo_staged = true;
+            continue;
+        }
+        redo_staged = false;
         if (ext) take_extension(c);
         const long long Beff = (long long)c.beff;
         if (Beff > 0) ++stt.chunks;
@@ -520,7 +561,6 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         const long long avail = limit - count;
         const long long committed = std::min(new_total, avail);
         S->tombs += new_total - committed;  // new children past the limit became tombstones
-        if (c.probe_fail) return fail(SNP_ERR_DEVICE, "visited set: probe found no free slot");
         if (c.overflow) {
             if ((st = rollback_level(S, io.level_base, count + committed))) return st;
             *count_out = count;

@@ -28,6 +28,14 @@
 // The transposed M_V of a column tile is staged once and serves the segment's
 // four 64-row quarters, each a 4 x (NT / 64) grid of 16 x 16 products per wave.
 //
+// Keys-first passes run the kernel twice.  Mode 1 (keys) computes only every
+// child's key, parent and child index: the reference child's H is H(parent)
+// plus H(M_k) of the rules it fires, the others follow by linearity as above;
+// no row is built.  After the visited-set probe has named the new children,
+// mode 2 (rows) builds the rows and writes each new child's row straight to
+// its place in the row store, every other row to its stage row (where the row
+// check reads it).  Mode 0 writes every row to the stage.
+//
 // MFMA operand layout (checked on the device): lane l supplies row l % 16 of
 // A and column l % 16 of B, with the 16 int8 of lane group l / 16 covering
 // K columns 16 * (l / 16) .. + 15; the 16x16 int32 result lands in lane l as
@@ -60,6 +68,8 @@ struct Lds {
     int* vlist;    // [kVMax] neurons of V, most significant first
     int* kbase;    // [kVMax] first K column of every neuron of V
     u64* rowh;     // [kTile] H of every row of the tile
+    void** rowdst; // [kTile] mode 2: where every row of the tile goes (shares rowh's bytes: that
+                   // mode computes no H)
     u64* placev;   // [kVMax] place value (over omega) of every neuron of V
     u64* wsum;     // [5]: [0..3] block sums, [4] the reference child's index t
     int* sc;       // scalars: [0] jstar, [1] nv, [2] kvar, [3] changed digits
@@ -105,6 +115,7 @@ __device__ __forceinline__ Lds carve(unsigned char* smem, int m, int nt) {
     L.kbase = (int*)(smem + o);
     o += (size_t)kVMax * 4;
     L.rowh = (u64*)(smem + o);
+    L.rowdst = (void**)L.rowh;
     o += (size_t)kTile * 8;
     L.placev = (u64*)(smem + o);
     o += (size_t)kVMax * 8;
@@ -200,8 +211,9 @@ __device__ __forceinline__ u64 delta_child(const DevSystem& s, const Lds& L, con
 
 size_t int8_lds(int m, int nt) { return int8_lds_bytes(m, nt); }
 
-template <typename T, int NT>
+template <typename T, int NT, int MODE>
 __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, int tiles_per_block) {
+    constexpr bool KEYS = MODE == 1, ROWS = MODE == 2;
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int m = s.m;
@@ -241,15 +253,31 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
     u64 place_k = 0, place_w = 0;
     u64 nmfma = 0;  // matrix-core instructions of this block (thread 0)
     u64 my_t = 0;   // thread r: child index t of row r of the tile
-    // the block's previous segment: parent, canonical index and stage row of
-    // its last child, and that row's H (its digits are in L.dp)
-    long long last_p = -1, last_row = 0;
+    // the block's previous segment: parent, canonical index and row of its
+    // last child, and that row's H (its digits are in L.dp)
+    long long last_p = -1;
+    const T* last_row = nullptr;
     u64 last_u = 0, last_h = 0;
+    u64 hP = 0;  // mode 1: H of the parent in L.om / L.am
 
     for (int tt = 0; tt < tiles_per_block; ++tt) {
     const long long b0 = (tile0 + tt) * kTile;
     if (b0 >= Beff) break;
     const int rows = (int)min((long long)kTile, Beff - b0);
+    if constexpr (ROWS) {
+        // destinations of the tile's rows (the previous tile's are no longer read)
+        __syncthreads();
+        for (int r = tid; r < kTile; r += blockDim.x) {
+            const long long b = b0 + r;
+            T* d = stage + b * (long long)m;
+            if (b < Beff && a.flag[b]) {
+                const long long q = (long long)a.tile_pre[b / kScanTile] + a.pos[b];
+                if (q < a.limit_new) d = (T*)a.arena + (a.arena_row + q) * (long long)m;
+            }
+            L.rowdst[r] = d;
+        }
+        __syncthreads();
+    }
     int c = 0;
     while (c < rows) {
         const u64 psi_p = a.psi[p];
@@ -265,6 +293,11 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
                 L.om[j] = (uint8_t)w;
             }
             have_p = p;
+            if constexpr (KEYS) {
+                u64 hp = 0;
+                for (int j = tid; j < m; j += blockDim.x) hp += hterm((uint32_t)P[j], s.R[j]);
+                hP = block_sum64(hp, L.wsum);
+            }
             __syncthreads();
             if (wid == 0) {
                 place_k = canon_place(m, lane, L.om, L.am);
@@ -339,26 +372,36 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
 
         // 5. reference child (first of the segment): from the previous
         //    segment's last child when that is its predecessor in this parent
-        //    and few digits differ, else by the sparse pull
-        T* refrow = stage + (b0 + c) * (long long)m;
-        int nch = kIncMax + 1;
-        if (p == last_p && ua == last_u + 1) {
-            if (tid == 0) L.sc[3] = 0;
-            __syncthreads();
+        //    and few digits differ, else by the sparse pull; mode 1 takes only
+        //    its H
+        T* refrow = ROWS ? (T*)L.rowdst[c] : stage + (b0 + c) * (long long)m;
+        u64 href = 0;
+        if constexpr (KEYS) {
+            u64 hs = 0;
             for (int j = tid; j < m; j += blockDim.x)
-                if (L.dg[j] != L.dp[j]) {
-                    const int q = atomicAdd(&L.sc[3], 1);
-                    if (q < kIncMax) L.chg[q] = j;
-                }
-            __syncthreads();
-            nch = L.sc[3];
+                if (L.om[j]) hs += s.hM[rule_of(s, L, j, L.dg[j])];
+            href = hP + block_sum64(hs, L.wsum);
+        } else {
+            int nch = kIncMax + 1;
+            if (p == last_p && ua == last_u + 1) {
+                if (tid == 0) L.sc[3] = 0;
+                __syncthreads();
+                for (int j = tid; j < m; j += blockDim.x)
+                    if (L.dg[j] != L.dp[j]) {
+                        const int q = atomicAdd(&L.sc[3], 1);
+                        if (q < kIncMax) L.chg[q] = j;
+                    }
+                __syncthreads();
+                nch = L.sc[3];
+            }
+            href = nch <= kIncMax ? delta_child<T>(s, L, last_row, refrow, last_h, nch, ovf)
+                                  : sparse_child<T>(s, L, P, refrow, ovf);
         }
-        const u64 href = nch <= kIncMax ? delta_child<T>(s, L, stage + last_row * (long long)m, refrow, last_h, nch, ovf)
-                                        : sparse_child<T>(s, L, P, refrow, ovf);
-        if (tid == 0) L.rowh[c] = href;
+        if (!ROWS && tid == 0) L.rowh[c] = href;
         if (len > 1) {
             // 6. D rows, row hashes and child indices (thread r: row r)
-            for (int q = tid; q < kTile * kKMax / 16; q += blockDim.x) ((int4*)L.D)[q] = make_int4(0, 0, 0, 0);
+            if constexpr (!KEYS)
+                for (int q = tid; q < kTile * kKMax / 16; q += blockDim.x) ((int4*)L.D)[q] = make_int4(0, 0, 0, 0);
             const u64 t_c = L.wsum[4];
             __syncthreads();
             if (tid > c && tid < cend) {
@@ -374,95 +417,103 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
                     delta = x / w;
                     if (e1 != e0) {
                         const int k1 = L.kbase[i] + e1, k0 = L.kbase[i] + e0;
-                        L.D[row * kKMax + k1] = 1;
-                        L.D[row * kKMax + k0] = -1;
-                        h += s.hM[L.klist[k1]] - s.hM[L.klist[k0]];
-                        const int om = L.om[j];
-                        tr += (u64)(long long)(canon_digit(L.am[j], om, e1) - canon_digit(L.am[j], om, e0)) *
-                              L.placev[i];
+                        if constexpr (!KEYS) {
+                            L.D[row * kKMax + k1] = 1;
+                            L.D[row * kKMax + k0] = -1;
+                        }
+                        if constexpr (!ROWS) {
+                            h += s.hM[L.klist[k1]] - s.hM[L.klist[k0]];
+                            const int om = L.om[j];
+                            tr += (u64)(long long)(canon_digit(L.am[j], om, e1) - canon_digit(L.am[j], om, e0)) *
+                                  L.placev[i];
+                        }
                     }
                 }
-                L.rowh[row] = h;
-                my_t = tr;
+                if constexpr (!ROWS) {
+                    L.rowh[row] = h;
+                    my_t = tr;
+                }
             }
-            // quarters of 64 rows that hold rows c + 1 .. cend - 1
-            const int q0 = (c + 1) >> 6, q1 = (cend - 1) >> 6;
-            // instructions this segment issues: (m / NT) column tiles x 4 waves x
-            // quarters x 4 row blocks x NT / 64 column blocks
-            if (tid == 0) nmfma += (u64)((m + NT - 1) / NT) * 4 * (q1 - q0 + 1) * 4 * (NT / 64);
-            // 7. column tiles: stage M_V transposed, then every quarter's product
-            //    plus the reference row.  Only the kvar live rule columns are
-            //    staged: D is 0 in every later column, so whatever MT holds there
-            //    adds nothing.  With m a multiple of 16 a rule's slice of the tile
-            //    is read as 16-byte vectors.
-            for (int n0 = 0; n0 < m; n0 += NT) {
-                __syncthreads();
-                if ((m & 15) == 0) {
-                    constexpr int G = NT / 16;
-                    for (int q = tid; q < kvar * G; q += blockDim.x) {
-                        const int k = q / G, n = 16 * (q - k * G);
-                        if (n0 + n >= m) continue;
-                        const int4 v = *(const int4*)&s.M8[(long long)L.klist[k] * m + n0 + n];
-                        const int8_t* b = (const int8_t*)&v;
-#pragma unroll
-                        for (int i = 0; i < 16; ++i) L.MT[(n + i) * kMTStride + k] = b[i];
+            if constexpr (!KEYS) {
+                // quarters of 64 rows that hold rows c + 1 .. cend - 1
+                const int q0 = (c + 1) >> 6, q1 = (cend - 1) >> 6;
+                // instructions this segment issues: (m / NT) column tiles x 4 waves x
+                // quarters x 4 row blocks x NT / 64 column blocks
+                if (tid == 0) nmfma += (u64)((m + NT - 1) / NT) * 4 * (q1 - q0 + 1) * 4 * (NT / 64);
+                // 7. column tiles: stage M_V transposed, then every quarter's product
+                //    plus the reference row.  Only the kvar live rule columns are
+                //    staged: D is 0 in every later column, so whatever MT holds there
+                //    adds nothing.  With m a multiple of 16 a rule's slice of the tile
+                //    is read as 16-byte vectors.
+                for (int n0 = 0; n0 < m; n0 += NT) {
+                    __syncthreads();
+                    if ((m & 15) == 0) {
+                        constexpr int G = NT / 16;
+                        for (int q = tid; q < kvar * G; q += blockDim.x) {
+                            const int k = q / G, n = 16 * (q - k * G);
+                            if (n0 + n >= m) continue;
+                            const int4 v = *(const int4*)&s.M8[(long long)L.klist[k] * m + n0 + n];
+                            const int8_t* b = (const int8_t*)&v;
+    #pragma unroll
+                            for (int i = 0; i < 16; ++i) L.MT[(n + i) * kMTStride + k] = b[i];
+                        }
+                    } else {
+                        for (int q = tid; q < kvar * NT; q += blockDim.x) {
+                            const int k = q / NT, n = q - k * NT;
+                            if (n0 + n < m) L.MT[n * kMTStride + k] = s.M8[(long long)L.klist[k] * m + n0 + n];
+                        }
                     }
-                } else {
-                    for (int q = tid; q < kvar * NT; q += blockDim.x) {
-                        const int k = q / NT, n = q - k * NT;
-                        if (n0 + n < m) L.MT[n * kMTStride + k] = s.M8[(long long)L.klist[k] * m + n0 + n];
+                    __syncthreads();
+                    // The product is taken transposed, (D . M_V)^T = M_V^T . D^T: the
+                    // staged MT is the A operand and the D rows the B operand, so lane
+                    // l ends with child row l % 16 of its 16-row block at the four
+                    // consecutive columns 4 (l / 16) .. + 3 of each 16-column block,
+                    // stored as one vector.
+                    constexpr int CB = NT / 64;  // 16-column blocks per wave
+                    const int colw = wid * (NT / 4);
+                    const bool vec = (m & 3) == 0;  // rows and 4-column groups aligned for vector access
+                    v4i af[CB];
+                    int refv[CB][4];
+    #pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) {
+                        af[cb] = *(const v4i*)&L.MT[(colw + 16 * cb + (lane & 15)) * kMTStride + 16 * (lane >> 4)];
+                        const int col0 = n0 + colw + 16 * cb + 4 * (lane >> 4);
+    #pragma unroll
+                        for (int i = 0; i < 4; ++i) refv[cb][i] = col0 + i < m ? (int)refrow[col0 + i] : 0;
                     }
-                }
-                __syncthreads();
-                // The product is taken transposed, (D . M_V)^T = M_V^T . D^T: the
-                // staged MT is the A operand and the D rows the B operand, so lane
-                // l ends with child row l % 16 of its 16-row block at the four
-                // consecutive columns 4 (l / 16) .. + 3 of each 16-column block,
-                // stored as one vector.
-                constexpr int CB = NT / 64;  // 16-column blocks per wave
-                const int colw = wid * (NT / 4);
-                const bool vec = (m & 3) == 0;  // rows and 4-column groups aligned for vector access
-                v4i af[CB];
-                int refv[CB][4];
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb) {
-                    af[cb] = *(const v4i*)&L.MT[(colw + 16 * cb + (lane & 15)) * kMTStride + 16 * (lane >> 4)];
-                    const int col0 = n0 + colw + 16 * cb + 4 * (lane >> 4);
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) refv[cb][i] = col0 + i < m ? (int)refrow[col0 + i] : 0;
-                }
-                for (int qr = q0; qr <= q1; ++qr) {
-#pragma unroll
-                    for (int rb = 0; rb < 4; ++rb) {
-                        const int row = 64 * qr + 16 * rb + (lane & 15);
-                        const v4i bf = *(const v4i*)&L.D[row * kKMax + 16 * (lane >> 4)];
-                        v4i acc[CB];
-#pragma unroll
-                        for (int cb = 0; cb < CB; ++cb)
-                            acc[cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[cb], bf, v4i{0, 0, 0, 0}, 0, 0, 0);
-                        if (row <= c || row >= cend) continue;
-                        T* out = stage + (b0 + row) * (long long)m;
-#pragma unroll
-                        for (int cb = 0; cb < CB; ++cb) {
-                            const int col0 = n0 + colw + 16 * cb + 4 * (lane >> 4);
-                            long long v[4];
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) {
-                                v[i] = (long long)refv[cb][i] + acc[cb][i];
-                                ovf |= (col0 + i < m) & ((v[i] < 0) | (v[i] > s.count_max));
-                            }
-                            if (vec && col0 + 3 < m) {
-                                if constexpr (sizeof(T) == 4) {
-                                    *(int4*)(out + col0) = make_int4((int)v[0], (int)v[1], (int)v[2], (int)v[3]);
-                                } else {
-                                    const uint2 pk = make_uint2((uint32_t)(uint16_t)v[0] | ((uint32_t)(uint16_t)v[1] << 16),
-                                                                (uint32_t)(uint16_t)v[2] | ((uint32_t)(uint16_t)v[3] << 16));
-                                    *(uint2*)(out + col0) = pk;
+                    for (int qr = q0; qr <= q1; ++qr) {
+    #pragma unroll
+                        for (int rb = 0; rb < 4; ++rb) {
+                            const int row = 64 * qr + 16 * rb + (lane & 15);
+                            const v4i bf = *(const v4i*)&L.D[row * kKMax + 16 * (lane >> 4)];
+                            v4i acc[CB];
+    #pragma unroll
+                            for (int cb = 0; cb < CB; ++cb)
+                                acc[cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[cb], bf, v4i{0, 0, 0, 0}, 0, 0, 0);
+                            if (row <= c || row >= cend) continue;
+                            T* out = ROWS ? (T*)L.rowdst[row] : stage + (b0 + row) * (long long)m;
+    #pragma unroll
+                            for (int cb = 0; cb < CB; ++cb) {
+                                const int col0 = n0 + colw + 16 * cb + 4 * (lane >> 4);
+                                long long v[4];
+    #pragma unroll
+                                for (int i = 0; i < 4; ++i) {
+                                    v[i] = (long long)refv[cb][i] + acc[cb][i];
+                                    ovf |= (col0 + i < m) & ((v[i] < 0) | (v[i] > s.count_max));
                                 }
-                            } else {
-#pragma unroll
-                                for (int i = 0; i < 4; ++i)
-                                    if (col0 + i < m) out[col0 + i] = (T)v[i];
+                                if (vec && col0 + 3 < m) {
+                                    if constexpr (sizeof(T) == 4) {
+                                        *(int4*)(out + col0) = make_int4((int)v[0], (int)v[1], (int)v[2], (int)v[3]);
+                                    } else {
+                                        const uint2 pk = make_uint2((uint32_t)(uint16_t)v[0] | ((uint32_t)(uint16_t)v[1] << 16),
+                                                                    (uint32_t)(uint16_t)v[2] | ((uint32_t)(uint16_t)v[3] << 16));
+                                        *(uint2*)(out + col0) = pk;
+                                    }
+                                } else {
+    #pragma unroll
+                                    for (int i = 0; i < 4; ++i)
+                                        if (col0 + i < m) out[col0 + i] = (T)v[i];
+                                }
                             }
                         }
                     }
@@ -470,18 +521,20 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
             }
         }
         __syncthreads();
-        // 8. per-row outputs of the segment
-        if (tid >= c && tid < cend) {
+        // 8. per-row outputs of the segment (mode 2: written by mode 1)
+        if (!ROWS && tid >= c && tid < cend) {
             a.hash[b0 + tid] = fmix64(L.rowh[tid]) & a.hash_mask;
             a.cpar[b0 + tid] = (int)p;
             a.ct[b0 + tid] = my_t;
         }
         // the last child of this segment, for the next reference child
-        for (int j = tid; j < m; j += blockDim.x) L.dp[j] = L.dgb[j];
+        if constexpr (!KEYS) {
+            for (int j = tid; j < m; j += blockDim.x) L.dp[j] = L.dgb[j];
+            last_row = ROWS ? (const T*)L.rowdst[cend - 1] : stage + (b0 + cend - 1) * (long long)m;
+            last_h = ROWS ? 0 : L.rowh[cend - 1];
+        }
         last_p = p;
         last_u = ua + (u64)(len - 1);
-        last_row = b0 + cend - 1;
-        last_h = L.rowh[cend - 1];
         // next segment: the rest of this parent's canonical children, else the
         // next parent with one
         c = cend;
@@ -513,14 +566,21 @@ hipError_t launch_expand_int8(int elem_bytes, const DevSystem& s, const ChunkArg
     const int tpb = a.tiles > 0 ? std::min(a.tiles, 64)
                                 : (int)std::max<long long>(1, std::min<long long>(16, tiles / (4 * resident)));
     const unsigned blocks = (unsigned)((tiles + tpb - 1) / tpb);
-#define SNP_I8(TT, NN) hipLaunchKernelGGL((k_expand_int8<TT, NN>), dim3(blocks), dim3(256), lds, st, s, a, tpb)
+#define SNP_I8(TT, NN, MM) hipLaunchKernelGGL((k_expand_int8<TT, NN, MM>), dim3(blocks), dim3(256), lds, st, s, a, tpb)
+#define SNP_I8M(TT, NN)                   \
+    do {                                  \
+        if (a.mode == 1) SNP_I8(TT, NN, 1); \
+        else if (a.mode == 2) SNP_I8(TT, NN, 2); \
+        else SNP_I8(TT, NN, 0);           \
+    } while (0)
     if (elem_bytes == 4) {
-        if (wide) SNP_I8(int32_t, 128);
-        else SNP_I8(int32_t, 64);
+        if (wide) SNP_I8M(int32_t, 128);
+        else SNP_I8M(int32_t, 64);
     } else {
-        if (wide) SNP_I8(uint16_t, 128);
-        else SNP_I8(uint16_t, 64);
+        if (wide) SNP_I8M(uint16_t, 128);
+        else SNP_I8M(uint16_t, 64);
     }
+#undef SNP_I8M
 #undef SNP_I8
     return hipGetLastError();
 }

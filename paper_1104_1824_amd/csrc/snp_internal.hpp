@@ -21,6 +21,8 @@ constexpr uint32_t kStageBase = 0x80000000u;
 constexpr uint32_t kMaxChunk = 1u << 30;
 constexpr u64 kEmpty = ~0ULL;           // never a valid entry (reference 0xFFFFFFFF)
 constexpr u64 kTomb = ~0ULL - 1;        // removed entry (reference 0xFFFFFFFE); never reused
+// Children per tile of the chunk-wide scans (new-child flags, offsets).
+constexpr int kScanTile = 1024;
 
 // Device counters one expansion pass reads back in a single copy.
 struct DevCounters {
@@ -46,6 +48,8 @@ struct DevCounters {
     u64 tend;          // canonical children the chunks may take: the prefix's, or fewer where
                        // the child budget ends (the budget's clip)
     u64 bud_par;       // budget clip: parent of the last child within the budget, + 1 (0: none)
+    u64 verify_fail;   // keys-first pass: a child taken for a repeat (its key met an entry) has a
+                       // row that differs from that entry's; the pass is redone with staged rows
 };
 
 // Device-side description of a loaded system.
@@ -107,6 +111,19 @@ struct ChunkArgs {
     u64 slot_mask;
     uint32_t* slot;        // [B]
     uint32_t* cand;        // [B]
+    // Keys-first passes of the int8 form.  mode 0 stages every child's row
+    // (then probe, row compares, commit copy); mode 1 computes keys, parents and
+    // child indices only; mode 2 computes the rows once the new children are
+    // known: new child b with prefix q = tile_pre[b / kScanTile] + pos[b] below
+    // limit_new goes to row arena_row + q of the row store, every other child
+    // to its stage row.
+    int mode;
+    const uint32_t* flag;
+    const uint32_t* pos;
+    const uint32_t* tile_pre;
+    void* arena;
+    long long arena_row;
+    long long limit_new;
 };
 
 // Insert/commit arguments.
@@ -120,6 +137,24 @@ struct TableArgs {
     long long B;
     DevCounters* ctr;
     uint32_t* cand;        // [B] children waiting for a row compare
+    int direct;            // keys-first pass: an entry with the child's tag is taken as its
+                           // configuration (the earliest child keeps an entry of the chunk);
+                           // no row compare (the rows are checked after the row pass)
+};
+
+// Row check of a keys-first pass: rows and destinations as in ChunkArgs mode 2.
+struct VerifyArgs {
+    const u64* table;
+    const uint32_t* slot;
+    const void* stage;
+    const void* arena;
+    const uint32_t* flag;
+    const uint32_t* pos;
+    const uint32_t* tile_pre;
+    long long arena_row;
+    long long limit_new;
+    long long B;
+    DevCounters* ctr;
 };
 
 struct CommitArgs {
@@ -150,6 +185,7 @@ struct CommitArgs {
     const uint8_t* hflag;  // nullable halting flags of the frontier: the block that fills the
                            // cap counts them up to the cap child's parent into ctr->count, and
                            // sums psif before that parent into ctr->capf_lo / capf_hi
+    int copy;              // 1: copy the new rows from the stage; 0: they are in place (keys-first)
 };
 
 // Deterministic batched run: one system per workgroup.
@@ -230,8 +266,10 @@ hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkA
                                 bool* probed);
 // probe false: the children were probed by the expansion; only the row compares run
 hipError_t launch_insert(int elem_bytes, int m, const TableArgs& a, hipStream_t st, bool probe);
+// scan: always fill tile_pre (else only past kCommitTiles tiles, the commit summing them itself)
 hipError_t launch_flags(const u64* table, const uint32_t* slot, long long B, DevCounters* ctr, uint32_t* flag,
-                        uint32_t* pos, uint32_t* tile_sums, uint32_t* tile_pre, hipStream_t st);
+                        uint32_t* pos, uint32_t* tile_sums, uint32_t* tile_pre, hipStream_t st, bool scan = false);
+hipError_t launch_verify(int elem_bytes, int m, const VerifyArgs& a, hipStream_t st);
 hipError_t launch_commit(int elem_bytes, int m, const CommitArgs& a, hipStream_t st);
 hipError_t launch_fill_u64(u64* p, long long n, u64 v, hipStream_t st);
 hipError_t launch_start_walk(int elem_bytes, int m, const u64* R, u64* table, u64 slot_mask, const void* c0,

@@ -376,7 +376,6 @@ __device__ __forceinline__ V vadd(V a, V b) {
     else return a + b;
 }
 
-constexpr int kScanTile = 1024;
 
 template <typename V, bool SAT>
 __global__ __launch_bounds__(256) void k_scan_tiles(const V* __restrict__ in, V* __restrict__ out,
@@ -1363,6 +1362,10 @@ hipError_t launch_expand_sparse(int elem_bytes, const DevSystem& s, const ChunkA
 //     with atomicMin (the entry ends at the first occurrence in canonical
 //     order); if different, keep probing (lane 0 drives, compares stay
 //     cooperative) until an empty slot or an equal row.
+// A keys-first pass (TableArgs::direct) has no rows yet: pass A takes the
+// entry with the child's tag as the child's configuration and lowers an entry
+// of the chunk to the earliest child with atomicMin at once; k_verify_rows
+// checks those rows after the row pass.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ const T* entry_row(const TableArgs& a, uint32_t ref, int m) {
@@ -1392,7 +1395,12 @@ __global__ __launch_bounds__(256) void k_insert_probe(int m, TableArgs a) {
                 e = old;
             }
             if (e != kTomb && (uint32_t)(e >> 32) == tag) {
-                queue = true;
+                // (an entry of the row store has a smaller reference than any child)
+                if (a.direct) {
+                    if (mine < e) atomicMin(&a.table[sl], mine);
+                } else {
+                    queue = true;
+                }
                 placed = true;
                 break;
             }
@@ -1466,10 +1474,10 @@ hipError_t launch_insert(int elem_bytes, int m, const TableArgs& a, hipStream_t 
     const unsigned cblocks = (unsigned)std::min<long long>((a.B + 3) / 4, 4096);
     if (elem_bytes == 4) {
         if (probe) hipLaunchKernelGGL(k_insert_probe<int32_t>, dim3(blocks), dim3(256), 0, st, m, a);
-        hipLaunchKernelGGL(k_insert_compare<int32_t>, dim3(cblocks), dim3(256), 0, st, m, a);
+        if (!a.direct) hipLaunchKernelGGL(k_insert_compare<int32_t>, dim3(cblocks), dim3(256), 0, st, m, a);
     } else {
         if (probe) hipLaunchKernelGGL(k_insert_probe<uint16_t>, dim3(blocks), dim3(256), 0, st, m, a);
-        hipLaunchKernelGGL(k_insert_compare<uint16_t>, dim3(cblocks), dim3(256), 0, st, m, a);
+        if (!a.direct) hipLaunchKernelGGL(k_insert_compare<uint16_t>, dim3(cblocks), dim3(256), 0, st, m, a);
     }
     return hipGetLastError();
 }
@@ -1519,12 +1527,12 @@ __global__ __launch_bounds__(256) void k_flag_tiles(const u64* __restrict__ tabl
 }
 
 hipError_t launch_flags(const u64* table, const uint32_t* slot, long long B, DevCounters* ctr, uint32_t* flag,
-                        uint32_t* pos, uint32_t* tile_sums, uint32_t* tile_pre, hipStream_t st) {
+                        uint32_t* pos, uint32_t* tile_sums, uint32_t* tile_pre, hipStream_t st, bool scan) {
     if (B <= 0) return hipSuccess;
     const long long nt = scan_tiles(B);
     hipLaunchKernelGGL(k_flag_tiles, dim3((unsigned)nt), dim3(256), 0, st, table, slot, B, ctr, flag, pos,
                        tile_sums);
-    if (nt > kCommitTiles)  // the commit reads the tile prefix (and the host the total) from here
+    if (scan || nt > kCommitTiles)  // the commit reads the tile prefix (and the host the total) from here
         hipLaunchKernelGGL((k_scan_sums<uint32_t, false>), dim3(1), dim3(1024), 0, st, tile_sums, tile_pre, nt,
                            (u64*)&ctr->total, nullptr, nullptr);
     return hipGetLastError();
@@ -1644,7 +1652,7 @@ __global__ __launch_bounds__(256) void k_commit(int upr /* units per row */, Com
         }
     }
     const long long first_local = a.level_count + (long long)p0;
-    const int ncopy = (int)max(0LL, min((long long)nnew, a.limit - first_local));
+    const int ncopy = a.copy ? (int)max(0LL, min((long long)nnew, a.limit - first_local)) : 0;
     const U* __restrict__ src = (const U*)a.stage + b0 * upr;
     U* __restrict__ dst = (U*)a.arena + (a.level_base + first_local) * upr;
     U* __restrict__ dst2 = a.row2 ? (U*)a.row2 + first_local * upr : nullptr;
@@ -1714,10 +1722,66 @@ __global__ __launch_bounds__(256) void k_commit(int upr /* units per row */, Com
     }
 }
 
+// Row check of a keys-first pass.  Every child that is not the first occurrence
+// of its key (its entry names another child of the chunk, or a row of the row
+// store) had its row written to its stage row by the row pass; it must equal
+// the row its entry names: a row-store row, or the first occurrence's row
+// where the row pass put it (the row store for a new child within the limit,
+// else its stage row).  A wave takes 64 children and compares the rows of its
+// repeats with all lanes; any difference sets ctr->verify_fail.
+__device__ __forceinline__ long long new_child_dest(const VerifyArgs& a, long long b) {
+    if (!a.flag[b]) return -1;
+    const long long q = (long long)a.tile_pre[b / kScanTile] + a.pos[b];
+    return q < a.limit_new ? a.arena_row + q : -1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_verify_rows(int m, VerifyArgs a) {
+    const int lane = threadIdx.x & 63;
+    const long long beff = min(a.B, (long long)a.ctr->beff);
+    const long long base = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
+    const long long b = base + lane;
+    bool rep = false;
+    uint32_t ref = 0;
+    if (b < beff) {
+        ref = (uint32_t)a.table[a.slot[b]];
+        rep = ref != kStageBase + (uint32_t)b;
+    }
+    u64 rm = __ballot(rep);
+    bool bad = false;
+    while (rm) {
+        const int l = __ffsll((long long)rm) - 1;
+        rm &= rm - 1;
+        const uint32_t r = (uint32_t)__shfl((int)ref, l);
+        const T* mine = (const T*)a.stage + (base + l) * (long long)m;
+        const T* other;
+        if (r < kStageBase) {
+            other = (const T*)a.arena + (long long)r * m;
+        } else {
+            const long long o = (long long)(r - kStageBase);
+            const long long d = new_child_dest(a, o);
+            other = d >= 0 ? (const T*)a.arena + d * m : (const T*)a.stage + o * m;
+        }
+        bool diff = false;
+        for (int j = lane; j < m; j += 64) diff |= mine[j] != other[j];
+        bad |= __any(diff);
+    }
+    if (bad && lane == 0) atomicOr((unsigned long long*)&a.ctr->verify_fail, 1ULL);
+}
+
+hipError_t launch_verify(int elem_bytes, int m, const VerifyArgs& a, hipStream_t st) {
+    if (a.B <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((a.B + 255) / 256);
+    if (elem_bytes == 4) hipLaunchKernelGGL(k_verify_rows<int32_t>, dim3(blocks), dim3(256), 0, st, m, a);
+    else hipLaunchKernelGGL(k_verify_rows<uint16_t>, dim3(blocks), dim3(256), 0, st, m, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_commit(int elem_bytes, int m, const CommitArgs& a_in, hipStream_t st) {
     if (a_in.B <= 0) return hipSuccess;
     CommitArgs a = a_in;
-    if (scan_tiles(a.B) <= kCommitTiles) a.tile_pre = nullptr;  // the blocks sum the tile counts themselves
+    // the blocks sum the tile counts themselves (unless the flags' scan was forced)
+    if (scan_tiles(a.B) <= kCommitTiles && a.copy) a.tile_pre = nullptr;
     const size_t rb = (size_t)m * elem_bytes;
     const uintptr_t al = (uintptr_t)a.stage | (uintptr_t)a.arena | (uintptr_t)a.row2;
     const unsigned blocks = (unsigned)((a.B + 255) / 256);
