@@ -265,19 +265,26 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
     if (b0 >= Beff) break;
     const int rows = (int)min((long long)kTile, Beff - b0);
     if constexpr (ROWS) {
-        // destinations of the tile's rows (the previous tile's are no longer read)
+        // destinations of the tile's rows (the previous tile's are no longer
+        // read).  A child with q new children before it in the chunk and
+        // q >= limit_new comes after the child that filled the level's limit:
+        // its row is never read (a repeat is of an earlier child), so it is not
+        // built; those children end the chunk, so the block stops at the first.
         __syncthreads();
         for (int r = tid; r < kTile; r += blockDim.x) {
             const long long b = b0 + r;
-            T* d = stage + b * (long long)m;
-            if (b < Beff && a.flag[b]) {
+            T* d = nullptr;
+            if (b < Beff) {
                 const long long q = (long long)a.tile_pre[b / kScanTile] + a.pos[b];
-                if (q < a.limit_new) d = (T*)a.arena + (a.arena_row + q) * (long long)m;
+                if (q < a.limit_new)
+                    d = a.flag[b] ? (T*)a.arena + (a.arena_row + q) * (long long)m : stage + b * (long long)m;
             }
             L.rowdst[r] = d;
         }
         __syncthreads();
+        if (!L.rowdst[0]) break;
     }
+    bool past = false;  // mode 2: the rest of the chunk lies past the level's limit
     int c = 0;
     while (c < rows) {
         const u64 psi_p = a.psi[p];
@@ -369,6 +376,12 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
         }
         const int cend = c + len;
         if (tid == c) my_t = L.wsum[4];
+        if constexpr (ROWS) {
+            if (!L.rowdst[c]) {
+                past = true;
+                break;
+            }
+        }
 
         // 5. reference child (first of the segment): from the previous
         //    segment's last child when that is its predecessor in this parent
@@ -492,6 +505,7 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
                                 acc[cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[cb], bf, v4i{0, 0, 0, 0}, 0, 0, 0);
                             if (row <= c || row >= cend) continue;
                             T* out = ROWS ? (T*)L.rowdst[row] : stage + (b0 + row) * (long long)m;
+                            if (ROWS && !out) continue;
     #pragma unroll
                             for (int cb = 0; cb < CB; ++cb) {
                                 const int col0 = n0 + colw + 16 * cb + 4 * (lane >> 4);
@@ -547,7 +561,7 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
         __syncthreads();
         if (c < rows && p >= a.n) break;  // unreachable while g0 + B <= sum of Psi
     }
-    if (p >= a.n) break;
+    if (p >= a.n || past) break;
     }
     if (__syncthreads_or(ovf) && tid == 0) atomicOr((unsigned long long*)&a.ctr->overflow, 1ULL);
     if (tid == 0 && nmfma) atomicAdd((unsigned long long*)&a.ctr->mfma, nmfma);

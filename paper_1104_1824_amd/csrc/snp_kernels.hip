@@ -1743,7 +1743,9 @@ __global__ __launch_bounds__(256) void k_verify_rows(int m, VerifyArgs a) {
     const long long b = base + lane;
     bool rep = false;
     uint32_t ref = 0;
-    if (b < beff) {
+    // (a child after the one that filled the level's limit is not recorded,
+    // whatever it repeats: its row was not built)
+    if (b < beff && (long long)a.tile_pre[b / kScanTile] + a.pos[b] < a.limit_new) {
         ref = (uint32_t)a.table[a.slot[b]];
         rep = ref != kStageBase + (uint32_t)b;
     }
