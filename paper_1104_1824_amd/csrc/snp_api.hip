@@ -481,9 +481,8 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         snp::TableArgs ta{S->d_table, S->slots - 1, io.arena, S->d_stage, S->d_hash, S->d_slot, B, S->d_ctr,
                           S->d_cand, direct ? 1 : 0};
         if (direct) {
-            ca.mode = 1;
+            ca.mode = 1;  // keys, each probed in the visited set by the kernel itself
             HIPCHK(snp::launch_expand_int8(S->elem_bytes, S->dsys, ca, S->stream));
-            HIPCHK(snp::launch_insert(S->elem_bytes, S->m, ta, S->stream, true));
             HIPCHK(snp::launch_flags(S->d_table, S->d_slot, B, S->d_ctr, S->d_flag, S->d_pos, S->d_fsums,
                                      S->d_fpre, S->stream, true));
             if ((st = mark(S, 1))) return st;

@@ -535,11 +535,43 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
             }
         }
         __syncthreads();
-        // 8. per-row outputs of the segment (mode 2: written by mode 1)
+        // 8. per-row outputs of the segment (mode 2: written by mode 1).  Mode
+        //    1 also probes the visited set with each key as a keys-first probe
+        //    does: claim an empty slot, or take an entry with the key's tag as
+        //    the child's configuration, the earliest child of the chunk keeping
+        //    an entry of the chunk (the row check settles it later).
         if (!ROWS && tid >= c && tid < cend) {
-            a.hash[b0 + tid] = fmix64(L.rowh[tid]) & a.hash_mask;
-            a.cpar[b0 + tid] = (int)p;
-            a.ct[b0 + tid] = my_t;
+            const long long b = b0 + tid;
+            const u64 key = fmix64(L.rowh[tid]) & a.hash_mask;
+            a.hash[b] = key;
+            a.cpar[b] = (int)p;
+            a.ct[b] = my_t;
+            if (KEYS && a.table) {
+                const uint32_t tag = (uint32_t)(key >> 32);
+                const u64 mine = ((u64)tag << 32) | (kStageBase + (uint32_t)b);
+                u64 sl = key & a.slot_mask;
+                bool placed = false;
+                for (u64 it = 0; it <= a.slot_mask; ++it) {
+                    u64 e = __hip_atomic_load(&a.table[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (e == kEmpty) {
+                        const u64 old = atomicCAS(&a.table[sl], kEmpty, mine);
+                        if (old == kEmpty) {
+                            placed = true;
+                            break;
+                        }
+                        e = old;
+                    }
+                    if (e != kTomb && (uint32_t)(e >> 32) == tag) {
+                        // (an entry of the row store has a smaller reference than any child)
+                        if (mine < e) atomicMin(&a.table[sl], mine);
+                        placed = true;
+                        break;
+                    }
+                    sl = (sl + 1) & a.slot_mask;
+                }
+                a.slot[b] = placed ? (uint32_t)sl : 0u;
+                if (!placed) atomicOr((unsigned long long*)&a.ctr->probe_fail, 1ULL);
+            }
         }
         // the last child of this segment, for the next reference child
         if constexpr (!KEYS) {

@@ -1745,9 +1745,10 @@ __global__ __launch_bounds__(256) void k_verify_rows(int m, VerifyArgs a) {
     uint32_t ref = 0;
     // (a child after the one that filled the level's limit is not recorded,
     // whatever it repeats: its row was not built)
-    if (b < beff && (long long)a.tile_pre[b / kScanTile] + a.pos[b] < a.limit_new) {
+    // (the flags name the children that own their entry; only the others read it)
+    if (b < beff && !a.flag[b] && (long long)a.tile_pre[b / kScanTile] + a.pos[b] < a.limit_new) {
         ref = (uint32_t)a.table[a.slot[b]];
-        rep = ref != kStageBase + (uint32_t)b;
+        rep = true;
     }
     u64 rm = __ballot(rep);
     bool bad = false;
