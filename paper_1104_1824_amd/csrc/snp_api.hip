@@ -93,6 +93,7 @@ struct snp_batch {
     uint32_t* d_rules = nullptr;
     uint32_t* d_magic = nullptr;
     int *d_nrp = nullptr, *d_in_ptr = nullptr, *d_in_src = nullptr;
+    uint32_t *d_fast = nullptr, *d_lut = nullptr;  // residue tables of the first applicable rule
     // per-run buffers, grown on demand
     int cap_steps = -1;
     long long ckpt_rows = 0;
@@ -117,7 +118,7 @@ struct snp_batch {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         void* ptrs[] = {d_sys, d_rules, d_magic, d_nrp, d_in_ptr, d_in_src, d_ckpt, d_hkey, d_hstep,
-                        d_halt, d_rep, d_done, d_digest, d_err};
+                        d_halt, d_rep, d_done, d_digest, d_err, d_fast, d_lut};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
     }
@@ -986,6 +987,39 @@ static uint32_t div_magic(uint32_t d) {
     return (uint32_t)(((1ULL << 32) * ((1ULL << l) - d)) / d + 1);
 }
 
+// The batched kernel pulls the e-th in-synapse source of 64 consecutive
+// neurons in one LDS read per wave (32 lanes per LDS cycle); the order of a
+// neuron's sources does not change its sum, so each list is reordered so that
+// at every e the 32 lanes of a half-wave read from distinct LDS banks (32
+// four-byte banks) as far as possible: greedily, lane by lane, the remaining
+// source whose bank is least used at that e.  A lane past its in-degree reads
+// the always-zero slot zslot.
+static void order_in_synapses(int m, const std::vector<int>& ptr, std::vector<int>& src) {
+    for (int g = 0; g < m; g += 64) {
+        const int g1 = std::min(m, g + 64);
+        int kmax = 0;
+        for (int j = g; j < g1; ++j) kmax = std::max(kmax, ptr[j + 1] - ptr[j]);
+        std::vector<std::vector<int>> rest(g1 - g);
+        for (int j = g; j < g1; ++j) rest[j - g].assign(src.begin() + ptr[j], src.begin() + ptr[j + 1]);
+        std::vector<int> out_pos(g1 - g, 0);
+        for (int e = 0; e < kmax; ++e)
+            for (int h = g; h < g1; h += 32) {
+                int used[32] = {0};
+                const int h1 = std::min(g1, h + 32);
+                for (int j = h; j < h1; ++j) {
+                    std::vector<int>& r = rest[j - g];
+                    if (r.empty()) continue;
+                    int best = 0;
+                    for (int q = 1; q < (int)r.size(); ++q)
+                        if (used[r[q] & 31] < used[r[best] & 31]) best = q;
+                    ++used[r[best] & 31];
+                    src[ptr[j] + out_pos[j - g]++] = r[best];
+                    r.erase(r.begin() + best);
+                }
+            }
+    }
+}
+
 snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* opt, snp_batch** out) {
     g_err.clear();
     if (!out) return fail(SNP_ERR_INVALID, "out is NULL");
@@ -994,7 +1028,7 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
     const int ct = descs[0].count_type;
     std::vector<snp::BatchSys> sys(n);
     std::vector<long long> row_off(n + 1, 0);
-    std::vector<uint32_t> rules, magic;
+    std::vector<uint32_t> rules, magic, fast, lut;
     std::vector<int> nrp, in_ptr, in_src;
     int m_max = 0, r_max = 0;
     for (int k = 0; k < n; ++k) {
@@ -1035,6 +1069,35 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
         for (int e = 0; e < d->n_syn; ++e) {
             const int dst = d->syn_dst[e];
             src[icnt[dst] + fill[dst]++] = d->syn_src[e];
+        }
+        order_in_synapses(d->m, icnt, src);
+        // residue tables (indexed like nrp: m + 1 entries per system, the last unused).
+        // For a count n >= T, a rule with j = 0 no longer applies (T > max(i, c))
+        // and a rule with j >= 1 applies iff n >= max(i, c) (true) and
+        // n = i (mod j); when every such j divides 24 the first applicable rule
+        // is a function of n mod 24.
+        for (int j = 0; j <= d->m; ++j) {
+            uint32_t T = 0, w[3] = {0, 0, 0};
+            bool ok = j < d->m && cnt[j + 1] - cnt[j] <= 15;
+            for (int q = j < d->m ? cnt[j] : 0; ok && q < cnt[j + 1]; ++q) {
+                const uint32_t ri = (uint32_t)d->rule_i[q], rj = (uint32_t)d->rule_j[q], rc = (uint32_t)d->rule_c[q];
+                const uint32_t lo = std::max(ri, rc);
+                if (rj == 0) T = std::max(T, lo + 1);
+                else {
+                    T = std::max(T, lo);
+                    if (24 % rj) ok = false;
+                }
+            }
+            for (uint32_t r = 0; ok && r < 24; ++r) {
+                uint32_t idx = 0;
+                for (int q = cnt[j]; q < cnt[j + 1] && !idx; ++q) {
+                    const int rj = d->rule_j[q];
+                    if (rj > 0 && (((int)r - d->rule_i[q]) % rj + rj) % rj == 0) idx = (uint32_t)(q - cnt[j] + 1);
+                }
+                w[r / 8] |= idx << (4 * (r % 8));
+            }
+            fast.push_back(ok ? (T | 0x80000000u) : 0u);
+            lut.insert(lut.end(), w, w + 3);
         }
         nrp.insert(nrp.end(), cnt.begin(), cnt.end());
         in_ptr.insert(in_ptr.end(), icnt.begin(), icnt.end());
@@ -1086,6 +1149,10 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
     BLOADCHK(dmalloc(&b->d_nrp, sizeof(int) * nrp.size()));
     BLOADCHK(dmalloc(&b->d_in_ptr, sizeof(int) * in_ptr.size()));
     BLOADCHK(dmalloc(&b->d_in_src, sizeof(int) * std::max<size_t>(1, in_src.size())));
+    BLOADCHK(dmalloc(&b->d_fast, sizeof(uint32_t) * fast.size()));
+    BLOADCHK(dmalloc(&b->d_lut, sizeof(uint32_t) * lut.size()));
+    BLOADCHK(hipMemcpy(b->d_fast, fast.data(), sizeof(uint32_t) * fast.size(), hipMemcpyHostToDevice));
+    BLOADCHK(hipMemcpy(b->d_lut, lut.data(), sizeof(uint32_t) * lut.size(), hipMemcpyHostToDevice));
     BLOADCHK(dmalloc(&b->d_halt, sizeof(int) * n));
     BLOADCHK(dmalloc(&b->d_rep, sizeof(int) * n));
     BLOADCHK(dmalloc(&b->d_done, sizeof(int) * n));
@@ -1146,6 +1213,8 @@ snp_status snp_batch_run(snp_batch* b, const void* c0_dev, int32_t steps, int32_
     snp::BatchArgs a{b->d_sys, b->d_rules, b->d_magic, b->d_nrp, b->d_in_ptr, b->d_in_src, c0_dev, final_dev, b->d_ckpt,
                      b->ckpt_rows, b->d_hkey, b->d_hstep, b->table_slots, b->m_max, b->r_max, steps,
                      detect_repeats ? 1 : 0, b->count_max, b->d_halt, b->d_rep, b->d_done, b->d_digest, b->d_err};
+    a.fast = b->d_fast;
+    a.lut = b->d_lut;
     auto enqueue = [&](hipStream_t st, int threads, int npt) -> hipError_t {
         if (detect_repeats) {
             const hipError_t e = snp::launch_fill_i32(b->d_hstep, (long long)b->table_slots * b->n, -1, st);
@@ -1396,6 +1465,8 @@ extern "C" snp_status snp_batch_run_static(snp_batch* b, const void* c0_dev, int
     snp::BatchArgs a{b->d_sys, b->d_rules, b->d_magic, b->d_nrp, b->d_in_ptr, b->d_in_src, c0_dev, final_dev,
                      base + o_ckpt, rows, (u64*)(base + o_hkey), d_hstep, slots, b->m_max, b->r_max, steps,
                      detect_repeats ? 1 : 0, b->count_max, d_halt, d_rep, d_done, d_dig, d_err};
+    a.fast = b->d_fast;
+    a.lut = b->d_lut;
     // every result is written by the kernel; the H sets start empty (-1), cleared by a fill kernel
     if (detect_repeats) HIPCHK(snp::launch_fill_i32(d_hstep, (long long)slots * n, -1, b->stream));
     HIPCHK(snp::launch_batch_det(b->elem_bytes, threads, npt, a, n, b->stream));

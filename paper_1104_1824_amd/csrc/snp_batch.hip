@@ -78,6 +78,9 @@ __device__ __forceinline__ bool applies_packed(int n, uint32_t R, uint32_t M) {
 template <int NPT>
 struct Neurons {
     int cnt[NPT];          // current spike count
+    int T[NPT];            // counts from T on take the residue table (0x7FFFFFFF: never)
+    uint32_t l0[NPT], l1[NPT], l2[NPT];  // first applicable rule + 1 per count mod 24, 4 bits each
+                                         // (residues 0-7, 8-15, 16-23; named, never indexed)
     int rs[NPT], rn[NPT];  // rules: lrules[rs .. rs + rn)
     int rw[NPT];           // the wave's largest rule count (uniform)
     int is[NPT], in[NPT];  // in-synapse sources: in_src[is .. is + in)
@@ -100,15 +103,33 @@ __device__ __forceinline__ bool det_step(Neurons<NPT>& N, const uint32_t* lrules
     for (int q = 0; q < NPT; ++q) {
         fc[q] = 0;
         int fp = 0;
-        // first applicable rule, over the wave's largest rule count (no early exit)
         bool found = false;
-        for (int k = 0; k < N.rw[q]; ++k) {
-            const int kk = N.rs[q] + min(k, max(N.rn[q] - 1, 0));
-            const uint32_t R = lrules[kk];
-            const bool ok = !found && k < N.rn[q] && applies_packed(N.cnt[q], R, lmagic[kk]);
-            fc[q] = ok ? (int)((R >> 16) & 0xFF) : fc[q];
-            fp = ok ? (int)(R >> 24) : fp;
-            found |= ok;
+        const int n = N.cnt[q];
+        const bool table = n >= N.T[q];
+        if (table) {
+            // the residue table: one lookup and the fired rule's (c, p)
+            const uint32_t r = (uint32_t)n % 24u;
+            // residues 0-15 from the 64-bit pair (l1:l0), 16-23 from l2: shifts, no indexing
+            const u64 lo = ((u64)N.l1[q] << 32) | N.l0[q];
+            const uint32_t sh = 4u * (r & 15u);
+            const int idx = (int)((r < 16 ? (uint32_t)(lo >> sh) : (N.l2[q] >> sh)) & 15u);
+            if (idx) {
+                const uint32_t R = lrules[N.rs[q] + idx - 1];
+                fc[q] = (int)((R >> 16) & 0xFF);
+                fp = (int)(R >> 24);
+                found = true;
+            }
+        }
+        if (__any(!table)) {
+            // first applicable rule, over the wave's largest rule count (no early exit)
+            for (int k = 0; k < N.rw[q]; ++k) {
+                const int kk = N.rs[q] + min(k, max(N.rn[q] - 1, 0));
+                const uint32_t R = lrules[kk];
+                const bool ok = !table && !found && k < N.rn[q] && applies_packed(n, R, lmagic[kk]);
+                fc[q] = ok ? (int)((R >> 16) & 0xFF) : fc[q];
+                fp = ok ? (int)(R >> 24) : fp;
+                found |= ok;
+            }
         }
         any |= found;
         if (N.valid[q]) prod[threadIdx.x + q * TPB] = fp;
@@ -260,6 +281,8 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
         const int j = threadIdx.x + q * TPB;
         N.valid[q] = j < B.m;
         N.cnt[q] = 0;
+        N.T[q] = 0x7FFFFFFF;
+        N.l0[q] = N.l1[q] = N.l2[q] = 0;
         N.rs[q] = N.rn[q] = N.is[q] = N.in[q] = 0;
         N.R[q] = 0;
 #pragma unroll
@@ -271,6 +294,13 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
             N.is[q] = B.in_off + a.in_ptr[B.nrp_off + j];
             N.in[q] = a.in_ptr[B.nrp_off + j + 1] - a.in_ptr[B.nrp_off + j];
             N.R[q] = mix64((u64)(j + 1) * kGamma);
+            const uint32_t f = a.fast[B.nrp_off + j];
+            if (f >> 31) {
+                N.T[q] = (int)(f & 0xFFFFu);
+                N.l0[q] = a.lut[3 * (B.nrp_off + j)];
+                N.l1[q] = a.lut[3 * (B.nrp_off + j) + 1];
+                N.l2[q] = a.lut[3 * (B.nrp_off + j) + 2];
+            }
 #pragma unroll
             for (int e = 0; e < kInReg; ++e)
                 if (e < N.in[q]) {

@@ -221,6 +221,14 @@ struct BatchArgs {
     int* steps_done;
     u64* digest;
     u64* err;               // bit 0: overflow; bit 1: two configurations with one 64-bit H
+    // Per neuron (indexed like nrp): the first applicable rule for large counts.
+    // fast = T | ok << 31: for a count n >= T every rule with j = 0 is past its
+    // only count and every other one applies iff n = i (mod j), so with ok (every
+    // j divides 24 and at most 15 rules) the first applicable rule depends on
+    // n mod 24 alone; lut[3 k .. 3 k + 2] hold 4 bits per residue: the rule's
+    // index in the neuron + 1 (0: none).
+    const uint32_t* fast;
+    const uint32_t* lut;
 };
 
 size_t batch_lds_bytes(int m_max, int r_max, int threads);
