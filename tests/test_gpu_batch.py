@@ -216,3 +216,36 @@ def test_batch_graph_replays(gpu, oracle_mod):
             d = oracle_mod.deterministic(s, steps)
             assert fin_rows[k].tolist() == d.final.tolist()
             assert int(res["digest"][k]) == d.digest and int(res["first_repeat"][k]) == d.first_repeat
+
+
+def periodic_rules_system(seed, m=96):
+    """Rules with the periods the kernel's residue table takes (j dividing 24)
+    and some it does not (5, 7, 9), thresholds i and c up to 40, productions up
+    to 3: counts pass the thresholds at different steps, some neurons never use
+    the table."""
+    rng = synth.SplitMix64((7 << 32) | seed)
+    js = (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 12, 24)
+    rules = []
+    for n in range(m):
+        for _ in range(rng.uniform(1, 4)):
+            i = rng.uniform(1, 40)
+            rules.append((n, i, rng.choice(js), rng.uniform(1, i), rng.uniform(0, 3)))
+    syn = []
+    for n in range(m):
+        seen = set()
+        while len(seen) < rng.uniform(1, 6):
+            d = rng.below(m)
+            if d != n:
+                seen.add(d)
+        syn.extend((n, d) for d in sorted(seen))
+    c0 = [rng.uniform(0, 60) for _ in range(m)]
+    return synth.make_system(m, rules, syn, c0, name=f"periodic_s{seed}")
+
+
+@pytest.mark.parametrize("threads", [256, 1024])
+def test_batch_residue_table_periods(gpu, oracle_mod, threads):
+    systems = [periodic_rules_system(s) for s in range(12)]
+    for steps in (1, 40, 700):
+        note(f"batch residue-table periods, {threads} threads, steps {steps}")
+        res = run_batch(systems, steps, threads=threads)
+        check_against_oracle(oracle_mod, systems, steps, res)
