@@ -52,6 +52,7 @@ constexpr int kTile = 256;  // children per block tile (one per thread)
 constexpr int kKMax = 64;   // rule columns of V per segment on the MFMA path (one 64-deep K step)
 constexpr int kVMax = 64;   // neurons in V per segment on the MFMA path
 constexpr int kMTStride = kKMax + 16;  // bytes per column of the transposed M_V tile (padding vs bank conflicts)
+static_assert(2 * 4608 <= kTile * kKMax, "the pull's fired-rule words fit in D for every m the library takes");
 constexpr int kIncMax = 32;  // most changed digits for a reference child derived from the previous segment's last
 
 struct Lds {
@@ -59,9 +60,9 @@ struct Lds {
     uint8_t* dg;   // [m] canonical digits of the child being computed by the sparse pull
     uint8_t* dgb;  // [m] canonical digits of the last child of the segment
     uint32_t* am;  // [m] applicable-rule mask (<= 16 rules per neuron) | canonical digits << 16
-    uint16_t* cp;  // [m] fired (c << 8 | p) of the child being computed by the pull
-    uint8_t* dp;   // [m] canonical digits of the previous segment's last child (shares cp's bytes:
-                   // needed only until the next reference child, which then needs no pull)
+    uint8_t* dp;   // [m] canonical digits of the previous segment's last child
+    uint16_t* cp;  // [m] fired (c << 8 | p) of the child being computed by the pull (shares D's
+                   // bytes: the pull ends before D is filled)
     int8_t* D;     // [kTile][kKMax]
     int8_t* MT;    // [NT][kMTStride]
     int* klist;    // [kKMax] rule of every K column
@@ -81,8 +82,8 @@ struct Lds {
 __host__ __device__ __forceinline__ size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 __host__ __device__ __forceinline__ size_t int8_lds_bytes(int m, int nt) {
-    size_t o = align16((size_t)3 * m);
-    o += align16((size_t)4 * m) + align16((size_t)2 * m);
+    size_t o = align16((size_t)4 * m);
+    o += align16((size_t)4 * m);
     o += (size_t)kTile * kKMax + (size_t)nt * kMTStride;
     o += align16((size_t)kKMax * 4) + (size_t)kVMax * 4 * 2;
     o += (size_t)kTile * 8 + (size_t)kVMax * 8 + 5 * 8 + 4 * 4;
@@ -95,13 +96,12 @@ __device__ __forceinline__ Lds carve(unsigned char* smem, int m, int nt) {
     L.om = smem;
     L.dg = smem + m;
     L.dgb = smem + 2 * m;
-    o = align16((size_t)3 * m);
+    L.dp = smem + 3 * m;
+    o = align16((size_t)4 * m);
     L.am = (uint32_t*)(smem + o);
     o += align16((size_t)4 * m);
-    L.cp = (uint16_t*)(smem + o);
-    L.dp = (uint8_t*)L.cp;
-    o += align16((size_t)2 * m);
     L.D = (int8_t*)(smem + o);
+    L.cp = (uint16_t*)L.D;  // 2 m <= kTile * kKMax for every m the library takes
     L.chg = (int*)L.D;
     L.k0 = L.chg + kIncMax;
     L.k1 = L.k0 + kIncMax;

@@ -107,3 +107,14 @@ def test_int8_per_child_segments(gpu, oracle_mod, kmax):
     note(f"int8 per-child segments kmax {kmax}: dense recipe seed 2")
     assert_same_bfs(gpu_bfs(s, max_depth=2, frontier_cap=1500, out_capacity=4000, path=INT8, int8_max_k=kmax),
                     oracle_mod.bfs(s, max_depth=2, frontier_cap=1500))
+
+
+def test_int8_at_the_largest_m(gpu, oracle_mod):
+    """m = 4608 (the most neurons a system may have) fits the int8 form's LDS
+    with 64-column tiles; m = 4096 takes 128-column tiles."""
+    for m in (4608, 4096):
+        s = synth.config_system(5, 1, m=m)
+        note(f"int8: large recipe m={m} u16 seed 1, cap 200, depth 2")
+        g = gpu_bfs(s, max_depth=2, frontier_cap=200, out_capacity=1000, path=INT8)
+        assert all(st["path_used"] == INT8 and st["int8_fallback"] == 0 for st in g["level_stats"] if st["chunks"])
+        assert_same_bfs(g, oracle_mod.bfs(s, max_depth=2, frontier_cap=200))
