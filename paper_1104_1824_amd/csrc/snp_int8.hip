@@ -467,7 +467,7 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
                             if (n0 + n >= m) continue;
                             const int4 v = *(const int4*)&s.M8[(long long)L.klist[k] * m + n0 + n];
                             const int8_t* b = (const int8_t*)&v;
-    #pragma unroll
+#pragma unroll
                             for (int i = 0; i < 16; ++i) L.MT[(n + i) * kMTStride + k] = b[i];
                         }
                     } else {
@@ -487,30 +487,63 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
                     const bool vec = (m & 3) == 0;  // rows and 4-column groups aligned for vector access
                     v4i af[CB];
                     int refv[CB][4];
-    #pragma unroll
+#pragma unroll
                     for (int cb = 0; cb < CB; ++cb) {
                         af[cb] = *(const v4i*)&L.MT[(colw + 16 * cb + (lane & 15)) * kMTStride + 16 * (lane >> 4)];
                         const int col0 = n0 + colw + 16 * cb + 4 * (lane >> 4);
-    #pragma unroll
+#pragma unroll
                         for (int i = 0; i < 4; ++i) refv[cb][i] = col0 + i < m ? (int)refrow[col0 + i] : 0;
                     }
                     for (int qr = q0; qr <= q1; ++qr) {
-    #pragma unroll
+#pragma unroll
                         for (int rb = 0; rb < 4; ++rb) {
                             const int row = 64 * qr + 16 * rb + (lane & 15);
                             const v4i bf = *(const v4i*)&L.D[row * kKMax + 16 * (lane >> 4)];
                             v4i acc[CB];
-    #pragma unroll
+#pragma unroll
                             for (int cb = 0; cb < CB; ++cb)
                                 acc[cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[cb], bf, v4i{0, 0, 0, 0}, 0, 0, 0);
                             if (row <= c || row >= cend) continue;
                             T* out = ROWS ? (T*)L.rowdst[row] : stage + (b0 + row) * (long long)m;
                             if (ROWS && !out) continue;
-    #pragma unroll
+                            if constexpr (sizeof(T) == 2 && CB % 2 == 0) {
+                                // 16-bit rows: lanes l and l ^ 16 (column groups g, g ^ 1 of one
+                                // row) trade one block's four counts, so every lane stores eight
+                                // consecutive columns (16 bytes) of block cb0 (g even) or cb1 (g odd)
+                                if ((m & 7) == 0 && n0 + colw + 16 * CB <= m) {
+                                    const int g = lane >> 4;
+#pragma unroll
+                                    for (int cb0 = 0; cb0 < CB; cb0 += 2) {
+                                        uint32_t pk[2][2];
+#pragma unroll
+                                        for (int h = 0; h < 2; ++h) {
+                                            const int cb = cb0 + h;
+                                            long long v[4];
+#pragma unroll
+                                            for (int i = 0; i < 4; ++i) {
+                                                v[i] = (long long)refv[cb][i] + acc[cb][i];
+                                                ovf |= (v[i] < 0) | (v[i] > s.count_max);
+                                            }
+                                            pk[h][0] = (uint32_t)(uint16_t)v[0] | ((uint32_t)(uint16_t)v[1] << 16);
+                                            pk[h][1] = (uint32_t)(uint16_t)v[2] | ((uint32_t)(uint16_t)v[3] << 16);
+                                        }
+                                        const bool even = (g & 1) == 0;
+                                        const uint32_t r0 = (uint32_t)__shfl_xor((int)(even ? pk[1][0] : pk[0][0]), 16);
+                                        const uint32_t r1 = (uint32_t)__shfl_xor((int)(even ? pk[1][1] : pk[0][1]), 16);
+                                        const int col = even ? n0 + colw + 16 * cb0 + 4 * g
+                                                             : n0 + colw + 16 * (cb0 + 1) + 4 * (g - 1);
+                                        const uint4 w = even ? make_uint4(pk[0][0], pk[0][1], r0, r1)
+                                                             : make_uint4(r0, r1, pk[1][0], pk[1][1]);
+                                        *(uint4*)(out + col) = w;
+                                    }
+                                    continue;
+                                }
+                            }
+#pragma unroll
                             for (int cb = 0; cb < CB; ++cb) {
                                 const int col0 = n0 + colw + 16 * cb + 4 * (lane >> 4);
                                 long long v[4];
-    #pragma unroll
+#pragma unroll
                                 for (int i = 0; i < 4; ++i) {
                                     v[i] = (long long)refv[cb][i] + acc[cb][i];
                                     ovf |= (col0 + i < m) & ((v[i] < 0) | (v[i] > s.count_max));
@@ -524,7 +557,7 @@ __global__ __launch_bounds__(256) void k_expand_int8(DevSystem s, ChunkArgs a, i
                                         *(uint2*)(out + col0) = pk;
                                     }
                                 } else {
-    #pragma unroll
+#pragma unroll
                                     for (int i = 0; i < 4; ++i)
                                         if (col0 + i < m) out[col0 + i] = (T)v[i];
                                 }
