@@ -168,11 +168,13 @@ typedef struct {
                                  the sparse form (SNP_PATH_INT8 falls back, int8_fallback = 1);
                                  0: off */
     void *stream;             /* hipStream_t for all work of the handle; NULL: default */
-    int32_t stage_rows;       /* nonzero: every pass of the int8 form writes every child's row to a
-                                 staging buffer and the commit copies the new ones to the row store;
-                                 0: snp_run's int8 passes are keys-first: keys and the visited set
-                                 come first, then the rows, each new one written once at its place in
-                                 the row store.  A key that met an entry is taken to name the same
+    int32_t stage_rows;       /* how snp_run's int8 passes write rows.  Staged: every child's row to
+                                 a staging buffer, the commit copying the new ones to the row store.
+                                 Keys-first: keys and the visited set first, then the rows, each new
+                                 one written once at its place in the row store.  > 0: staged;
+                                 < 0: keys-first; 0: keys-first for a pass whose chunk holds at least
+                                 64 MiB of rows (where the copy it saves outweighs its two extra
+                                 launches), else staged.  A key that met an entry is taken to name the same
                                  configuration until the rows are compared after the row pass; when
                                  two differ (a 32-bit tag or 64-bit key shared by two configurations)
                                  the pass is undone and redone staged (snp_expand_stats.redone), so
@@ -218,6 +220,7 @@ typedef struct {
     /* In a keys-first pass ns_psi also holds the key pass, the visited-set probe and the flags,
      * ns_expand the row pass, ns_insert the row check, and ns_flags stays 0. */
     int64_t redone;          /* keys-first passes undone and redone staged after their row check */
+    int64_t keys_first;      /* passes that ran keys-first (see snp_options.stage_rows) */
 } snp_expand_stats;
 
 typedef struct snp_system snp_system; /* opaque; owns derived tables and the visited set */

@@ -297,6 +297,10 @@ snp_status start_walk(snp_system* S, const void* c0_dev, void* arena, bool wait,
     return wait ? read_counters(S) : SNP_OK;
 }
 
+// A keys-first pass (stage_rows 0) when the chunk's rows reach this many bytes:
+// below it the commit's copy costs less than the key pass and the row check.
+constexpr double kKeysFirstBytes = 64.0 * 1024 * 1024;
+
 // Up to this many parents the commit block that fills the cap counts the
 // halting parents itself (a few loads per thread).
 constexpr long long kCommitHaltMax = 1 << 16;
@@ -478,7 +482,8 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
         stt.path_used = use_int8 ? SNP_PATH_INT8 : SNP_PATH_SPARSE;
         // keys-first: keys, probe and flags, then every row once (new rows
         // straight to the row store), then the row check
-        const bool direct = use_int8 && !redo_staged && io.row2 == nullptr && !S->opt.stage_rows;
+        const bool direct = use_int8 && !redo_staged && io.row2 == nullptr && S->opt.stage_rows <= 0 &&
+                            (S->opt.stage_rows < 0 || (double)B * (double)rb >= kKeysFirstBytes);
         snp::TableArgs ta{S->d_table, S->slots - 1, io.arena, S->d_stage, S->d_hash, S->d_slot, B, S->d_ctr,
                           S->d_cand, direct ? 1 : 0};
         if (direct) {
@@ -550,6 +555,7 @@ snp_status expand_level(snp_system* S, const LevelIO& io, snp_expand_stats* out,
             continue;
         }
         redo_staged = false;
+        if (direct) ++stt.keys_first;
         if (ext) take_extension(c);
         const long long Beff = (long long)c.beff;
         if (Beff > 0) ++stt.chunks;

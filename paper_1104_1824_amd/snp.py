@@ -77,6 +77,7 @@ class snp_expand_stats(ctypes.Structure):
         ("path_used", ctypes.c_int32), ("int8_fallback", ctypes.c_int32),
         ("ns_psi", ctypes.c_int64), ("ns_expand", ctypes.c_int64), ("ns_insert", ctypes.c_int64),
         ("ns_flags", ctypes.c_int64), ("ns_commit", ctypes.c_int64), ("redone", ctypes.c_int64),
+        ("keys_first", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -261,7 +262,7 @@ def snp_load(system, *, path: int = SNP_PATH_AUTO, stop_at_cap: bool = False, fr
              child_budget: int = 0, expand_max_count: int = -1, max_rows: int = 1 << 20,
              max_frontier: int = 0, chunk: int = 0, hash_mask: int = 0, profile: int = 0,
              int8_max_k: int = 0, deterministic: bool = False, out_neuron: int = 0, stream=None,
-             M: Optional[np.ndarray] = None, stage_rows: bool = False) -> Handle:
+             M: Optional[np.ndarray] = None, stage_rows: int = 0) -> Handle:
     """snp_load.  ``system`` has m, rule_neuron/i/j/c/p, syn_src/dst and
     count_type ("i32" or "u16") attributes; ``stream`` is a torch.cuda.Stream
     (None: torch's current stream).  With ``out_neuron`` > 0 (1-based) rows
@@ -275,7 +276,7 @@ def snp_load(system, *, path: int = SNP_PATH_AUTO, stop_at_cap: bool = False, fr
     o = snp_options(int(path), int(bool(stop_at_cap)), int(frontier_cap), int(child_budget),
                     int(expand_max_count), int(max_rows), int(max_frontier), int(chunk),
                     int(hash_mask) & ((1 << 64) - 1), int(profile), int(int8_max_k), int(bool(deterministic)),
-                    int(out_neuron), sp or None, int(bool(stage_rows)))
+                    int(out_neuron), sp or None, int(stage_rows))
     out = ctypes.c_void_p()
     _check(lib().snp_load(ctypes.byref(d), ctypes.byref(o), ctypes.byref(out)), "snp_load")
     h = Handle(out.value, arrs, 0, ct)
