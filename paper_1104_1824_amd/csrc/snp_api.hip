@@ -93,7 +93,8 @@ struct snp_batch {
     uint32_t* d_rules = nullptr;
     uint32_t* d_magic = nullptr;
     int *d_nrp = nullptr, *d_in_ptr = nullptr, *d_in_src = nullptr;
-    uint32_t *d_fast = nullptr, *d_lut = nullptr;  // residue tables of the first applicable rule
+    uint32_t *d_fast = nullptr, *d_lut = nullptr;  // tables of the first applicable rule
+    int* d_perm = nullptr;                           // slot -> neuron
     // per-run buffers, grown on demand
     int cap_steps = -1;
     long long ckpt_rows = 0;
@@ -118,7 +119,7 @@ struct snp_batch {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         void* ptrs[] = {d_sys, d_rules, d_magic, d_nrp, d_in_ptr, d_in_src, d_ckpt, d_hkey, d_hstep,
-                        d_halt, d_rep, d_done, d_digest, d_err, d_fast, d_lut};
+                        d_halt, d_rep, d_done, d_digest, d_err, d_fast, d_lut, d_perm};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
     }
@@ -1035,7 +1036,7 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
     std::vector<snp::BatchSys> sys(n);
     std::vector<long long> row_off(n + 1, 0);
     std::vector<uint32_t> rules, magic, fast, lut;
-    std::vector<int> nrp, in_ptr, in_src;
+    std::vector<int> nrp, in_ptr, in_src, slots;
     int m_max = 0, r_max = 0;
     for (int k = 0; k < n; ++k) {
         const snp_desc* d = &descs[k];
@@ -1059,33 +1060,50 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
         B.rule_off = (int)rules.size();
         B.nrp_off = (int)nrp.size();
         B.in_off = (int)in_src.size();
-        for (int q = 0; q < d->r; ++q)
-            magic.push_back(div_magic((uint32_t)d->rule_j[q]));
-        for (int q = 0; q < d->r; ++q)
-            rules.push_back((uint32_t)d->rule_i[q] | ((uint32_t)d->rule_j[q] << 8) | ((uint32_t)d->rule_c[q] << 16) |
-                            ((uint32_t)d->rule_p[q] << 24));
+        // Slots: the kernel runs slot s on thread s mod TPB; neurons take the
+        // slots in order of decreasing in-degree (ties by index) so that the 64
+        // lanes of a wave pull similar numbers of in-synapses.  Rules, tables and
+        // in-synapse lists are laid out by slot; perm maps a slot to its neuron
+        // (rows in HBM, the H weights).
+        std::vector<int> indeg(d->m, 0), perm(d->m), slot_of(d->m);
+        for (int e = 0; e < d->n_syn; ++e) indeg[d->syn_dst[e]]++;
+        for (int j = 0; j < d->m; ++j) perm[j] = j;
+        std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return indeg[x] > indeg[y]; });
+        for (int s = 0; s < d->m; ++s) slot_of[perm[s]] = s;
+        std::vector<int> first(d->m + 1, 0);  // rules of neuron j: [first[j], first[j+1]) (sorted by neuron)
+        for (int q = 0; q < d->r; ++q) first[d->rule_neuron[q] + 1]++;
+        for (int j = 0; j < d->m; ++j) first[j + 1] += first[j];
         std::vector<int> cnt(d->m + 1, 0), icnt(d->m + 1, 0);
-        for (int q = 0; q < d->r; ++q) cnt[d->rule_neuron[q] + 1]++;
-        for (int e = 0; e < d->n_syn; ++e) icnt[d->syn_dst[e] + 1]++;
-        for (int j = 0; j < d->m; ++j) {
-            cnt[j + 1] += cnt[j];
-            icnt[j + 1] += icnt[j];
+        for (int s = 0; s < d->m; ++s) {
+            const int j = perm[s];
+            cnt[s + 1] = cnt[s] + first[j + 1] - first[j];
+            icnt[s + 1] = icnt[s] + indeg[j];
+            for (int q = first[j]; q < first[j + 1]; ++q) {  // the neuron's rules, in their order
+                magic.push_back(div_magic((uint32_t)d->rule_j[q]));
+                rules.push_back((uint32_t)d->rule_i[q] | ((uint32_t)d->rule_j[q] << 8) |
+                                ((uint32_t)d->rule_c[q] << 16) | ((uint32_t)d->rule_p[q] << 24));
+            }
         }
         std::vector<int> src(d->n_syn), fill(d->m, 0);
         for (int e = 0; e < d->n_syn; ++e) {
-            const int dst = d->syn_dst[e];
-            src[icnt[dst] + fill[dst]++] = d->syn_src[e];
+            const int dst = slot_of[d->syn_dst[e]];
+            src[icnt[dst] + fill[dst]++] = slot_of[d->syn_src[e]];
         }
         order_in_synapses(d->m, icnt, src);
-        // residue tables (indexed like nrp: m + 1 entries per system, the last unused).
-        // For a count n >= T, a rule with j = 0 no longer applies (T > max(i, c))
-        // and a rule with j >= 1 applies iff n >= max(i, c) (true) and
-        // n = i (mod j); when every such j divides 24 the first applicable rule
-        // is a function of n mod 24.
-        for (int j = 0; j <= d->m; ++j) {
-            uint32_t T = 0, w[3] = {0, 0, 0};
-            bool ok = j < d->m && cnt[j + 1] - cnt[j] <= 15;
-            for (int q = j < d->m ? cnt[j] : 0; ok && q < cnt[j + 1]; ++q) {
+        // Tables of the first applicable rule (indexed like nrp: m + 1 entries per
+        // system, the last unused), 4 bits per entry: the rule's index in the
+        // neuron + 1, 0 for none.  Counts 0-15 by direct lookup (at most 15
+        // rules).  For a count n >= T a rule with j = 0 no longer applies
+        // (T > max(i, c)) and a rule with j >= 1 applies iff n >= max(i, c)
+        // (true) and n = i (mod j); when every such j divides 24 the first
+        // applicable rule is a function of n mod 24.
+        for (int s = 0; s <= d->m; ++s) {
+            const int j = s < d->m ? perm[s] : 0;
+            const int q0 = s < d->m ? first[j] : 0, q1 = s < d->m ? first[j + 1] : 0;
+            uint32_t T = 0, w[5] = {0, 0, 0, 0, 0};
+            const bool small = s < d->m && q1 - q0 <= 15;
+            bool ok = small;
+            for (int q = q0; ok && q < q1; ++q) {
                 const uint32_t ri = (uint32_t)d->rule_i[q], rj = (uint32_t)d->rule_j[q], rc = (uint32_t)d->rule_c[q];
                 const uint32_t lo = std::max(ri, rc);
                 if (rj == 0) T = std::max(T, lo + 1);
@@ -1096,14 +1114,24 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
             }
             for (uint32_t r = 0; ok && r < 24; ++r) {
                 uint32_t idx = 0;
-                for (int q = cnt[j]; q < cnt[j + 1] && !idx; ++q) {
+                for (int q = q0; q < q1 && !idx; ++q) {
                     const int rj = d->rule_j[q];
-                    if (rj > 0 && (((int)r - d->rule_i[q]) % rj + rj) % rj == 0) idx = (uint32_t)(q - cnt[j] + 1);
+                    if (rj > 0 && (((int)r - d->rule_i[q]) % rj + rj) % rj == 0) idx = (uint32_t)(q - q0 + 1);
                 }
                 w[r / 8] |= idx << (4 * (r % 8));
             }
-            fast.push_back(ok ? (T | 0x80000000u) : 0u);
-            lut.insert(lut.end(), w, w + 3);
+            for (int n = 0; small && n < 16; ++n) {
+                uint32_t idx = 0;
+                for (int q = q0; q < q1 && !idx; ++q) {
+                    const int ri = d->rule_i[q], rj = d->rule_j[q];
+                    const bool in_e = n >= ri && (rj == 0 ? n == ri : (n - ri) % rj == 0);
+                    if (in_e && n >= d->rule_c[q]) idx = (uint32_t)(q - q0 + 1);
+                }
+                w[3 + n / 8] |= idx << (4 * (n % 8));
+            }
+            fast.push_back((ok ? (T | 0x80000000u) : 0u) | (small ? 0x40000000u : 0u));
+            lut.insert(lut.end(), w, w + 5);
+            slots.push_back(s < d->m ? j : 0);
         }
         nrp.insert(nrp.end(), cnt.begin(), cnt.end());
         in_ptr.insert(in_ptr.end(), icnt.begin(), icnt.end());
@@ -1116,7 +1144,7 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
     for (int th : {256, 512, 1024}) {
         int npt = (m_max + th - 1) / th;
         npt = npt <= 1 ? 1 : (npt <= 2 ? 2 : (npt <= 4 ? 4 : 0));
-        if (npt && snp::batch_lds_bytes(m_max, r_max, th) <= 64 * 1024) shapes.push_back({th, npt});
+        if (npt && snp::batch_lds_bytes(r_max, th, npt) <= 64 * 1024) shapes.push_back({th, npt});
     }
     const int forced = opt ? (int)opt->chunk : 0;
     if (forced) {
@@ -1159,6 +1187,8 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
     BLOADCHK(dmalloc(&b->d_lut, sizeof(uint32_t) * lut.size()));
     BLOADCHK(hipMemcpy(b->d_fast, fast.data(), sizeof(uint32_t) * fast.size(), hipMemcpyHostToDevice));
     BLOADCHK(hipMemcpy(b->d_lut, lut.data(), sizeof(uint32_t) * lut.size(), hipMemcpyHostToDevice));
+    BLOADCHK(dmalloc(&b->d_perm, sizeof(int) * slots.size()));
+    BLOADCHK(hipMemcpy(b->d_perm, slots.data(), sizeof(int) * slots.size(), hipMemcpyHostToDevice));
     BLOADCHK(dmalloc(&b->d_halt, sizeof(int) * n));
     BLOADCHK(dmalloc(&b->d_rep, sizeof(int) * n));
     BLOADCHK(dmalloc(&b->d_done, sizeof(int) * n));
@@ -1221,6 +1251,7 @@ snp_status snp_batch_run(snp_batch* b, const void* c0_dev, int32_t steps, int32_
                      detect_repeats ? 1 : 0, b->count_max, b->d_halt, b->d_rep, b->d_done, b->d_digest, b->d_err};
     a.fast = b->d_fast;
     a.lut = b->d_lut;
+    a.perm = b->d_perm;
     auto enqueue = [&](hipStream_t st, int threads, int npt) -> hipError_t {
         if (detect_repeats) {
             const hipError_t e = snp::launch_fill_i32(b->d_hstep, (long long)b->table_slots * b->n, -1, st);
@@ -1473,6 +1504,7 @@ extern "C" snp_status snp_batch_run_static(snp_batch* b, const void* c0_dev, int
                      detect_repeats ? 1 : 0, b->count_max, d_halt, d_rep, d_done, d_dig, d_err};
     a.fast = b->d_fast;
     a.lut = b->d_lut;
+    a.perm = b->d_perm;
     // every result is written by the kernel; the H sets start empty (-1), cleared by a fill kernel
     if (detect_repeats) HIPCHK(snp::launch_fill_i32(d_hstep, (long long)slots * n, -1, b->stream));
     HIPCHK(snp::launch_batch_det(b->elem_bytes, threads, npt, a, n, b->stream));

@@ -4,20 +4,27 @@
 // clock; the first of Algorithm 2's spiking vectors), C_{k+1} = C_k + S_k.M
 // (Equation next-config), until the step limit or a halting configuration.
 //
-// One workgroup of TPB threads runs one system; thread t owns neurons
-// t, t + TPB, ... (NPT per thread).  Counts, rule ranges and the first kInReg
-// in-synapse sources of every owned neuron live in registers; the block shares
-// the packed rule table and double-buffered production words in LDS.  A step:
-// every neuron writes the production p of its fired rule (0: none), one
-// barrier (which also tells whether any neuron fired), then every neuron pulls
+// One workgroup of TPB threads runs one system; thread t owns slots
+// t, t + TPB, ... (NPT per thread), each holding one neuron (neurons take the
+// slots by decreasing in-degree, so a wave's in-synapse pulls are alike).
+// Counts, rule tables and the LDS addresses of the first kInReg in-synapse
+// sources of every owned neuron live in registers; the block shares the packed
+// rule table and double-buffered production words in LDS.  A step: every
+// neuron writes the production p of its fired rule (0: none), one barrier
+// (which also tells whether any neuron fired), then every neuron pulls
 // C' = C - c + sum of p over its in-synapses.  Step k uses buffer k & 1, so
-// the barrier of step k+1 separates step k's reads from step k+2's writes.
-// TPB and NPT are picked per batch by timing the candidates (host side).
+// the barrier of step k+1 separates step k's reads from step k+2's writes; the
+// two buffers sit a fixed distance apart at the start of LDS and the step loop
+// is unrolled by parity, so the odd buffer is reached through the LDS
+// instruction's offset field.  TPB and NPT are picked per batch by timing the
+// candidates (host side).
 //
 // Trajectory checksum: H(C) = sum_n C[n] * R_n (mod 2^64) with R_n the
 // SplitMix64 stream (seed 0); digest = sum_k mix64(H(C_k) + k * gamma).  Each
-// step leaves one partial sum per wave in LDS; the block adds them up once
-// every kBatch steps.  First repeat: at those boundaries the block stores a
+// wave sums its lanes' terms of 4 steps at once (a transposed butterfly: the
+// first two stages halve the number of values per lane, so 4 sums cost about
+// what one plain wave sum costs), leaving one partial sum per wave and step in
+// LDS; the block adds them up once every kBatch steps.  First repeat: at those boundaries the block stores a
 // checkpoint row and looks the batch's H values up in a per-system
 // open-addressing set of earlier H values (and within the batch); a candidate
 // pair (l, k) is confirmed by re-simulating C_l and C_k from their
@@ -30,7 +37,8 @@ namespace snp {
 namespace {
 
 constexpr int kInReg = 32;     // in-synapses per neuron held in registers
-constexpr int kBatch = 64;     // steps between checkpoints / repeat checks
+constexpr int kBatch = 64;     // steps between checkpoints / repeat checks (a multiple of 4)
+constexpr int kGroup = 4;      // steps per wave sum of the H terms
 constexpr int kMaxThreads = 1024;
 constexpr u64 kGamma = 0x9E3779B97F4A7C15ULL;
 
@@ -62,6 +70,42 @@ __device__ __forceinline__ u64 wave_sum64(u64 v) {
 }
 #undef SNP_DPP64
 
+template <int CTRL>
+__device__ __forceinline__ u64 dpp64(u64 v) {
+    const uint32_t lo = __builtin_amdgcn_update_dpp(0u, (uint32_t)v, CTRL, 0xf, 0xf, false);
+    const uint32_t hi = __builtin_amdgcn_update_dpp(0u, (uint32_t)(v >> 32), CTRL, 0xf, 0xf, false);
+    return ((u64)hi << 32) | lo;
+}
+
+// One transposed butterfly stage over a lane bit: a lane keeps x (bit clear)
+// or y (bit set) and adds the partner's other one; the partner (CTRL) differs
+// from the lane in that bit only.
+template <int CTRL>
+__device__ __forceinline__ u64 tstage(u64 x, u64 y, bool bit) {
+    return (bit ? y : x) + dpp64<CTRL>(bit ? x : y);
+}
+
+// Wave sums of four per-lane values at once: lane l returns the sum over the
+// wave's 64 lanes of h[l & 3].  Stages: lane bit 0 (quad_perm 1,0,3,2) and bit 1
+// (quad_perm 2,3,0,1) transposed, leaving the quad's sum of h[l & 3]; then
+// the quads of a row (row_ror 4, then row_ror 8: every quad of the row reaches
+// every lane), then the rows (xor 16, xor 32).
+__device__ __forceinline__ u64 wave_sum4(const u64 (&h)[kGroup], int lane) {
+    const u64 r0 = tstage<0xB1>(h[0], h[1], lane & 1), r1 = tstage<0xB1>(h[2], h[3], lane & 1);
+    u64 t = tstage<0x4E>(r0, r1, (lane >> 1) & 1);
+    t += dpp64<0x124>(t);
+    t += dpp64<0x128>(t);
+    t += __shfl_xor(t, 16);
+    t += __shfl_xor(t, 32);
+    return t;
+}
+
+typedef __attribute__((address_space(3))) int lds_i32;
+
+// A generic pointer into LDS as an LDS byte address, and a load from one.
+__device__ __forceinline__ uint32_t lds_addr(const void* p) { return (uint32_t)(uintptr_t)(const lds_i32*)p; }
+__device__ __forceinline__ int lds_load(uint32_t addr) { return *(const lds_i32*)(uintptr_t)addr; }
+
 // Packed rule (i | j << 8 | c << 16 | p << 24): a^n in L(a^i (a^j)*) and n >= c.
 // (n - i) mod j by the exact multiply-shift quotient with the rule's
 // multiplier M (Granlund-Montgomery; every 32-bit x, 2 <= j < 256); no branch.
@@ -79,24 +123,30 @@ template <int NPT>
 struct Neurons {
     int cnt[NPT];          // current spike count
     int T[NPT];            // counts from T on take the residue table (0x7FFFFFFF: never)
+    int S[NPT];            // counts below S take the small-count table (16, or 0: never)
     uint32_t l0[NPT], l1[NPT], l2[NPT];  // first applicable rule + 1 per count mod 24, 4 bits each
                                          // (residues 0-7, 8-15, 16-23; named, never indexed)
+    uint32_t s0[NPT], s1[NPT];           // the same per count 0-7 and 8-15
+    int orig[NPT];         // the slot's neuron (its entry in rows of HBM)
     int rs[NPT], rn[NPT];  // rules: lrules[rs .. rs + rn)
     int rw[NPT];           // the wave's largest rule count (uniform)
     int is[NPT], in[NPT];  // in-synapse sources: in_src[is .. is + in)
-    uint32_t reg_in[NPT][kInReg / 2];  // first kInReg sources, two u16 per word (zero slot past in)
+    uint32_t src[NPT][kInReg];  // LDS addresses in the even buffer of the first kInReg sources
+                                // (the zero slot past in)
     int kw[NPT];           // the wave's largest in-degree held in registers (uniform)
     u64 R[NPT];            // H weights
     bool valid[NPT];
 };
 
-// One step of the deterministic branch; prod is this step's production buffer.
-// Returns whether a neuron of this wave fired.  When no neuron of the block
-// fires (a halting configuration) the step changes nothing, so halting is
-// detected afterwards, once per batch of steps, from the waves' records.
-template <int TPB, int NPT>
+// One step of the deterministic branch; prod is this step's production buffer
+// (the even one, or the odd one kProdBytes further on when ODD).  Returns
+// whether a neuron of this wave fired.  When no neuron of the block fires (a
+// halting configuration) the step changes nothing, so halting is detected
+// afterwards, once per batch of steps, from the waves' records.
+template <int TPB, int NPT, bool ODD>
 __device__ __forceinline__ bool det_step(Neurons<NPT>& N, const uint32_t* lrules, const uint32_t* lmagic, int* prod,
-                                         const int* __restrict__ in_src, long long count_max, bool& ovf) {
+                                         const int* __restrict__ in_src, uint32_t count_max, bool& ovf) {
+    constexpr uint32_t kOff = ODD ? 4u * (TPB * NPT + 4) : 0u;
     int fc[NPT];
     bool any = false;
 #pragma unroll
@@ -105,12 +155,15 @@ __device__ __forceinline__ bool det_step(Neurons<NPT>& N, const uint32_t* lrules
         int fp = 0;
         bool found = false;
         const int n = N.cnt[q];
-        const bool table = n >= N.T[q];
+        const bool small = n < N.S[q];
+        const bool table = small || n >= N.T[q];
         if (table) {
-            // the residue table: one lookup and the fired rule's (c, p)
-            const uint32_t r = (uint32_t)n % 24u;
-            // residues 0-15 from the 64-bit pair (l1:l0), 16-23 from l2: shifts, no indexing
-            const u64 lo = ((u64)N.l1[q] << 32) | N.l0[q];
+            // one lookup (the count itself below 16, else its residue mod 24)
+            // and the fired rule's (c, p)
+            const uint32_t r = small ? (uint32_t)n : (uint32_t)n % 24u;
+            // entries 0-15 from a 64-bit pair (s1:s0 or l1:l0), residues 16-23
+            // from l2: shifts, no indexing
+            const u64 lo = small ? (((u64)N.s1[q] << 32) | N.s0[q]) : (((u64)N.l1[q] << 32) | N.l0[q]);
             const uint32_t sh = 4u * (r & 15u);
             const int idx = (int)((r < 16 ? (uint32_t)(lo >> sh) : (N.l2[q] >> sh)) & 15u);
             if (idx) {
@@ -140,26 +193,33 @@ __device__ __forceinline__ bool det_step(Neurons<NPT>& N, const uint32_t* lrules
     for (int q = 0; q < NPT; ++q) {
         if (!N.valid[q]) continue;
         // unconditional reads, issued together (sources past the in-degree read
-        // a slot that always holds 0); half of them only when the wave needs them
+        // a slot that always holds 0), in groups of 8 up to the wave's largest
+        // in-degree (uniform: slots are ordered by in-degree)
         int recv = 0;
 #pragma unroll
-        for (int e = 0; e < kInReg / 2; e += 2) {
-            const uint32_t w = N.reg_in[q][e >> 1];
-            recv += prod[w & 0xFFFFu] + prod[w >> 16];
-        }
-        if (N.kw[q] > kInReg / 2) {
+        for (int g = 0; g < kInReg; g += 8) {
+            if (g == 0 || N.kw[q] > g) {
 #pragma unroll
-            for (int e = kInReg / 2; e < kInReg; e += 2) {
-                const uint32_t w = N.reg_in[q][e >> 1];
-                recv += prod[w & 0xFFFFu] + prod[w >> 16];
+                for (int e = g; e < g + 8; ++e) recv += lds_load(N.src[q][e] + kOff);
             }
         }
         for (int e = kInReg; e < N.in[q]; ++e) recv += prod[in_src[N.is[q] + e]];
-        const long long v = (long long)N.cnt[q] - fc[q] + recv;
-        ovf |= (v < 0) | (v > count_max);
+        // a fired rule consumes at most the count (c <= n), and recv < 2^21
+        // (p <= 255, at most 4096 sources), so the new count fits 32 bits
+        const uint32_t v = (uint32_t)N.cnt[q] - (uint32_t)fc[q] + (uint32_t)recv;
+        ovf |= v > count_max;
         N.cnt[q] = (int)v;
     }
     return wave_fired;
+}
+
+// det_step with the parity known only at run time (re-simulations).
+template <int TPB, int NPT>
+__device__ __forceinline__ void det_step_any(Neurons<NPT>& N, int t, const uint32_t* lrules, const uint32_t* lmagic,
+                                             int* prod0, int* prod1, const int* __restrict__ in_src,
+                                             uint32_t count_max, bool& ovf) {
+    if (t & 1) det_step<TPB, NPT, true>(N, lrules, lmagic, prod1, in_src, count_max, ovf);
+    else det_step<TPB, NPT, false>(N, lrules, lmagic, prod0, in_src, count_max, ovf);
 }
 
 template <int NPT>
@@ -185,6 +245,14 @@ __device__ __forceinline__ void store_counts(const Neurons<NPT>& N, T* row) {
         if (N.valid[q]) row[threadIdx.x + q * TPB] = (T)N.cnt[q];
 }
 
+// The counts into a row of HBM, each at its neuron's place.
+template <typename T, int TPB, int NPT>
+__device__ __forceinline__ void store_final(const Neurons<NPT>& N, T* row) {
+#pragma unroll
+    for (int q = 0; q < NPT; ++q)
+        if (N.valid[q]) row[N.orig[q]] = (T)N.cnt[q];
+}
+
 // Block-wide H of the current counts (every thread gets it).
 template <int TPB, int NPT>
 __device__ __forceinline__ u64 block_hash(const Neurons<NPT>& N, u64* bpart) {
@@ -198,11 +266,11 @@ __device__ __forceinline__ u64 block_hash(const Neurons<NPT>& N, u64* bpart) {
 }
 
 struct BatchLds {
+    int* prod0;        // [slots + 4] at the start of LDS; slot `slots` always holds 0
+    int* prod1;        // [slots + 4] right after prod0 (4 (slots + 4) bytes on)
     uint32_t* lrules;  // [r_max]
     uint32_t* lmagic;  // [r_max]
-    int* prod0;        // [m4]
-    int* prod1;        // [m4]
-    int* xrow;         // [m4] a configuration under verification
+    int* xrow;         // [slots] a configuration under verification
     u64* wpart;        // [(kBatch + 1) * waves]: per-wave partial H of every step of the batch
     u64* bpart;        // [waves]
     u64* hring;        // [kBatch + 1]: H(C_{batch_start + i})
@@ -211,21 +279,22 @@ struct BatchLds {
     u64* fired;        // [waves]: steps of the batch where a neuron of the wave fired
 };
 
-__host__ __device__ __forceinline__ size_t lds_layout(int m_max, int r_max, int waves, unsigned char* base,
+// slots = TPB * NPT (a multiple of 4, so each production buffer is a whole
+// number of 16-byte units and prod1 starts exactly 4 (slots + 4) bytes on).
+__host__ __device__ __forceinline__ size_t lds_layout(int slots, int r_max, int waves, unsigned char* base,
                                                       BatchLds* L) {
     const size_t r4 = ((size_t)r_max + 3) & ~(size_t)3;
-    const size_t m4 = ((size_t)m_max + 3) & ~(size_t)3;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         unsigned char* p = base ? base + o : nullptr;
         o += (bytes + 15) & ~(size_t)15;
         return p;
     };
+    unsigned char* p_prod0 = take(((size_t)slots + 4) * 4);
+    unsigned char* p_prod1 = take(((size_t)slots + 4) * 4);
     unsigned char* p_rules = take(r4 * 4);
     unsigned char* p_magic = take(r4 * 4);
-    unsigned char* p_prod0 = take(m4 * 4 + 16);  // slot m4 always holds 0
-    unsigned char* p_prod1 = take(m4 * 4 + 16);
-    unsigned char* p_xrow = take(m4 * 4);
+    unsigned char* p_xrow = take((size_t)slots * 4);
     unsigned char* p_wpart = take((size_t)(kBatch + 1) * waves * 8);
     unsigned char* p_bpart = take((size_t)waves * 8);
     unsigned char* p_hring = take((kBatch + 1) * 8);
@@ -250,8 +319,8 @@ __host__ __device__ __forceinline__ size_t lds_layout(int m_max, int r_max, int 
 
 }  // namespace
 
-size_t batch_lds_bytes(int m_max, int r_max, int threads) {
-    return lds_layout(m_max, r_max, threads / 64, nullptr, nullptr);
+size_t batch_lds_bytes(int r_max, int threads, int npt) {
+    return lds_layout(threads * npt, r_max, threads / 64, nullptr, nullptr);
 }
 
 int batch_max_threads() { return kMaxThreads; }
@@ -265,14 +334,15 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const BatchSys B = a.sys[sys];
     BatchLds L;
-    lds_layout(a.m_max, a.r_max, W, smem, &L);
+    constexpr int kSlots = TPB * NPT;
+    lds_layout(kSlots, a.r_max, W, smem, &L);
 
     for (int q = threadIdx.x; q < B.r; q += TPB) {
         L.lrules[q] = a.rules[B.rule_off + q];
         L.lmagic[q] = a.magic[B.rule_off + q];
     }
-    const int zslot = (a.m_max + 3) & ~3;
-    if (threadIdx.x == 0) L.prod0[zslot] = L.prod1[zslot] = 0;
+    if (threadIdx.x == 0) L.prod0[kSlots] = L.prod1[kSlots] = 0;  // the zero slot
+    const uint32_t pbase = lds_addr(L.prod0);
 
     Neurons<NPT> N;
     const T* c0 = (const T*)a.c0 + B.row_off;
@@ -282,32 +352,38 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
         N.valid[q] = j < B.m;
         N.cnt[q] = 0;
         N.T[q] = 0x7FFFFFFF;
-        N.l0[q] = N.l1[q] = N.l2[q] = 0;
+        N.S[q] = 0;
+        N.l0[q] = N.l1[q] = N.l2[q] = N.s0[q] = N.s1[q] = 0;
+        N.orig[q] = 0;
         N.rs[q] = N.rn[q] = N.is[q] = N.in[q] = 0;
         N.R[q] = 0;
 #pragma unroll
-        for (int e = 0; e < kInReg / 2; ++e) N.reg_in[q][e] = ((uint32_t)zslot << 16) | (uint32_t)zslot;
+        for (int e = 0; e < kInReg; ++e) N.src[q][e] = pbase + 4u * kSlots;
         if (N.valid[q]) {
-            N.cnt[q] = (int)c0[j];
+            const int o = a.perm[B.nrp_off + j];
+            N.orig[q] = o;
+            N.cnt[q] = (int)c0[o];
             N.rs[q] = a.nrp[B.nrp_off + j];
             N.rn[q] = a.nrp[B.nrp_off + j + 1] - N.rs[q];
             N.is[q] = B.in_off + a.in_ptr[B.nrp_off + j];
             N.in[q] = a.in_ptr[B.nrp_off + j + 1] - a.in_ptr[B.nrp_off + j];
-            N.R[q] = mix64((u64)(j + 1) * kGamma);
+            N.R[q] = mix64((u64)(o + 1) * kGamma);
             const uint32_t f = a.fast[B.nrp_off + j];
+            const uint32_t* lt = a.lut + 5 * (B.nrp_off + j);
             if (f >> 31) {
                 N.T[q] = (int)(f & 0xFFFFu);
-                N.l0[q] = a.lut[3 * (B.nrp_off + j)];
-                N.l1[q] = a.lut[3 * (B.nrp_off + j) + 1];
-                N.l2[q] = a.lut[3 * (B.nrp_off + j) + 2];
+                N.l0[q] = lt[0];
+                N.l1[q] = lt[1];
+                N.l2[q] = lt[2];
+            }
+            if (f & 0x40000000u) {
+                N.S[q] = 16;
+                N.s0[q] = lt[3];
+                N.s1[q] = lt[4];
             }
 #pragma unroll
             for (int e = 0; e < kInReg; ++e)
-                if (e < N.in[q]) {
-                    const uint32_t s = (uint32_t)a.in_src[N.is[q] + e] & 0xFFFFu;
-                    uint32_t& w = N.reg_in[q][e >> 1];
-                    w = (e & 1) ? ((w & 0xFFFFu) | (s << 16)) : ((w & 0xFFFF0000u) | s);
-                }
+                if (e < N.in[q]) N.src[q][e] = pbase + 4u * (uint32_t)a.in_src[N.is[q] + e];
         }
         int kw = min(N.in[q], kInReg), rw = N.rn[q];
 #pragma unroll
@@ -315,8 +391,8 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
             kw = max(kw, __shfl_xor(kw, o));
             rw = max(rw, __shfl_xor(rw, o));
         }
-        N.kw[q] = kw;
-        N.rw[q] = rw;
+        N.kw[q] = __builtin_amdgcn_readfirstlane(kw);
+        N.rw[q] = __builtin_amdgcn_readfirstlane(rw);
     }
     T* ckpt = (T*)a.ckpt + a.ckpt_rows * B.row_off;  // row q = the configuration at step q * kBatch
     u64* hkey = a.hkey + (u64)sys * a.table_slots;
@@ -331,18 +407,31 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
     if (threadIdx.x == 0) L.hring[0] = h0;
     int k = 0, batch_start = 0, halt = -1, first_rep = -1;
     bool ovf = false, collision = false;
-    u64 fired = 0;  // bit i: a neuron of this wave fired at the step from C_{batch_start + i}
+    const uint32_t cmax = (uint32_t)a.count_max;
 
     for (;;) {
-        bool done = k >= steps;
-        if (!done) {
-            const bool wf = det_step<TPB, NPT>(N, L.lrules, L.lmagic, (k & 1) ? L.prod1 : L.prod0, a.in_src, a.count_max, ovf);
-            fired |= (wf ? 1ULL : 0ULL) << (k - batch_start);
-            ++k;
-            const u64 hw = wave_sum64(h_partial(N));
-            if (lane == 0) L.wpart[(k - batch_start) * W + wid] = hw;
+        // the batch's steps (batch_start is a multiple of kBatch: step
+        // batch_start + i reads buffer i & 1), in groups of kGroup
+        const int nb_run = min(kBatch, steps - batch_start);
+        u64 fired = 0;  // bit i: a neuron of this wave fired at the step from C_{batch_start + i}
+        for (int i = 0; i < nb_run; i += kGroup) {
+            u64 hv[kGroup];
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) {
+                hv[u] = 0;
+                if (i + u < nb_run) {
+                    const bool wf = (u & 1)
+                        ? det_step<TPB, NPT, true>(N, L.lrules, L.lmagic, L.prod1, a.in_src, cmax, ovf)
+                        : det_step<TPB, NPT, false>(N, L.lrules, L.lmagic, L.prod0, a.in_src, cmax, ovf);
+                    fired |= (wf ? 1ULL : 0ULL) << (i + u);
+                    hv[u] = h_partial(N);
+                }
+            }
+            const u64 hs = wave_sum4(hv, lane);  // the wave's part of H(C_{batch_start + i + (lane & 3) + 1})
+            if (lane < kGroup && i + lane < nb_run) L.wpart[(i + lane + 1) * W + wid] = hs;
         }
-        if (!done && k - batch_start < kBatch) continue;
+        k = batch_start + nb_run;
+        bool done = k >= steps;
 
         // ---- batch boundary (or end of run) ----
         int nb = k - batch_start;  // H(C_{batch_start + i}) in hring[i], i = 0 .. nb
@@ -362,9 +451,9 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
                 done = true;
             }
         }
-        fired = 0;
-        if (done) store_counts<T, TPB, NPT>(N, (T*)a.final_out + B.row_off);
-        else store_counts<T, TPB, NPT>(N, ckpt + (long long)(k / kBatch) * B.m);
+        if (done) store_final<T, TPB, NPT>(N, (T*)a.final_out + B.row_off);
+        if (k - batch_start == kBatch)  // a whole batch: the checkpoint of step k
+            store_counts<T, TPB, NPT>(N, ckpt + (long long)(k / kBatch) * B.m);
         __syncthreads();  // the batch's per-wave partials are complete
         {
             const int i = threadIdx.x;
@@ -413,11 +502,11 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
                 resimulated = true;
                 load_counts<T, TPB, NPT>(N, ckpt + (long long)(l / kBatch) * B.m);
                 for (int t = (l / kBatch) * kBatch; t < l; ++t)
-                    det_step<TPB, NPT>(N, L.lrules, L.lmagic, (t & 1) ? L.prod1 : L.prod0, a.in_src, a.count_max, ovf);
+                    det_step_any<TPB, NPT>(N, t, L.lrules, L.lmagic, L.prod0, L.prod1, a.in_src, cmax, ovf);
                 store_counts<int, TPB, NPT>(N, L.xrow);
                 load_counts<T, TPB, NPT>(N, ckpt + (long long)(kk / kBatch) * B.m);
                 for (int t = (kk / kBatch) * kBatch; t < kk; ++t)
-                    det_step<TPB, NPT>(N, L.lrules, L.lmagic, (t & 1) ? L.prod1 : L.prod0, a.in_src, a.count_max, ovf);
+                    det_step_any<TPB, NPT>(N, t, L.lrules, L.lmagic, L.prod0, L.prod1, a.in_src, cmax, ovf);
                 bool diff = false;
 #pragma unroll
                 for (int u = 0; u < NPT; ++u)
@@ -457,7 +546,7 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
 
 hipError_t launch_batch_det(int elem_bytes, int threads, int npt, const BatchArgs& a, int n_sys, hipStream_t st) {
     if (n_sys <= 0) return hipSuccess;
-    const size_t lds = batch_lds_bytes(a.m_max, a.r_max, threads);
+    const size_t lds = batch_lds_bytes(a.r_max, threads, npt);
 #define SNP_BATCH(TT, TPB, NN) \
     hipLaunchKernelGGL((k_batch_det<TT, TPB, NN>), dim3(n_sys), dim3(TPB), lds, st, a)
 #define SNP_BATCH_NPT(TT, TPB)                      \

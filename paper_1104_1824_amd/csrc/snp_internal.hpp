@@ -201,12 +201,12 @@ struct BatchArgs {
     const BatchSys* sys;
     const uint32_t* rules;  // packed (i | j << 8 | c << 16 | p << 24)
     const uint32_t* magic;  // per rule: multiplier for an exact (n - i) / j (j >= 2; 0 otherwise)
-    const int* nrp;         // per system: rules of neuron n are [nrp[n], nrp[n+1]) (system-relative)
-    const int* in_ptr;      // per system: in-synapses of neuron n are in_src[in_off + in_ptr[n] ..)
-    const int* in_src;
+    const int* nrp;         // per system: rules of slot s are [nrp[s], nrp[s+1]) (system-relative)
+    const int* in_ptr;      // per system: in-synapses of slot s are in_src[in_off + in_ptr[s] ..)
+    const int* in_src;      // source slots
     const void* c0;
     void* final_out;
-    void* ckpt;             // system k's checkpoint rows (m elements each) start at element
+    void* ckpt;             // system k's checkpoint rows (m elements each, by slot) start at element
                             // ckpt_rows * row_off of system k
     long long ckpt_rows;    // checkpoint rows per system
     u64* hkey;              // system k's H set: slots k * table_slots .. + table_slots
@@ -221,17 +221,20 @@ struct BatchArgs {
     int* steps_done;
     u64* digest;
     u64* err;               // bit 0: overflow; bit 1: two configurations with one 64-bit H
-    // Per neuron (indexed like nrp): the first applicable rule for large counts.
-    // fast = T | ok << 31: for a count n >= T every rule with j = 0 is past its
-    // only count and every other one applies iff n = i (mod j), so with ok (every
-    // j divides 24 and at most 15 rules) the first applicable rule depends on
-    // n mod 24 alone; lut[3 k .. 3 k + 2] hold 4 bits per residue: the rule's
-    // index in the neuron + 1 (0: none).
+    // Per slot (indexed like nrp; the arrays above are laid out by slot too):
+    // tables of the first applicable rule.  fast = T | ok << 31 | small << 30:
+    // for a count n >= T every rule with j = 0 is past its only count and every
+    // other one applies iff n = i (mod j), so with ok (every j divides 24 and at
+    // most 15 rules) the first applicable rule depends on n mod 24 alone;
+    // lut[5 k .. 5 k + 2] hold 4 bits per residue: the rule's index in the
+    // neuron + 1 (0: none); with small (at most 15 rules) lut[5 k + 3 .. 5 k + 4]
+    // hold the same for the counts 0-15.
     const uint32_t* fast;
     const uint32_t* lut;
+    const int* perm;        // per slot: its neuron (the entry in c0 and final_out rows, H weight)
 };
 
-size_t batch_lds_bytes(int m_max, int r_max, int threads);
+size_t batch_lds_bytes(int r_max, int threads, int npt);
 int batch_max_threads();
 int batch_interval();
 hipError_t launch_batch_det(int elem_bytes, int threads, int npt, const BatchArgs& a, int n_sys, hipStream_t st);
