@@ -95,6 +95,7 @@ struct snp_batch {
     int *d_nrp = nullptr, *d_in_ptr = nullptr, *d_in_src = nullptr;
     uint32_t *d_fast = nullptr, *d_lut = nullptr;  // tables of the first applicable rule
     int* d_perm = nullptr;                           // slot -> neuron
+    uint16_t* d_reg_src = nullptr;                   // per slot: where each pull round reads
     // per-run buffers, grown on demand
     int cap_steps = -1;
     long long ckpt_rows = 0;
@@ -119,7 +120,7 @@ struct snp_batch {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         void* ptrs[] = {d_sys, d_rules, d_magic, d_nrp, d_in_ptr, d_in_src, d_ckpt, d_hkey, d_hstep,
-                        d_halt, d_rep, d_done, d_digest, d_err, d_fast, d_lut, d_perm};
+                        d_halt, d_rep, d_done, d_digest, d_err, d_fast, d_lut, d_perm, d_reg_src};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
     }
@@ -994,37 +995,79 @@ static uint32_t div_magic(uint32_t d) {
     return (uint32_t)(((1ULL << 32) * ((1ULL << l) - d)) / d + 1);
 }
 
-// The batched kernel pulls the e-th in-synapse source of 64 consecutive
-// neurons in one LDS read per wave (32 lanes per LDS cycle); the order of a
-// neuron's sources does not change its sum, so each list is reordered so that
-// at every e the 32 lanes of a half-wave read from distinct LDS banks (32
-// four-byte banks) as far as possible: greedily, lane by lane, the remaining
-// source whose bank is least used at that e.  A lane past its in-degree reads
-// the always-zero slot zslot.
-static void order_in_synapses(int m, const std::vector<int>& ptr, std::vector<int>& src) {
+// Where the batched kernel reads each in-synapse source.  A wave pulls the
+// production words of its 64 slots' sources in P rounds (P = 8, 16, 24 or 32
+// by the wave's largest in-degree, capped at 32), one LDS read per round; LDS
+// serves a half-wave (32 lanes) per cycle from 32 four-byte banks, and a
+// bank holding several addresses in one round serialises them (one address
+// read by many lanes is a broadcast).  Word s of a production buffer is in
+// bank s mod 32; 32 zero words, one per bank, follow the slots.  For each
+// half-wave and round, in round order: the lanes with the fewest spare
+// rounds choose first; a lane takes the source of its own (up to 32) whose
+// bank is least loaded in the round, or, when that bank is taken and it has a
+// round to spare, nothing; lanes with nothing read a zero word in a free bank.
+// reg receives kRegSrc entries per slot: a source slot, or kZeroWord | bank.
+// The sources past the first kRegSrc of a slot stay at the end of its list.
+static constexpr int kRegSrc = 32;
+static constexpr uint16_t kZeroWord = 0xFFE0;
+static bool place_in_synapses(int m, const std::vector<int>& ptr, const std::vector<int>& src,
+                              std::vector<uint16_t>& reg) {
+    reg.assign((size_t)m * kRegSrc, 0);
     for (int g = 0; g < m; g += 64) {
         const int g1 = std::min(m, g + 64);
-        int kmax = 0;
-        for (int j = g; j < g1; ++j) kmax = std::max(kmax, ptr[j + 1] - ptr[j]);
-        std::vector<std::vector<int>> rest(g1 - g);
-        for (int j = g; j < g1; ++j) rest[j - g].assign(src.begin() + ptr[j], src.begin() + ptr[j + 1]);
-        std::vector<int> out_pos(g1 - g, 0);
-        for (int e = 0; e < kmax; ++e)
-            for (int h = g; h < g1; h += 32) {
-                int used[32] = {0};
-                const int h1 = std::min(g1, h + 32);
-                for (int j = h; j < h1; ++j) {
-                    std::vector<int>& r = rest[j - g];
-                    if (r.empty()) continue;
-                    int best = 0;
-                    for (int q = 1; q < (int)r.size(); ++q)
-                        if (used[r[q] & 31] < used[r[best] & 31]) best = q;
-                    ++used[r[best] & 31];
-                    src[ptr[j] + out_pos[j - g]++] = r[best];
-                    r.erase(r.begin() + best);
+        int kw = 0;
+        for (int j = g; j < g1; ++j) kw = std::max(kw, std::min(kRegSrc, ptr[j + 1] - ptr[j]));
+        const int P = kw > 24 ? 32 : kw > 16 ? 24 : kw > 8 ? 16 : 8;
+        for (int h = g; h < g1; h += 32) {
+            const int h1 = std::min(g1, h + 32);
+            std::vector<std::vector<int>> rest(h1 - h);
+            for (int j = h; j < h1; ++j)
+                rest[j - h].assign(src.begin() + ptr[j], src.begin() + ptr[j] + std::min(kRegSrc, ptr[j + 1] - ptr[j]));
+            std::vector<int> order(h1 - h);
+            for (int e = 0; e < kRegSrc; ++e) {
+                int load[32] = {0}, addr[32];
+                for (int b = 0; b < 32; ++b) addr[b] = -1;
+                std::vector<int> got(h1 - h, -1);
+                if (e < P) {
+                    for (int l = 0; l < h1 - h; ++l) order[l] = l;
+                    std::stable_sort(order.begin(), order.end(),
+                                     [&](int x, int y) { return rest[x].size() > rest[y].size(); });
+                    for (int l : order) {
+                        std::vector<int>& r = rest[l];
+                        if (r.empty()) continue;
+                        int best = 0, best_cost = 1 << 30;
+                        for (int q = 0; q < (int)r.size(); ++q) {
+                            const int b = r[q] & 31;
+                            const int c = addr[b] == r[q] ? 0 : load[b];
+                            if (c < best_cost) best_cost = c, best = q;
+                        }
+                        const int spare = P - e - (int)r.size();
+                        if (best_cost > 0 && spare > 0) continue;
+                        const int v = r[best], b = v & 31;
+                        if (addr[b] != v) ++load[b], addr[b] = v;
+                        got[l] = v;
+                        r.erase(r.begin() + best);
+                    }
+                }
+                // zero words: free banks first, then one already read (a broadcast)
+                int zb = -1;
+                for (int l = 0; l < h1 - h; ++l) {
+                    if (got[l] >= 0) {
+                        reg[(size_t)(h + l) * kRegSrc + e] = (uint16_t)got[l];
+                        continue;
+                    }
+                    int b = 0;
+                    while (b < 32 && load[b]) ++b;
+                    if (b < 32) ++load[b], zb = b;
+                    else b = zb >= 0 ? zb : 0;
+                    reg[(size_t)(h + l) * kRegSrc + e] = (uint16_t)(kZeroWord | b);
                 }
             }
+            for (const auto& r : rest)
+                if (!r.empty()) return false;  // cannot happen: a lane with no round to spare always takes one
+        }
     }
+    return true;
 }
 
 snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* opt, snp_batch** out) {
@@ -1037,6 +1080,7 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
     std::vector<long long> row_off(n + 1, 0);
     std::vector<uint32_t> rules, magic, fast, lut;
     std::vector<int> nrp, in_ptr, in_src, slots;
+    std::vector<uint16_t> reg_src;  // kRegSrc per slot; system k's from kRegSrc * row_off[k] on
     int m_max = 0, r_max = 0;
     for (int k = 0; k < n; ++k) {
         const snp_desc* d = &descs[k];
@@ -1089,7 +1133,10 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
             const int dst = slot_of[d->syn_dst[e]];
             src[icnt[dst] + fill[dst]++] = slot_of[d->syn_src[e]];
         }
-        order_in_synapses(d->m, icnt, src);
+        std::vector<uint16_t> reg;
+        if (!place_in_synapses(d->m, icnt, src, reg))
+            return fail(SNP_ERR_INVALID, "system %d: in-synapse placement left sources unread", k);
+        reg_src.insert(reg_src.end(), reg.begin(), reg.end());
         // Tables of the first applicable rule (indexed like nrp: m + 1 entries per
         // system, the last unused), 4 bits per entry: the rule's index in the
         // neuron + 1, 0 for none.  Counts 0-15 by direct lookup (at most 15
@@ -1187,6 +1234,8 @@ snp_status snp_batch_load(const snp_desc* descs, int32_t n, const snp_options* o
     BLOADCHK(dmalloc(&b->d_lut, sizeof(uint32_t) * lut.size()));
     BLOADCHK(hipMemcpy(b->d_fast, fast.data(), sizeof(uint32_t) * fast.size(), hipMemcpyHostToDevice));
     BLOADCHK(hipMemcpy(b->d_lut, lut.data(), sizeof(uint32_t) * lut.size(), hipMemcpyHostToDevice));
+    BLOADCHK(dmalloc(&b->d_reg_src, sizeof(uint16_t) * reg_src.size()));
+    BLOADCHK(hipMemcpy(b->d_reg_src, reg_src.data(), sizeof(uint16_t) * reg_src.size(), hipMemcpyHostToDevice));
     BLOADCHK(dmalloc(&b->d_perm, sizeof(int) * slots.size()));
     BLOADCHK(hipMemcpy(b->d_perm, slots.data(), sizeof(int) * slots.size(), hipMemcpyHostToDevice));
     BLOADCHK(dmalloc(&b->d_halt, sizeof(int) * n));
@@ -1252,6 +1301,7 @@ snp_status snp_batch_run(snp_batch* b, const void* c0_dev, int32_t steps, int32_
     a.fast = b->d_fast;
     a.lut = b->d_lut;
     a.perm = b->d_perm;
+    a.reg_src = b->d_reg_src;
     auto enqueue = [&](hipStream_t st, int threads, int npt) -> hipError_t {
         if (detect_repeats) {
             const hipError_t e = snp::launch_fill_i32(b->d_hstep, (long long)b->table_slots * b->n, -1, st);
@@ -1505,6 +1555,7 @@ extern "C" snp_status snp_batch_run_static(snp_batch* b, const void* c0_dev, int
     a.fast = b->d_fast;
     a.lut = b->d_lut;
     a.perm = b->d_perm;
+    a.reg_src = b->d_reg_src;
     // every result is written by the kernel; the H sets start empty (-1), cleared by a fill kernel
     if (detect_repeats) HIPCHK(snp::launch_fill_i32(d_hstep, (long long)slots * n, -1, b->stream));
     HIPCHK(snp::launch_batch_det(b->elem_bytes, threads, npt, a, n, b->stream));

@@ -39,6 +39,7 @@ namespace {
 constexpr int kInReg = 32;     // in-synapses per neuron held in registers
 constexpr int kBatch = 64;     // steps between checkpoints / repeat checks (a multiple of 4)
 constexpr int kGroup = 4;      // steps per wave sum of the H terms
+constexpr int kZeros = 32;     // zero words after the slots of a production buffer, one per LDS bank
 constexpr int kMaxThreads = 1024;
 constexpr u64 kGamma = 0x9E3779B97F4A7C15ULL;
 
@@ -127,6 +128,8 @@ struct Neurons {
     uint32_t l0[NPT], l1[NPT], l2[NPT];  // first applicable rule + 1 per count mod 24, 4 bits each
                                          // (residues 0-7, 8-15, 16-23; named, never indexed)
     uint32_t s0[NPT], s1[NPT];           // the same per count 0-7 and 8-15
+    uint32_t cp0[NPT], cp1[NPT];         // (c | p << 8) of the neuron's rules 1, 2 (cp0) and 3, 4 (cp1),
+                                         // 16 bits each
     int orig[NPT];         // the slot's neuron (its entry in rows of HBM)
     int rs[NPT], rn[NPT];  // rules: lrules[rs .. rs + rn)
     int rw[NPT];           // the wave's largest rule count (uniform)
@@ -138,6 +141,18 @@ struct Neurons {
     bool valid[NPT];
 };
 
+// Sum of the production words at the first G source addresses (+ OFF bytes).
+template <int G, uint32_t OFF>
+__device__ __forceinline__ int pull_sum(const uint32_t (&src)[kInReg]) {
+    int v[G];
+#pragma unroll
+    for (int e = 0; e < G; ++e) v[e] = lds_load(src[e] + OFF);
+    int t = 0;
+#pragma unroll
+    for (int e = 0; e < G; ++e) t += v[e];
+    return t;
+}
+
 // One step of the deterministic branch; prod is this step's production buffer
 // (the even one, or the odd one kProdBytes further on when ODD).  Returns
 // whether a neuron of this wave fired.  When no neuron of the block fires (a
@@ -146,63 +161,60 @@ struct Neurons {
 template <int TPB, int NPT, bool ODD>
 __device__ __forceinline__ bool det_step(Neurons<NPT>& N, const uint32_t* lrules, const uint32_t* lmagic, int* prod,
                                          const int* __restrict__ in_src, uint32_t count_max, bool& ovf) {
-    constexpr uint32_t kOff = ODD ? 4u * (TPB * NPT + 4) : 0u;
+    constexpr uint32_t kOff = ODD ? 4u * (TPB * NPT + kZeros) : 0u;
     int fc[NPT];
     bool any = false;
 #pragma unroll
     for (int q = 0; q < NPT; ++q) {
-        fc[q] = 0;
-        int fp = 0;
-        bool found = false;
         const int n = N.cnt[q];
         const bool small = n < N.S[q];
         const bool table = small || n >= N.T[q];
-        if (table) {
-            // one lookup (the count itself below 16, else its residue mod 24)
-            // and the fired rule's (c, p)
-            const uint32_t r = small ? (uint32_t)n : (uint32_t)n % 24u;
-            // entries 0-15 from a 64-bit pair (s1:s0 or l1:l0), residues 16-23
-            // from l2: shifts, no indexing
-            const u64 lo = small ? (((u64)N.s1[q] << 32) | N.s0[q]) : (((u64)N.l1[q] << 32) | N.l0[q]);
-            const uint32_t sh = 4u * (r & 15u);
-            const int idx = (int)((r < 16 ? (uint32_t)(lo >> sh) : (N.l2[q] >> sh)) & 15u);
-            if (idx) {
+        // one lookup (the count itself below 16, else its residue mod 24):
+        // entries 0-15 from a 64-bit pair (s1:s0 or l1:l0), residues 16-23
+        // from l2; shifts and selects, no indexing and no branch
+        const uint32_t r = small ? (uint32_t)n : (uint32_t)n % 24u;
+        const u64 lo = small ? (((u64)N.s1[q] << 32) | N.s0[q]) : (((u64)N.l1[q] << 32) | N.l0[q]);
+        const uint32_t sh = 4u * (r & 15u);
+        const int idx = table ? (int)((r < 16 ? (uint32_t)(lo >> sh) : (N.l2[q] >> sh)) & 15u) : 0;
+        // the fired rule's (c, p): rules 1-4 from registers, later ones from LDS
+        const uint32_t w = idx > 2 ? N.cp1[q] : N.cp0[q];
+        uint32_t cp = idx ? (w >> (16u * ((uint32_t)(idx - 1) & 1u))) & 0xFFFFu : 0u;
+        if (__any(idx > 4)) {
+            if (idx > 4) {
                 const uint32_t R = lrules[N.rs[q] + idx - 1];
-                fc[q] = (int)((R >> 16) & 0xFF);
-                fp = (int)(R >> 24);
-                found = true;
+                cp = ((R >> 16) & 0xFFu) | ((R >> 24) << 8);
             }
         }
+        bool found = idx != 0;
         if (__any(!table)) {
             // first applicable rule, over the wave's largest rule count (no early exit)
             for (int k = 0; k < N.rw[q]; ++k) {
                 const int kk = N.rs[q] + min(k, max(N.rn[q] - 1, 0));
                 const uint32_t R = lrules[kk];
                 const bool ok = !table && !found && k < N.rn[q] && applies_packed(n, R, lmagic[kk]);
-                fc[q] = ok ? (int)((R >> 16) & 0xFF) : fc[q];
-                fp = ok ? (int)(R >> 24) : fp;
+                cp = ok ? (((R >> 16) & 0xFFu) | ((R >> 24) << 8)) : cp;
                 found |= ok;
             }
         }
+        fc[q] = (int)(cp & 0xFFu);
         any |= found;
-        if (N.valid[q]) prod[threadIdx.x + q * TPB] = fp;
+        if (N.valid[q]) prod[threadIdx.x + q * TPB] = (int)(cp >> 8);
     }
     const bool wave_fired = __any(any);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NPT; ++q) {
         if (!N.valid[q]) continue;
-        // unconditional reads, issued together (sources past the in-degree read
-        // a slot that always holds 0), in groups of 8 up to the wave's largest
-        // in-degree (uniform: slots are ordered by in-degree)
-        int recv = 0;
-#pragma unroll
-        for (int g = 0; g < kInReg; g += 8) {
-            if (g == 0 || N.kw[q] > g) {
-#pragma unroll
-                for (int e = g; e < g + 8; ++e) recv += lds_load(N.src[q][e] + kOff);
-            }
-        }
+        // unconditional reads, all issued before the first add (sources past
+        // the in-degree read a slot that always holds 0): 8, 16, 24 or 32 of
+        // them by the wave's largest in-degree (uniform; slots are ordered by
+        // in-degree, so a wave's neurons are alike)
+        const int kw = N.kw[q];
+        int recv;
+        if (kw > 24) recv = pull_sum<32, kOff>(N.src[q]);
+        else if (kw > 16) recv = pull_sum<24, kOff>(N.src[q]);
+        else if (kw > 8) recv = pull_sum<16, kOff>(N.src[q]);
+        else recv = pull_sum<8, kOff>(N.src[q]);
         for (int e = kInReg; e < N.in[q]; ++e) recv += prod[in_src[N.is[q] + e]];
         // a fired rule consumes at most the count (c <= n), and recv < 2^21
         // (p <= 255, at most 4096 sources), so the new count fits 32 bits
@@ -266,8 +278,8 @@ __device__ __forceinline__ u64 block_hash(const Neurons<NPT>& N, u64* bpart) {
 }
 
 struct BatchLds {
-    int* prod0;        // [slots + 4] at the start of LDS; slot `slots` always holds 0
-    int* prod1;        // [slots + 4] right after prod0 (4 (slots + 4) bytes on)
+    int* prod0;        // [slots + kZeros] at the start of LDS; the last kZeros words always hold 0
+    int* prod1;        // [slots + kZeros] right after prod0 (4 (slots + kZeros) bytes on)
     uint32_t* lrules;  // [r_max]
     uint32_t* lmagic;  // [r_max]
     int* xrow;         // [slots] a configuration under verification
@@ -279,8 +291,9 @@ struct BatchLds {
     u64* fired;        // [waves]: steps of the batch where a neuron of the wave fired
 };
 
-// slots = TPB * NPT (a multiple of 4, so each production buffer is a whole
-// number of 16-byte units and prod1 starts exactly 4 (slots + 4) bytes on).
+// slots = TPB * NPT (a multiple of 32, so each production buffer is a whole
+// number of 16-byte units, prod1 starts exactly 4 (slots + kZeros) bytes on,
+// and zero word b sits in LDS bank b).
 __host__ __device__ __forceinline__ size_t lds_layout(int slots, int r_max, int waves, unsigned char* base,
                                                       BatchLds* L) {
     const size_t r4 = ((size_t)r_max + 3) & ~(size_t)3;
@@ -290,8 +303,8 @@ __host__ __device__ __forceinline__ size_t lds_layout(int slots, int r_max, int 
         o += (bytes + 15) & ~(size_t)15;
         return p;
     };
-    unsigned char* p_prod0 = take(((size_t)slots + 4) * 4);
-    unsigned char* p_prod1 = take(((size_t)slots + 4) * 4);
+    unsigned char* p_prod0 = take(((size_t)slots + kZeros) * 4);
+    unsigned char* p_prod1 = take(((size_t)slots + kZeros) * 4);
     unsigned char* p_rules = take(r4 * 4);
     unsigned char* p_magic = take(r4 * 4);
     unsigned char* p_xrow = take((size_t)slots * 4);
@@ -341,7 +354,7 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
         L.lrules[q] = a.rules[B.rule_off + q];
         L.lmagic[q] = a.magic[B.rule_off + q];
     }
-    if (threadIdx.x == 0) L.prod0[kSlots] = L.prod1[kSlots] = 0;  // the zero slot
+    if (threadIdx.x < kZeros) L.prod0[kSlots + threadIdx.x] = L.prod1[kSlots + threadIdx.x] = 0;  // zero words
     const uint32_t pbase = lds_addr(L.prod0);
 
     Neurons<NPT> N;
@@ -354,11 +367,12 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
         N.T[q] = 0x7FFFFFFF;
         N.S[q] = 0;
         N.l0[q] = N.l1[q] = N.l2[q] = N.s0[q] = N.s1[q] = 0;
+        N.cp0[q] = N.cp1[q] = 0;
         N.orig[q] = 0;
         N.rs[q] = N.rn[q] = N.is[q] = N.in[q] = 0;
         N.R[q] = 0;
 #pragma unroll
-        for (int e = 0; e < kInReg; ++e) N.src[q][e] = pbase + 4u * kSlots;
+        for (int e = 0; e < kInReg; ++e) N.src[q][e] = pbase + 4u * kSlots;  // a zero word
         if (N.valid[q]) {
             const int o = a.perm[B.nrp_off + j];
             N.orig[q] = o;
@@ -368,6 +382,12 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
             N.is[q] = B.in_off + a.in_ptr[B.nrp_off + j];
             N.in[q] = a.in_ptr[B.nrp_off + j + 1] - a.in_ptr[B.nrp_off + j];
             N.R[q] = mix64((u64)(o + 1) * kGamma);
+            for (int k = 0; k < min(N.rn[q], 4); ++k) {
+                const uint32_t R = a.rules[B.rule_off + N.rs[q] + k];
+                const uint32_t cp = ((R >> 16) & 0xFFu) | ((R >> 24) << 8);
+                if (k < 2) N.cp0[q] |= cp << (16 * k);
+                else N.cp1[q] |= cp << (16 * (k - 2));
+            }
             const uint32_t f = a.fast[B.nrp_off + j];
             const uint32_t* lt = a.lut + 5 * (B.nrp_off + j);
             if (f >> 31) {
@@ -381,9 +401,12 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
                 N.s0[q] = lt[3];
                 N.s1[q] = lt[4];
             }
+            const uint16_t* rg = a.reg_src + (B.row_off + j) * kInReg;
 #pragma unroll
-            for (int e = 0; e < kInReg; ++e)
-                if (e < N.in[q]) N.src[q][e] = pbase + 4u * (uint32_t)a.in_src[N.is[q] + e];
+            for (int e = 0; e < kInReg; ++e) {
+                const uint32_t v = rg[e];
+                N.src[q][e] = pbase + 4u * (v >= 0xFFE0u ? (uint32_t)kSlots + (v & 31u) : v);
+            }
         }
         int kw = min(N.in[q], kInReg), rw = N.rn[q];
 #pragma unroll

@@ -232,6 +232,12 @@ struct BatchArgs {
     const uint32_t* fast;
     const uint32_t* lut;
     const int* perm;        // per slot: its neuron (the entry in c0 and final_out rows, H weight)
+    // Per slot (system k's from 32 * row_off on): the slot whose production
+    // word each of the 32 pull rounds reads, or 0xFFE0 | b for the zero word
+    // in bank b (placed at load so that a half-wave's reads in a round fall on
+    // distinct LDS banks where possible); the sources past the first 32 of a
+    // slot are read from the end of its in_src list.
+    const uint16_t* reg_src;
 };
 
 size_t batch_lds_bytes(int r_max, int threads, int npt);
