@@ -996,8 +996,8 @@ static uint32_t div_magic(uint32_t d) {
 }
 
 // Where the batched kernel reads each in-synapse source.  A wave pulls the
-// production words of its 64 slots' sources in P rounds (P = 8, 16, 24 or 32
-// by the wave's largest in-degree, capped at 32), one LDS read per round; LDS
+// production words of its 64 slots' sources in P rounds (the wave's largest
+// in-degree, capped at 32, rounded up to a multiple of 4), one LDS read per round; LDS
 // serves a half-wave (32 lanes) per cycle from 32 four-byte banks, and a
 // bank holding several addresses in one round serialises them (one address
 // read by many lanes is a broadcast).  Word s of a production buffer is in
@@ -1017,7 +1017,7 @@ static bool place_in_synapses(int m, const std::vector<int>& ptr, const std::vec
         const int g1 = std::min(m, g + 64);
         int kw = 0;
         for (int j = g; j < g1; ++j) kw = std::max(kw, std::min(kRegSrc, ptr[j + 1] - ptr[j]));
-        const int P = kw > 24 ? 32 : kw > 16 ? 24 : kw > 8 ? 16 : 8;
+        const int P = std::max(4, (kw + 3) & ~3);
         for (int h = g; h < g1; h += 32) {
             const int h1 = std::min(g1, h + 32);
             std::vector<std::vector<int>> rest(h1 - h);

@@ -6,7 +6,9 @@
 //
 // One workgroup of TPB threads runs one system; thread t owns slots
 // t, t + TPB, ... (NPT per thread), each holding one neuron (neurons take the
-// slots by decreasing in-degree, so a wave's in-synapse pulls are alike).
+// slots by decreasing in-degree, so a wave's in-synapse pulls are alike); a
+// slot past m runs as a neuron with no rule, no in-synapse and weight 0, so
+// the step has no per-lane branch.
 // Counts, rule tables and the LDS addresses of the first kInReg in-synapse
 // sources of every owned neuron live in registers; the block shares the packed
 // rule table and double-buffered production words in LDS.  A step: every
@@ -198,23 +200,29 @@ __device__ __forceinline__ bool det_step(Neurons<NPT>& N, const uint32_t* lrules
         }
         fc[q] = (int)(cp & 0xFFu);
         any |= found;
-        if (N.valid[q]) prod[threadIdx.x + q * TPB] = (int)(cp >> 8);
+        prod[threadIdx.x + q * TPB] = (int)(cp >> 8);  // a slot past m writes 0 to its own word
     }
     const bool wave_fired = __any(any);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NPT; ++q) {
-        if (!N.valid[q]) continue;
-        // unconditional reads, all issued before the first add (sources past
-        // the in-degree read a slot that always holds 0): 8, 16, 24 or 32 of
-        // them by the wave's largest in-degree (uniform; slots are ordered by
-        // in-degree, so a wave's neurons are alike)
+        // unconditional reads, all issued before the first add (a lane past
+        // its in-degree reads a zero word): 4, 8, ..., 32 of them by the wave's
+        // largest in-degree (uniform; slots are ordered by in-degree, so a
+        // wave's neurons are alike)
         const int kw = N.kw[q];
         int recv;
-        if (kw > 24) recv = pull_sum<32, kOff>(N.src[q]);
-        else if (kw > 16) recv = pull_sum<24, kOff>(N.src[q]);
-        else if (kw > 8) recv = pull_sum<16, kOff>(N.src[q]);
-        else recv = pull_sum<8, kOff>(N.src[q]);
+        if (kw > 16) {
+            if (kw > 28) recv = pull_sum<32, kOff>(N.src[q]);
+            else if (kw > 24) recv = pull_sum<28, kOff>(N.src[q]);
+            else if (kw > 20) recv = pull_sum<24, kOff>(N.src[q]);
+            else recv = pull_sum<20, kOff>(N.src[q]);
+        } else {
+            if (kw > 12) recv = pull_sum<16, kOff>(N.src[q]);
+            else if (kw > 8) recv = pull_sum<12, kOff>(N.src[q]);
+            else if (kw > 4) recv = pull_sum<8, kOff>(N.src[q]);
+            else recv = pull_sum<4, kOff>(N.src[q]);
+        }
         for (int e = kInReg; e < N.in[q]; ++e) recv += prod[in_src[N.is[q] + e]];
         // a fired rule consumes at most the count (c <= n), and recv < 2^21
         // (p <= 255, at most 4096 sources), so the new count fits 32 bits
@@ -239,7 +247,7 @@ __device__ __forceinline__ u64 h_partial(const Neurons<NPT>& N) {
     u64 h = 0;
 #pragma unroll
     for (int q = 0; q < NPT; ++q)
-        if (N.valid[q]) h += (u64)(uint32_t)N.cnt[q] * N.R[q];
+        h += (u64)(uint32_t)N.cnt[q] * N.R[q];  // R = 0 past m
     return h;
 }
 
@@ -365,7 +373,7 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
         N.valid[q] = j < B.m;
         N.cnt[q] = 0;
         N.T[q] = 0x7FFFFFFF;
-        N.S[q] = 0;
+        N.S[q] = N.valid[q] ? 0 : 16;  // a slot past m: no rule ever applies (its small table is 0)
         N.l0[q] = N.l1[q] = N.l2[q] = N.s0[q] = N.s1[q] = 0;
         N.cp0[q] = N.cp1[q] = 0;
         N.orig[q] = 0;
