@@ -354,15 +354,21 @@ def batch_work(systems):
     return [s.r + s.n_syn + s.m for s in systems]
 
 
-def batched_line(reps=3, cpu=None):
+def batched_line(reps=3, cpu=None, largest=False):
+    """The batched launch; largest=True runs only the workload's largest
+    system (the one that bounds the launch), for per-step counters."""
     import numpy as np
     import torch
 
     import synth
     from paper_1104_1824_amd import snp
 
-    log("batched deterministic launch, 256 systems x 10k steps")
     systems = synth.batched_systems(0, 256)
+    if largest:
+        systems = [max(systems, key=lambda x: x.m)]
+        log(f"batched deterministic launch, the largest system alone (m={systems[0].m}) x 10k steps")
+    else:
+        log("batched deterministic launch, 256 systems x 10k steps")
     b = snp.snp_batch_load(systems)
     off = snp.snp_batch_offsets(b)
     c0 = torch.from_numpy(np.concatenate([x.c0 for x in systems]).astype(np.int32)).cuda()
@@ -382,7 +388,8 @@ def batched_line(reps=3, cpu=None):
     # the launch cannot end before the whole batch's work at the chip's vector
     # rate, nor before the largest system's work at one CU's rate
     t_min = max(work.sum() / (VALU_PEAK_GOPS * 1e9), work.max() / (CU_PEAK_GOPS * 1e9))
-    line = dict(workload=BATCH_WORKLOAD, value=round(steps_total / dt, 1), unit="system-steps/s",
+    line = dict(workload=BATCH_WORKLOAD + (", largest system alone" if largest else ""),
+                value=round(steps_total / dt, 1), unit="system-steps/s",
                 ms_per_launch=round(dt * 1e3, 3), dtype="int32", threads_per_system=shape[0],
                 neurons_per_thread=shape[1],
                 roofline=dict(bound="alu", achieved=round(work.sum() / dt / 1e9, 2),
@@ -479,6 +486,8 @@ def main():
                          "new ones are recorded")
     ap.add_argument("--only", choices=sorted(SECONDARY) + ["dense"],
                     help="run only this workload (no CPU baseline) and print its line")
+    ap.add_argument("--batch-largest", action="store_true",
+                    help="with --only batched: run the workload's largest system alone")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reads 1 GiB, writes 1 GiB) five times, to scale "
                          "FETCH_SIZE / WRITE_SIZE counters")
@@ -504,7 +513,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     if args.only and args.only != "dense":
-        kw = {} if args.only == "batched" else dict(tune=not args.no_tune, cache=args.tuning_cache)
+        kw = dict(largest=args.batch_largest) if args.only == "batched" else dict(tune=not args.no_tune,
+                                                                                  cache=args.tuning_cache)
         print(json.dumps({args.only: SECONDARY[args.only](**kw)}), flush=True)
         return
     s, results, dt = run_dense(args.steps, args.warmup, not args.no_tune, args.tuning_cache)
