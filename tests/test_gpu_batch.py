@@ -249,3 +249,42 @@ def test_batch_residue_table_periods(gpu, oracle_mod, threads):
         note(f"batch residue-table periods, {threads} threads, steps {steps}")
         res = run_batch(systems, steps, threads=threads)
         check_against_oracle(oracle_mod, systems, steps, res)
+
+
+def many_rules_system(seed, m=70):
+    """Neurons with 5 to 16 rules whose first ones need large counts (so the
+    fired rule is often past the fourth, and a 16-rule neuron has no table for
+    small counts), plus a hub neuron with 60 in-synapses (past the 32 sources a
+    lane holds in registers); m = 70 leaves slots past m in the last wave."""
+    rng = synth.SplitMix64((11 << 32) | seed)
+    rules = []
+    for n in range(m):
+        k = 16 if n % 7 == 0 else rng.uniform(5, 12)
+        for q in range(k):
+            if q < k - 3:  # thresholds that the counts reach only now and then
+                i = rng.uniform(8, 40)
+                rules.append((n, i, rng.choice((0, 1, 2, 3, 5)), rng.uniform(1, i), rng.uniform(0, 3)))
+            else:  # late rules that apply to small counts
+                i = rng.uniform(1, 3)
+                rules.append((n, i, rng.choice((0, 1, 2)), rng.uniform(1, i), rng.uniform(0, 2)))
+    syn = set()
+    hub = m - 1
+    for n in range(m):
+        for _ in range(rng.uniform(1, 4)):
+            d = rng.below(m)
+            if d != n:
+                syn.add((n, d))
+    for n in range(60):
+        if n != hub:
+            syn.add((n, hub))
+    c0 = [rng.uniform(0, 30) for _ in range(m)]
+    return synth.make_system(m, rules, sorted(syn), c0, name=f"many_rules_s{seed}")
+
+
+@pytest.mark.parametrize("threads", [256, 512, 1024])
+def test_batch_many_rules_and_a_hub(gpu, oracle_mod, threads):
+    systems = [many_rules_system(s) for s in range(6)]
+    assert max(np.bincount(s.syn_dst).max() for s in systems) > 32
+    for steps in (1, 37, 500):
+        note(f"batch many rules and a hub, {threads} threads, steps {steps}")
+        check_against_oracle(oracle_mod, systems, steps, run_batch(systems, steps, threads=threads))
