@@ -88,19 +88,31 @@ __device__ __forceinline__ u64 tstage(u64 x, u64 y, bool bit) {
     return (bit ? y : x) + dpp64<CTRL>(bit ? x : y);
 }
 
+// t + the same lane's t in the other row of its row pair (lanes 16 apart) or
+// in the other half of the wave (lanes 32 apart): the permlane swaps of a value
+// with itself leave, in each lane, its own and its partner's value.
+__device__ __forceinline__ u64 xor_sum16(u64 t) {
+    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)t, (uint32_t)t, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(t >> 32), (uint32_t)(t >> 32), false, false);
+    return (((u64)hi[0] << 32) | lo[0]) + (((u64)hi[1] << 32) | lo[1]);
+}
+__device__ __forceinline__ u64 xor_sum32(u64 t) {
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)t, (uint32_t)t, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(t >> 32), (uint32_t)(t >> 32), false, false);
+    return (((u64)hi[0] << 32) | lo[0]) + (((u64)hi[1] << 32) | lo[1]);
+}
+
 // Wave sums of four per-lane values at once: lane l returns the sum over the
 // wave's 64 lanes of h[l & 3].  Stages: lane bit 0 (quad_perm 1,0,3,2) and bit 1
 // (quad_perm 2,3,0,1) transposed, leaving the quad's sum of h[l & 3]; then
 // the quads of a row (row_ror 4, then row_ror 8: every quad of the row reaches
-// every lane), then the rows (xor 16, xor 32).
+// every lane), then the rows (lanes 16 apart, then 32 apart; VALU swaps, no LDS).
 __device__ __forceinline__ u64 wave_sum4(const u64 (&h)[kGroup], int lane) {
     const u64 r0 = tstage<0xB1>(h[0], h[1], lane & 1), r1 = tstage<0xB1>(h[2], h[3], lane & 1);
     u64 t = tstage<0x4E>(r0, r1, (lane >> 1) & 1);
     t += dpp64<0x124>(t);
     t += dpp64<0x128>(t);
-    t += __shfl_xor(t, 16);
-    t += __shfl_xor(t, 32);
-    return t;
+    return xor_sum32(xor_sum16(t));
 }
 
 typedef __attribute__((address_space(3))) int lds_i32;
@@ -130,8 +142,9 @@ struct Neurons {
     uint32_t l0[NPT], l1[NPT], l2[NPT];  // first applicable rule + 1 per count mod 24, 4 bits each
                                          // (residues 0-7, 8-15, 16-23; named, never indexed)
     uint32_t s0[NPT], s1[NPT];           // the same per count 0-7 and 8-15
-    uint32_t cp0[NPT], cp1[NPT];         // (c | p << 8) of the neuron's rules 1, 2 (cp0) and 3, 4 (cp1),
-                                         // 16 bits each
+    u64 cpw[NPT];          // (c | p << 8) of the neuron's rules 1-3 at bits 16 k (k = 1-3; bits 0-15: 0)
+    bool far[NPT];         // uniform: a lane of the wave has more than 3 rules
+    bool slow[NPT];        // uniform: a lane of the wave has counts that neither table covers
     int orig[NPT];         // the slot's neuron (its entry in rows of HBM)
     int rs[NPT], rn[NPT];  // rules: lrules[rs .. rs + rn)
     int rw[NPT];           // the wave's largest rule count (uniform)
@@ -178,17 +191,17 @@ __device__ __forceinline__ bool det_step(Neurons<NPT>& N, const uint32_t* lrules
         const u64 lo = small ? (((u64)N.s1[q] << 32) | N.s0[q]) : (((u64)N.l1[q] << 32) | N.l0[q]);
         const uint32_t sh = 4u * (r & 15u);
         const int idx = table ? (int)((r < 16 ? (uint32_t)(lo >> sh) : (N.l2[q] >> sh)) & 15u) : 0;
-        // the fired rule's (c, p): rules 1-4 from registers, later ones from LDS
-        const uint32_t w = idx > 2 ? N.cp1[q] : N.cp0[q];
-        uint32_t cp = idx ? (w >> (16u * ((uint32_t)(idx - 1) & 1u))) & 0xFFFFu : 0u;
-        if (__any(idx > 4)) {
-            if (idx > 4) {
+        // the fired rule's (c, p): rules 1-3 from a register word (idx 0: none),
+        // later ones from LDS
+        uint32_t cp = (uint32_t)(N.cpw[q] >> (16u * (uint32_t)min(idx, 3))) & 0xFFFFu;
+        if (N.far[q] && __any(idx > 3)) {
+            if (idx > 3) {
                 const uint32_t R = lrules[N.rs[q] + idx - 1];
                 cp = ((R >> 16) & 0xFFu) | ((R >> 24) << 8);
             }
         }
         bool found = idx != 0;
-        if (__any(!table)) {
+        if (N.slow[q] && __any(!table)) {
             // first applicable rule, over the wave's largest rule count (no early exit)
             for (int k = 0; k < N.rw[q]; ++k) {
                 const int kk = N.rs[q] + min(k, max(N.rn[q] - 1, 0));
@@ -375,7 +388,7 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
         N.T[q] = 0x7FFFFFFF;
         N.S[q] = N.valid[q] ? 0 : 16;  // a slot past m: no rule ever applies (its small table is 0)
         N.l0[q] = N.l1[q] = N.l2[q] = N.s0[q] = N.s1[q] = 0;
-        N.cp0[q] = N.cp1[q] = 0;
+        N.cpw[q] = 0;
         N.orig[q] = 0;
         N.rs[q] = N.rn[q] = N.is[q] = N.in[q] = 0;
         N.R[q] = 0;
@@ -390,11 +403,9 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
             N.is[q] = B.in_off + a.in_ptr[B.nrp_off + j];
             N.in[q] = a.in_ptr[B.nrp_off + j + 1] - a.in_ptr[B.nrp_off + j];
             N.R[q] = mix64((u64)(o + 1) * kGamma);
-            for (int k = 0; k < min(N.rn[q], 4); ++k) {
+            for (int k = 0; k < min(N.rn[q], 3); ++k) {
                 const uint32_t R = a.rules[B.rule_off + N.rs[q] + k];
-                const uint32_t cp = ((R >> 16) & 0xFFu) | ((R >> 24) << 8);
-                if (k < 2) N.cp0[q] |= cp << (16 * k);
-                else N.cp1[q] |= cp << (16 * (k - 2));
+                N.cpw[q] |= (u64)(((R >> 16) & 0xFFu) | ((R >> 24) << 8)) << (16 * (k + 1));
             }
             const uint32_t f = a.fast[B.nrp_off + j];
             const uint32_t* lt = a.lut + 5 * (B.nrp_off + j);
@@ -424,6 +435,10 @@ __global__ __launch_bounds__(TPB) void k_batch_det(BatchArgs a) {
         }
         N.kw[q] = __builtin_amdgcn_readfirstlane(kw);
         N.rw[q] = __builtin_amdgcn_readfirstlane(rw);
+        // every count of a lane is covered by the tables when the small one
+        // exists (S = 16) and the residue one starts by 16 (a slot past m: count 0)
+        N.far[q] = __any(N.valid[q] && N.rn[q] > 3);
+        N.slow[q] = __any(N.valid[q] && !(N.S[q] == 16 && N.T[q] <= 16));
     }
     T* ckpt = (T*)a.ckpt + a.ckpt_rows * B.row_off;  // row q = the configuration at step q * kBatch
     u64* hkey = a.hkey + (u64)sys * a.table_slots;
