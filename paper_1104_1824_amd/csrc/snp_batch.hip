@@ -14,7 +14,10 @@
 // rule table and double-buffered production words in LDS.  A step: every
 // neuron writes the production p of its fired rule (0: none), one barrier
 // (which also tells whether any neuron fired), then every neuron pulls
-// C' = C - c + sum of p over its in-synapses.  Step k uses buffer k & 1, so
+// C' = C - c + sum of p over its in-synapses, in rounds of one LDS read per
+// lane whose sources were placed at load so that a half-wave's reads in a round
+// fall on distinct banks (a lane with nothing to read takes a zero word in a
+// free bank).  Step k uses buffer k & 1, so
 // the barrier of step k+1 separates step k's reads from step k+2's writes; the
 // two buffers sit a fixed distance apart at the start of LDS and the step loop
 // is unrolled by parity, so the odd buffer is reached through the LDS
@@ -26,11 +29,11 @@
 // wave sums its lanes' terms of 4 steps at once (a transposed butterfly: the
 // first two stages halve the number of values per lane, so 4 sums cost about
 // what one plain wave sum costs), leaving one partial sum per wave and step in
-// LDS; the block adds them up once every kBatch steps.  First repeat: at those boundaries the block stores a
-// checkpoint row and looks the batch's H values up in a per-system
-// open-addressing set of earlier H values (and within the batch); a candidate
-// pair (l, k) is confirmed by re-simulating C_l and C_k from their
-// checkpoints and comparing the rows.  A candidate whose rows differ (two
+// LDS; the block adds them up once every kBatch steps.  First repeat: at those
+// boundaries the block stores a checkpoint row and looks the batch's H values
+// up in a per-system open-addressing set of earlier H values (and within the
+// batch); a candidate pair (l, k) is confirmed by re-simulating C_l and C_k
+// from their checkpoints and comparing the rows.  A candidate whose rows differ (two
 // configurations with one 64-bit H) is reported as an error, never guessed.
 #include "snp_internal.hpp"
 
