@@ -472,6 +472,36 @@ def copy_calibration(nbytes=1 << 30, reps=5):
     log(f"copy calibration: {reps} launches, each reads {nbytes} B and writes {nbytes} B")
 
 
+def hbm_check(nbytes=2 << 30, reps=10):
+    """What plain torch kernels reach on this GPU (context for the rooflines,
+    which use the published 8 TB/s): a fill (writes only) and a copy (reads and
+    writes), each timed with HIP events on the current stream."""
+    import torch
+
+    a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        torch.cuda.synchronize()
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / reps / 1e3
+
+    tf = timed(lambda: a.fill_(3))
+    tc = timed(lambda: b.copy_(a))
+    print(json.dumps({"hbm_check": {"bytes": nbytes, "fill_ms": round(tf * 1e3, 4),
+                                    "fill_write_gbs": round(nbytes / tf / 1e9, 1), "copy_ms": round(tc * 1e3, 4),
+                                    "copy_read_write_gbs": round(2 * nbytes / tc / 1e9, 1)}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -488,6 +518,8 @@ def main():
                     help="run only this workload (no CPU baseline) and print its line")
     ap.add_argument("--batch-largest", action="store_true",
                     help="with --only batched: run the workload's largest system alone")
+    ap.add_argument("--hbm-check", action="store_true",
+                    help="time a 2 GiB fill and copy (what plain kernels reach on this GPU) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reads 1 GiB, writes 1 GiB) five times, to scale "
                          "FETCH_SIZE / WRITE_SIZE counters")
@@ -497,6 +529,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.hbm_check:
+        hbm_check()
         return
     # the CPU oracle runs first, before this process touches the GPU (its
     # process pool is forked from here)
