@@ -32,10 +32,17 @@ if ROOT not in sys.path:
 METRIC = "new configurations/sec (deduped) per BFS step; int8-MFMA/batched vs plain sparse"
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 matrix cores, published (no sparsity)
-# Vector ALU: 256 CUs x 128 lanes x 2.4 GHz = 78.6e12 32-bit integer operations per
-# second (one op per lane per clock; the published fp32 157.3 TFLOP/s counts an FMA as 2)
-VALU_PEAK_GOPS = 256 * 128 * 2.4
-CU_PEAK_GOPS = 128 * 2.4
+# Vector ALU for 32-bit integer work: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz =
+# 39.3e12 operations per second (the published fp32 157.3 TFLOP/s counts an FMA as
+# 2 flops and two fp32 values per packed instruction; 32-bit integer adds and
+# compares are not packed)
+CLOCK_GHZ = 2.4
+INT_VALU_PER_CU = 64
+VALU_PEAK_GOPS = 256 * INT_VALU_PER_CU * CLOCK_GHZ
+CU_PEAK_GOPS = INT_VALU_PER_CU * CLOCK_GHZ
+# LDS: 32 banks of 4 bytes per clock per CU, so a gather of 32-bit words from
+# LDS takes at least one clock per 32 words
+LDS_WORDS_PER_CU = 32
 ENTRY_BYTES = 16             # visited-set entry written per new configuration
 # bytes per child of the one-neuron-per-lane expansion besides its row: key 8,
 # parent 4, child index 8, probe slot 4, visited-set entry 8
@@ -385,9 +392,14 @@ def batched_line(reps=3, cpu=None, largest=False):
     done = res["steps_done"].astype(np.int64)
     steps_total = int(done.sum())
     work = np.asarray(batch_work(systems), dtype=np.int64) * done
+    gathers = np.asarray([s.n_syn for s in systems], dtype=np.int64) * done
     # the launch cannot end before the whole batch's work at the chip's vector
-    # rate, nor before the largest system's work at one CU's rate
-    t_min = max(work.sum() / (VALU_PEAK_GOPS * 1e9), work.max() / (CU_PEAK_GOPS * 1e9))
+    # rate, nor before any system's work at one CU's vector rate or its
+    # in-synapse gathers (one LDS word each) at one CU's LDS rate
+    t_chip = work.sum() / (VALU_PEAK_GOPS * 1e9)
+    t_valu = work / (CU_PEAK_GOPS * 1e9)
+    t_lds = gathers / (LDS_WORDS_PER_CU * CLOCK_GHZ * 1e9)
+    t_min = max(t_chip, float(np.maximum(t_valu, t_lds).max()))
     line = dict(workload=BATCH_WORKLOAD + (", largest system alone" if largest else ""),
                 value=round(steps_total / dt, 1), unit="system-steps/s",
                 ms_per_launch=round(dt * 1e3, 3), dtype="int32", threads_per_system=shape[0],
@@ -396,6 +408,8 @@ def batched_line(reps=3, cpu=None, largest=False):
                               peak=round(work.sum() / t_min / 1e9, 2), unit="Gop/s",
                               frac=round(t_min / dt, 4), traffic=None,
                               critical_path_ms=round(t_min * 1e3, 3),
+                              chip_valu_ms=round(t_chip * 1e3, 3), cu_valu_ms=round(float(t_valu.max()) * 1e3, 3),
+                              cu_lds_ms=round(float(t_lds.max()) * 1e3, 3),
                               largest_system_ops=int(work.max()), total_ops=int(work.sum())),
                 cpu_baseline=cpu)
     return line
