@@ -354,13 +354,17 @@ snp_status snp_load_tuning(snp_system *sys, const char *cache_path, int32_t max_
 typedef struct snp_batch snp_batch; /* opaque; owns the packed tables of all systems */
 
 /* Load n >= 1 systems (host descriptions, copied).  All must share one
- * count_type.  Limits of this mode: m <= 4096, and i, j, c, p <= 255.
+ * count_type.  Limits of this mode: m <= 4096, and i, j, c, p <= 255; a
+ * launch shape (threads per system, neurons per thread) also needs the
+ * largest system to fit one block's 64 KiB of LDS: about
+ * 8 r_max + 12 s + 536 w + 1,600 bytes for s = threads x neurons per thread
+ * (s >= m_max) and w = threads / 64; shapes that do not fit are skipped.
  * opt: NULL or options; used are `stream`, and `chunk`, which here fixes the
  *   threads per system (256, 512 or 1024; each thread owns up to 4 neurons).
  *   chunk = 0: the first snp_batch_run times every fitting shape on a short
  *   run of the batch and keeps the fastest.  Other fields are ignored.
- * Errors: SNP_ERR_INVALID (as snp_load, plus the limits above, or a `chunk`
- *   that does not fit), SNP_ERR_DEVICE. */
+ * Errors: SNP_ERR_INVALID (as snp_load, plus the limits above, a `chunk`
+ *   that does not fit, or no shape that fits), SNP_ERR_DEVICE. */
 snp_status snp_batch_load(const snp_desc *descs, int32_t n, const snp_options *opt, snp_batch **out);
 
 void snp_batch_free(snp_batch *b);
