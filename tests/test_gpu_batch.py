@@ -288,3 +288,17 @@ def test_batch_many_rules_and_a_hub(gpu, oracle_mod, threads):
     for steps in (1, 37, 500):
         note(f"batch many rules and a hub, {threads} threads, steps {steps}")
         check_against_oracle(oracle_mod, systems, steps, run_batch(systems, steps, threads=threads))
+
+
+@pytest.mark.parametrize("seed", [300, 307, 314])
+def test_batch_random_sweep(gpu, oracle_mod, seed):
+    """Systems of the batched recipe from other seeds, every launch shape that
+    fits, step counts that end inside a 4-step group and inside a 64-step batch
+    (odd counts leave the odd production buffer last)."""
+    systems = synth.batched_systems(seed, 4)
+    rng = synth.SplitMix64((13 << 32) | seed)
+    for threads in (256, 512, 1024):
+        fit = [s for s in systems if s.m <= 4 * threads]
+        for steps in (rng.uniform(1, 7), rng.uniform(65, 130), rng.uniform(200, 600)):
+            note(f"batch random sweep seed {seed}, {threads} threads, {len(fit)} systems, steps {steps}")
+            check_against_oracle(oracle_mod, fit, steps, run_batch(fit, steps, threads=threads))
