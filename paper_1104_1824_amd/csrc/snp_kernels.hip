@@ -209,7 +209,10 @@ __device__ __forceinline__ void add_full_total(DevCounters* ctr, u64 lo, u64 hi)
     if (hi) atomicAdd((unsigned long long*)&ctr->psif_hi, hi);
 }
 
-template <typename T, bool TBL_LDS>
+// S > 0: rows of at most 64 S entries, S strips of 64 held in registers, and
+// the next parent's strips loaded while the current one is counted (its
+// latency overlaps the work); S = 0: any width, one parent after another.
+template <typename T, bool TBL_LDS, int S>
 __global__ __launch_bounds__(256) void k_psi(DevSystem s, const T* __restrict__ F, long long n,
                                              long long expand_max, u64* __restrict__ psi, u64* __restrict__ psif,
                                              uint8_t* __restrict__ halt_flag, DevCounters* __restrict__ ctr,
@@ -218,12 +221,53 @@ __global__ __launch_bounds__(256) void k_psi(DevSystem s, const T* __restrict__ 
     const int lane = threadIdx.x & 63;
     const PsiTables tb = stage_psi_tables<TBL_LDS>(s, smem);
     const long long w0 = ((long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * parents_per_wave;
+    const long long pend = min(n, w0 + parents_per_wave);
     unsigned halting = 0;
     u64 flo = 0, fhi = 0;
-    for (long long p = w0; p < min(n, w0 + parents_per_wave); ++p) {
+    constexpr int SR = S > 0 ? S : 1;
+    int dl[SR], x[SR], wt[SR];  // per strip: the wait column of the lane's neuron (-1: none), count, wait
+    auto load = [&](long long p, int (&xx)[SR], int (&ww)[SR]) {
+        const T* row = F + p * (long long)s.m;
+#pragma unroll
+        for (int q = 0; q < SR; ++q) {
+            const int j = q * 64 + lane;
+            xx[q] = j < s.m ? (int)row[j] : 0;
+            ww[q] = dl[q] >= 0 ? (int)row[dl[q]] : 0;  // as neuron_wait
+        }
+    };
+    if constexpr (S > 0) {
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int j = q * 64 + lane;
+            dl[q] = (s.dlink && j < s.mcount) ? s.dlink[j] : -1;
+        }
+        if (w0 < pend) load(w0, x, wt);
+    }
+    for (long long p = w0; p < pend; ++p) {
         bool h;
-        const PsiPair v = parent_psi<T>(F + p * (long long)s.m, s.m, tb.nrp, tb.rules, s.dlink, s.mcount, expand_max,
-                                        s.track, lane, h);
+        PsiPair v;
+        if constexpr (S > 0) {
+            int xn[SR], wn[SR];
+#pragma unroll
+            for (int q = 0; q < SR; ++q) xn[q] = wn[q] = 0;
+            if (p + 1 < pend) load(p + 1, xn, wn);
+            PsiAcc A;
+#pragma unroll
+            for (int q = 0; q < S; ++q)
+                psi_add_neuron(A, x[q], wt[q], q * 64 + lane, s.m, s.mcount, tb.nrp, tb.rules, expand_max, s.track);
+            v = psi_finish(A, h);
+            if (v.full >= kPsiSat)
+                v.canon = min(v.canon, canon_rank<T>(F + p * (long long)s.m, s.m, tb.nrp, tb.rules, s.dlink, s.mcount,
+                                                     kPsiSat, lane));
+#pragma unroll
+            for (int q = 0; q < SR; ++q) {
+                x[q] = xn[q];
+                wt[q] = wn[q];
+            }
+        } else {
+            v = parent_psi<T>(F + p * (long long)s.m, s.m, tb.nrp, tb.rules, s.dlink, s.mcount, expand_max, s.track,
+                              lane, h);
+        }
         const u64 full = min(v.full, s.psi_cap);
         if (lane == 0) {
             psi[p] = min(v.canon, s.psi_cap);
@@ -329,9 +373,17 @@ hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, 
     const long long waves = (n + ppw - 1) / ppw;
     const unsigned blocks = (unsigned)((waves + 3) / 4);
     const size_t lds = tbl_lds ? tbl : 0;
-#define SNP_PSI(TT, L)                                                                                       \
-    hipLaunchKernelGGL((k_psi<TT, L>), dim3(blocks), dim3(256), lds, st, s, (const TT*)frontier, n, expand_max, \
+    const int strips = s.m <= 64 ? 1 : s.m <= 128 ? 2 : s.m <= 256 ? 4 : 0;
+#define SNP_PSI_S(TT, L, SS)                                                                                       \
+    hipLaunchKernelGGL((k_psi<TT, L, SS>), dim3(blocks), dim3(256), lds, st, s, (const TT*)frontier, n, expand_max, \
                        psi, psif, halt_flag, ctr, ppw)
+#define SNP_PSI(TT, L)                              \
+    do {                                            \
+        if (strips == 1) SNP_PSI_S(TT, L, 1);       \
+        else if (strips == 2) SNP_PSI_S(TT, L, 2);  \
+        else if (strips == 4) SNP_PSI_S(TT, L, 4);  \
+        else SNP_PSI_S(TT, L, 0);                   \
+    } while (0)
     if (elem_bytes == 4) {
         if (tbl_lds) SNP_PSI(int32_t, true);
         else SNP_PSI(int32_t, false);
@@ -340,6 +392,7 @@ hipError_t launch_psi(int elem_bytes, const DevSystem& s, const void* frontier, 
         else SNP_PSI(uint16_t, false);
     }
 #undef SNP_PSI
+#undef SNP_PSI_S
     return hipGetLastError();
 }
 
