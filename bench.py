@@ -361,6 +361,23 @@ def batch_work(systems):
     return [s.r + s.n_syn + s.m for s in systems]
 
 
+def batch_bound(systems, steps_done):
+    """Times (s) a batched launch cannot beat, from unit counts: the batch's
+    work at the chip's 32-bit vector rate, each system's work at one CU's
+    vector rate, and each system's in-synapse gathers at one CU's LDS rate.
+    Returns (bound, chip, largest CU vector term, largest CU LDS term, work)."""
+    import numpy as np
+
+    done = np.asarray(steps_done, dtype=np.int64)
+    work = np.asarray(batch_work(systems), dtype=np.int64) * done
+    gathers = np.asarray([s.n_syn for s in systems], dtype=np.int64) * done
+    t_chip = work.sum() / (VALU_PEAK_GOPS * 1e9)
+    t_valu = work / (CU_PEAK_GOPS * 1e9)
+    t_lds = gathers / (LDS_WORDS_PER_CU * CLOCK_GHZ * 1e9)
+    bound = max(t_chip, float(np.maximum(t_valu, t_lds).max()))
+    return bound, t_chip, float(t_valu.max()), float(t_lds.max()), work
+
+
 def batched_line(reps=3, cpu=None, largest=False):
     """The batched launch; largest=True runs only the workload's largest
     system (the one that bounds the launch), for per-step counters."""
@@ -391,15 +408,7 @@ def batched_line(reps=3, cpu=None, largest=False):
     b.close()
     done = res["steps_done"].astype(np.int64)
     steps_total = int(done.sum())
-    work = np.asarray(batch_work(systems), dtype=np.int64) * done
-    gathers = np.asarray([s.n_syn for s in systems], dtype=np.int64) * done
-    # the launch cannot end before the whole batch's work at the chip's vector
-    # rate, nor before any system's work at one CU's vector rate or its
-    # in-synapse gathers (one LDS word each) at one CU's LDS rate
-    t_chip = work.sum() / (VALU_PEAK_GOPS * 1e9)
-    t_valu = work / (CU_PEAK_GOPS * 1e9)
-    t_lds = gathers / (LDS_WORDS_PER_CU * CLOCK_GHZ * 1e9)
-    t_min = max(t_chip, float(np.maximum(t_valu, t_lds).max()))
+    t_min, t_chip, t_valu, t_lds, work = batch_bound(systems, done)
     line = dict(workload=BATCH_WORKLOAD + (", largest system alone" if largest else ""),
                 value=round(steps_total / dt, 1), unit="system-steps/s",
                 ms_per_launch=round(dt * 1e3, 3), dtype="int32", threads_per_system=shape[0],
@@ -408,8 +417,8 @@ def batched_line(reps=3, cpu=None, largest=False):
                               peak=round(work.sum() / t_min / 1e9, 2), unit="Gop/s",
                               frac=round(t_min / dt, 4), traffic=None,
                               critical_path_ms=round(t_min * 1e3, 3),
-                              chip_valu_ms=round(t_chip * 1e3, 3), cu_valu_ms=round(float(t_valu.max()) * 1e3, 3),
-                              cu_lds_ms=round(float(t_lds.max()) * 1e3, 3),
+                              chip_valu_ms=round(t_chip * 1e3, 3), cu_valu_ms=round(t_valu * 1e3, 3),
+                              cu_lds_ms=round(t_lds * 1e3, 3),
                               largest_system_ops=int(work.max()), total_ops=int(work.sum())),
                 cpu_baseline=cpu)
     return line

@@ -50,6 +50,29 @@ def test_batch_work_per_step():
     assert bench.batch_work(systems) == [12, 448]
 
 
+def test_batch_bound_terms():
+    """Clock 2.4 GHz: one CU does 64 integer operations and 32 LDS words per
+    clock, the chip 256 times the former.  System a: r 1, 767 synapses, m 1
+    (work 769 per step); b: r 1, 7 synapses, m 4088 (work 4096, 7 gathers)."""
+    a = types.SimpleNamespace(r=1, n_syn=767, m=1)
+    b = types.SimpleNamespace(r=1, n_syn=7, m=4088)
+    steps = [2400, 2400]
+    bound, chip, valu, lds, work = bench.batch_bound([a, b], steps)
+    assert work.tolist() == [769 * 2400, 4096 * 2400]
+    # b's work at 64 per clock: 4096 * 2400 / 64 clocks = 153600 clocks = 64 us
+    assert abs(valu - 64e-6) < 1e-12
+    # a's gathers at 32 per clock: 767 * 2400 / 32 = 57525 clocks = 23.97 us
+    assert abs(lds - 767 * 2400 / 32 / 2.4e9) < 1e-15
+    # both systems at 256 CUs x 64 per clock
+    assert abs(chip - (769 + 4096) * 2400 / (256 * 64 * 2.4e9)) < 1e-15
+    assert bound == valu
+    # with a's synapses multiplied the LDS term takes over
+    a.n_syn = 7670
+    a.r = 1
+    bound, chip, valu, lds, _ = bench.batch_bound([a, b], steps)
+    assert bound == lds and abs(lds - 7670 * 2400 / 32 / 2.4e9) < 1e-15
+
+
 def test_more_than_one_gpu_is_refused():
     res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                          text=True, timeout=120, cwd=ROOT)
