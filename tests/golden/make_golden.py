@@ -4,9 +4,10 @@ Calls only the CPU oracle (``oracle/``) and the seeded generator (``synth/``);
 nothing here touches the GPU library.  Two files are written next to this
 script:
 
-* ``dense_m512_s0_walk.txt`` -- the breadth-first walk of the dense workload
-  (m = 512, 3 rules per neuron, p in [0, 4], out-degree 64, C0 in [0, 4],
-  int32 counts; seed 0), depth 3, frontier cap 1e6 per level (Algorithm 1 with
+* ``dense_m512_s0_walk.txt`` and ``dense_m512_s1_walk.txt`` -- the
+  breadth-first walk of the dense workload (m = 512, 3 rules per neuron, p in
+  [0, 4], out-degree 64, C0 in [0, 4], int32 counts; seeds 0 and 1), depth 3,
+  frontier cap 1e6 per level (Algorithm 1 with
   the children of every configuration in Algorithm 2 order, Equation
   next-config).  The walk's rows are cut into blocks of 1024 consecutive rows
   (global row index, C0 is row 0); every block gets two digests: SHA-256 of the
@@ -20,8 +21,8 @@ script:
   int32, the halting step, the first repeat, the steps computed and the
   trajectory checksum.
 
-Usage: ``python tests/golden/make_golden.py [dense|batched|all]`` (the dense
-walk takes a few minutes of one CPU core and about 13 GB of memory).
+Usage: ``python tests/golden/make_golden.py [dense|dense1|batched|all]`` (each
+dense walk takes a few minutes of one CPU core and about 13 GB of memory).
 """
 import hashlib
 import os
@@ -41,7 +42,14 @@ import synth  # noqa: E402
 
 BLOCK = 1024
 HEX = 24
-DENSE_FILE = os.path.join(HERE, "dense_m512_s0_walk.txt")
+DENSE_SEEDS = (0, 1)
+
+
+def dense_file(seed: int = 0) -> str:
+    return os.path.join(HERE, f"dense_m512_s{seed}_walk.txt")
+
+
+DENSE_FILE = dense_file(0)
 BATCH_FILE = os.path.join(HERE, "batched_256x10k.txt")
 DENSE_RUN = dict(max_depth=3, frontier_cap=1000000)
 BATCH_STEPS = 10000
@@ -85,17 +93,17 @@ def read_table(path):
     return head, data
 
 
-def write_dense():
-    s = synth.config_system(3, 0)
+def write_dense(seed=0):
+    s = synth.config_system(3, seed)
     t0 = time.time()
     res = oracle.bfs(s, rows_cap=3000001, **DENSE_RUN)
     dt = time.time() - t0
     digs = block_digests(res.rows, res.parent, res.tindex)
-    with open(DENSE_FILE, "w") as f:
+    with open(dense_file(seed), "w") as f:
         f.write("# Breadth-first walk of the dense workload, computed by the CPU oracle\n")
         f.write("# (written by tests/golden/make_golden.py, which calls only oracle/ and synth/).\n")
         f.write("# System: m=512, 3 rules per neuron, E = a^i (a^j)* with i in [1,4], j in [0,3], c in [1,i],\n")
-        f.write("# p in [0,4], out-degree 64, C0 in [0,4], int32 counts; seed 0 of the dense recipe.\n")
+        f.write(f"# p in [0,4], out-degree 64, C0 in [0,4], int32 counts; seed {seed} of the dense recipe.\n")
         f.write("# Walk: Algorithm 1 (one global visited set, first occurrence kept) with the children of a\n")
         f.write("# configuration in Algorithm 2 step II-3 order, C' = C + S.M (Equation next-config);\n")
         f.write("# depth 3, every level truncated to its first 1e6 new configurations.\n")
@@ -109,7 +117,7 @@ def write_dense():
         f.write(f"# int64 (C0: -1, -1), each cut to its first {HEX} hex digits.\n")
         for k, (a, b) in enumerate(digs):
             f.write(f"{k} {a} {b}\n")
-    print(f"dense walk: {res.n_levels} levels {res.level_sizes.tolist()}, {len(digs)} blocks, oracle {dt:.1f} s")
+    print(f"dense walk, seed {seed}: {res.n_levels} levels {res.level_sizes.tolist()}, {len(digs)} blocks, oracle {dt:.1f} s")
 
 
 def batch_line(seed):
@@ -145,4 +153,6 @@ if __name__ == "__main__":
     if what in ("batched", "all"):
         write_batched()
     if what in ("dense", "all"):
-        write_dense()
+        write_dense(0)
+    if what in ("dense1", "all"):
+        write_dense(1)

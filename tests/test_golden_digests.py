@@ -8,8 +8,9 @@ import synth
 from tests.golden import make_golden
 
 
-def test_dense_walk_file_shape():
-    head, data = make_golden.read_table(make_golden.DENSE_FILE)
+@pytest.mark.parametrize("seed", make_golden.DENSE_SEEDS)
+def test_dense_walk_file_shape(seed):
+    head, data = make_golden.read_table(make_golden.dense_file(seed))
     levels = [int(x) for x in head["levels"].split()]
     assert levels == [1, 1000000, 1000000, 1000000]
     assert int(head["block_rows"]) == make_golden.BLOCK
@@ -18,11 +19,12 @@ def test_dense_walk_file_shape():
     assert all(len(x[1]) == make_golden.HEX and len(x[2]) == make_golden.HEX for x in data)
 
 
-def test_dense_walk_first_blocks(oracle_mod):
+@pytest.mark.parametrize("seed", make_golden.DENSE_SEEDS)
+def test_dense_walk_first_blocks(oracle_mod, seed):
     """Blocks 0-3 cover C0 and the first 4095 rows of level 1, which a walk
     capped at 4095 new configurations per level reproduces."""
-    _, data = make_golden.read_table(make_golden.DENSE_FILE)
-    s = synth.config_system(3, 0)
+    _, data = make_golden.read_table(make_golden.dense_file(seed))
+    s = synth.config_system(3, seed)
     w = oracle_mod.bfs(s, max_depth=1, frontier_cap=4 * make_golden.BLOCK - 1, rows_cap=4 * make_golden.BLOCK)
     got = make_golden.block_digests(w.rows, w.parent, w.tindex)
     assert [list(g) for g in got] == [x[1:] for x in data[:4]]

@@ -25,10 +25,10 @@ from tests.gpu_helpers import dev_dtype, from_device_rows, note, to_device_rows
 pytestmark = pytest.mark.gpu
 
 
-def run_full(system, path, cap, depth, out_cap, chunk=1 << 20):
+def run_full(system, path, cap, depth, out_cap, chunk=1 << 20, stage_rows=0):
     import torch
 
-    h = snp.snp_load(system, path=path, frontier_cap=cap, max_rows=out_cap, chunk=chunk)
+    h = snp.snp_load(system, path=path, frontier_cap=cap, max_rows=out_cap, chunk=chunk, stage_rows=stage_rows)
     try:
         c0 = to_device_rows(system, system.c0)
         out = torch.empty((out_cap, system.m), dtype=dev_dtype(system), device="cuda")
@@ -133,12 +133,12 @@ def check_walk(oracle_mod, system, res, rows, par, chi, n_samples, seed):
             assert recorded(oracle_mod.child_at(system, prow, t - 1)), f"child ({p}, {t - 1}) missing"
 
 
-def compare_with_golden_walk(res, rows, par, chi, path_name):
+def compare_with_golden_walk(res, rows, par, chi, path_name, seed=0):
     """Every 1024-row block of the walk (rows, and parent/child-index pairs)
-    against the oracle-written digests of tests/golden/dense_m512_s0_walk.txt."""
+    against the oracle-written digests of tests/golden/dense_m512_s<seed>_walk.txt."""
     from tests.golden import make_golden
 
-    head, data = make_golden.read_table(make_golden.DENSE_FILE)
+    head, data = make_golden.read_table(make_golden.dense_file(seed))
     assert res["level_sizes"].tolist() == [int(x) for x in head["levels"].split()]
     assert res["stop_reason"] == int(head["stop_reason"])
     st = res["level_stats"]
@@ -152,7 +152,7 @@ def compare_with_golden_walk(res, rows, par, chi, path_name):
     bad = []
     for a in range(0, n, step):
         b = min(n, a + step)
-        got = make_golden.block_digests(from_device_rows(SYS_DENSE(), rows[a:b]), par[a:b].cpu().numpy(),
+        got = make_golden.block_digests(from_device_rows(SYS_DENSE(seed), rows[a:b]), par[a:b].cpu().numpy(),
                                         chi[a:b].cpu().numpy())
         for k, (dr, dp) in enumerate(got):
             line = data[a // blk + k]
@@ -161,8 +161,8 @@ def compare_with_golden_walk(res, rows, par, chi, path_name):
     assert not bad, f"{path_name}: {len(bad)} blocks differ from the oracle's digests, first {bad[:5]}"
 
 
-def SYS_DENSE():
-    return synth.config_system(3, 0)
+def SYS_DENSE(seed=0):
+    return synth.config_system(3, seed)
 
 
 @pytest.mark.parametrize("path", [snp.SNP_PATH_INT8, snp.SNP_PATH_SPARSE, snp.SNP_PATH_AUTO])
@@ -177,6 +177,20 @@ def test_dense_full_size_golden(gpu, path):
     compare_with_golden_walk(res, rows, par, chi, f"path {path}")
     if path == snp.SNP_PATH_AUTO:
         assert all(x["path_used"] == snp.SNP_PATH_INT8 for x in res["level_stats"] if x["chunks"])
+
+
+@pytest.mark.parametrize("stage_rows", [0, 1])
+def test_dense_full_size_golden_seed1(gpu, stage_rows):
+    """Seed 1 of the dense workload at full size on the int8 form, keys-first
+    (the default for passes this large) and staged, block by block against the
+    oracle's digests of that seed."""
+    s = SYS_DENSE(1)
+    note(f"full size: dense seed 1, cap 1e6, depth 3, int8, stage_rows {stage_rows}")
+    res, rows, par, chi = run_full(s, snp.SNP_PATH_INT8, 1000000, 3, 3000001, chunk=1 << 20, stage_rows=stage_rows)
+    note(f"full size: dense seed 1, stage_rows {stage_rows}: block digests")
+    compare_with_golden_walk(res, rows, par, chi, f"seed 1, stage_rows {stage_rows}", seed=1)
+    kf = sum(x["keys_first"] for x in res["level_stats"])
+    assert (kf > 0) == (stage_rows == 0)
 
 
 def test_dense_full_size(gpu, oracle_mod):
